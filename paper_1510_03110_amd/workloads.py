@@ -1,0 +1,169 @@
+"""Seeded synthetic UFTOC workloads.
+
+This module only draws random problem data; it holds none of the solver's
+arithmetic and is shared by the GPU path's callers and by the oracle's tests.
+
+A problem is a dict of float64 arrays with row-major blocks:
+
+    Qx (N,nx,nx)  Qw (N,nu,nu)  Qxw (N,nx,nu)  A (N,nx,nx)  B (N,nx,nu)
+    a (N,nx)  lx (N,nx)  lw (N,nu)  c (N,)  QxN (nx,nx)  lN (nx,)  cN ()
+    x0 (nx,)
+
+Generators (the paper does not publish its test systems; these stand in for
+them with the problem structure of Sec. 2):
+
+* ``g1`` - time-invariant A with N(0,1) entries rescaled to spectral radius
+  0.95 (materialised per stage), B ~ N(0,1), diagonal Qx, Qw with U[0.5,2]
+  entries, Qxw = 0, a, lx, lw ~ N(0,1), c = 0, x0 ~ N(0,I).
+* ``g2`` - time-varying A_t = A + 0.05 N(0,1) (A as in g1), B_t = N(0,1)/sqrt(nx),
+  Qx_t = M M' + 0.1 I with fresh M ~ N(0,1), Qw diagonal U[0.5,2] and a cross
+  term Qxw_t = beta_t 0.1 N(0,1) with beta_t = min(1, 0.5/||L^{-1} S R^{-1/2}||_F)
+  (Qx = L L'), which keeps R - S' Qx^{-1} S >= 0.75 R, i.e. the stage Hessian
+  positive definite.
+
+The terminal cost is drawn like a stage Qx (reading: the configurations do not
+state it) and lN ~ N(0,I).  Seeds are 151003110 + 1000*config + instance.
+"""
+import math
+
+import numpy as np
+
+SEED_BASE = 151003110
+
+
+def seed_for(config, instance=0):
+    return SEED_BASE + 1000 * int(config) + int(instance)
+
+
+def _spectral_scale(A, rho=0.95):
+    r = np.max(np.abs(np.linalg.eigvals(A)))
+    return A * (rho / r)
+
+
+def g1(nx, nu, N, seed):
+    rng = np.random.default_rng(seed)
+    A = _spectral_scale(rng.standard_normal((nx, nx)))
+    B = rng.standard_normal((nx, nu))
+    p = dict(
+        Qx=np.stack([np.diag(rng.uniform(0.5, 2.0, nx)) for _ in range(N)]).reshape(N, nx, nx),
+        Qw=np.stack([np.diag(rng.uniform(0.5, 2.0, nu)) for _ in range(N)]).reshape(N, nu, nu),
+        Qxw=np.zeros((N, nx, nu)),
+        A=np.broadcast_to(A, (N, nx, nx)).copy(),
+        B=np.broadcast_to(B, (N, nx, nu)).copy(),
+        a=rng.standard_normal((N, nx)),
+        lx=rng.standard_normal((N, nx)),
+        lw=rng.standard_normal((N, nu)),
+        c=np.zeros(N),
+        QxN=np.diag(rng.uniform(0.5, 2.0, nx)),
+        lN=rng.standard_normal(nx),
+        cN=np.float64(0.0),
+        x0=rng.standard_normal(nx),
+    )
+    return p
+
+
+def _cross_term(rng, Qx, Rdiag, nu):
+    nx = Qx.shape[0]
+    S = 0.1 * rng.standard_normal((nx, nu))
+    L = np.linalg.cholesky(Qx)
+    T = np.linalg.solve(L, S) / np.sqrt(Rdiag)[None, :]
+    fro = np.linalg.norm(T)
+    beta = 1.0 if fro == 0 else min(1.0, 0.5 / fro)
+    return beta * S
+
+
+def g2(nx, nu, N, seed, cross=True):
+    rng = np.random.default_rng(seed)
+    A0 = _spectral_scale(rng.standard_normal((nx, nx)))
+    A = A0[None] + 0.05 * rng.standard_normal((N, nx, nx))
+    B = rng.standard_normal((N, nx, nu)) / math.sqrt(nx)
+    M = rng.standard_normal((N, nx, nx))
+    Qx = M @ np.swapaxes(M, 1, 2) + 0.1 * np.eye(nx)[None]
+    Rd = rng.uniform(0.5, 2.0, (N, nu))
+    Qw = np.zeros((N, nu, nu))
+    idx = np.arange(nu)
+    Qw[:, idx, idx] = Rd
+    if cross:
+        Qxw = np.stack([_cross_term(rng, Qx[t], Rd[t], nu) for t in range(N)]).reshape(N, nx, nu)
+    else:
+        Qxw = np.zeros((N, nx, nu))
+    MN = rng.standard_normal((nx, nx))
+    p = dict(
+        Qx=Qx, Qw=Qw, Qxw=Qxw, A=A, B=B,
+        a=rng.standard_normal((N, nx)),
+        lx=rng.standard_normal((N, nx)),
+        lw=rng.standard_normal((N, nu)),
+        c=np.zeros(N),
+        QxN=MN @ MN.T + 0.1 * np.eye(nx),
+        lN=rng.standard_normal(nx),
+        cN=np.float64(0.0),
+        x0=rng.standard_normal(nx),
+    )
+    return p
+
+
+def with_costs(prob, seed):
+    """Copy of ``prob`` with c_t, cN ~ N(0,1) (for objective-value checks)."""
+    rng = np.random.default_rng(seed)
+    q = dict(prob)
+    q["c"] = rng.standard_normal(prob["Qx"].shape[0])
+    q["cN"] = np.float64(rng.standard_normal())
+    return q
+
+
+# ---------------------------------------------------------------- device side
+def g2_torch(nx, nu, N, count, seed, device="cuda", cross=True):
+    """Batch of ``count`` g2-distributed instances drawn directly in device
+    memory with torch's generator (for batches too large to draw on the host).
+    Same distributions as ``g2``; a different random stream.  Returns a dict
+    of stacked tensors with a leading instance axis."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    f64 = dict(dtype=torch.float64, device=device)
+    # spectral scaling of the base A per instance (host eigvals, tiny)
+    A0 = torch.randn((count, nx, nx), generator=gen, **f64)
+    rad = torch.linalg.eigvals(A0.cpu()).abs().amax(dim=-1).to(device)
+    A0 = A0 * (0.95 / rad)[:, None, None]
+    A = A0[:, None] + 0.05 * torch.randn((count, N, nx, nx), generator=gen, **f64)
+    B = torch.randn((count, N, nx, nu), generator=gen, **f64) / math.sqrt(nx)
+    Qx = torch.empty((count, N, nx, nx), **f64)
+    eye = torch.eye(nx, **f64)
+    for i in range(count):          # chunked so the temporaries stay small
+        M = torch.randn((N, nx, nx), generator=gen, **f64)
+        Qx[i] = torch.matmul(M, M.transpose(1, 2).contiguous()) + 0.1 * eye
+    Rd = torch.rand((count, N, nu), generator=gen, **f64) * 1.5 + 0.5
+    Qw = torch.diag_embed(Rd)
+    if cross:
+        Qxw = torch.empty((count, N, nx, nu), **f64)
+        for i in range(count):
+            S = 0.1 * torch.randn((N, nx, nu), generator=gen, **f64)
+            L = torch.linalg.cholesky(Qx[i])
+            T = torch.linalg.solve_triangular(L, S, upper=False) / Rd[i].sqrt()[:, None, :]
+            fro = torch.linalg.matrix_norm(T)
+            beta = torch.clamp(0.5 / fro, max=1.0)
+            Qxw[i] = beta[:, None, None] * S
+    else:
+        Qxw = torch.zeros((count, N, nx, nu), **f64)
+    MN = torch.randn((count, nx, nx), generator=gen, **f64)
+    QxN = torch.matmul(MN, MN.transpose(1, 2).contiguous()) + 0.1 * eye
+    return dict(
+        Qx=Qx, Qw=Qw, Qxw=Qxw, A=A, B=B,
+        a=torch.randn((count, N, nx), generator=gen, **f64),
+        lx=torch.randn((count, N, nx), generator=gen, **f64),
+        lw=torch.randn((count, N, nu), generator=gen, **f64),
+        c=torch.zeros((count, N), **f64),
+        QxN=QxN,
+        lN=torch.randn((count, nx), generator=gen, **f64),
+        cN=torch.zeros((count,), **f64),
+        x0=torch.randn((count, nx), generator=gen, **f64),
+    )
+
+
+def instance_to_numpy(batch, i):
+    """Instance ``i`` of a stacked torch batch as a numpy problem dict."""
+    out = {}
+    for k, v in batch.items():
+        out[k] = v[i].detach().cpu().numpy().astype(np.float64)
+    out["cN"] = np.float64(out["cN"])
+    return out

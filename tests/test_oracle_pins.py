@@ -1,0 +1,227 @@
+"""Pins of the serial FP64 Riccati oracle against things other than itself:
+exact rational solutions, brute-force dense LU of the KKT system, the
+objective evaluated term by term, closed forms of special cases, and the
+RTS smoother on a linear-Gaussian MHE problem (paper Sec. 2-3, Sec. 5)."""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import kkt, mhe, riccati
+from paper_1510_03110_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "tiny_exact.json")
+
+
+def _to_float(v):
+    if isinstance(v, dict):
+        return {k: _to_float(e) for k, e in v.items()}
+    if isinstance(v, list):
+        return np.array([_to_float(e) for e in v], dtype=np.float64)
+    return float(Fraction(v))
+
+
+@pytest.mark.parametrize("name", ["tiny_n2_m1_N3", "scalar_N2_zero_terminal", "n1_m2_N1"])
+def test_exact_rational_golden(name):
+    """Oracle vs exact rational KKT solutions stored under tests/golden/."""
+    with open(GOLDEN) as f:
+        case = json.load(f)[name]
+    prob = _to_float(case["problem"])
+    ref = _to_float(case["solution"])
+    sol = riccati.solve(prob)
+    for key in ("x", "w", "lam"):
+        np.testing.assert_allclose(sol[key], ref[key].reshape(sol[key].shape), rtol=1e-13, atol=1e-13)
+    assert abs(sol["obj"] - ref["obj"]) <= 1e-13 * max(1.0, abs(ref["obj"]))
+
+
+CASES = [
+    ("g1", 4, 2, 1), ("g1", 4, 2, 7), ("g1", 4, 2, 16), ("g2", 3, 2, 9), ("g2", 5, 3, 12),
+    ("g2", 2, 4, 6), ("g2", 1, 1, 10), ("g2", 6, 6, 5), ("g1", 3, 1, 16),
+]
+
+
+@pytest.mark.parametrize("gen,nx,nu,N", CASES)
+def test_oracle_vs_dense_lu(gen, nx, nu, N):
+    """Riccati (Alg. 1-3) equals brute-force LU of the assembled KKT system."""
+    prob = getattr(W, gen)(nx, nu, N, seed=W.seed_for(0, 100 * nx + 10 * nu + N))
+    prob = W.with_costs(prob, seed=7)
+    sol = riccati.solve(prob)
+    ref = kkt.solve_dense(prob)
+    assert kkt.rel_error(sol, ref) < 1e-11
+    K, r = kkt.assemble(prob)
+    assert np.allclose(K, K.T)          # the KKT matrix of P(N) is symmetric
+
+
+@pytest.mark.parametrize("gen,nx,nu,N", CASES)
+def test_objective_identity(gen, nx, nu, N):
+    """Optimal value 1/2 x0'P_0 x0 - Psi_0'x0 + cbar_0 equals the objective of
+    P(N) evaluated term by term at the returned (x, w)."""
+    prob = W.with_costs(getattr(W, gen)(nx, nu, N, seed=W.seed_for(0, 3 + N)), seed=11)
+    sol = riccati.solve(prob)
+    J = kkt.objective(prob, sol["x"], sol["w"])
+    assert abs(sol["obj"] - J) <= 1e-10 * max(1.0, abs(J))
+
+
+def test_residual_long_horizon():
+    """At a full-length horizon the KKT residual is at the FP64 floor."""
+    prob = W.g2(20, 10, 1024, seed=W.seed_for(2, 0))
+    sol = riccati.solve(prob)
+    assert kkt.rel_residual(prob, sol["x"], sol["w"], sol["lam"]) < 1e-12
+
+
+def test_optimality_by_perturbation():
+    """Any feasible perturbation of the inputs w raises the objective (convex
+    problem, Q_t positive semidefinite, G_t positive definite)."""
+    prob = W.with_costs(W.g2(3, 2, 8, seed=5), seed=3)
+    sol = riccati.solve(prob)
+    J0 = kkt.objective(prob, sol["x"], sol["w"])
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        dw = 1e-3 * rng.standard_normal(sol["w"].shape)
+        w = sol["w"] + dw
+        x = [prob["x0"]]
+        for t in range(8):
+            x.append(prob["A"][t] @ x[-1] + prob["B"][t] @ w[t] + prob["a"][t])
+        assert kkt.objective(prob, np.array(x), w) > J0
+
+
+def test_special_case_single_stage_closed_form():
+    """N = 1: w0 = -(Qw + B'QN B)^{-1} (Qxw'x0 + lw + B'(QN (A x0 + a) + lN))."""
+    prob = W.with_costs(W.g2(4, 3, 1, seed=9), seed=1)
+    sol = riccati.solve(prob)
+    A, B, QN = prob["A"][0], prob["B"][0], prob["QxN"]
+    x0 = prob["x0"]
+    G = prob["Qw"][0] + B.T @ QN @ B
+    rhs = prob["Qxw"][0].T @ x0 + prob["lw"][0] + B.T @ (QN @ (A @ x0 + prob["a"][0]) + prob["lN"])
+    w0 = -np.linalg.solve(G, rhs)
+    np.testing.assert_allclose(sol["w"][0], w0, rtol=1e-12, atol=1e-12)
+    x1 = A @ x0 + B @ w0 + prob["a"][0]
+    np.testing.assert_allclose(sol["lam"][1], QN @ x1 + prob["lN"], rtol=1e-12, atol=1e-12)
+
+
+def test_special_case_no_input_coupling():
+    """B_t = 0: the inputs decouple, w_t = -Qw^{-1}(Qxw' x_t + lw_t)."""
+    prob = W.g2(3, 2, 6, seed=4)
+    prob["B"] = np.zeros_like(prob["B"])
+    sol = riccati.solve(prob)
+    for t in range(6):
+        wt = -np.linalg.solve(prob["Qw"][t], prob["Qxw"][t].T @ sol["x"][t] + prob["lw"][t])
+        np.testing.assert_allclose(sol["w"][t], wt, rtol=1e-12, atol=1e-12)
+
+
+def test_special_case_zero_dynamics():
+    """A_t = 0 and Qxw = 0: x_{t+1} = B_t w_t + a_t and each stage is a small
+    independent quadratic program in w_t given the next stage's cost."""
+    prob = W.g1(2, 2, 3, seed=8)
+    prob["A"] = np.zeros_like(prob["A"])
+    sol = riccati.solve(prob)
+    ref = kkt.solve_dense(prob)
+    assert kkt.rel_error(sol, ref) < 1e-12
+    # last stage: w_{N-1} minimises 1/2 w'Qw w + lw'w + terminal(B w + a)
+    t = 2
+    B, QN = prob["B"][t], prob["QxN"]
+    G = prob["Qw"][t] + B.T @ QN @ B
+    w = -np.linalg.solve(G, prob["lw"][t] + B.T @ (QN @ prob["a"][t] + prob["lN"]))
+    np.testing.assert_allclose(sol["w"][t], w, rtol=1e-12, atol=1e-12)
+
+
+def test_scalar_hand_computed():
+    """n_x = n_u = 1, N = 1, every datum 1, zero linear terms: the Riccati
+    scalars are G = 2, K = -1/2, P_0 = 3/2, and w_0 = -x0/2."""
+    one = np.ones((1, 1, 1))
+    prob = dict(Qx=one, Qw=one, Qxw=0 * one, A=one, B=one, a=np.zeros((1, 1)),
+                lx=np.zeros((1, 1)), lw=np.zeros((1, 1)), c=np.zeros(1),
+                QxN=np.ones((1, 1)), lN=np.zeros(1), cN=0.0, x0=np.array([2.0]))
+    sol = riccati.solve(prob, want_factors=True)
+    assert sol["G"][0, 0, 0] == pytest.approx(2.0)
+    assert sol["K"][0, 0, 0] == pytest.approx(-0.5)
+    assert sol["P"][0, 0, 0] == pytest.approx(1.5)
+    assert sol["w"][0, 0] == pytest.approx(-1.0)
+    assert sol["obj"] == pytest.approx(0.5 * 1.5 * 4.0)
+
+
+def test_not_spd_is_reported():
+    prob = W.g1(2, 2, 4, seed=1)
+    prob["Qw"] = prob["Qw"].copy()
+    prob["Qw"][2] = -10.0 * np.eye(2)
+    prob["B"] = np.zeros_like(prob["B"])
+    with pytest.raises(riccati.OracleError, match="t=2"):
+        riccati.solve(prob)
+
+
+def _mhe_case(nx, ny, Nm, seed):
+    rng = np.random.default_rng(seed)
+    A0 = W._spectral_scale(rng.standard_normal((nx, nx)))
+    A = [A0 + 0.05 * rng.standard_normal((nx, nx)) for _ in range(Nm + 1)]
+    B = [rng.standard_normal((nx, nx)) / np.sqrt(nx) for _ in range(Nm + 1)]
+    a = [0.1 * rng.standard_normal(nx) for _ in range(Nm + 1)]
+    C = [rng.standard_normal((ny, nx)) for _ in range(Nm + 1)]
+    d = [0.1 * rng.standard_normal(ny) for _ in range(Nm + 1)]
+    y = [rng.standard_normal(ny) for _ in range(Nm + 1)]
+    wtil = [0.1 * rng.standard_normal(nx) for _ in range(Nm + 1)]
+    vtil = [0.1 * rng.standard_normal(ny) for _ in range(Nm + 1)]
+
+    def spd(k):
+        M = rng.standard_normal((k, k))
+        return M @ M.T / k + 0.5 * np.eye(k)
+
+    Qw = [spd(nx) for _ in range(Nm + 1)]
+    Qv = [spd(ny) for _ in range(Nm + 1)]
+    xtil0 = rng.standard_normal(nx)
+    P0 = spd(nx)
+    return A, B, a, C, d, y, xtil0, P0, wtil, vtil, Qw, Qv
+
+
+@pytest.mark.parametrize("nx,ny,Nm", [(3, 2, 6), (4, 4, 20), (2, 1, 0)])
+def test_oracle_vs_rts_smoother(nx, ny, Nm):
+    """MHE with uncorrelated noise (S = 0): the UFTOC solution of the paper's
+    conversion equals the RTS-smoothed state means x_0..x_{Nmhe+1}."""
+    args = _mhe_case(nx, ny, Nm, seed=nx * 100 + Nm)
+    prob = mhe.mhe_to_uftoc(*args)
+    sol = riccati.solve(prob)
+    ms = mhe.rts_smoother(*args)
+    # UFTOC state t is the MHE state k = t - 1 (t = 1..N)
+    np.testing.assert_allclose(sol["x"][1:], ms, rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(sol["x"][0], args[6], rtol=0, atol=0)
+
+
+def test_mhe_conversion_correlated_noise_matches_direct_map():
+    """Correlated noise (S != 0): the converted UFTOC optimum equals the
+    minimiser of the MHE objective of eq. org_mhe written directly over
+    (x_0, w_0..w_Nmhe) and solved by dense least squares."""
+    nx, ny, Nm = 2, 2, 3
+    rng = np.random.default_rng(42)
+    A, B, a, C, d, y, xtil0, P0, wtil, vtil, Qw, Qv = _mhe_case(nx, ny, Nm, seed=3)
+    Qwv = [0.2 * rng.standard_normal((nx, ny)) for _ in range(Nm + 1)]
+    prob = mhe.mhe_to_uftoc(A, B, a, C, d, y, xtil0, P0, wtil, vtil, Qw, Qv, Qwv)
+    sol = riccati.solve(prob)
+    # direct: unknowns u = (x0, w_0..w_Nm); x_k affine in u; cost = sum of
+    # squared whitened residuals -> linear least squares
+    nvar = nx + (Nm + 1) * nx
+    xs = []          # x_k = X_k u + x_k^c
+    Xk, xk = np.zeros((nx, nvar)), np.zeros(nx)
+    Xk[:, :nx] = np.eye(nx)
+    rows, rhs = [], []
+    Li = np.linalg.cholesky(np.linalg.inv(P0))
+    r0 = np.zeros((nx, nvar))
+    r0[:, :nx] = np.eye(nx)
+    rows.append(Li.T @ r0)
+    rhs.append(Li.T @ xtil0)
+    for k in range(Nm + 1):
+        xs.append((Xk.copy(), xk.copy()))
+        cov = np.block([[Qw[k], Qwv[k]], [Qwv[k].T, Qv[k]]])
+        Lc = np.linalg.cholesky(np.linalg.inv(cov))
+        Wsel = np.zeros((nx, nvar))
+        Wsel[:, nx + k * nx: nx + (k + 1) * nx] = np.eye(nx)
+        # [w - wtil; v - vtil] with v = y - C x - d
+        Rk = np.vstack([Wsel, -C[k] @ Xk])
+        ck = np.concatenate([wtil[k], vtil[k] - (y[k] - d[k] - C[k] @ xk)])
+        rows.append(Lc.T @ Rk)
+        rhs.append(Lc.T @ ck)
+        xk = A[k] @ xk + a[k]
+        Xk = A[k] @ Xk + B[k] @ Wsel
+    u = np.linalg.lstsq(np.vstack(rows), np.concatenate(rhs), rcond=None)[0]
+    for k, (Xm, xc) in enumerate(xs):
+        np.testing.assert_allclose(sol["x"][k + 1], Xm @ u + xc, rtol=1e-9, atol=1e-9)
