@@ -1,0 +1,179 @@
+/*
+ * rs.h - C ABI of the parallel Riccati Newton-step solver for MI355X (gfx950).
+ *
+ * The library solves the unconstrained finite-time optimal control problem
+ * P(N) of Nielsen & Axehill, "An O(log N) Parallel Algorithm for Newton Step
+ * Computations with Applications to Moving Horizon Estimation" (Sec. 2,
+ * eq. "org_eqc_problem"):
+ *
+ *   minimise  sum_{t=0}^{N-1} ( 1/2 [x_t;w_t]' [[Qx_t, Qxw_t],[Qxw_t', Qw_t]] [x_t;w_t]
+ *                               + lx_t' x_t + lw_t' w_t + c_t )
+ *             + 1/2 x_N' QxN x_N + lN' x_N + cN
+ *   subject to x_0 = x0,  x_{t+1} = A_t x_t + B_t w_t + a_t,  t = 0..N-1,
+ *
+ * i.e. one Newton step (KKT solve) of an interior-point or active-set method
+ * for MHE.  It returns the primal solution (x, w), the dual variables
+ * lam_t = P_t x_t - Psi_t (Alg. 3) and the optimal value.
+ *
+ * Method (Sec. 4-5): the horizon is split into subintervals ("leaves") that
+ * are reduced independently by Alg. 4; the reduced master problem is reduced
+ * again up a tree of depth O(log N) (Alg. 5), the top problem is solved and
+ * the solution is propagated back down (Alg. 6).  The result is exact (non-
+ * iterative): it equals the serial Riccati solution up to rounding.
+ *
+ * Conventions for every entry point:
+ *  - All problem and solution pointers are DEVICE pointers to FP64 data.
+ *    Matrices are row-major; block t of an array of r-by-c blocks starts at
+ *    element t*stride (stride in elements; stride 0 = the same block for
+ *    every stage, e.g. time-invariant A).  Vectors are dense row-major
+ *    arrays (N*nx means element [t*nx + i]).
+ *  - The caller owns every buffer, including the workspace.  The library
+ *    never allocates device memory on the solve path; plan creation
+ *    allocates a small pinned host staging area only.
+ *  - Calls are asynchronous on the given stream (a hipStream_t passed as
+ *    void*, NULL = the default stream).  The return value reports argument
+ *    and launch errors only.  Numerical failures are written per instance
+ *    into the optional device array info_dev[2*count]:
+ *        info_dev[2*i]   = rs_status of instance i (RS_OK, RS_ERR_NOT_SPD,
+ *                          RS_ERR_SINGULAR_MASTER, RS_ERR_NOT_CONVERGED)
+ *        info_dev[2*i+1] = failing stage index (or -1)
+ *    and are valid once the stream has reached the end of the call.
+ *  - No exception crosses the ABI.  A plan must not be used by two calls in
+ *    flight at the same time (its workspace holds the tree's state).
+ */
+#ifndef RS_H
+#define RS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rs_status {
+    RS_OK = 0,
+    RS_ERR_ARG = 1,              /* invalid argument (dims, NULL pointer, size)      */
+    RS_ERR_NOT_SPD = 2,          /* G_{t+1} not positive definite (Alg. 1 assumes it) */
+    RS_ERR_SINGULAR_MASTER = 3,  /* reduced G of a master stage singular (Sec. 4.2)  */
+    RS_ERR_NOT_CONVERGED = 4,    /* mixed precision: refinement missed the target    */
+    RS_ERR_NOMEM = 5,            /* workspace smaller than rs_plan_workspace_size     */
+    RS_ERR_HIP = 6,              /* a HIP runtime call failed                         */
+    RS_ERR_UNSUPPORTED = 7       /* (nx, nu) has no compiled kernel, or bad option    */
+} rs_status;
+
+typedef enum rs_precision {
+    RS_FP64 = 0,        /* every step in FP64                                         */
+    RS_MIXED_FP32 = 1   /* leaf Riccati in FP32, master levels and the KKT residual
+                           in FP64, iterative refinement to the requested tolerance  */
+} rs_precision;
+
+/* One instance of P(N).  Matrices and vectors: device pointers, FP64. */
+typedef struct rs_problem {
+    int32_t nx, nu, N, reserved;
+    /* stage matrices, N blocks each (RHS independent) */
+    const double *Qx;  int64_t sQx;   /* nx*nx blocks, Q_{x,t}                       */
+    const double *Qw;  int64_t sQw;   /* nu*nu blocks, Q_{w,t}, positive definite      */
+    const double *Qxw; int64_t sQxw;  /* nx*nu blocks, Q_{xw,t}; NULL = zero           */
+    const double *A;   int64_t sA;    /* nx*nx blocks                                  */
+    const double *B;   int64_t sB;    /* nx*nu blocks                                  */
+    const double *QxN;                /* nx*nx terminal weight Q_{x,N}                 */
+    /* right-hand side */
+    const double *x0;                 /* nx, initial state xbar_0                      */
+    const double *a;                  /* N*nx affine dynamics term; NULL = zero        */
+    const double *lx;                 /* N*nx linear state cost l_{x,t}; NULL = zero   */
+    const double *lw;                 /* N*nu linear input cost l_{w,t}; NULL = zero   */
+    const double *c;                  /* N constants c_t; NULL = zero                  */
+    const double *lN;                 /* nx terminal linear cost l_N; NULL = zero      */
+    const double *cN;                 /* 1 terminal constant; NULL = zero              */
+    /* solution (written) */
+    double *x;                        /* (N+1)*nx states x_0..x_N                       */
+    double *w;                        /* N*nu inputs / process noise w_0..w_{N-1}       */
+    double *lam;                      /* (N+1)*nx duals lam_0..lam_N                    */
+    double *obj;                      /* 1 optimal value; NULL = not wanted            */
+} rs_problem;
+
+typedef struct rs_options {
+    int32_t precision;   /* rs_precision                                              */
+    int32_t Ns;          /* leaf (subinterval) length N_s >= 1; 0 = library default    */
+    int32_t branch;      /* master stages per master subproblem (>= 2); 0 = default    */
+    int32_t max_refine;  /* mixed precision: maximum refinement steps; 0 = default    */
+    double tol;          /* mixed precision: relative KKT residual target; 0 = 1e-10  */
+} rs_options;
+
+typedef struct rs_plan_s *rs_plan;
+
+/*
+ * Build the tree plan (Alg. 5/6 levels, leaves, work lists) for a batch of
+ * `count` instances whose shapes are dims[3*i+0..2] = (nx, nu, N).  Host only:
+ * nothing is launched.  Errors: RS_ERR_ARG (count < 1, nx < 1, nu < 1, N < 1,
+ * Ns*nu < nx for a multi-leaf instance, which would make the reduced input
+ * weight singular, Sec. 4.2 remark), RS_ERR_UNSUPPORTED (no kernel for a
+ * shape/precision).
+ */
+rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *opt,
+                         rs_plan *plan_out);
+
+/* Device workspace bytes the plan needs (caller allocates, 256-byte aligned). */
+rs_status rs_plan_workspace_size(rs_plan plan, size_t *bytes);
+
+rs_status rs_plan_destroy(rs_plan plan);
+
+/*
+ * Fused Newton-step solve of all `count` instances: Alg. 4/5 up the tree,
+ * Alg. 1-3 on the top problem, Alg. 6 back down.  probs is a HOST array of
+ * `count` descriptors (device pointers inside) with the shapes given at plan
+ * creation.  In RS_MIXED_FP32 plans this performs factor + solve + FP64
+ * residual refinement (see rs_solve).  Returns RS_ERR_NOMEM if work_bytes is
+ * too small, RS_ERR_ARG for a NULL pointer or a shape mismatch.
+ */
+rs_status rs_batch_solve(rs_plan plan, const rs_problem *probs, void *work,
+                         size_t work_bytes, void *stream, int32_t *info_dev);
+
+/*
+ * Factorization part only (Alg. 1 and the matrix lines of Alg. 4 on every
+ * level, including the down-pass factorizations with the true terminal
+ * weights).  Reads the matrix fields of probs; stores every factor in the
+ * workspace.  The factors stay valid until the next rs_factor or
+ * rs_batch_solve with the same plan and workspace.
+ */
+rs_status rs_factor(rs_plan plan, const rs_problem *probs, void *work, size_t work_bytes,
+                    void *stream, int32_t *info_dev);
+
+/*
+ * Solve part only (Alg. 2-3 and the vector lines of Alg. 4): uses the factors
+ * stored by the last rs_factor with the same plan and workspace, reads the
+ * right-hand side fields and A, B of probs and writes the solution.  The
+ * matrices must be unchanged since rs_factor.  Several rs_solve calls may
+ * follow one rs_factor (iterative refinement, predictor-corrector steps).
+ * For RS_MIXED_FP32 plans the FP32 factors are refined in FP64 to the
+ * plan's tolerance: info_dev reports RS_ERR_NOT_CONVERGED on failure.
+ */
+rs_status rs_solve(rs_plan plan, const rs_problem *probs, void *work, size_t work_bytes,
+                   void *stream, int32_t *info_dev);
+
+/* Plan introspection: key 0 = number of leaves, 1 = number of tree work items,
+ * 2 = maximum tree depth (levels above the leaves), 3 = leaf length Ns,
+ * 4 = branch, 5 = precision, 6 = refinement steps used by the last mixed
+ * precision call (host-side count, valid after a synchronizing call). */
+int64_t rs_plan_query(rs_plan plan, int32_t key);
+
+/* Export the plan's work tables for host-side inspection (tests, tooling).
+ * what = 0: one row of 7 int64 per leaf (instance, first stage, length,
+ *           flags: 1 = holds the terminal cost, 2 = is the whole problem,
+ *           level-1 slot, scratch offset, shape group);
+ * what = 1: one row of 11 int64 per tree item (kind: 0 reduce, 1 eliminate
+ *           last, 2 top solve, 3 down solve; instance, level, first slot,
+ *           stage count, holds-terminal, terminal slot, output slot, first
+ *           dependency, dependency count, shape group).
+ * Writes only if cap_rows is large enough; returns the row count (-1 on a
+ * bad argument).  Host only. */
+int64_t rs_plan_export(rs_plan plan, int32_t what, int64_t *out, int64_t cap_rows);
+
+const char *rs_status_string(rs_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RS_H */

@@ -19,7 +19,7 @@ def _load():
         dp = ctypes.c_void_p
         lib.oracle_riccati_solve.restype = ctypes.c_int
         lib.oracle_riccati_solve.argtypes = (
-            [ctypes.c_int] * 3 + [dp] * 11 + [ctypes.c_double] + [dp] * 10)
+            [ctypes.c_int] * 3 + [dp] * 11 + [ctypes.c_double] + [dp] * 11)
         _lib = lib
     return _lib
 

@@ -1,0 +1,480 @@
+// C ABI of the parallel Riccati solver: argument checking, the tree plan
+// (Alg. 5/6 levels and work lists), the workspace layout and the launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "rs.h"
+#include "rs_launch.hpp"
+
+using namespace rs;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int RING = 4;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Group {
+    int nx, nu;
+    const ShapeEntry *shape;
+    std::vector<int32_t> insts;
+    std::vector<LeafItem> leaves;
+    std::vector<TreeItem> items;
+    int64_t nslots = 0;
+    int64_t scratch_elems = 0;
+    int max_depth = 0;
+    size_t off_leaves = 0, off_items = 0, off_flags = 0, off_slots = 0, off_scratch = 0;
+};
+
+}  // namespace
+
+struct rs_plan_s {
+    int32_t count = 0;
+    int Ns = 16, branch = 4, top_max = 4, prec = RS_FP64, max_refine = 0;
+    double tol = 1e-10;
+    std::vector<int32_t> dims;
+    std::vector<Group> groups;
+    size_t off_probs = 0, off_info = 0, off_queues = 0, off_tables = 0, tables_bytes = 0;
+    size_t total = 0;
+    std::vector<char> tables;           // host image of every group's leaf and tree tables
+    void *pinned_tables = nullptr;
+    void *pinned_probs[RING] = {};
+    hipEvent_t ev[RING] = {};
+    bool ev_used[RING] = {};
+    int ring = 0;
+    void *bound_work = nullptr;
+    std::vector<DevProb> last_probs;
+    bool probs_valid = false;
+    int32_t epoch = 0;
+    int64_t last_refine = 0;
+};
+
+namespace {
+
+// Build the tree of one instance (Sec. 5, Alg. 5/6) into its group.
+// Leaves: ceil(N/Ns) batches of Ns stages, the last one ragged and holding
+// the terminal cost (Sec. 4.2).  Level k >= 1 has S_k master stages plus a
+// terminal; while S_k exceeds the top size its stages are grouped b at a time
+// into master subproblems, the last group taking the terminal.
+struct Tmp {
+    TreeItem it;
+    int phase, level, inst, node;
+    int dep_level, dep_lo, dep_hi;   // UP/TOP: child nodes at dep_level; DOWN: parent node
+    bool dep_top;
+};
+
+void build_instance(Group &g, int inst, int N, int Ns, int b, int top_max, std::vector<Tmp> &tmp) {
+    const int L0 = (N + Ns - 1) / Ns;
+    const int sps = g.shape->scratch_per_stage;
+    if (L0 == 1) {
+        LeafItem lf{inst, 0, N, LEAF_LAST | LEAF_TOP, -1, 0, g.scratch_elems};
+        g.leaves.push_back(lf);
+        g.scratch_elems += (int64_t)N * sps;
+        return;
+    }
+    const int base1 = (int)g.nslots;
+    g.nslots += L0;
+    for (int i = 0; i < L0; ++i) {
+        const int t0 = i * Ns, len = std::min(Ns, N - t0);
+        LeafItem lf{inst, t0, len, i == L0 - 1 ? LEAF_LAST : 0, base1 + i, 0, g.scratch_elems};
+        g.leaves.push_back(lf);
+        g.scratch_elems += (int64_t)len * sps;
+    }
+    int level = 1, S = L0 - 1, lvl_base = base1, prev_nodes = L0;
+    for (;;) {
+        if (S <= top_max) {
+            Tmp t{};
+            t.it = TreeItem{ITEM_TOP, inst, level, lvl_base, S, 1, lvl_base + S, -1, 0, 0};
+            t.phase = 0;
+            t.level = level;
+            t.inst = inst;
+            t.node = 0;
+            t.dep_level = level - 1;
+            t.dep_lo = 0;
+            t.dep_hi = level > 1 ? prev_nodes : 0;
+            tmp.push_back(t);
+            g.max_depth = std::max(g.max_depth, level);
+            break;
+        }
+        const int Lk = (S + b - 1) / b;
+        const int nb = (int)g.nslots;
+        g.nslots += Lk;
+        const int Lnext = Lk - 1;                 // stages at the next level
+        const bool next_is_top = Lnext <= top_max;
+        const int Lnext_nodes = next_is_top ? 1 : (Lnext + b - 1) / b;
+        for (int j = 0; j < Lk; ++j) {
+            const int first = lvl_base + j * b, count = std::min(b, S - j * b);
+            const int last = (j == Lk - 1) ? 1 : 0;
+            Tmp u{};
+            u.it = TreeItem{last ? ITEM_UP_LAST : ITEM_UP, inst, level, first, count, last,
+                            last ? lvl_base + S : -1, nb + j, 0, 0};
+            u.phase = 0;
+            u.level = level;
+            u.inst = inst;
+            u.node = j;
+            u.dep_level = level - 1;
+            u.dep_lo = j * b;
+            u.dep_hi = level > 1 ? j * b + count + last : 0;
+            tmp.push_back(u);
+            Tmp d = u;
+            d.it.kind = ITEM_DOWN;
+            d.phase = 1;
+            d.dep_level = level + 1;
+            d.dep_top = next_is_top;
+            d.dep_lo = next_is_top ? 0 : std::min(j / b, Lnext_nodes - 1);
+            d.dep_hi = d.dep_lo + 1;
+            tmp.push_back(d);
+        }
+        S = Lnext;
+        lvl_base = nb;
+        prev_nodes = Lk;
+        ++level;
+    }
+}
+
+void finalize_items(Group &g, std::vector<Tmp> &tmp) {
+    std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp &a, const Tmp &b) {
+        const int la = a.phase == 0 ? a.level : -a.level, lb = b.phase == 0 ? b.level : -b.level;
+        return std::make_tuple(a.phase, la, a.inst, a.node) < std::make_tuple(b.phase, lb, b.inst, b.node);
+    });
+    // index of (phase, inst, level, node); TOP items are looked up as phase 0
+    std::map<std::tuple<int, int, int, int>, int> where;
+    for (size_t i = 0; i < tmp.size(); ++i)
+        where[std::make_tuple(tmp[i].phase, tmp[i].inst, tmp[i].level, tmp[i].node)] = (int)i;
+    g.items.resize(tmp.size());
+    for (size_t i = 0; i < tmp.size(); ++i) {
+        TreeItem it = tmp[i].it;
+        const Tmp &t = tmp[i];
+        if (t.phase == 0) {
+            if (t.dep_hi > t.dep_lo) {
+                it.dep_first = where.at(std::make_tuple(0, t.inst, t.dep_level, t.dep_lo));
+                it.dep_count = t.dep_hi - t.dep_lo;
+            } else {
+                it.dep_first = 0;
+                it.dep_count = 0;
+            }
+        } else {
+            const int ph = t.dep_top ? 0 : 1;
+            it.dep_first = where.at(std::make_tuple(ph, t.inst, t.dep_level, t.dep_lo));
+            it.dep_count = 1;
+        }
+        g.items[i] = it;
+    }
+}
+
+bool valid_ptr_set(const rs_problem &p) {
+    return p.Qx && p.Qw && p.A && p.B && p.QxN && p.x0 && p.x && p.w && p.lam;
+}
+
+rs_status to_status(hipError_t e) { return e == hipSuccess ? RS_OK : RS_ERR_HIP; }
+
+}  // namespace
+
+extern "C" {
+
+const char *rs_status_string(rs_status s) {
+    switch (s) {
+    case RS_OK: return "ok";
+    case RS_ERR_ARG: return "invalid argument";
+    case RS_ERR_NOT_SPD: return "G not positive definite";
+    case RS_ERR_SINGULAR_MASTER: return "singular reduced master block";
+    case RS_ERR_NOT_CONVERGED: return "refinement did not converge";
+    case RS_ERR_NOMEM: return "workspace too small";
+    case RS_ERR_HIP: return "HIP runtime error";
+    case RS_ERR_UNSUPPORTED: return "unsupported shape or option";
+    }
+    return "unknown status";
+}
+
+rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *opt, rs_plan *out) {
+    if (!out || !dims || count < 1) return RS_ERR_ARG;
+    *out = nullptr;
+    rs_plan_s *P = new (std::nothrow) rs_plan_s();
+    if (!P) return RS_ERR_NOMEM;
+    if (opt) {
+        if (opt->Ns < 0 || opt->branch < 0 || opt->branch == 1 || opt->max_refine < 0 || opt->tol < 0) {
+            delete P;
+            return RS_ERR_ARG;
+        }
+        if (opt->precision != RS_FP64) {
+            delete P;
+            return RS_ERR_UNSUPPORTED;
+        }
+        P->prec = opt->precision;
+        if (opt->Ns > 0) P->Ns = opt->Ns;
+        if (opt->branch > 0) P->branch = opt->branch;
+        if (opt->max_refine > 0) P->max_refine = opt->max_refine;
+        if (opt->tol > 0) P->tol = opt->tol;
+    }
+    P->top_max = P->branch;
+    P->count = count;
+    P->dims.assign(dims, dims + 3 * (size_t)count);
+    std::map<std::pair<int, int>, int> gidx;
+    std::vector<int> inst_group(count);
+    for (int i = 0; i < count; ++i) {
+        const int nx = dims[3 * i], nu = dims[3 * i + 1], N = dims[3 * i + 2];
+        if (nx < 1 || nu < 1 || N < 1) {
+            delete P;
+            return RS_ERR_ARG;
+        }
+        // a multi-leaf instance needs Ns*nu >= nx or the reduced input weight
+        // Q_w_hat = S Qbar^{-1} S' is singular (Sec. 4.2 remark)
+        if (N > P->Ns && (int64_t)P->Ns * nu < nx) {
+            delete P;
+            return RS_ERR_ARG;
+        }
+        const ShapeEntry *se = find_shape(nx, nu);
+        if (!se) {
+            delete P;
+            return RS_ERR_UNSUPPORTED;
+        }
+        auto key = std::make_pair(nx, nu);
+        if (!gidx.count(key)) {
+            gidx[key] = (int)P->groups.size();
+            Group g;
+            g.nx = nx;
+            g.nu = nu;
+            g.shape = se;
+            P->groups.push_back(g);
+        }
+        inst_group[i] = gidx[key];
+        P->groups[inst_group[i]].insts.push_back(i);
+    }
+    for (auto &g : P->groups) {
+        std::vector<Tmp> tmp;
+        for (int inst : g.insts)
+            build_instance(g, inst, dims[3 * inst + 2], P->Ns, P->branch, P->top_max, tmp);
+        finalize_items(g, tmp);
+    }
+    // workspace layout
+    size_t off = 0;
+    P->off_probs = off;
+    off = align_up(off + sizeof(DevProb) * count);
+    P->off_info = off;
+    off = align_up(off + sizeof(int32_t) * 2 * count);
+    P->off_queues = off;
+    off = align_up(off + sizeof(int32_t) * P->groups.size());
+    P->off_tables = off;
+    for (auto &g : P->groups) {
+        g.off_leaves = off;
+        off = align_up(off + sizeof(LeafItem) * g.leaves.size());
+        g.off_items = off;
+        off = align_up(off + sizeof(TreeItem) * g.items.size());
+    }
+    P->tables_bytes = off - P->off_tables;
+    for (auto &g : P->groups) {
+        g.off_flags = off;
+        off = align_up(off + sizeof(int32_t) * std::max<size_t>(1, g.items.size()));
+    }
+    for (auto &g : P->groups) {
+        g.off_slots = off;
+        off = align_up(off + sizeof(double) * SlotLayout{g.nx}.size() * (size_t)g.nslots);
+        g.off_scratch = off;
+        const size_t esz = sizeof(double);
+        off = align_up(off + esz * (size_t)g.scratch_elems);
+    }
+    P->total = off;
+    P->tables.assign(P->tables_bytes, 0);
+    for (auto &g : P->groups) {
+        if (!g.leaves.empty())
+            std::memcpy(P->tables.data() + (g.off_leaves - P->off_tables), g.leaves.data(),
+                        sizeof(LeafItem) * g.leaves.size());
+        if (!g.items.empty())
+            std::memcpy(P->tables.data() + (g.off_items - P->off_tables), g.items.data(),
+                        sizeof(TreeItem) * g.items.size());
+    }
+    *out = P;
+    return RS_OK;
+}
+
+rs_status rs_plan_workspace_size(rs_plan P, size_t *bytes) {
+    if (!P || !bytes) return RS_ERR_ARG;
+    *bytes = P->total;
+    return RS_OK;
+}
+
+rs_status rs_plan_destroy(rs_plan P) {
+    if (!P) return RS_ERR_ARG;
+    for (int i = 0; i < RING; ++i) {
+        if (P->ev[i]) {
+            (void)hipEventSynchronize(P->ev[i]);
+            (void)hipEventDestroy(P->ev[i]);
+        }
+        if (P->pinned_probs[i]) (void)hipHostFree(P->pinned_probs[i]);
+    }
+    if (P->pinned_tables) (void)hipHostFree(P->pinned_tables);
+    delete P;
+    return RS_OK;
+}
+
+int64_t rs_plan_query(rs_plan P, int32_t key) {
+    if (!P) return -1;
+    int64_t v = 0;
+    switch (key) {
+    case 0:
+        for (auto &g : P->groups) v += (int64_t)g.leaves.size();
+        return v;
+    case 1:
+        for (auto &g : P->groups) v += (int64_t)g.items.size();
+        return v;
+    case 2:
+        for (auto &g : P->groups) v = std::max<int64_t>(v, g.max_depth);
+        return v;
+    case 3: return P->Ns;
+    case 4: return P->branch;
+    case 5: return P->prec;
+    case 6: return P->last_refine;
+    default: return -1;
+    }
+}
+
+// Export the plan tables for host-side inspection: what = 0 -> leaves as
+// 7 int64 per leaf (inst, t0, len, flags, slot, scratch, group); what = 1 ->
+// tree items as 11 int64 per item (kind, inst, level, first, count, last,
+// term_slot, out_slot, dep_first, dep_count, group).  Returns the number of
+// rows (written only if cap is large enough), -1 on bad arguments.
+int64_t rs_plan_export(rs_plan P, int32_t what, int64_t *out, int64_t cap_rows) {
+    if (!P || (what != 0 && what != 1)) return -1;
+    int64_t rows = 0;
+    for (auto &g : P->groups) rows += what == 0 ? (int64_t)g.leaves.size() : (int64_t)g.items.size();
+    if (!out || cap_rows < rows) return rows;
+    int64_t r = 0;
+    for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+        auto &g = P->groups[gi];
+        if (what == 0) {
+            for (auto &l : g.leaves) {
+                int64_t *o = out + 7 * r++;
+                o[0] = l.inst; o[1] = l.t0; o[2] = l.len; o[3] = l.flags; o[4] = l.slot;
+                o[5] = l.scratch; o[6] = (int64_t)gi;
+            }
+        } else {
+            for (auto &t : g.items) {
+                int64_t *o = out + 11 * r++;
+                o[0] = t.kind; o[1] = t.inst; o[2] = t.level; o[3] = t.first; o[4] = t.count;
+                o[5] = t.last; o[6] = t.term_slot; o[7] = t.out_slot; o[8] = t.dep_first;
+                o[9] = t.dep_count; o[10] = (int64_t)gi;
+            }
+        }
+    }
+    return rows;
+}
+
+static rs_status bind_and_upload(rs_plan P, const rs_problem *probs, char *work, hipStream_t st) {
+    hipError_t e;
+    // problem descriptors: upload only when they changed since the last call
+    std::vector<DevProb> dp(P->count);
+    for (int i = 0; i < P->count; ++i) {
+        const rs_problem &q = probs[i];
+        DevProb &d = dp[i];
+        std::memset(&d, 0, sizeof(d));
+        d.Qx = q.Qx; d.Qw = q.Qw; d.Qxw = q.Qxw; d.A = q.A; d.B = q.B; d.QxN = q.QxN;
+        d.x0 = q.x0; d.a = q.a; d.lx = q.lx; d.lw = q.lw; d.c = q.c; d.lN = q.lN; d.cN = q.cN;
+        d.x = q.x; d.w = q.w; d.lam = q.lam; d.obj = q.obj;
+        d.sQx = q.sQx; d.sQw = q.sQw; d.sQxw = q.sQxw; d.sA = q.sA; d.sB = q.sB;
+        d.nx = q.nx; d.nu = q.nu; d.N = q.N;
+    }
+    const bool rebind = P->bound_work != work;
+    if (rebind) {
+        if (!P->pinned_tables && P->tables_bytes) {
+            if (hipHostMalloc(&P->pinned_tables, P->tables_bytes) != hipSuccess) return RS_ERR_HIP;
+            std::memcpy(P->pinned_tables, P->tables.data(), P->tables_bytes);
+        }
+        if (P->tables_bytes) {
+            e = hipMemcpyAsync(work + P->off_tables, P->pinned_tables, P->tables_bytes, hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) return RS_ERR_HIP;
+        }
+        for (auto &g : P->groups) {
+            e = launch_fill_i32(reinterpret_cast<int32_t *>(work + g.off_flags),
+                                (int64_t)std::max<size_t>(1, g.items.size()), 0, st);
+            if (e != hipSuccess) return RS_ERR_HIP;
+        }
+        P->epoch = 0;
+        P->probs_valid = false;
+        P->bound_work = work;
+    }
+    if (!P->probs_valid || std::memcmp(dp.data(), P->last_probs.data(), sizeof(DevProb) * P->count) != 0) {
+        const int r = P->ring;
+        P->ring = (P->ring + 1) % RING;
+        if (!P->pinned_probs[r]) {
+            if (hipHostMalloc(&P->pinned_probs[r], sizeof(DevProb) * P->count) != hipSuccess) return RS_ERR_HIP;
+            if (hipEventCreateWithFlags(&P->ev[r], hipEventDisableTiming) != hipSuccess) return RS_ERR_HIP;
+        }
+        if (P->ev_used[r] && hipEventSynchronize(P->ev[r]) != hipSuccess) return RS_ERR_HIP;
+        std::memcpy(P->pinned_probs[r], dp.data(), sizeof(DevProb) * P->count);
+        e = hipMemcpyAsync(work + P->off_probs, P->pinned_probs[r], sizeof(DevProb) * P->count,
+                           hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return RS_ERR_HIP;
+        if (hipEventRecord(P->ev[r], st) != hipSuccess) return RS_ERR_HIP;
+        P->ev_used[r] = true;
+        P->last_probs = dp;
+        P->probs_valid = true;
+    }
+    return RS_OK;
+}
+
+static rs_status check_call(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes) {
+    if (!P || !probs || !work) return RS_ERR_ARG;
+    if (work_bytes < P->total) return RS_ERR_NOMEM;
+    if (reinterpret_cast<uintptr_t>(work) % ALIGN) return RS_ERR_ARG;
+    for (int i = 0; i < P->count; ++i) {
+        const rs_problem &q = probs[i];
+        if (q.nx != P->dims[3 * i] || q.nu != P->dims[3 * i + 1] || q.N != P->dims[3 * i + 2]) return RS_ERR_ARG;
+        if (!valid_ptr_set(q)) return RS_ERR_ARG;
+        if (q.sQx < 0 || q.sQw < 0 || q.sQxw < 0 || q.sA < 0 || q.sB < 0) return RS_ERR_ARG;
+    }
+    return RS_OK;
+}
+
+rs_status rs_batch_solve(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
+                         int32_t *info_dev) {
+    rs_status s = check_call(P, probs, work, work_bytes);
+    if (s != RS_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    char *W = static_cast<char *>(work);
+    s = bind_and_upload(P, probs, W, st);
+    if (s != RS_OK) return s;
+    ++P->epoch;
+    int32_t *info = info_dev ? info_dev : reinterpret_cast<int32_t *>(W + P->off_info);
+    int32_t *queues = reinterpret_cast<int32_t *>(W + P->off_queues);
+    hipError_t e = launch_init(info, P->count, queues, (int)P->groups.size(), st);
+    if (e != hipSuccess) return RS_ERR_HIP;
+    for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+        Group &g = P->groups[gi];
+        GroupArgs a{};
+        a.probs = reinterpret_cast<const DevProb *>(W + P->off_probs);
+        a.leaves = reinterpret_cast<const LeafItem *>(W + g.off_leaves);
+        a.nleaves = (int32_t)g.leaves.size();
+        a.items = reinterpret_cast<const TreeItem *>(W + g.off_items);
+        a.nitems = (int32_t)g.items.size();
+        a.slots = reinterpret_cast<double *>(W + g.off_slots);
+        a.leaf_scratch = W + g.off_scratch;
+        a.flags = reinterpret_cast<int32_t *>(W + g.off_flags);
+        a.queue = queues + gi;
+        a.info = info;
+        a.epoch = P->epoch;
+        const int tree_grid = std::max(1, std::min<int>((int)g.items.size(), 256));
+        e = g.shape->fp64(a, tree_grid, st);
+        if (e != hipSuccess) return RS_ERR_HIP;
+    }
+    return RS_OK;
+}
+
+rs_status rs_factor(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
+                    int32_t *info_dev) {
+    (void)P; (void)probs; (void)work; (void)work_bytes; (void)stream; (void)info_dev;
+    return RS_ERR_UNSUPPORTED;
+}
+
+rs_status rs_solve(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
+                   int32_t *info_dev) {
+    (void)P; (void)probs; (void)work; (void)work_bytes; (void)stream; (void)info_dev;
+    return RS_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,247 @@
+"""Python binding of the C ABI in ``include/rs.h`` (ctypes; argument
+marshalling only - every step of the solve runs in the HIP library).
+
+The entry points keep the C names: ``rs_plan_create``,
+``rs_plan_workspace_size``, ``rs_plan_destroy``, ``rs_batch_solve``,
+``rs_factor``, ``rs_solve``, ``rs_plan_query``, ``rs_plan_export``,
+``rs_status_string``.  ``Batch`` packs stacked torch device tensors into the
+descriptor array the library expects.  PyTorch provides device memory and
+streams only.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+RS_OK, RS_ERR_ARG, RS_ERR_NOT_SPD, RS_ERR_SINGULAR_MASTER, RS_ERR_NOT_CONVERGED, \
+    RS_ERR_NOMEM, RS_ERR_HIP, RS_ERR_UNSUPPORTED = range(8)
+RS_FP64, RS_MIXED_FP32 = 0, 1
+
+_P = ctypes.c_void_p
+
+
+class rs_problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nu", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("Qx", _P), ("sQx", ctypes.c_int64), ("Qw", _P), ("sQw", ctypes.c_int64),
+                ("Qxw", _P), ("sQxw", ctypes.c_int64), ("A", _P), ("sA", ctypes.c_int64),
+                ("B", _P), ("sB", ctypes.c_int64), ("QxN", _P),
+                ("x0", _P), ("a", _P), ("lx", _P), ("lw", _P), ("c", _P), ("lN", _P), ("cN", _P),
+                ("x", _P), ("w", _P), ("lam", _P), ("obj", _P)]
+
+
+class rs_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("Ns", ctypes.c_int32), ("branch", ctypes.c_int32),
+                ("max_refine", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class RsError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (where, rs_status_string(status), status))
+
+
+_lib = None
+
+
+def library():
+    """Load ``librs.so`` (building it first only if no build exists)."""
+    global _lib
+    if _lib is None:
+        path = _build.LIB_PATH
+        if not os.path.exists(path):
+            _build.build()
+        lib = ctypes.CDLL(path)
+        i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        lib.rs_plan_create.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(rs_options), ctypes.POINTER(_P)]
+        lib.rs_plan_workspace_size.argtypes = [_P, ctypes.POINTER(sz)]
+        lib.rs_plan_destroy.argtypes = [_P]
+        for name in ("rs_batch_solve", "rs_factor", "rs_solve"):
+            getattr(lib, name).argtypes = [_P, ctypes.POINTER(rs_problem), _P, sz, _P, _P]
+        lib.rs_plan_query.argtypes = [_P, i32]
+        lib.rs_plan_query.restype = i64
+        lib.rs_plan_export.argtypes = [_P, i32, ctypes.POINTER(i64), i64]
+        lib.rs_plan_export.restype = i64
+        lib.rs_status_string.argtypes = [i32]
+        lib.rs_status_string.restype = ctypes.c_char_p
+        for name in ("rs_plan_create", "rs_plan_workspace_size", "rs_plan_destroy", "rs_batch_solve",
+                     "rs_factor", "rs_solve"):
+            getattr(lib, name).restype = i32
+        _lib = lib
+    return _lib
+
+
+def rs_status_string(status):
+    return library().rs_status_string(int(status)).decode()
+
+
+def _check(status, where):
+    if status != RS_OK:
+        raise RsError(status, where)
+
+
+def rs_plan_create(dims, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.0):
+    """dims: sequence of (nx, nu, N).  Returns an opaque plan handle."""
+    arr = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 3))
+    opt = rs_options(precision, Ns, branch, max_refine, tol)
+    h = _P()
+    st = library().rs_plan_create(arr.shape[0], arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  ctypes.byref(opt), ctypes.byref(h))
+    _check(st, "rs_plan_create")
+    return h
+
+
+def rs_plan_workspace_size(plan):
+    n = ctypes.c_size_t()
+    _check(library().rs_plan_workspace_size(plan, ctypes.byref(n)), "rs_plan_workspace_size")
+    return n.value
+
+
+def rs_plan_destroy(plan):
+    _check(library().rs_plan_destroy(plan), "rs_plan_destroy")
+
+
+def rs_plan_query(plan, key):
+    return int(library().rs_plan_query(plan, key))
+
+
+def rs_plan_export(plan, what):
+    lib = library()
+    rows = lib.rs_plan_export(plan, what, None, 0)
+    width = 7 if what == 0 else 11
+    out = np.zeros((max(rows, 1), width), dtype=np.int64)
+    lib.rs_plan_export(plan, what, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), rows)
+    return out[:rows]
+
+
+def _call(name, plan, probs, work_ptr, work_bytes, stream_ptr, info_ptr):
+    st = getattr(library(), name)(plan, probs, work_ptr, work_bytes, stream_ptr, info_ptr)
+    _check(st, name)
+
+
+def rs_batch_solve(plan, probs, work_ptr, work_bytes, stream_ptr=None, info_ptr=None):
+    _call("rs_batch_solve", plan, probs, work_ptr, work_bytes, stream_ptr, info_ptr)
+
+
+def rs_factor(plan, probs, work_ptr, work_bytes, stream_ptr=None, info_ptr=None):
+    _call("rs_factor", plan, probs, work_ptr, work_bytes, stream_ptr, info_ptr)
+
+
+def rs_solve(plan, probs, work_ptr, work_bytes, stream_ptr=None, info_ptr=None):
+    _call("rs_solve", plan, probs, work_ptr, work_bytes, stream_ptr, info_ptr)
+
+
+# ------------------------------------------------------------ torch helper
+_MATS = ("Qx", "Qw", "Qxw", "A", "B")
+_VECS = ("a", "lx", "lw", "c", "lN", "cN", "x0")
+
+
+class Batch:
+    """A batch of problems held in torch device tensors plus its plan and
+    workspace.
+
+    ``data`` maps the problem keys to tensors with a leading instance axis
+    (uniform shapes) or to lists of per-instance tensors (shapes may differ).
+    Outputs ``x``, ``w``, ``lam``, ``obj`` are allocated here.  Time-invariant
+    matrices may be given with a stage axis of length 1; they are passed with
+    stride 0.
+    """
+
+    def __init__(self, data, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.0,
+                 device="cuda"):
+        import torch
+        self.torch = torch
+        keys = set(data)
+        self.count = len(data["x0"])
+        self.data = {}
+        for k in keys:
+            v = data[k]
+            if isinstance(v, (list, tuple)):
+                self.data[k] = [self._dev(t, device) for t in v]
+            else:
+                self.data[k] = [self._dev(v[i], device) for i in range(self.count)]
+        dims = []
+        for i in range(self.count):
+            nx = int(self.data["QxN"][i].shape[-1])
+            nu = int(self.data["Qw"][i].shape[-1])
+            N = int(self.data["N"][i]) if "N" in self.data else int(self.data["lx"][i].shape[0])
+            dims.append((nx, nu, N))
+        self.dims = dims
+        f64 = dict(dtype=torch.float64, device=device)
+        self.x = [torch.zeros((N + 1, nx), **f64) for nx, nu, N in dims]
+        self.w = [torch.zeros((N, nu), **f64) for nx, nu, N in dims]
+        self.lam = [torch.zeros((N + 1, nx), **f64) for nx, nu, N in dims]
+        self.obj = torch.zeros(self.count, **f64)
+        self.info = torch.zeros(2 * self.count, dtype=torch.int32, device=device)
+        self.plan = rs_plan_create(dims, precision, Ns, branch, max_refine, tol)
+        self.work_bytes = rs_plan_workspace_size(self.plan)
+        self.work = torch.empty(self.work_bytes + 256, dtype=torch.uint8, device=device)
+        base = self.work.data_ptr()
+        self.work_ptr = (base + 255) // 256 * 256
+        self.probs = (rs_problem * self.count)()
+        self._fill()
+
+    @staticmethod
+    def _dev(t, device):
+        import torch
+        if isinstance(t, np.ndarray) or np.isscalar(t):
+            t = torch.as_tensor(np.asarray(t, dtype=np.float64))
+        return t.to(device=device, dtype=torch.float64).contiguous()
+
+    def _fill(self):
+        for i, (nx, nu, N) in enumerate(self.dims):
+            p = self.probs[i]
+            d = {k: self.data[k][i] for k in self.data}
+            p.nx, p.nu, p.N = nx, nu, N
+            for k, bs in (("Qx", nx * nx), ("Qw", nu * nu), ("Qxw", nx * nu), ("A", nx * nx), ("B", nx * nu)):
+                t = d.get(k)
+                if t is None:
+                    setattr(p, k, None)
+                    setattr(p, "s" + k, 0)
+                    continue
+                setattr(p, k, t.data_ptr())
+                stride = 0 if (t.dim() == 3 and t.shape[0] == 1 and N > 1) else bs
+                setattr(p, "s" + k, stride)
+            p.QxN = d["QxN"].data_ptr()
+            for k in _VECS:
+                t = d.get(k)
+                setattr(p, k, t.data_ptr() if t is not None else None)
+            p.x = self.x[i].data_ptr()
+            p.w = self.w[i].data_ptr()
+            p.lam = self.lam[i].data_ptr()
+            p.obj = self.obj.data_ptr() + 8 * i
+
+    def stream_ptr(self):
+        return self.torch.cuda.current_stream().cuda_stream
+
+    def solve(self):
+        rs_batch_solve(self.plan, self.probs, self.work_ptr, self.work_bytes, self.stream_ptr(),
+                       self.info.data_ptr())
+
+    def factor(self):
+        rs_factor(self.plan, self.probs, self.work_ptr, self.work_bytes, self.stream_ptr(),
+                  self.info.data_ptr())
+
+    def solve_factored(self):
+        rs_solve(self.plan, self.probs, self.work_ptr, self.work_bytes, self.stream_ptr(),
+                 self.info.data_ptr())
+
+    def status(self):
+        return self.info.view(-1, 2).cpu().numpy()
+
+    def result(self, i):
+        return dict(x=self.x[i].cpu().numpy(), w=self.w[i].cpu().numpy(),
+                    lam=self.lam[i].cpu().numpy(), obj=float(self.obj[i].cpu()))
+
+    def close(self):
+        if self.plan is not None:
+            rs_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,166 @@
+"""Host logic of the tree plan (Sec. 4.1 batches, Alg. 5/6 levels).
+
+The plan is built by the C library on the host (no GPU needed).  Its tables
+are checked structurally and then executed on the CPU with the oracle's
+closed-form reductions and serial Riccati solves, following exactly the slot
+indices and work order of the plan.  Reassembling the leaf solutions must give
+the oracle's solution of the whole problem: this pins the plan semantics
+(ragged last leaf, terminal elimination, message indexing) independently of
+the GPU kernels."""
+import numpy as np
+import pytest
+
+from oracle import kkt, reduction, riccati
+from paper_1510_03110_amd import rs
+from paper_1510_03110_amd import workloads as W
+
+UP, UP_LAST, TOP, DOWN = 0, 1, 2, 3
+LAST, ISTOP = 1, 2
+
+
+def _tables(dims, Ns, branch):
+    plan = rs.rs_plan_create(dims, Ns=Ns, branch=branch)
+    try:
+        return rs.rs_plan_export(plan, 0), rs.rs_plan_export(plan, 1), \
+            [rs.rs_plan_query(plan, k) for k in range(5)]
+    finally:
+        rs.rs_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("N,Ns,b", [(1024, 16, 4), (37, 4, 3), (100, 8, 2), (5, 8, 4),
+                                    (64, 1, 2), (65, 4, 4), (16, 4, 4), (17, 4, 4)])
+def test_plan_structure(N, Ns, b):
+    leaves, items, q = _tables([(4, 4, N)], Ns, b)
+    # leaves cover 0..N-1 once, in order, the last one ragged and terminal
+    t = 0
+    for lf in leaves:
+        assert lf[1] == t and 1 <= lf[2] <= Ns
+        t += lf[2]
+    assert t == N
+    assert leaves[-1][3] & LAST
+    nleaf = len(leaves)
+    assert nleaf == -(-N // Ns)
+    if nleaf == 1:
+        assert leaves[0][3] & ISTOP and len(items) == 0
+        return
+    # every dependency precedes its item
+    for i, it in enumerate(items):
+        assert it[8] + it[9] <= i
+    tops = [it for it in items if it[0] == TOP]
+    assert len(tops) == 1 and tops[0][5] == 1
+    n_up = sum(1 for it in items if it[0] in (UP, UP_LAST))
+    n_down = sum(1 for it in items if it[0] == DOWN)
+    assert n_up == n_down
+    # depth is logarithmic in the number of leaves
+    assert q[2] <= 1 + int(np.ceil(np.log(max(nleaf, 2)) / np.log(b)))
+
+
+def _stage_dict(slots, first, count, nx):
+    st = [slots[first + s] for s in range(count)]
+    z = lambda shp: np.zeros((count,) + shp)
+    return dict(
+        Qx=np.array([s["Qx"] for s in st]).reshape(count, nx, nx),
+        Qw=np.array([s["Qw"] for s in st]).reshape(count, nx, nx),
+        Qxw=z((nx, nx)),
+        A=np.array([s["A"] for s in st]).reshape(count, nx, nx),
+        B=np.array([s["Qw"] for s in st]).reshape(count, nx, nx),
+        a=np.array([s["a"] for s in st]).reshape(count, nx),
+        lx=np.array([s["lx"] for s in st]).reshape(count, nx),
+        lw=z((nx,)), c=np.array([s["c"] for s in st]).reshape(count))
+
+
+def _emulate(prob, leaves, items):
+    """Run the plan on the CPU with oracle arithmetic."""
+    nx = prob["QxN"].shape[0]
+    N = prob["Qx"].shape[0]
+    slots = {}
+    real_term = (prob["QxN"], -prob["lN"], float(prob["cN"]))
+    for lf in leaves:
+        _, t0, ln, fl, slot = lf[:5]
+        if fl & ISTOP:
+            continue
+        if fl & LAST:
+            QxN, lN, cN = reduction.eliminate_last(reduction.sub_problem(prob, t0, t0 + ln, real_term))
+            slots[slot] = dict(Qx=QxN, lx=lN, c=cN)
+        else:
+            slots[slot] = reduction.reduce_closed_form(reduction.sub_problem(prob, t0, t0 + ln))
+    for it in items:
+        kind, _, _, first, count, last, term, out = it[:8]
+        sub = _stage_dict(slots, first, count, nx)
+        if kind in (UP, UP_LAST):
+            if kind == UP:
+                sub.update(QxN=np.zeros((nx, nx)), lN=np.zeros(nx), cN=0.0, x0=np.zeros(nx))
+                slots[out] = reduction.reduce_closed_form(sub)
+            else:
+                t = slots[term]
+                sub.update(QxN=t["Qx"], lN=t["lx"], cN=t["c"], x0=np.zeros(nx))
+                QxN, lN, cN = reduction.eliminate_last(sub)
+                slots[out] = dict(Qx=QxN, lx=lN, c=cN)
+        else:
+            if kind == TOP:
+                x0 = prob["x0"]
+            else:
+                x0 = slots[out]["xh"]
+            if last:
+                t = slots[term]
+                sub.update(QxN=t["Qx"], lN=t["lx"], cN=t["c"])
+            else:
+                m = slots[out]
+                sub.update(QxN=m["P"], lN=-m["Psi"], cN=m["cb"])
+            sub["x0"] = x0
+            sol = riccati.solve(sub, want_factors=True)
+            for s in range(count):
+                slots[first + s].update(xh=sol["x"][s], P=sol["P"][s + 1], Psi=sol["Psi"][s + 1],
+                                        cb=sol["cbar"][s + 1])
+            if last:
+                slots[term]["xh"] = sol["x"][count]
+    x = np.zeros((N + 1, prob["QxN"].shape[0]))
+    w = np.zeros((N, prob["Qw"].shape[1]))
+    lam = np.zeros_like(x)
+    for lf in leaves:
+        _, t0, ln, fl, slot = lf[:5]
+        if fl & (LAST | ISTOP):
+            term = real_term
+        else:
+            m = slots[slot]
+            term = (m["P"], m["Psi"], m["cb"])
+        sub = reduction.sub_problem(prob, t0, t0 + ln, term)
+        sub["x0"] = prob["x0"] if fl & ISTOP else slots[slot]["xh"]
+        sol = riccati.solve(sub)
+        x[t0:t0 + ln + 1] = sol["x"]
+        w[t0:t0 + ln] = sol["w"]
+        lam[t0:t0 + ln + 1] = sol["lam"]
+    return dict(x=x, w=w, lam=lam)
+
+
+@pytest.mark.parametrize("nx,nu,N,Ns,b", [(3, 2, 37, 4, 3), (4, 2, 64, 4, 4), (2, 2, 23, 2, 2),
+                                          (4, 4, 17, 4, 4), (4, 4, 9, 8, 2), (2, 1, 40, 2, 3)])
+def test_plan_emulated_with_oracle_matches_serial(nx, nu, N, Ns, b):
+    prob = W.g2(nx, nu, N, seed=N + 13 * nx)
+    leaves, items, _ = _tables([(nx, nu, N)], Ns, b)
+    emu = _emulate(prob, leaves, items)
+    ref = riccati.solve(prob)
+    assert kkt.rel_error(emu, ref) < 1e-9
+
+
+def test_plan_batch_groups_and_offsets():
+    dims = [(4, 2, 64), (3, 2, 10), (4, 2, 7), (4, 2, 130)]
+    leaves, items, q = _tables(dims, 8, 4)
+    assert q[0] == sum(-(-N // 8) for _, _, N in dims)
+    # scratch offsets of a group increase with the stages they cover
+    for g in np.unique(leaves[:, 6]):
+        L = leaves[leaves[:, 6] == g]
+        assert np.all(np.diff(L[:, 5]) > 0)
+
+
+def test_plan_rejects_bad_arguments():
+    with pytest.raises(rs.RsError):
+        rs.rs_plan_create([(4, 1, 64)], Ns=2)          # Ns*nu < nx: singular Q_w_hat
+    with pytest.raises(rs.RsError):
+        rs.rs_plan_create([(0, 1, 64)])
+    with pytest.raises(rs.RsError):
+        rs.rs_plan_create([(5, 5, 64)])                # no kernel for this shape
+    with pytest.raises(rs.RsError):
+        rs.rs_plan_create([(4, 2, 3)], Ns=1)           # Ns*nu < nx on a multi-leaf problem
+    p = rs.rs_plan_create([(4, 2, 1)], Ns=1)           # a single leaf needs no reduction
+    rs.rs_plan_destroy(p)
