@@ -170,6 +170,16 @@ int64_t rs_plan_query(rs_plan plan, int32_t key);
  * bad argument).  Host only. */
 int64_t rs_plan_export(rs_plan plan, int32_t what, int64_t *out, int64_t cap_rows);
 
+/* Kernel timing (measurement aid).  While enabled, each call records a pair
+ * of HIP events on its stream around every kernel it launches.
+ * rs_plan_kernel_times waits for the recorded events and returns, per kernel
+ * kind (0 status/queue reset, 1 leaf reduction, 2 tree levels, 3 leaf solve,
+ * 4..7 reserved), the summed elapsed milliseconds and the number of
+ * launches since the last reset; reset != 0 starts a new window.  ms and
+ * launches point to 8 host values each. */
+rs_status rs_plan_set_timing(rs_plan plan, int32_t enable);
+rs_status rs_plan_kernel_times(rs_plan plan, double *ms, int64_t *launches, int32_t reset);
+
 const char *rs_status_string(rs_status s);
 
 #ifdef __cplusplus

@@ -53,6 +53,14 @@ struct rs_plan_s {
     bool probs_valid = false;
     int32_t epoch = 0;
     int64_t last_refine = 0;
+    // optional per-kernel timing with HIP events on the call's stream
+    bool timing = false;
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
 };
 
 namespace {
@@ -173,6 +181,31 @@ bool valid_ptr_set(const rs_problem &p) {
 }
 
 rs_status to_status(hipError_t e) { return e == hipSuccess ? RS_OK : RS_ERR_HIP; }
+
+hipEvent_t take_event(rs_plan_s *P) {
+    hipEvent_t e = nullptr;
+    if (!P->pool.empty()) {
+        e = P->pool.back();
+        P->pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+    }
+    return e;
+}
+
+// Launch one kernel of the given kind, bracketed by timing events when the
+// plan's timing mode is on.
+template <class F>
+hipError_t timed(rs_plan_s *P, int kind, hipStream_t st, F &&launch) {
+    if (!P->timing) return launch();
+    hipEvent_t a = take_event(P), b = take_event(P);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, st);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    P->recs.push_back({kind, a, b});
+    return e;
+}
 
 }  // namespace
 
@@ -309,6 +342,12 @@ rs_status rs_plan_destroy(rs_plan P) {
         if (P->pinned_probs[i]) (void)hipHostFree(P->pinned_probs[i]);
     }
     if (P->pinned_tables) (void)hipHostFree(P->pinned_tables);
+    for (auto &r : P->recs) {
+        (void)hipEventSynchronize(r.b);
+        P->pool.push_back(r.a);
+        P->pool.push_back(r.b);
+    }
+    for (auto e : P->pool) (void)hipEventDestroy(e);
     delete P;
     return RS_OK;
 }
@@ -442,7 +481,7 @@ rs_status rs_batch_solve(rs_plan P, const rs_problem *probs, void *work, size_t 
     ++P->epoch;
     int32_t *info = info_dev ? info_dev : reinterpret_cast<int32_t *>(W + P->off_info);
     int32_t *queues = reinterpret_cast<int32_t *>(W + P->off_queues);
-    hipError_t e = launch_init(info, P->count, queues, (int)P->groups.size(), st);
+    hipError_t e = timed(P, KK_INIT, st, [&] { return launch_init(info, P->count, queues, (int)P->groups.size(), st); });
     if (e != hipSuccess) return RS_ERR_HIP;
     for (size_t gi = 0; gi < P->groups.size(); ++gi) {
         Group &g = P->groups[gi];
@@ -459,8 +498,48 @@ rs_status rs_batch_solve(rs_plan P, const rs_problem *probs, void *work, size_t 
         a.info = info;
         a.epoch = P->epoch;
         const int tree_grid = std::max(1, std::min<int>((int)g.items.size(), 256));
-        e = g.shape->fp64(a, tree_grid, st);
-        if (e != hipSuccess) return RS_ERR_HIP;
+        const Launcher *L = g.shape->fp64;
+        if (a.nleaves > 0) {
+            e = timed(P, KK_LEAF_UP, st, [&] { return L[0](a, a.nleaves, st); });
+            if (e != hipSuccess) return RS_ERR_HIP;
+        }
+        if (a.nitems > 0) {
+            e = timed(P, KK_TREE, st, [&] { return L[1](a, tree_grid, st); });
+            if (e != hipSuccess) return RS_ERR_HIP;
+        }
+        if (a.nleaves > 0) {
+            e = timed(P, KK_LEAF_DOWN, st, [&] { return L[2](a, a.nleaves, st); });
+            if (e != hipSuccess) return RS_ERR_HIP;
+        }
+    }
+    return RS_OK;
+}
+
+rs_status rs_plan_set_timing(rs_plan P, int32_t enable) {
+    if (!P) return RS_ERR_ARG;
+    P->timing = enable != 0;
+    return RS_OK;
+}
+
+rs_status rs_plan_kernel_times(rs_plan P, double *ms, int64_t *launches, int32_t reset) {
+    if (!P || !ms || !launches) return RS_ERR_ARG;
+    for (int k = 0; k < KK_COUNT; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (auto &r : P->recs) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return RS_ERR_HIP;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return RS_ERR_HIP;
+        ms[r.kind] += t;
+        launches[r.kind] += 1;
+    }
+    if (reset) {
+        for (auto &r : P->recs) {
+            P->pool.push_back(r.a);
+            P->pool.push_back(r.b);
+        }
+        P->recs.clear();
     }
     return RS_OK;
 }

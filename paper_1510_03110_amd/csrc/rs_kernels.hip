@@ -301,16 +301,18 @@ __global__ void __launch_bounds__(NT) k_tree(GroupArgs g) {
 
 // ---------------------------------------------------------------- launchers
 template <class T, int NX, int NU>
-static hipError_t launch_group(const GroupArgs &g, int tree_grid, hipStream_t st) {
-    if (g.nleaves > 0) {
-        hipLaunchKernelGGL((k_leaf_up<T, NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
-    }
-    if (g.nitems > 0) {
-        hipLaunchKernelGGL((k_tree<NX>), dim3(tree_grid), dim3(NT), 0, st, g);
-    }
-    if (g.nleaves > 0) {
-        hipLaunchKernelGGL((k_leaf_down<T, NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
-    }
+static hipError_t launch_leaf_up(const GroupArgs &g, int, hipStream_t st) {
+    hipLaunchKernelGGL((k_leaf_up<T, NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+template <int NX>
+static hipError_t launch_tree(const GroupArgs &g, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_tree<NX>), dim3(grid), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+template <class T, int NX, int NU>
+static hipError_t launch_leaf_down(const GroupArgs &g, int, hipStream_t st) {
+    hipLaunchKernelGGL((k_leaf_down<T, NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
     return hipGetLastError();
 }
 
@@ -331,7 +333,8 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st) {
 
 const ShapeEntry *find_shape(int nx, int nu) {
     static const ShapeEntry table[] = {
-#define RS_ENTRY(a, b) {a, b, &launch_group<double, a, b>, scratch_per_stage(a, b)},
+#define RS_ENTRY(a, b) \
+    {a, b, {&launch_leaf_up<double, a, b>, &launch_tree<a>, &launch_leaf_down<double, a, b>}, scratch_per_stage(a, b)},
         RS_SHAPES(RS_ENTRY)
 #undef RS_ENTRY
     };

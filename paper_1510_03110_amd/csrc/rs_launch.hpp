@@ -10,11 +10,14 @@ namespace rs {
 // Per-stage element count of the leaf solve's scratch (K, k, P, Psi).
 constexpr int scratch_per_stage(int nx, int nu) { return nu * nx + nu + nx * nx + nx; }
 
-typedef hipError_t (*GroupLauncher)(const GroupArgs &, int tree_grid, hipStream_t);
+typedef hipError_t (*Launcher)(const GroupArgs &, int grid, hipStream_t);
+
+// Kernel kinds, also the index of the per-kind timers of a plan.
+enum KernelKind { KK_INIT = 0, KK_LEAF_UP = 1, KK_TREE = 2, KK_LEAF_DOWN = 3, KK_COUNT = 8 };
 
 struct ShapeEntry {
     int nx, nu;
-    GroupLauncher fp64;
+    Launcher fp64[3];        // leaf up, tree, leaf down
     int scratch_per_stage;
 };
 

@@ -64,6 +64,10 @@ def library():
         lib.rs_plan_query.restype = i64
         lib.rs_plan_export.argtypes = [_P, i32, ctypes.POINTER(i64), i64]
         lib.rs_plan_export.restype = i64
+        lib.rs_plan_set_timing.argtypes = [_P, i32]
+        lib.rs_plan_set_timing.restype = i32
+        lib.rs_plan_kernel_times.argtypes = [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]
+        lib.rs_plan_kernel_times.restype = i32
         lib.rs_status_string.argtypes = [i32]
         lib.rs_status_string.restype = ctypes.c_char_p
         for name in ("rs_plan_create", "rs_plan_workspace_size", "rs_plan_destroy", "rs_batch_solve",
@@ -114,6 +118,21 @@ def rs_plan_export(plan, what):
     out = np.zeros((max(rows, 1), width), dtype=np.int64)
     lib.rs_plan_export(plan, what, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), rows)
     return out[:rows]
+
+
+KERNEL_KINDS = ("init", "leaf_up", "tree", "leaf_down")
+
+
+def rs_plan_set_timing(plan, enable):
+    _check(library().rs_plan_set_timing(plan, int(bool(enable))), "rs_plan_set_timing")
+
+
+def rs_plan_kernel_times(plan, reset=True):
+    """{kind: (total_ms, launches)} since the last reset (synchronizes)."""
+    ms = (ctypes.c_double * 8)()
+    n = (ctypes.c_int64 * 8)()
+    _check(library().rs_plan_kernel_times(plan, ms, n, int(bool(reset))), "rs_plan_kernel_times")
+    return {KERNEL_KINDS[k]: (ms[k], n[k]) for k in range(len(KERNEL_KINDS))}
 
 
 def _call(name, plan, probs, work_ptr, work_bytes, stream_ptr, info_ptr):
