@@ -13,11 +13,11 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB_PATH = os.path.join(BUILD_DIR, "librs.so")
-SOURCES = ["rs_kernels.hip", "rs_capi.cpp"]
-HEADERS = ["rs_types.hpp", "rs_device.hpp", "rs_launch.hpp"]
+SOURCES = ["rs_kernels.hip", "rs_kernels_mfma.hip", "rs_capi.cpp"]
+HEADERS = ["rs_types.hpp", "rs_device.hpp", "rs_mfma.hpp", "rs_launch.hpp"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]
@@ -30,21 +30,36 @@ def hipcc():
     return "hipcc"
 
 
-def build(verbose=False):
-    os.makedirs(BUILD_DIR, exist_ok=True)
-    tmp = LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC] + \
-        [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+def _compile(src, obj, verbose):
+    cmd = [hipcc()] + HIPCC_FLAGS + ["-c", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                                     os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in res.stdout.splitlines()
                     if "packed-fp32-ops" not in l)      # host-pass notice, harmless
-    if res.returncode != 0:
-        sys.stderr.write(out + "\n")
-        raise RuntimeError("hipcc failed (%d)" % res.returncode)
-    if verbose and out.strip():
-        print(out)
+    return res.returncode, out
+
+
+def build(verbose=False):
+    """Compile every source to an object (in parallel) and link librs.so."""
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    objs = [os.path.join(BUILD_DIR, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    jobs = min(len(SOURCES), max(1, int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(lambda so: _compile(so[0], so[1], verbose), zip(SOURCES, objs)))
+    for (rc, out), src in zip(results, SOURCES):
+        if rc != 0:
+            sys.stderr.write(out + "\n")
+            raise RuntimeError("hipcc failed on %s (%d)" % (src, rc))
+        if verbose and out.strip():
+            print(out)
+    tmp = LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 

@@ -328,18 +328,50 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st) {
     return hipGetLastError();
 }
 
-#define RS_SHAPES(X) \
-    X(1, 1) X(2, 1) X(2, 2) X(3, 2) X(4, 2) X(4, 4) X(6, 3) X(8, 4) X(16, 8) X(20, 10) X(32, 16)
+// Shapes with generic (VALU) kernels; shapes whose dimensions are multiples
+// of 16 use the matrix-core kernels instead (rs_kernels_mfma.hip), and the
+// master levels use them whenever n_x is a multiple of 16.
+#define RS_GENERIC_SHAPES(X) \
+    X(1, 1) X(2, 1) X(2, 2) X(3, 2) X(4, 2) X(4, 4) X(6, 3) X(8, 4) X(16, 8) X(20, 10)
+
+Launcher mfma_leaf_up(int nx, int nu);
+Launcher mfma_leaf_down(int nx, int nu);
+Launcher mfma_tree(int nx);
+
+namespace {
+struct GenericEntry {
+    int nx, nu;
+    Launcher up, tree, down;
+};
+const GenericEntry generic_table[] = {
+#define RS_ENTRY(a, b) {a, b, &launch_leaf_up<double, a, b>, &launch_tree<a>, &launch_leaf_down<double, a, b>},
+    RS_GENERIC_SHAPES(RS_ENTRY)
+#undef RS_ENTRY
+};
+}  // namespace
 
 const ShapeEntry *find_shape(int nx, int nu) {
-    static const ShapeEntry table[] = {
-#define RS_ENTRY(a, b) \
-    {a, b, {&launch_leaf_up<double, a, b>, &launch_tree<a>, &launch_leaf_down<double, a, b>}, scratch_per_stage(a, b)},
-        RS_SHAPES(RS_ENTRY)
-#undef RS_ENTRY
-    };
-    for (const auto &e : table)
-        if (e.nx == nx && e.nu == nu) return &e;
+    static ShapeEntry table[64];
+    static int n = 0;
+    static bool init = false;
+    if (!init) {
+        auto add = [&](int a, int b, Launcher up, Launcher tr, Launcher dn) {
+            ShapeEntry e;
+            e.nx = a;
+            e.nu = b;
+            e.fp64[0] = mfma_leaf_up(a, b) ? mfma_leaf_up(a, b) : up;
+            e.fp64[1] = mfma_tree(a) ? mfma_tree(a) : tr;
+            e.fp64[2] = mfma_leaf_down(a, b) ? mfma_leaf_down(a, b) : dn;
+            e.scratch_per_stage = scratch_per_stage(a, b);
+            if (e.fp64[0] && e.fp64[1] && e.fp64[2]) table[n++] = e;
+        };
+        for (const auto &g : generic_table) add(g.nx, g.nu, g.up, g.tree, g.down);
+        const int mshapes[][2] = {{16, 16}, {32, 16}, {32, 32}};
+        for (const auto &m : mshapes) add(m[0], m[1], nullptr, nullptr, nullptr);
+        init = true;
+    }
+    for (int i = 0; i < n; ++i)
+        if (table[i].nx == nx && table[i].nu == nu) return &table[i];
     return nullptr;
 }
 

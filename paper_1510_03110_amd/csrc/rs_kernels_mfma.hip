@@ -1,0 +1,504 @@
+// Matrix-core kernels of the fused parallel Riccati solve for n_x, n_u that
+// are multiples of 16 (FP64).  Same work split as the generic kernels:
+//   km_leaf_up    one workgroup per leaf: Alg. 4 (or last-leaf elimination)
+//   km_tree       work-queue kernel over the master levels (Alg. 5 up, top
+//                 solve, Alg. 6 down to level 1)
+//   km_leaf_down  one workgroup per leaf: Alg. 1-3 with the parent's message
+#include <hip/hip_runtime.h>
+
+#include "rs_launch.hpp"
+#include "rs_mfma.hpp"
+
+namespace rs {
+namespace mf {
+
+constexpr int SPIN_LIMIT = 1 << 26;
+
+__device__ __forceinline__ LeafItem load_leaf_u(const LeafItem *tab, int i) {
+    const LeafItem r = tab[i];
+    LeafItem u;
+    u.inst = uni(r.inst);
+    u.t0 = uni(r.t0);
+    u.len = uni(r.len);
+    u.flags = uni(r.flags);
+    u.slot = uni(r.slot);
+    u.pad = 0;
+    u.scratch = ((int64_t)uni((int)(r.scratch >> 32)) << 32) | (uint32_t)uni((int)(r.scratch & 0xffffffff));
+    return u;
+}
+__device__ __forceinline__ TreeItem load_item_u(const TreeItem *tab, int i) {
+    const TreeItem r = tab[i];
+    TreeItem u;
+    u.kind = uni(r.kind);
+    u.inst = uni(r.inst);
+    u.level = uni(r.level);
+    u.first = uni(r.first);
+    u.count = uni(r.count);
+    u.last = uni(r.last);
+    u.term_slot = uni(r.term_slot);
+    u.out_slot = uni(r.out_slot);
+    u.dep_first = uni(r.dep_first);
+    u.dep_count = uni(r.dep_count);
+    return u;
+}
+
+template <int NX, int NU>
+struct Sizes {
+    static constexpr size_t red = sizeof(MSmem<NX, NU, true, false>), elim = sizeof(MSmem<NX, NU, false, false>),
+                            solve = sizeof(MSmem<NX, NU, false, true>);
+    static constexpr size_t up = red > elim ? red : elim;
+    static constexpr size_t all = up > solve ? up : solve;
+};
+
+// Reduce (Alg. 4) and write the M1 message.
+template <int NX, int NU, class Get>
+__device__ void reduce_to(MSmem<NX, NU, true, false> &S, Get get, int count, double *out, int32_t *info, int inst,
+                          int stage_base, int fail_code) {
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NX * NX; e += NT) {
+        S.P[e] = 0.0;
+        S.V[e] = (e / NX == e % NX) ? 1.0 : 0.0;
+        S.Qh[e] = 0.0;
+    }
+    for (int i = tid; i < NX; i += NT) {
+        S.Psi[i] = 0.0;
+        S.v[i] = 0.0;
+    }
+    if (tid == 0) S.cbar = 0.0;
+    __syncthreads();
+    mfma_pass<NX, NU, true, false>(
+        S, get, count, info, inst, stage_base, fail_code, [](int, auto &) {}, [](int, auto &) {});
+    const SlotLayout SL{NX};
+    for (int e = tid; e < NX * NX; e += NT) {
+        const int i = e / NX, j = e % NX;
+        out[SL.A() + e] = S.V[j * NX + i];     // A_hat = V_0'
+        out[SL.Qw() + e] = S.Qh[e];
+        out[SL.Qx() + e] = S.P[e];
+    }
+    for (int i = tid; i < NX; i += NT) {
+        out[SL.a() + i] = S.v[i];
+        out[SL.lx() + i] = -S.Psi[i];
+    }
+    if (tid == 0) out[SL.c()] = S.cbar;
+}
+
+// Eliminate a subproblem with known terminal (already in S) and write the
+// terminal cost it passes up (Sec. 4.2, last subproblem).
+template <int NX, int NU, class Get>
+__device__ void eliminate_to(MSmem<NX, NU, false, false> &S, Get get, int count, double *out, int32_t *info,
+                             int inst, int stage_base, int fail_code) {
+    const int tid = threadIdx.x;
+    mfma_pass<NX, NU, false, false>(
+        S, get, count, info, inst, stage_base, fail_code, [](int, auto &) {}, [](int, auto &) {});
+    const SlotLayout SL{NX};
+    for (int e = tid; e < NX * NX; e += NT) out[SL.Qx() + e] = S.P[e];
+    for (int i = tid; i < NX; i += NT) out[SL.lx() + i] = -S.Psi[i];
+    if (tid == 0) out[SL.c()] = S.cbar;
+}
+
+// Forward recursion (Alg. 3) over `count` stages from x in S.x.  Per stage
+// the feedback K, k (and for leaves P_t, Psi_t) come from `fac(s)`, the
+// dynamics from get(s).  Two barriers per stage; the next stage's operands
+// are prefetched into registers and committed to LDS once free.  B is
+// double-buffered (S.B / S.W) because it is read in the second half.
+template <int NX, int NU, bool LAM>
+struct FwdPrefetch {
+    static constexpr int NK = (NU * NX + NT - 1) / NT, NA = (NX * NX + NT - 1) / NT, NB = (NX * NU + NT - 1) / NT,
+                         NP = LAM ? (NX * NX + NT - 1) / NT : 0;
+    double k_[NK], a_[NA], b_[NB], p_[NP > 0 ? NP : 1];
+    double kk, av, psi;
+};
+
+template <int NX, int NU, bool LAM, class Get, class Fac>
+__device__ __forceinline__ void fwd_fetch(FwdPrefetch<NX, NU, LAM> &f, Get get, Fac fac, int s) {
+    using FP = FwdPrefetch<NX, NU, LAM>;
+    const int tid = threadIdx.x;
+    const StageSrc src = get(s);
+    const double *K = fac.K(s), *P = fac.P(s);
+#pragma unroll
+    for (int q = 0; q < FP::NK; ++q) {
+        const int e = tid + q * NT;
+        f.k_[q] = e < NU * NX ? K[e] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < FP::NA; ++q) {
+        const int e = tid + q * NT;
+        f.a_[q] = e < NX * NX ? src.A[e] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < FP::NB; ++q) {
+        const int e = tid + q * NT;
+        f.b_[q] = e < NX * NU ? src.B[e] : 0.0;
+    }
+    if constexpr (LAM) {
+#pragma unroll
+        for (int q = 0; q < FP::NP; ++q) {
+            const int e = tid + q * NT;
+            f.p_[q] = e < NX * NX ? P[e] : 0.0;
+        }
+    }
+    f.kk = tid < NU ? fac.k(s)[tid] : 0.0;
+    f.av = (tid < NX && src.a) ? src.a[tid] : 0.0;
+    f.psi = (LAM && tid < NX) ? fac.Psi(s)[tid] : 0.0;
+}
+
+template <int NX, int NU, bool LAM>
+__device__ __forceinline__ void fwd_commit_main(MSmem<NX, NU, false, true> &S, const FwdPrefetch<NX, NU, LAM> &f) {
+    using FP = FwdPrefetch<NX, NU, LAM>;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < FP::NK; ++q) {
+        const int e = tid + q * NT;
+        if (e < NU * NX) S.K[e] = f.k_[q];
+    }
+#pragma unroll
+    for (int q = 0; q < FP::NA; ++q) {
+        const int e = tid + q * NT;
+        if (e < NX * NX) S.A[e] = f.a_[q];
+    }
+    if constexpr (LAM) {
+#pragma unroll
+        for (int q = 0; q < FP::NP; ++q) {
+            const int e = tid + q * NT;
+            if (e < NX * NX) S.P[e] = f.p_[q];
+        }
+    }
+    if (tid < NU) S.kk[tid] = f.kk;
+    if (tid < NX) {
+        S.av[tid] = f.av;
+        S.Psi[tid] = f.psi;
+    }
+}
+
+template <int NX, int NU, bool LAM>
+__device__ __forceinline__ void fwd_commit_B(double *Bbuf, const FwdPrefetch<NX, NU, LAM> &f) {
+    using FP = FwdPrefetch<NX, NU, LAM>;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < FP::NB; ++q) {
+        const int e = tid + q * NT;
+        if (e < NX * NU) Bbuf[e] = f.b_[q];
+    }
+}
+
+template <int NX, int NU, bool LAM, class Get, class Fac, class Emit>
+__device__ void forward_m(MSmem<NX, NU, false, true> &S, Get get, int count, Fac fac, Emit emit) {
+    static_assert(NX * NU <= NX * (NX + NU), "second B buffer lives in W");
+    const int tid = threadIdx.x;
+    count = uni(count);
+    FwdPrefetch<NX, NU, LAM> f;
+    double *Bcur = S.B, *Bnxt = S.W;
+    if (count > 0) {
+        fwd_fetch<NX, NU, LAM>(f, get, fac, 0);
+        fwd_commit_main<NX, NU, LAM>(S, f);
+        fwd_commit_B<NX, NU, LAM>(Bcur, f);
+    }
+    __syncthreads();
+    for (int s = 0; s < count; ++s) {
+        if (s + 1 < count) fwd_fetch<NX, NU, LAM>(f, get, fac, s + 1);
+        // half 1: w = k + K x, A x + a, (leaf) lam = P x - Psi
+        if (tid < NU) {
+            double acc = S.kk[tid];
+#pragma unroll 8
+            for (int c = 0; c < NX; ++c) acc += S.K[tid * NX + c] * S.x[c];
+            S.wv[tid] = acc;
+        } else if (tid >= 64 && tid < 64 + NX) {
+            const int i = tid - 64;
+            double acc = S.av[i];
+#pragma unroll 8
+            for (int c = 0; c < NX; ++c) acc += S.A[i * NX + c] * S.x[c];
+            S.ax[i] = acc;
+        } else if (LAM && tid >= 128 && tid < 128 + NX) {
+            const int i = tid - 128;
+            double acc = -S.Psi[i];
+#pragma unroll 8
+            for (int c = 0; c < NX; ++c) acc += S.P[i * NX + c] * S.x[c];
+            emit.lam(s, i, acc);
+        }
+        emit.x(s, S.x);
+        if (s + 1 < count) fwd_commit_B<NX, NU, LAM>(Bnxt, f);
+        __syncthreads();
+        // half 2: x_{t+1} = A x + a + B w
+        if (tid < NX) {
+            double acc = S.ax[tid];
+#pragma unroll
+            for (int r = 0; r < NU; ++r) acc += Bcur[tid * NU + r] * S.wv[r];
+            S.x[tid] = acc;
+        }
+        emit.w(s, S.wv);
+        if (s + 1 < count) fwd_commit_main<NX, NU, LAM>(S, f);
+        double *t = Bcur;
+        Bcur = Bnxt;
+        Bnxt = t;
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ leaves
+template <int NX, int NU>
+__global__ void __launch_bounds__(NT, 2) km_leaf_up(GroupArgs g) {
+    __shared__ __attribute__((aligned(16))) char raw[Sizes<NX, NU>::up];
+    const LeafItem it = load_leaf_u(g.leaves, blockIdx.x);
+    if (it.flags & LEAF_TOP) return;
+    const DevProb &p = g.probs[it.inst];
+    const SlotLayout SL{NX};
+    double *out = g.slots + (int64_t)it.slot * SL.size();
+    auto get = [&](int s) { return prob_stage(p, it.t0 + s); };
+    if (!(it.flags & LEAF_LAST)) {
+        auto &S = *reinterpret_cast<MSmem<NX, NU, true, false> *>(raw);
+        reduce_to<NX, NU>(S, get, it.len, out, g.info, it.inst, it.t0, 2);
+    } else {
+        auto &S = *reinterpret_cast<MSmem<NX, NU, false, false> *>(raw);
+        const int tid = threadIdx.x;
+        for (int e = tid; e < NX * NX; e += NT) S.P[e] = p.QxN[e];
+        for (int i = tid; i < NX; i += NT) S.Psi[i] = p.lN ? -p.lN[i] : 0.0;
+        if (tid == 0) S.cbar = p.cN ? p.cN[0] : 0.0;
+        __syncthreads();
+        eliminate_to<NX, NU>(S, get, it.len, out, g.info, it.inst, it.t0, 2);
+    }
+}
+
+// Leaf-solve scratch per stage: K (NU*NX) | k (NU) | P (NX*NX) | Psi (NX)
+template <int NX, int NU>
+struct LeafFac {
+    const double *base;
+    static constexpr int K_ = 0, k_ = NU * NX, P_ = NU * NX + NU, Psi_ = NU * NX + NU + NX * NX,
+                         per = NU * NX + NU + NX * NX + NX;
+    __device__ const double *K(int s) const { return base + (int64_t)s * per + K_; }
+    __device__ const double *k(int s) const { return base + (int64_t)s * per + k_; }
+    __device__ const double *P(int s) const { return base + (int64_t)s * per + P_; }
+    __device__ const double *Psi(int s) const { return base + (int64_t)s * per + Psi_; }
+};
+
+template <int NX, int NU>
+__global__ void __launch_bounds__(NT, 2) km_leaf_down(GroupArgs g) {
+    __shared__ __attribute__((aligned(16))) char raw[sizeof(MSmem<NX, NU, false, true>)];
+    auto &S = *reinterpret_cast<MSmem<NX, NU, false, true> *>(raw);
+    using LF = LeafFac<NX, NU>;
+    const LeafItem it = load_leaf_u(g.leaves, blockIdx.x);
+    const DevProb &p = g.probs[it.inst];
+    const SlotLayout SL{NX};
+    const int tid = threadIdx.x;
+    const bool known_end = (it.flags & (LEAF_LAST | LEAF_TOP)) != 0;
+    const double *msg = (it.flags & LEAF_TOP) ? nullptr : g.slots + (int64_t)it.slot * SL.size();
+    double *scr = reinterpret_cast<double *>(g.leaf_scratch) + it.scratch;
+    for (int e = tid; e < NX * NX; e += NT) S.P[e] = known_end ? p.QxN[e] : msg[SL.P() + e];
+    for (int i = tid; i < NX; i += NT) {
+        S.Psi[i] = known_end ? (p.lN ? -p.lN[i] : 0.0) : msg[SL.Psi() + i];
+        S.x[i] = msg ? msg[SL.xh() + i] : p.x0[i];
+    }
+    if (tid == 0) S.cbar = known_end ? (p.cN ? p.cN[0] : 0.0) : msg[SL.cb()];
+    __syncthreads();
+    auto get = [&](int s) { return prob_stage(p, it.t0 + s); };
+    mfma_pass<NX, NU, false, true>(
+        S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {},
+        [&](int s, auto &Sm) {
+            double *d = scr + (int64_t)s * LF::per;
+            for (int e = tid; e < NU * NX; e += NT) d[LF::K_ + e] = Sm.K[e];
+            for (int e = tid; e < NX * NX; e += NT) d[LF::P_ + e] = Sm.P[e];
+            if (tid < NX) d[LF::Psi_ + tid] = Sm.Psi[tid];
+            if (tid < NU) d[LF::k_ + tid] = Sm.kk[tid];
+        });
+    if ((it.flags & LEAF_TOP) && p.obj) {
+        if (threadIdx.x < 64) {
+            double part = 0;
+            const int i = threadIdx.x;
+            if (i < NX) {
+                double acc = 0;
+                for (int k = 0; k < NX; ++k) acc += S.P[i * NX + k] * S.x[k];
+                part = S.x[i] * (0.5 * acc - S.Psi[i]);
+            }
+            part = wave_sum(part);
+            if (i == 0) p.obj[0] = part + S.cbar;
+        }
+    }
+    __syncthreads();     // scratch written by all threads before it is read back
+    struct Emit {
+        const DevProb &p;
+        int t0;
+        __device__ void lam(int s, int i, double v) const { p.lam[(int64_t)(t0 + s) * NX + i] = v; }
+        __device__ void x(int s, const double *xv) const {
+            const int tid = threadIdx.x;
+            if (tid >= 192 && tid < 192 + NX) p.x[(int64_t)(t0 + s) * NX + (tid - 192)] = xv[tid - 192];
+        }
+        __device__ void w(int s, const double *wv) const {
+            const int tid = threadIdx.x;
+            if (tid >= 192 && tid < 192 + NU) p.w[(int64_t)(t0 + s) * NU + (tid - 192)] = wv[tid - 192];
+        }
+    } emit{p, it.t0};
+    forward_m<NX, NU, true>(S, get, it.len, LF{scr}, emit);
+    if (known_end) {
+        const int t = it.t0 + it.len;
+        for (int i = tid; i < NX; i += NT) {
+            double acc = p.lN ? p.lN[i] : 0.0;
+            for (int k = 0; k < NX; ++k) acc += p.QxN[i * NX + k] * S.x[k];
+            p.lam[(int64_t)t * NX + i] = acc;       // lam_N = QxN x_N + lN
+            p.x[(int64_t)t * NX + i] = S.x[i];
+        }
+    }
+}
+
+// -------------------------------------------------------------- the tree
+template <int NX>
+struct SlotFac {
+    double *slots;
+    int first;
+    __device__ const double *base(int s) const { return slots + (int64_t)(first + s) * SlotLayout{NX}.size(); }
+    __device__ const double *K(int s) const { return base(s) + SlotLayout{NX}.K(); }
+    __device__ const double *k(int s) const { return base(s) + SlotLayout{NX}.k(); }
+    __device__ const double *P(int s) const { return nullptr; }
+    __device__ const double *Psi(int s) const { return nullptr; }
+};
+
+template <int NX>
+__device__ void tree_solve_m(MSmem<NX, NX, false, true> &S, const TreeItem &it, const DevProb &p, GroupArgs &g) {
+    const SlotLayout SL{NX};
+    const int tid = threadIdx.x;
+    double *slots = g.slots;
+    auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
+    const bool top = it.kind == ITEM_TOP;
+    const double *msg = top ? nullptr : slot(it.out_slot);
+    const double *term = it.last ? slot(it.term_slot) : nullptr;
+    for (int e = tid; e < NX * NX; e += NT) S.P[e] = term ? term[SL.Qx() + e] : msg[SL.P() + e];
+    for (int i = tid; i < NX; i += NT) {
+        S.Psi[i] = term ? -term[SL.lx() + i] : msg[SL.Psi() + i];
+        S.x[i] = top ? p.x0[i] : msg[SL.xh() + i];
+    }
+    if (tid == 0) S.cbar = term ? term[SL.c()] : msg[SL.cb()];
+    __syncthreads();
+    auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };
+    mfma_pass<NX, NX, false, true>(
+        S, get, it.count, g.info, it.inst, -1, 3,
+        [&](int s, auto &Sm) {          // M2 for child s: cost to go at the end of stage s
+            double *d = slot(it.first + s);
+            for (int e = tid; e < NX * NX; e += NT) d[SL.P() + e] = Sm.P[e];
+            if (tid < NX) d[SL.Psi() + tid] = Sm.Psi[tid];
+            if (tid == 0) d[SL.cb()] = Sm.cbar;
+        },
+        [&](int s, auto &Sm) {          // master feedback of stage s
+            double *d = slot(it.first + s);
+            for (int e = tid; e < NX * NX; e += NT) d[SL.K() + e] = Sm.K[e];
+            if (tid < NX) d[SL.k() + tid] = Sm.kk[tid];
+        });
+    if (top && p.obj && tid < 64) {
+        double part = 0;
+        if (tid < NX) {
+            double acc = 0;
+            for (int k = 0; k < NX; ++k) acc += S.P[tid * NX + k] * S.x[k];
+            part = S.x[tid] * (0.5 * acc - S.Psi[tid]);
+        }
+        part = wave_sum(part);
+        if (tid == 0) p.obj[0] = part + S.cbar;
+    }
+    __threadfence_block();
+    __syncthreads();
+    struct Emit {
+        double *slots;
+        int first;
+        __device__ void lam(int, int, double) const {}
+        __device__ void x(int s, const double *xv) const {
+            const int tid = threadIdx.x;
+            if (tid >= 192 && tid < 192 + NX)
+                slots[(int64_t)(first + s) * SlotLayout{NX}.size() + SlotLayout{NX}.xh() + (tid - 192)] = xv[tid - 192];
+        }
+        __device__ void w(int, const double *) const {}
+    } emit{slots, it.first};
+    forward_m<NX, NX, false>(S, get, it.count, SlotFac<NX>{slots, it.first}, emit);
+    if (it.last) {
+        double *d = slot(it.term_slot);
+        for (int i = tid; i < NX; i += NT) d[SL.xh() + i] = S.x[i];
+    }
+}
+
+template <int NX>
+__global__ void __launch_bounds__(NT) km_tree(GroupArgs g) {
+    __shared__ __attribute__((aligned(16))) char raw[Sizes<NX, NX>::all];
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    const SlotLayout SL{NX};
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(g.queue, 1);
+        __syncthreads();
+        const int idx = uni(s_item);
+        __syncthreads();
+        if (idx >= g.nitems) break;
+        const TreeItem it = load_item_u(g.items, idx);
+        if (tid == 0) {
+            for (int d = 0; d < it.dep_count; ++d) {
+                int spins = 0;
+                while (__hip_atomic_load(&g.flags[it.dep_first + d], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) !=
+                       g.epoch) {
+                    __builtin_amdgcn_s_sleep(4);
+                    if (++spins > SPIN_LIMIT) {
+                        record_failure(g.info, it.inst, 6, -2);
+                        break;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const DevProb &p = g.probs[it.inst];
+        double *slots = g.slots;
+        auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
+        auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };
+        if (it.kind == ITEM_UP) {
+            auto &S = *reinterpret_cast<MSmem<NX, NX, true, false> *>(raw);
+            reduce_to<NX, NX>(S, get, it.count, slot(it.out_slot), g.info, it.inst, -1, 3);
+        } else if (it.kind == ITEM_UP_LAST) {
+            auto &S = *reinterpret_cast<MSmem<NX, NX, false, false> *>(raw);
+            const double *term = slot(it.term_slot);
+            for (int e = tid; e < NX * NX; e += NT) S.P[e] = term[SL.Qx() + e];
+            for (int i = tid; i < NX; i += NT) S.Psi[i] = -term[SL.lx() + i];
+            if (tid == 0) S.cbar = term[SL.c()];
+            __syncthreads();
+            eliminate_to<NX, NX>(S, get, it.count, slot(it.out_slot), g.info, it.inst, -1, 3);
+        } else {
+            auto &S = *reinterpret_cast<MSmem<NX, NX, false, true> *>(raw);
+            tree_solve_m<NX>(S, it, p, g);
+        }
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(&g.flags[idx], g.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+    }
+}
+
+template <int NX, int NU>
+hipError_t launch_leaf_up_m(const GroupArgs &g, int, hipStream_t st) {
+    hipLaunchKernelGGL((km_leaf_up<NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+template <int NX>
+hipError_t launch_tree_m(const GroupArgs &g, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((km_tree<NX>), dim3(grid), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+template <int NX, int NU>
+hipError_t launch_leaf_down_m(const GroupArgs &g, int, hipStream_t st) {
+    hipLaunchKernelGGL((km_leaf_down<NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+
+}  // namespace mf
+
+// MFMA launchers for the shapes that have them (nullptr: use the generic kernel).
+Launcher mfma_leaf_up(int nx, int nu) {
+    if (nx == 16 && nu == 16) return &mf::launch_leaf_up_m<16, 16>;
+    if (nx == 32 && nu == 16) return &mf::launch_leaf_up_m<32, 16>;
+    if (nx == 32 && nu == 32) return &mf::launch_leaf_up_m<32, 32>;
+    return nullptr;
+}
+Launcher mfma_leaf_down(int nx, int nu) {
+    if (nx == 16 && nu == 16) return &mf::launch_leaf_down_m<16, 16>;
+    if (nx == 32 && nu == 16) return &mf::launch_leaf_down_m<32, 16>;
+    if (nx == 32 && nu == 32) return &mf::launch_leaf_down_m<32, 32>;
+    return nullptr;
+}
+Launcher mfma_tree(int nx) {
+    if (nx == 16) return &mf::launch_tree_m<16>;
+    if (nx == 32) return &mf::launch_tree_m<32>;
+    return nullptr;
+}
+
+}  // namespace rs

@@ -1,0 +1,466 @@
+// Matrix-core (MFMA) version of the per-stage Riccati recursion for state and
+// input dimensions that are multiples of 16 (FP64, gfx950).
+//
+// Every dense product of a stage is a list of 16x16 output tiles computed
+// with v_mfma_f64_16x16x4f64 by the four wavefronts of the workgroup, tile t
+// going to wave t mod 4.  Operands are read from LDS; products are arranged so
+// that the A operand is always read as a transposed (column-contiguous) view,
+// which keeps the 16 lanes of one row group on consecutive addresses:
+//
+//   W   = P [A B]         (P symmetric, so P = P')
+//   F   = Qx + A' W_A     H' = Qxw' + B' W_A      G = Qw + B' W_B      (Alg. 1)
+//   Y   = L^{-1} H'       z = L^{-1} g_w          (G = L L')
+//   P   = F - Y'Y         Psi = g_x - Y'z                              (Alg. 1-2)
+//   Alg. 4:  X = L^{-1} B'V,  Q_w_hat += X'X,  V = A'V - Y'X,  v += V'a + X'z
+//   solve:   K = -L^{-T} Y,  k = L^{-T} z
+//
+// Symmetric results (F, P, Q_w_hat) are formed on the lower tiles only and
+// mirrored, so they are exactly symmetric.  A stage costs five workgroup
+// barriers; the next stage's inputs are prefetched into registers at the
+// start of a stage and written to LDS once the current ones are dead.
+#pragma once
+#include "rs_device.hpp"
+
+namespace rs {
+namespace mf {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int wave() { return uni((int)(threadIdx.x >> 6)); }
+__device__ __forceinline__ int lane() { return (int)(threadIdx.x & 63); }
+
+// acc += opA[16ti.., k] opB[k, 16tj..] over k < K.  opA(i,k) = TA ? A[k*lda+i]
+// : A[i*lda+k]; opB(k,j) = TB ? B[j*ldb+k] : B[k*ldb+j].  Operand layout of
+// the 16x16x4 f64 instruction (checked on gfx950): A element (i,k) in lane
+// i + 16k, B element (k,j) in lane j + 16k; result element
+// (lane/16 + 4r, lane%16) in acc[r].
+template <int K, bool TA, bool TB>
+__device__ __forceinline__ d4 mma(d4 acc, const double *__restrict__ A, int lda, const double *__restrict__ B,
+                                  int ldb, int ti, int tj) {
+    const int l = lane(), r16 = l & 15, k4 = l >> 4;
+    const int i = 16 * ti + r16, j = 16 * tj + r16;
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const int k = k0 + k4;
+        const double a = TA ? A[k * lda + i] : A[i * lda + k];
+        const double b = TB ? B[j * ldb + k] : B[k * ldb + j];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ d4 zero4() { return d4{0.0, 0.0, 0.0, 0.0}; }
+
+// Row / column of element r of this lane in tile (ti, tj).
+__device__ __forceinline__ int trow(int ti, int r) { return 16 * ti + (lane() >> 4) + 4 * r; }
+__device__ __forceinline__ int tcol(int tj) { return 16 * tj + (lane() & 15); }
+
+template <class F>
+__device__ __forceinline__ void tile_for(int ti, int tj, F f) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) f(r, trow(ti, r), tcol(tj));
+}
+
+// Store element (i, j) of a lower tile and its mirror (j, i).  In a diagonal
+// tile only the i >= j half writes, so each element has a single writer.
+__device__ __forceinline__ void put_sym(double *M, int ld, int ti, int tj, int i, int j, double v) {
+    if (ti != tj || i >= j) {
+        M[i * ld + j] = v;
+        M[j * ld + i] = v;
+    }
+}
+
+// Lower-triangular tile index t (0 .. T(T+1)/2-1) of a T x T tile grid.
+__device__ __forceinline__ void lower_tile(int t, int &ti, int &tj) {
+    ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    tj = t - ti * (ti + 1) / 2;
+}
+
+// ------------------------------------------------------------------- LDS
+template <int NX, int NU, bool RED, bool SOLVE>
+struct MSmem {
+    static constexpr int NW = NX + NU;
+    double P[NX * NX];          // P_{t+1}, then P_t
+    double A[NX * NX];          // stage A_t
+    double B[NX * NU];          // stage B_t
+    double W[NX * NW];          // P [A B]; A'V in the Alg. 4 pass
+    double F[NX * NX];
+    double HT[NU * NX];         // H'
+    double G[NU * NU];          // G, then L^{-1} (row-major) with G = L L'
+    double LiT[NU * NU];        // L^{-T} (row-major), i.e. L^{-1} by columns
+    double Y[NU * NX];          // L^{-1} H'
+    double K[SOLVE ? NU * NX : 1];
+    double V[RED ? NX * NX : 1];
+    double Qh[RED ? NX * NX : 1];
+    double BV[RED ? NU * NX : 1];   // B'V
+    double X[RED ? NU * NX : 1];    // L^{-1} B'V
+    double Psi[NX], av[NX], lx[NX], pt[NX], gx[NX], x[NX], ax[NX];
+    double lw[NU], gw[NU], z[NU], kk[NU], wv[NU];
+    double v[RED ? NX : 1], Vta[RED ? NX : 1];
+    double c, cbar, red[4];
+    int bad;
+};
+
+// Per-thread registers holding the next stage's inputs until they can be
+// written to LDS (A, B, a, lx, lw, c) and the tiles of Qx, Qxw', Qw that this
+// thread's wave adds in the F / H' / G products.
+template <int NX, int NU>
+struct Prefetch {
+    static constexpr int NA = (NX * NX + NT - 1) / NT, NB = (NX * NU + NT - 1) / NT;
+    static constexpr int TF = (NX / 16) * (NX / 16 + 1) / 2, TH = (NU / 16) * (NX / 16), TG = (NU / 16) * (NU / 16 + 1) / 2;
+    static constexpr int TILES = TF + TH + TG;
+    static constexpr int PER_WAVE = (TILES + 3) / 4;
+    double a_[NA], b_[NB];
+    double av, lx, lw, c;
+    d4 q[PER_WAVE];
+};
+
+// Tile t of phase B: F lower tiles, then H' tiles, then G lower tiles.
+template <int NX, int NU>
+__device__ __forceinline__ void phaseB_tile(int t, int &kind, int &ti, int &tj) {
+    using PF = Prefetch<NX, NU>;
+    if (t < PF::TF) {
+        kind = 0;
+        lower_tile(t, ti, tj);
+    } else if (t < PF::TF + PF::TH) {
+        kind = 1;
+        const int u = t - PF::TF;
+        ti = u / (NX / 16);
+        tj = u % (NX / 16);
+    } else {
+        kind = 2;
+        lower_tile(t - PF::TF - PF::TH, ti, tj);
+    }
+}
+
+template <int NX, int NU>
+__device__ __forceinline__ void prefetch_stage(Prefetch<NX, NU> &pf, const StageSrc &s) {
+    using PF = Prefetch<NX, NU>;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < PF::NA; ++q) {
+        const int e = tid + q * NT;
+        pf.a_[q] = e < NX * NX ? s.A[e] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PF::NB; ++q) {
+        const int e = tid + q * NT;
+        pf.b_[q] = e < NX * NU ? s.B[e] : 0.0;
+    }
+    pf.av = (tid < NX && s.a) ? s.a[tid] : 0.0;
+    pf.lx = (tid < NX && s.lx) ? s.lx[tid] : 0.0;
+    pf.lw = (tid < NU && s.lw) ? s.lw[tid] : 0.0;
+    pf.c = s.c;
+    const int w = wave();
+#pragma unroll
+    for (int u = 0; u < PF::PER_WAVE; ++u) {
+        const int t = w + 4 * u;
+        d4 q = zero4();
+        if (t < PF::TILES) {
+            int kind, ti, tj;
+            phaseB_tile<NX, NU>(t, kind, ti, tj);
+            tile_for(ti, tj, [&](int r, int i, int j) {
+                if (kind == 0) q[r] = s.Qx[i * NX + j];
+                else if (kind == 1) q[r] = s.Qxw ? s.Qxw[j * NU + i] : 0.0;
+                else q[r] = s.Qw[i * NU + j];
+            });
+        }
+        pf.q[u] = q;
+    }
+}
+
+template <int NX, int NU, bool RED, bool SOLVE>
+__device__ __forceinline__ void commit_stage(MSmem<NX, NU, RED, SOLVE> &S, const Prefetch<NX, NU> &pf) {
+    using PF = Prefetch<NX, NU>;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < PF::NA; ++q) {
+        const int e = tid + q * NT;
+        if (e < NX * NX) S.A[e] = pf.a_[q];
+    }
+#pragma unroll
+    for (int q = 0; q < PF::NB; ++q) {
+        const int e = tid + q * NT;
+        if (e < NX * NU) S.B[e] = pf.b_[q];
+    }
+    if (tid < NX) {
+        S.av[tid] = pf.av;
+        S.lx[tid] = pf.lx;
+    }
+    if (tid < NU) S.lw[tid] = pf.lw;
+    if (tid == 0) S.c = pf.c;
+}
+
+// Cholesky factorization G = L L' ("a factorization of G", Alg. 1) and the
+// inverse L^{-1}, by one wavefront.  Lane i holds row i of G / L in
+// registers; entries of other rows are broadcast with readlane, which places
+// them in scalar registers.  On return G holds L^{-1} row-major and LiT holds
+// L^{-T} row-major.  Both sweeps are right-looking, so the dependency chain
+// is one multiply-add per column.  Returns nonzero (wave-uniform) if a pivot
+// is not positive or not finite; a unit pivot is used in its place.
+template <int M>
+__device__ __forceinline__ int chol_inv_wave(double *G, double *LiT) {
+    static_assert(M <= 64, "one wavefront factors at most 64 rows");
+    const int ln = threadIdx.x & 63;
+    double g[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) g[j] = (ln < M) ? G[ln * M + j] : 0.0;
+    int fail = 0;
+    double invd = 0.0;                   // 1 / L[ln][ln]
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        double d = bcast_lane(g[j], j);
+        if (!(d > 0.0) || !(d < 1e300)) {
+            fail = 1;
+            d = 1.0;
+        }
+        const double sq = sqrt(d);
+        const double is = 1.0 / sq;
+        const double lij = (ln == j) ? sq : g[j] * is;
+        if (ln == j) invd = is;
+        g[j] = lij;
+#pragma unroll
+        for (int k = j + 1; k < M; ++k) g[k] -= lij * bcast_lane(lij, k);
+    }
+    // lane c: column c of L^{-1}, from L x = e_c
+    double x[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) x[i] = (ln == i) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        x[k] *= bcast_lane(invd, k);
+#pragma unroll
+        for (int i = k + 1; i < M; ++i) x[i] -= bcast_lane(g[k], i) * x[k];
+    }
+    if (ln < M) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            G[i * M + ln] = x[i];        // L^{-1}[i][ln]
+            LiT[ln * M + i] = x[i];      // L^{-T}[ln][i]
+        }
+    }
+    return fail;
+}
+
+// Wave-level sum over the 64 lanes (result in every lane).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ====================================================== one Riccati pass
+// Backward pass over `count` stages (local s = count-1 .. 0).  Starting
+// state (P, Psi, cbar; and V = I, v = 0, Q_w_hat = 0 for RED) must be in LDS.
+//   RED   : Alg. 4 (reduction with the preliminary terminal P = 0)
+//   SOLVE : Alg. 1-2 forming K, k; store(s) sees P_t, Psi_t, K, k after
+//           stage s, pre(s) sees P_{t+1}, Psi_{t+1}, cbar_{t+1} before it
+//   neither: elimination of a subproblem with known terminal (Alg. 1-2)
+template <int NX, int NU, bool RED, bool SOLVE, class Get, class Pre, class Store>
+__device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int32_t *info, int inst,
+                          int stage_base, int fail_code, Pre pre, Store store) {
+    static_assert(NX % 16 == 0 && NU % 16 == 0, "MFMA path needs multiples of 16");
+    static_assert(NX <= 64 && NU <= 64, "per-wave vector roles assume NX, NU <= 64");
+    constexpr int NW = NX + NU, TX = NX / 16, TU = NU / 16;
+    const int tid = threadIdx.x, w = wave(), l = lane();
+    count = uni(count);
+    Prefetch<NX, NU> pf;
+    if (tid == 0) S.bad = 0;
+    if (count > 0) {
+        prefetch_stage<NX, NU>(pf, get(count - 1));
+        commit_stage(S, pf);
+    }
+    __syncthreads();
+    for (int s = count - 1; s >= 0; --s) {
+        // results of stage s+1 are still intact here (overwritten in phases D/E)
+        if (s < count - 1) store(s + 1, S);
+        // stage s inputs: A, B, a, lx, lw, c in LDS; Qx/Qxw'/Qw tiles in pf.q
+        d4 qt[Prefetch<NX, NU>::PER_WAVE];
+#pragma unroll
+        for (int u = 0; u < Prefetch<NX, NU>::PER_WAVE; ++u) qt[u] = pf.q[u];
+        if (s > 0) prefetch_stage<NX, NU>(pf, get(s - 1));
+        pre(s, S);
+        // ---- phase A: W = P[A B], (RED) B'V; P a, Psi - P a, (RED) V'a
+        {
+            constexpr int TW = TX * (TX + TU), TBV = RED ? TU * TX : 0;
+            for (int t = w; t < TW + TBV; t += 4) {
+                d4 acc = zero4();
+                if (t < TW) {
+                    const int ti = t / (TX + TU), tj = t % (TX + TU);
+                    if (tj < TX)
+                        acc = mma<NX, true, false>(acc, S.P, NX, S.A, NX, ti, tj);
+                    else
+                        acc = mma<NX, true, false>(acc, S.P, NX, S.B, NU, ti, tj - TX);
+                    tile_for(ti, tj, [&](int r, int i, int j) { S.W[i * NW + j] = acc[r]; });
+                } else if constexpr (RED) {
+                    const int u = t - TW, ti = u / TX, tj = u % TX;
+                    acc = mma<NX, true, false>(acc, S.B, NU, S.V, NX, ti, tj);
+                    tile_for(ti, tj, [&](int r, int i, int j) { S.BV[i * NX + j] = acc[r]; });
+                }
+            }
+            if (w == 0) {
+                double part = 0;
+                if (l < NX) {
+                    double pa = 0;
+#pragma unroll 8
+                    for (int k = 0; k < NX; ++k) pa += S.P[k * NX + l] * S.av[k];
+                    S.pt[l] = S.Psi[l] - pa;
+                    part = S.av[l] * (0.5 * pa - S.Psi[l]);
+                }
+                // cbar += 1/2 a'Pa - Psi'a + c (Alg. 2, with P_{t+1}, Psi_{t+1})
+                part = wave_sum(part);
+                if (l == 0) S.cbar += part + S.c;
+            } else if (RED && tid >= 64 && tid < 64 + NX) {
+                const int i = tid - 64;
+                double acc = 0;
+#pragma unroll 8
+                for (int k = 0; k < NX; ++k) acc += S.V[k * NX + i] * S.av[k];
+                S.Vta[i] = acc;
+            }
+        }
+        __syncthreads();
+        // ---- phase B: F = Qx + A'W_A (lower), H' = Qxw' + B'W_A, G = Qw + B'W_B (lower)
+        {
+            using PF = Prefetch<NX, NU>;
+#pragma unroll
+            for (int u = 0; u < PF::PER_WAVE; ++u) {
+                const int t = w + 4 * u;
+                if (t < PF::TILES) {
+                    int kind, ti, tj;
+                    phaseB_tile<NX, NU>(t, kind, ti, tj);
+                    d4 acc = qt[u];
+                    if (kind == 0) {
+                        acc = mma<NX, true, false>(acc, S.A, NX, S.W, NW, ti, tj);
+                        tile_for(ti, tj, [&](int r, int i, int j) { put_sym(S.F, NX, ti, tj, i, j, acc[r]); });
+                    } else if (kind == 1) {
+                        acc = mma<NX, true, false>(acc, S.B, NU, S.W, NW, ti, tj);
+                        tile_for(ti, tj, [&](int r, int i, int j) { S.HT[i * NX + j] = acc[r]; });
+                    } else {
+                        acc = mma<NX, true, false>(acc, S.B, NU, S.W + NX, NW, ti, tj);
+                        tile_for(ti, tj, [&](int r, int i, int j) { put_sym(S.G, NU, ti, tj, i, j, acc[r]); });
+                    }
+                }
+            }
+            if (tid >= 192 && tid < 192 + NX) {
+                const int i = tid - 192;
+                double acc = -S.lx[i];
+#pragma unroll 8
+                for (int k = 0; k < NX; ++k) acc += S.A[k * NX + i] * S.pt[k];
+                S.gx[i] = acc;
+            } else if (tid >= 128 && tid < 128 + NU) {
+                const int i = tid - 128;
+                double acc = -S.lw[i];
+#pragma unroll 8
+                for (int k = 0; k < NX; ++k) acc += S.B[k * NU + i] * S.pt[k];
+                S.gw[i] = acc;
+            }
+        }
+        __syncthreads();
+        // ---- phase C: factor and invert G (wave 0); (RED) A'V into W (waves 1-3)
+        if (w == 0) {
+            const int f = chol_inv_wave<NU>(S.G, S.LiT);
+            if (f && l == 0) S.bad = 1;
+        } else if constexpr (RED) {
+            for (int t = w - 1; t < TX * TX; t += 3) {
+                const int ti = t / TX, tj = t % TX;
+                d4 acc = mma<NX, true, false>(zero4(), S.A, NX, S.V, NX, ti, tj);
+                tile_for(ti, tj, [&](int r, int i, int j) { S.W[i * NX + j] = acc[r]; });
+            }
+        }
+        __syncthreads();
+        if (tid == 0 && S.bad) {
+            record_failure(info, inst, fail_code, stage_base < 0 ? -1 : stage_base + s);
+            S.bad = 0;
+        }
+        // ---- phase D: Y = L^{-1} H', (RED) X = L^{-1} B'V, z = L^{-1} g_w
+        {
+            constexpr int TY = TU * TX, TXX = RED ? TU * TX : 0;
+            for (int t = w; t < TY + TXX; t += 4) {
+                const int u = t < TY ? t : t - TY, ti = u / TX, tj = u % TX;
+                if (t < TY) {
+                    d4 acc = mma<NU, true, false>(zero4(), S.LiT, NU, S.HT, NX, ti, tj);
+                    tile_for(ti, tj, [&](int r, int i, int j) { S.Y[i * NX + j] = acc[r]; });
+                } else if constexpr (RED) {
+                    d4 acc = mma<NU, true, false>(zero4(), S.LiT, NU, S.BV, NX, ti, tj);
+                    tile_for(ti, tj, [&](int r, int i, int j) { S.X[i * NX + j] = acc[r]; });
+                }
+            }
+            if (tid >= 192 && tid < 192 + NU) {
+                const int i = tid - 192;
+                double acc = 0;
+#pragma unroll
+                for (int k = 0; k < NU; ++k) acc += S.LiT[k * NU + i] * S.gw[k];
+                S.z[i] = acc;
+            }
+        }
+        __syncthreads();
+        // ---- phase E: P = F - Y'Y, (RED) Q_w_hat += X'X, V = A'V - Y'X,
+        //      (SOLVE) K = -L^{-T} Y, k = L^{-T} z;
+        //      Psi = g_x - Y'z, (RED) v += V'a + X'z, cbar -= z'z/2
+        {
+            constexpr int TL = TX * (TX + 1) / 2, TQ = RED ? TL : 0, TV = RED ? TX * TX : 0,
+                          TK = SOLVE ? TU * TX : 0;
+            for (int t = w; t < TL + TQ + TV + TK; t += 4) {
+                if (t < TL) {
+                    int ti, tj;
+                    lower_tile(t, ti, tj);
+                    d4 acc = mma<NU, true, false>(zero4(), S.Y, NX, S.Y, NX, ti, tj);
+                    tile_for(ti, tj, [&](int r, int i, int j) { put_sym(S.P, NX, ti, tj, i, j, S.F[i * NX + j] - acc[r]); });
+                } else if (t < TL + TQ) {
+                    if constexpr (RED) {
+                        int ti, tj;
+                        lower_tile(t - TL, ti, tj);
+                        d4 acc = mma<NU, true, false>(zero4(), S.X, NX, S.X, NX, ti, tj);
+                        tile_for(ti, tj, [&](int r, int i, int j) {
+                            put_sym(S.Qh, NX, ti, tj, i, j, S.Qh[i * NX + j] + acc[r]);
+                        });
+                    }
+                } else if (t < TL + TQ + TV) {
+                    if constexpr (RED) {
+                        const int u = t - TL - TQ, ti = u / TX, tj = u % TX;
+                        d4 acc = mma<NU, true, false>(zero4(), S.Y, NX, S.X, NX, ti, tj);
+                        tile_for(ti, tj, [&](int r, int i, int j) { S.V[i * NX + j] = S.W[i * NX + j] - acc[r]; });
+                    }
+                } else {
+                    if constexpr (SOLVE) {
+                        const int u = t - TL - TQ - TV, ti = u / TX, tj = u % TX;
+                        d4 acc = mma<NU, true, false>(zero4(), S.G, NU, S.Y, NX, ti, tj);
+                        tile_for(ti, tj, [&](int r, int i, int j) { S.K[i * NX + j] = -acc[r]; });
+                    }
+                }
+            }
+            if (tid >= 192 && tid < 192 + NX) {
+                const int i = tid - 192;
+                double acc = S.gx[i];
+#pragma unroll
+                for (int r = 0; r < NU; ++r) acc -= S.Y[r * NX + i] * S.z[r];
+                S.Psi[i] = acc;
+            } else if (RED && tid >= 128 && tid < 128 + NX) {
+                const int i = tid - 128;
+                double acc = S.Vta[i];
+#pragma unroll
+                for (int r = 0; r < NU; ++r) acc += S.X[r * NX + i] * S.z[r];
+                S.v[i] += acc;
+            } else if (SOLVE && tid >= 128 && tid < 128 + NU) {
+                const int i = tid - 128;
+                double acc = 0;
+#pragma unroll
+                for (int r = 0; r < NU; ++r) acc += S.G[r * NU + i] * S.z[r];
+                S.kk[i] = acc;
+            } else if (tid >= 64 && tid < 128) {
+                const double zz = wave_sum(l < NU ? S.z[l] * S.z[l] : 0.0);
+                if (l == 0) S.cbar -= 0.5 * zz;
+            }
+            if (s > 0) commit_stage(S, pf);
+        }
+        __syncthreads();
+    }
+    if (count > 0) {
+        store(0, S);
+        __syncthreads();
+    }
+}
+
+}  // namespace mf
+}  // namespace rs

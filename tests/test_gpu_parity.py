@@ -57,7 +57,7 @@ def test_ragged_and_degenerate_trees(N, Ns, b):
     _check(prob, sol)
 
 
-@pytest.mark.parametrize("nx,nu", [(1, 1), (2, 1), (2, 2), (3, 2), (6, 3), (8, 4), (16, 8)])
+@pytest.mark.parametrize("nx,nu", [(1, 1), (2, 1), (2, 2), (3, 2), (6, 3), (8, 4), (16, 8), (16, 16), (32, 16), (32, 32)])
 def test_shapes(nx, nu):
     prob = W.g2(nx, nu, 96, seed=nx * 10 + nu)
     Ns = max(4, -(-nx // nu))
