@@ -165,6 +165,52 @@ struct StageSrc {
     double c;
 };
 
+// Problem descriptor copied once into wave-uniform registers.  Reading it
+// through the global-memory reference at every stage would re-issue a chain of
+// dependent loads (the compiler cannot prove the descriptor unchanged across
+// the kernel's own global stores).
+__device__ __forceinline__ const double *uni_ptr(const double *q) {
+    const uint64_t v = (uint64_t)q;
+    const uint32_t lo = (uint32_t)uni((int)(uint32_t)(v & 0xffffffffu)), hi = (uint32_t)uni((int)(uint32_t)(v >> 32));
+    return (const double *)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+    const uint32_t lo = (uint32_t)uni((int)(uint32_t)((uint64_t)v & 0xffffffffu)),
+                   hi = (uint32_t)uni((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ DevProb load_prob(const DevProb *tab, int i) {
+    const DevProb r = tab[i];
+    DevProb u;
+    u.Qx = uni_ptr(r.Qx);
+    u.Qw = uni_ptr(r.Qw);
+    u.Qxw = uni_ptr(r.Qxw);
+    u.A = uni_ptr(r.A);
+    u.B = uni_ptr(r.B);
+    u.QxN = uni_ptr(r.QxN);
+    u.x0 = uni_ptr(r.x0);
+    u.a = uni_ptr(r.a);
+    u.lx = uni_ptr(r.lx);
+    u.lw = uni_ptr(r.lw);
+    u.c = uni_ptr(r.c);
+    u.lN = uni_ptr(r.lN);
+    u.cN = uni_ptr(r.cN);
+    u.x = const_cast<double *>(uni_ptr(r.x));
+    u.w = const_cast<double *>(uni_ptr(r.w));
+    u.lam = const_cast<double *>(uni_ptr(r.lam));
+    u.obj = const_cast<double *>(uni_ptr(r.obj));
+    u.sQx = uni64(r.sQx);
+    u.sQw = uni64(r.sQw);
+    u.sQxw = uni64(r.sQxw);
+    u.sA = uni64(r.sA);
+    u.sB = uni64(r.sB);
+    u.nx = uni(r.nx);
+    u.nu = uni(r.nu);
+    u.N = uni(r.N);
+    u.pad = 0;
+    return u;
+}
+
 __device__ __forceinline__ StageSrc prob_stage(const DevProb &p, int t) {
     StageSrc s;
     s.Qx = p.Qx + (int64_t)t * p.sQx;

@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(NT) k_leaf_up(GroupArgs g) {
     __shared__ __attribute__((aligned(16))) char raw[LeafSmem<T, NX, NU>::bytes];
     const LeafItem it = load_leaf(g.leaves, blockIdx.x);
     if (it.flags & LEAF_TOP) return;
-    const DevProb &p = g.probs[it.inst];
+    const DevProb p = load_prob(g.probs, it.inst);
     const SlotLayout SL{NX};
     double *out = g.slots + (int64_t)it.slot * SL.size();
     auto get = [&](int s) { return prob_stage(p, it.t0 + s); };
@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(NT) k_leaf_down(GroupArgs g) {
     auto &S = *reinterpret_cast<Smem<T, NX, NU, false> *>(raw);
     using SC = LeafScratch<NX, NU>;
     const LeafItem it = load_leaf(g.leaves, blockIdx.x);
-    const DevProb &p = g.probs[it.inst];
+    const DevProb p = load_prob(g.probs, it.inst);
     const SlotLayout SL{NX};
     const int tid = threadIdx.x;
     const bool known_end = (it.flags & (LEAF_LAST | LEAF_TOP)) != 0;
@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(NT) k_tree(GroupArgs g) {
         }
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const DevProb &p = g.probs[it.inst];
+        const DevProb p = load_prob(g.probs, it.inst);
         double *slots = g.slots;
         auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
         auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };

@@ -66,8 +66,7 @@ __device__ void reduce_to(MSmem<NX, NU, true, false> &S, Get get, int count, dou
     }
     if (tid == 0) S.cbar = 0.0;
     __syncthreads();
-    mfma_pass<NX, NU, true, false>(
-        S, get, count, info, inst, stage_base, fail_code, [](int, auto &) {}, [](int, auto &) {});
+    mfma_pass<NX, NU, true, false>(S, get, count, info, inst, stage_base, fail_code, [](int, auto &) {}, NoEmit{});
     const SlotLayout SL{NX};
     for (int e = tid; e < NX * NX; e += NT) {
         const int i = e / NX, j = e % NX;
@@ -88,8 +87,7 @@ template <int NX, int NU, class Get>
 __device__ void eliminate_to(MSmem<NX, NU, false, false> &S, Get get, int count, double *out, int32_t *info,
                              int inst, int stage_base, int fail_code) {
     const int tid = threadIdx.x;
-    mfma_pass<NX, NU, false, false>(
-        S, get, count, info, inst, stage_base, fail_code, [](int, auto &) {}, [](int, auto &) {});
+    mfma_pass<NX, NU, false, false>(S, get, count, info, inst, stage_base, fail_code, [](int, auto &) {}, NoEmit{});
     const SlotLayout SL{NX};
     for (int e = tid; e < NX * NX; e += NT) out[SL.Qx() + e] = S.P[e];
     for (int i = tid; i < NX; i += NT) out[SL.lx() + i] = -S.Psi[i];
@@ -99,8 +97,11 @@ __device__ void eliminate_to(MSmem<NX, NU, false, false> &S, Get get, int count,
 // Forward recursion (Alg. 3) over `count` stages from x in S.x.  Per stage
 // the feedback K, k (and for leaves P_t, Psi_t) come from `fac(s)`, the
 // dynamics from get(s).  Two barriers per stage; the next stage's operands
-// are prefetched into registers and committed to LDS once free.  B is
-// double-buffered (S.B / S.W) because it is read in the second half.
+// are prefetched into registers and committed to LDS once free.  K, A and B
+// are committed transposed so that the lane-per-row products read
+// consecutive LDS words; B is double-buffered because it is read in the
+// second half.  LDS use: K' in W[0, NU*NX), the second B buffer in
+// W[NU*NX, 2*NU*NX), A' in S.A, P in S.P (symmetric).
 template <int NX, int NU, bool LAM>
 struct FwdPrefetch {
     static constexpr int NK = (NU * NX + NT - 1) / NT, NA = (NX * NX + NT - 1) / NT, NB = (NX * NU + NT - 1) / NT,
@@ -146,15 +147,16 @@ template <int NX, int NU, bool LAM>
 __device__ __forceinline__ void fwd_commit_main(MSmem<NX, NU, false, true> &S, const FwdPrefetch<NX, NU, LAM> &f) {
     using FP = FwdPrefetch<NX, NU, LAM>;
     const int tid = threadIdx.x;
+    double *KT = S.W;
 #pragma unroll
     for (int q = 0; q < FP::NK; ++q) {
-        const int e = tid + q * NT;
-        if (e < NU * NX) S.K[e] = f.k_[q];
+        const int e = tid + q * NT;        // K[r][c], e = r*NX + c
+        if (e < NU * NX) KT[(e % NX) * NU + e / NX] = f.k_[q];
     }
 #pragma unroll
     for (int q = 0; q < FP::NA; ++q) {
-        const int e = tid + q * NT;
-        if (e < NX * NX) S.A[e] = f.a_[q];
+        const int e = tid + q * NT;        // A[i][c], e = i*NX + c
+        if (e < NX * NX) S.A[(e % NX) * NX + e / NX] = f.a_[q];
     }
     if constexpr (LAM) {
 #pragma unroll
@@ -171,23 +173,24 @@ __device__ __forceinline__ void fwd_commit_main(MSmem<NX, NU, false, true> &S, c
 }
 
 template <int NX, int NU, bool LAM>
-__device__ __forceinline__ void fwd_commit_B(double *Bbuf, const FwdPrefetch<NX, NU, LAM> &f) {
+__device__ __forceinline__ void fwd_commit_B(double *BT, const FwdPrefetch<NX, NU, LAM> &f) {
     using FP = FwdPrefetch<NX, NU, LAM>;
     const int tid = threadIdx.x;
 #pragma unroll
     for (int q = 0; q < FP::NB; ++q) {
-        const int e = tid + q * NT;
-        if (e < NX * NU) Bbuf[e] = f.b_[q];
+        const int e = tid + q * NT;        // B[i][r], e = i*NU + r
+        if (e < NX * NU) BT[(e % NU) * NX + e / NU] = f.b_[q];
     }
 }
 
 template <int NX, int NU, bool LAM, class Get, class Fac, class Emit>
 __device__ void forward_m(MSmem<NX, NU, false, true> &S, Get get, int count, Fac fac, Emit emit) {
-    static_assert(NX * NU <= NX * (NX + NU), "second B buffer lives in W");
+    static_assert(2 * NX * NU <= NX * (NX + NU), "K' and the second B buffer live in W");
     const int tid = threadIdx.x;
     count = uni(count);
     FwdPrefetch<NX, NU, LAM> f;
-    double *Bcur = S.B, *Bnxt = S.W;
+    const double *KT = S.W;
+    double *Bcur = S.B, *Bnxt = S.W + NU * NX;
     if (count > 0) {
         fwd_fetch<NX, NU, LAM>(f, get, fac, 0);
         fwd_commit_main<NX, NU, LAM>(S, f);
@@ -200,19 +203,19 @@ __device__ void forward_m(MSmem<NX, NU, false, true> &S, Get get, int count, Fac
         if (tid < NU) {
             double acc = S.kk[tid];
 #pragma unroll 8
-            for (int c = 0; c < NX; ++c) acc += S.K[tid * NX + c] * S.x[c];
+            for (int c = 0; c < NX; ++c) acc += KT[c * NU + tid] * S.x[c];
             S.wv[tid] = acc;
         } else if (tid >= 64 && tid < 64 + NX) {
             const int i = tid - 64;
             double acc = S.av[i];
 #pragma unroll 8
-            for (int c = 0; c < NX; ++c) acc += S.A[i * NX + c] * S.x[c];
+            for (int c = 0; c < NX; ++c) acc += S.A[c * NX + i] * S.x[c];
             S.ax[i] = acc;
         } else if (LAM && tid >= 128 && tid < 128 + NX) {
             const int i = tid - 128;
             double acc = -S.Psi[i];
 #pragma unroll 8
-            for (int c = 0; c < NX; ++c) acc += S.P[i * NX + c] * S.x[c];
+            for (int c = 0; c < NX; ++c) acc += S.P[c * NX + i] * S.x[c];
             emit.lam(s, i, acc);
         }
         emit.x(s, S.x);
@@ -222,7 +225,7 @@ __device__ void forward_m(MSmem<NX, NU, false, true> &S, Get get, int count, Fac
         if (tid < NX) {
             double acc = S.ax[tid];
 #pragma unroll
-            for (int r = 0; r < NU; ++r) acc += Bcur[tid * NU + r] * S.wv[r];
+            for (int r = 0; r < NU; ++r) acc += Bcur[r * NX + tid] * S.wv[r];
             S.x[tid] = acc;
         }
         emit.w(s, S.wv);
@@ -240,7 +243,7 @@ __global__ void __launch_bounds__(NT, 2) km_leaf_up(GroupArgs g) {
     __shared__ __attribute__((aligned(16))) char raw[Sizes<NX, NU>::up];
     const LeafItem it = load_leaf_u(g.leaves, blockIdx.x);
     if (it.flags & LEAF_TOP) return;
-    const DevProb &p = g.probs[it.inst];
+    const DevProb p = load_prob(g.probs, it.inst);
     const SlotLayout SL{NX};
     double *out = g.slots + (int64_t)it.slot * SL.size();
     auto get = [&](int s) { return prob_stage(p, it.t0 + s); };
@@ -271,12 +274,12 @@ struct LeafFac {
 };
 
 template <int NX, int NU>
-__global__ void __launch_bounds__(NT, 2) km_leaf_down(GroupArgs g) {
+__global__ void __launch_bounds__(NT, 3) km_leaf_down(GroupArgs g) {
     __shared__ __attribute__((aligned(16))) char raw[sizeof(MSmem<NX, NU, false, true>)];
     auto &S = *reinterpret_cast<MSmem<NX, NU, false, true> *>(raw);
     using LF = LeafFac<NX, NU>;
     const LeafItem it = load_leaf_u(g.leaves, blockIdx.x);
-    const DevProb &p = g.probs[it.inst];
+    const DevProb p = load_prob(g.probs, it.inst);
     const SlotLayout SL{NX};
     const int tid = threadIdx.x;
     const bool known_end = (it.flags & (LEAF_LAST | LEAF_TOP)) != 0;
@@ -290,15 +293,15 @@ __global__ void __launch_bounds__(NT, 2) km_leaf_down(GroupArgs g) {
     if (tid == 0) S.cbar = known_end ? (p.cN ? p.cN[0] : 0.0) : msg[SL.cb()];
     __syncthreads();
     auto get = [&](int s) { return prob_stage(p, it.t0 + s); };
-    mfma_pass<NX, NU, false, true>(
-        S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {},
-        [&](int s, auto &Sm) {
-            double *d = scr + (int64_t)s * LF::per;
-            for (int e = tid; e < NU * NX; e += NT) d[LF::K_ + e] = Sm.K[e];
-            for (int e = tid; e < NX * NX; e += NT) d[LF::P_ + e] = Sm.P[e];
-            if (tid < NX) d[LF::Psi_ + tid] = Sm.Psi[tid];
-            if (tid < NU) d[LF::k_ + tid] = Sm.kk[tid];
-        });
+    struct Out {
+        double *scr;
+        __device__ double *at(int s) const { return scr + (int64_t)s * LF::per; }
+        __device__ void K(int s, int i, int j, double v) const { at(s)[LF::K_ + i * NX + j] = v; }
+        __device__ void P(int s, int i, int j, double v) const { at(s)[LF::P_ + i * NX + j] = v; }
+        __device__ void Psi(int s, int i, double v) const { at(s)[LF::Psi_ + i] = v; }
+        __device__ void k(int s, int i, double v) const { at(s)[LF::k_ + i] = v; }
+    };
+    mfma_pass<NX, NU, false, true>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {}, Out{scr});
     if ((it.flags & LEAF_TOP) && p.obj) {
         if (threadIdx.x < 64) {
             double part = 0;
@@ -350,6 +353,18 @@ struct SlotFac {
     __device__ const double *Psi(int s) const { return nullptr; }
 };
 
+// Master feedback K, k of each stage goes to the stage's slot.
+template <int NX>
+struct SlotOut {
+    double *slots;
+    int first;
+    __device__ double *at(int s) const { return slots + (int64_t)(first + s) * SlotLayout{NX}.size(); }
+    __device__ void K(int s, int i, int j, double v) const { at(s)[SlotLayout{NX}.K() + i * NX + j] = v; }
+    __device__ void P(int, int, int, double) const {}
+    __device__ void Psi(int, int, double) const {}
+    __device__ void k(int s, int i, double v) const { at(s)[SlotLayout{NX}.k() + i] = v; }
+};
+
 template <int NX>
 __device__ void tree_solve_m(MSmem<NX, NX, false, true> &S, const TreeItem &it, const DevProb &p, GroupArgs &g) {
     const SlotLayout SL{NX};
@@ -371,15 +386,11 @@ __device__ void tree_solve_m(MSmem<NX, NX, false, true> &S, const TreeItem &it, 
         S, get, it.count, g.info, it.inst, -1, 3,
         [&](int s, auto &Sm) {          // M2 for child s: cost to go at the end of stage s
             double *d = slot(it.first + s);
-            for (int e = tid; e < NX * NX; e += NT) d[SL.P() + e] = Sm.P[e];
+            block_copy<NX * NX>(d + SL.P(), Sm.P);
             if (tid < NX) d[SL.Psi() + tid] = Sm.Psi[tid];
             if (tid == 0) d[SL.cb()] = Sm.cbar;
         },
-        [&](int s, auto &Sm) {          // master feedback of stage s
-            double *d = slot(it.first + s);
-            for (int e = tid; e < NX * NX; e += NT) d[SL.K() + e] = Sm.K[e];
-            if (tid < NX) d[SL.k() + tid] = Sm.kk[tid];
-        });
+        SlotOut<NX>{slots, it.first});
     if (top && p.obj && tid < 64) {
         double part = 0;
         if (tid < NX) {
@@ -438,7 +449,7 @@ __global__ void __launch_bounds__(NT) km_tree(GroupArgs g) {
         }
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const DevProb &p = g.probs[it.inst];
+        const DevProb p = load_prob(g.probs, it.inst);
         double *slots = g.slots;
         auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
         auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };

@@ -34,19 +34,42 @@ __device__ __forceinline__ int lane() { return (int)(threadIdx.x & 63); }
 // the 16x16x4 f64 instruction (checked on gfx950): A element (i,k) in lane
 // i + 16k, B element (k,j) in lane j + 16k; result element
 // (lane/16 + 4r, lane%16) in acc[r].
+// All operand reads of a tile are issued before its first MFMA so that the
+// LDS latency is paid once per tile, not once per instruction.
 template <int K, bool TA, bool TB>
 __device__ __forceinline__ d4 mma(d4 acc, const double *__restrict__ A, int lda, const double *__restrict__ B,
                                   int ldb, int ti, int tj) {
+    constexpr int S = K / 4;
     const int l = lane(), r16 = l & 15, k4 = l >> 4;
     const int i = 16 * ti + r16, j = 16 * tj + r16;
+    double a[S], b[S];
 #pragma unroll
-    for (int k0 = 0; k0 < K; k0 += 4) {
-        const int k = k0 + k4;
-        const double a = TA ? A[k * lda + i] : A[i * lda + k];
-        const double b = TB ? B[j * ldb + k] : B[k * ldb + j];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    for (int s = 0; s < S; ++s) {
+        const int k = 4 * s + k4;
+        a[s] = TA ? A[k * lda + i] : A[i * lda + k];
+        b[s] = TB ? B[j * ldb + k] : B[k * ldb + j];
     }
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
     return acc;
+}
+
+// dst[e] = src[e] for e < n (compile-time n), all reads before all writes.
+template <int n, class D, class Sx>
+__device__ __forceinline__ void block_copy(D *__restrict__ dst, const Sx *__restrict__ src) {
+    constexpr int R = (n + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    double v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int e = tid + q * NT;
+        v[q] = (e < n) ? (double)src[e] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int e = tid + q * NT;
+        if (e < n) dst[e] = (D)v[q];
+    }
 }
 
 __device__ __forceinline__ d4 zero4() { return d4{0.0, 0.0, 0.0, 0.0}; }
@@ -81,16 +104,13 @@ __device__ __forceinline__ void lower_tile(int t, int &ti, int &tj) {
 template <int NX, int NU, bool RED, bool SOLVE>
 struct MSmem {
     static constexpr int NW = NX + NU;
-    double P[NX * NX];          // P_{t+1}, then P_t
+    double P[NX * NX];          // P_{t+1}; F_{t+1} (phase B); P_t (phase E)
     double A[NX * NX];          // stage A_t
     double B[NX * NU];          // stage B_t
-    double W[NX * NW];          // P [A B]; A'V in the Alg. 4 pass
-    double F[NX * NX];
+    double W[NX * NW];          // P [A B]; then A'V (RED, first NX*NX) and Y (last NU*NX)
     double HT[NU * NX];         // H'
     double G[NU * NU];          // G, then L^{-1} (row-major) with G = L L'
     double LiT[NU * NU];        // L^{-T} (row-major), i.e. L^{-1} by columns
-    double Y[NU * NX];          // L^{-1} H'
-    double K[SOLVE ? NU * NX : 1];
     double V[RED ? NX * NX : 1];
     double Qh[RED ? NX * NX : 1];
     double BV[RED ? NU * NX : 1];   // B'V
@@ -100,6 +120,21 @@ struct MSmem {
     double v[RED ? NX : 1], Vta[RED ? NX : 1];
     double c, cbar, red[4];
     int bad;
+    // F is formed in phase B after the last read of P_{t+1} (phase A) and is
+    // turned into P_t in place in phase E; Y = L^{-1} H' lives in the part of
+    // W that A'V does not use.
+    __device__ double *F() { return P; }
+    __device__ double *Y() { return W + NX * NX; }
+    static_assert(NX * NW >= NX * NX + NU * NX, "Y fits behind A'V in W");
+};
+
+// Results of a solve-mode stage, emitted from the registers that computed
+// them (phase E).  The default does nothing (reduction / elimination).
+struct NoEmit {
+    __device__ void K(int, int, int, double) const {}
+    __device__ void P(int, int, int, double) const {}
+    __device__ void Psi(int, int, double) const {}
+    __device__ void k(int, int, double) const {}
 };
 
 // Per-thread registers holding the next stage's inputs until they can be
@@ -254,12 +289,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Backward pass over `count` stages (local s = count-1 .. 0).  Starting
 // state (P, Psi, cbar; and V = I, v = 0, Q_w_hat = 0 for RED) must be in LDS.
 //   RED   : Alg. 4 (reduction with the preliminary terminal P = 0)
-//   SOLVE : Alg. 1-2 forming K, k; store(s) sees P_t, Psi_t, K, k after
-//           stage s, pre(s) sees P_{t+1}, Psi_{t+1}, cbar_{t+1} before it
+//   SOLVE : Alg. 1-2 forming K, k; out.K / out.P / out.Psi / out.k receive
+//           K_{t+1}, P_t, Psi_t, k_{t+1} of stage s from the lanes that
+//           computed them; pre(s) sees P_{t+1}, Psi_{t+1}, cbar_{t+1}
 //   neither: elimination of a subproblem with known terminal (Alg. 1-2)
-template <int NX, int NU, bool RED, bool SOLVE, class Get, class Pre, class Store>
+template <int NX, int NU, bool RED, bool SOLVE, class Get, class Pre, class Out>
 __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int32_t *info, int inst,
-                          int stage_base, int fail_code, Pre pre, Store store) {
+                          int stage_base, int fail_code, Pre pre, Out out) {
     static_assert(NX % 16 == 0 && NU % 16 == 0, "MFMA path needs multiples of 16");
     static_assert(NX <= 64 && NU <= 64, "per-wave vector roles assume NX, NU <= 64");
     constexpr int NW = NX + NU, TX = NX / 16, TU = NU / 16;
@@ -273,8 +309,6 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
     }
     __syncthreads();
     for (int s = count - 1; s >= 0; --s) {
-        // results of stage s+1 are still intact here (overwritten in phases D/E)
-        if (s < count - 1) store(s + 1, S);
         // stage s inputs: A, B, a, lx, lw, c in LDS; Qx/Qxw'/Qw tiles in pf.q
         d4 qt[Prefetch<NX, NU>::PER_WAVE];
 #pragma unroll
@@ -299,7 +333,7 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                     tile_for(ti, tj, [&](int r, int i, int j) { S.BV[i * NX + j] = acc[r]; });
                 }
             }
-            if (w == 0) {
+            if (w == 3) {
                 double part = 0;
                 if (l < NX) {
                     double pa = 0;
@@ -311,8 +345,8 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                 // cbar += 1/2 a'Pa - Psi'a + c (Alg. 2, with P_{t+1}, Psi_{t+1})
                 part = wave_sum(part);
                 if (l == 0) S.cbar += part + S.c;
-            } else if (RED && tid >= 64 && tid < 64 + NX) {
-                const int i = tid - 64;
+            } else if (RED && tid >= 128 && tid < 128 + NX) {
+                const int i = tid - 128;
                 double acc = 0;
 #pragma unroll 8
                 for (int k = 0; k < NX; ++k) acc += S.V[k * NX + i] * S.av[k];
@@ -332,7 +366,7 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                     d4 acc = qt[u];
                     if (kind == 0) {
                         acc = mma<NX, true, false>(acc, S.A, NX, S.W, NW, ti, tj);
-                        tile_for(ti, tj, [&](int r, int i, int j) { put_sym(S.F, NX, ti, tj, i, j, acc[r]); });
+                        tile_for(ti, tj, [&](int r, int i, int j) { put_sym(S.F(), NX, ti, tj, i, j, acc[r]); });
                     } else if (kind == 1) {
                         acc = mma<NX, true, false>(acc, S.B, NU, S.W, NW, ti, tj);
                         tile_for(ti, tj, [&](int r, int i, int j) { S.HT[i * NX + j] = acc[r]; });
@@ -380,7 +414,7 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                 const int u = t < TY ? t : t - TY, ti = u / TX, tj = u % TX;
                 if (t < TY) {
                     d4 acc = mma<NU, true, false>(zero4(), S.LiT, NU, S.HT, NX, ti, tj);
-                    tile_for(ti, tj, [&](int r, int i, int j) { S.Y[i * NX + j] = acc[r]; });
+                    tile_for(ti, tj, [&](int r, int i, int j) { S.Y()[i * NX + j] = acc[r]; });
                 } else if constexpr (RED) {
                     d4 acc = mma<NU, true, false>(zero4(), S.LiT, NU, S.BV, NX, ti, tj);
                     tile_for(ti, tj, [&](int r, int i, int j) { S.X[i * NX + j] = acc[r]; });
@@ -405,8 +439,18 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                 if (t < TL) {
                     int ti, tj;
                     lower_tile(t, ti, tj);
-                    d4 acc = mma<NU, true, false>(zero4(), S.Y, NX, S.Y, NX, ti, tj);
-                    tile_for(ti, tj, [&](int r, int i, int j) { put_sym(S.P, NX, ti, tj, i, j, S.F[i * NX + j] - acc[r]); });
+                    d4 acc = mma<NU, true, false>(zero4(), S.Y(), NX, S.Y(), NX, ti, tj);
+                    tile_for(ti, tj, [&](int r, int i, int j) {
+                        if (ti != tj || i >= j) {
+                            const double v = S.F()[i * NX + j] - acc[r];
+                            S.P[i * NX + j] = v;
+                            S.P[j * NX + i] = v;
+                            if constexpr (SOLVE) {
+                                out.P(s, i, j, v);
+                                if (i != j) out.P(s, j, i, v);
+                            }
+                        }
+                    });
                 } else if (t < TL + TQ) {
                     if constexpr (RED) {
                         int ti, tj;
@@ -419,14 +463,14 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                 } else if (t < TL + TQ + TV) {
                     if constexpr (RED) {
                         const int u = t - TL - TQ, ti = u / TX, tj = u % TX;
-                        d4 acc = mma<NU, true, false>(zero4(), S.Y, NX, S.X, NX, ti, tj);
+                        d4 acc = mma<NU, true, false>(zero4(), S.Y(), NX, S.X, NX, ti, tj);
                         tile_for(ti, tj, [&](int r, int i, int j) { S.V[i * NX + j] = S.W[i * NX + j] - acc[r]; });
                     }
                 } else {
                     if constexpr (SOLVE) {
                         const int u = t - TL - TQ - TV, ti = u / TX, tj = u % TX;
-                        d4 acc = mma<NU, true, false>(zero4(), S.G, NU, S.Y, NX, ti, tj);
-                        tile_for(ti, tj, [&](int r, int i, int j) { S.K[i * NX + j] = -acc[r]; });
+                        d4 acc = mma<NU, true, false>(zero4(), S.G, NU, S.Y(), NX, ti, tj);
+                        tile_for(ti, tj, [&](int r, int i, int j) { out.K(s, i, j, -acc[r]); });
                     }
                 }
             }
@@ -434,8 +478,9 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                 const int i = tid - 192;
                 double acc = S.gx[i];
 #pragma unroll
-                for (int r = 0; r < NU; ++r) acc -= S.Y[r * NX + i] * S.z[r];
+                for (int r = 0; r < NU; ++r) acc -= S.Y()[r * NX + i] * S.z[r];
                 S.Psi[i] = acc;
+                if constexpr (SOLVE) out.Psi(s, i, acc);
             } else if (RED && tid >= 128 && tid < 128 + NX) {
                 const int i = tid - 128;
                 double acc = S.Vta[i];
@@ -448,16 +493,13 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
 #pragma unroll
                 for (int r = 0; r < NU; ++r) acc += S.G[r * NU + i] * S.z[r];
                 S.kk[i] = acc;
+                out.k(s, i, acc);
             } else if (tid >= 64 && tid < 128) {
                 const double zz = wave_sum(l < NU ? S.z[l] * S.z[l] : 0.0);
                 if (l == 0) S.cbar -= 0.5 * zz;
             }
             if (s > 0) commit_stage(S, pf);
         }
-        __syncthreads();
-    }
-    if (count > 0) {
-        store(0, S);
         __syncthreads();
     }
 }
