@@ -99,7 +99,14 @@ typedef struct rs_options {
     int32_t branch;      /* master stages per master subproblem (>= 2); 0 = default    */
     int32_t max_refine;  /* mixed precision: maximum refinement steps; 0 = default    */
     double tol;          /* mixed precision: relative KKT residual target; 0 = 1e-10  */
+    int32_t flags;       /* RS_PLAN_* bits                                            */
+    int32_t reserved;
 } rs_options;
+
+/* rs_options.flags: reserve workspace for the stored factorization so that
+ * rs_factor / rs_solve can be used (about (4 nx^2 + 4 nu^2 + 2 nu nx) doubles
+ * per stage more).  Implied by RS_MIXED_FP32. */
+#define RS_PLAN_FACTORED 1
 
 typedef struct rs_plan_s *rs_plan;
 
@@ -133,9 +140,14 @@ rs_status rs_batch_solve(rs_plan plan, const rs_problem *probs, void *work,
 /*
  * Factorization part only (Alg. 1 and the matrix lines of Alg. 4 on every
  * level, including the down-pass factorizations with the true terminal
- * weights).  Reads the matrix fields of probs; stores every factor in the
- * workspace.  The factors stay valid until the next rs_factor or
- * rs_batch_solve with the same plan and workspace.
+ * weights).  Reads the matrix fields of probs (Qx, Qw, Qxw, A, B, QxN);
+ * stores every factor in the workspace: per stage P_t, L^{-1} and L^{-T}
+ * (G_{t+1} = L L'), K_{t+1} and, for Alg. 4, V_t.  Numerical failures
+ * (RS_ERR_NOT_SPD with the stage, RS_ERR_SINGULAR_MASTER) go to info_dev as
+ * for rs_batch_solve.  The factors stay valid until the next rs_factor or
+ * rs_batch_solve with the same plan and workspace.  Needs a plan created
+ * with RS_PLAN_FACTORED (else RS_ERR_ARG); RS_ERR_UNSUPPORTED for shapes
+ * without factor kernels (nx, nu not multiples of 16).
  */
 rs_status rs_factor(rs_plan plan, const rs_problem *probs, void *work, size_t work_bytes,
                     void *stream, int32_t *info_dev);
@@ -143,9 +155,11 @@ rs_status rs_factor(rs_plan plan, const rs_problem *probs, void *work, size_t wo
 /*
  * Solve part only (Alg. 2-3 and the vector lines of Alg. 4): uses the factors
  * stored by the last rs_factor with the same plan and workspace, reads the
- * right-hand side fields and A, B of probs and writes the solution.  The
- * matrices must be unchanged since rs_factor.  Several rs_solve calls may
- * follow one rs_factor (iterative refinement, predictor-corrector steps).
+ * right-hand side fields (x0, a, lx, lw, c, lN, cN) and A, B, QxN of probs
+ * and writes x, w, lam and obj.  The matrices must be unchanged since
+ * rs_factor.  Several rs_solve calls may follow one rs_factor (iterative
+ * refinement, predictor-corrector steps).  The status words in info_dev are
+ * left as rs_factor wrote them (a solve adds only a tree-wait failure).
  * For RS_MIXED_FP32 plans the FP32 factors are refined in FP64 to the
  * plan's tolerance: info_dev reports RS_ERR_NOT_CONVERGED on failure.
  */
@@ -173,10 +187,12 @@ int64_t rs_plan_export(rs_plan plan, int32_t what, int64_t *out, int64_t cap_row
 /* Kernel timing (measurement aid).  While enabled, each call records a pair
  * of HIP events on its stream around every kernel it launches.
  * rs_plan_kernel_times waits for the recorded events and returns, per kernel
- * kind (0 status/queue reset, 1 leaf reduction, 2 tree levels, 3 leaf solve,
- * 4..7 reserved), the summed elapsed milliseconds and the number of
- * launches since the last reset; reset != 0 starts a new window.  ms and
- * launches point to 8 host values each. */
+ * kind, the summed elapsed milliseconds and the number of launches since the
+ * last reset; reset != 0 starts a new window.  Kinds: 0 status/queue reset;
+ * fused solve 1 leaf reduction, 2 tree levels, 3 leaf solve; rs_factor
+ * 4 leaf, 5 tree, 6 leaf down; rs_solve 7 leaf, 8 tree, 9 leaf down;
+ * 10..15 reserved.  ms and launches point to RS_KERNEL_KINDS host values. */
+#define RS_KERNEL_KINDS 16
 rs_status rs_plan_set_timing(rs_plan plan, int32_t enable);
 rs_status rs_plan_kernel_times(rs_plan plan, double *ms, int64_t *launches, int32_t reset);
 

@@ -29,7 +29,8 @@ struct Group {
     int64_t nslots = 0;
     int64_t scratch_elems = 0;
     int max_depth = 0;
-    size_t off_leaves = 0, off_items = 0, off_flags = 0, off_slots = 0, off_scratch = 0;
+    int64_t leaf_stages = 0;
+    size_t off_leaves = 0, off_items = 0, off_flags = 0, off_slots = 0, off_scratch = 0, off_fstore = 0;
 };
 
 }  // namespace
@@ -37,6 +38,7 @@ struct Group {
 struct rs_plan_s {
     int32_t count = 0;
     int Ns = 16, branch = 4, top_max = 4, prec = RS_FP64, max_refine = 0;
+    bool factored = false;          // workspace holds the stored factorization
     double tol = 1e-10;
     std::vector<int32_t> dims;
     std::vector<Group> groups;
@@ -240,6 +242,7 @@ rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *o
             return RS_ERR_UNSUPPORTED;
         }
         P->prec = opt->precision;
+        P->factored = (opt->flags & RS_PLAN_FACTORED) != 0;
         if (opt->Ns > 0) P->Ns = opt->Ns;
         if (opt->branch > 0) P->branch = opt->branch;
         if (opt->max_refine > 0) P->max_refine = opt->max_refine;
@@ -263,7 +266,7 @@ rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *o
             return RS_ERR_ARG;
         }
         const ShapeEntry *se = find_shape(nx, nu);
-        if (!se) {
+        if (!se || (P->factored && !(se->factor[0] && se->vsolve[0]))) {
             delete P;
             return RS_ERR_UNSUPPORTED;
         }
@@ -311,6 +314,9 @@ rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *o
         g.off_scratch = off;
         const size_t esz = sizeof(double);
         off = align_up(off + esz * (size_t)g.scratch_elems);
+        g.leaf_stages = g.scratch_elems / g.shape->scratch_per_stage;
+        g.off_fstore = off;
+        if (P->factored) off = align_up(off + sizeof(double) * (size_t)g.leaf_stages * LeafRec{g.nx, g.nu}.per_stage());
     }
     P->total = off;
     P->tables.assign(P->tables_bytes, 0);
@@ -470,10 +476,14 @@ static rs_status check_call(rs_plan P, const rs_problem *probs, void *work, size
     return RS_OK;
 }
 
-rs_status rs_batch_solve(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
-                         int32_t *info_dev) {
+// The three launches (leaf up, tree, leaf down) of one pass over every shape
+// group.  mode 0 = fused solve, 1 = rs_factor, 2 = rs_solve.  rs_solve keeps
+// the status words that rs_factor wrote and resets only the work queues.
+static rs_status run_pass(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
+                          int32_t *info_dev, int mode) {
     rs_status s = check_call(P, probs, work, work_bytes);
     if (s != RS_OK) return s;
+    if (mode != 0 && !P->factored) return RS_ERR_ARG;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     char *W = static_cast<char *>(work);
     s = bind_and_upload(P, probs, W, st);
@@ -481,8 +491,12 @@ rs_status rs_batch_solve(rs_plan P, const rs_problem *probs, void *work, size_t 
     ++P->epoch;
     int32_t *info = info_dev ? info_dev : reinterpret_cast<int32_t *>(W + P->off_info);
     int32_t *queues = reinterpret_cast<int32_t *>(W + P->off_queues);
-    hipError_t e = timed(P, KK_INIT, st, [&] { return launch_init(info, P->count, queues, (int)P->groups.size(), st); });
+    const int ninfo = mode == 2 ? 0 : P->count;
+    hipError_t e = timed(P, KK_INIT, st, [&] { return launch_init(info, ninfo, queues, (int)P->groups.size(), st); });
     if (e != hipSuccess) return RS_ERR_HIP;
+    static const int kinds[3][3] = {{KK_LEAF_UP, KK_TREE, KK_LEAF_DOWN},
+                                    {KK_F_LEAF_UP, KK_F_TREE, KK_F_LEAF_DOWN},
+                                    {KK_S_LEAF_UP, KK_S_TREE, KK_S_LEAF_DOWN}};
     for (size_t gi = 0; gi < P->groups.size(); ++gi) {
         Group &g = P->groups[gi];
         GroupArgs a{};
@@ -497,22 +511,31 @@ rs_status rs_batch_solve(rs_plan P, const rs_problem *probs, void *work, size_t 
         a.queue = queues + gi;
         a.info = info;
         a.epoch = P->epoch;
-        const int tree_grid = std::max(1, std::min<int>((int)g.items.size(), 256));
-        const Launcher *L = g.shape->fp64;
+        a.sps = g.shape->scratch_per_stage;
+        a.fstore = P->factored ? reinterpret_cast<double *>(W + g.off_fstore) : nullptr;
+        const Launcher *L = mode == 0 ? g.shape->fp64 : mode == 1 ? g.shape->factor : g.shape->vsolve;
+        // the vector passes run one wavefront per work item
+        const int cap = mode == 2 ? 1024 : 256;
+        const int tree_grid = std::max(1, std::min<int>((int)g.items.size(), cap));
         if (a.nleaves > 0) {
-            e = timed(P, KK_LEAF_UP, st, [&] { return L[0](a, a.nleaves, st); });
+            e = timed(P, kinds[mode][0], st, [&] { return L[0](a, a.nleaves, st); });
             if (e != hipSuccess) return RS_ERR_HIP;
         }
         if (a.nitems > 0) {
-            e = timed(P, KK_TREE, st, [&] { return L[1](a, tree_grid, st); });
+            e = timed(P, kinds[mode][1], st, [&] { return L[1](a, tree_grid, st); });
             if (e != hipSuccess) return RS_ERR_HIP;
         }
         if (a.nleaves > 0) {
-            e = timed(P, KK_LEAF_DOWN, st, [&] { return L[2](a, a.nleaves, st); });
+            e = timed(P, kinds[mode][2], st, [&] { return L[2](a, a.nleaves, st); });
             if (e != hipSuccess) return RS_ERR_HIP;
         }
     }
     return RS_OK;
+}
+
+rs_status rs_batch_solve(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
+                         int32_t *info_dev) {
+    return run_pass(P, probs, work, work_bytes, stream, info_dev, 0);
 }
 
 rs_status rs_plan_set_timing(rs_plan P, int32_t enable) {
@@ -546,14 +569,12 @@ rs_status rs_plan_kernel_times(rs_plan P, double *ms, int64_t *launches, int32_t
 
 rs_status rs_factor(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
                     int32_t *info_dev) {
-    (void)P; (void)probs; (void)work; (void)work_bytes; (void)stream; (void)info_dev;
-    return RS_ERR_UNSUPPORTED;
+    return run_pass(P, probs, work, work_bytes, stream, info_dev, 1);
 }
 
 rs_status rs_solve(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
                    int32_t *info_dev) {
-    (void)P; (void)probs; (void)work; (void)work_bytes; (void)stream; (void)info_dev;
-    return RS_ERR_UNSUPPORTED;
+    return run_pass(P, probs, work, work_bytes, stream, info_dev, 2);
 }
 
 }  // extern "C"

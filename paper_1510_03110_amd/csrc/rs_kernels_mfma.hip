@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(NT, 3) km_leaf_down(GroupArgs g) {
     if (tid == 0) S.cbar = known_end ? (p.cN ? p.cN[0] : 0.0) : msg[SL.cb()];
     __syncthreads();
     auto get = [&](int s) { return prob_stage(p, it.t0 + s); };
-    struct Out {
+    struct Out : NoEmit {
         double *scr;
         __device__ double *at(int s) const { return scr + (int64_t)s * LF::per; }
         __device__ void K(int s, int i, int j, double v) const { at(s)[LF::K_ + i * NX + j] = v; }
@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(NT, 3) km_leaf_down(GroupArgs g) {
         __device__ void Psi(int s, int i, double v) const { at(s)[LF::Psi_ + i] = v; }
         __device__ void k(int s, int i, double v) const { at(s)[LF::k_ + i] = v; }
     };
-    mfma_pass<NX, NU, false, true>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {}, Out{scr});
+    mfma_pass<NX, NU, false, true>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {}, Out{{}, scr});
     if ((it.flags & LEAF_TOP) && p.obj) {
         if (threadIdx.x < 64) {
             double part = 0;
@@ -355,13 +355,11 @@ struct SlotFac {
 
 // Master feedback K, k of each stage goes to the stage's slot.
 template <int NX>
-struct SlotOut {
+struct SlotOut : NoEmit {
     double *slots;
     int first;
     __device__ double *at(int s) const { return slots + (int64_t)(first + s) * SlotLayout{NX}.size(); }
     __device__ void K(int s, int i, int j, double v) const { at(s)[SlotLayout{NX}.K() + i * NX + j] = v; }
-    __device__ void P(int, int, int, double) const {}
-    __device__ void Psi(int, int, double) const {}
     __device__ void k(int s, int i, double v) const { at(s)[SlotLayout{NX}.k() + i] = v; }
 };
 
@@ -390,7 +388,7 @@ __device__ void tree_solve_m(MSmem<NX, NX, false, true> &S, const TreeItem &it, 
             if (tid < NX) d[SL.Psi() + tid] = Sm.Psi[tid];
             if (tid == 0) d[SL.cb()] = Sm.cbar;
         },
-        SlotOut<NX>{slots, it.first});
+        SlotOut<NX>{{}, slots, it.first});
     if (top && p.obj && tid < 64) {
         double part = 0;
         if (tid < NX) {
@@ -475,6 +473,195 @@ __global__ void __launch_bounds__(NT) km_tree(GroupArgs g) {
     }
 }
 
+// ================================================ stored factorization
+// rs_factor: the matrix lines of every pass (no right-hand side), writing the
+// per-stage factors that rs_solve's vector passes read back.
+
+// Leaf record writer: up records at +0, down records at +up() of each stage.
+template <int NX, int NU, bool UP>
+struct LeafFacOut : NoEmit {
+    static constexpr bool VEC = false, KF = true, PF = true, LF = true, VF = UP;
+    double *base;                                    // stage 0 of this leaf
+    __device__ double *at(int s) const {
+        const LeafRec R{NX, NU};
+        return base + (int64_t)s * R.per_stage() + (UP ? 0 : R.up());
+    }
+    __device__ void K(int s, int i, int j, double v) const { at(s)[LeafRec{NX, NU}.K() + i * NX + j] = v; }
+    __device__ void P(int s, int i, int j, double v) const { at(s)[LeafRec{NX, NU}.P() + i * NX + j] = v; }
+    __device__ void V(int s, int i, int j, double v) const { at(s)[LeafRec{NX, NU}.V() + i * NX + j] = v; }
+    __device__ void L(int s, const double *Li) const {
+        double *d = at(s);
+        const LeafRec R{NX, NU};
+        for (int e = threadIdx.x; e < NU * NU; e += NT) {
+            const double v = Li[e];
+            d[R.L() + e] = v;
+            d[R.LT() + (e % NU) * NU + e / NU] = v;
+        }
+    }
+};
+
+// Master-slot writer: up factors (Alg. 4 / elimination) or down factors.
+template <int NX, bool UP>
+struct SlotFacOut : NoEmit {
+    static constexpr bool VEC = false, KF = true, PF = UP, LF = true, VF = UP;
+    double *slots;
+    int first;
+    __device__ double *at(int s) const { return slots + (int64_t)(first + s) * SlotLayout{NX}.size(); }
+    __device__ void K(int s, int i, int j, double v) const {
+        const SlotLayout L{NX};
+        at(s)[(UP ? L.uK() : L.K()) + i * NX + j] = v;
+    }
+    __device__ void P(int s, int i, int j, double v) const {
+        if (UP) at(s)[SlotLayout{NX}.uP() + i * NX + j] = v;
+    }
+    __device__ void V(int s, int i, int j, double v) const {
+        if (UP) at(s)[SlotLayout{NX}.uV() + i * NX + j] = v;
+    }
+    __device__ void L(int s, const double *Li) const {
+        double *d = at(s);
+        const SlotLayout SL{NX};
+        const int oL = UP ? SL.uL() : SL.dL(), oT = UP ? SL.uLT() : SL.dLT();
+        for (int e = threadIdx.x; e < NX * NX; e += NT) {
+            const double v = Li[e];
+            d[oL + e] = v;
+            d[oT + (e % NX) * NX + e / NX] = v;
+        }
+    }
+};
+
+template <int NX, int NU>
+__global__ void __launch_bounds__(NT, 2) kf_leaf_up(GroupArgs g) {
+    __shared__ __attribute__((aligned(16))) char raw[Sizes<NX, NU>::up];
+    const LeafItem it = load_leaf_u(g.leaves, blockIdx.x);
+    if (it.flags & LEAF_TOP) return;
+    const DevProb p = load_prob(g.probs, it.inst);
+    const SlotLayout SL{NX};
+    double *out = g.slots + (int64_t)it.slot * SL.size();
+    double *base = g.fstore + (it.scratch / g.sps) * (int64_t)LeafRec{NX, NU}.per_stage();
+    auto get = [&](int s) { return prob_stage(p, it.t0 + s); };
+    const int tid = threadIdx.x;
+    if (!(it.flags & LEAF_LAST)) {
+        auto &S = *reinterpret_cast<MSmem<NX, NU, true, false> *>(raw);
+        for (int e = tid; e < NX * NX; e += NT) {
+            S.P[e] = 0.0;
+            S.V[e] = (e / NX == e % NX) ? 1.0 : 0.0;
+            S.Qh[e] = 0.0;
+        }
+        __syncthreads();
+        mfma_pass<NX, NU, true, false>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {},
+                                       LeafFacOut<NX, NU, true>{{}, base});
+        for (int e = tid; e < NX * NX; e += NT) {
+            const int i = e / NX, j = e % NX;
+            out[SL.A() + e] = S.V[j * NX + i];
+            out[SL.Qw() + e] = S.Qh[e];
+            out[SL.Qx() + e] = S.P[e];
+        }
+    } else {
+        auto &S = *reinterpret_cast<MSmem<NX, NU, false, false> *>(raw);
+        for (int e = tid; e < NX * NX; e += NT) S.P[e] = p.QxN[e];
+        __syncthreads();
+        mfma_pass<NX, NU, false, false>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {},
+                                        LeafFacOut<NX, NU, true>{{}, base});
+        for (int e = tid; e < NX * NX; e += NT) out[SL.Qx() + e] = S.P[e];
+    }
+}
+
+template <int NX, int NU>
+__global__ void __launch_bounds__(NT, 3) kf_leaf_down(GroupArgs g) {
+    __shared__ __attribute__((aligned(16))) char raw[sizeof(MSmem<NX, NU, false, true>)];
+    auto &S = *reinterpret_cast<MSmem<NX, NU, false, true> *>(raw);
+    const LeafItem it = load_leaf_u(g.leaves, blockIdx.x);
+    const DevProb p = load_prob(g.probs, it.inst);
+    const SlotLayout SL{NX};
+    const bool known_end = (it.flags & (LEAF_LAST | LEAF_TOP)) != 0;
+    const double *msg = (it.flags & LEAF_TOP) ? nullptr : g.slots + (int64_t)it.slot * SL.size();
+    double *base = g.fstore + (it.scratch / g.sps) * (int64_t)LeafRec{NX, NU}.per_stage();
+    for (int e = threadIdx.x; e < NX * NX; e += NT) S.P[e] = known_end ? p.QxN[e] : msg[SL.P() + e];
+    __syncthreads();
+    auto get = [&](int s) { return prob_stage(p, it.t0 + s); };
+    mfma_pass<NX, NU, false, true>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {},
+                                   LeafFacOut<NX, NU, false>{{}, base});
+}
+
+template <int NX>
+__global__ void __launch_bounds__(NT) kf_tree(GroupArgs g) {
+    __shared__ __attribute__((aligned(16))) char raw[Sizes<NX, NX>::all];
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    const SlotLayout SL{NX};
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(g.queue, 1);
+        __syncthreads();
+        const int idx = uni(s_item);
+        __syncthreads();
+        if (idx >= g.nitems) break;
+        const TreeItem it = load_item_u(g.items, idx);
+        if (tid == 0) {
+            for (int d = 0; d < it.dep_count; ++d) {
+                int spins = 0;
+                while (__hip_atomic_load(&g.flags[it.dep_first + d], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) !=
+                       g.epoch) {
+                    __builtin_amdgcn_s_sleep(4);
+                    if (++spins > SPIN_LIMIT) {
+                        record_failure(g.info, it.inst, 6, -2);
+                        break;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        double *slots = g.slots;
+        auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
+        auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };
+        if (it.kind == ITEM_UP) {
+            auto &S = *reinterpret_cast<MSmem<NX, NX, true, false> *>(raw);
+            for (int e = tid; e < NX * NX; e += NT) {
+                S.P[e] = 0.0;
+                S.V[e] = (e / NX == e % NX) ? 1.0 : 0.0;
+                S.Qh[e] = 0.0;
+            }
+            __syncthreads();
+            mfma_pass<NX, NX, true, false>(S, get, it.count, g.info, it.inst, -1, 3, [](int, auto &) {},
+                                           SlotFacOut<NX, true>{{}, slots, it.first});
+            double *out = slot(it.out_slot);
+            for (int e = tid; e < NX * NX; e += NT) {
+                const int i = e / NX, j = e % NX;
+                out[SL.A() + e] = S.V[j * NX + i];
+                out[SL.Qw() + e] = S.Qh[e];
+                out[SL.Qx() + e] = S.P[e];
+            }
+        } else if (it.kind == ITEM_UP_LAST) {
+            auto &S = *reinterpret_cast<MSmem<NX, NX, false, false> *>(raw);
+            const double *term = slot(it.term_slot);
+            for (int e = tid; e < NX * NX; e += NT) S.P[e] = term[SL.Qx() + e];
+            __syncthreads();
+            mfma_pass<NX, NX, false, false>(S, get, it.count, g.info, it.inst, -1, 3, [](int, auto &) {},
+                                            SlotFacOut<NX, true>{{}, slots, it.first});
+            double *out = slot(it.out_slot);
+            for (int e = tid; e < NX * NX; e += NT) out[SL.Qx() + e] = S.P[e];
+        } else {
+            auto &S = *reinterpret_cast<MSmem<NX, NX, false, true> *>(raw);
+            const bool top = it.kind == ITEM_TOP;
+            const double *msg = top ? nullptr : slot(it.out_slot);
+            const double *term = it.last ? slot(it.term_slot) : nullptr;
+            for (int e = tid; e < NX * NX; e += NT) S.P[e] = term ? term[SL.Qx() + e] : msg[SL.P() + e];
+            __syncthreads();
+            mfma_pass<NX, NX, false, true>(
+                S, get, it.count, g.info, it.inst, -1, 3,
+                [&](int s, auto &Sm) {      // M2 for child s: P at the end of stage s
+                    block_copy<NX * NX>(slot(it.first + s) + SL.P(), Sm.P);
+                },
+                SlotFacOut<NX, false>{{}, slots, it.first});
+            if (top) block_copy<NX * NX>(slot(it.term_slot) + SL.P(), S.P);   // P_0, for the optimal value
+        }
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(&g.flags[idx], g.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+    }
+}
+
 template <int NX, int NU>
 hipError_t launch_leaf_up_m(const GroupArgs &g, int, hipStream_t st) {
     hipLaunchKernelGGL((km_leaf_up<NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
@@ -491,7 +678,37 @@ hipError_t launch_leaf_down_m(const GroupArgs &g, int, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int NX, int NU>
+hipError_t launch_factor_leaf_up(const GroupArgs &g, int, hipStream_t st) {
+    hipLaunchKernelGGL((kf_leaf_up<NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+template <int NX>
+hipError_t launch_factor_tree(const GroupArgs &g, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((kf_tree<NX>), dim3(grid), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+template <int NX, int NU>
+hipError_t launch_factor_leaf_down(const GroupArgs &g, int, hipStream_t st) {
+    hipLaunchKernelGGL((kf_leaf_down<NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+
 }  // namespace mf
+
+Launcher mfma_factor(int nx, int nu, int which) {
+#define RS_FAC(a, b)                                                                   \
+    if (nx == a && nu == b) {                                                          \
+        if (which == 0) return &mf::launch_factor_leaf_up<a, b>;                       \
+        if (which == 1) return &mf::launch_factor_tree<a>;                             \
+        return &mf::launch_factor_leaf_down<a, b>;                                     \
+    }
+    RS_FAC(16, 16)
+    RS_FAC(32, 16)
+    RS_FAC(32, 32)
+#undef RS_FAC
+    return nullptr;
+}
 
 // MFMA launchers for the shapes that have them (nullptr: use the generic kernel).
 Launcher mfma_leaf_up(int nx, int nu) {

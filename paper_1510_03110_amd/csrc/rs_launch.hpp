@@ -13,13 +13,24 @@ constexpr int scratch_per_stage(int nx, int nu) { return nu * nx + nu + nx * nx 
 typedef hipError_t (*Launcher)(const GroupArgs &, int grid, hipStream_t);
 
 // Kernel kinds, also the index of the per-kind timers of a plan.
-enum KernelKind { KK_INIT = 0, KK_LEAF_UP = 1, KK_TREE = 2, KK_LEAF_DOWN = 3, KK_COUNT = 8 };
+enum KernelKind {
+    KK_INIT = 0,
+    KK_LEAF_UP = 1, KK_TREE = 2, KK_LEAF_DOWN = 3,          // fused solve
+    KK_F_LEAF_UP = 4, KK_F_TREE = 5, KK_F_LEAF_DOWN = 6,    // rs_factor
+    KK_S_LEAF_UP = 7, KK_S_TREE = 8, KK_S_LEAF_DOWN = 9,    // rs_solve
+    KK_COUNT = 16
+};
 
 struct ShapeEntry {
     int nx, nu;
-    Launcher fp64[3];        // leaf up, tree, leaf down
+    Launcher fp64[3];        // fused: leaf up, tree, leaf down
+    Launcher factor[3];      // stored factorization (nullptr: not available for the shape)
+    Launcher vsolve[3];      // right-hand-side passes on the stored factorization
     int scratch_per_stage;
 };
+
+Launcher mfma_factor(int nx, int nu, int which);
+Launcher vector_solve(int nx, int nu, int which);
 
 const ShapeEntry *find_shape(int nx, int nu);
 hipError_t launch_init(int32_t *info, int count, int32_t *queues, int nq, hipStream_t st);

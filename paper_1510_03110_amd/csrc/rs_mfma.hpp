@@ -128,11 +128,18 @@ struct MSmem {
     static_assert(NX * NW >= NX * NX + NU * NX, "Y fits behind A'V in W");
 };
 
-// Results of a solve-mode stage, emitted from the registers that computed
-// them (phase E).  The default does nothing (reduction / elimination).
+// Per-stage results handed out of the pass from the lanes that computed them
+// (phase E), and compile-time switches of the pass:
+//   VEC  form the vector (right-hand side) quantities of Alg. 2 / Alg. 4
+//   KF   form K_{t+1} = -G^{-1} H' also in the reduction (for a later solve)
+//   PF, LF, VF  emit P_t, L^{-1} and V_t (stored factorization)
+// The default does nothing and keeps the vector work (fused solve).
 struct NoEmit {
+    static constexpr bool VEC = true, KF = false, PF = false, LF = false, VF = false;
     __device__ void K(int, int, int, double) const {}
     __device__ void P(int, int, int, double) const {}
+    __device__ void L(int, const double *) const {}
+    __device__ void V(int, int, int, double) const {}
     __device__ void Psi(int, int, double) const {}
     __device__ void k(int, int, double) const {}
 };
@@ -299,6 +306,7 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
     static_assert(NX % 16 == 0 && NU % 16 == 0, "MFMA path needs multiples of 16");
     static_assert(NX <= 64 && NU <= 64, "per-wave vector roles assume NX, NU <= 64");
     constexpr int NW = NX + NU, TX = NX / 16, TU = NU / 16;
+    constexpr bool VEC = Out::VEC, KFORM = SOLVE || Out::KF, PEMIT = SOLVE || Out::PF;
     const int tid = threadIdx.x, w = wave(), l = lane();
     count = uni(count);
     Prefetch<NX, NU> pf;
@@ -333,7 +341,7 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                     tile_for(ti, tj, [&](int r, int i, int j) { S.BV[i * NX + j] = acc[r]; });
                 }
             }
-            if (w == 3) {
+            if (VEC && w == 3) {
                 double part = 0;
                 if (l < NX) {
                     double pa = 0;
@@ -345,7 +353,7 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                 // cbar += 1/2 a'Pa - Psi'a + c (Alg. 2, with P_{t+1}, Psi_{t+1})
                 part = wave_sum(part);
                 if (l == 0) S.cbar += part + S.c;
-            } else if (RED && tid >= 128 && tid < 128 + NX) {
+            } else if (VEC && RED && tid >= 128 && tid < 128 + NX) {
                 const int i = tid - 128;
                 double acc = 0;
 #pragma unroll 8
@@ -376,13 +384,13 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                     }
                 }
             }
-            if (tid >= 192 && tid < 192 + NX) {
+            if (VEC && tid >= 192 && tid < 192 + NX) {
                 const int i = tid - 192;
                 double acc = -S.lx[i];
 #pragma unroll 8
                 for (int k = 0; k < NX; ++k) acc += S.A[k * NX + i] * S.pt[k];
                 S.gx[i] = acc;
-            } else if (tid >= 128 && tid < 128 + NU) {
+            } else if (VEC && tid >= 128 && tid < 128 + NU) {
                 const int i = tid - 128;
                 double acc = -S.lw[i];
 #pragma unroll 8
@@ -420,7 +428,7 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                     tile_for(ti, tj, [&](int r, int i, int j) { S.X[i * NX + j] = acc[r]; });
                 }
             }
-            if (tid >= 192 && tid < 192 + NU) {
+            if (VEC && tid >= 192 && tid < 192 + NU) {
                 const int i = tid - 192;
                 double acc = 0;
 #pragma unroll
@@ -434,7 +442,7 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
         //      Psi = g_x - Y'z, (RED) v += V'a + X'z, cbar -= z'z/2
         {
             constexpr int TL = TX * (TX + 1) / 2, TQ = RED ? TL : 0, TV = RED ? TX * TX : 0,
-                          TK = SOLVE ? TU * TX : 0;
+                          TK = KFORM ? TU * TX : 0;
             for (int t = w; t < TL + TQ + TV + TK; t += 4) {
                 if (t < TL) {
                     int ti, tj;
@@ -445,7 +453,7 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                             const double v = S.F()[i * NX + j] - acc[r];
                             S.P[i * NX + j] = v;
                             S.P[j * NX + i] = v;
-                            if constexpr (SOLVE) {
+                            if constexpr (PEMIT) {
                                 out.P(s, i, j, v);
                                 if (i != j) out.P(s, j, i, v);
                             }
@@ -464,37 +472,42 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                     if constexpr (RED) {
                         const int u = t - TL - TQ, ti = u / TX, tj = u % TX;
                         d4 acc = mma<NU, true, false>(zero4(), S.Y(), NX, S.X, NX, ti, tj);
-                        tile_for(ti, tj, [&](int r, int i, int j) { S.V[i * NX + j] = S.W[i * NX + j] - acc[r]; });
+                        tile_for(ti, tj, [&](int r, int i, int j) {
+                            const double v = S.W[i * NX + j] - acc[r];
+                            S.V[i * NX + j] = v;
+                            if constexpr (Out::VF) out.V(s, i, j, v);
+                        });
                     }
                 } else {
-                    if constexpr (SOLVE) {
+                    if constexpr (KFORM) {
                         const int u = t - TL - TQ - TV, ti = u / TX, tj = u % TX;
                         d4 acc = mma<NU, true, false>(zero4(), S.G, NU, S.Y(), NX, ti, tj);
                         tile_for(ti, tj, [&](int r, int i, int j) { out.K(s, i, j, -acc[r]); });
                     }
                 }
             }
-            if (tid >= 192 && tid < 192 + NX) {
+            if constexpr (Out::LF) out.L(s, S.G);
+            if (VEC && tid >= 192 && tid < 192 + NX) {
                 const int i = tid - 192;
                 double acc = S.gx[i];
 #pragma unroll
                 for (int r = 0; r < NU; ++r) acc -= S.Y()[r * NX + i] * S.z[r];
                 S.Psi[i] = acc;
                 if constexpr (SOLVE) out.Psi(s, i, acc);
-            } else if (RED && tid >= 128 && tid < 128 + NX) {
+            } else if (VEC && RED && tid >= 128 && tid < 128 + NX) {
                 const int i = tid - 128;
                 double acc = S.Vta[i];
 #pragma unroll
                 for (int r = 0; r < NU; ++r) acc += S.X[r * NX + i] * S.z[r];
                 S.v[i] += acc;
-            } else if (SOLVE && tid >= 128 && tid < 128 + NU) {
+            } else if (VEC && SOLVE && tid >= 128 && tid < 128 + NU) {
                 const int i = tid - 128;
                 double acc = 0;
 #pragma unroll
                 for (int r = 0; r < NU; ++r) acc += S.G[r * NU + i] * S.z[r];
                 S.kk[i] = acc;
                 out.k(s, i, acc);
-            } else if (tid >= 64 && tid < 128) {
+            } else if (VEC && tid >= 64 && tid < 128) {
                 const double zz = wave_sum(l < NU ? S.z[l] * S.z[l] : 0.0);
                 if (l == 0) S.cbar -= 0.5 * zz;
             }

@@ -45,6 +45,9 @@ enum { ITEM_UP = 0, ITEM_UP_LAST = 1, ITEM_TOP = 2, ITEM_DOWN = 3 };
 //   M1 (sent to the parent, Alg. 5):   Ahat n*n | Qwhat n*n | Qxhat n*n | ahat n | lxhat n | chat 1
 //   M2 (sent to a child, Alg. 6):      xhat n | P n*n | Psi n | cbar 1
 //   factors of the down pass:          K n*n | k n
+//   stored factorization (factor / solve split), master stage of this slot:
+//     up pass (Alg. 4):   P_after n*n | L^{-1} n*n | L^{-T} n*n | K n*n | V_after n*n
+//     down pass (Alg. 1): L^{-1} n*n | L^{-T} n*n   (its K is the K above)
 struct SlotLayout {
     int n;
     __host__ __device__ int A() const { return 0; }
@@ -59,7 +62,33 @@ struct SlotLayout {
     __host__ __device__ int cb() const { return 4 * n * n + 4 * n + 1; }
     __host__ __device__ int K() const { return 4 * n * n + 4 * n + 2; }
     __host__ __device__ int k() const { return 5 * n * n + 4 * n + 2; }
-    __host__ __device__ int size() const { return ((5 * n * n + 5 * n + 2) + 7) & ~7; }
+    __host__ __device__ int uP() const { return 5 * n * n + 5 * n + 2; }
+    __host__ __device__ int uL() const { return 6 * n * n + 5 * n + 2; }
+    __host__ __device__ int uLT() const { return 7 * n * n + 5 * n + 2; }
+    __host__ __device__ int uK() const { return 8 * n * n + 5 * n + 2; }
+    __host__ __device__ int uV() const { return 9 * n * n + 5 * n + 2; }
+    __host__ __device__ int dL() const { return 10 * n * n + 5 * n + 2; }
+    __host__ __device__ int dLT() const { return 11 * n * n + 5 * n + 2; }
+    __host__ __device__ int size() const { return ((12 * n * n + 5 * n + 2) + 7) & ~7; }
+};
+
+// Stored factorization of one leaf stage (factor / solve split), doubles:
+//   up record (Alg. 4 or last-leaf elimination): P_after | L^{-1} | L^{-T} | K | V_after
+//   down record (Alg. 1 with the true terminal):  P_after | L^{-1} | L^{-T} | K
+//   down-pass vectors written by the solve:       Psi_after | k
+// P_after / V_after are the values after the stage (P_t, V_t), L^{-1} is the
+// inverse Cholesky factor of G_{t+1} and K = K_{t+1}.
+struct LeafRec {
+    int nx, nu;
+    __host__ __device__ int P() const { return 0; }
+    __host__ __device__ int L() const { return nx * nx; }
+    __host__ __device__ int LT() const { return nx * nx + nu * nu; }
+    __host__ __device__ int K() const { return nx * nx + 2 * nu * nu; }
+    __host__ __device__ int V() const { return nx * nx + 2 * nu * nu + nu * nx; }
+    __host__ __device__ int up() const { return 2 * nx * nx + 2 * nu * nu + nu * nx; }
+    __host__ __device__ int down() const { return nx * nx + 2 * nu * nu + nu * nx; }
+    __host__ __device__ int vec() const { return nx + nu; }
+    __host__ __device__ int per_stage() const { return up() + down() + vec(); }
 };
 
 // Everything a kernel launch of one shape group needs.
@@ -75,7 +104,8 @@ struct GroupArgs {
     int32_t *queue;         // tree work-queue counter
     int32_t *info;          // per instance: status, stage
     int32_t epoch;
-    int32_t pad;
+    int32_t sps;            // fused-solve scratch elements per stage (leaf stage index = scratch / sps)
+    double *fstore;         // stored factorization of the leaves (LeafRec per stage)
 };
 
 }  // namespace rs

@@ -18,6 +18,8 @@ from . import build as _build
 RS_OK, RS_ERR_ARG, RS_ERR_NOT_SPD, RS_ERR_SINGULAR_MASTER, RS_ERR_NOT_CONVERGED, \
     RS_ERR_NOMEM, RS_ERR_HIP, RS_ERR_UNSUPPORTED = range(8)
 RS_FP64, RS_MIXED_FP32 = 0, 1
+RS_PLAN_FACTORED = 1
+RS_KERNEL_KINDS = 16
 
 _P = ctypes.c_void_p
 
@@ -34,7 +36,8 @@ class rs_problem(ctypes.Structure):
 
 class rs_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("Ns", ctypes.c_int32), ("branch", ctypes.c_int32),
-                ("max_refine", ctypes.c_int32), ("tol", ctypes.c_double)]
+                ("max_refine", ctypes.c_int32), ("tol", ctypes.c_double), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class RsError(RuntimeError):
@@ -86,10 +89,10 @@ def _check(status, where):
         raise RsError(status, where)
 
 
-def rs_plan_create(dims, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.0):
+def rs_plan_create(dims, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.0, flags=0):
     """dims: sequence of (nx, nu, N).  Returns an opaque plan handle."""
     arr = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 3))
-    opt = rs_options(precision, Ns, branch, max_refine, tol)
+    opt = rs_options(precision, Ns, branch, max_refine, tol, flags, 0)
     h = _P()
     st = library().rs_plan_create(arr.shape[0], arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                   ctypes.byref(opt), ctypes.byref(h))
@@ -120,7 +123,8 @@ def rs_plan_export(plan, what):
     return out[:rows]
 
 
-KERNEL_KINDS = ("init", "leaf_up", "tree", "leaf_down")
+KERNEL_KINDS = ("init", "leaf_up", "tree", "leaf_down", "factor_leaf_up", "factor_tree", "factor_leaf_down",
+                "solve_leaf_up", "solve_tree", "solve_leaf_down")
 
 
 def rs_plan_set_timing(plan, enable):
@@ -129,8 +133,8 @@ def rs_plan_set_timing(plan, enable):
 
 def rs_plan_kernel_times(plan, reset=True):
     """{kind: (total_ms, launches)} since the last reset (synchronizes)."""
-    ms = (ctypes.c_double * 8)()
-    n = (ctypes.c_int64 * 8)()
+    ms = (ctypes.c_double * RS_KERNEL_KINDS)()
+    n = (ctypes.c_int64 * RS_KERNEL_KINDS)()
     _check(library().rs_plan_kernel_times(plan, ms, n, int(bool(reset))), "rs_plan_kernel_times")
     return {KERNEL_KINDS[k]: (ms[k], n[k]) for k in range(len(KERNEL_KINDS))}
 
@@ -165,11 +169,12 @@ class Batch:
     (uniform shapes) or to lists of per-instance tensors (shapes may differ).
     Outputs ``x``, ``w``, ``lam``, ``obj`` are allocated here.  Time-invariant
     matrices may be given with a stage axis of length 1; they are passed with
-    stride 0.
+    stride 0.  ``factored=True`` reserves the stored factorization so that
+    ``factor()`` / ``solve_factored()`` can be used.
     """
 
     def __init__(self, data, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.0,
-                 device="cuda"):
+                 device="cuda", factored=False):
         import torch
         self.torch = torch
         keys = set(data)
@@ -194,7 +199,8 @@ class Batch:
         self.lam = [torch.zeros((N + 1, nx), **f64) for nx, nu, N in dims]
         self.obj = torch.zeros(self.count, **f64)
         self.info = torch.zeros(2 * self.count, dtype=torch.int32, device=device)
-        self.plan = rs_plan_create(dims, precision, Ns, branch, max_refine, tol)
+        self.plan = rs_plan_create(dims, precision, Ns, branch, max_refine, tol,
+                                   RS_PLAN_FACTORED if factored else 0)
         self.work_bytes = rs_plan_workspace_size(self.plan)
         self.work = torch.empty(self.work_bytes + 256, dtype=torch.uint8, device=device)
         base = self.work.data_ptr()
@@ -246,6 +252,12 @@ class Batch:
     def solve_factored(self):
         rs_solve(self.plan, self.probs, self.work_ptr, self.work_bytes, self.stream_ptr(),
                  self.info.data_ptr())
+
+    def update(self, key, i, values):
+        """Overwrite problem field ``key`` of instance ``i`` in place (same
+        device buffer, so the descriptors stay valid)."""
+        t = self.data[key][i]
+        t.copy_(self._dev(values, t.device).reshape(t.shape))
 
     def status(self):
         return self.info.view(-1, 2).cpu().numpy()

@@ -1,0 +1,34 @@
+"""The C-ABI library loads on the host and exports every function that
+include/rs.h declares (no compute call: no GPU needed)."""
+import ctypes
+import os
+import re
+
+from paper_1510_03110_amd import rs
+
+HEADER = os.path.join(os.path.dirname(__file__), "..", "include", "rs.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(rs_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("rs_plan_create", "rs_plan_workspace_size", "rs_plan_destroy", "rs_batch_solve",
+              "rs_factor", "rs_solve", "rs_plan_query", "rs_plan_export", "rs_status_string"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rs.library()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_options_struct_matches_header_size():
+    # int32 precision, Ns, branch, max_refine; double tol; int32 flags, reserved
+    assert ctypes.sizeof(rs.rs_options) == 32

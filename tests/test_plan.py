@@ -164,3 +164,40 @@ def test_plan_rejects_bad_arguments():
         rs.rs_plan_create([(4, 2, 3)], Ns=1)           # Ns*nu < nx on a multi-leaf problem
     p = rs.rs_plan_create([(4, 2, 1)], Ns=1)           # a single leaf needs no reduction
     rs.rs_plan_destroy(p)
+
+
+def test_factored_plan_workspace_and_shape_support():
+    """The stored factorization adds LeafRec doubles per leaf stage; it exists
+    for matrix-core shapes only."""
+    dims = [(32, 16, 1024)]
+    p0 = rs.rs_plan_create(dims, Ns=16, branch=4)
+    p1 = rs.rs_plan_create(dims, Ns=16, branch=4, flags=rs.RS_PLAN_FACTORED)
+    try:
+        extra = rs.rs_plan_workspace_size(p1) - rs.rs_plan_workspace_size(p0)
+        nx, nu = 32, 16
+        per_stage = (2 * nx * nx + 2 * nu * nu + nu * nx) + (nx * nx + 2 * nu * nu + nu * nx) + nx + nu
+        assert 0 <= extra - 8 * 1024 * per_stage < 4096
+    finally:
+        rs.rs_plan_destroy(p0)
+        rs.rs_plan_destroy(p1)
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_plan_create([(4, 2, 64)], flags=rs.RS_PLAN_FACTORED)
+    assert e.value.status == rs.RS_ERR_UNSUPPORTED
+
+
+def test_factor_needs_factored_plan():
+    """rs_factor / rs_solve on a plan without the stored factorization is an
+    argument error, reported before anything is launched."""
+    plan = rs.rs_plan_create([(16, 16, 64)], Ns=8)
+    try:
+        probs = (rs.rs_problem * 1)()
+        p = probs[0]
+        p.nx, p.nu, p.N = 16, 16, 64
+        fake = 1 << 20          # never dereferenced: the call fails its checks first
+        for k in ("Qx", "Qw", "A", "B", "QxN", "x0", "x", "w", "lam"):
+            setattr(p, k, fake)
+        for name in ("rs_factor", "rs_solve"):
+            st = getattr(rs.library(), name)(plan, probs, fake, rs.rs_plan_workspace_size(plan), None, None)
+            assert st == rs.RS_ERR_ARG
+    finally:
+        rs.rs_plan_destroy(plan)
