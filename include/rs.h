@@ -97,7 +97,7 @@ typedef struct rs_options {
     int32_t precision;   /* rs_precision                                              */
     int32_t Ns;          /* leaf (subinterval) length N_s >= 1; 0 = library default    */
     int32_t branch;      /* master stages per master subproblem (>= 2); 0 = default    */
-    int32_t max_refine;  /* mixed precision: maximum refinement steps; 0 = default    */
+    int32_t max_refine;  /* mixed precision: maximum refinement steps; 0 = default 5  */
     double tol;          /* mixed precision: relative KKT residual target; 0 = 1e-10  */
     int32_t flags;       /* RS_PLAN_* bits                                            */
     int32_t reserved;
@@ -168,8 +168,9 @@ rs_status rs_solve(rs_plan plan, const rs_problem *probs, void *work, size_t wor
 
 /* Plan introspection: key 0 = number of leaves, 1 = number of tree work items,
  * 2 = maximum tree depth (levels above the leaves), 3 = leaf length Ns,
- * 4 = branch, 5 = precision, 6 = refinement steps used by the last mixed
- * precision call (host-side count, valid after a synchronizing call). */
+ * 4 = branch, 5 = precision, 6 = refinement iterations launched by the last
+ * mixed-precision call (converged instances skip the remaining ones; the
+ * per-instance count is in rs_refine_stats). */
 int64_t rs_plan_query(rs_plan plan, int32_t key);
 
 /* Export the plan's work tables for host-side inspection (tests, tooling).
@@ -191,10 +192,23 @@ int64_t rs_plan_export(rs_plan plan, int32_t what, int64_t *out, int64_t cap_row
  * last reset; reset != 0 starts a new window.  Kinds: 0 status/queue reset;
  * fused solve 1 leaf reduction, 2 tree levels, 3 leaf solve; rs_factor
  * 4 leaf, 5 tree, 6 leaf down; rs_solve 7 leaf, 8 tree, 9 leaf down;
- * 10..15 reserved.  ms and launches point to RS_KERNEL_KINDS host values. */
+ * refinement 10 FP64 residual, 11 update, 12 convergence check;
+ * 13..15 reserved.  ms and launches point to RS_KERNEL_KINDS host values. */
 #define RS_KERNEL_KINDS 16
 rs_status rs_plan_set_timing(rs_plan plan, int32_t enable);
 rs_status rs_plan_kernel_times(rs_plan plan, double *ms, int64_t *launches, int32_t reset);
+
+/* Refinement statistics of the last mixed-precision solve with this plan and
+ * workspace, 4 doubles per instance, copied to host memory `out` (waits for
+ * `stream`): relative KKT residual ||r - K z||_inf / ||r||_inf of the
+ * returned solution (FP64), size of the last correction relative to the
+ * solution (max over the x, w, lam blocks; an estimate of the forward error
+ * before that correction), corrections applied, converged flag.  The
+ * iteration stops for an instance once its correction is <= tol/10; it is
+ * reported RS_ERR_NOT_CONVERGED if that never happens within max_refine
+ * corrections or the final relative residual exceeds tol.  RS_ERR_ARG for a
+ * plan that is not RS_MIXED_FP32. */
+rs_status rs_refine_stats(rs_plan plan, const void *work, double *out, void *stream);
 
 const char *rs_status_string(rs_status s);
 

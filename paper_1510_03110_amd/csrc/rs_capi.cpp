@@ -30,15 +30,22 @@ struct Group {
     int64_t scratch_elems = 0;
     int max_depth = 0;
     int64_t leaf_stages = 0;
-    size_t off_leaves = 0, off_items = 0, off_flags = 0, off_slots = 0, off_scratch = 0, off_fstore = 0;
+    int32_t leaf_base = 0;                  // global index of the group's first leaf
+    size_t off_leaves = 0, off_items = 0, off_flags = 0, off_slots = 0, off_scratch = 0, off_fstore = 0,
+           off_fvec = 0;
 };
 
 }  // namespace
 
 struct rs_plan_s {
     int32_t count = 0;
-    int Ns = 16, branch = 4, top_max = 4, prec = RS_FP64, max_refine = 0;
+    int Ns = 16, branch = 4, top_max = 4, prec = RS_FP64, max_refine = 5;
     bool factored = false;          // workspace holds the stored factorization
+    bool mixed = false;             // FP32 leaf factorization + FP64 refinement
+    int32_t total_leaves = 0;
+    std::vector<InstInfo> inst;     // per instance: leaf range (refinement reductions)
+    std::vector<size_t> off_cbuf;   // per instance: correction buffers (mixed)
+    size_t off_inst = 0, off_conv = 0, off_stats = 0, off_part = 0;
     double tol = 1e-10;
     std::vector<int32_t> dims;
     std::vector<Group> groups;
@@ -237,15 +244,16 @@ rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *o
             delete P;
             return RS_ERR_ARG;
         }
-        if (opt->precision != RS_FP64) {
+        if (opt->precision != RS_FP64 && opt->precision != RS_MIXED_FP32) {
             delete P;
             return RS_ERR_UNSUPPORTED;
         }
         P->prec = opt->precision;
-        P->factored = (opt->flags & RS_PLAN_FACTORED) != 0;
+        P->mixed = opt->precision == RS_MIXED_FP32;
+        P->factored = P->mixed || (opt->flags & RS_PLAN_FACTORED) != 0;
         if (opt->Ns > 0) P->Ns = opt->Ns;
         if (opt->branch > 0) P->branch = opt->branch;
-        if (opt->max_refine > 0) P->max_refine = opt->max_refine;
+        P->max_refine = opt->max_refine > 0 ? opt->max_refine : 5;
         if (opt->tol > 0) P->tol = opt->tol;
     }
     P->top_max = P->branch;
@@ -266,7 +274,8 @@ rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *o
             return RS_ERR_ARG;
         }
         const ShapeEntry *se = find_shape(nx, nu);
-        if (!se || (P->factored && !(se->factor[0] && se->vsolve[0]))) {
+        const int f32 = P->mixed ? 1 : 0;
+        if (!se || (P->factored && !(se->factor[f32][0] && se->vsolve[f32][0])) || (P->mixed && !se->refine[0])) {
             delete P;
             return RS_ERR_UNSUPPORTED;
         }
@@ -282,16 +291,27 @@ rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *o
         inst_group[i] = gidx[key];
         P->groups[inst_group[i]].insts.push_back(i);
     }
+    P->inst.assign(count, InstInfo{});
     for (auto &g : P->groups) {
         std::vector<Tmp> tmp;
-        for (int inst : g.insts)
+        g.leaf_base = P->total_leaves;
+        for (int inst : g.insts) {
+            const int before = (int)g.leaves.size();
             build_instance(g, inst, dims[3 * inst + 2], P->Ns, P->branch, P->top_max, tmp);
+            InstInfo &in = P->inst[inst];
+            in.first_leaf = g.leaf_base + before;
+            in.nleaves = (int)g.leaves.size() - before;
+            in.nx = g.nx;
+            in.nu = g.nu;
+            in.N = dims[3 * inst + 2];
+        }
+        P->total_leaves += (int32_t)g.leaves.size();
         finalize_items(g, tmp);
     }
     // workspace layout
     size_t off = 0;
-    P->off_probs = off;
-    off = align_up(off + sizeof(DevProb) * count);
+    P->off_probs = off;                 // user problems, then (mixed) the correction problems
+    off = align_up(off + sizeof(DevProb) * count * (P->mixed ? 2 : 1));
     P->off_info = off;
     off = align_up(off + sizeof(int32_t) * 2 * count);
     P->off_queues = off;
@@ -303,6 +323,8 @@ rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *o
         g.off_items = off;
         off = align_up(off + sizeof(TreeItem) * g.items.size());
     }
+    P->off_inst = off;
+    off = align_up(off + sizeof(InstInfo) * count);
     P->tables_bytes = off - P->off_tables;
     for (auto &g : P->groups) {
         g.off_flags = off;
@@ -316,10 +338,31 @@ rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *o
         off = align_up(off + esz * (size_t)g.scratch_elems);
         g.leaf_stages = g.scratch_elems / g.shape->scratch_per_stage;
         g.off_fstore = off;
-        if (P->factored) off = align_up(off + sizeof(double) * (size_t)g.leaf_stages * LeafRec{g.nx, g.nu}.per_stage());
+        if (P->factored) {
+            const size_t rec = P->mixed ? sizeof(float) : sizeof(double);
+            off = align_up(off + rec * (size_t)g.leaf_stages * LeafRec{g.nx, g.nu}.per_stage());
+            g.off_fvec = off;
+            off = align_up(off + sizeof(double) * (size_t)g.leaf_stages * LeafRec{g.nx, g.nu}.vec());
+        }
+    }
+    if (P->mixed) {
+        P->off_conv = off;
+        off = align_up(off + sizeof(int32_t) * count);
+        P->off_stats = off;
+        off = align_up(off + sizeof(double) * ST_N * count);
+        P->off_part = off;
+        off = align_up(off + sizeof(double) * PART_N * (size_t)P->total_leaves);
+        // per instance: xbar0' nx | a' N nx | lx' N nx | lw' N nu | lN' nx | dx (N+1) nx | dw N nu | dlam (N+1) nx
+        P->off_cbuf.resize(count);
+        for (int i = 0; i < count; ++i) {
+            const size_t nx = dims[3 * i], nu = dims[3 * i + 1], N = dims[3 * i + 2];
+            P->off_cbuf[i] = off;
+            off = align_up(off + sizeof(double) * (nx + 2 * N * nx + N * nu + nx + 2 * (N + 1) * nx + N * nu));
+        }
     }
     P->total = off;
     P->tables.assign(P->tables_bytes, 0);
+    std::memcpy(P->tables.data() + (P->off_inst - P->off_tables), P->inst.data(), sizeof(InstInfo) * count);
     for (auto &g : P->groups) {
         if (!g.leaves.empty())
             std::memcpy(P->tables.data() + (g.off_leaves - P->off_tables), g.leaves.data(),
@@ -424,6 +467,29 @@ static rs_status bind_and_upload(rs_plan P, const rs_problem *probs, char *work,
         d.sQx = q.sQx; d.sQw = q.sQw; d.sQxw = q.sQxw; d.sA = q.sA; d.sB = q.sB;
         d.nx = q.nx; d.nu = q.nu; d.N = q.N;
     }
+    if (P->mixed) {
+        // correction problems: the same matrices; right-hand side and
+        // solution in the workspace (c = cN = 0, no objective)
+        dp.resize(2 * (size_t)P->count);
+        for (int i = 0; i < P->count; ++i) {
+            DevProb d = dp[i];
+            const size_t nx = d.nx, nu = d.nu, N = d.N;
+            double *b = reinterpret_cast<double *>(work + P->off_cbuf[i]);
+            d.x0 = b;
+            d.a = b + nx;
+            d.lx = b + nx + N * nx;
+            d.lw = b + nx + 2 * N * nx;
+            d.lN = b + nx + 2 * N * nx + N * nu;
+            d.c = nullptr;
+            d.cN = nullptr;
+            d.x = b + 2 * nx + 2 * N * nx + N * nu;
+            d.w = d.x + (N + 1) * nx;
+            d.lam = d.w + N * nu;
+            d.obj = nullptr;
+            dp[P->count + i] = d;
+        }
+    }
+    const size_t nprob = dp.size();
     const bool rebind = P->bound_work != work;
     if (rebind) {
         if (!P->pinned_tables && P->tables_bytes) {
@@ -443,16 +509,16 @@ static rs_status bind_and_upload(rs_plan P, const rs_problem *probs, char *work,
         P->probs_valid = false;
         P->bound_work = work;
     }
-    if (!P->probs_valid || std::memcmp(dp.data(), P->last_probs.data(), sizeof(DevProb) * P->count) != 0) {
+    if (!P->probs_valid || std::memcmp(dp.data(), P->last_probs.data(), sizeof(DevProb) * nprob) != 0) {
         const int r = P->ring;
         P->ring = (P->ring + 1) % RING;
         if (!P->pinned_probs[r]) {
-            if (hipHostMalloc(&P->pinned_probs[r], sizeof(DevProb) * P->count) != hipSuccess) return RS_ERR_HIP;
+            if (hipHostMalloc(&P->pinned_probs[r], sizeof(DevProb) * nprob) != hipSuccess) return RS_ERR_HIP;
             if (hipEventCreateWithFlags(&P->ev[r], hipEventDisableTiming) != hipSuccess) return RS_ERR_HIP;
         }
         if (P->ev_used[r] && hipEventSynchronize(P->ev[r]) != hipSuccess) return RS_ERR_HIP;
-        std::memcpy(P->pinned_probs[r], dp.data(), sizeof(DevProb) * P->count);
-        e = hipMemcpyAsync(work + P->off_probs, P->pinned_probs[r], sizeof(DevProb) * P->count,
+        std::memcpy(P->pinned_probs[r], dp.data(), sizeof(DevProb) * nprob);
+        e = hipMemcpyAsync(work + P->off_probs, P->pinned_probs[r], sizeof(DevProb) * nprob,
                            hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return RS_ERR_HIP;
         if (hipEventRecord(P->ev[r], st) != hipSuccess) return RS_ERR_HIP;
@@ -476,10 +542,118 @@ static rs_status check_call(rs_plan P, const rs_problem *probs, void *work, size
     return RS_OK;
 }
 
-// The three launches (leaf up, tree, leaf down) of one pass over every shape
-// group.  mode 0 = fused solve, 1 = rs_factor, 2 = rs_solve.  rs_solve keeps
-// the status words that rs_factor wrote and resets only the work queues.
-static rs_status run_pass(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
+// Launch arguments of one shape group.  corr = true points the problem
+// array at the correction problems of a mixed-precision plan.
+static GroupArgs group_args(rs_plan P, char *W, size_t gi, int32_t *info, bool corr, bool with_conv) {
+    Group &g = P->groups[gi];
+    GroupArgs a{};
+    const DevProb *user = reinterpret_cast<const DevProb *>(W + P->off_probs);
+    a.probs = corr ? user + P->count : user;
+    a.leaves = reinterpret_cast<const LeafItem *>(W + g.off_leaves);
+    a.nleaves = (int32_t)g.leaves.size();
+    a.items = reinterpret_cast<const TreeItem *>(W + g.off_items);
+    a.nitems = (int32_t)g.items.size();
+    a.slots = reinterpret_cast<double *>(W + g.off_slots);
+    a.leaf_scratch = W + g.off_scratch;
+    a.flags = reinterpret_cast<int32_t *>(W + g.off_flags);
+    a.queue = reinterpret_cast<int32_t *>(W + P->off_queues) + gi;
+    a.info = info;
+    a.epoch = P->epoch;
+    a.sps = g.shape->scratch_per_stage;
+    a.fstore = P->factored ? W + g.off_fstore : nullptr;
+    a.fvec = P->factored ? reinterpret_cast<double *>(W + g.off_fvec) : nullptr;
+    if (P->mixed) {
+        a.corr = user + P->count;
+        a.conv = with_conv ? reinterpret_cast<const int32_t *>(W + P->off_conv) : nullptr;
+        a.part = reinterpret_cast<double *>(W + P->off_part);
+        a.leaf_base = g.leaf_base;
+    }
+    return a;
+}
+
+// One pass (leaf up, tree, leaf down) over every shape group, after a reset
+// of the tree work queues (and, unless keep_status, of the status words).
+// pass 0 = fused solve, 1 = stored factorization, 2 = solve on the stored
+// factorization.
+static rs_status launch_pass(rs_plan P, char *W, int32_t *info, hipStream_t st, int pass, bool keep_status,
+                             bool corr, bool with_conv) {
+    static const int kinds[3][3] = {{KK_LEAF_UP, KK_TREE, KK_LEAF_DOWN},
+                                    {KK_F_LEAF_UP, KK_F_TREE, KK_F_LEAF_DOWN},
+                                    {KK_S_LEAF_UP, KK_S_TREE, KK_S_LEAF_DOWN}};
+    ++P->epoch;
+    int32_t *queues = reinterpret_cast<int32_t *>(W + P->off_queues);
+    const int ninfo = keep_status ? 0 : P->count;
+    hipError_t e = timed(P, KK_INIT, st, [&] { return launch_init(info, ninfo, queues, (int)P->groups.size(), st); });
+    if (e != hipSuccess) return RS_ERR_HIP;
+    const int f32 = P->mixed ? 1 : 0;
+    for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+        Group &g = P->groups[gi];
+        GroupArgs a = group_args(P, W, gi, info, corr, with_conv);
+        const Launcher *L = pass == 0 ? g.shape->fp64 : pass == 1 ? g.shape->factor[f32] : g.shape->vsolve[f32];
+        // the vector passes run one wavefront per work item
+        const int cap = pass == 2 ? 1024 : 256;
+        const int tree_grid = std::max(1, std::min<int>((int)g.items.size(), cap));
+        if (a.nleaves > 0) {
+            e = timed(P, kinds[pass][0], st, [&] { return L[0](a, a.nleaves, st); });
+            if (e != hipSuccess) return RS_ERR_HIP;
+        }
+        if (a.nitems > 0) {
+            e = timed(P, kinds[pass][1], st, [&] { return L[1](a, tree_grid, st); });
+            if (e != hipSuccess) return RS_ERR_HIP;
+        }
+        if (a.nleaves > 0) {
+            e = timed(P, kinds[pass][2], st, [&] { return L[2](a, a.nleaves, st); });
+            if (e != hipSuccess) return RS_ERR_HIP;
+        }
+    }
+    return RS_OK;
+}
+
+// Per-leaf refinement kernel (0 residual, 1 update) over every group.
+static rs_status launch_refine(rs_plan P, char *W, int32_t *info, hipStream_t st, int which, bool with_conv) {
+    for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+        Group &g = P->groups[gi];
+        GroupArgs a = group_args(P, W, gi, info, false, with_conv);
+        if (a.nleaves == 0) continue;
+        hipError_t e = timed(P, which == 0 ? KK_RESIDUAL : KK_UPDATE, st,
+                             [&] { return g.shape->refine[which](a, a.nleaves, st); });
+        if (e != hipSuccess) return RS_ERR_HIP;
+    }
+    return RS_OK;
+}
+
+static rs_status launch_check(rs_plan P, char *W, int32_t *info, hipStream_t st, int mode) {
+    hipError_t e = timed(P, KK_CHECK, st, [&] {
+        return launch_refine_check(reinterpret_cast<const InstInfo *>(W + P->off_inst), P->count,
+                                   reinterpret_cast<const double *>(W + P->off_part),
+                                   reinterpret_cast<double *>(W + P->off_stats),
+                                   reinterpret_cast<int32_t *>(W + P->off_conv), info,
+                                   reinterpret_cast<const DevProb *>(W + P->off_probs), mode, P->tol, st);
+    });
+    return e == hipSuccess ? RS_OK : RS_ERR_HIP;
+}
+
+// Solve on the stored mixed-precision factorization with FP64 iterative
+// refinement: z = solve(r); then up to max_refine times rho = r - K z (FP64),
+// d = solve(rho), z += d, until the correction is below tol/10 relative to z;
+// finally the relative residual of z and the objective.
+static rs_status mixed_solve(rs_plan P, char *W, int32_t *info, hipStream_t st) {
+    rs_status s = launch_check(P, W, info, st, 0);
+    if (s == RS_OK) s = launch_pass(P, W, info, st, 2, true, false, true);
+    for (int k = 0; k < P->max_refine && s == RS_OK; ++k) {
+        s = launch_refine(P, W, info, st, 0, true);
+        if (s == RS_OK) s = launch_pass(P, W, info, st, 2, true, true, true);
+        if (s == RS_OK) s = launch_refine(P, W, info, st, 1, true);
+        if (s == RS_OK) s = launch_check(P, W, info, st, 1);
+    }
+    if (s == RS_OK) s = launch_refine(P, W, info, st, 0, false);
+    if (s == RS_OK) s = launch_check(P, W, info, st, 2);
+    P->last_refine = P->max_refine;
+    return s;
+}
+
+// mode 0 = rs_batch_solve, 1 = rs_factor, 2 = rs_solve.
+static rs_status run_call(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
                           int32_t *info_dev, int mode) {
     rs_status s = check_call(P, probs, work, work_bytes);
     if (s != RS_OK) return s;
@@ -488,54 +662,31 @@ static rs_status run_pass(rs_plan P, const rs_problem *probs, void *work, size_t
     char *W = static_cast<char *>(work);
     s = bind_and_upload(P, probs, W, st);
     if (s != RS_OK) return s;
-    ++P->epoch;
     int32_t *info = info_dev ? info_dev : reinterpret_cast<int32_t *>(W + P->off_info);
-    int32_t *queues = reinterpret_cast<int32_t *>(W + P->off_queues);
-    const int ninfo = mode == 2 ? 0 : P->count;
-    hipError_t e = timed(P, KK_INIT, st, [&] { return launch_init(info, ninfo, queues, (int)P->groups.size(), st); });
-    if (e != hipSuccess) return RS_ERR_HIP;
-    static const int kinds[3][3] = {{KK_LEAF_UP, KK_TREE, KK_LEAF_DOWN},
-                                    {KK_F_LEAF_UP, KK_F_TREE, KK_F_LEAF_DOWN},
-                                    {KK_S_LEAF_UP, KK_S_TREE, KK_S_LEAF_DOWN}};
-    for (size_t gi = 0; gi < P->groups.size(); ++gi) {
-        Group &g = P->groups[gi];
-        GroupArgs a{};
-        a.probs = reinterpret_cast<const DevProb *>(W + P->off_probs);
-        a.leaves = reinterpret_cast<const LeafItem *>(W + g.off_leaves);
-        a.nleaves = (int32_t)g.leaves.size();
-        a.items = reinterpret_cast<const TreeItem *>(W + g.off_items);
-        a.nitems = (int32_t)g.items.size();
-        a.slots = reinterpret_cast<double *>(W + g.off_slots);
-        a.leaf_scratch = W + g.off_scratch;
-        a.flags = reinterpret_cast<int32_t *>(W + g.off_flags);
-        a.queue = queues + gi;
-        a.info = info;
-        a.epoch = P->epoch;
-        a.sps = g.shape->scratch_per_stage;
-        a.fstore = P->factored ? reinterpret_cast<double *>(W + g.off_fstore) : nullptr;
-        const Launcher *L = mode == 0 ? g.shape->fp64 : mode == 1 ? g.shape->factor : g.shape->vsolve;
-        // the vector passes run one wavefront per work item
-        const int cap = mode == 2 ? 1024 : 256;
-        const int tree_grid = std::max(1, std::min<int>((int)g.items.size(), cap));
-        if (a.nleaves > 0) {
-            e = timed(P, kinds[mode][0], st, [&] { return L[0](a, a.nleaves, st); });
-            if (e != hipSuccess) return RS_ERR_HIP;
-        }
-        if (a.nitems > 0) {
-            e = timed(P, kinds[mode][1], st, [&] { return L[1](a, tree_grid, st); });
-            if (e != hipSuccess) return RS_ERR_HIP;
-        }
-        if (a.nleaves > 0) {
-            e = timed(P, kinds[mode][2], st, [&] { return L[2](a, a.nleaves, st); });
-            if (e != hipSuccess) return RS_ERR_HIP;
-        }
+    if (!P->mixed) {
+        return launch_pass(P, W, info, st, mode, mode == 2, false, false);
     }
-    return RS_OK;
+    if (mode != 2) {
+        s = launch_pass(P, W, info, st, 1, false, false, false);
+        if (s != RS_OK || mode == 1) return s;
+    }
+    return mixed_solve(P, W, info, st);
 }
 
 rs_status rs_batch_solve(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
                          int32_t *info_dev) {
-    return run_pass(P, probs, work, work_bytes, stream, info_dev, 0);
+    return run_call(P, probs, work, work_bytes, stream, info_dev, 0);
+}
+
+rs_status rs_refine_stats(rs_plan P, const void *work, double *out, void *stream) {
+    if (!P || !work || !out) return RS_ERR_ARG;
+    if (!P->mixed) return RS_ERR_ARG;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const char *W = static_cast<const char *>(work);
+    if (hipMemcpyAsync(out, W + P->off_stats, sizeof(double) * ST_N * P->count, hipMemcpyDeviceToHost, st) !=
+        hipSuccess)
+        return RS_ERR_HIP;
+    return hipStreamSynchronize(st) == hipSuccess ? RS_OK : RS_ERR_HIP;
 }
 
 rs_status rs_plan_set_timing(rs_plan P, int32_t enable) {
@@ -569,12 +720,12 @@ rs_status rs_plan_kernel_times(rs_plan P, double *ms, int64_t *launches, int32_t
 
 rs_status rs_factor(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
                     int32_t *info_dev) {
-    return run_pass(P, probs, work, work_bytes, stream, info_dev, 1);
+    return run_call(P, probs, work, work_bytes, stream, info_dev, 1);
 }
 
 rs_status rs_solve(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
                    int32_t *info_dev) {
-    return run_pass(P, probs, work, work_bytes, stream, info_dev, 2);
+    return run_call(P, probs, work, work_bytes, stream, info_dev, 2);
 }
 
 }  // extern "C"

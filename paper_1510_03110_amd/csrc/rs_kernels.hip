@@ -362,10 +362,13 @@ const ShapeEntry *find_shape(int nx, int nu) {
             e.fp64[0] = mfma_leaf_up(a, b) ? mfma_leaf_up(a, b) : up;
             e.fp64[1] = mfma_tree(a) ? mfma_tree(a) : tr;
             e.fp64[2] = mfma_leaf_down(a, b) ? mfma_leaf_down(a, b) : dn;
-            for (int k = 0; k < 3; ++k) {
-                e.factor[k] = mfma_factor(a, b, k);
-                e.vsolve[k] = vector_solve(a, b, k);
-            }
+            for (int f = 0; f < 2; ++f)
+                for (int k = 0; k < 3; ++k) {
+                    e.factor[f][k] = mfma_factor(a, b, k, f == 1);
+                    e.vsolve[f][k] = vector_solve(a, b, k, f == 1);
+                }
+            e.refine[0] = refine_kernel(a, b, 0);
+            e.refine[1] = refine_kernel(a, b, 1);
             e.scratch_per_stage = scratch_per_stage(a, b);
             if (e.fp64[0] && e.fp64[1] && e.fp64[2]) table[n++] = e;
         };

@@ -44,15 +44,15 @@ __device__ __forceinline__ TreeItem load_item_u(const TreeItem *tab, int i) {
 
 template <int NX, int NU>
 struct Sizes {
-    static constexpr size_t red = sizeof(MSmem<NX, NU, true, false>), elim = sizeof(MSmem<NX, NU, false, false>),
-                            solve = sizeof(MSmem<NX, NU, false, true>);
+    static constexpr size_t red = sizeof(MSmem<double, NX, NU, true, false>), elim = sizeof(MSmem<double, NX, NU, false, false>),
+                            solve = sizeof(MSmem<double, NX, NU, false, true>);
     static constexpr size_t up = red > elim ? red : elim;
     static constexpr size_t all = up > solve ? up : solve;
 };
 
 // Reduce (Alg. 4) and write the M1 message.
 template <int NX, int NU, class Get>
-__device__ void reduce_to(MSmem<NX, NU, true, false> &S, Get get, int count, double *out, int32_t *info, int inst,
+__device__ void reduce_to(MSmem<double, NX, NU, true, false> &S, Get get, int count, double *out, int32_t *info, int inst,
                           int stage_base, int fail_code) {
     const int tid = threadIdx.x;
     for (int e = tid; e < NX * NX; e += NT) {
@@ -66,7 +66,7 @@ __device__ void reduce_to(MSmem<NX, NU, true, false> &S, Get get, int count, dou
     }
     if (tid == 0) S.cbar = 0.0;
     __syncthreads();
-    mfma_pass<NX, NU, true, false>(S, get, count, info, inst, stage_base, fail_code, [](int, auto &) {}, NoEmit{});
+    mfma_pass(S, get, count, info, inst, stage_base, fail_code, [](int, auto &) {}, NoEmit{});
     const SlotLayout SL{NX};
     for (int e = tid; e < NX * NX; e += NT) {
         const int i = e / NX, j = e % NX;
@@ -84,10 +84,10 @@ __device__ void reduce_to(MSmem<NX, NU, true, false> &S, Get get, int count, dou
 // Eliminate a subproblem with known terminal (already in S) and write the
 // terminal cost it passes up (Sec. 4.2, last subproblem).
 template <int NX, int NU, class Get>
-__device__ void eliminate_to(MSmem<NX, NU, false, false> &S, Get get, int count, double *out, int32_t *info,
+__device__ void eliminate_to(MSmem<double, NX, NU, false, false> &S, Get get, int count, double *out, int32_t *info,
                              int inst, int stage_base, int fail_code) {
     const int tid = threadIdx.x;
-    mfma_pass<NX, NU, false, false>(S, get, count, info, inst, stage_base, fail_code, [](int, auto &) {}, NoEmit{});
+    mfma_pass(S, get, count, info, inst, stage_base, fail_code, [](int, auto &) {}, NoEmit{});
     const SlotLayout SL{NX};
     for (int e = tid; e < NX * NX; e += NT) out[SL.Qx() + e] = S.P[e];
     for (int i = tid; i < NX; i += NT) out[SL.lx() + i] = -S.Psi[i];
@@ -144,7 +144,7 @@ __device__ __forceinline__ void fwd_fetch(FwdPrefetch<NX, NU, LAM> &f, Get get, 
 }
 
 template <int NX, int NU, bool LAM>
-__device__ __forceinline__ void fwd_commit_main(MSmem<NX, NU, false, true> &S, const FwdPrefetch<NX, NU, LAM> &f) {
+__device__ __forceinline__ void fwd_commit_main(MSmem<double, NX, NU, false, true> &S, const FwdPrefetch<NX, NU, LAM> &f) {
     using FP = FwdPrefetch<NX, NU, LAM>;
     const int tid = threadIdx.x;
     double *KT = S.W;
@@ -184,7 +184,7 @@ __device__ __forceinline__ void fwd_commit_B(double *BT, const FwdPrefetch<NX, N
 }
 
 template <int NX, int NU, bool LAM, class Get, class Fac, class Emit>
-__device__ void forward_m(MSmem<NX, NU, false, true> &S, Get get, int count, Fac fac, Emit emit) {
+__device__ void forward_m(MSmem<double, NX, NU, false, true> &S, Get get, int count, Fac fac, Emit emit) {
     static_assert(2 * NX * NU <= NX * (NX + NU), "K' and the second B buffer live in W");
     const int tid = threadIdx.x;
     count = uni(count);
@@ -248,10 +248,10 @@ __global__ void __launch_bounds__(NT, 2) km_leaf_up(GroupArgs g) {
     double *out = g.slots + (int64_t)it.slot * SL.size();
     auto get = [&](int s) { return prob_stage(p, it.t0 + s); };
     if (!(it.flags & LEAF_LAST)) {
-        auto &S = *reinterpret_cast<MSmem<NX, NU, true, false> *>(raw);
+        auto &S = *reinterpret_cast<MSmem<double, NX, NU, true, false> *>(raw);
         reduce_to<NX, NU>(S, get, it.len, out, g.info, it.inst, it.t0, 2);
     } else {
-        auto &S = *reinterpret_cast<MSmem<NX, NU, false, false> *>(raw);
+        auto &S = *reinterpret_cast<MSmem<double, NX, NU, false, false> *>(raw);
         const int tid = threadIdx.x;
         for (int e = tid; e < NX * NX; e += NT) S.P[e] = p.QxN[e];
         for (int i = tid; i < NX; i += NT) S.Psi[i] = p.lN ? -p.lN[i] : 0.0;
@@ -275,8 +275,8 @@ struct LeafFac {
 
 template <int NX, int NU>
 __global__ void __launch_bounds__(NT, 3) km_leaf_down(GroupArgs g) {
-    __shared__ __attribute__((aligned(16))) char raw[sizeof(MSmem<NX, NU, false, true>)];
-    auto &S = *reinterpret_cast<MSmem<NX, NU, false, true> *>(raw);
+    __shared__ __attribute__((aligned(16))) char raw[sizeof(MSmem<double, NX, NU, false, true>)];
+    auto &S = *reinterpret_cast<MSmem<double, NX, NU, false, true> *>(raw);
     using LF = LeafFac<NX, NU>;
     const LeafItem it = load_leaf_u(g.leaves, blockIdx.x);
     const DevProb p = load_prob(g.probs, it.inst);
@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(NT, 3) km_leaf_down(GroupArgs g) {
         __device__ void Psi(int s, int i, double v) const { at(s)[LF::Psi_ + i] = v; }
         __device__ void k(int s, int i, double v) const { at(s)[LF::k_ + i] = v; }
     };
-    mfma_pass<NX, NU, false, true>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {}, Out{{}, scr});
+    mfma_pass(S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {}, Out{{}, scr});
     if ((it.flags & LEAF_TOP) && p.obj) {
         if (threadIdx.x < 64) {
             double part = 0;
@@ -364,7 +364,7 @@ struct SlotOut : NoEmit {
 };
 
 template <int NX>
-__device__ void tree_solve_m(MSmem<NX, NX, false, true> &S, const TreeItem &it, const DevProb &p, GroupArgs &g) {
+__device__ void tree_solve_m(MSmem<double, NX, NX, false, true> &S, const TreeItem &it, const DevProb &p, GroupArgs &g) {
     const SlotLayout SL{NX};
     const int tid = threadIdx.x;
     double *slots = g.slots;
@@ -380,7 +380,7 @@ __device__ void tree_solve_m(MSmem<NX, NX, false, true> &S, const TreeItem &it, 
     if (tid == 0) S.cbar = term ? term[SL.c()] : msg[SL.cb()];
     __syncthreads();
     auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };
-    mfma_pass<NX, NX, false, true>(
+    mfma_pass(
         S, get, it.count, g.info, it.inst, -1, 3,
         [&](int s, auto &Sm) {          // M2 for child s: cost to go at the end of stage s
             double *d = slot(it.first + s);
@@ -452,10 +452,10 @@ __global__ void __launch_bounds__(NT) km_tree(GroupArgs g) {
         auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
         auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };
         if (it.kind == ITEM_UP) {
-            auto &S = *reinterpret_cast<MSmem<NX, NX, true, false> *>(raw);
+            auto &S = *reinterpret_cast<MSmem<double, NX, NX, true, false> *>(raw);
             reduce_to<NX, NX>(S, get, it.count, slot(it.out_slot), g.info, it.inst, -1, 3);
         } else if (it.kind == ITEM_UP_LAST) {
-            auto &S = *reinterpret_cast<MSmem<NX, NX, false, false> *>(raw);
+            auto &S = *reinterpret_cast<MSmem<double, NX, NX, false, false> *>(raw);
             const double *term = slot(it.term_slot);
             for (int e = tid; e < NX * NX; e += NT) S.P[e] = term[SL.Qx() + e];
             for (int i = tid; i < NX; i += NT) S.Psi[i] = -term[SL.lx() + i];
@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(NT) km_tree(GroupArgs g) {
             __syncthreads();
             eliminate_to<NX, NX>(S, get, it.count, slot(it.out_slot), g.info, it.inst, -1, 3);
         } else {
-            auto &S = *reinterpret_cast<MSmem<NX, NX, false, true> *>(raw);
+            auto &S = *reinterpret_cast<MSmem<double, NX, NX, false, true> *>(raw);
             tree_solve_m<NX>(S, it, p, g);
         }
         __threadfence();
@@ -475,25 +475,28 @@ __global__ void __launch_bounds__(NT) km_tree(GroupArgs g) {
 
 // ================================================ stored factorization
 // rs_factor: the matrix lines of every pass (no right-hand side), writing the
-// per-stage factors that rs_solve's vector passes read back.
+// per-stage factors that rs_solve's vector passes read back.  The leaf passes
+// run in T (FP64, or FP32 in mixed-precision plans) and store their records in
+// T; the master levels always run in FP64.
 
 // Leaf record writer: up records at +0, down records at +up() of each stage.
-template <int NX, int NU, bool UP>
+template <class T, int NX, int NU, bool UP>
 struct LeafFacOut : NoEmit {
     static constexpr bool VEC = false, KF = true, PF = true, LF = true, VF = UP;
-    double *base;                                    // stage 0 of this leaf
-    __device__ double *at(int s) const {
+    T *base;                                         // stage 0 of this leaf
+    __device__ T *at(int s) const {
         const LeafRec R{NX, NU};
         return base + (int64_t)s * R.per_stage() + (UP ? 0 : R.up());
     }
-    __device__ void K(int s, int i, int j, double v) const { at(s)[LeafRec{NX, NU}.K() + i * NX + j] = v; }
-    __device__ void P(int s, int i, int j, double v) const { at(s)[LeafRec{NX, NU}.P() + i * NX + j] = v; }
-    __device__ void V(int s, int i, int j, double v) const { at(s)[LeafRec{NX, NU}.V() + i * NX + j] = v; }
-    __device__ void L(int s, const double *Li) const {
-        double *d = at(s);
+    __device__ void K(int s, int i, int j, double v) const { at(s)[LeafRec{NX, NU}.K() + i * NX + j] = (T)v; }
+    __device__ void P(int s, int i, int j, double v) const { at(s)[LeafRec{NX, NU}.P() + i * NX + j] = (T)v; }
+    __device__ void V(int s, int i, int j, double v) const { at(s)[LeafRec{NX, NU}.V() + i * NX + j] = (T)v; }
+    template <class U>
+    __device__ void L(int s, const U *Li) const {
+        T *d = at(s);
         const LeafRec R{NX, NU};
         for (int e = threadIdx.x; e < NU * NU; e += NT) {
-            const double v = Li[e];
+            const T v = (T)Li[e];
             d[R.L() + e] = v;
             d[R.LT() + (e % NU) * NU + e / NU] = v;
         }
@@ -517,7 +520,8 @@ struct SlotFacOut : NoEmit {
     __device__ void V(int s, int i, int j, double v) const {
         if (UP) at(s)[SlotLayout{NX}.uV() + i * NX + j] = v;
     }
-    __device__ void L(int s, const double *Li) const {
+    template <class U>
+    __device__ void L(int s, const U *Li) const {
         double *d = at(s);
         const SlotLayout SL{NX};
         const int oL = UP ? SL.uL() : SL.dL(), oT = UP ? SL.uLT() : SL.dLT();
@@ -529,27 +533,33 @@ struct SlotFacOut : NoEmit {
     }
 };
 
-template <int NX, int NU>
+template <class T, int NX, int NU>
+struct FSizes {
+    static constexpr size_t red = sizeof(MSmem<T, NX, NU, true, false>), elim = sizeof(MSmem<T, NX, NU, false, false>);
+    static constexpr size_t up = red > elim ? red : elim;
+};
+
+template <class T, int NX, int NU>
 __global__ void __launch_bounds__(NT, 2) kf_leaf_up(GroupArgs g) {
-    __shared__ __attribute__((aligned(16))) char raw[Sizes<NX, NU>::up];
+    __shared__ __attribute__((aligned(16))) char raw[FSizes<T, NX, NU>::up];
     const LeafItem it = load_leaf_u(g.leaves, blockIdx.x);
     if (it.flags & LEAF_TOP) return;
     const DevProb p = load_prob(g.probs, it.inst);
     const SlotLayout SL{NX};
     double *out = g.slots + (int64_t)it.slot * SL.size();
-    double *base = g.fstore + (it.scratch / g.sps) * (int64_t)LeafRec{NX, NU}.per_stage();
+    T *base = reinterpret_cast<T *>(g.fstore) + (it.scratch / g.sps) * (int64_t)LeafRec{NX, NU}.per_stage();
     auto get = [&](int s) { return prob_stage(p, it.t0 + s); };
     const int tid = threadIdx.x;
     if (!(it.flags & LEAF_LAST)) {
-        auto &S = *reinterpret_cast<MSmem<NX, NU, true, false> *>(raw);
+        auto &S = *reinterpret_cast<MSmem<T, NX, NU, true, false> *>(raw);
         for (int e = tid; e < NX * NX; e += NT) {
-            S.P[e] = 0.0;
-            S.V[e] = (e / NX == e % NX) ? 1.0 : 0.0;
-            S.Qh[e] = 0.0;
+            S.P[e] = T(0);
+            S.V[e] = (e / NX == e % NX) ? T(1) : T(0);
+            S.Qh[e] = T(0);
         }
         __syncthreads();
-        mfma_pass<NX, NU, true, false>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {},
-                                       LeafFacOut<NX, NU, true>{{}, base});
+        mfma_pass(S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {},
+                  LeafFacOut<T, NX, NU, true>{{}, base});
         for (int e = tid; e < NX * NX; e += NT) {
             const int i = e / NX, j = e % NX;
             out[SL.A() + e] = S.V[j * NX + i];
@@ -557,30 +567,29 @@ __global__ void __launch_bounds__(NT, 2) kf_leaf_up(GroupArgs g) {
             out[SL.Qx() + e] = S.P[e];
         }
     } else {
-        auto &S = *reinterpret_cast<MSmem<NX, NU, false, false> *>(raw);
-        for (int e = tid; e < NX * NX; e += NT) S.P[e] = p.QxN[e];
+        auto &S = *reinterpret_cast<MSmem<T, NX, NU, false, false> *>(raw);
+        for (int e = tid; e < NX * NX; e += NT) S.P[e] = (T)p.QxN[e];
         __syncthreads();
-        mfma_pass<NX, NU, false, false>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {},
-                                        LeafFacOut<NX, NU, true>{{}, base});
+        mfma_pass(S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {},
+                  LeafFacOut<T, NX, NU, true>{{}, base});
         for (int e = tid; e < NX * NX; e += NT) out[SL.Qx() + e] = S.P[e];
     }
 }
 
-template <int NX, int NU>
+template <class T, int NX, int NU>
 __global__ void __launch_bounds__(NT, 3) kf_leaf_down(GroupArgs g) {
-    __shared__ __attribute__((aligned(16))) char raw[sizeof(MSmem<NX, NU, false, true>)];
-    auto &S = *reinterpret_cast<MSmem<NX, NU, false, true> *>(raw);
+    __shared__ __attribute__((aligned(16))) char raw[sizeof(MSmem<T, NX, NU, false, true>)];
+    auto &S = *reinterpret_cast<MSmem<T, NX, NU, false, true> *>(raw);
     const LeafItem it = load_leaf_u(g.leaves, blockIdx.x);
     const DevProb p = load_prob(g.probs, it.inst);
     const SlotLayout SL{NX};
     const bool known_end = (it.flags & (LEAF_LAST | LEAF_TOP)) != 0;
     const double *msg = (it.flags & LEAF_TOP) ? nullptr : g.slots + (int64_t)it.slot * SL.size();
-    double *base = g.fstore + (it.scratch / g.sps) * (int64_t)LeafRec{NX, NU}.per_stage();
-    for (int e = threadIdx.x; e < NX * NX; e += NT) S.P[e] = known_end ? p.QxN[e] : msg[SL.P() + e];
+    T *base = reinterpret_cast<T *>(g.fstore) + (it.scratch / g.sps) * (int64_t)LeafRec{NX, NU}.per_stage();
+    for (int e = threadIdx.x; e < NX * NX; e += NT) S.P[e] = (T)(known_end ? p.QxN[e] : msg[SL.P() + e]);
     __syncthreads();
     auto get = [&](int s) { return prob_stage(p, it.t0 + s); };
-    mfma_pass<NX, NU, false, true>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {},
-                                   LeafFacOut<NX, NU, false>{{}, base});
+    mfma_pass(S, get, it.len, g.info, it.inst, it.t0, 2, [](int, auto &) {}, LeafFacOut<T, NX, NU, false>{{}, base});
 }
 
 template <int NX>
@@ -615,14 +624,14 @@ __global__ void __launch_bounds__(NT) kf_tree(GroupArgs g) {
         auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
         auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };
         if (it.kind == ITEM_UP) {
-            auto &S = *reinterpret_cast<MSmem<NX, NX, true, false> *>(raw);
+            auto &S = *reinterpret_cast<MSmem<double, NX, NX, true, false> *>(raw);
             for (int e = tid; e < NX * NX; e += NT) {
                 S.P[e] = 0.0;
                 S.V[e] = (e / NX == e % NX) ? 1.0 : 0.0;
                 S.Qh[e] = 0.0;
             }
             __syncthreads();
-            mfma_pass<NX, NX, true, false>(S, get, it.count, g.info, it.inst, -1, 3, [](int, auto &) {},
+            mfma_pass(S, get, it.count, g.info, it.inst, -1, 3, [](int, auto &) {},
                                            SlotFacOut<NX, true>{{}, slots, it.first});
             double *out = slot(it.out_slot);
             for (int e = tid; e < NX * NX; e += NT) {
@@ -632,22 +641,22 @@ __global__ void __launch_bounds__(NT) kf_tree(GroupArgs g) {
                 out[SL.Qx() + e] = S.P[e];
             }
         } else if (it.kind == ITEM_UP_LAST) {
-            auto &S = *reinterpret_cast<MSmem<NX, NX, false, false> *>(raw);
+            auto &S = *reinterpret_cast<MSmem<double, NX, NX, false, false> *>(raw);
             const double *term = slot(it.term_slot);
             for (int e = tid; e < NX * NX; e += NT) S.P[e] = term[SL.Qx() + e];
             __syncthreads();
-            mfma_pass<NX, NX, false, false>(S, get, it.count, g.info, it.inst, -1, 3, [](int, auto &) {},
+            mfma_pass(S, get, it.count, g.info, it.inst, -1, 3, [](int, auto &) {},
                                             SlotFacOut<NX, true>{{}, slots, it.first});
             double *out = slot(it.out_slot);
             for (int e = tid; e < NX * NX; e += NT) out[SL.Qx() + e] = S.P[e];
         } else {
-            auto &S = *reinterpret_cast<MSmem<NX, NX, false, true> *>(raw);
+            auto &S = *reinterpret_cast<MSmem<double, NX, NX, false, true> *>(raw);
             const bool top = it.kind == ITEM_TOP;
             const double *msg = top ? nullptr : slot(it.out_slot);
             const double *term = it.last ? slot(it.term_slot) : nullptr;
             for (int e = tid; e < NX * NX; e += NT) S.P[e] = term ? term[SL.Qx() + e] : msg[SL.P() + e];
             __syncthreads();
-            mfma_pass<NX, NX, false, true>(
+            mfma_pass(
                 S, get, it.count, g.info, it.inst, -1, 3,
                 [&](int s, auto &Sm) {      // M2 for child s: P at the end of stage s
                     block_copy<NX * NX>(slot(it.first + s) + SL.P(), Sm.P);
@@ -678,9 +687,9 @@ hipError_t launch_leaf_down_m(const GroupArgs &g, int, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int NX, int NU>
+template <class T, int NX, int NU>
 hipError_t launch_factor_leaf_up(const GroupArgs &g, int, hipStream_t st) {
-    hipLaunchKernelGGL((kf_leaf_up<NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL((kf_leaf_up<T, NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
     return hipGetLastError();
 }
 template <int NX>
@@ -688,20 +697,25 @@ hipError_t launch_factor_tree(const GroupArgs &g, int grid, hipStream_t st) {
     hipLaunchKernelGGL((kf_tree<NX>), dim3(grid), dim3(NT), 0, st, g);
     return hipGetLastError();
 }
-template <int NX, int NU>
+template <class T, int NX, int NU>
 hipError_t launch_factor_leaf_down(const GroupArgs &g, int, hipStream_t st) {
-    hipLaunchKernelGGL((kf_leaf_down<NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL((kf_leaf_down<T, NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
     return hipGetLastError();
 }
 
 }  // namespace mf
 
-Launcher mfma_factor(int nx, int nu, int which) {
+// which: 0 leaf up, 1 tree, 2 leaf down; fp32: leaf passes in FP32 (the tree
+// is FP64 in both).
+Launcher mfma_factor(int nx, int nu, int which, bool fp32) {
 #define RS_FAC(a, b)                                                                   \
     if (nx == a && nu == b) {                                                          \
-        if (which == 0) return &mf::launch_factor_leaf_up<a, b>;                       \
         if (which == 1) return &mf::launch_factor_tree<a>;                             \
-        return &mf::launch_factor_leaf_down<a, b>;                                     \
+        if (which == 0)                                                                \
+            return fp32 ? &mf::launch_factor_leaf_up<float, a, b>                     \
+                        : &mf::launch_factor_leaf_up<double, a, b>;                   \
+        return fp32 ? &mf::launch_factor_leaf_down<float, a, b>                       \
+                    : &mf::launch_factor_leaf_down<double, a, b>;                     \
     }
     RS_FAC(16, 16)
     RS_FAC(32, 16)

@@ -18,19 +18,24 @@ enum KernelKind {
     KK_LEAF_UP = 1, KK_TREE = 2, KK_LEAF_DOWN = 3,          // fused solve
     KK_F_LEAF_UP = 4, KK_F_TREE = 5, KK_F_LEAF_DOWN = 6,    // rs_factor
     KK_S_LEAF_UP = 7, KK_S_TREE = 8, KK_S_LEAF_DOWN = 9,    // rs_solve
+    KK_RESIDUAL = 10, KK_UPDATE = 11, KK_CHECK = 12,        // mixed-precision refinement
     KK_COUNT = 16
 };
 
 struct ShapeEntry {
     int nx, nu;
     Launcher fp64[3];        // fused: leaf up, tree, leaf down
-    Launcher factor[3];      // stored factorization (nullptr: not available for the shape)
-    Launcher vsolve[3];      // right-hand-side passes on the stored factorization
+    Launcher factor[2][3];   // stored factorization [fp32 leaves][pass] (nullptr: not available)
+    Launcher vsolve[2][3];   // right-hand-side passes on the stored factorization
+    Launcher refine[2];      // FP64 residual, refinement update
     int scratch_per_stage;
 };
 
-Launcher mfma_factor(int nx, int nu, int which);
-Launcher vector_solve(int nx, int nu, int which);
+Launcher mfma_factor(int nx, int nu, int which, bool fp32);
+Launcher vector_solve(int nx, int nu, int which, bool fp32);
+Launcher refine_kernel(int nx, int nu, int which);       // 0 residual, 1 update
+hipError_t launch_refine_check(const InstInfo *tab, int count, const double *part, double *stats, int32_t *conv,
+                               int32_t *info, const DevProb *probs, int mode, double tol, hipStream_t st);
 
 const ShapeEntry *find_shape(int nx, int nu);
 hipError_t launch_init(int32_t *info, int count, int32_t *queues, int nq, hipStream_t st);

@@ -1,9 +1,11 @@
 // Matrix-core (MFMA) version of the per-stage Riccati recursion for state and
-// input dimensions that are multiples of 16 (FP64, gfx950).
+// input dimensions that are multiples of 16 (gfx950), in FP64 or FP32: the
+// element type T of the working set selects v_mfma_f64_16x16x4f64 or
+// v_mfma_f32_16x16x4f32.  Inputs are always read as FP64 and rounded to T
+// when staged.
 //
 // Every dense product of a stage is a list of 16x16 output tiles computed
-// with v_mfma_f64_16x16x4f64 by the four wavefronts of the workgroup, tile t
-// going to wave t mod 4.  Operands are read from LDS; products are arranged so
+// by the four wavefronts of the workgroup, tile t going to wave t mod 4.  Operands are read from LDS; products are arranged so
 // that the A operand is always read as a transposed (column-contiguous) view,
 // which keeps the 16 lanes of one row group on consecutive addresses:
 //
@@ -24,25 +26,46 @@
 namespace rs {
 namespace mf {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-
 __device__ __forceinline__ int wave() { return uni((int)(threadIdx.x >> 6)); }
 __device__ __forceinline__ int lane() { return (int)(threadIdx.x & 63); }
 
+// The 16x16x4 matrix instruction of each element type.  Operand layout
+// (checked on gfx950 for both): A element (i,k) in lane i + 16k, B element
+// (k,j) in lane j + 16k.  Result element (row(r), lane%16) in acc[r] with
+// row(r) = lane/16 + 4r for f64 and 4(lane/16) + r for f32.
+template <class T>
+struct MT;
+template <>
+struct MT<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mfma(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int r) { return (lane() >> 4) + 4 * r; }
+};
+template <>
+struct MT<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mfma(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int r) { return 4 * (lane() >> 4) + r; }
+};
+template <class T>
+using v4_t = typename MT<T>::v4;
+typedef v4_t<double> d4;
+
 // acc += opA[16ti.., k] opB[k, 16tj..] over k < K.  opA(i,k) = TA ? A[k*lda+i]
-// : A[i*lda+k]; opB(k,j) = TB ? B[j*ldb+k] : B[k*ldb+j].  Operand layout of
-// the 16x16x4 f64 instruction (checked on gfx950): A element (i,k) in lane
-// i + 16k, B element (k,j) in lane j + 16k; result element
-// (lane/16 + 4r, lane%16) in acc[r].
+// : A[i*lda+k]; opB(k,j) = TB ? B[j*ldb+k] : B[k*ldb+j].
 // All operand reads of a tile are issued before its first MFMA so that the
 // LDS latency is paid once per tile, not once per instruction.
-template <int K, bool TA, bool TB>
-__device__ __forceinline__ d4 mma(d4 acc, const double *__restrict__ A, int lda, const double *__restrict__ B,
-                                  int ldb, int ti, int tj) {
+template <int K, bool TA, bool TB, class T>
+__device__ __forceinline__ v4_t<T> mma(v4_t<T> acc, const T *__restrict__ A, int lda, const T *__restrict__ B,
+                                       int ldb, int ti, int tj) {
     constexpr int S = K / 4;
     const int l = lane(), r16 = l & 15, k4 = l >> 4;
     const int i = 16 * ti + r16, j = 16 * tj + r16;
-    double a[S], b[S];
+    T a[S], b[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const int k = 4 * s + k4;
@@ -50,7 +73,7 @@ __device__ __forceinline__ d4 mma(d4 acc, const double *__restrict__ A, int lda,
         b[s] = TB ? B[j * ldb + k] : B[k * ldb + j];
     }
 #pragma unroll
-    for (int s = 0; s < S; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+    for (int s = 0; s < S; ++s) acc = MT<T>::mfma(a[s], b[s], acc);
     return acc;
 }
 
@@ -72,21 +95,24 @@ __device__ __forceinline__ void block_copy(D *__restrict__ dst, const Sx *__rest
     }
 }
 
-__device__ __forceinline__ d4 zero4() { return d4{0.0, 0.0, 0.0, 0.0}; }
+template <class T = double>
+__device__ __forceinline__ v4_t<T> zero4() { return v4_t<T>{T(0), T(0), T(0), T(0)}; }
 
 // Row / column of element r of this lane in tile (ti, tj).
-__device__ __forceinline__ int trow(int ti, int r) { return 16 * ti + (lane() >> 4) + 4 * r; }
+template <class T>
+__device__ __forceinline__ int trow(int ti, int r) { return 16 * ti + MT<T>::row(r); }
 __device__ __forceinline__ int tcol(int tj) { return 16 * tj + (lane() & 15); }
 
-template <class F>
+template <class T, class F>
 __device__ __forceinline__ void tile_for(int ti, int tj, F f) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) f(r, trow(ti, r), tcol(tj));
+    for (int r = 0; r < 4; ++r) f(r, trow<T>(ti, r), tcol(tj));
 }
 
 // Store element (i, j) of a lower tile and its mirror (j, i).  In a diagonal
 // tile only the i >= j half writes, so each element has a single writer.
-__device__ __forceinline__ void put_sym(double *M, int ld, int ti, int tj, int i, int j, double v) {
+template <class T>
+__device__ __forceinline__ void put_sym(T *M, int ld, int ti, int tj, int i, int j, T v) {
     if (ti != tj || i >= j) {
         M[i * ld + j] = v;
         M[j * ld + i] = v;
@@ -101,30 +127,31 @@ __device__ __forceinline__ void lower_tile(int t, int &ti, int &tj) {
 }
 
 // ------------------------------------------------------------------- LDS
-template <int NX, int NU, bool RED, bool SOLVE>
+template <class T, int NX, int NU, bool RED, bool SOLVE>
 struct MSmem {
+    typedef T elem;
     static constexpr int NW = NX + NU;
-    double P[NX * NX];          // P_{t+1}; F_{t+1} (phase B); P_t (phase E)
-    double A[NX * NX];          // stage A_t
-    double B[NX * NU];          // stage B_t
-    double W[NX * NW];          // P [A B]; then A'V (RED, first NX*NX) and Y (last NU*NX)
-    double HT[NU * NX];         // H'
-    double G[NU * NU];          // G, then L^{-1} (row-major) with G = L L'
-    double LiT[NU * NU];        // L^{-T} (row-major), i.e. L^{-1} by columns
-    double V[RED ? NX * NX : 1];
-    double Qh[RED ? NX * NX : 1];
-    double BV[RED ? NU * NX : 1];   // B'V
-    double X[RED ? NU * NX : 1];    // L^{-1} B'V
-    double Psi[NX], av[NX], lx[NX], pt[NX], gx[NX], x[NX], ax[NX];
-    double lw[NU], gw[NU], z[NU], kk[NU], wv[NU];
-    double v[RED ? NX : 1], Vta[RED ? NX : 1];
-    double c, cbar, red[4];
+    T P[NX * NX];          // P_{t+1}; F_{t+1} (phase B); P_t (phase E)
+    T A[NX * NX];          // stage A_t
+    T B[NX * NU];          // stage B_t
+    T W[NX * NW];          // P [A B]; then A'V (RED, first NX*NX) and Y (last NU*NX)
+    T HT[NU * NX];         // H'
+    T G[NU * NU];          // G, then L^{-1} (row-major) with G = L L'
+    T LiT[NU * NU];        // L^{-T} (row-major), i.e. L^{-1} by columns
+    T V[RED ? NX * NX : 1];
+    T Qh[RED ? NX * NX : 1];
+    T BV[RED ? NU * NX : 1];   // B'V
+    T X[RED ? NU * NX : 1];    // L^{-1} B'V
+    T Psi[NX], av[NX], lx[NX], pt[NX], gx[NX], x[NX], ax[NX];
+    T lw[NU], gw[NU], z[NU], kk[NU], wv[NU];
+    T v[RED ? NX : 1], Vta[RED ? NX : 1];
+    T c, cbar, red[4];
     int bad;
     // F is formed in phase B after the last read of P_{t+1} (phase A) and is
     // turned into P_t in place in phase E; Y = L^{-1} H' lives in the part of
     // W that A'V does not use.
-    __device__ double *F() { return P; }
-    __device__ double *Y() { return W + NX * NX; }
+    __device__ T *F() { return P; }
+    __device__ T *Y() { return W + NX * NX; }
     static_assert(NX * NW >= NX * NX + NU * NX, "Y fits behind A'V in W");
 };
 
@@ -138,7 +165,8 @@ struct NoEmit {
     static constexpr bool VEC = true, KF = false, PF = false, LF = false, VF = false;
     __device__ void K(int, int, int, double) const {}
     __device__ void P(int, int, int, double) const {}
-    __device__ void L(int, const double *) const {}
+    template <class U>
+    __device__ void L(int, const U *) const {}
     __device__ void V(int, int, int, double) const {}
     __device__ void Psi(int, int, double) const {}
     __device__ void k(int, int, double) const {}
@@ -148,20 +176,24 @@ struct NoEmit {
 // written to LDS (A, B, a, lx, lw, c) and the tiles of Qx, Qxw', Qw that this
 // thread's wave adds in the F / H' / G products.
 template <int NX, int NU>
-struct Prefetch {
-    static constexpr int NA = (NX * NX + NT - 1) / NT, NB = (NX * NU + NT - 1) / NT;
+struct Tiles {
     static constexpr int TF = (NX / 16) * (NX / 16 + 1) / 2, TH = (NU / 16) * (NX / 16), TG = (NU / 16) * (NU / 16 + 1) / 2;
     static constexpr int TILES = TF + TH + TG;
     static constexpr int PER_WAVE = (TILES + 3) / 4;
-    double a_[NA], b_[NB];
-    double av, lx, lw, c;
-    d4 q[PER_WAVE];
+};
+
+template <class T, int NX, int NU>
+struct Prefetch : Tiles<NX, NU> {
+    static constexpr int NA = (NX * NX + NT - 1) / NT, NB = (NX * NU + NT - 1) / NT;
+    T a_[NA], b_[NB];
+    T av, lx, lw, c;
+    v4_t<T> q[Tiles<NX, NU>::PER_WAVE];
 };
 
 // Tile t of phase B: F lower tiles, then H' tiles, then G lower tiles.
 template <int NX, int NU>
 __device__ __forceinline__ void phaseB_tile(int t, int &kind, int &ti, int &tj) {
-    using PF = Prefetch<NX, NU>;
+    using PF = Tiles<NX, NU>;
     if (t < PF::TF) {
         kind = 0;
         lower_tile(t, ti, tj);
@@ -176,45 +208,45 @@ __device__ __forceinline__ void phaseB_tile(int t, int &kind, int &ti, int &tj) 
     }
 }
 
-template <int NX, int NU>
-__device__ __forceinline__ void prefetch_stage(Prefetch<NX, NU> &pf, const StageSrc &s) {
-    using PF = Prefetch<NX, NU>;
+template <class T, int NX, int NU>
+__device__ __forceinline__ void prefetch_stage(Prefetch<T, NX, NU> &pf, const StageSrc &s) {
+    using PF = Prefetch<T, NX, NU>;
     const int tid = threadIdx.x;
 #pragma unroll
     for (int q = 0; q < PF::NA; ++q) {
         const int e = tid + q * NT;
-        pf.a_[q] = e < NX * NX ? s.A[e] : 0.0;
+        pf.a_[q] = e < NX * NX ? (T)s.A[e] : T(0);
     }
 #pragma unroll
     for (int q = 0; q < PF::NB; ++q) {
         const int e = tid + q * NT;
-        pf.b_[q] = e < NX * NU ? s.B[e] : 0.0;
+        pf.b_[q] = e < NX * NU ? (T)s.B[e] : T(0);
     }
-    pf.av = (tid < NX && s.a) ? s.a[tid] : 0.0;
-    pf.lx = (tid < NX && s.lx) ? s.lx[tid] : 0.0;
-    pf.lw = (tid < NU && s.lw) ? s.lw[tid] : 0.0;
-    pf.c = s.c;
+    pf.av = (tid < NX && s.a) ? (T)s.a[tid] : T(0);
+    pf.lx = (tid < NX && s.lx) ? (T)s.lx[tid] : T(0);
+    pf.lw = (tid < NU && s.lw) ? (T)s.lw[tid] : T(0);
+    pf.c = (T)s.c;
     const int w = wave();
 #pragma unroll
     for (int u = 0; u < PF::PER_WAVE; ++u) {
         const int t = w + 4 * u;
-        d4 q = zero4();
+        v4_t<T> q = zero4<T>();
         if (t < PF::TILES) {
             int kind, ti, tj;
             phaseB_tile<NX, NU>(t, kind, ti, tj);
-            tile_for(ti, tj, [&](int r, int i, int j) {
-                if (kind == 0) q[r] = s.Qx[i * NX + j];
-                else if (kind == 1) q[r] = s.Qxw ? s.Qxw[j * NU + i] : 0.0;
-                else q[r] = s.Qw[i * NU + j];
+            tile_for<T>(ti, tj, [&](int r, int i, int j) {
+                if (kind == 0) q[r] = (T)s.Qx[i * NX + j];
+                else if (kind == 1) q[r] = s.Qxw ? (T)s.Qxw[j * NU + i] : T(0);
+                else q[r] = (T)s.Qw[i * NU + j];
             });
         }
         pf.q[u] = q;
     }
 }
 
-template <int NX, int NU, bool RED, bool SOLVE>
-__device__ __forceinline__ void commit_stage(MSmem<NX, NU, RED, SOLVE> &S, const Prefetch<NX, NU> &pf) {
-    using PF = Prefetch<NX, NU>;
+template <class T, int NX, int NU, bool RED, bool SOLVE>
+__device__ __forceinline__ void commit_stage(MSmem<T, NX, NU, RED, SOLVE> &S, const Prefetch<T, NX, NU> &pf) {
+    using PF = Prefetch<T, NX, NU>;
     const int tid = threadIdx.x;
 #pragma unroll
     for (int q = 0; q < PF::NA; ++q) {
@@ -241,34 +273,34 @@ __device__ __forceinline__ void commit_stage(MSmem<NX, NU, RED, SOLVE> &S, const
 // L^{-T} row-major.  Both sweeps are right-looking, so the dependency chain
 // is one multiply-add per column.  Returns nonzero (wave-uniform) if a pivot
 // is not positive or not finite; a unit pivot is used in its place.
-template <int M>
-__device__ __forceinline__ int chol_inv_wave(double *G, double *LiT) {
+template <int M, class T>
+__device__ __forceinline__ int chol_inv_wave(T *G, T *LiT) {
     static_assert(M <= 64, "one wavefront factors at most 64 rows");
     const int ln = threadIdx.x & 63;
-    double g[M];
+    T g[M];
 #pragma unroll
-    for (int j = 0; j < M; ++j) g[j] = (ln < M) ? G[ln * M + j] : 0.0;
+    for (int j = 0; j < M; ++j) g[j] = (ln < M) ? G[ln * M + j] : T(0);
     int fail = 0;
-    double invd = 0.0;                   // 1 / L[ln][ln]
+    T invd = T(0);                       // 1 / L[ln][ln]
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        double d = bcast_lane(g[j], j);
-        if (!(d > 0.0) || !(d < 1e300)) {
+        T d = bcast_lane(g[j], j);
+        if (!(d > T(0)) || !__builtin_isfinite(d)) {
             fail = 1;
-            d = 1.0;
+            d = T(1);
         }
-        const double sq = sqrt(d);
-        const double is = 1.0 / sq;
-        const double lij = (ln == j) ? sq : g[j] * is;
+        const T sq = rs_sqrt(d);
+        const T is = T(1) / sq;
+        const T lij = (ln == j) ? sq : g[j] * is;
         if (ln == j) invd = is;
         g[j] = lij;
 #pragma unroll
         for (int k = j + 1; k < M; ++k) g[k] -= lij * bcast_lane(lij, k);
     }
     // lane c: column c of L^{-1}, from L x = e_c
-    double x[M];
+    T x[M];
 #pragma unroll
-    for (int i = 0; i < M; ++i) x[i] = (ln == i) ? 1.0 : 0.0;
+    for (int i = 0; i < M; ++i) x[i] = (ln == i) ? T(1) : T(0);
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         x[k] *= bcast_lane(invd, k);
@@ -286,7 +318,8 @@ __device__ __forceinline__ int chol_inv_wave(double *G, double *LiT) {
 }
 
 // Wave-level sum over the 64 lanes (result in every lane).
-__device__ __forceinline__ double wave_sum(double v) {
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
@@ -300,8 +333,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 //           K_{t+1}, P_t, Psi_t, k_{t+1} of stage s from the lanes that
 //           computed them; pre(s) sees P_{t+1}, Psi_{t+1}, cbar_{t+1}
 //   neither: elimination of a subproblem with known terminal (Alg. 1-2)
-template <int NX, int NU, bool RED, bool SOLVE, class Get, class Pre, class Out>
-__device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int32_t *info, int inst,
+template <class T, int NX, int NU, bool RED, bool SOLVE, class Get, class Pre, class Out>
+__device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, int32_t *info, int inst,
                           int stage_base, int fail_code, Pre pre, Out out) {
     static_assert(NX % 16 == 0 && NU % 16 == 0, "MFMA path needs multiples of 16");
     static_assert(NX <= 64 && NU <= 64, "per-wave vector roles assume NX, NU <= 64");
@@ -309,53 +342,53 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
     constexpr bool VEC = Out::VEC, KFORM = SOLVE || Out::KF, PEMIT = SOLVE || Out::PF;
     const int tid = threadIdx.x, w = wave(), l = lane();
     count = uni(count);
-    Prefetch<NX, NU> pf;
+    Prefetch<T, NX, NU> pf;
     if (tid == 0) S.bad = 0;
     if (count > 0) {
-        prefetch_stage<NX, NU>(pf, get(count - 1));
+        prefetch_stage<T, NX, NU>(pf, get(count - 1));
         commit_stage(S, pf);
     }
     __syncthreads();
     for (int s = count - 1; s >= 0; --s) {
         // stage s inputs: A, B, a, lx, lw, c in LDS; Qx/Qxw'/Qw tiles in pf.q
-        d4 qt[Prefetch<NX, NU>::PER_WAVE];
+        v4_t<T> qt[Tiles<NX, NU>::PER_WAVE];
 #pragma unroll
-        for (int u = 0; u < Prefetch<NX, NU>::PER_WAVE; ++u) qt[u] = pf.q[u];
-        if (s > 0) prefetch_stage<NX, NU>(pf, get(s - 1));
+        for (int u = 0; u < Tiles<NX, NU>::PER_WAVE; ++u) qt[u] = pf.q[u];
+        if (s > 0) prefetch_stage<T, NX, NU>(pf, get(s - 1));
         pre(s, S);
         // ---- phase A: W = P[A B], (RED) B'V; P a, Psi - P a, (RED) V'a
         {
             constexpr int TW = TX * (TX + TU), TBV = RED ? TU * TX : 0;
             for (int t = w; t < TW + TBV; t += 4) {
-                d4 acc = zero4();
+                v4_t<T> acc = zero4<T>();
                 if (t < TW) {
                     const int ti = t / (TX + TU), tj = t % (TX + TU);
                     if (tj < TX)
                         acc = mma<NX, true, false>(acc, S.P, NX, S.A, NX, ti, tj);
                     else
                         acc = mma<NX, true, false>(acc, S.P, NX, S.B, NU, ti, tj - TX);
-                    tile_for(ti, tj, [&](int r, int i, int j) { S.W[i * NW + j] = acc[r]; });
+                    tile_for<T>(ti, tj, [&](int r, int i, int j) { S.W[i * NW + j] = acc[r]; });
                 } else if constexpr (RED) {
                     const int u = t - TW, ti = u / TX, tj = u % TX;
                     acc = mma<NX, true, false>(acc, S.B, NU, S.V, NX, ti, tj);
-                    tile_for(ti, tj, [&](int r, int i, int j) { S.BV[i * NX + j] = acc[r]; });
+                    tile_for<T>(ti, tj, [&](int r, int i, int j) { S.BV[i * NX + j] = acc[r]; });
                 }
             }
             if (VEC && w == 3) {
-                double part = 0;
+                T part = T(0);
                 if (l < NX) {
-                    double pa = 0;
+                    T pa = T(0);
 #pragma unroll 8
                     for (int k = 0; k < NX; ++k) pa += S.P[k * NX + l] * S.av[k];
                     S.pt[l] = S.Psi[l] - pa;
-                    part = S.av[l] * (0.5 * pa - S.Psi[l]);
+                    part = S.av[l] * (T(0.5) * pa - S.Psi[l]);
                 }
                 // cbar += 1/2 a'Pa - Psi'a + c (Alg. 2, with P_{t+1}, Psi_{t+1})
                 part = wave_sum(part);
                 if (l == 0) S.cbar += part + S.c;
             } else if (VEC && RED && tid >= 128 && tid < 128 + NX) {
                 const int i = tid - 128;
-                double acc = 0;
+                T acc = T(0);
 #pragma unroll 8
                 for (int k = 0; k < NX; ++k) acc += S.V[k * NX + i] * S.av[k];
                 S.Vta[i] = acc;
@@ -364,35 +397,35 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
         __syncthreads();
         // ---- phase B: F = Qx + A'W_A (lower), H' = Qxw' + B'W_A, G = Qw + B'W_B (lower)
         {
-            using PF = Prefetch<NX, NU>;
+            using PF = Tiles<NX, NU>;
 #pragma unroll
             for (int u = 0; u < PF::PER_WAVE; ++u) {
                 const int t = w + 4 * u;
                 if (t < PF::TILES) {
                     int kind, ti, tj;
                     phaseB_tile<NX, NU>(t, kind, ti, tj);
-                    d4 acc = qt[u];
+                    v4_t<T> acc = qt[u];
                     if (kind == 0) {
                         acc = mma<NX, true, false>(acc, S.A, NX, S.W, NW, ti, tj);
-                        tile_for(ti, tj, [&](int r, int i, int j) { put_sym(S.F(), NX, ti, tj, i, j, acc[r]); });
+                        tile_for<T>(ti, tj, [&](int r, int i, int j) { put_sym(S.F(), NX, ti, tj, i, j, acc[r]); });
                     } else if (kind == 1) {
                         acc = mma<NX, true, false>(acc, S.B, NU, S.W, NW, ti, tj);
-                        tile_for(ti, tj, [&](int r, int i, int j) { S.HT[i * NX + j] = acc[r]; });
+                        tile_for<T>(ti, tj, [&](int r, int i, int j) { S.HT[i * NX + j] = acc[r]; });
                     } else {
                         acc = mma<NX, true, false>(acc, S.B, NU, S.W + NX, NW, ti, tj);
-                        tile_for(ti, tj, [&](int r, int i, int j) { put_sym(S.G, NU, ti, tj, i, j, acc[r]); });
+                        tile_for<T>(ti, tj, [&](int r, int i, int j) { put_sym(S.G, NU, ti, tj, i, j, acc[r]); });
                     }
                 }
             }
             if (VEC && tid >= 192 && tid < 192 + NX) {
                 const int i = tid - 192;
-                double acc = -S.lx[i];
+                T acc = -S.lx[i];
 #pragma unroll 8
                 for (int k = 0; k < NX; ++k) acc += S.A[k * NX + i] * S.pt[k];
                 S.gx[i] = acc;
             } else if (VEC && tid >= 128 && tid < 128 + NU) {
                 const int i = tid - 128;
-                double acc = -S.lw[i];
+                T acc = -S.lw[i];
 #pragma unroll 8
                 for (int k = 0; k < NX; ++k) acc += S.B[k * NU + i] * S.pt[k];
                 S.gw[i] = acc;
@@ -406,8 +439,8 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
         } else if constexpr (RED) {
             for (int t = w - 1; t < TX * TX; t += 3) {
                 const int ti = t / TX, tj = t % TX;
-                d4 acc = mma<NX, true, false>(zero4(), S.A, NX, S.V, NX, ti, tj);
-                tile_for(ti, tj, [&](int r, int i, int j) { S.W[i * NX + j] = acc[r]; });
+                v4_t<T> acc = mma<NX, true, false>(zero4<T>(), S.A, NX, S.V, NX, ti, tj);
+                tile_for<T>(ti, tj, [&](int r, int i, int j) { S.W[i * NX + j] = acc[r]; });
             }
         }
         __syncthreads();
@@ -421,16 +454,16 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
             for (int t = w; t < TY + TXX; t += 4) {
                 const int u = t < TY ? t : t - TY, ti = u / TX, tj = u % TX;
                 if (t < TY) {
-                    d4 acc = mma<NU, true, false>(zero4(), S.LiT, NU, S.HT, NX, ti, tj);
-                    tile_for(ti, tj, [&](int r, int i, int j) { S.Y()[i * NX + j] = acc[r]; });
+                    v4_t<T> acc = mma<NU, true, false>(zero4<T>(), S.LiT, NU, S.HT, NX, ti, tj);
+                    tile_for<T>(ti, tj, [&](int r, int i, int j) { S.Y()[i * NX + j] = acc[r]; });
                 } else if constexpr (RED) {
-                    d4 acc = mma<NU, true, false>(zero4(), S.LiT, NU, S.BV, NX, ti, tj);
-                    tile_for(ti, tj, [&](int r, int i, int j) { S.X[i * NX + j] = acc[r]; });
+                    v4_t<T> acc = mma<NU, true, false>(zero4<T>(), S.LiT, NU, S.BV, NX, ti, tj);
+                    tile_for<T>(ti, tj, [&](int r, int i, int j) { S.X[i * NX + j] = acc[r]; });
                 }
             }
             if (VEC && tid >= 192 && tid < 192 + NU) {
                 const int i = tid - 192;
-                double acc = 0;
+                T acc = T(0);
 #pragma unroll
                 for (int k = 0; k < NU; ++k) acc += S.LiT[k * NU + i] * S.gw[k];
                 S.z[i] = acc;
@@ -447,10 +480,10 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                 if (t < TL) {
                     int ti, tj;
                     lower_tile(t, ti, tj);
-                    d4 acc = mma<NU, true, false>(zero4(), S.Y(), NX, S.Y(), NX, ti, tj);
-                    tile_for(ti, tj, [&](int r, int i, int j) {
+                    v4_t<T> acc = mma<NU, true, false>(zero4<T>(), S.Y(), NX, S.Y(), NX, ti, tj);
+                    tile_for<T>(ti, tj, [&](int r, int i, int j) {
                         if (ti != tj || i >= j) {
-                            const double v = S.F()[i * NX + j] - acc[r];
+                            const T v = S.F()[i * NX + j] - acc[r];
                             S.P[i * NX + j] = v;
                             S.P[j * NX + i] = v;
                             if constexpr (PEMIT) {
@@ -463,17 +496,17 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                     if constexpr (RED) {
                         int ti, tj;
                         lower_tile(t - TL, ti, tj);
-                        d4 acc = mma<NU, true, false>(zero4(), S.X, NX, S.X, NX, ti, tj);
-                        tile_for(ti, tj, [&](int r, int i, int j) {
+                        v4_t<T> acc = mma<NU, true, false>(zero4<T>(), S.X, NX, S.X, NX, ti, tj);
+                        tile_for<T>(ti, tj, [&](int r, int i, int j) {
                             put_sym(S.Qh, NX, ti, tj, i, j, S.Qh[i * NX + j] + acc[r]);
                         });
                     }
                 } else if (t < TL + TQ + TV) {
                     if constexpr (RED) {
                         const int u = t - TL - TQ, ti = u / TX, tj = u % TX;
-                        d4 acc = mma<NU, true, false>(zero4(), S.Y(), NX, S.X, NX, ti, tj);
-                        tile_for(ti, tj, [&](int r, int i, int j) {
-                            const double v = S.W[i * NX + j] - acc[r];
+                        v4_t<T> acc = mma<NU, true, false>(zero4<T>(), S.Y(), NX, S.X, NX, ti, tj);
+                        tile_for<T>(ti, tj, [&](int r, int i, int j) {
+                            const T v = S.W[i * NX + j] - acc[r];
                             S.V[i * NX + j] = v;
                             if constexpr (Out::VF) out.V(s, i, j, v);
                         });
@@ -481,35 +514,35 @@ __device__ void mfma_pass(MSmem<NX, NU, RED, SOLVE> &S, Get get, int count, int3
                 } else {
                     if constexpr (KFORM) {
                         const int u = t - TL - TQ - TV, ti = u / TX, tj = u % TX;
-                        d4 acc = mma<NU, true, false>(zero4(), S.G, NU, S.Y(), NX, ti, tj);
-                        tile_for(ti, tj, [&](int r, int i, int j) { out.K(s, i, j, -acc[r]); });
+                        v4_t<T> acc = mma<NU, true, false>(zero4<T>(), S.G, NU, S.Y(), NX, ti, tj);
+                        tile_for<T>(ti, tj, [&](int r, int i, int j) { out.K(s, i, j, -acc[r]); });
                     }
                 }
             }
             if constexpr (Out::LF) out.L(s, S.G);
             if (VEC && tid >= 192 && tid < 192 + NX) {
                 const int i = tid - 192;
-                double acc = S.gx[i];
+                T acc = S.gx[i];
 #pragma unroll
                 for (int r = 0; r < NU; ++r) acc -= S.Y()[r * NX + i] * S.z[r];
                 S.Psi[i] = acc;
                 if constexpr (SOLVE) out.Psi(s, i, acc);
             } else if (VEC && RED && tid >= 128 && tid < 128 + NX) {
                 const int i = tid - 128;
-                double acc = S.Vta[i];
+                T acc = S.Vta[i];
 #pragma unroll
                 for (int r = 0; r < NU; ++r) acc += S.X[r * NX + i] * S.z[r];
                 S.v[i] += acc;
             } else if (VEC && SOLVE && tid >= 128 && tid < 128 + NU) {
                 const int i = tid - 128;
-                double acc = 0;
+                T acc = T(0);
 #pragma unroll
                 for (int r = 0; r < NU; ++r) acc += S.G[r * NU + i] * S.z[r];
                 S.kk[i] = acc;
                 out.k(s, i, acc);
             } else if (VEC && tid >= 64 && tid < 128) {
-                const double zz = wave_sum(l < NU ? S.z[l] * S.z[l] : 0.0);
-                if (l == 0) S.cbar -= 0.5 * zz;
+                const T zz = wave_sum(l < NU ? S.z[l] * S.z[l] : T(0));
+                if (l == 0) S.cbar -= T(0.5) * zz;
             }
             if (s > 0) commit_stage(S, pf);
         }

@@ -1,0 +1,288 @@
+// FP64 KKT residual and iterative refinement of the mixed-precision solve.
+//
+// KKT system of P(N) (Sec. 2; unknowns lam_0, x_0, w_0, lam_1, ..., lam_N,
+// x_N; the Lagrangian carries +lam_0'(xbar_0 - x_0) and
+// +lam_{t+1}'(A_t x_t + B_t w_t + a_t - x_{t+1})), right-hand side r:
+//   lam_0 row:      -x_0                                             = -xbar_0
+//   x_t row:        Qx x_t + Qxw w_t - lam_t + A' lam_{t+1}           = -lx_t
+//   w_t row:        Qxw' x_t + Qw w_t + B' lam_{t+1}                  = -lw_t
+//   lam_{t+1} row:  A x_t + B w_t - x_{t+1}                           = -a_t
+//   x_N row:        QxN x_N - lam_N                                   = -lN
+// The residual rho = r - K z is evaluated blockwise in FP64.  Since r depends
+// linearly on the problem's (xbar_0, lx, lw, a, lN) with a minus sign, the
+// correction K d = rho is the solve of the same problem with
+//   xbar_0' = x_0 - xbar_0,  lx' = lx + (Qx x + Qxw w - lam + A' lam+),
+//   lw' = lw + (Qxw' x + Qw w + B' lam+),  a' = a + (A x + B w - x+),
+//   lN' = lN + QxN x_N - lam_N,  c' = 0,
+// i.e. exactly (-rho) arranged as problem data.  The residual kernel writes
+// these into the correction problem and, from the same reads, the objective
+// of the current iterate.
+//   kr_residual  per leaf (4 wavefronts, stages round-robin): correction data,
+//                max |r|, max |rho| and the objective part of the leaf
+//   kr_update    per leaf: z += d; max |d| and max |z| per block (x, w, lam)
+//   kr_check     per instance: reduces the leaf parts in a fixed order;
+//                decides convergence, writes the statistics, the objective
+//                and RS_ERR_NOT_CONVERGED
+#include <hip/hip_runtime.h>
+
+#include "rs_launch.hpp"
+#include "rs_vec.hpp"
+
+namespace rs {
+namespace sv {
+
+constexpr int RT = 256;   // 4 wavefronts per leaf
+
+// Orders the LDS traffic of one wavefront (each wavefront of the residual
+// kernel works on its own stages and LDS vectors, so no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int NX, int NU>
+struct RSmem {
+    double x[4][NX], w[4][NU], ln[4][NX];
+    double red[4][3];
+};
+
+template <int NX, int NU>
+__global__ void __launch_bounds__(RT) kr_residual(GroupArgs g) {
+    __shared__ RSmem<NX, NU> S;
+    const LeafItem it = load_leaf(g.leaves, blockIdx.x);
+    if (skip_inst(g, it.inst)) return;
+    const Prob p = load_prob(g.probs, it.inst);
+    const Prob c = load_prob(g.corr, it.inst);
+    const int wv = (int)(threadIdx.x >> 6), l = lane();
+    double rhs = 0.0, res = 0.0, obj = 0.0;
+    double *xs = S.x[wv], *ws = S.w[wv], *ls = S.ln[wv];
+    const int len = uni(it.len);
+    for (int s = wv; s < len; s += 4) {
+        const int t = it.t0 + s;
+        const double *x = p.x + (int64_t)t * NX, *xn = x + NX, *w = p.w + (int64_t)t * NU;
+        const double *lam = p.lam + (int64_t)t * NX, *lamn = lam + NX;
+        const double *Qx = p.Qx + (int64_t)t * p.sQx, *Qw = p.Qw + (int64_t)t * p.sQw;
+        const double *Qxw = p.Qxw ? p.Qxw + (int64_t)t * p.sQxw : nullptr;
+        const double *A = p.A + (int64_t)t * p.sA, *B = p.B + (int64_t)t * p.sB;
+        Op<NX, NX> oQx, oAT, oA;
+        Op<NX, NU> oQxw, oB;
+        Op<NU, NX> oQxwT, oBT;
+        Op<NU, NU> oQw;
+        oQx.template load<false>(Qx, NX);
+        oAT.template load<false>(A, NX);
+        oA.template load<true>(A, NX);
+        oQxw.template load<true>(Qxw, NU);
+        oB.template load<true>(B, NU);
+        oQxwT.template load<false>(Qxw, NU);
+        oBT.template load<false>(B, NU);
+        oQw.template load<false>(Qw, NU);
+        const double xi = l < NX ? x[l] : 0.0, wi = l < NU ? w[l] : 0.0;
+        const double lami = l < NX ? lam[l] : 0.0, xni = l < NX ? xn[l] : 0.0;
+        const double lxi = (l < NX && p.lx) ? p.lx[(int64_t)t * NX + l] : 0.0;
+        const double lwi = (l < NU && p.lw) ? p.lw[(int64_t)t * NU + l] : 0.0;
+        const double ai = (l < NX && p.a) ? p.a[(int64_t)t * NX + l] : 0.0;
+        const double ct = p.c ? p.c[t] : 0.0;
+        if (l < NX) {
+            xs[l] = xi;
+            ls[l] = lamn[l];
+        }
+        if (l < NU) ws[l] = wi;
+        wave_sync();
+        const double qx = oQx.apply(xs), qxw = oQxw.apply(ws), atl = oAT.apply(ls);
+        const double ax = oA.apply(xs), bw = oB.apply(ws);
+        const double qxwt = oQxwT.apply(xs), qw = oQw.apply(ws), btl = oBT.apply(ls);
+        wave_sync();
+        double part = 0.0;
+        if (l < NX) {
+            const double dlx = lxi + qx + qxw - lami + atl;
+            const double da = ai + ax + bw - xni;
+            const_cast<double *>(c.lx)[(int64_t)t * NX + l] = dlx;
+            const_cast<double *>(c.a)[(int64_t)t * NX + l] = da;
+            rhs = fmax(rhs, fmax(fabs(lxi), fabs(ai)));
+            res = fmax(res, fmax(fabs(dlx), fabs(da)));
+            part += xi * (0.5 * qx + qxw + lxi);
+        }
+        if (l < NU) {
+            const double dlw = lwi + qxwt + qw + btl;
+            const_cast<double *>(c.lw)[(int64_t)t * NU + l] = dlw;
+            rhs = fmax(rhs, fabs(lwi));
+            res = fmax(res, fabs(dlw));
+            part += wi * (0.5 * qw + lwi);
+        }
+        obj += wave_sum(part) + ct;
+    }
+    if (wv == 0 && it.t0 == 0) {            // lam_0 row
+        if (l < NX) {
+            const double d0 = p.x[l] - p.x0[l];
+            const_cast<double *>(c.x0)[l] = d0;
+            rhs = fmax(rhs, fabs(p.x0[l]));
+            res = fmax(res, fabs(d0));
+        }
+    }
+    if (wv == 1 && (it.flags & LEAF_LAST)) {   // x_N row and the terminal cost
+        const int64_t N = it.t0 + len;
+        const double *x = p.x + N * NX, *lam = p.lam + N * NX;
+        Op<NX, NX> oQ;
+        oQ.template load<false>(p.QxN, NX);
+        if (l < NX) xs[l] = x[l];
+        wave_sync();
+        const double qx = oQ.apply(xs);
+        double part = 0.0;
+        if (l < NX) {
+            const double lNi = p.lN ? p.lN[l] : 0.0;
+            const double dN = lNi + qx - lam[l];
+            const_cast<double *>(c.lN)[l] = dN;
+            rhs = fmax(rhs, fabs(lNi));
+            res = fmax(res, fabs(dN));
+            part = x[l] * (0.5 * qx + lNi);
+        }
+        obj += wave_sum(part) + (p.cN ? p.cN[0] : 0.0);
+    }
+    rhs = wave_max(rhs);
+    res = wave_max(res);
+    if (l == 0) {
+        S.red[wv][0] = rhs;
+        S.red[wv][1] = res;
+        S.red[wv][2] = obj;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double* out = g.part + (int64_t)(g.leaf_base + blockIdx.x) * PART_N;
+        double a = 0.0, b = 0.0, o = 0.0;
+        for (int q = 0; q < 4; ++q) {
+            a = fmax(a, S.red[q][0]);
+            b = fmax(b, S.red[q][1]);
+            o += S.red[q][2];
+        }
+        out[PART_RHS] = a;
+        out[PART_RES] = b;
+        out[PART_OBJ] = o;
+    }
+}
+
+// z += d over the leaf's stages (and x_N, lam_N for the last leaf).
+template <int NX, int NU>
+__global__ void __launch_bounds__(RT) kr_update(GroupArgs g) {
+    __shared__ double red[4][6];
+    const LeafItem it = load_leaf(g.leaves, blockIdx.x);
+    if (skip_inst(g, it.inst)) return;
+    const Prob p = load_prob(g.probs, it.inst);
+    const Prob c = load_prob(g.corr, it.inst);
+    const int tid = threadIdx.x, wv = tid >> 6, l = lane();
+    const int nst = uni(it.len) + ((it.flags & LEAF_LAST) ? 1 : 0);   // x, lam entries
+    double m[6] = {0, 0, 0, 0, 0, 0};
+    {
+        const int64_t b0 = (int64_t)it.t0 * NX, n = (int64_t)nst * NX;
+        for (int64_t e = tid; e < n; e += RT) {
+            const double dx = c.x[b0 + e], dl = c.lam[b0 + e];
+            const double xv = p.x[b0 + e] + dx, lv = p.lam[b0 + e] + dl;
+            p.x[b0 + e] = xv;
+            p.lam[b0 + e] = lv;
+            m[0] = fmax(m[0], fabs(dx));
+            m[2] = fmax(m[2], fabs(dl));
+            m[3] = fmax(m[3], fabs(xv));
+            m[5] = fmax(m[5], fabs(lv));
+        }
+    }
+    {
+        const int64_t b0 = (int64_t)it.t0 * NU, n = (int64_t)it.len * NU;
+        for (int64_t e = tid; e < n; e += RT) {
+            const double dw = c.w[b0 + e];
+            const double wv2 = p.w[b0 + e] + dw;
+            p.w[b0 + e] = wv2;
+            m[1] = fmax(m[1], fabs(dw));
+            m[4] = fmax(m[4], fabs(wv2));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) m[q] = wave_max(m[q]);
+    if (l == 0)
+        for (int q = 0; q < 6; ++q) red[wv][q] = m[q];
+    __syncthreads();
+    if (tid < 6) {
+        double v = 0.0;
+        for (int q = 0; q < 4; ++q) v = fmax(v, red[q][tid]);
+        g.part[(int64_t)(g.leaf_base + blockIdx.x) * PART_N + PART_DX + tid] = v;
+    }
+}
+
+// mode 0: start of a refinement (conv = status != OK, statistics cleared);
+// mode 1: after an update (correction size, convergence);
+// mode 2: final (relative residual, objective, status).
+__global__ void kr_check(const InstInfo *tab, int count, const double *part, double *stats, int32_t *conv,
+                         int32_t *info, const DevProb *probs, int mode, double tol) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double *st = stats + (int64_t)i * ST_N;
+    if (mode == 0) {
+        conv[i] = info[2 * i] != STATUS_OK ? 1 : 0;
+        for (int q = 0; q < ST_N; ++q) st[q] = 0.0;
+        st[ST_DZ] = 1.0;
+        return;
+    }
+    const InstInfo in = tab[i];
+    const double *pp = part + (int64_t)in.first_leaf * PART_N;
+    if (mode == 1) {
+        if (conv[i]) return;
+        double d[3] = {0, 0, 0}, z[3] = {0, 0, 0};
+        for (int lf = 0; lf < in.nleaves; ++lf)
+            for (int b = 0; b < 3; ++b) {
+                d[b] = fmax(d[b], pp[lf * PART_N + PART_DX + b]);
+                z[b] = fmax(z[b], pp[lf * PART_N + PART_X + b]);
+            }
+        double dz = 0.0;
+        for (int b = 0; b < 3; ++b) dz = fmax(dz, z[b] > 0.0 ? d[b] / z[b] : d[b]);
+        st[ST_DZ] = dz;
+        st[ST_ITERS] += 1.0;
+        if (dz <= 0.1 * tol) conv[i] = 1;
+        return;
+    }
+    double rhs = 0.0, res = 0.0, obj = 0.0;
+    for (int lf = 0; lf < in.nleaves; ++lf) {
+        rhs = fmax(rhs, pp[lf * PART_N + PART_RHS]);
+        res = fmax(res, pp[lf * PART_N + PART_RES]);
+        obj += pp[lf * PART_N + PART_OBJ];
+    }
+    const double rres = rhs > 0.0 ? res / rhs : res;
+    st[ST_RRES] = rres;
+    st[ST_CONV] = conv[i] ? 1.0 : 0.0;
+    if (probs[i].obj) probs[i].obj[0] = obj;
+    if (info[2 * i] == STATUS_OK && (!conv[i] || !(rres <= tol))) {
+        info[2 * i] = STATUS_NOT_CONVERGED;
+        info[2 * i + 1] = -1;
+    }
+}
+
+template <int NX, int NU>
+hipError_t launch_residual(const GroupArgs &g, int, hipStream_t st) {
+    hipLaunchKernelGGL((kr_residual<NX, NU>), dim3(g.nleaves), dim3(RT), 0, st, g);
+    return hipGetLastError();
+}
+template <int NX, int NU>
+hipError_t launch_update(const GroupArgs &g, int, hipStream_t st) {
+    hipLaunchKernelGGL((kr_update<NX, NU>), dim3(g.nleaves), dim3(RT), 0, st, g);
+    return hipGetLastError();
+}
+
+}  // namespace sv
+
+// which: 0 residual, 1 update.
+Launcher refine_kernel(int nx, int nu, int which) {
+#define RS_REF(a, b)                                                                   \
+    if (nx == a && nu == b) return which == 0 ? &sv::launch_residual<a, b> : &sv::launch_update<a, b>;
+    RS_REF(16, 16)
+    RS_REF(32, 16)
+    RS_REF(32, 32)
+#undef RS_REF
+    return nullptr;
+}
+
+hipError_t launch_refine_check(const InstInfo *tab, int count, const double *part, double *stats, int32_t *conv,
+                               int32_t *info, const DevProb *probs, int mode, double tol, hipStream_t st) {
+    hipLaunchKernelGGL(sv::kr_check, dim3((count + 63) / 64), dim3(64), 0, st, tab, count, part, stats, conv, info,
+                       probs, mode, tol);
+    return hipGetLastError();
+}
+
+}  // namespace rs

@@ -25,69 +25,10 @@
 #include <hip/hip_runtime.h>
 
 #include "rs_launch.hpp"
+#include "rs_vec.hpp"
 
 namespace rs {
 namespace sv {
-
-constexpr int WT = 64;
-constexpr int SPIN_LIMIT = 1 << 26;
-
-__device__ __forceinline__ int lane() { return (int)threadIdx.x; }
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ const double *uni_ptr(const double *q) {
-    const uint64_t v = (uint64_t)q;
-    const uint32_t lo = (uint32_t)uni((int)(uint32_t)(v & 0xffffffffu)), hi = (uint32_t)uni((int)(uint32_t)(v >> 32));
-    return (const double *)(((uint64_t)hi << 32) | lo);
-}
-__device__ __forceinline__ double *uni_ptr(double *q) { return const_cast<double *>(uni_ptr((const double *)q)); }
-__device__ __forceinline__ int64_t uni64(int64_t v) {
-    return ((int64_t)uni((int)(v >> 32)) << 32) | (uint32_t)uni((int)(v & 0xffffffff));
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Matrix operand of one product y = M x with R outputs and C inputs, held in
-// registers.  The wavefront is split into 64 / Rp parts (Rp = R rounded up to
-// a power of two); part p sums the contiguous input range
-// [p*CH, (p+1)*CH) and the parts are combined with lane shuffles.
-//   COL: M(i, k) = M[k*ld + i]  (lanes of a part read consecutive words)
-//   ROW: M(i, k) = M[i*ld + k]
-template <int R, int C>
-struct Op {
-    static constexpr int Rp = R <= 1 ? 1 : R <= 2 ? 2 : R <= 4 ? 4 : R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 64;
-    static constexpr int SP = 64 / Rp, CH = (C + SP - 1) / SP;
-    static_assert(R <= 64, "at most 64 outputs");
-    double m[CH];
-
-    template <bool ROW>
-    __device__ __forceinline__ void load(const double *M, int ld) {
-        const int l = lane(), i = l % Rp, p = l / Rp;
-#pragma unroll
-        for (int q = 0; q < CH; ++q) {
-            const int k = p * CH + q;
-            m[q] = (M && i < R && k < C) ? (ROW ? M[i * ld + k] : M[k * ld + i]) : 0.0;
-        }
-    }
-    // y_i in every lane with lane % Rp == i (meaningful for i < R).
-    __device__ __forceinline__ double apply(const double *x) const {
-        const int p = lane() / Rp;
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < CH; ++q) {
-            const int k = p * CH + q;
-            if (k < C) acc += m[q] * x[k];
-        }
-#pragma unroll
-        for (int o = Rp; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
-        return acc;
-    }
-};
-
-__device__ __forceinline__ void wsync() { __syncthreads(); }   // one-wavefront workgroups
 
 // LDS vectors of one work unit.
 template <int NX, int NU>
@@ -97,13 +38,17 @@ struct VSmem {
     double v[NX];
 };
 
-// Where a backward stage's operands live.
+// Where a backward stage's operands live.  Stored factors are of type TR
+// (double, or float for mixed-precision leaves); a P_{t+1} that comes from
+// the problem or a parent's message is FP64 (Pn64).
+template <class TR>
 struct VSrc {
-    const double *Pn;      // P_{t+1}, symmetric; nullptr = 0 (Alg. 4 preliminary terminal)
-    const double *Vn;      // V_{t+1}; nullptr = identity (Alg. 4 only)
+    const TR *Pn;          // P_{t+1}, symmetric
+    const double *Pn64;    // used when Pn is null; both null = 0 (Alg. 4 preliminary terminal)
+    const TR *Vn;          // V_{t+1}; nullptr = identity (Alg. 4 only)
+    const TR *Li, *LT;     // L^{-1}, L^{-T}, row-major NU x NU
+    const TR *K;           // NU x NX row-major
     const double *A, *B;   // dynamics (B: NX x NU row-major)
-    const double *Li, *LT; // L^{-1}, L^{-T}, row-major NU x NU
-    const double *K;       // NU x NX row-major
     const double *a, *lx, *lw;
     double c;
 };
@@ -111,14 +56,17 @@ struct VSrc {
 // One backward stage of the vector recursion.  Psi, cbar (and v for RED) are
 // the running state; Psi_t and k_{t+1} are returned in LDS (S.Psi, S.kk) and
 // handed to emit(Psi_i, k_i) from lanes i < NX / i < NU.
-template <int NX, int NU, bool RED, bool WANTK, class Emit>
-__device__ __forceinline__ void vstage(VSmem<NX, NU> &S, const VSrc &q, double &cbar, Emit emit) {
+template <int NX, int NU, bool RED, bool WANTK, class TR, class Emit>
+__device__ __forceinline__ void vstage(VSmem<NX, NU> &S, const VSrc<TR> &q, double &cbar, Emit emit) {
     const int l = lane();
     Op<NX, NX> oP, oA, oV;
     Op<NU, NX> oB;
     Op<NU, NU> oLT, oLi;
     Op<NX, NU> oK, oBr;
-    oP.template load<false>(q.Pn, NX);
+    if (q.Pn)
+        oP.template load<false>(q.Pn, NX);
+    else
+        oP.template load<false>(q.Pn64, NX);
     oB.template load<false>(q.B, NU);
     oLT.template load<false>(q.LT, NU);
     oA.template load<false>(q.A, NX);
@@ -177,9 +125,9 @@ __device__ __forceinline__ void vstage(VSmem<NX, NU> &S, const VSrc &q, double &
 
 // One forward stage (Alg. 3): w = K x + k, x_{t+1} = A x + a + B w and, for
 // leaves, lam_t = P_t x - Psi_t.  Operands as in VSrc (ROW-read here).
-template <int NX, int NU, bool LAM>
-__device__ __forceinline__ void fstage(VSmem<NX, NU> &S, const double *K, const double *kvec, const double *A,
-                                       const double *B, const double *a, const double *P, const double *Psi,
+template <int NX, int NU, bool LAM, class TR>
+__device__ __forceinline__ void fstage(VSmem<NX, NU> &S, const TR *K, const double *kvec, const double *A,
+                                       const double *B, const double *a, const TR *P, const double *Psi,
                                        double &lam_out, double &w_out) {
     const int l = lane();
     Op<NU, NX> oK;
@@ -205,8 +153,8 @@ __device__ __forceinline__ void fstage(VSmem<NX, NU> &S, const double *K, const 
 }
 
 // 1/2 x'Px - Psi'x + cbar (value of the cost to go at x).
-template <int NX, int NU>
-__device__ __forceinline__ double cost_to_go(const VSmem<NX, NU> &S, const double *P, double cbar) {
+template <int NX, int NU, class TP>
+__device__ __forceinline__ double cost_to_go(const VSmem<NX, NU> &S, const TP *P, double cbar) {
     const int l = lane();
     Op<NX, NX> oP;
     oP.template load<false>(P, NX);
@@ -215,18 +163,6 @@ __device__ __forceinline__ double cost_to_go(const VSmem<NX, NU> &S, const doubl
     return wave_sum(part) + cbar;
 }
 
-__device__ __forceinline__ LeafItem load_leaf(const LeafItem *tab, int i) {
-    const LeafItem r = tab[i];
-    LeafItem u;
-    u.inst = uni(r.inst);
-    u.t0 = uni(r.t0);
-    u.len = uni(r.len);
-    u.flags = uni(r.flags);
-    u.slot = uni(r.slot);
-    u.pad = 0;
-    u.scratch = uni64(r.scratch);
-    return u;
-}
 __device__ __forceinline__ TreeItem load_item(const TreeItem *tab, int i) {
     const TreeItem r = tab[i];
     TreeItem u;
@@ -243,36 +179,12 @@ __device__ __forceinline__ TreeItem load_item(const TreeItem *tab, int i) {
     return u;
 }
 
-struct Prob {
-    const double *A, *B, *QxN, *x0, *a, *lx, *lw, *c, *lN, *cN;
-    double *x, *w, *lam, *obj;
-    int64_t sA, sB;
-};
-__device__ __forceinline__ Prob load_prob(const DevProb *tab, int i) {
-    const DevProb &d = tab[i];
-    Prob p;
-    p.A = uni_ptr(d.A);
-    p.B = uni_ptr(d.B);
-    p.QxN = uni_ptr(d.QxN);
-    p.x0 = uni_ptr(d.x0);
-    p.a = uni_ptr(d.a);
-    p.lx = uni_ptr(d.lx);
-    p.lw = uni_ptr(d.lw);
-    p.c = uni_ptr(d.c);
-    p.lN = uni_ptr(d.lN);
-    p.cN = uni_ptr(d.cN);
-    p.x = uni_ptr(d.x);
-    p.w = uni_ptr(d.w);
-    p.lam = uni_ptr(d.lam);
-    p.obj = uni_ptr(d.obj);
-    p.sA = uni64(d.sA);
-    p.sB = uni64(d.sB);
-    return p;
-}
-
-template <int NX, int NU>
-__device__ __forceinline__ VSrc prob_src(const Prob &p, int t) {
-    VSrc q;
+template <int NX, int NU, class TR>
+__device__ __forceinline__ VSrc<TR> prob_src(const Prob &p, int t) {
+    VSrc<TR> q;
+    q.Pn = nullptr;
+    q.Pn64 = nullptr;
+    q.Vn = nullptr;
     q.A = p.A + (int64_t)t * p.sA;
     q.B = p.B + (int64_t)t * p.sB;
     q.a = p.a ? p.a + (int64_t)t * NX : nullptr;
@@ -283,9 +195,12 @@ __device__ __forceinline__ VSrc prob_src(const Prob &p, int t) {
 }
 
 template <int NX>
-__device__ __forceinline__ VSrc slot_src(const double *sl) {
+__device__ __forceinline__ VSrc<double> slot_src(const double *sl) {
     const SlotLayout L{NX};
-    VSrc q;
+    VSrc<double> q;
+    q.Pn = nullptr;
+    q.Pn64 = nullptr;
+    q.Vn = nullptr;
     q.A = sl + L.A();
     q.B = sl + L.Qw();
     q.a = sl + L.a();
@@ -296,15 +211,15 @@ __device__ __forceinline__ VSrc slot_src(const double *sl) {
 }
 
 // ------------------------------------------------------------------ leaves
-template <int NX, int NU>
+template <int NX, int NU, class TR>
 __global__ void __launch_bounds__(WT) kv_leaf_up(GroupArgs g) {
     __shared__ VSmem<NX, NU> S;
     const LeafItem it = load_leaf(g.leaves, blockIdx.x);
-    if (it.flags & LEAF_TOP) return;
+    if ((it.flags & LEAF_TOP) || skip_inst(g, it.inst)) return;
     const Prob p = load_prob(g.probs, it.inst);
     const LeafRec R{NX, NU};
     const SlotLayout SL{NX};
-    const double *rec = g.fstore + (it.scratch / g.sps) * (int64_t)R.per_stage();
+    const TR *rec = reinterpret_cast<const TR *>(g.fstore) + (it.scratch / g.sps) * (int64_t)R.per_stage();
     double *out = g.slots + (int64_t)it.slot * SL.size();
     const int l = lane();
     const bool last = (it.flags & LEAF_LAST) != 0;
@@ -316,9 +231,9 @@ __global__ void __launch_bounds__(WT) kv_leaf_up(GroupArgs g) {
     wsync();
     auto none = [](double, double) {};
     for (int s = uni(it.len) - 1; s >= 0; --s) {
-        VSrc q = prob_src<NX, NU>(p, it.t0 + s);
-        const double *r = rec + (int64_t)s * R.per_stage();
-        const double *rn = r + R.per_stage();
+        VSrc<TR> q = prob_src<NX, NU, TR>(p, it.t0 + s);
+        const TR *r = rec + (int64_t)s * R.per_stage();
+        const TR *rn = r + R.per_stage();
         const bool end = s + 1 == it.len;
         q.Li = r + R.L();
         q.LT = r + R.LT();
@@ -328,8 +243,8 @@ __global__ void __launch_bounds__(WT) kv_leaf_up(GroupArgs g) {
             q.Vn = end ? nullptr : rn + R.V();
             vstage<NX, NU, true, false>(S, q, cbar, none);
         } else {
-            q.Pn = end ? p.QxN : rn + R.P();
-            q.Vn = nullptr;
+            q.Pn = end ? nullptr : rn + R.P();
+            q.Pn64 = end ? p.QxN : nullptr;
             vstage<NX, NU, false, false>(S, q, cbar, none);
         }
     }
@@ -340,14 +255,17 @@ __global__ void __launch_bounds__(WT) kv_leaf_up(GroupArgs g) {
     if (l == 0) out[SL.c()] = cbar;
 }
 
-template <int NX, int NU>
+template <int NX, int NU, class TR>
 __global__ void __launch_bounds__(WT) kv_leaf_down(GroupArgs g) {
     __shared__ VSmem<NX, NU> S;
     const LeafItem it = load_leaf(g.leaves, blockIdx.x);
+    if (skip_inst(g, it.inst)) return;
     const Prob p = load_prob(g.probs, it.inst);
     const LeafRec R{NX, NU};
     const SlotLayout SL{NX};
-    double *rec = g.fstore + (it.scratch / g.sps) * (int64_t)R.per_stage();
+    const int64_t stage0 = it.scratch / g.sps;
+    const TR *rec = reinterpret_cast<const TR *>(g.fstore) + stage0 * (int64_t)R.per_stage();
+    double *vec0 = g.fvec + stage0 * (int64_t)R.vec();
     const int l = lane();
     const bool known_end = (it.flags & (LEAF_LAST | LEAF_TOP)) != 0;
     const double *msg = (it.flags & LEAF_TOP) ? nullptr : g.slots + (int64_t)it.slot * SL.size();
@@ -360,15 +278,15 @@ __global__ void __launch_bounds__(WT) kv_leaf_down(GroupArgs g) {
     wsync();
     const int len = uni(it.len);
     for (int s = len - 1; s >= 0; --s) {
-        VSrc q = prob_src<NX, NU>(p, it.t0 + s);
-        double *r = rec + (int64_t)s * R.per_stage();
-        const double *dn = r + R.up();
-        q.Pn = s + 1 == len ? Pend : rec + (int64_t)(s + 1) * R.per_stage() + R.up() + R.P();
-        q.Vn = nullptr;
+        VSrc<TR> q = prob_src<NX, NU, TR>(p, it.t0 + s);
+        const TR *dn = rec + (int64_t)s * R.per_stage() + R.up();
+        const bool end = s + 1 == len;
+        q.Pn = end ? nullptr : dn + R.per_stage() + R.P();
+        q.Pn64 = end ? Pend : nullptr;
         q.Li = dn + R.L();
         q.LT = dn + R.LT();
         q.K = dn + R.K();
-        double *vec = r + R.up() + R.down();
+        double *vec = vec0 + (int64_t)s * R.vec();
         vstage<NX, NU, false, true>(S, q, cbar, [&](double psi, double k) {
             if (l < NX) vec[l] = psi;
             if (l < NU) vec[NX + l] = k;
@@ -381,8 +299,8 @@ __global__ void __launch_bounds__(WT) kv_leaf_down(GroupArgs g) {
     wsync();
     for (int s = 0; s < len; ++s) {
         const int t = it.t0 + s;
-        const double *r = rec + (int64_t)s * R.per_stage();
-        const double *dn = r + R.up(), *vec = dn + R.down();
+        const TR *dn = rec + (int64_t)s * R.per_stage() + R.up();
+        const double *vec = vec0 + (int64_t)s * R.vec();
         double lam = 0.0, w = 0.0;
         if (l < NX) p.x[(int64_t)t * NX + l] = S.x[l];
         fstage<NX, NU, true>(S, dn + R.K(), vec + NX, p.A + (int64_t)t * p.sA, p.B + (int64_t)t * p.sB,
@@ -436,7 +354,9 @@ __global__ void __launch_bounds__(WT) kv_tree(GroupArgs g) {
         wsync();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const int count = it.count;
-        if (it.kind == ITEM_UP || it.kind == ITEM_UP_LAST) {
+        if (skip_inst(g, it.inst)) {
+            // converged: nothing to do (its dependents belong to the same instance)
+        } else if (it.kind == ITEM_UP || it.kind == ITEM_UP_LAST) {
             const bool red = it.kind == ITEM_UP;
             const double *term = red ? nullptr : slot(it.term_slot);
             if (l < NX) {
@@ -448,7 +368,7 @@ __global__ void __launch_bounds__(WT) kv_tree(GroupArgs g) {
             auto none = [](double, double) {};
             for (int s = count - 1; s >= 0; --s) {
                 const double *sl = slot(it.first + s);
-                VSrc q = slot_src<NX>(sl);
+                VSrc<double> q = slot_src<NX>(sl);
                 const double *sn = slot(it.first + s + 1);
                 const bool end = s + 1 == count;
                 q.Li = sl + SL.uL();
@@ -486,7 +406,7 @@ __global__ void __launch_bounds__(WT) kv_tree(GroupArgs g) {
                 // message to child s: cost to go at the end of master stage s
                 if (l < NX) sl[SL.Psi() + l] = S.Psi[l];
                 if (l == 0) sl[SL.cb()] = cbar;
-                VSrc q = slot_src<NX>(sl);
+                VSrc<double> q = slot_src<NX>(sl);
                 q.Pn = sl + SL.P();
                 q.Vn = nullptr;
                 q.Li = sl + SL.dL();
@@ -505,8 +425,8 @@ __global__ void __launch_bounds__(WT) kv_tree(GroupArgs g) {
                 double *sl = slot(it.first + s);
                 if (l < NX) sl[SL.xh() + l] = S.x[l];
                 double lam, w;
-                fstage<NX, NX, false>(S, sl + SL.K(), sl + SL.k(), sl + SL.A(), sl + SL.Qw(), sl + SL.a(), nullptr,
-                                      nullptr, lam, w);
+                fstage<NX, NX, false, double>(S, sl + SL.K(), sl + SL.k(), sl + SL.A(), sl + SL.Qw(), sl + SL.a(),
+                                              nullptr, nullptr, lam, w);
             }
             if (it.last && l < NX) slot(it.term_slot)[SL.xh() + l] = S.x[l];
         }
@@ -517,9 +437,9 @@ __global__ void __launch_bounds__(WT) kv_tree(GroupArgs g) {
     }
 }
 
-template <int NX, int NU>
+template <int NX, int NU, class TR>
 hipError_t launch_up(const GroupArgs &g, int, hipStream_t st) {
-    hipLaunchKernelGGL((kv_leaf_up<NX, NU>), dim3(g.nleaves), dim3(WT), 0, st, g);
+    hipLaunchKernelGGL((kv_leaf_up<NX, NU, TR>), dim3(g.nleaves), dim3(WT), 0, st, g);
     return hipGetLastError();
 }
 template <int NX>
@@ -527,20 +447,21 @@ hipError_t launch_tree(const GroupArgs &g, int grid, hipStream_t st) {
     hipLaunchKernelGGL((kv_tree<NX>), dim3(grid), dim3(WT), 0, st, g);
     return hipGetLastError();
 }
-template <int NX, int NU>
+template <int NX, int NU, class TR>
 hipError_t launch_down(const GroupArgs &g, int, hipStream_t st) {
-    hipLaunchKernelGGL((kv_leaf_down<NX, NU>), dim3(g.nleaves), dim3(WT), 0, st, g);
+    hipLaunchKernelGGL((kv_leaf_down<NX, NU, TR>), dim3(g.nleaves), dim3(WT), 0, st, g);
     return hipGetLastError();
 }
 
 }  // namespace sv
 
-Launcher vector_solve(int nx, int nu, int which) {
+// which: 0 leaf up, 1 tree, 2 leaf down; fp32: the leaf records are FP32.
+Launcher vector_solve(int nx, int nu, int which, bool fp32) {
 #define RS_VEC(a, b)                                                                   \
     if (nx == a && nu == b) {                                                          \
-        if (which == 0) return &sv::launch_up<a, b>;                                   \
         if (which == 1) return &sv::launch_tree<a>;                                    \
-        return &sv::launch_down<a, b>;                                                 \
+        if (which == 0) return fp32 ? &sv::launch_up<a, b, float> : &sv::launch_up<a, b, double>; \
+        return fp32 ? &sv::launch_down<a, b, float> : &sv::launch_down<a, b, double>; \
     }
     RS_VEC(16, 16)
     RS_VEC(32, 16)

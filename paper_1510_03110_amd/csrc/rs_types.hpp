@@ -5,6 +5,9 @@
 
 namespace rs {
 
+// Status words written by the kernels (values of rs_status in rs.h).
+constexpr int32_t STATUS_OK = 0, STATUS_NOT_SPD = 2, STATUS_SINGULAR_MASTER = 3, STATUS_NOT_CONVERGED = 4;
+
 // Device copy of one problem descriptor (pointers are device pointers).
 struct DevProb {
     const double *Qx, *Qw, *Qxw, *A, *B, *QxN;
@@ -72,12 +75,14 @@ struct SlotLayout {
     __host__ __device__ int size() const { return ((12 * n * n + 5 * n + 2) + 7) & ~7; }
 };
 
-// Stored factorization of one leaf stage (factor / solve split), doubles:
+// Stored factorization of one leaf stage (factor / solve split), in the
+// factor precision (FP64, or FP32 in mixed-precision plans):
 //   up record (Alg. 4 or last-leaf elimination): P_after | L^{-1} | L^{-T} | K | V_after
 //   down record (Alg. 1 with the true terminal):  P_after | L^{-1} | L^{-T} | K
-//   down-pass vectors written by the solve:       Psi_after | k
 // P_after / V_after are the values after the stage (P_t, V_t), L^{-1} is the
-// inverse Cholesky factor of G_{t+1} and K = K_{t+1}.
+// inverse Cholesky factor of G_{t+1} and K = K_{t+1}.  The down-pass vectors
+// of a solve (Psi_t | k_{t+1}, nx + nu doubles per stage) live in a separate
+// FP64 array.
 struct LeafRec {
     int nx, nu;
     __host__ __device__ int P() const { return 0; }
@@ -87,9 +92,24 @@ struct LeafRec {
     __host__ __device__ int V() const { return nx * nx + 2 * nu * nu + nu * nx; }
     __host__ __device__ int up() const { return 2 * nx * nx + 2 * nu * nu + nu * nx; }
     __host__ __device__ int down() const { return nx * nx + 2 * nu * nu + nu * nx; }
+    __host__ __device__ int per_stage() const { return up() + down(); }
     __host__ __device__ int vec() const { return nx + nu; }
-    __host__ __device__ int per_stage() const { return up() + down() + vec(); }
 };
+
+// Per-instance entry of the refinement tables: the instance's leaves are
+// global leaf indices first_leaf .. first_leaf + nleaves - 1.
+struct InstInfo {
+    int32_t first_leaf, nleaves, nx, nu, N, pad;
+};
+
+// Per-leaf partial results of the refinement kernels (doubles):
+//   residual: max |r| (right-hand side), max |r - K z|, objective part
+//   update:   max |dx|, |dw|, |dlam|, max |x|, |w|, |lam| after the update
+enum { PART_RHS = 0, PART_RES = 1, PART_OBJ = 2, PART_DX = 3, PART_X = 6, PART_N = 9 };
+// Per-instance refinement statistics (doubles): relative residual of the
+// returned solution, last correction relative to the solution (forward
+// error estimate), corrections applied, converged flag.
+enum { ST_RRES = 0, ST_DZ = 1, ST_ITERS = 2, ST_CONV = 3, ST_N = 4 };
 
 // Everything a kernel launch of one shape group needs.
 struct GroupArgs {
@@ -105,7 +125,13 @@ struct GroupArgs {
     int32_t *info;          // per instance: status, stage
     int32_t epoch;
     int32_t sps;            // fused-solve scratch elements per stage (leaf stage index = scratch / sps)
-    double *fstore;         // stored factorization of the leaves (LeafRec per stage)
+    void *fstore;           // stored factorization of the leaves (LeafRec per stage, double or float)
+    double *fvec;           // down-pass vectors of the leaves (nx + nu doubles per stage)
+    // mixed-precision refinement (nullptr / 0 otherwise)
+    const DevProb *corr;    // correction problems: same matrices, RHS and outputs in the workspace
+    const int32_t *conv;    // per instance: 1 once converged (later passes skip it)
+    double *part;           // per global leaf: PART_N partial results
+    int32_t leaf_base;      // global index of this group's first leaf
 };
 
 }  // namespace rs

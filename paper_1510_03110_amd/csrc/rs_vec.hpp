@@ -1,0 +1,131 @@
+// Wavefront-level helpers of the matrix-vector kernels (stored-factor
+// solve, residual, refinement update): uniform loads, wave reductions and a
+// register-held matrix operand for y = M x.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "rs_types.hpp"
+
+namespace rs {
+namespace sv {
+
+constexpr int WT = 64;
+constexpr int SPIN_LIMIT = 1 << 26;
+
+__device__ __forceinline__ int lane() { return (int)(threadIdx.x & 63); }
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ const double *uni_ptr(const double *q) {
+    const uint64_t v = (uint64_t)q;
+    const uint32_t lo = (uint32_t)uni((int)(uint32_t)(v & 0xffffffffu)), hi = (uint32_t)uni((int)(uint32_t)(v >> 32));
+    return (const double *)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double *uni_ptr(double *q) { return const_cast<double *>(uni_ptr((const double *)q)); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+    return ((int64_t)uni((int)(v >> 32)) << 32) | (uint32_t)uni((int)(v & 0xffffffff));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Matrix operand of one product y = M x with R outputs and C inputs, held in
+// registers.  The wavefront is split into 64 / Rp parts (Rp = R rounded up to
+// a power of two); part p sums the contiguous input range
+// [p*CH, (p+1)*CH) and the parts are combined with lane shuffles.
+//   COL: M(i, k) = M[k*ld + i]  (lanes of a part read consecutive words)
+//   ROW: M(i, k) = M[i*ld + k]
+template <int R, int C>
+struct Op {
+    static constexpr int Rp = R <= 1 ? 1 : R <= 2 ? 2 : R <= 4 ? 4 : R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 64;
+    static constexpr int SP = 64 / Rp, CH = (C + SP - 1) / SP;
+    static_assert(R <= 64, "at most 64 outputs");
+    double m[CH];
+
+    template <bool ROW, class U>
+    __device__ __forceinline__ void load(const U *M, int ld) {
+        const int l = lane(), i = l % Rp, p = l / Rp;
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int k = p * CH + q;
+            m[q] = (M && i < R && k < C) ? (double)(ROW ? M[i * ld + k] : M[k * ld + i]) : 0.0;
+        }
+    }
+    // y_i in every lane with lane % Rp == i (meaningful for i < R).
+    __device__ __forceinline__ double apply(const double *x) const {
+        const int p = lane() / Rp;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int k = p * CH + q;
+            if (k < C) acc += m[q] * x[k];
+        }
+#pragma unroll
+        for (int o = Rp; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+        return acc;
+    }
+};
+
+__device__ __forceinline__ void wsync() { __syncthreads(); }
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ LeafItem load_leaf(const LeafItem *tab, int i) {
+    const LeafItem r = tab[i];
+    LeafItem u;
+    u.inst = uni(r.inst);
+    u.t0 = uni(r.t0);
+    u.len = uni(r.len);
+    u.flags = uni(r.flags);
+    u.slot = uni(r.slot);
+    u.pad = 0;
+    u.scratch = uni64(r.scratch);
+    return u;
+}
+
+// Problem descriptor in wave-uniform registers.
+struct Prob {
+    const double *Qx, *Qw, *Qxw, *A, *B, *QxN, *x0, *a, *lx, *lw, *c, *lN, *cN;
+    double *x, *w, *lam, *obj;
+    int64_t sQx, sQw, sQxw, sA, sB;
+};
+__device__ __forceinline__ Prob load_prob(const DevProb *tab, int i) {
+    const DevProb &d = tab[i];
+    Prob p;
+    p.Qx = uni_ptr(d.Qx);
+    p.Qw = uni_ptr(d.Qw);
+    p.Qxw = uni_ptr(d.Qxw);
+    p.A = uni_ptr(d.A);
+    p.B = uni_ptr(d.B);
+    p.QxN = uni_ptr(d.QxN);
+    p.x0 = uni_ptr(d.x0);
+    p.a = uni_ptr(d.a);
+    p.lx = uni_ptr(d.lx);
+    p.lw = uni_ptr(d.lw);
+    p.c = uni_ptr(d.c);
+    p.lN = uni_ptr(d.lN);
+    p.cN = uni_ptr(d.cN);
+    p.x = uni_ptr(d.x);
+    p.w = uni_ptr(d.w);
+    p.lam = uni_ptr(d.lam);
+    p.obj = uni_ptr(d.obj);
+    p.sQx = uni64(d.sQx);
+    p.sQw = uni64(d.sQw);
+    p.sQxw = uni64(d.sQxw);
+    p.sA = uni64(d.sA);
+    p.sB = uni64(d.sB);
+    return p;
+}
+
+// A converged instance (mixed-precision refinement) is skipped.
+__device__ __forceinline__ bool skip_inst(const GroupArgs &g, int inst) {
+    return g.conv && uni(g.conv[inst]) != 0;
+}
+
+}  // namespace sv
+}  // namespace rs

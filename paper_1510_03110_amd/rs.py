@@ -71,6 +71,8 @@ def library():
         lib.rs_plan_set_timing.restype = i32
         lib.rs_plan_kernel_times.argtypes = [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]
         lib.rs_plan_kernel_times.restype = i32
+        lib.rs_refine_stats.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_double), _P]
+        lib.rs_refine_stats.restype = i32
         lib.rs_status_string.argtypes = [i32]
         lib.rs_status_string.restype = ctypes.c_char_p
         for name in ("rs_plan_create", "rs_plan_workspace_size", "rs_plan_destroy", "rs_batch_solve",
@@ -124,7 +126,7 @@ def rs_plan_export(plan, what):
 
 
 KERNEL_KINDS = ("init", "leaf_up", "tree", "leaf_down", "factor_leaf_up", "factor_tree", "factor_leaf_down",
-                "solve_leaf_up", "solve_tree", "solve_leaf_down")
+                "solve_leaf_up", "solve_tree", "solve_leaf_down", "residual", "update", "check")
 
 
 def rs_plan_set_timing(plan, enable):
@@ -137,6 +139,15 @@ def rs_plan_kernel_times(plan, reset=True):
     n = (ctypes.c_int64 * RS_KERNEL_KINDS)()
     _check(library().rs_plan_kernel_times(plan, ms, n, int(bool(reset))), "rs_plan_kernel_times")
     return {KERNEL_KINDS[k]: (ms[k], n[k]) for k in range(len(KERNEL_KINDS))}
+
+
+def rs_refine_stats(plan, work_ptr, count, stream_ptr=None):
+    """(count, 4) array: relative residual, last relative correction,
+    corrections applied, converged flag (synchronizes the stream)."""
+    out = np.zeros(4 * count, dtype=np.float64)
+    _check(library().rs_refine_stats(plan, work_ptr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     stream_ptr), "rs_refine_stats")
+    return out.reshape(count, 4)
 
 
 def _call(name, plan, probs, work_ptr, work_bytes, stream_ptr, info_ptr):
@@ -252,6 +263,9 @@ class Batch:
     def solve_factored(self):
         rs_solve(self.plan, self.probs, self.work_ptr, self.work_bytes, self.stream_ptr(),
                  self.info.data_ptr())
+
+    def refine_stats(self):
+        return rs_refine_stats(self.plan, self.work_ptr, self.count, self.stream_ptr())
 
     def update(self, key, i, values):
         """Overwrite problem field ``key`` of instance ``i`` in place (same
