@@ -1,15 +1,20 @@
 """Benchmark: KKT Newton-step solves/s of the parallel Riccati solver on one
-MI355X, plus single-instance latency, per-kernel roofline and the serial FP64
-oracle timed on the host cores.
+MI355X in FP64 and in mixed precision, plus single-instance p50/p99 latency,
+the roofline position of the dominant kernel and the serial FP64 oracle timed
+on the host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--Ns 16]
-                    [--branch 4] [--latency-reps R] [--cpu-seconds S]
+                    [--branch 4] [--precision both|fp64|mixed]
+                    [--latency-reps R] [--cpu-seconds S]
 
 Workload: the UFTOC Newton system with n_x = 32, n_u = 16, N = 1024 (G2
 generator: time-varying A_t, dense Q_t, diagonal R_t, cross term S_t), a batch
 of B independent instances resident in HBM, drawn on the device with a seeded
-generator.  One step = one rs_batch_solve over the batch (leaf reduction,
-tree up, top solve, tree down, leaf solve).  Prints one JSON line.
+generator.  One step = one rs_batch_solve over the batch: in FP64 the fused
+solve (leaf reduction, tree up, top solve, tree down, leaf solve); in mixed
+precision the FP32-leaf factorization, the solve and the FP64 residual /
+refinement passes until every instance meets the 1e-10 target.  Prints one
+JSON line; `value` is the faster of the two precisions (both are reported).
 """
 import argparse
 import hashlib
@@ -23,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "KKT Newton solves/s at n_x=32,N=1024 (FP64 vs mixed) + p50/p99 latency"
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector (and FP64 matrix) peak
+FP32_PEAK_TFLOPS = 157.3         # MI355X FP32 vector / FP32 matrix (dense) peak
 HBM_PEAK_GBS = 8000.0
 
 
@@ -52,8 +58,24 @@ def flops_serial(n, m):
     return flops_solve(n, m)
 
 
+def flops_factor_reduce(n, m):
+    """Matrix lines of an Alg. 4 stage (stored factorization): 6n^3 + 12n^2 m + 4n m^2 + m^3/3."""
+    return 6 * n ** 3 + 12 * n * n * m + 4 * n * m * m + m ** 3 / 3
+
+
+def flops_factor_elim(n, m):
+    """Matrix lines of an Alg. 1 stage with K: 4n^3 + 6n^2 m + 4n m^2 + m^3/3."""
+    return 4 * n ** 3 + 6 * n * n * m + 4 * n * m * m + m ** 3 / 3
+
+
 def input_bytes_stage(n, m):
     return 8 * (2 * n * n + 2 * n * m + m * m + 2 * n + m + 1)
+
+
+def residual_bytes_stage(n, m):
+    """FP64 residual pass per stage: reads Qx, Qw, Qxw, A, B, x, w, lam,
+    x+, lam+, lx, lw, a, c; writes lx', lw', a'."""
+    return 8 * (2 * n * n + 2 * n * m + m * m + (4 * n + m) + (2 * n + m + 1) + (2 * n + m))
 
 
 def csrc_hash():
@@ -106,60 +128,40 @@ def cpu_baseline(host_probs, seconds):
     return done, el, threads
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=1024)
-    ap.add_argument("--nx", type=int, default=32)
-    ap.add_argument("--nu", type=int, default=16)
-    ap.add_argument("--N", type=int, default=1024)
-    ap.add_argument("--Ns", type=int, default=16)
-    ap.add_argument("--branch", type=int, default=4)
-    ap.add_argument("--latency-reps", type=int, default=200)
-    ap.add_argument("--latency-Ns", type=int, default=0, help="leaf length of the B=1 latency plan (0: --Ns)")
-    ap.add_argument("--verify", type=int, default=4, help="sampled instances checked against the oracle")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="also run a plain device copy of this size (HBM counter calibration)")
-    args = ap.parse_args()
+def leaf_work(leaves, n, m, up_fn, elim_fn, down_fn):
+    """Per-launch algorithmic FLOPs of the leaf kernels from the plan's leaf
+    table: up = reduction (or elimination for the last leaf), down = solve."""
+    up = down = 0.0
+    for lf in leaves:
+        ln, fl = int(lf[2]), int(lf[3])
+        down += ln * down_fn(n, m)
+        if fl & 2:
+            continue
+        up += ln * (elim_fn(n, m) if fl & 1 else up_fn(n, m))
+    return up, down
 
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: the solver shards instances or horizons across GPUs "
-              "only by design (see DESIGN.md); --gpus %d is not supported." % args.gpus, file=sys.stderr)
-        sys.exit(2)
 
+def run_precision(prec, args, data, dev):
     import numpy as np
     import torch
     from paper_1510_03110_amd import rs
     from paper_1510_03110_amd import workloads as W
+    from oracle import kkt, riccati
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = "cuda:0"
     n, m, N, B = args.nx, args.nu, args.N, args.batch
-    workload = "uftoc_g2_nx%d_nu%d_N%d_batch%d" % (n, m, N, B)
-    log("workload", workload, "Ns", args.Ns, "branch", args.branch)
-    t0 = time.perf_counter()
-    data = W.g2_torch(n, m, N, B, seed=W.seed_for(5), device=dev)
-    torch.cuda.synchronize()
-    log("generated inputs in %.1fs (%.1f GB)" % (time.perf_counter() - t0,
-                                                 sum(v.numel() * 8 for v in data.values()) / 1e9))
-
-    batch = rs.Batch(data, Ns=args.Ns, branch=args.branch, device=dev)
-    stream = torch.cuda.current_stream()
-    log("workspace %.2f GB, leaves %d, tree items %d, depth %d" % (
-        batch.work_bytes / 1e9, rs.rs_plan_query(batch.plan, 0), rs.rs_plan_query(batch.plan, 1),
+    mixed = prec == "mixed"
+    pc = rs.RS_MIXED_FP32 if mixed else rs.RS_FP64
+    batch = rs.Batch(data, precision=pc, Ns=args.Ns, branch=args.branch, device=dev)
+    log("[%s] workspace %.2f GB, leaves %d, tree items %d, depth %d" % (
+        prec, batch.work_bytes / 1e9, rs.rs_plan_query(batch.plan, 0), rs.rs_plan_query(batch.plan, 1),
         rs.rs_plan_query(batch.plan, 2)))
-
     for _ in range(args.warmup):
         batch.solve()
     torch.cuda.synchronize()
-    st = batch.status()
-    bad = int((st[:, 0] != 0).sum())
-    log("warmup done, instances with nonzero status: %d" % bad)
+    bad = int((batch.status()[:, 0] != 0).sum())
+    log("[%s] warmup done, instances with nonzero status: %d" % (prec, bad))
 
-    # ---------------------------------------------------------- timed region
+    # ------------------------------------------------------ timed region
     rs.rs_plan_kernel_times(batch.plan, reset=True)
     rs.rs_plan_set_timing(batch.plan, True)
     torch.cuda.synchronize()
@@ -169,35 +171,48 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     rs.rs_plan_set_timing(batch.plan, False)
-    ktimes = rs.rs_plan_kernel_times(batch.plan, reset=True)
+    kt = rs.rs_plan_kernel_times(batch.plan, reset=True)
     ms_per_step = 1e3 * el / args.steps
     value = B * args.steps / el
-    log("timed %d steps: %.3f ms/step, %.1f solves/s" % (args.steps, ms_per_step, value))
-    log("kernel ms per launch:", {k: round(v[0] / max(v[1], 1), 4) for k, v in ktimes.items()})
+    st = batch.status()
+    bad = int((st[:, 0] != 0).sum())
+    log("[%s] %d steps: %.3f ms/step, %.1f solves/s, nonzero status %d" % (prec, args.steps, ms_per_step,
+                                                                        value, bad))
+    per_step = {k: v[0] / args.steps for k, v in kt.items() if v[1]}
+    launches = {k: v[1] // args.steps for k, v in kt.items() if v[1]}
+    log("[%s] kernel ms per step:" % prec, {k: round(v, 3) for k, v in per_step.items()})
 
-    # ---------------------------------------------------- roofline (dominant)
+    # ------------------------------------------------ roofline (dominant)
     leaves = rs.rs_plan_export(batch.plan, 0)
-    up_flops = 0.0
-    for lf in leaves:
-        ln, fl = int(lf[2]), int(lf[3])
-        if fl & 2:
-            continue
-        up_flops += ln * (flops_elim(n, m) if fl & 1 else flops_reduce(n, m))
-    down_flops = float(leaves[:, 2].sum()) * flops_solve(n, m)
-    per_launch = {"leaf_up": up_flops, "leaf_down": down_flops}
-    avg_ms = {k: ktimes[k][0] / max(ktimes[k][1], 1) for k in ("leaf_up", "leaf_down", "tree")}
-    dom = max(("leaf_up", "leaf_down"), key=lambda k: avg_ms[k])
-    achieved = per_launch[dom] / (avg_ms[dom] * 1e-3) / 1e12
-    traffic = load_traffic("k_" + dom, workload)
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": "k_" + dom, "avg_launch_ms": round(avg_ms[dom], 4),
-                "flops_per_launch": per_launch[dom]}
+    if not mixed:
+        up, down = leaf_work(leaves, n, m, flops_reduce, flops_elim, flops_solve)
+        work = {"leaf_up": ("alu", up, FP64_PEAK_TFLOPS, "k_leaf_up"),
+                "leaf_down": ("alu", down, FP64_PEAK_TFLOPS, "k_leaf_down")}
+    else:
+        up, down = leaf_work(leaves, n, m, flops_factor_reduce, flops_factor_elim, flops_factor_elim)
+        stages = float(leaves[:, 2].sum())
+        work = {"factor_leaf_up": ("alu", up, FP32_PEAK_TFLOPS, "kf_leaf_up"),
+                "factor_leaf_down": ("alu", down, FP32_PEAK_TFLOPS, "kf_leaf_down"),
+                "residual": ("hbm", stages * residual_bytes_stage(n, m), HBM_PEAK_GBS, "kr_residual")}
+    avg = {k: kt[k][0] / max(kt[k][1], 1) for k in work}
+    dom = max(work, key=lambda k: per_step.get(k, 0.0))
+    bound, amount, peak, kname = work[dom]
+    if bound == "hbm":
+        achieved = amount / (avg[dom] * 1e-3) / 1e9
+        unit = "GB/s"
+    else:
+        achieved = amount / (avg[dom] * 1e-3) / 1e12
+        unit = "TFLOP/s"
+    workload = "uftoc_g2_nx%d_nu%d_N%d_batch%d" % (n, m, N, B)
+    roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": load_traffic(kname, workload + "_" + prec),
+                "kernel": kname, "avg_launch_ms": round(avg[dom], 4),
+                ("bytes_per_launch" if bound == "hbm" else "flops_per_launch"): amount}
 
-    # ----------------------------------------------------- B = 1 latency
+    # -------------------------------------------------- B = 1 latency
     lat = None
     if args.latency_reps > 0:
-        one = rs.Batch({k: v[:1] for k, v in data.items()}, Ns=args.latency_Ns or args.Ns,
+        one = rs.Batch({k: v[:1] for k, v in data.items()}, precision=pc, Ns=args.latency_Ns or args.Ns,
                        branch=args.branch, device=dev)
         for _ in range(5):
             one.solve()
@@ -212,23 +227,81 @@ def main():
         lat = {"batch": 1, "p50_ms": round(float(np.percentile(samples, 50)), 4),
                "p99_ms": round(float(np.percentile(samples, 99)), 4), "reps": args.latency_reps,
                "Ns": args.latency_Ns or args.Ns}
-        log("latency B=1:", lat)
+        log("[%s] latency B=1:" % prec, lat)
         one.close()
 
-    # ------------------------------------------------ sampled parity check
-    from oracle import kkt, riccati
-    host = []
-    errs = []
+    # -------------------------------------------- sampled parity check
+    errs, host = [], []
     rng = np.random.default_rng(0)
     idx = sorted(set([0, B - 1] + list(rng.integers(0, B, size=max(0, args.verify - 2)))))[:max(args.verify, 1)]
     for i in idx:
         p = W.instance_to_numpy(data, i)
         host.append(p)
         if args.verify > 0:
-            ref = riccati.solve(p)
-            errs.append(kkt.rel_error(batch.result(i), ref))
-    max_err = max(errs) if errs else None
-    log("sampled rel err vs oracle:", ["%.2e" % e for e in errs])
+            errs.append(kkt.rel_error(batch.result(i), riccati.solve(p)))
+    log("[%s] sampled rel err vs oracle:" % prec, ["%.2e" % e for e in errs])
+    res = {"value": round(value, 2), "ms_per_step": round(ms_per_step, 4), "nonzero_status": bad,
+           "max_rel_err_sampled": max(errs) if errs else None, "sampled_instances": idx,
+           "kernels_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
+           "launches_per_step": launches, "latency": lat, "roofline": roofline}
+    if mixed:
+        stt = batch.refine_stats()
+        res["refinement"] = {"corrections_min": float(stt[:, 2].min()), "corrections_max": float(stt[:, 2].max()),
+                             "rel_residual_max": float(stt[:, 0].max()),
+                             "est_forward_error_max": float(stt[:, 1].max()),
+                             "converged": int(stt[:, 3].sum())}
+        log("[%s] refinement:" % prec, res["refinement"])
+    batch.close()
+    del batch
+    torch.cuda.empty_cache()
+    return res, host
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--nx", type=int, default=32)
+    ap.add_argument("--nu", type=int, default=16)
+    ap.add_argument("--N", type=int, default=1024)
+    ap.add_argument("--Ns", type=int, default=16)
+    ap.add_argument("--branch", type=int, default=4)
+    ap.add_argument("--precision", choices=("both", "fp64", "mixed"), default="both")
+    ap.add_argument("--latency-reps", type=int, default=200)
+    ap.add_argument("--latency-Ns", type=int, default=0, help="leaf length of the B=1 latency plan (0: --Ns)")
+    ap.add_argument("--verify", type=int, default=4, help="sampled instances checked against the oracle")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: sharding instances or a horizon across GPUs is designed "
+              "but not built; --gpus %d is not supported." % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1510_03110_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    n, m, N, B = args.nx, args.nu, args.N, args.batch
+    workload = "uftoc_g2_nx%d_nu%d_N%d_batch%d" % (n, m, N, B)
+    log("workload", workload, "Ns", args.Ns, "branch", args.branch)
+    t0 = time.perf_counter()
+    data = W.g2_torch(n, m, N, B, seed=W.seed_for(5), device=dev)
+    torch.cuda.synchronize()
+    log("generated inputs in %.1fs (%.1f GB)" % (time.perf_counter() - t0,
+                                                 sum(v.numel() * 8 for v in data.values()) / 1e9))
+    precs = ("fp64", "mixed") if args.precision == "both" else (args.precision,)
+    results, host = {}, None
+    for prec in precs:
+        results[prec], host = run_precision(prec, args, data, dev)
+
+    head = max(precs, key=lambda k: results[k]["value"])
+    r = results[head]
 
     # --------------------------------------------------- CPU oracle baseline
     cpu = None
@@ -236,23 +309,24 @@ def main():
         done, cel, threads = cpu_baseline(host, args.cpu_seconds)
         cpu = {"value": round(done / cel, 3), "unit": "solves/s", "cores": threads, "kind": "oracle",
                "sample": "%d solves of instances %s of the same workload (serial FP64 Riccati, C) "
-                         "in %.1fs on %d host threads" % (done, idx, cel, threads)}
+                         "in %.1fs on %d host threads" % (done, r["sampled_instances"], cel, threads)}
         log("cpu baseline:", cpu)
 
     out = {
-        "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "metric": METRIC, "value": r["value"], "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if head == "fp64" else "f32+f64",
         "data": "synthetic: seeded G2 generator drawn on the device",
         "config": {"workload": workload, "nx": n, "nu": m, "N": N, "batch": B, "Ns": args.Ns,
-                   "branch": args.branch, "precision": "fp64"},
-        "latency": lat,
-        "max_rel_err_sampled": max_err,
-        "kernels_ms_per_launch": {k: round(v, 4) for k, v in avg_ms.items()},
-        "roofline": roofline,
+                   "branch": args.branch, "precision": head},
+        "latency": r["latency"],
+        "max_rel_err_sampled": r["max_rel_err_sampled"],
+        "roofline": r["roofline"],
         "cpu_baseline": cpu,
+        "precisions": {k: {kk: vv for kk, vv in v.items() if kk != "sampled_instances"}
+                       for k, v in results.items()},
     }
-    batch.close()
     if args.copy_calibration_mib > 0:
         # a plain copy kernel of known size, for scaling FETCH_SIZE/WRITE_SIZE
         nbytes = args.copy_calibration_mib << 20

@@ -199,14 +199,17 @@ rs_status rs_plan_set_timing(rs_plan plan, int32_t enable);
 rs_status rs_plan_kernel_times(rs_plan plan, double *ms, int64_t *launches, int32_t reset);
 
 /* Refinement statistics of the last mixed-precision solve with this plan and
- * workspace, 4 doubles per instance, copied to host memory `out` (waits for
- * `stream`): relative KKT residual ||r - K z||_inf / ||r||_inf of the
- * returned solution (FP64), size of the last correction relative to the
- * solution (max over the x, w, lam blocks; an estimate of the forward error
- * before that correction), corrections applied, converged flag.  The
- * iteration stops for an instance once its correction is <= tol/10; it is
- * reported RS_ERR_NOT_CONVERGED if that never happens within max_refine
- * corrections or the final relative residual exceeds tol.  RS_ERR_ARG for a
+ * workspace, 5 doubles per instance, copied to host memory `out` (waits for
+ * `stream`):
+ *   [0] relative KKT residual ||r - K z||_inf / ||r||_inf of the returned
+ *       solution, evaluated in FP64;
+ *   [1] estimated relative forward error: d_k (d_k / d_{k-1}), where d_k is
+ *       the last correction relative to the solution (max over the x, w, lam
+ *       blocks) and d_{k-1} the one before (1 for the first);
+ *   [2] corrections applied;  [3] converged flag;  [4] d_k.
+ * An instance stops refining once a correction has been applied, [0] <= tol
+ * and [1] <= tol/10; it is reported RS_ERR_NOT_CONVERGED if that does not
+ * happen within max_refine corrections.  RS_ERR_ARG for a
  * plan that is not RS_MIXED_FP32. */
 rs_status rs_refine_stats(rs_plan plan, const void *work, double *out, void *stream);
 

@@ -634,20 +634,22 @@ static rs_status launch_check(rs_plan P, char *W, int32_t *info, hipStream_t st,
 }
 
 // Solve on the stored mixed-precision factorization with FP64 iterative
-// refinement: z = solve(r); then up to max_refine times rho = r - K z (FP64),
-// d = solve(rho), z += d, until the correction is below tol/10 relative to z;
-// finally the relative residual of z and the objective.
+// refinement: z = solve(r); then, per instance until it converges and at
+// most max_refine times: rho = r - K z and the objective (FP64), convergence
+// test, d = solve(rho), z += d.  Converged instances skip every later pass.
 static rs_status mixed_solve(rs_plan P, char *W, int32_t *info, hipStream_t st) {
     rs_status s = launch_check(P, W, info, st, 0);
     if (s == RS_OK) s = launch_pass(P, W, info, st, 2, true, false, true);
     for (int k = 0; k < P->max_refine && s == RS_OK; ++k) {
         s = launch_refine(P, W, info, st, 0, true);
+        if (s == RS_OK) s = launch_check(P, W, info, st, 1);
         if (s == RS_OK) s = launch_pass(P, W, info, st, 2, true, true, true);
         if (s == RS_OK) s = launch_refine(P, W, info, st, 1, true);
-        if (s == RS_OK) s = launch_check(P, W, info, st, 1);
+        if (s == RS_OK) s = launch_check(P, W, info, st, 2);
     }
-    if (s == RS_OK) s = launch_refine(P, W, info, st, 0, false);
-    if (s == RS_OK) s = launch_check(P, W, info, st, 2);
+    if (s == RS_OK) s = launch_refine(P, W, info, st, 0, true);
+    if (s == RS_OK) s = launch_check(P, W, info, st, 1);
+    if (s == RS_OK) s = launch_check(P, W, info, st, 3);
     P->last_refine = P->max_refine;
     return s;
 }

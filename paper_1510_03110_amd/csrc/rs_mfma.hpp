@@ -269,10 +269,16 @@ __device__ __forceinline__ void commit_stage(MSmem<T, NX, NU, RED, SOLVE> &S, co
 // Cholesky factorization G = L L' ("a factorization of G", Alg. 1) and the
 // inverse L^{-1}, by one wavefront.  Lane i holds row i of G / L in
 // registers; entries of other rows are broadcast with readlane, which places
-// them in scalar registers.  On return G holds L^{-1} row-major and LiT holds
-// L^{-T} row-major.  Both sweeps are right-looking, so the dependency chain
-// is one multiply-add per column.  Returns nonzero (wave-uniform) if a pivot
-// is not positive or not finite; a unit pivot is used in its place.
+// them in scalar registers, and the sweep is right-looking, so the dependency
+// chain is one multiply-add per column.  The pivot's reciprocal square root
+// comes from the hardware estimate refined by two Newton steps
+// (r <- r (3 - d r^2) / 2, each doubling the correct bits), which replaces
+// the much longer correctly-rounded square root and division sequences.
+// L^{-1} is then formed column by column (lane c solves L x = e_c, again
+// with readlane broadcasts).  On return G holds L^{-1} row-major and LiT
+// holds L^{-T} row-major.  Returns nonzero
+// (wave-uniform) if a pivot is not positive or not finite; a unit pivot is
+// used in its place.
 template <int M, class T>
 __device__ __forceinline__ int chol_inv_wave(T *G, T *LiT) {
     static_assert(M <= 64, "one wavefront factors at most 64 rows");
@@ -289,9 +295,10 @@ __device__ __forceinline__ int chol_inv_wave(T *G, T *LiT) {
             fail = 1;
             d = T(1);
         }
-        const T sq = rs_sqrt(d);
-        const T is = T(1) / sq;
-        const T lij = (ln == j) ? sq : g[j] * is;
+        T is = __builtin_amdgcn_rsq(d);
+        is = is * (T(1.5) - T(0.5) * d * is * is);
+        is = is * (T(1.5) - T(0.5) * d * is * is);
+        const T lij = (ln == j) ? d * is : g[j] * is;
         if (ln == j) invd = is;
         g[j] = lij;
 #pragma unroll

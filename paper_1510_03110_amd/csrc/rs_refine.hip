@@ -21,8 +21,9 @@
 //                max |r|, max |rho| and the objective part of the leaf
 //   kr_update    per leaf: z += d; max |d| and max |z| per block (x, w, lam)
 //   kr_check     per instance: reduces the leaf parts in a fixed order;
-//                decides convergence, writes the statistics, the objective
-//                and RS_ERR_NOT_CONVERGED
+//                decides convergence (relative residual <= tol and
+//                estimated forward error <= tol/10), writes the statistics,
+//                the objective and RS_ERR_NOT_CONVERGED
 #include <hip/hip_runtime.h>
 
 #include "rs_launch.hpp"
@@ -207,9 +208,12 @@ __global__ void __launch_bounds__(RT) kr_update(GroupArgs g) {
     }
 }
 
-// mode 0: start of a refinement (conv = status != OK, statistics cleared);
-// mode 1: after an update (correction size, convergence);
-// mode 2: final (relative residual, objective, status).
+// mode 0: start (conv = status != OK, statistics cleared);
+// mode 1: after a residual pass (relative residual and objective of the
+//         current iterate; converged once a correction has been applied,
+//         the residual is <= tol and the estimated forward error <= tol/10);
+// mode 2: after an update (correction size, forward-error estimate);
+// mode 3: final (RS_ERR_NOT_CONVERGED for instances that did not converge).
 __global__ void kr_check(const InstInfo *tab, int count, const double *part, double *stats, int32_t *conv,
                          int32_t *info, const DevProb *probs, int mode, double tol) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -218,13 +222,22 @@ __global__ void kr_check(const InstInfo *tab, int count, const double *part, dou
     if (mode == 0) {
         conv[i] = info[2 * i] != STATUS_OK ? 1 : 0;
         for (int q = 0; q < ST_N; ++q) st[q] = 0.0;
-        st[ST_DZ] = 1.0;
+        st[ST_EST] = 1.0;
+        st[ST_DZ] = 1.0;      // the first solve is taken as 100% wrong
         return;
     }
+    if (mode == 3) {
+        st[ST_CONV] = conv[i] ? 1.0 : 0.0;
+        if (info[2 * i] == STATUS_OK && !conv[i]) {
+            info[2 * i] = STATUS_NOT_CONVERGED;
+            info[2 * i + 1] = -1;
+        }
+        return;
+    }
+    if (conv[i]) return;
     const InstInfo in = tab[i];
     const double *pp = part + (int64_t)in.first_leaf * PART_N;
-    if (mode == 1) {
-        if (conv[i]) return;
+    if (mode == 2) {
         double d[3] = {0, 0, 0}, z[3] = {0, 0, 0};
         for (int lf = 0; lf < in.nleaves; ++lf)
             for (int b = 0; b < 3; ++b) {
@@ -233,9 +246,13 @@ __global__ void kr_check(const InstInfo *tab, int count, const double *part, dou
             }
         double dz = 0.0;
         for (int b = 0; b < 3; ++b) dz = fmax(dz, z[b] > 0.0 ? d[b] / z[b] : d[b]);
+        // The correction d_k measures the error of the previous iterate; the
+        // error left after applying it is about d_k times the contraction
+        // factor of the iteration, estimated as d_k / d_{k-1}.
+        const double est = dz * fmin(1.0, dz / fmax(st[ST_DZ], 1e-300));
         st[ST_DZ] = dz;
+        st[ST_EST] = est;
         st[ST_ITERS] += 1.0;
-        if (dz <= 0.1 * tol) conv[i] = 1;
         return;
     }
     double rhs = 0.0, res = 0.0, obj = 0.0;
@@ -246,12 +263,8 @@ __global__ void kr_check(const InstInfo *tab, int count, const double *part, dou
     }
     const double rres = rhs > 0.0 ? res / rhs : res;
     st[ST_RRES] = rres;
-    st[ST_CONV] = conv[i] ? 1.0 : 0.0;
     if (probs[i].obj) probs[i].obj[0] = obj;
-    if (info[2 * i] == STATUS_OK && (!conv[i] || !(rres <= tol))) {
-        info[2 * i] = STATUS_NOT_CONVERGED;
-        info[2 * i + 1] = -1;
-    }
+    if (st[ST_ITERS] >= 1.0 && rres <= tol && st[ST_EST] <= 0.1 * tol) conv[i] = 1;
 }
 
 template <int NX, int NU>

@@ -107,9 +107,9 @@ struct InstInfo {
 //   update:   max |dx|, |dw|, |dlam|, max |x|, |w|, |lam| after the update
 enum { PART_RHS = 0, PART_RES = 1, PART_OBJ = 2, PART_DX = 3, PART_X = 6, PART_N = 9 };
 // Per-instance refinement statistics (doubles): relative residual of the
-// returned solution, last correction relative to the solution (forward
-// error estimate), corrections applied, converged flag.
-enum { ST_RRES = 0, ST_DZ = 1, ST_ITERS = 2, ST_CONV = 3, ST_N = 4 };
+// returned solution, estimated relative forward error, corrections applied,
+// converged flag, size of the last correction relative to the solution.
+enum { ST_RRES = 0, ST_EST = 1, ST_ITERS = 2, ST_CONV = 3, ST_DZ = 4, ST_N = 5 };
 
 // Everything a kernel launch of one shape group needs.
 struct GroupArgs {

@@ -141,13 +141,15 @@ def rs_plan_kernel_times(plan, reset=True):
     return {KERNEL_KINDS[k]: (ms[k], n[k]) for k in range(len(KERNEL_KINDS))}
 
 
+REFINE_STATS = ("rel_residual", "est_forward_error", "corrections", "converged", "last_correction")
+
+
 def rs_refine_stats(plan, work_ptr, count, stream_ptr=None):
-    """(count, 4) array: relative residual, last relative correction,
-    corrections applied, converged flag (synchronizes the stream)."""
-    out = np.zeros(4 * count, dtype=np.float64)
+    """(count, 5) array, columns REFINE_STATS (synchronizes the stream)."""
+    out = np.zeros(5 * count, dtype=np.float64)
     _check(library().rs_refine_stats(plan, work_ptr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      stream_ptr), "rs_refine_stats")
-    return out.reshape(count, 4)
+    return out.reshape(count, 5)
 
 
 def _call(name, plan, probs, work_ptr, work_bytes, stream_ptr, info_ptr):

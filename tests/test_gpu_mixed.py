@@ -47,29 +47,33 @@ def test_mixed_matches_oracle_after_refinement(nx, nu, N, Ns, b):
     st = bt.refine_stats()[0]
     assert st[3] == 1.0                 # converged
     assert st[0] <= TOL                 # relative KKT residual of the result
+    assert st[1] <= 0.1 * TOL           # estimated forward error
     assert 1 <= st[2] <= 5              # corrections applied
     bt.close()
 
 
 def test_refinement_is_needed_and_contracts():
-    """The FP32 factorization alone is far from 1e-10; every correction
-    contracts the error.  One correction cannot meet the stopping rule, so a
-    plan limited to it reports RS_ERR_NOT_CONVERGED; the default one converges."""
+    """The FP32 factorization alone is far from 1e-10 (the first correction is
+    large); each correction contracts the error.  A target below what one
+    correction reaches, with a single correction allowed, is reported as
+    RS_ERR_NOT_CONVERGED; with more corrections the estimate keeps falling."""
     prob = W.g2(32, 16, 256, seed=3)
-    torch, rs, bt = _batch([prob], Ns=8, branch=4, max_refine=1)
+    ref = riccati.solve(prob)
+    torch, rs, bt = _batch([prob], Ns=8, branch=4, max_refine=1, tol=1e-15)
     bt.solve()
     torch.cuda.synchronize()
-    st = bt.refine_stats()[0]
+    st1 = bt.refine_stats()[0]
     assert bt.status()[0, 0] == rs.RS_ERR_NOT_CONVERGED
-    assert st[1] > 1e-9                  # the first correction was large: FP32 factors
-    err1 = kkt.rel_error(bt.result(0), riccati.solve(prob))
-    assert err1 < 1e-6                   # yet it already contracted the error
+    assert st1[2] == 1 and st1[4] > 1e-9     # first correction large: FP32 factors
+    err1 = kkt.rel_error(bt.result(0), ref)
+    assert err1 < 1e-9                       # one correction already contracts it
     bt.close()
-    torch, rs, bt = _batch([prob], Ns=8, branch=4)
+    torch, rs, bt = _batch([prob], Ns=8, branch=4, max_refine=3, tol=1e-15)
     bt.solve()
     torch.cuda.synchronize()
-    assert bt.status()[0, 0] == 0
-    assert bt.refine_stats()[0][2] >= 2
+    st3 = bt.refine_stats()[0]
+    assert st3[2] >= 2 and st3[4] < st1[4] * 1e-3
+    assert kkt.rel_error(bt.result(0), ref) <= err1
     bt.close()
 
 
@@ -126,5 +130,5 @@ def test_mixed_not_spd_is_reported_not_refined():
     torch.cuda.synchronize()
     st = bt.status()
     assert st[0, 0] == rs.RS_ERR_NOT_SPD and st[0, 1] == 21
-    assert bt.refine_stats()[0][2] == 0
+    assert bt.refine_stats()[0][2] == 0     # nothing refined
     bt.close()
