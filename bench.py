@@ -186,14 +186,15 @@ def run_precision(prec, args, data, dev):
     leaves = rs.rs_plan_export(batch.plan, 0)
     if not mixed:
         up, down = leaf_work(leaves, n, m, flops_reduce, flops_elim, flops_solve)
-        work = {"leaf_up": ("alu", up, FP64_PEAK_TFLOPS, "k_leaf_up"),
-                "leaf_down": ("alu", down, FP64_PEAK_TFLOPS, "k_leaf_down")}
+        work = {"leaf_up": ("alu", up, FP64_PEAK_TFLOPS, "km_leaf_up"),
+                "leaf_down": ("alu", down, FP64_PEAK_TFLOPS, "km_leaf_down")}
     else:
         up, down = leaf_work(leaves, n, m, flops_factor_reduce, flops_factor_elim, flops_factor_elim)
         stages = float(leaves[:, 2].sum())
+        # kernels launched once per step (the refinement kernels skip
+        # converged instances, so their per-launch work is not fixed)
         work = {"factor_leaf_up": ("alu", up, FP32_PEAK_TFLOPS, "kf_leaf_up"),
-                "factor_leaf_down": ("alu", down, FP32_PEAK_TFLOPS, "kf_leaf_down"),
-                "residual": ("hbm", stages * residual_bytes_stage(n, m), HBM_PEAK_GBS, "kr_residual")}
+                "factor_leaf_down": ("alu", down, FP32_PEAK_TFLOPS, "kf_leaf_down")}
     avg = {k: kt[k][0] / max(kt[k][1], 1) for k in work}
     dom = max(work, key=lambda k: per_step.get(k, 0.0))
     bound, amount, peak, kname = work[dom]

@@ -121,6 +121,17 @@ typedef struct rs_plan_s *rs_plan;
 rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *opt,
                          rs_plan *plan_out);
 
+/*
+ * As rs_plan_create, with a leaf length and branch per instance: dims5 holds
+ * (nx, nu, N, Ns, branch) per instance, Ns = 0 / branch = 0 taking the
+ * plan-wide value of opt.  The tree of an instance depends only on its own
+ * row, never on the rest of the batch, so an instance gives bit-identical
+ * results alone and in any batch (an autotuner chooses Ns and branch per
+ * (nx, nu, N range, precision)).  Errors as rs_plan_create.
+ */
+rs_status rs_plan_create_ex(int32_t count, const int32_t *dims5, const rs_options *opt,
+                            rs_plan *plan_out);
+
 /* Device workspace bytes the plan needs (caller allocates, 256-byte aligned). */
 rs_status rs_plan_workspace_size(rs_plan plan, size_t *bytes);
 
@@ -212,6 +223,25 @@ rs_status rs_plan_kernel_times(rs_plan plan, double *ms, int64_t *launches, int3
  * happen within max_refine corrections.  RS_ERR_ARG for a
  * plan that is not RS_MIXED_FP32. */
 rs_status rs_refine_stats(rs_plan plan, const void *work, double *out, void *stream);
+
+/*
+ * HIP graph of one call (mode 0 = rs_batch_solve, 1 = rs_factor, 2 =
+ * rs_solve): binds the descriptors as the call would, then captures its whole
+ * kernel sequence on `stream` (which must not be the NULL stream) into an
+ * executable graph.  Nothing runs at creation except the descriptor upload.
+ * rs_graph_launch replays the call on any stream: the launch overhead of the
+ * multi-kernel sequence (mixed precision: up to 6 + 7*max_refine kernels) is
+ * paid once.  A replay reads the problem descriptors bound most recently to
+ * the plan's workspace, so data may change behind the same pointers between
+ * replays; new pointers need a new graph.  The graph clears the tree's
+ * completion flags with a kernel at its start.  One graph of a plan may run
+ * at a time, and not concurrently with a direct call on the same workspace.
+ */
+typedef struct rs_graph_s *rs_graph;
+rs_status rs_graph_create(rs_plan plan, int32_t mode, const rs_problem *probs, void *work,
+                          size_t work_bytes, void *stream, int32_t *info_dev, rs_graph *graph_out);
+rs_status rs_graph_launch(rs_graph graph, void *stream);
+rs_status rs_graph_destroy(rs_graph graph);
 
 const char *rs_status_string(rs_status s);
 

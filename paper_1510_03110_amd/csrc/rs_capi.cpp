@@ -47,7 +47,8 @@ struct rs_plan_s {
     std::vector<size_t> off_cbuf;   // per instance: correction buffers (mixed)
     size_t off_inst = 0, off_conv = 0, off_stats = 0, off_part = 0;
     double tol = 1e-10;
-    std::vector<int32_t> dims;
+    std::vector<int32_t> dims;          // (nx, nu, N) per instance
+    std::vector<int32_t> inst_Ns, inst_branch;   // leaf length and branch per instance
     std::vector<Group> groups;
     size_t off_probs = 0, off_info = 0, off_queues = 0, off_tables = 0, tables_bytes = 0;
     size_t total = 0;
@@ -234,8 +235,9 @@ const char *rs_status_string(rs_status s) {
     return "unknown status";
 }
 
-rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *opt, rs_plan *out) {
-    if (!out || !dims || count < 1) return RS_ERR_ARG;
+static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, const rs_options *opt,
+                             rs_plan *out) {
+    if (!out || !dims_in || count < 1) return RS_ERR_ARG;
     *out = nullptr;
     rs_plan_s *P = new (std::nothrow) rs_plan_s();
     if (!P) return RS_ERR_NOMEM;
@@ -258,7 +260,21 @@ rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *o
     }
     P->top_max = P->branch;
     P->count = count;
-    P->dims.assign(dims, dims + 3 * (size_t)count);
+    P->dims.resize(3 * (size_t)count);
+    P->inst_Ns.resize(count);
+    P->inst_branch.resize(count);
+    for (int i = 0; i < count; ++i) {
+        for (int k = 0; k < 3; ++k) P->dims[3 * i + k] = dims_in[(size_t)stride * i + k];
+        const int ns = stride >= 5 ? dims_in[(size_t)stride * i + 3] : 0;
+        const int br = stride >= 5 ? dims_in[(size_t)stride * i + 4] : 0;
+        if (ns < 0 || br < 0 || br == 1) {
+            delete P;
+            return RS_ERR_ARG;
+        }
+        P->inst_Ns[i] = ns > 0 ? ns : P->Ns;
+        P->inst_branch[i] = br > 0 ? br : P->branch;
+    }
+    const int32_t *dims = P->dims.data();
     std::map<std::pair<int, int>, int> gidx;
     std::vector<int> inst_group(count);
     for (int i = 0; i < count; ++i) {
@@ -269,7 +285,7 @@ rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *o
         }
         // a multi-leaf instance needs Ns*nu >= nx or the reduced input weight
         // Q_w_hat = S Qbar^{-1} S' is singular (Sec. 4.2 remark)
-        if (N > P->Ns && (int64_t)P->Ns * nu < nx) {
+        if (N > P->inst_Ns[i] && (int64_t)P->inst_Ns[i] * nu < nx) {
             delete P;
             return RS_ERR_ARG;
         }
@@ -297,7 +313,8 @@ rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *o
         g.leaf_base = P->total_leaves;
         for (int inst : g.insts) {
             const int before = (int)g.leaves.size();
-            build_instance(g, inst, dims[3 * inst + 2], P->Ns, P->branch, P->top_max, tmp);
+            build_instance(g, inst, dims[3 * inst + 2], P->inst_Ns[inst], P->inst_branch[inst], P->inst_branch[inst],
+                           tmp);
             InstInfo &in = P->inst[inst];
             in.first_leaf = g.leaf_base + before;
             in.nleaves = (int)g.leaves.size() - before;
@@ -373,6 +390,14 @@ rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *o
     }
     *out = P;
     return RS_OK;
+}
+
+rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *opt, rs_plan *out) {
+    return plan_create(count, dims, 3, opt, out);
+}
+
+rs_status rs_plan_create_ex(int32_t count, const int32_t *dims5, const rs_options *opt, rs_plan *out) {
+    return plan_create(count, dims5, 5, opt, out);
 }
 
 rs_status rs_plan_workspace_size(rs_plan P, size_t *bytes) {
@@ -654,7 +679,17 @@ static rs_status mixed_solve(rs_plan P, char *W, int32_t *info, hipStream_t st) 
     return s;
 }
 
+// Kernel sequence of a call once the descriptors are bound.
 // mode 0 = rs_batch_solve, 1 = rs_factor, 2 = rs_solve.
+static rs_status run_sequence(rs_plan P, char *W, int32_t *info, hipStream_t st, int mode) {
+    if (!P->mixed) return launch_pass(P, W, info, st, mode, mode == 2, false, false);
+    if (mode != 2) {
+        rs_status s = launch_pass(P, W, info, st, 1, false, false, false);
+        if (s != RS_OK || mode == 1) return s;
+    }
+    return mixed_solve(P, W, info, st);
+}
+
 static rs_status run_call(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
                           int32_t *info_dev, int mode) {
     rs_status s = check_call(P, probs, work, work_bytes);
@@ -665,14 +700,72 @@ static rs_status run_call(rs_plan P, const rs_problem *probs, void *work, size_t
     s = bind_and_upload(P, probs, W, st);
     if (s != RS_OK) return s;
     int32_t *info = info_dev ? info_dev : reinterpret_cast<int32_t *>(W + P->off_info);
-    if (!P->mixed) {
-        return launch_pass(P, W, info, st, mode, mode == 2, false, false);
+    return run_sequence(P, W, info, st, mode);
+}
+
+struct rs_graph_s {
+    rs_plan plan = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+rs_status rs_graph_create(rs_plan P, int32_t mode, const rs_problem *probs, void *work, size_t work_bytes,
+                          void *stream, int32_t *info_dev, rs_graph *out) {
+    if (!out || mode < 0 || mode > 2 || !stream) return RS_ERR_ARG;
+    *out = nullptr;
+    rs_status s = check_call(P, probs, work, work_bytes);
+    if (s != RS_OK) return s;
+    if (mode != 0 && !P->factored) return RS_ERR_ARG;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    char *W = static_cast<char *>(work);
+    s = bind_and_upload(P, probs, W, st);
+    if (s != RS_OK) return s;
+    int32_t *info = info_dev ? info_dev : reinterpret_cast<int32_t *>(W + P->off_info);
+    rs_graph_s *G = new (std::nothrow) rs_graph_s();
+    if (!G) return RS_ERR_NOMEM;
+    G->plan = P;
+    const bool timing = P->timing;
+    P->timing = false;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        P->timing = timing;
+        delete G;
+        return RS_ERR_HIP;
     }
-    if (mode != 2) {
-        s = launch_pass(P, W, info, st, 1, false, false, false);
-        if (s != RS_OK || mode == 1) return s;
+    // the tree flags are cleared at the start of every replay, so the epochs
+    // recorded in the graph are fresh each time (a fill kernel, not a memset)
+    for (auto &g : P->groups) {
+        if (s == RS_OK && launch_fill_i32(reinterpret_cast<int32_t *>(W + g.off_flags),
+                                          (int64_t)std::max<size_t>(1, g.items.size()), 0, st) != hipSuccess)
+            s = RS_ERR_HIP;
     }
-    return mixed_solve(P, W, info, st);
+    if (s == RS_OK) s = run_sequence(P, W, info, st, mode);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    P->timing = timing;
+    if (s == RS_OK && (ec != hipSuccess || !graph)) s = RS_ERR_HIP;
+    if (s == RS_OK && hipGraphInstantiate(&G->exec, graph, nullptr, nullptr, 0) != hipSuccess) s = RS_ERR_HIP;
+    G->graph = graph;
+    if (s != RS_OK) {
+        if (G->exec) (void)hipGraphExecDestroy(G->exec);
+        if (G->graph) (void)hipGraphDestroy(G->graph);
+        delete G;
+        return s;
+    }
+    *out = G;
+    return RS_OK;
+}
+
+rs_status rs_graph_launch(rs_graph G, void *stream) {
+    if (!G || !G->exec) return RS_ERR_ARG;
+    return hipGraphLaunch(G->exec, reinterpret_cast<hipStream_t>(stream)) == hipSuccess ? RS_OK : RS_ERR_HIP;
+}
+
+rs_status rs_graph_destroy(rs_graph G) {
+    if (!G) return RS_ERR_ARG;
+    if (G->exec) (void)hipGraphExecDestroy(G->exec);
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    delete G;
+    return RS_OK;
 }
 
 rs_status rs_batch_solve(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,

@@ -59,6 +59,10 @@ def library():
         lib = ctypes.CDLL(path)
         i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         lib.rs_plan_create.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(rs_options), ctypes.POINTER(_P)]
+        lib.rs_plan_create_ex.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(rs_options), ctypes.POINTER(_P)]
+        lib.rs_graph_create.argtypes = [_P, i32, ctypes.POINTER(rs_problem), _P, sz, _P, _P, ctypes.POINTER(_P)]
+        lib.rs_graph_launch.argtypes = [_P, _P]
+        lib.rs_graph_destroy.argtypes = [_P]
         lib.rs_plan_workspace_size.argtypes = [_P, ctypes.POINTER(sz)]
         lib.rs_plan_destroy.argtypes = [_P]
         for name in ("rs_batch_solve", "rs_factor", "rs_solve"):
@@ -75,8 +79,9 @@ def library():
         lib.rs_refine_stats.restype = i32
         lib.rs_status_string.argtypes = [i32]
         lib.rs_status_string.restype = ctypes.c_char_p
-        for name in ("rs_plan_create", "rs_plan_workspace_size", "rs_plan_destroy", "rs_batch_solve",
-                     "rs_factor", "rs_solve"):
+        for name in ("rs_plan_create", "rs_plan_create_ex", "rs_plan_workspace_size", "rs_plan_destroy",
+                     "rs_batch_solve", "rs_factor", "rs_solve", "rs_graph_create", "rs_graph_launch",
+                     "rs_graph_destroy"):
             getattr(lib, name).restype = i32
         _lib = lib
     return _lib
@@ -92,12 +97,16 @@ def _check(status, where):
 
 
 def rs_plan_create(dims, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.0, flags=0):
-    """dims: sequence of (nx, nu, N).  Returns an opaque plan handle."""
-    arr = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 3))
+    """dims: sequence of (nx, nu, N), or of (nx, nu, N, Ns, branch) for a
+    leaf length and branch per instance (rs_plan_create_ex).  Returns an
+    opaque plan handle."""
+    arr = np.asarray(dims, dtype=np.int32)
+    width = 5 if arr.ndim == 2 and arr.shape[1] == 5 else 3
+    arr = np.ascontiguousarray(arr.reshape(-1, width))
     opt = rs_options(precision, Ns, branch, max_refine, tol, flags, 0)
     h = _P()
-    st = library().rs_plan_create(arr.shape[0], arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                  ctypes.byref(opt), ctypes.byref(h))
+    fn = library().rs_plan_create_ex if width == 5 else library().rs_plan_create
+    st = fn(arr.shape[0], arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(opt), ctypes.byref(h))
     _check(st, "rs_plan_create")
     return h
 
@@ -169,6 +178,22 @@ def rs_solve(plan, probs, work_ptr, work_bytes, stream_ptr=None, info_ptr=None):
     _call("rs_solve", plan, probs, work_ptr, work_bytes, stream_ptr, info_ptr)
 
 
+def rs_graph_create(plan, mode, probs, work_ptr, work_bytes, stream_ptr, info_ptr=None):
+    """Capture one call (0 batch solve, 1 factor, 2 solve) into a HIP graph."""
+    h = _P()
+    _check(library().rs_graph_create(plan, mode, probs, work_ptr, work_bytes, stream_ptr, info_ptr,
+                                     ctypes.byref(h)), "rs_graph_create")
+    return h
+
+
+def rs_graph_launch(graph, stream_ptr):
+    _check(library().rs_graph_launch(graph, stream_ptr), "rs_graph_launch")
+
+
+def rs_graph_destroy(graph):
+    _check(library().rs_graph_destroy(graph), "rs_graph_destroy")
+
+
 # ------------------------------------------------------------ torch helper
 _MATS = ("Qx", "Qw", "Qxw", "A", "B")
 _VECS = ("a", "lx", "lw", "c", "lN", "cN", "x0")
@@ -187,7 +212,7 @@ class Batch:
     """
 
     def __init__(self, data, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.0,
-                 device="cuda", factored=False):
+                 device="cuda", factored=False, per_instance=None):
         import torch
         self.torch = torch
         keys = set(data)
@@ -212,8 +237,10 @@ class Batch:
         self.lam = [torch.zeros((N + 1, nx), **f64) for nx, nu, N in dims]
         self.obj = torch.zeros(self.count, **f64)
         self.info = torch.zeros(2 * self.count, dtype=torch.int32, device=device)
-        self.plan = rs_plan_create(dims, precision, Ns, branch, max_refine, tol,
+        pdims = dims if per_instance is None else [d + tuple(pi) for d, pi in zip(dims, per_instance)]
+        self.plan = rs_plan_create(pdims, precision, Ns, branch, max_refine, tol,
                                    RS_PLAN_FACTORED if factored else 0)
+        self.graphs = []
         self.work_bytes = rs_plan_workspace_size(self.plan)
         self.work = torch.empty(self.work_bytes + 256, dtype=torch.uint8, device=device)
         base = self.work.data_ptr()
@@ -275,6 +302,21 @@ class Batch:
         t = self.data[key][i]
         t.copy_(self._dev(values, t.device).reshape(t.shape))
 
+    def capture(self, mode=0):
+        """HIP graph of solve (0), factor (1) or solve_factored (2) on a side
+        stream; replay it with ``replay``."""
+        torch = self.torch
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        g = rs_graph_create(self.plan, mode, self.probs, self.work_ptr, self.work_bytes, side.cuda_stream,
+                            self.info.data_ptr())
+        torch.cuda.current_stream().wait_stream(side)
+        self.graphs.append(g)
+        return g
+
+    def replay(self, graph):
+        rs_graph_launch(graph, self.stream_ptr())
+
     def status(self):
         return self.info.view(-1, 2).cpu().numpy()
 
@@ -283,6 +325,9 @@ class Batch:
                     lam=self.lam[i].cpu().numpy(), obj=float(self.obj[i].cpu()))
 
     def close(self):
+        for g in getattr(self, "graphs", []):
+            rs_graph_destroy(g)
+        self.graphs = []
         if self.plan is not None:
             rs_plan_destroy(self.plan)
             self.plan = None

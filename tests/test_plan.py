@@ -201,3 +201,29 @@ def test_factor_needs_factored_plan():
             assert st == rs.RS_ERR_ARG
     finally:
         rs.rs_plan_destroy(plan)
+
+
+def test_per_instance_leaf_length_and_branch():
+    """rs_plan_create_ex: each instance's tree follows its own (Ns, branch)."""
+    dims = [(4, 2, 100, 8, 2), (4, 2, 100, 4, 3), (4, 2, 37, 0, 0)]
+    plan = rs.rs_plan_create(dims, Ns=16, branch=4)
+    try:
+        leaves = rs.rs_plan_export(plan, 0)
+        for inst, (ns, n) in enumerate(((8, 100), (4, 100), (16, 37))):
+            L = leaves[leaves[:, 0] == inst]
+            assert len(L) == -(-n // ns)
+            assert L[0, 2] == min(ns, n)
+        # the same instance alone gets the same tree
+        alone = rs.rs_plan_create([dims[1]], Ns=16, branch=4)
+        try:
+            a_items = rs.rs_plan_export(alone, 1)
+        finally:
+            rs.rs_plan_destroy(alone)
+        items = rs.rs_plan_export(plan, 1)
+        mine = items[items[:, 1] == 1]
+        assert len(mine) == len(a_items)
+        assert np.array_equal(np.sort(mine[:, 2]), np.sort(a_items[:, 2]))
+    finally:
+        rs.rs_plan_destroy(plan)
+    with pytest.raises(rs.RsError):
+        rs.rs_plan_create([(4, 2, 100, 8, 1)])       # branch 1 is invalid
