@@ -68,9 +68,15 @@ typedef enum rs_precision {
                            in FP64, iterative refinement to the requested tolerance  */
 } rs_precision;
 
+/* rs_problem.flags: the instance is left untouched by this call (its outputs
+ * and status are not written).  A serving loop keeps one plan over all its
+ * sessions and marks the sessions without a pending request this way. */
+#define RS_PROB_SKIP 1
+
 /* One instance of P(N).  Matrices and vectors: device pointers, FP64. */
 typedef struct rs_problem {
-    int32_t nx, nu, N, reserved;
+    int32_t nx, nu, N;
+    int32_t flags;                    /* RS_PROB_SKIP: exclude the instance from this call */
     /* stage matrices, N blocks each (RHS independent) */
     const double *Qx;  int64_t sQx;   /* nx*nx blocks, Q_{x,t}                       */
     const double *Qw;  int64_t sQw;   /* nu*nu blocks, Q_{w,t}, positive definite      */
@@ -80,10 +86,10 @@ typedef struct rs_problem {
     const double *QxN;                /* nx*nx terminal weight Q_{x,N}                 */
     /* right-hand side */
     const double *x0;                 /* nx, initial state xbar_0                      */
-    const double *a;                  /* N*nx affine dynamics term; NULL = zero        */
-    const double *lx;                 /* N*nx linear state cost l_{x,t}; NULL = zero   */
-    const double *lw;                 /* N*nu linear input cost l_{w,t}; NULL = zero   */
-    const double *c;                  /* N constants c_t; NULL = zero                  */
+    const double *a;                  /* N blocks of nx (stride sa): affine term a_t; NULL = zero */
+    const double *lx;                 /* N blocks of nx (stride slx): l_{x,t}; NULL = zero */
+    const double *lw;                 /* N blocks of nu (stride slw): l_{w,t}; NULL = zero */
+    const double *c;                  /* N constants c_t (stride sc); NULL = zero      */
     const double *lN;                 /* nx terminal linear cost l_N; NULL = zero      */
     const double *cN;                 /* 1 terminal constant; NULL = zero              */
     /* solution (written) */
@@ -91,6 +97,10 @@ typedef struct rs_problem {
     double *w;                        /* N*nu inputs / process noise w_0..w_{N-1}       */
     double *lam;                      /* (N+1)*nx duals lam_0..lam_N                    */
     double *obj;                      /* 1 optimal value; NULL = not wanted            */
+    /* element strides between the stages of a, lx, lw and c (dense arrays:
+     * nx, nx, nu, 1; 0 = the same vector every stage).  With strides a
+     * window may live in stage-major records, as a serving ring does. */
+    int64_t sa, slx, slw, sc;
 } rs_problem;
 
 typedef struct rs_options {

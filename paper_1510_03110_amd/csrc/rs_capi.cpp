@@ -490,7 +490,8 @@ static rs_status bind_and_upload(rs_plan P, const rs_problem *probs, char *work,
         d.x0 = q.x0; d.a = q.a; d.lx = q.lx; d.lw = q.lw; d.c = q.c; d.lN = q.lN; d.cN = q.cN;
         d.x = q.x; d.w = q.w; d.lam = q.lam; d.obj = q.obj;
         d.sQx = q.sQx; d.sQw = q.sQw; d.sQxw = q.sQxw; d.sA = q.sA; d.sB = q.sB;
-        d.nx = q.nx; d.nu = q.nu; d.N = q.N;
+        d.sa = q.sa; d.slx = q.slx; d.slw = q.slw; d.sc = q.sc;
+        d.nx = q.nx; d.nu = q.nu; d.N = q.N; d.flags = q.flags;
     }
     if (P->mixed) {
         // correction problems: the same matrices; right-hand side and
@@ -507,6 +508,10 @@ static rs_status bind_and_upload(rs_plan P, const rs_problem *probs, char *work,
             d.lN = b + nx + 2 * N * nx + N * nu;
             d.c = nullptr;
             d.cN = nullptr;
+            d.sa = nx;
+            d.slx = nx;
+            d.slw = nu;
+            d.sc = 0;
             d.x = b + 2 * nx + 2 * N * nx + N * nu;
             d.w = d.x + (N + 1) * nx;
             d.lam = d.w + N * nu;
@@ -563,6 +568,7 @@ static rs_status check_call(rs_plan P, const rs_problem *probs, void *work, size
         if (q.nx != P->dims[3 * i] || q.nu != P->dims[3 * i + 1] || q.N != P->dims[3 * i + 2]) return RS_ERR_ARG;
         if (!valid_ptr_set(q)) return RS_ERR_ARG;
         if (q.sQx < 0 || q.sQw < 0 || q.sQxw < 0 || q.sA < 0 || q.sB < 0) return RS_ERR_ARG;
+        if (q.sa < 0 || q.slx < 0 || q.slw < 0 || q.sc < 0) return RS_ERR_ARG;
     }
     return RS_OK;
 }

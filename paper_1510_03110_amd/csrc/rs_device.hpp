@@ -37,6 +37,11 @@ __device__ __forceinline__ float bcast_lane(float v, int lane) {
 // compiler sees uniform control flow and keeps every barrier in lock-step.
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Instance excluded from this call (its descriptor carries PROB_SKIP).
+__device__ __forceinline__ bool inst_skipped(const DevProb *probs, int inst) {
+    return (uni(probs[inst].flags) & PROB_SKIP) != 0;
+}
+
 __device__ __forceinline__ double rs_sqrt(double v) { return sqrt(v); }
 __device__ __forceinline__ float rs_sqrt(float v) { return sqrtf(v); }
 
@@ -204,10 +209,14 @@ __device__ __forceinline__ DevProb load_prob(const DevProb *tab, int i) {
     u.sQxw = uni64(r.sQxw);
     u.sA = uni64(r.sA);
     u.sB = uni64(r.sB);
+    u.sa = uni64(r.sa);
+    u.slx = uni64(r.slx);
+    u.slw = uni64(r.slw);
+    u.sc = uni64(r.sc);
     u.nx = uni(r.nx);
     u.nu = uni(r.nu);
     u.N = uni(r.N);
-    u.pad = 0;
+    u.flags = uni(r.flags);
     return u;
 }
 
@@ -218,10 +227,10 @@ __device__ __forceinline__ StageSrc prob_stage(const DevProb &p, int t) {
     s.Qxw = p.Qxw ? p.Qxw + (int64_t)t * p.sQxw : nullptr;
     s.A = p.A + (int64_t)t * p.sA;
     s.B = p.B + (int64_t)t * p.sB;
-    s.a = p.a ? p.a + (int64_t)t * p.nx : nullptr;
-    s.lx = p.lx ? p.lx + (int64_t)t * p.nx : nullptr;
-    s.lw = p.lw ? p.lw + (int64_t)t * p.nu : nullptr;
-    s.c = p.c ? p.c[t] : 0.0;
+    s.a = p.a ? p.a + (int64_t)t * p.sa : nullptr;
+    s.lx = p.lx ? p.lx + (int64_t)t * p.slx : nullptr;
+    s.lw = p.lw ? p.lw + (int64_t)t * p.slw : nullptr;
+    s.c = p.c ? p.c[(int64_t)t * p.sc] : 0.0;
     return s;
 }
 

@@ -85,7 +85,7 @@ template <class T, int NX, int NU>
 __global__ void __launch_bounds__(NT) k_leaf_up(GroupArgs g) {
     __shared__ __attribute__((aligned(16))) char raw[LeafSmem<T, NX, NU>::bytes];
     const LeafItem it = load_leaf(g.leaves, blockIdx.x);
-    if (it.flags & LEAF_TOP) return;
+    if ((it.flags & LEAF_TOP) || inst_skipped(g.probs, it.inst)) return;
     const DevProb p = load_prob(g.probs, it.inst);
     const SlotLayout SL{NX};
     double *out = g.slots + (int64_t)it.slot * SL.size();
@@ -113,6 +113,7 @@ __global__ void __launch_bounds__(NT) k_leaf_down(GroupArgs g) {
     auto &S = *reinterpret_cast<Smem<T, NX, NU, false> *>(raw);
     using SC = LeafScratch<NX, NU>;
     const LeafItem it = load_leaf(g.leaves, blockIdx.x);
+    if (inst_skipped(g.probs, it.inst)) return;
     const DevProb p = load_prob(g.probs, it.inst);
     const SlotLayout SL{NX};
     const int tid = threadIdx.x;
@@ -270,7 +271,9 @@ __global__ void __launch_bounds__(NT) k_tree(GroupArgs g) {
         double *slots = g.slots;
         auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
         auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };
-        if (it.kind == ITEM_UP) {
+        if (inst_skipped(g.probs, it.inst)) {
+            // excluded instance: only its completion flag is published
+        } else if (it.kind == ITEM_UP) {
             auto &S = *reinterpret_cast<Smem<double, NX, NX, true> *>(raw);
             reduce_pass<double, NX, NX>(S, get, it.count, slot(it.out_slot), g.info, it.inst, -1);
         } else if (it.kind == ITEM_UP_LAST) {

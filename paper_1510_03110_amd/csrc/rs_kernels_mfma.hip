@@ -242,7 +242,7 @@ template <int NX, int NU>
 __global__ void __launch_bounds__(NT, 2) km_leaf_up(GroupArgs g) {
     __shared__ __attribute__((aligned(16))) char raw[Sizes<NX, NU>::up];
     const LeafItem it = load_leaf_u(g.leaves, blockIdx.x);
-    if (it.flags & LEAF_TOP) return;
+    if ((it.flags & LEAF_TOP) || inst_skipped(g.probs, it.inst)) return;
     const DevProb p = load_prob(g.probs, it.inst);
     const SlotLayout SL{NX};
     double *out = g.slots + (int64_t)it.slot * SL.size();
@@ -279,6 +279,7 @@ __global__ void __launch_bounds__(NT, 3) km_leaf_down(GroupArgs g) {
     auto &S = *reinterpret_cast<MSmem<double, NX, NU, false, true> *>(raw);
     using LF = LeafFac<NX, NU>;
     const LeafItem it = load_leaf_u(g.leaves, blockIdx.x);
+    if (inst_skipped(g.probs, it.inst)) return;
     const DevProb p = load_prob(g.probs, it.inst);
     const SlotLayout SL{NX};
     const int tid = threadIdx.x;
@@ -451,7 +452,9 @@ __global__ void __launch_bounds__(NT) km_tree(GroupArgs g) {
         double *slots = g.slots;
         auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
         auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };
-        if (it.kind == ITEM_UP) {
+        if (inst_skipped(g.probs, it.inst)) {
+            // excluded instance: only its completion flag is published
+        } else if (it.kind == ITEM_UP) {
             auto &S = *reinterpret_cast<MSmem<double, NX, NX, true, false> *>(raw);
             reduce_to<NX, NX>(S, get, it.count, slot(it.out_slot), g.info, it.inst, -1, 3);
         } else if (it.kind == ITEM_UP_LAST) {
@@ -543,7 +546,7 @@ template <class T, int NX, int NU>
 __global__ void __launch_bounds__(NT, 2) kf_leaf_up(GroupArgs g) {
     __shared__ __attribute__((aligned(16))) char raw[FSizes<T, NX, NU>::up];
     const LeafItem it = load_leaf_u(g.leaves, blockIdx.x);
-    if (it.flags & LEAF_TOP) return;
+    if ((it.flags & LEAF_TOP) || inst_skipped(g.probs, it.inst)) return;
     const DevProb p = load_prob(g.probs, it.inst);
     const SlotLayout SL{NX};
     double *out = g.slots + (int64_t)it.slot * SL.size();
@@ -581,6 +584,7 @@ __global__ void __launch_bounds__(NT, 3) kf_leaf_down(GroupArgs g) {
     __shared__ __attribute__((aligned(16))) char raw[sizeof(MSmem<T, NX, NU, false, true>)];
     auto &S = *reinterpret_cast<MSmem<T, NX, NU, false, true> *>(raw);
     const LeafItem it = load_leaf_u(g.leaves, blockIdx.x);
+    if (inst_skipped(g.probs, it.inst)) return;
     const DevProb p = load_prob(g.probs, it.inst);
     const SlotLayout SL{NX};
     const bool known_end = (it.flags & (LEAF_LAST | LEAF_TOP)) != 0;
@@ -623,7 +627,9 @@ __global__ void __launch_bounds__(NT) kf_tree(GroupArgs g) {
         double *slots = g.slots;
         auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
         auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };
-        if (it.kind == ITEM_UP) {
+        if (inst_skipped(g.probs, it.inst)) {
+            // excluded instance: only its completion flag is published
+        } else if (it.kind == ITEM_UP) {
             auto &S = *reinterpret_cast<MSmem<double, NX, NX, true, false> *>(raw);
             for (int e = tid; e < NX * NX; e += NT) {
                 S.P[e] = 0.0;

@@ -80,10 +80,10 @@ __global__ void __launch_bounds__(RT) kr_residual(GroupArgs g) {
         oQw.template load<false>(Qw, NU);
         const double xi = l < NX ? x[l] : 0.0, wi = l < NU ? w[l] : 0.0;
         const double lami = l < NX ? lam[l] : 0.0, xni = l < NX ? xn[l] : 0.0;
-        const double lxi = (l < NX && p.lx) ? p.lx[(int64_t)t * NX + l] : 0.0;
-        const double lwi = (l < NU && p.lw) ? p.lw[(int64_t)t * NU + l] : 0.0;
-        const double ai = (l < NX && p.a) ? p.a[(int64_t)t * NX + l] : 0.0;
-        const double ct = p.c ? p.c[t] : 0.0;
+        const double lxi = (l < NX && p.lx) ? p.lx[(int64_t)t * p.slx + l] : 0.0;
+        const double lwi = (l < NU && p.lw) ? p.lw[(int64_t)t * p.slw + l] : 0.0;
+        const double ai = (l < NX && p.a) ? p.a[(int64_t)t * p.sa + l] : 0.0;
+        const double ct = p.c ? p.c[(int64_t)t * p.sc] : 0.0;
         if (l < NX) {
             xs[l] = xi;
             ls[l] = lamn[l];
@@ -98,15 +98,15 @@ __global__ void __launch_bounds__(RT) kr_residual(GroupArgs g) {
         if (l < NX) {
             const double dlx = lxi + qx + qxw - lami + atl;
             const double da = ai + ax + bw - xni;
-            const_cast<double *>(c.lx)[(int64_t)t * NX + l] = dlx;
-            const_cast<double *>(c.a)[(int64_t)t * NX + l] = da;
+            const_cast<double *>(c.lx)[(int64_t)t * c.slx + l] = dlx;
+            const_cast<double *>(c.a)[(int64_t)t * c.sa + l] = da;
             rhs = fmax(rhs, fmax(fabs(lxi), fabs(ai)));
             res = fmax(res, fmax(fabs(dlx), fabs(da)));
             part += xi * (0.5 * qx + qxw + lxi);
         }
         if (l < NU) {
             const double dlw = lwi + qxwt + qw + btl;
-            const_cast<double *>(c.lw)[(int64_t)t * NU + l] = dlw;
+            const_cast<double *>(c.lw)[(int64_t)t * c.slw + l] = dlw;
             rhs = fmax(rhs, fabs(lwi));
             res = fmax(res, fabs(dlw));
             part += wi * (0.5 * qw + lwi);
@@ -220,7 +220,7 @@ __global__ void kr_check(const InstInfo *tab, int count, const double *part, dou
     if (i >= count) return;
     double *st = stats + (int64_t)i * ST_N;
     if (mode == 0) {
-        conv[i] = info[2 * i] != STATUS_OK ? 1 : 0;
+        conv[i] = (info[2 * i] != STATUS_OK || (probs[i].flags & PROB_SKIP)) ? 1 : 0;
         for (int q = 0; q < ST_N; ++q) st[q] = 0.0;
         st[ST_EST] = 1.0;
         st[ST_DZ] = 1.0;      // the first solve is taken as 100% wrong

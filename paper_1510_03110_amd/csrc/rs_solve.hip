@@ -187,10 +187,10 @@ __device__ __forceinline__ VSrc<TR> prob_src(const Prob &p, int t) {
     q.Vn = nullptr;
     q.A = p.A + (int64_t)t * p.sA;
     q.B = p.B + (int64_t)t * p.sB;
-    q.a = p.a ? p.a + (int64_t)t * NX : nullptr;
-    q.lx = p.lx ? p.lx + (int64_t)t * NX : nullptr;
-    q.lw = p.lw ? p.lw + (int64_t)t * NU : nullptr;
-    q.c = p.c ? p.c[t] : 0.0;
+    q.a = p.a ? p.a + (int64_t)t * p.sa : nullptr;
+    q.lx = p.lx ? p.lx + (int64_t)t * p.slx : nullptr;
+    q.lw = p.lw ? p.lw + (int64_t)t * p.slw : nullptr;
+    q.c = p.c ? p.c[(int64_t)t * p.sc] : 0.0;
     return q;
 }
 
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(WT) kv_leaf_down(GroupArgs g) {
         double lam = 0.0, w = 0.0;
         if (l < NX) p.x[(int64_t)t * NX + l] = S.x[l];
         fstage<NX, NU, true>(S, dn + R.K(), vec + NX, p.A + (int64_t)t * p.sA, p.B + (int64_t)t * p.sB,
-                             p.a ? p.a + (int64_t)t * NX : nullptr, dn + R.P(), vec, lam, w);
+                             p.a ? p.a + (int64_t)t * p.sa : nullptr, dn + R.P(), vec, lam, w);
         if (l < NX) p.lam[(int64_t)t * NX + l] = lam;
         if (l < NU) p.w[(int64_t)t * NU + l] = w;
     }

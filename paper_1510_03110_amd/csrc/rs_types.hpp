@@ -14,8 +14,10 @@ struct DevProb {
     const double *x0, *a, *lx, *lw, *c, *lN, *cN;
     double *x, *w, *lam, *obj;
     int64_t sQx, sQw, sQxw, sA, sB;
-    int32_t nx, nu, N, pad;
+    int64_t sa, slx, slw, sc;       // element strides of the stage vectors
+    int32_t nx, nu, N, flags;    // flags: PROB_SKIP leaves the instance untouched
 };
+constexpr int32_t PROB_SKIP = 1;
 
 // One leaf (level-0 subproblem, a batch of original stages, Sec. 4.1).
 struct LeafItem {

@@ -92,7 +92,7 @@ __device__ __forceinline__ LeafItem load_leaf(const LeafItem *tab, int i) {
 struct Prob {
     const double *Qx, *Qw, *Qxw, *A, *B, *QxN, *x0, *a, *lx, *lw, *c, *lN, *cN;
     double *x, *w, *lam, *obj;
-    int64_t sQx, sQw, sQxw, sA, sB;
+    int64_t sQx, sQw, sQxw, sA, sB, sa, slx, slw, sc;
 };
 __device__ __forceinline__ Prob load_prob(const DevProb *tab, int i) {
     const DevProb &d = tab[i];
@@ -119,12 +119,17 @@ __device__ __forceinline__ Prob load_prob(const DevProb *tab, int i) {
     p.sQxw = uni64(d.sQxw);
     p.sA = uni64(d.sA);
     p.sB = uni64(d.sB);
+    p.sa = uni64(d.sa);
+    p.slx = uni64(d.slx);
+    p.slw = uni64(d.slw);
+    p.sc = uni64(d.sc);
     return p;
 }
 
-// A converged instance (mixed-precision refinement) is skipped.
+// An instance excluded from the call, or converged in the mixed-precision
+// refinement, is skipped.
 __device__ __forceinline__ bool skip_inst(const GroupArgs &g, int inst) {
-    return g.conv && uni(g.conv[inst]) != 0;
+    return (uni(g.probs[inst].flags) & PROB_SKIP) != 0 || (g.conv && uni(g.conv[inst]) != 0);
 }
 
 }  // namespace sv

@@ -19,6 +19,7 @@ RS_OK, RS_ERR_ARG, RS_ERR_NOT_SPD, RS_ERR_SINGULAR_MASTER, RS_ERR_NOT_CONVERGED,
     RS_ERR_NOMEM, RS_ERR_HIP, RS_ERR_UNSUPPORTED = range(8)
 RS_FP64, RS_MIXED_FP32 = 0, 1
 RS_PLAN_FACTORED = 1
+RS_PROB_SKIP = 1
 RS_KERNEL_KINDS = 16
 
 _P = ctypes.c_void_p
@@ -26,12 +27,13 @@ _P = ctypes.c_void_p
 
 class rs_problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("nu", ctypes.c_int32), ("N", ctypes.c_int32),
-                ("reserved", ctypes.c_int32),
+                ("flags", ctypes.c_int32),
                 ("Qx", _P), ("sQx", ctypes.c_int64), ("Qw", _P), ("sQw", ctypes.c_int64),
                 ("Qxw", _P), ("sQxw", ctypes.c_int64), ("A", _P), ("sA", ctypes.c_int64),
                 ("B", _P), ("sB", ctypes.c_int64), ("QxN", _P),
                 ("x0", _P), ("a", _P), ("lx", _P), ("lw", _P), ("c", _P), ("lN", _P), ("cN", _P),
-                ("x", _P), ("w", _P), ("lam", _P), ("obj", _P)]
+                ("x", _P), ("w", _P), ("lam", _P), ("obj", _P),
+                ("sa", ctypes.c_int64), ("slx", ctypes.c_int64), ("slw", ctypes.c_int64), ("sc", ctypes.c_int64)]
 
 
 class rs_options(ctypes.Structure):
@@ -273,6 +275,11 @@ class Batch:
             for k in _VECS:
                 t = d.get(k)
                 setattr(p, k, t.data_ptr() if t is not None else None)
+            # stage vectors: dense, or one vector for every stage (stage axis 1)
+            for k, bs in (("a", nx), ("lx", nx), ("lw", nu), ("c", 1)):
+                t = d.get(k)
+                one = t is not None and t.numel() == bs and N > 1
+                setattr(p, "s" + k, 0 if one else bs)
             p.x = self.x[i].data_ptr()
             p.w = self.w[i].data_ptr()
             p.lam = self.lam[i].data_ptr()
@@ -292,6 +299,10 @@ class Batch:
     def solve_factored(self):
         rs_solve(self.plan, self.probs, self.work_ptr, self.work_bytes, self.stream_ptr(),
                  self.info.data_ptr())
+
+    def set_skip(self, i, skip=True):
+        """Exclude instance i from the following calls (RS_PROB_SKIP)."""
+        self.probs[i].flags = RS_PROB_SKIP if skip else 0
 
     def refine_stats(self):
         return rs_refine_stats(self.plan, self.work_ptr, self.count, self.stream_ptr())
