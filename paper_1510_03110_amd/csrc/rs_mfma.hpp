@@ -324,6 +324,81 @@ __device__ __forceinline__ int chol_inv_wave(T *G, T *LiT) {
     return fail;
 }
 
+// 32 x 32 version of chol_inv_wave by 2 x 2 blocks of 16, run by the whole
+// workgroup (every thread must call it):
+//   L11 = chol(G11), L21 = G21 L11^{-T}, L22 = chol(G22 - L21 L21'),
+//   L^{-1} = [L11^{-1}, 0; -L22^{-1} L21 L11^{-1}, L22^{-1}].
+// The two 16 x 16 factorizations are chol_inv_wave<16> on wave 0 (a shorter
+// dependency chain and a quarter of the registers of the 32 x 32 sweep); the
+// block products are single 16x16 matrix-core tiles.  `side` is run by
+// waves 1-3 while wave 0 factors the first block.  LiT and G serve as
+// scratch (four 16 x 16 blocks in LiT, three in G).  On return G holds
+// L^{-1} and LiT holds L^{-T}, row-major; *bad is set if a pivot failed.
+template <class T, class Side>
+__device__ __forceinline__ void chol_inv_block32(T *G, T *LiT, int *bad, Side side) {
+    constexpr int M = 32, H = 16;
+    const int tid = threadIdx.x, w = wave(), l = lane();
+    T *T0 = LiT, *T1 = LiT + 256, *T2 = LiT + 512, *T3 = LiT + 768;   // L11^-1, L11^-T, L21, G22 - L21 L21'
+    T *Gt = G, *Gm = G + 256, *Gc = G + 512;                         // L22^-T, L21 L11^-1, C
+    for (int e = tid; e < H * H; e += NT) T0[e] = G[(e / H) * M + e % H];
+    __syncthreads();
+    if (w == 0) {
+        int f = chol_inv_wave<H>(T0, T1);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // L21 = G21 L11^{-T}
+        v4_t<T> acc = mma<H, false, false>(zero4<T>(), G + H * M, M, T1, H, 0, 0);
+        tile_for<T>(0, 0, [&](int r, int i, int j) { T2[i * H + j] = acc[r]; });
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // Schur complement G22 - L21 L21'
+        acc = mma<H, false, true>(zero4<T>(), T2, H, T2, H, 0, 0);
+        tile_for<T>(0, 0, [&](int r, int i, int j) { T3[i * H + j] = G[(H + i) * M + H + j] - acc[r]; });
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        f |= chol_inv_wave<H>(T3, Gt);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // C = -L22^{-1} (L21 L11^{-1})
+        acc = mma<H, false, false>(zero4<T>(), T2, H, T0, H, 0, 0);
+        tile_for<T>(0, 0, [&](int r, int i, int j) { Gm[i * H + j] = acc[r]; });
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        acc = mma<H, false, false>(zero4<T>(), T3, H, Gm, H, 0, 0);
+        tile_for<T>(0, 0, [&](int r, int i, int j) { Gc[i * H + j] = -acc[r]; });
+        if (f && l == 0) *bad = 1;
+    } else {
+        side();
+    }
+    __syncthreads();
+    constexpr int R = M * M / NT;
+    T li[R], lt[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int e = tid + q * NT, i = e / M, j = e % M;
+        const int bi = i & (H - 1), bj = j & (H - 1);
+        if (i < H) {
+            li[q] = j < H ? T0[bi * H + bj] : T(0);
+            lt[q] = j < H ? T1[bi * H + bj] : Gc[bj * H + bi];
+        } else {
+            li[q] = j < H ? Gc[bi * H + bj] : T3[bi * H + bj];
+            lt[q] = j < H ? T(0) : Gt[bi * H + bj];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int e = tid + q * NT;
+        G[e] = li[q];
+        LiT[e] = lt[q];
+    }
+}
+
 // Wave-level sum over the 64 lanes (result in every lane).
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -440,14 +515,23 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
         }
         __syncthreads();
         // ---- phase C: factor and invert G (wave 0); (RED) A'V into W (waves 1-3)
-        if (w == 0) {
-            const int f = chol_inv_wave<NU>(S.G, S.LiT);
-            if (f && l == 0) S.bad = 1;
-        } else if constexpr (RED) {
-            for (int t = w - 1; t < TX * TX; t += 3) {
-                const int ti = t / TX, tj = t % TX;
-                v4_t<T> acc = mma<NX, true, false>(zero4<T>(), S.A, NX, S.V, NX, ti, tj);
-                tile_for<T>(ti, tj, [&](int r, int i, int j) { S.W[i * NX + j] = acc[r]; });
+        auto av_tiles = [&]() {
+            if constexpr (RED) {
+                for (int t = w - 1; t < TX * TX; t += 3) {
+                    const int ti = t / TX, tj = t % TX;
+                    v4_t<T> acc = mma<NX, true, false>(zero4<T>(), S.A, NX, S.V, NX, ti, tj);
+                    tile_for<T>(ti, tj, [&](int r, int i, int j) { S.W[i * NX + j] = acc[r]; });
+                }
+            }
+        };
+        if constexpr (NU == 32) {
+            chol_inv_block32(S.G, S.LiT, &S.bad, av_tiles);
+        } else {
+            if (w == 0) {
+                const int f = chol_inv_wave<NU>(S.G, S.LiT);
+                if (f && l == 0) S.bad = 1;
+            } else {
+                av_tiles();
             }
         }
         __syncthreads();
