@@ -38,19 +38,27 @@ def log(*a):
 
 # ------------------------------------------------ algorithmic work per stage
 def flops_reduce(n, m):
-    """Alg. 4 stage as executed by the leaf reduction (dense products counted
-    in full): 6n^3 + 12n^2 m + 4n m^2 + m^3/3 + 6n^2 + 6nm + m^2."""
-    return 6 * n ** 3 + 12 * n * n * m + 4 * n * m * m + m ** 3 / 3 + 6 * n * n + 6 * n * m + m * m
+    """Alg. 4 stage as executed by the leaf reduction, dense products counted
+    in full, including K, k and L = -G^{-1} B'V that it stores for the leaf
+    solve: 6n^3 + 12n^2 m + 6n m^2 + m^3/3 + 6n^2 + 6nm + 3m^2."""
+    return 6 * n ** 3 + 12 * n * n * m + 6 * n * m * m + m ** 3 / 3 + 6 * n * n + 6 * n * m + 3 * m * m
 
 
 def flops_elim(n, m):
-    """Alg. 1-2 stage (last leaf): 4n^3 + 6n^2 m + 3n m^2 + m^3/3 + 4n^2 + 4nm + m^2."""
-    return 4 * n ** 3 + 6 * n * n * m + 3 * n * m * m + m ** 3 / 3 + 4 * n * n + 4 * n * m + m * m
+    """Alg. 1-2 stage (last leaf, with K and k stored):
+    4n^3 + 6n^2 m + 4n m^2 + m^3/3 + 4n^2 + 4nm + 3m^2."""
+    return 4 * n ** 3 + 6 * n * n * m + 4 * n * m * m + m ** 3 / 3 + 4 * n * n + 4 * n * m + 3 * m * m
 
 
 def flops_solve(n, m):
-    """Alg. 1-3 stage (leaf solve): 4n^3 + 6n^2 m + 4n m^2 + m^3/3 + 8n^2 + 8nm + 2m^2."""
+    """Alg. 1-3 stage (whole-problem leaf): 4n^3 + 6n^2 m + 4n m^2 + m^3/3 + 8n^2 + 8nm + 2m^2."""
     return 4 * n ** 3 + 6 * n * n * m + 4 * n * m * m + m ** 3 / 3 + 8 * n * n + 8 * n * m + 2 * m * m
+
+
+def flops_forward(n, m):
+    """Leaf solve as a forward sweep on the stored preliminary solution:
+    K x, L lam_N, P x, V lam_N, A x, B w: 6n^2 + 6nm."""
+    return 6 * n * n + 6 * n * m
 
 
 def flops_serial(n, m):
@@ -128,13 +136,14 @@ def cpu_baseline(host_probs, seconds):
     return done, el, threads
 
 
-def leaf_work(leaves, n, m, up_fn, elim_fn, down_fn):
+def leaf_work(leaves, n, m, up_fn, elim_fn, down_fn, top_fn=None):
     """Per-launch algorithmic FLOPs of the leaf kernels from the plan's leaf
-    table: up = reduction (or elimination for the last leaf), down = solve."""
+    table: up = reduction (or elimination for the last leaf), down = solve
+    (top_fn for a leaf that is a whole instance)."""
     up = down = 0.0
     for lf in leaves:
         ln, fl = int(lf[2]), int(lf[3])
-        down += ln * down_fn(n, m)
+        down += ln * ((top_fn or down_fn)(n, m) if fl & 2 else down_fn(n, m))
         if fl & 2:
             continue
         up += ln * (elim_fn(n, m) if fl & 1 else up_fn(n, m))
@@ -185,7 +194,7 @@ def run_precision(prec, args, data, dev):
     # ------------------------------------------------ roofline (dominant)
     leaves = rs.rs_plan_export(batch.plan, 0)
     if not mixed:
-        up, down = leaf_work(leaves, n, m, flops_reduce, flops_elim, flops_solve)
+        up, down = leaf_work(leaves, n, m, flops_reduce, flops_elim, flops_forward, flops_solve)
         work = {"leaf_up": ("alu", up, FP64_PEAK_TFLOPS, "km_leaf_up"),
                 "leaf_down": ("alu", down, FP64_PEAK_TFLOPS, "km_leaf_down")}
     else:

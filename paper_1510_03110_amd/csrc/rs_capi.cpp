@@ -31,6 +31,7 @@ struct Group {
     int max_depth = 0;
     int64_t leaf_stages = 0;
     int32_t leaf_base = 0;                  // global index of the group's first leaf
+    int32_t ntop = 0;                       // single-leaf instances
     size_t off_leaves = 0, off_items = 0, off_flags = 0, off_slots = 0, off_scratch = 0, off_fstore = 0,
            off_fvec = 0;
 };
@@ -323,6 +324,7 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
             in.N = dims[3 * inst + 2];
         }
         P->total_leaves += (int32_t)g.leaves.size();
+        for (auto &lf : g.leaves) g.ntop += (lf.flags & LEAF_TOP) ? 1 : 0;
         finalize_items(g, tmp);
     }
     // workspace layout
@@ -591,6 +593,7 @@ static GroupArgs group_args(rs_plan P, char *W, size_t gi, int32_t *info, bool c
     a.info = info;
     a.epoch = P->epoch;
     a.sps = g.shape->scratch_per_stage;
+    a.ntop = g.ntop;
     a.fstore = P->factored ? W + g.off_fstore : nullptr;
     a.fvec = P->factored ? reinterpret_cast<double *>(W + g.off_fvec) : nullptr;
     if (P->mixed) {

@@ -372,7 +372,7 @@ const ShapeEntry *find_shape(int nx, int nu) {
                 }
             e.refine[0] = refine_kernel(a, b, 0);
             e.refine[1] = refine_kernel(a, b, 1);
-            e.scratch_per_stage = scratch_per_stage(a, b);
+            e.scratch_per_stage = mfma_leaf_down(a, b) ? scratch_per_stage_fwd(a, b) : scratch_per_stage(a, b);
             if (e.fp64[0] && e.fp64[1] && e.fp64[2]) table[n++] = e;
         };
         for (const auto &g : generic_table) add(g.nx, g.nu, g.up, g.tree, g.down);

@@ -51,9 +51,9 @@ struct Sizes {
 };
 
 // Reduce (Alg. 4) and write the M1 message.
-template <int NX, int NU, class Get>
+template <int NX, int NU, class Get, class Out = NoEmit>
 __device__ void reduce_to(MSmem<double, NX, NU, true, false> &S, Get get, int count, double *out, int32_t *info, int inst,
-                          int stage_base, int fail_code) {
+                          int stage_base, int fail_code, Out emit = Out{}) {
     const int tid = threadIdx.x;
     for (int e = tid; e < NX * NX; e += NT) {
         S.P[e] = 0.0;
@@ -66,7 +66,7 @@ __device__ void reduce_to(MSmem<double, NX, NU, true, false> &S, Get get, int co
     }
     if (tid == 0) S.cbar = 0.0;
     __syncthreads();
-    mfma_pass(S, get, count, info, inst, stage_base, fail_code, [](int, auto &) {}, NoEmit{});
+    mfma_pass(S, get, count, info, inst, stage_base, fail_code, [](int, auto &) {}, emit);
     const SlotLayout SL{NX};
     for (int e = tid; e < NX * NX; e += NT) {
         const int i = e / NX, j = e % NX;
@@ -83,11 +83,11 @@ __device__ void reduce_to(MSmem<double, NX, NU, true, false> &S, Get get, int co
 
 // Eliminate a subproblem with known terminal (already in S) and write the
 // terminal cost it passes up (Sec. 4.2, last subproblem).
-template <int NX, int NU, class Get>
+template <int NX, int NU, class Get, class Out = NoEmit>
 __device__ void eliminate_to(MSmem<double, NX, NU, false, false> &S, Get get, int count, double *out, int32_t *info,
-                             int inst, int stage_base, int fail_code) {
+                             int inst, int stage_base, int fail_code, Out emit = Out{}) {
     const int tid = threadIdx.x;
-    mfma_pass(S, get, count, info, inst, stage_base, fail_code, [](int, auto &) {}, NoEmit{});
+    mfma_pass(S, get, count, info, inst, stage_base, fail_code, [](int, auto &) {}, emit);
     const SlotLayout SL{NX};
     for (int e = tid; e < NX * NX; e += NT) out[SL.Qx() + e] = S.P[e];
     for (int i = tid; i < NX; i += NT) out[SL.lx() + i] = -S.Psi[i];
@@ -237,6 +237,38 @@ __device__ void forward_m(MSmem<double, NX, NU, false, true> &S, Get get, int co
     }
 }
 
+// Per-stage record of a leaf in the fused solve (leaf scratch), doubles:
+//   K_{t+1} (NU*NX) | k_{t+1} (NU) | P_t (NX*NX) | Psi_t (NX) | V_t (NX*NX) | L_{t+1} (NU*NX)
+// Written by the leaf reduction: the preliminary solution of Alg. 4 (P = 0
+// terminal) with V_t and L_{t+1} = -G^{-1} B' V_{t+1}; for the last leaf (true
+// terminal) the first four fields only.  The leaf solve of the whole problem
+// (single-leaf instances) writes the first four fields itself.
+template <int NX, int NU>
+struct LeafFac {
+    const double *base;
+    static constexpr int K_ = 0, k_ = NU * NX, P_ = NU * NX + NU, Psi_ = NU * NX + NU + NX * NX,
+                         V_ = Psi_ + NX, L_ = V_ + NX * NX, per = L_ + NU * NX;
+    __device__ const double *K(int s) const { return base + (int64_t)s * per + K_; }
+    __device__ const double *k(int s) const { return base + (int64_t)s * per + k_; }
+    __device__ const double *P(int s) const { return base + (int64_t)s * per + P_; }
+    __device__ const double *Psi(int s) const { return base + (int64_t)s * per + Psi_; }
+};
+
+// Writer of those records from the lanes that form each quantity.
+template <int NX, int NU, bool RED>
+struct LeafRecOut : NoEmit {
+    static constexpr bool KF = true, PF = true, VF = RED, LTF = RED, PSF = true, KVF = true;
+    double *base;
+    using Rec = LeafFac<NX, NU>;
+    __device__ double *at(int s) const { return base + (int64_t)s * Rec::per; }
+    __device__ void K(int s, int i, int j, double v) const { at(s)[Rec::K_ + i * NX + j] = v; }
+    __device__ void k(int s, int i, double v) const { at(s)[Rec::k_ + i] = v; }
+    __device__ void P(int s, int i, int j, double v) const { at(s)[Rec::P_ + i * NX + j] = v; }
+    __device__ void Psi(int s, int i, double v) const { at(s)[Rec::Psi_ + i] = v; }
+    __device__ void V(int s, int i, int j, double v) const { at(s)[Rec::V_ + i * NX + j] = v; }
+    __device__ void Lt(int s, int i, int j, double v) const { at(s)[Rec::L_ + i * NX + j] = v; }
+};
+
 // ------------------------------------------------------------------ leaves
 template <int NX, int NU>
 __global__ void __launch_bounds__(NT, 2) km_leaf_up(GroupArgs g) {
@@ -247,9 +279,10 @@ __global__ void __launch_bounds__(NT, 2) km_leaf_up(GroupArgs g) {
     const SlotLayout SL{NX};
     double *out = g.slots + (int64_t)it.slot * SL.size();
     auto get = [&](int s) { return prob_stage(p, it.t0 + s); };
+    double *rec = reinterpret_cast<double *>(g.leaf_scratch) + it.scratch;
     if (!(it.flags & LEAF_LAST)) {
         auto &S = *reinterpret_cast<MSmem<double, NX, NU, true, false> *>(raw);
-        reduce_to<NX, NU>(S, get, it.len, out, g.info, it.inst, it.t0, 2);
+        reduce_to<NX, NU>(S, get, it.len, out, g.info, it.inst, it.t0, 2, LeafRecOut<NX, NU, true>{{}, rec});
     } else {
         auto &S = *reinterpret_cast<MSmem<double, NX, NU, false, false> *>(raw);
         const int tid = threadIdx.x;
@@ -257,21 +290,9 @@ __global__ void __launch_bounds__(NT, 2) km_leaf_up(GroupArgs g) {
         for (int i = tid; i < NX; i += NT) S.Psi[i] = p.lN ? -p.lN[i] : 0.0;
         if (tid == 0) S.cbar = p.cN ? p.cN[0] : 0.0;
         __syncthreads();
-        eliminate_to<NX, NU>(S, get, it.len, out, g.info, it.inst, it.t0, 2);
+        eliminate_to<NX, NU>(S, get, it.len, out, g.info, it.inst, it.t0, 2, LeafRecOut<NX, NU, false>{{}, rec});
     }
 }
-
-// Leaf-solve scratch per stage: K (NU*NX) | k (NU) | P (NX*NX) | Psi (NX)
-template <int NX, int NU>
-struct LeafFac {
-    const double *base;
-    static constexpr int K_ = 0, k_ = NU * NX, P_ = NU * NX + NU, Psi_ = NU * NX + NU + NX * NX,
-                         per = NU * NX + NU + NX * NX + NX;
-    __device__ const double *K(int s) const { return base + (int64_t)s * per + K_; }
-    __device__ const double *k(int s) const { return base + (int64_t)s * per + k_; }
-    __device__ const double *P(int s) const { return base + (int64_t)s * per + P_; }
-    __device__ const double *Psi(int s) const { return base + (int64_t)s * per + Psi_; }
-};
 
 template <int NX, int NU>
 __global__ void __launch_bounds__(NT, 3) km_leaf_down(GroupArgs g) {
@@ -279,7 +300,9 @@ __global__ void __launch_bounds__(NT, 3) km_leaf_down(GroupArgs g) {
     auto &S = *reinterpret_cast<MSmem<double, NX, NU, false, true> *>(raw);
     using LF = LeafFac<NX, NU>;
     const LeafItem it = load_leaf_u(g.leaves, blockIdx.x);
-    if (inst_skipped(g.probs, it.inst)) return;
+    // leaves of multi-leaf instances are finished by the forward sweep on
+    // the stored records (leaf_forward)
+    if (!(it.flags & LEAF_TOP) || inst_skipped(g.probs, it.inst)) return;
     const DevProb p = load_prob(g.probs, it.inst);
     const SlotLayout SL{NX};
     const int tid = threadIdx.x;
@@ -688,9 +711,13 @@ hipError_t launch_tree_m(const GroupArgs &g, int grid, hipStream_t st) {
     return hipGetLastError();
 }
 template <int NX, int NU>
-hipError_t launch_leaf_down_m(const GroupArgs &g, int, hipStream_t st) {
-    hipLaunchKernelGGL((km_leaf_down<NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
-    return hipGetLastError();
+hipError_t launch_leaf_down_m(const GroupArgs &g, int grid, hipStream_t st) {
+    if (g.ntop > 0) {
+        hipLaunchKernelGGL((km_leaf_down<NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return leaf_forward(NX, NU)(g, grid, st);
 }
 
 template <class T, int NX, int NU>

@@ -9,6 +9,9 @@ namespace rs {
 
 // Per-stage element count of the leaf solve's scratch (K, k, P, Psi).
 constexpr int scratch_per_stage(int nx, int nu) { return nu * nx + nu + nx * nx + nx; }
+// Matrix-core leaves also keep V and L of Alg. 4 (leaf solve by a forward
+// sweep on the stored preliminary solution).
+constexpr int scratch_per_stage_fwd(int nx, int nu) { return 2 * nu * nx + nu + 2 * nx * nx + nx; }
 
 typedef hipError_t (*Launcher)(const GroupArgs &, int grid, hipStream_t);
 
@@ -34,6 +37,7 @@ struct ShapeEntry {
 Launcher mfma_factor(int nx, int nu, int which, bool fp32);
 Launcher vector_solve(int nx, int nu, int which, bool fp32);
 Launcher refine_kernel(int nx, int nu, int which);       // 0 residual, 1 update
+Launcher leaf_forward(int nx, int nu);                   // leaf solve on the stored leaf records
 hipError_t launch_refine_check(const InstInfo *tab, int count, const double *part, double *stats, int32_t *conv,
                                int32_t *info, const DevProb *probs, int mode, double tol, hipStream_t st);
 

@@ -160,9 +160,13 @@ struct MSmem {
 //   VEC  form the vector (right-hand side) quantities of Alg. 2 / Alg. 4
 //   KF   form K_{t+1} = -G^{-1} H' also in the reduction (for a later solve)
 //   PF, LF, VF  emit P_t, L^{-1} and V_t (stored factorization)
+//   LTF  (Alg. 4) form and emit L_{t+1} = -G^{-1} B' V_{t+1} (= -L^{-T} X)
+//   PSF, KVF  emit Psi_t and k_{t+1} also outside the solve pass
 // The default does nothing and keeps the vector work (fused solve).
 struct NoEmit {
-    static constexpr bool VEC = true, KF = false, PF = false, LF = false, VF = false;
+    static constexpr bool VEC = true, KF = false, PF = false, LF = false, VF = false, LTF = false, PSF = false,
+                          KVF = false;
+    __device__ void Lt(int, int, int, double) const {}
     __device__ void K(int, int, int, double) const {}
     __device__ void P(int, int, int, double) const {}
     template <class U>
@@ -422,6 +426,7 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
     static_assert(NX <= 64 && NU <= 64, "per-wave vector roles assume NX, NU <= 64");
     constexpr int NW = NX + NU, TX = NX / 16, TU = NU / 16;
     constexpr bool VEC = Out::VEC, KFORM = SOLVE || Out::KF, PEMIT = SOLVE || Out::PF;
+    constexpr bool LTFORM = RED && Out::LTF, PSEMIT = SOLVE || Out::PSF, KVEC = VEC && (SOLVE || Out::KVF);
     const int tid = threadIdx.x, w = wave(), l = lane();
     count = uni(count);
     Prefetch<T, NX, NU> pf;
@@ -566,8 +571,8 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
         //      Psi = g_x - Y'z, (RED) v += V'a + X'z, cbar -= z'z/2
         {
             constexpr int TL = TX * (TX + 1) / 2, TQ = RED ? TL : 0, TV = RED ? TX * TX : 0,
-                          TK = KFORM ? TU * TX : 0;
-            for (int t = w; t < TL + TQ + TV + TK; t += 4) {
+                          TK = KFORM ? TU * TX : 0, TLT = LTFORM ? TU * TX : 0;
+            for (int t = w; t < TL + TQ + TV + TK + TLT; t += 4) {
                 if (t < TL) {
                     int ti, tj;
                     lower_tile(t, ti, tj);
@@ -602,11 +607,17 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
                             if constexpr (Out::VF) out.V(s, i, j, v);
                         });
                     }
-                } else {
+                } else if (t < TL + TQ + TV + TK) {
                     if constexpr (KFORM) {
                         const int u = t - TL - TQ - TV, ti = u / TX, tj = u % TX;
                         v4_t<T> acc = mma<NU, true, false>(zero4<T>(), S.G, NU, S.Y(), NX, ti, tj);
                         tile_for<T>(ti, tj, [&](int r, int i, int j) { out.K(s, i, j, -acc[r]); });
+                    }
+                } else {
+                    if constexpr (LTFORM) {
+                        const int u = t - TL - TQ - TV - TK, ti = u / TX, tj = u % TX;
+                        v4_t<T> acc = mma<NU, true, false>(zero4<T>(), S.G, NU, S.X, NX, ti, tj);
+                        tile_for<T>(ti, tj, [&](int r, int i, int j) { out.Lt(s, i, j, -acc[r]); });
                     }
                 }
             }
@@ -617,15 +628,16 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
 #pragma unroll
                 for (int r = 0; r < NU; ++r) acc -= S.Y()[r * NX + i] * S.z[r];
                 S.Psi[i] = acc;
-                if constexpr (SOLVE) out.Psi(s, i, acc);
+                if constexpr (PSEMIT) out.Psi(s, i, acc);
             } else if (VEC && RED && tid >= 128 && tid < 128 + NX) {
                 const int i = tid - 128;
                 T acc = S.Vta[i];
 #pragma unroll
                 for (int r = 0; r < NU; ++r) acc += S.X[r * NX + i] * S.z[r];
                 S.v[i] += acc;
-            } else if (VEC && SOLVE && tid >= 128 && tid < 128 + NU) {
-                const int i = tid - 128;
+            } else if (KVEC && tid < NU) {
+                // k_{t+1} = L^{-T} z (wave 0 has no other vector work here)
+                const int i = tid;
                 T acc = T(0);
 #pragma unroll
                 for (int r = 0; r < NU; ++r) acc += S.G[r * NU + i] * S.z[r];

@@ -320,6 +320,102 @@ __global__ void __launch_bounds__(WT) kv_leaf_down(GroupArgs g) {
     }
 }
 
+// ------------------------------------------- leaf solve of the fused path
+// Leaf solve from the records the leaf reduction stored (preliminary
+// solution of Alg. 4 with terminal P = 0).  With the leaf's terminal
+// costate lam_N = P_hat x_hat_{i+1} - Psi_hat (the master solution, Alg. 6),
+// the Riccati quantities of the true terminal follow by superposition, since
+// Psi and k are affine in the terminal Psi_N = -lam_N:
+//   Psi_t = Psi_0,t - V_t lam_N,   k_{t+1} = k_0,t+1 + L_{t+1} lam_N,
+// with V_t = prod (A + B K)' and L_{t+1} = -G^{-1} B' V_{t+1}; P and K do not
+// depend on the terminal linear term.  Alg. 3 then reads
+//   w_t = K x_t + k_0 + L lam_N,  lam_t = P_t x_t - Psi_0,t + V_t lam_N,
+//   x_{t+1} = A x_t + B w_t + a_t.
+// The last leaf was reduced with the true terminal, so its records are
+// already final (no V, L terms).  One wavefront per leaf.
+template <int NX, int NU>
+__global__ void __launch_bounds__(WT) kv_leaf_fwd(GroupArgs g) {
+    __shared__ VSmem<NX, NU> S;
+    __shared__ double lamN[NX];
+    const LeafItem it = load_leaf(g.leaves, blockIdx.x);
+    if ((it.flags & LEAF_TOP) || skip_inst(g, it.inst)) return;
+    const Prob p = load_prob(g.probs, it.inst);
+    const SlotLayout SL{NX};
+    constexpr int K_ = 0, k_ = NU * NX, P_ = NU * NX + NU, Psi_ = P_ + NX * NX, V_ = Psi_ + NX, L_ = V_ + NX * NX,
+                  per = L_ + NU * NX;
+    const double *rec = reinterpret_cast<const double *>(g.leaf_scratch) + it.scratch;
+    const double *msg = g.slots + (int64_t)it.slot * SL.size();
+    const bool last = (it.flags & LEAF_LAST) != 0;
+    const int l = lane();
+    if (!last) {
+        const double *nxt = msg + SL.size();           // the next leaf's slot: x_hat_{i+1}
+        if (l < NX) S.x[l] = nxt[SL.xh() + l];
+        wsync();
+        Op<NX, NX> oP;
+        oP.template load<false>(msg + SL.P(), NX);
+        const double lam = oP.apply(S.x) - (l < NX ? msg[SL.Psi() + l] : 0.0);
+        if (l < NX) lamN[l] = lam;
+        wsync();
+    }
+    if (l < NX) S.x[l] = msg[SL.xh() + l];
+    wsync();
+    const int len = uni(it.len);
+    for (int s = 0; s < len; ++s) {
+        const int t = it.t0 + s;
+        const double *r = rec + (int64_t)s * per;
+        Op<NU, NX> oK, oL;
+        Op<NX, NX> oA, oP, oV;
+        Op<NX, NU> oB;
+        oK.template load<true>(r + K_, NX);
+        oA.template load<true>(p.A + (int64_t)t * p.sA, NX);
+        oB.template load<true>(p.B + (int64_t)t * p.sB, NU);
+        oP.template load<false>(r + P_, NX);
+        if (!last) {
+            oL.template load<true>(r + L_, NX);
+            oV.template load<true>(r + V_, NX);
+        }
+        const double kk = l < NU ? r[k_ + l] : 0.0;
+        const double psi = l < NX ? r[Psi_ + l] : 0.0;
+        const double av = (l < NX && p.a) ? p.a[(int64_t)t * p.sa + l] : 0.0;
+        double wv = oK.apply(S.x) + kk;
+        double lam = oP.apply(S.x) - psi;
+        if (!last) {
+            wv += oL.apply(lamN);
+            lam += oV.apply(lamN);
+        }
+        const double ax = oA.apply(S.x) + av;
+        if (l < NX) {
+            p.x[(int64_t)t * NX + l] = S.x[l];
+            p.lam[(int64_t)t * NX + l] = lam;
+        }
+        if (l < NU) {
+            S.wv[l] = wv;
+            p.w[(int64_t)t * NU + l] = wv;
+        }
+        wsync();
+        const double xn = ax + oB.apply(S.wv);
+        wsync();
+        if (l < NX) S.x[l] = xn;
+        wsync();
+    }
+    if (last) {
+        const int t = it.t0 + len;
+        Op<NX, NX> oQ;
+        oQ.template load<false>(p.QxN, NX);
+        const double lam = oQ.apply(S.x) + ((l < NX && p.lN) ? p.lN[l] : 0.0);
+        if (l < NX) {
+            p.lam[(int64_t)t * NX + l] = lam;       // lam_N = QxN x_N + lN
+            p.x[(int64_t)t * NX + l] = S.x[l];
+        }
+    }
+}
+
+template <int NX, int NU>
+hipError_t launch_fwd(const GroupArgs &g, int, hipStream_t st) {
+    hipLaunchKernelGGL((kv_leaf_fwd<NX, NU>), dim3(g.nleaves), dim3(WT), 0, st, g);
+    return hipGetLastError();
+}
+
 // -------------------------------------------------------------- the tree
 template <int NX>
 __global__ void __launch_bounds__(WT) kv_tree(GroupArgs g) {
@@ -454,6 +550,13 @@ hipError_t launch_down(const GroupArgs &g, int, hipStream_t st) {
 }
 
 }  // namespace sv
+
+Launcher leaf_forward(int nx, int nu) {
+    if (nx == 16 && nu == 16) return &sv::launch_fwd<16, 16>;
+    if (nx == 32 && nu == 16) return &sv::launch_fwd<32, 16>;
+    if (nx == 32 && nu == 32) return &sv::launch_fwd<32, 32>;
+    return nullptr;
+}
 
 // which: 0 leaf up, 1 tree, 2 leaf down; fp32: the leaf records are FP32.
 Launcher vector_solve(int nx, int nu, int which, bool fp32) {

@@ -134,6 +134,7 @@ struct GroupArgs {
     const int32_t *conv;    // per instance: 1 once converged (later passes skip it)
     double *part;           // per global leaf: PART_N partial results
     int32_t leaf_base;      // global index of this group's first leaf
+    int32_t ntop;           // leaves that are a whole instance (LEAF_TOP)
 };
 
 }  // namespace rs
