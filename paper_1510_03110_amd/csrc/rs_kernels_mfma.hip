@@ -508,7 +508,7 @@ __global__ void __launch_bounds__(NT) km_tree(GroupArgs g) {
 // Leaf record writer: up records at +0, down records at +up() of each stage.
 template <class T, int NX, int NU, bool UP>
 struct LeafFacOut : NoEmit {
-    static constexpr bool VEC = false, KF = true, PF = true, LF = true, VF = UP;
+    static constexpr bool VEC = false, KF = true, PF = true, LF = true, VF = UP, LTF = UP;
     T *base;                                         // stage 0 of this leaf
     __device__ T *at(int s) const {
         const LeafRec R{NX, NU};
@@ -517,6 +517,7 @@ struct LeafFacOut : NoEmit {
     __device__ void K(int s, int i, int j, double v) const { at(s)[LeafRec{NX, NU}.K() + i * NX + j] = (T)v; }
     __device__ void P(int s, int i, int j, double v) const { at(s)[LeafRec{NX, NU}.P() + i * NX + j] = (T)v; }
     __device__ void V(int s, int i, int j, double v) const { at(s)[LeafRec{NX, NU}.V() + i * NX + j] = (T)v; }
+    __device__ void Lt(int s, int i, int j, double v) const { at(s)[LeafRec{NX, NU}.Lt() + i * NX + j] = (T)v; }
     template <class U>
     __device__ void L(int s, const U *Li) const {
         T *d = at(s);
@@ -607,7 +608,9 @@ __global__ void __launch_bounds__(NT, 3) kf_leaf_down(GroupArgs g) {
     __shared__ __attribute__((aligned(16))) char raw[sizeof(MSmem<T, NX, NU, false, true>)];
     auto &S = *reinterpret_cast<MSmem<T, NX, NU, false, true> *>(raw);
     const LeafItem it = load_leaf_u(g.leaves, blockIdx.x);
-    if (inst_skipped(g.probs, it.inst)) return;
+    // only whole-problem leaves need the factorization with the true terminal;
+    // the others are solved from their up records
+    if (!(it.flags & LEAF_TOP) || inst_skipped(g.probs, it.inst)) return;
     const DevProb p = load_prob(g.probs, it.inst);
     const SlotLayout SL{NX};
     const bool known_end = (it.flags & (LEAF_LAST | LEAF_TOP)) != 0;
@@ -732,6 +735,7 @@ hipError_t launch_factor_tree(const GroupArgs &g, int grid, hipStream_t st) {
 }
 template <class T, int NX, int NU>
 hipError_t launch_factor_leaf_down(const GroupArgs &g, int, hipStream_t st) {
+    if (g.ntop == 0) return hipSuccess;
     hipLaunchKernelGGL((kf_leaf_down<T, NX, NU>), dim3(g.nleaves), dim3(NT), 0, st, g);
     return hipGetLastError();
 }

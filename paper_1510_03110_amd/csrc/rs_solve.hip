@@ -211,6 +211,101 @@ __device__ __forceinline__ VSrc<double> slot_src(const double *sl) {
 }
 
 // ------------------------------------------------------------------ leaves
+// Leaf solve from the stored preliminary solution of the leaf reduction
+// (Alg. 4 with terminal P = 0).  With the leaf's terminal costate
+// lam_N = P_hat x_hat_{i+1} - Psi_hat (the master solution, Alg. 6), the
+// Riccati quantities of the true terminal follow by superposition, since
+// Psi and k are affine in the terminal Psi_N = -lam_N:
+//   Psi_t = Psi_0,t - V_t lam_N,   k_{t+1} = k_0,t+1 + L_{t+1} lam_N,
+// with V_t = prod (A + B K)' and L_{t+1} = -G^{-1} B' V_{t+1}; P and K do not
+// depend on the terminal linear term.  Alg. 3 then reads
+//   w_t = K x_t + k_0 + L lam_N,  lam_t = P_t x_t - Psi_0,t + V_t lam_N,
+//   x_{t+1} = A x_t + B w_t + a_t.
+// The last leaf was reduced with the true terminal, so its records are
+// final (no V, L terms).  `rec` gives the stage pointers K, k, P, Psi, V, L.
+template <int NX, int NU, class Rec>
+__device__ __forceinline__ void leaf_forward_sweep(VSmem<NX, NU> &S, double *lamN, const Prob &p,
+                                                   const LeafItem &it, const double *msg, Rec rec) {
+    const SlotLayout SL{NX};
+    const bool last = (it.flags & LEAF_LAST) != 0;
+    const int l = lane();
+    if (!last) {
+        const double *nxt = msg + SL.size();           // the next leaf's slot: x_hat_{i+1}
+        if (l < NX) S.x[l] = nxt[SL.xh() + l];
+        wsync();
+        Op<NX, NX> oP;
+        oP.template load<false>(msg + SL.P(), NX);
+        const double lam = oP.apply(S.x) - (l < NX ? msg[SL.Psi() + l] : 0.0);
+        if (l < NX) lamN[l] = lam;
+        wsync();
+    }
+    if (l < NX) S.x[l] = msg[SL.xh() + l];
+    wsync();
+    const int len = uni(it.len);
+    for (int s = 0; s < len; ++s) {
+        const int t = it.t0 + s;
+        Op<NU, NX> oK, oL;
+        Op<NX, NX> oA, oP, oV;
+        Op<NX, NU> oB;
+        oK.template load<true>(rec.K(s), NX);
+        oA.template load<true>(p.A + (int64_t)t * p.sA, NX);
+        oB.template load<true>(p.B + (int64_t)t * p.sB, NU);
+        oP.template load<false>(rec.P(s), NX);
+        if (!last) {
+            oL.template load<true>(rec.L(s), NX);
+            oV.template load<true>(rec.V(s), NX);
+        }
+        const double kk = l < NU ? (double)rec.k(s)[l] : 0.0;
+        const double psi = l < NX ? (double)rec.Psi(s)[l] : 0.0;
+        const double av = (l < NX && p.a) ? p.a[(int64_t)t * p.sa + l] : 0.0;
+        double wv = oK.apply(S.x) + kk;
+        double lam = oP.apply(S.x) - psi;
+        if (!last) {
+            wv += oL.apply(lamN);
+            lam += oV.apply(lamN);
+        }
+        const double ax = oA.apply(S.x) + av;
+        if (l < NX) {
+            p.x[(int64_t)t * NX + l] = S.x[l];
+            p.lam[(int64_t)t * NX + l] = lam;
+        }
+        if (l < NU) {
+            S.wv[l] = wv;
+            p.w[(int64_t)t * NU + l] = wv;
+        }
+        wsync();
+        const double xn = ax + oB.apply(S.wv);
+        wsync();
+        if (l < NX) S.x[l] = xn;
+        wsync();
+    }
+    if (last) {
+        const int t = it.t0 + len;
+        Op<NX, NX> oQ;
+        oQ.template load<false>(p.QxN, NX);
+        const double lam = oQ.apply(S.x) + ((l < NX && p.lN) ? p.lN[l] : 0.0);
+        if (l < NX) {
+            p.lam[(int64_t)t * NX + l] = lam;       // lam_N = QxN x_N + lN
+            p.x[(int64_t)t * NX + l] = S.x[l];
+        }
+    }
+}
+
+// Stage pointers of a stored-factorization leaf: matrices in the up record
+// (type TR), Psi_0 and k_0 in the FP64 vector array.
+template <int NX, int NU, class TR>
+struct UpRecs {
+    const TR *rec;
+    const double *vec;
+    __device__ const TR *r(int s) const { return rec + (int64_t)s * LeafRec{NX, NU}.per_stage(); }
+    __device__ const TR *K(int s) const { return r(s) + LeafRec{NX, NU}.K(); }
+    __device__ const TR *P(int s) const { return r(s) + LeafRec{NX, NU}.P(); }
+    __device__ const TR *V(int s) const { return r(s) + LeafRec{NX, NU}.V(); }
+    __device__ const TR *L(int s) const { return r(s) + LeafRec{NX, NU}.Lt(); }
+    __device__ const double *Psi(int s) const { return vec + (int64_t)s * (NX + NU); }
+    __device__ const double *k(int s) const { return vec + (int64_t)s * (NX + NU) + NX; }
+};
+
 template <int NX, int NU, class TR>
 __global__ void __launch_bounds__(WT) kv_leaf_up(GroupArgs g) {
     __shared__ VSmem<NX, NU> S;
@@ -228,8 +323,8 @@ __global__ void __launch_bounds__(WT) kv_leaf_up(GroupArgs g) {
         S.v[l] = 0.0;
     }
     double cbar = (last && p.cN) ? p.cN[0] : 0.0;
+    double *vec0 = g.fvec + (it.scratch / g.sps) * (int64_t)R.vec();
     wsync();
-    auto none = [](double, double) {};
     for (int s = uni(it.len) - 1; s >= 0; --s) {
         VSrc<TR> q = prob_src<NX, NU, TR>(p, it.t0 + s);
         const TR *r = rec + (int64_t)s * R.per_stage();
@@ -238,14 +333,20 @@ __global__ void __launch_bounds__(WT) kv_leaf_up(GroupArgs g) {
         q.Li = r + R.L();
         q.LT = r + R.LT();
         q.K = r + R.K();
+        // Psi_t and k_{t+1} of this sweep, for the leaf solve
+        double *vec = vec0 + (int64_t)s * R.vec();
+        auto keep = [&](double psi, double k) {
+            if (l < NX) vec[l] = psi;
+            if (l < NU) vec[NX + l] = k;
+        };
         if (!last) {
             q.Pn = end ? nullptr : rn + R.P();
             q.Vn = end ? nullptr : rn + R.V();
-            vstage<NX, NU, true, false>(S, q, cbar, none);
+            vstage<NX, NU, true, false>(S, q, cbar, keep);
         } else {
             q.Pn = end ? nullptr : rn + R.P();
             q.Pn64 = end ? p.QxN : nullptr;
-            vstage<NX, NU, false, false>(S, q, cbar, none);
+            vstage<NX, NU, false, true>(S, q, cbar, keep);
         }
     }
     if (l < NX) {
@@ -258,9 +359,18 @@ __global__ void __launch_bounds__(WT) kv_leaf_up(GroupArgs g) {
 template <int NX, int NU, class TR>
 __global__ void __launch_bounds__(WT) kv_leaf_down(GroupArgs g) {
     __shared__ VSmem<NX, NU> S;
+    __shared__ double lamN[NX];
     const LeafItem it = load_leaf(g.leaves, blockIdx.x);
     if (skip_inst(g, it.inst)) return;
     const Prob p = load_prob(g.probs, it.inst);
+    if (!(it.flags & LEAF_TOP)) {
+        const int64_t stage0 = it.scratch / g.sps;
+        const TR *rec = reinterpret_cast<const TR *>(g.fstore) + stage0 * (int64_t)LeafRec{NX, NU}.per_stage();
+        const double *msg = g.slots + (int64_t)it.slot * SlotLayout{NX}.size();
+        leaf_forward_sweep<NX, NU>(S, lamN, p, it, msg,
+                                   UpRecs<NX, NU, TR>{rec, g.fvec + stage0 * (int64_t)LeafRec{NX, NU}.vec()});
+        return;
+    }
     const LeafRec R{NX, NU};
     const SlotLayout SL{NX};
     const int64_t stage0 = it.scratch / g.sps;
@@ -321,18 +431,24 @@ __global__ void __launch_bounds__(WT) kv_leaf_down(GroupArgs g) {
 }
 
 // ------------------------------------------- leaf solve of the fused path
-// Leaf solve from the records the leaf reduction stored (preliminary
-// solution of Alg. 4 with terminal P = 0).  With the leaf's terminal
-// costate lam_N = P_hat x_hat_{i+1} - Psi_hat (the master solution, Alg. 6),
-// the Riccati quantities of the true terminal follow by superposition, since
-// Psi and k are affine in the terminal Psi_N = -lam_N:
-//   Psi_t = Psi_0,t - V_t lam_N,   k_{t+1} = k_0,t+1 + L_{t+1} lam_N,
-// with V_t = prod (A + B K)' and L_{t+1} = -G^{-1} B' V_{t+1}; P and K do not
-// depend on the terminal linear term.  Alg. 3 then reads
-//   w_t = K x_t + k_0 + L lam_N,  lam_t = P_t x_t - Psi_0,t + V_t lam_N,
-//   x_{t+1} = A x_t + B w_t + a_t.
-// The last leaf was reduced with the true terminal, so its records are
-// already final (no V, L terms).  One wavefront per leaf.
+// Records of the fused leaf reduction (leaf scratch, FP64 per stage):
+//   K (NU*NX) | k (NU) | P (NX*NX) | Psi (NX) | V (NX*NX) | L (NU*NX)
+template <int NX, int NU>
+struct FusedRecs {
+    const double *rec;
+    static constexpr int K_ = 0, k_ = NU * NX, P_ = NU * NX + NU, Psi_ = P_ + NX * NX, V_ = Psi_ + NX,
+                         L_ = V_ + NX * NX, per = L_ + NU * NX;
+    __device__ const double *r(int s) const { return rec + (int64_t)s * per; }
+    __device__ const double *K(int s) const { return r(s) + K_; }
+    __device__ const double *k(int s) const { return r(s) + k_; }
+    __device__ const double *P(int s) const { return r(s) + P_; }
+    __device__ const double *Psi(int s) const { return r(s) + Psi_; }
+    __device__ const double *V(int s) const { return r(s) + V_; }
+    __device__ const double *L(int s) const { return r(s) + L_; }
+};
+
+// One wavefront per leaf of a multi-leaf instance (whole-problem leaves are
+// solved by the fused leaf-down kernel).
 template <int NX, int NU>
 __global__ void __launch_bounds__(WT) kv_leaf_fwd(GroupArgs g) {
     __shared__ VSmem<NX, NU> S;
@@ -340,74 +456,9 @@ __global__ void __launch_bounds__(WT) kv_leaf_fwd(GroupArgs g) {
     const LeafItem it = load_leaf(g.leaves, blockIdx.x);
     if ((it.flags & LEAF_TOP) || skip_inst(g, it.inst)) return;
     const Prob p = load_prob(g.probs, it.inst);
-    const SlotLayout SL{NX};
-    constexpr int K_ = 0, k_ = NU * NX, P_ = NU * NX + NU, Psi_ = P_ + NX * NX, V_ = Psi_ + NX, L_ = V_ + NX * NX,
-                  per = L_ + NU * NX;
-    const double *rec = reinterpret_cast<const double *>(g.leaf_scratch) + it.scratch;
-    const double *msg = g.slots + (int64_t)it.slot * SL.size();
-    const bool last = (it.flags & LEAF_LAST) != 0;
-    const int l = lane();
-    if (!last) {
-        const double *nxt = msg + SL.size();           // the next leaf's slot: x_hat_{i+1}
-        if (l < NX) S.x[l] = nxt[SL.xh() + l];
-        wsync();
-        Op<NX, NX> oP;
-        oP.template load<false>(msg + SL.P(), NX);
-        const double lam = oP.apply(S.x) - (l < NX ? msg[SL.Psi() + l] : 0.0);
-        if (l < NX) lamN[l] = lam;
-        wsync();
-    }
-    if (l < NX) S.x[l] = msg[SL.xh() + l];
-    wsync();
-    const int len = uni(it.len);
-    for (int s = 0; s < len; ++s) {
-        const int t = it.t0 + s;
-        const double *r = rec + (int64_t)s * per;
-        Op<NU, NX> oK, oL;
-        Op<NX, NX> oA, oP, oV;
-        Op<NX, NU> oB;
-        oK.template load<true>(r + K_, NX);
-        oA.template load<true>(p.A + (int64_t)t * p.sA, NX);
-        oB.template load<true>(p.B + (int64_t)t * p.sB, NU);
-        oP.template load<false>(r + P_, NX);
-        if (!last) {
-            oL.template load<true>(r + L_, NX);
-            oV.template load<true>(r + V_, NX);
-        }
-        const double kk = l < NU ? r[k_ + l] : 0.0;
-        const double psi = l < NX ? r[Psi_ + l] : 0.0;
-        const double av = (l < NX && p.a) ? p.a[(int64_t)t * p.sa + l] : 0.0;
-        double wv = oK.apply(S.x) + kk;
-        double lam = oP.apply(S.x) - psi;
-        if (!last) {
-            wv += oL.apply(lamN);
-            lam += oV.apply(lamN);
-        }
-        const double ax = oA.apply(S.x) + av;
-        if (l < NX) {
-            p.x[(int64_t)t * NX + l] = S.x[l];
-            p.lam[(int64_t)t * NX + l] = lam;
-        }
-        if (l < NU) {
-            S.wv[l] = wv;
-            p.w[(int64_t)t * NU + l] = wv;
-        }
-        wsync();
-        const double xn = ax + oB.apply(S.wv);
-        wsync();
-        if (l < NX) S.x[l] = xn;
-        wsync();
-    }
-    if (last) {
-        const int t = it.t0 + len;
-        Op<NX, NX> oQ;
-        oQ.template load<false>(p.QxN, NX);
-        const double lam = oQ.apply(S.x) + ((l < NX && p.lN) ? p.lN[l] : 0.0);
-        if (l < NX) {
-            p.lam[(int64_t)t * NX + l] = lam;       // lam_N = QxN x_N + lN
-            p.x[(int64_t)t * NX + l] = S.x[l];
-        }
-    }
+    const double *msg = g.slots + (int64_t)it.slot * SlotLayout{NX}.size();
+    leaf_forward_sweep<NX, NU>(S, lamN, p, it, msg,
+                               FusedRecs<NX, NU>{reinterpret_cast<const double *>(g.leaf_scratch) + it.scratch});
 }
 
 template <int NX, int NU>

@@ -79,12 +79,15 @@ struct SlotLayout {
 
 // Stored factorization of one leaf stage (factor / solve split), in the
 // factor precision (FP64, or FP32 in mixed-precision plans):
-//   up record (Alg. 4 or last-leaf elimination): P_after | L^{-1} | L^{-T} | K | V_after
-//   down record (Alg. 1 with the true terminal):  P_after | L^{-1} | L^{-T} | K
+//   up record (Alg. 4 or last-leaf elimination):
+//       P_after | L^{-1} | L^{-T} | K | V_after | Lt
+//   down record (Alg. 1 with the true terminal, whole-problem leaves only):
+//       P_after | L^{-1} | L^{-T} | K
 // P_after / V_after are the values after the stage (P_t, V_t), L^{-1} is the
-// inverse Cholesky factor of G_{t+1} and K = K_{t+1}.  The down-pass vectors
-// of a solve (Psi_t | k_{t+1}, nx + nu doubles per stage) live in a separate
-// FP64 array.
+// inverse Cholesky factor of G_{t+1}, K = K_{t+1} and Lt = -G^{-1} B' V_{t+1}.
+// The vectors of a solve (Psi_t | k_{t+1}, nx + nu doubles per stage: of the
+// preliminary solution for multi-leaf instances, of the true one for
+// whole-problem leaves) live in a separate FP64 array.
 struct LeafRec {
     int nx, nu;
     __host__ __device__ int P() const { return 0; }
@@ -92,7 +95,8 @@ struct LeafRec {
     __host__ __device__ int LT() const { return nx * nx + nu * nu; }
     __host__ __device__ int K() const { return nx * nx + 2 * nu * nu; }
     __host__ __device__ int V() const { return nx * nx + 2 * nu * nu + nu * nx; }
-    __host__ __device__ int up() const { return 2 * nx * nx + 2 * nu * nu + nu * nx; }
+    __host__ __device__ int Lt() const { return 2 * nx * nx + 2 * nu * nu + nu * nx; }
+    __host__ __device__ int up() const { return 2 * nx * nx + 2 * nu * nu + 2 * nu * nx; }
     __host__ __device__ int down() const { return nx * nx + 2 * nu * nu + nu * nx; }
     __host__ __device__ int per_stage() const { return up() + down(); }
     __host__ __device__ int vec() const { return nx + nu; }

@@ -175,7 +175,7 @@ def test_factored_plan_workspace_and_shape_support():
     try:
         extra = rs.rs_plan_workspace_size(p1) - rs.rs_plan_workspace_size(p0)
         nx, nu = 32, 16
-        per_stage = (2 * nx * nx + 2 * nu * nu + nu * nx) + (nx * nx + 2 * nu * nu + nu * nx) + nx + nu
+        per_stage = (2 * nx * nx + 2 * nu * nu + 2 * nu * nx) + (nx * nx + 2 * nu * nu + nu * nx) + nx + nu
         assert 0 <= extra - 8 * 1024 * per_stage < 4096
     finally:
         rs.rs_plan_destroy(p0)
