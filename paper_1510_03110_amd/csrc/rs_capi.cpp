@@ -365,8 +365,8 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         }
     }
     if (P->mixed) {
-        P->off_conv = off;
-        off = align_up(off + sizeof(int32_t) * count);
+        P->off_conv = off;                 // conv[count] | active[max_refine + 1]
+        off = align_up(off + sizeof(int32_t) * (count + P->max_refine + 1));
         P->off_stats = off;
         off = align_up(off + sizeof(double) * ST_N * count);
         P->off_part = off;
@@ -577,7 +577,8 @@ static rs_status check_call(rs_plan P, const rs_problem *probs, void *work, size
 
 // Launch arguments of one shape group.  corr = true points the problem
 // array at the correction problems of a mixed-precision plan.
-static GroupArgs group_args(rs_plan P, char *W, size_t gi, int32_t *info, bool corr, bool with_conv) {
+static GroupArgs group_args(rs_plan P, char *W, size_t gi, int32_t *info, bool corr, bool with_conv,
+                            int iter = -1) {
     Group &g = P->groups[gi];
     GroupArgs a{};
     const DevProb *user = reinterpret_cast<const DevProb *>(W + P->off_probs);
@@ -599,6 +600,7 @@ static GroupArgs group_args(rs_plan P, char *W, size_t gi, int32_t *info, bool c
     if (P->mixed) {
         a.corr = user + P->count;
         a.conv = with_conv ? reinterpret_cast<const int32_t *>(W + P->off_conv) : nullptr;
+        a.active = iter >= 0 ? reinterpret_cast<const int32_t *>(W + P->off_conv) + P->count + iter : nullptr;
         a.part = reinterpret_cast<double *>(W + P->off_part);
         a.leaf_base = g.leaf_base;
     }
@@ -610,7 +612,7 @@ static GroupArgs group_args(rs_plan P, char *W, size_t gi, int32_t *info, bool c
 // pass 0 = fused solve, 1 = stored factorization, 2 = solve on the stored
 // factorization.
 static rs_status launch_pass(rs_plan P, char *W, int32_t *info, hipStream_t st, int pass, bool keep_status,
-                             bool corr, bool with_conv) {
+                             bool corr, bool with_conv, int iter = -1) {
     static const int kinds[3][3] = {{KK_LEAF_UP, KK_TREE, KK_LEAF_DOWN},
                                     {KK_F_LEAF_UP, KK_F_TREE, KK_F_LEAF_DOWN},
                                     {KK_S_LEAF_UP, KK_S_TREE, KK_S_LEAF_DOWN}};
@@ -622,7 +624,7 @@ static rs_status launch_pass(rs_plan P, char *W, int32_t *info, hipStream_t st, 
     const int f32 = P->mixed ? 1 : 0;
     for (size_t gi = 0; gi < P->groups.size(); ++gi) {
         Group &g = P->groups[gi];
-        GroupArgs a = group_args(P, W, gi, info, corr, with_conv);
+        GroupArgs a = group_args(P, W, gi, info, corr, with_conv, iter);
         const Launcher *L = pass == 0 ? g.shape->fp64 : pass == 1 ? g.shape->factor[f32] : g.shape->vsolve[f32];
         // the vector passes run one wavefront per work item
         const int cap = pass == 2 ? 1024 : 256;
@@ -656,13 +658,15 @@ static rs_status launch_refine(rs_plan P, char *W, int32_t *info, hipStream_t st
     return RS_OK;
 }
 
-static rs_status launch_check(rs_plan P, char *W, int32_t *info, hipStream_t st, int mode) {
+static rs_status launch_check(rs_plan P, char *W, int32_t *info, hipStream_t st, int mode, int iter = -1) {
+    int32_t *conv = reinterpret_cast<int32_t *>(W + P->off_conv);
     hipError_t e = timed(P, KK_CHECK, st, [&] {
         return launch_refine_check(reinterpret_cast<const InstInfo *>(W + P->off_inst), P->count,
                                    reinterpret_cast<const double *>(W + P->off_part),
-                                   reinterpret_cast<double *>(W + P->off_stats),
-                                   reinterpret_cast<int32_t *>(W + P->off_conv), info,
-                                   reinterpret_cast<const DevProb *>(W + P->off_probs), mode, P->tol, st);
+                                   reinterpret_cast<double *>(W + P->off_stats), conv, info,
+                                   reinterpret_cast<const DevProb *>(W + P->off_probs), mode, P->tol,
+                                   iter >= 0 ? conv + P->count + iter : (mode == 0 ? conv + P->count : nullptr),
+                                   mode == 0 ? P->max_refine + 1 : 0, st);
     });
     return e == hipSuccess ? RS_OK : RS_ERR_HIP;
 }
@@ -676,8 +680,8 @@ static rs_status mixed_solve(rs_plan P, char *W, int32_t *info, hipStream_t st) 
     if (s == RS_OK) s = launch_pass(P, W, info, st, 2, true, false, true);
     for (int k = 0; k < P->max_refine && s == RS_OK; ++k) {
         s = launch_refine(P, W, info, st, 0, true);
-        if (s == RS_OK) s = launch_check(P, W, info, st, 1);
-        if (s == RS_OK) s = launch_pass(P, W, info, st, 2, true, true, true);
+        if (s == RS_OK) s = launch_check(P, W, info, st, 1, k);     // counts active[k]
+        if (s == RS_OK) s = launch_pass(P, W, info, st, 2, true, true, true, k);
         if (s == RS_OK) s = launch_refine(P, W, info, st, 1, true);
         if (s == RS_OK) s = launch_check(P, W, info, st, 2);
     }

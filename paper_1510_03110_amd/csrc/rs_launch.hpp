@@ -38,8 +38,11 @@ Launcher mfma_factor(int nx, int nu, int which, bool fp32);
 Launcher vector_solve(int nx, int nu, int which, bool fp32);
 Launcher refine_kernel(int nx, int nu, int which);       // 0 residual, 1 update
 Launcher leaf_forward(int nx, int nu);                   // leaf solve on the stored leaf records
+// mode 0 also clears active[0 .. nactive); mode 1 counts the instances still
+// iterating into *active.
 hipError_t launch_refine_check(const InstInfo *tab, int count, const double *part, double *stats, int32_t *conv,
-                               int32_t *info, const DevProb *probs, int mode, double tol, hipStream_t st);
+                               int32_t *info, const DevProb *probs, int mode, double tol, int32_t *active,
+                               int nactive, hipStream_t st);
 
 const ShapeEntry *find_shape(int nx, int nu);
 hipError_t launch_init(int32_t *info, int count, int32_t *queues, int nq, hipStream_t st);

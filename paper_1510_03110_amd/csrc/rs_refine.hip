@@ -215,8 +215,9 @@ __global__ void __launch_bounds__(RT) kr_update(GroupArgs g) {
 // mode 2: after an update (correction size, forward-error estimate);
 // mode 3: final (RS_ERR_NOT_CONVERGED for instances that did not converge).
 __global__ void kr_check(const InstInfo *tab, int count, const double *part, double *stats, int32_t *conv,
-                         int32_t *info, const DevProb *probs, int mode, double tol) {
+                         int32_t *info, const DevProb *probs, int mode, double tol, int32_t *active, int nactive) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (mode == 0 && i < nactive) active[i] = 0;
     if (i >= count) return;
     double *st = stats + (int64_t)i * ST_N;
     if (mode == 0) {
@@ -265,6 +266,7 @@ __global__ void kr_check(const InstInfo *tab, int count, const double *part, dou
     st[ST_RRES] = rres;
     if (probs[i].obj) probs[i].obj[0] = obj;
     if (st[ST_ITERS] >= 1.0 && rres <= tol && st[ST_EST] <= 0.1 * tol) conv[i] = 1;
+    else if (active) atomicAdd(active, 1);      // the next correction pass has work
 }
 
 template <int NX, int NU>
@@ -292,9 +294,11 @@ Launcher refine_kernel(int nx, int nu, int which) {
 }
 
 hipError_t launch_refine_check(const InstInfo *tab, int count, const double *part, double *stats, int32_t *conv,
-                               int32_t *info, const DevProb *probs, int mode, double tol, hipStream_t st) {
-    hipLaunchKernelGGL(sv::kr_check, dim3((count + 63) / 64), dim3(64), 0, st, tab, count, part, stats, conv, info,
-                       probs, mode, tol);
+                               int32_t *info, const DevProb *probs, int mode, double tol, int32_t *active,
+                               int nactive, hipStream_t st) {
+    const int n = count > nactive ? count : nactive;
+    hipLaunchKernelGGL(sv::kr_check, dim3((n + 63) / 64), dim3(64), 0, st, tab, count, part, stats, conv, info,
+                       probs, mode, tol, active, nactive);
     return hipGetLastError();
 }
 

@@ -309,6 +309,7 @@ struct UpRecs {
 template <int NX, int NU, class TR>
 __global__ void __launch_bounds__(WT) kv_leaf_up(GroupArgs g) {
     __shared__ VSmem<NX, NU> S;
+    if (pass_idle(g)) return;
     const LeafItem it = load_leaf(g.leaves, blockIdx.x);
     if ((it.flags & LEAF_TOP) || skip_inst(g, it.inst)) return;
     const Prob p = load_prob(g.probs, it.inst);
@@ -360,6 +361,7 @@ template <int NX, int NU, class TR>
 __global__ void __launch_bounds__(WT) kv_leaf_down(GroupArgs g) {
     __shared__ VSmem<NX, NU> S;
     __shared__ double lamN[NX];
+    if (pass_idle(g)) return;
     const LeafItem it = load_leaf(g.leaves, blockIdx.x);
     if (skip_inst(g, it.inst)) return;
     const Prob p = load_prob(g.probs, it.inst);
@@ -476,6 +478,7 @@ __global__ void __launch_bounds__(WT) kv_tree(GroupArgs g) {
     const SlotLayout SL{NX};
     double *slots = uni_ptr(g.slots);
     auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
+    if (pass_idle(g)) return;
     for (;;) {
         if (l == 0) s_item = atomicAdd(g.queue, 1);
         wsync();

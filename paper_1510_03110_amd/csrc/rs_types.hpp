@@ -139,6 +139,7 @@ struct GroupArgs {
     double *part;           // per global leaf: PART_N partial results
     int32_t leaf_base;      // global index of this group's first leaf
     int32_t ntop;           // leaves that are a whole instance (LEAF_TOP)
+    const int32_t *active;  // refinement: instances still iterating (0: the pass has nothing to do)
 };
 
 }  // namespace rs

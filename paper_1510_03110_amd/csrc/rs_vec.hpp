@@ -126,6 +126,9 @@ __device__ __forceinline__ Prob load_prob(const DevProb *tab, int i) {
     return p;
 }
 
+// Nothing to do in this refinement pass: every instance has converged.
+__device__ __forceinline__ bool pass_idle(const GroupArgs &g) { return g.active && uni(*g.active) == 0; }
+
 // An instance excluded from the call, or converged in the mixed-precision
 // refinement, is skipped.
 __device__ __forceinline__ bool skip_inst(const GroupArgs &g, int inst) {

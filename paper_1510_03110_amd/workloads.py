@@ -62,6 +62,38 @@ def g1(nx, nu, N, seed):
     return p
 
 
+def g1_invariant(nx, nu, N, seed):
+    """G1 instance with the time-invariant A and B given once (stage axis of
+    length 1, passed with stage stride 0) and the diagonal weights drawn in
+    one call each.  Same distributions as ``g1``; a different random stream.
+    For large batches of long horizons."""
+    rng = np.random.default_rng(seed)
+    A = _spectral_scale(rng.standard_normal((nx, nx)))
+    B = rng.standard_normal((nx, nu))
+    qx = rng.uniform(0.5, 2.0, (N, nx))
+    qw = rng.uniform(0.5, 2.0, (N, nu))
+    Qx = np.zeros((N, nx, nx))
+    Qx[:, np.arange(nx), np.arange(nx)] = qx
+    Qw = np.zeros((N, nu, nu))
+    Qw[:, np.arange(nu), np.arange(nu)] = qw
+    return dict(Qx=Qx, Qw=Qw, Qxw=np.zeros((1, nx, nu)), A=A[None].copy(), B=B[None].copy(),
+                a=rng.standard_normal((N, nx)), lx=rng.standard_normal((N, nx)),
+                lw=rng.standard_normal((N, nu)), c=np.zeros(N),
+                QxN=np.diag(rng.uniform(0.5, 2.0, nx)), lN=rng.standard_normal(nx), cN=np.float64(0.0),
+                x0=rng.standard_normal(nx))
+
+
+def materialize(prob):
+    """Copy of ``prob`` with every stage-axis-1 matrix repeated over the N
+    stages (the form the oracle takes)."""
+    N = prob["lx"].shape[0]
+    q = dict(prob)
+    for k in ("Qx", "Qw", "Qxw", "A", "B"):
+        if q[k].shape[0] == 1 and N > 1:
+            q[k] = np.repeat(q[k], N, axis=0)
+    return q
+
+
 def _cross_term(rng, Qx, Rdiag, nu):
     nx = Qx.shape[0]
     S = 0.1 * rng.standard_normal((nx, nu))

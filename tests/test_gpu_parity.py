@@ -150,3 +150,24 @@ def test_repeated_calls_same_workspace():
     for o in outs[1:]:
         np.testing.assert_array_equal(o["x"], outs[0]["x"])
     _check(prob, outs[0])
+
+
+def test_batching_config_uneven_horizons_sampled():
+    """4096 instances of n_x=16, n_u=8 with horizons uniform in [32, 2048]
+    (G1), one launch per kernel kind; sampled instances (first, last and
+    seeded picks, the shortest and the longest) against the oracle."""
+    torch, rs = _rs()
+    rng = np.random.default_rng(W.seed_for(2))
+    Ns_all = rng.integers(32, 2049, size=4096)
+    probs = [W.g1_invariant(16, 8, int(n), seed=W.seed_for(2, i)) for i, n in enumerate(Ns_all)]
+    data = {k: [p[k] for p in probs] for k in probs[0]}
+    b = rs.Batch(data, Ns=16, branch=4)        # A, B, Qxw with stage stride 0
+    b.solve()
+    torch.cuda.synchronize()
+    st = b.status()
+    assert np.all(st[:, 0] == 0)
+    pick = sorted({0, 4095, int(np.argmin(Ns_all)), int(np.argmax(Ns_all))} |
+                  set(int(i) for i in rng.integers(0, 4096, size=60)))
+    for i in pick:
+        _check(W.materialize(probs[i]), b.result(i))
+    b.close()
