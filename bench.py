@@ -223,7 +223,7 @@ def run_precision(prec, args, data, dev):
     lat = None
     if args.latency_reps > 0:
         one = rs.Batch({k: v[:1] for k, v in data.items()}, precision=pc, Ns=args.latency_Ns or args.Ns,
-                       branch=args.branch, device=dev)
+                       branch=args.latency_branch or args.branch, device=dev)
         for _ in range(5):
             one.solve()
         torch.cuda.synchronize()
@@ -236,7 +236,7 @@ def run_precision(prec, args, data, dev):
         samples = np.array(samples)
         lat = {"batch": 1, "p50_ms": round(float(np.percentile(samples, 50)), 4),
                "p99_ms": round(float(np.percentile(samples, 99)), 4), "reps": args.latency_reps,
-               "Ns": args.latency_Ns or args.Ns}
+               "Ns": args.latency_Ns or args.Ns, "branch": args.latency_branch or args.branch}
         log("[%s] latency B=1:" % prec, lat)
         one.close()
 
@@ -276,11 +276,15 @@ def main():
     ap.add_argument("--nx", type=int, default=32)
     ap.add_argument("--nu", type=int, default=16)
     ap.add_argument("--N", type=int, default=1024)
-    ap.add_argument("--Ns", type=int, default=16)
-    ap.add_argument("--branch", type=int, default=4)
+    # Throughput tree shape chosen by the autotuner at this shape and batch
+    # (leaf length 128, branch 8); the B = 1 latency plan keeps short leaves
+    # (16, branch 4), where the O(log N) tree is what lowers the latency.
+    ap.add_argument("--Ns", type=int, default=128)
+    ap.add_argument("--branch", type=int, default=8)
     ap.add_argument("--precision", choices=("both", "fp64", "mixed"), default="both")
     ap.add_argument("--latency-reps", type=int, default=200)
-    ap.add_argument("--latency-Ns", type=int, default=0, help="leaf length of the B=1 latency plan (0: --Ns)")
+    ap.add_argument("--latency-Ns", type=int, default=16, help="leaf length of the B=1 latency plan")
+    ap.add_argument("--latency-branch", type=int, default=4, help="branch of the B=1 latency plan")
     ap.add_argument("--verify", type=int, default=4, help="sampled instances checked against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,

@@ -42,6 +42,28 @@ __device__ __forceinline__ bool inst_skipped(const DevProb *probs, int inst) {
     return (uni(probs[inst].flags) & PROB_SKIP) != 0;
 }
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also orders
+// global memory, which makes every wave wait for all of its outstanding
+// global loads and stores (the next stage's prefetch, the records just
+// written) at each barrier; the passes only exchange data through LDS
+// between their phases, so their barriers leave global traffic in flight.
+__device__ __forceinline__ void lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Load through a global-address-space pointer.  Problem data are reached
+// through pointers read from descriptors, which the compiler would access
+// with flat instructions; flat loads also count as LDS operations, so every
+// LDS wait before a barrier would then wait for them too.  Global loads
+// leave the prefetched data in flight across the barriers.
+template <class T>
+__device__ __forceinline__ T gload(const T *p) {
+    typedef const __attribute__((address_space(1))) T *gptr;
+    return *(gptr)(p);
+}
+
 __device__ __forceinline__ double rs_sqrt(double v) { return sqrt(v); }
 __device__ __forceinline__ float rs_sqrt(float v) { return sqrtf(v); }
 
@@ -230,7 +252,7 @@ __device__ __forceinline__ StageSrc prob_stage(const DevProb &p, int t) {
     s.a = p.a ? p.a + (int64_t)t * p.sa : nullptr;
     s.lx = p.lx ? p.lx + (int64_t)t * p.slx : nullptr;
     s.lw = p.lw ? p.lw + (int64_t)t * p.slw : nullptr;
-    s.c = p.c ? p.c[(int64_t)t * p.sc] : 0.0;
+    s.c = p.c ? gload(p.c + (int64_t)t * p.sc) : 0.0;
     return s;
 }
 

@@ -119,28 +119,28 @@ __device__ __forceinline__ void fwd_fetch(FwdPrefetch<NX, NU, LAM> &f, Get get, 
 #pragma unroll
     for (int q = 0; q < FP::NK; ++q) {
         const int e = tid + q * NT;
-        f.k_[q] = e < NU * NX ? K[e] : 0.0;
+        f.k_[q] = e < NU * NX ? gload(K + e) : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < FP::NA; ++q) {
         const int e = tid + q * NT;
-        f.a_[q] = e < NX * NX ? src.A[e] : 0.0;
+        f.a_[q] = e < NX * NX ? gload(src.A + e) : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < FP::NB; ++q) {
         const int e = tid + q * NT;
-        f.b_[q] = e < NX * NU ? src.B[e] : 0.0;
+        f.b_[q] = e < NX * NU ? gload(src.B + e) : 0.0;
     }
     if constexpr (LAM) {
 #pragma unroll
         for (int q = 0; q < FP::NP; ++q) {
             const int e = tid + q * NT;
-            f.p_[q] = e < NX * NX ? P[e] : 0.0;
+            f.p_[q] = e < NX * NX ? gload(P + e) : 0.0;
         }
     }
-    f.kk = tid < NU ? fac.k(s)[tid] : 0.0;
-    f.av = (tid < NX && src.a) ? src.a[tid] : 0.0;
-    f.psi = (LAM && tid < NX) ? fac.Psi(s)[tid] : 0.0;
+    f.kk = tid < NU ? gload(fac.k(s) + tid) : 0.0;
+    f.av = (tid < NX && src.a) ? gload(src.a + tid) : 0.0;
+    f.psi = (LAM && tid < NX) ? gload(fac.Psi(s) + tid) : 0.0;
 }
 
 template <int NX, int NU, bool LAM>
@@ -196,7 +196,7 @@ __device__ void forward_m(MSmem<double, NX, NU, false, true> &S, Get get, int co
         fwd_commit_main<NX, NU, LAM>(S, f);
         fwd_commit_B<NX, NU, LAM>(Bcur, f);
     }
-    __syncthreads();
+    lds_sync();
     for (int s = 0; s < count; ++s) {
         if (s + 1 < count) fwd_fetch<NX, NU, LAM>(f, get, fac, s + 1);
         // half 1: w = k + K x, A x + a, (leaf) lam = P x - Psi
@@ -220,7 +220,7 @@ __device__ void forward_m(MSmem<double, NX, NU, false, true> &S, Get get, int co
         }
         emit.x(s, S.x);
         if (s + 1 < count) fwd_commit_B<NX, NU, LAM>(Bnxt, f);
-        __syncthreads();
+        lds_sync();
         // half 2: x_{t+1} = A x + a + B w
         if (tid < NX) {
             double acc = S.ax[tid];
@@ -233,7 +233,7 @@ __device__ void forward_m(MSmem<double, NX, NU, false, true> &S, Get get, int co
         double *t = Bcur;
         Bcur = Bnxt;
         Bnxt = t;
-        __syncthreads();
+        lds_sync();
     }
 }
 

@@ -219,16 +219,16 @@ __device__ __forceinline__ void prefetch_stage(Prefetch<T, NX, NU> &pf, const St
 #pragma unroll
     for (int q = 0; q < PF::NA; ++q) {
         const int e = tid + q * NT;
-        pf.a_[q] = e < NX * NX ? (T)s.A[e] : T(0);
+        pf.a_[q] = e < NX * NX ? (T)gload(s.A + e) : T(0);
     }
 #pragma unroll
     for (int q = 0; q < PF::NB; ++q) {
         const int e = tid + q * NT;
-        pf.b_[q] = e < NX * NU ? (T)s.B[e] : T(0);
+        pf.b_[q] = e < NX * NU ? (T)gload(s.B + e) : T(0);
     }
-    pf.av = (tid < NX && s.a) ? (T)s.a[tid] : T(0);
-    pf.lx = (tid < NX && s.lx) ? (T)s.lx[tid] : T(0);
-    pf.lw = (tid < NU && s.lw) ? (T)s.lw[tid] : T(0);
+    pf.av = (tid < NX && s.a) ? (T)gload(s.a + tid) : T(0);
+    pf.lx = (tid < NX && s.lx) ? (T)gload(s.lx + tid) : T(0);
+    pf.lw = (tid < NU && s.lw) ? (T)gload(s.lw + tid) : T(0);
     pf.c = (T)s.c;
     const int w = wave();
 #pragma unroll
@@ -239,9 +239,9 @@ __device__ __forceinline__ void prefetch_stage(Prefetch<T, NX, NU> &pf, const St
             int kind, ti, tj;
             phaseB_tile<NX, NU>(t, kind, ti, tj);
             tile_for<T>(ti, tj, [&](int r, int i, int j) {
-                if (kind == 0) q[r] = (T)s.Qx[i * NX + j];
-                else if (kind == 1) q[r] = s.Qxw ? (T)s.Qxw[j * NU + i] : T(0);
-                else q[r] = (T)s.Qw[i * NU + j];
+                if (kind == 0) q[r] = (T)gload(s.Qx + i * NX + j);
+                else if (kind == 1) q[r] = s.Qxw ? (T)gload(s.Qxw + j * NU + i) : T(0);
+                else q[r] = (T)gload(s.Qw + i * NU + j);
             });
         }
         pf.q[u] = q;
@@ -345,7 +345,7 @@ __device__ __forceinline__ void chol_inv_block32(T *G, T *LiT, int *bad, Side si
     T *T0 = LiT, *T1 = LiT + 256, *T2 = LiT + 512, *T3 = LiT + 768;   // L11^-1, L11^-T, L21, G22 - L21 L21'
     T *Gt = G, *Gm = G + 256, *Gc = G + 512;                         // L22^-T, L21 L11^-1, C
     for (int e = tid; e < H * H; e += NT) T0[e] = G[(e / H) * M + e % H];
-    __syncthreads();
+    lds_sync();
     if (w == 0) {
         int f = chol_inv_wave<H>(T0, T1);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -379,7 +379,7 @@ __device__ __forceinline__ void chol_inv_block32(T *G, T *LiT, int *bad, Side si
     } else {
         side();
     }
-    __syncthreads();
+    lds_sync();
     constexpr int R = M * M / NT;
     T li[R], lt[R];
 #pragma unroll
@@ -394,7 +394,7 @@ __device__ __forceinline__ void chol_inv_block32(T *G, T *LiT, int *bad, Side si
             lt[q] = j < H ? T(0) : Gt[bi * H + bj];
         }
     }
-    __syncthreads();
+    lds_sync();
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int e = tid + q * NT;
@@ -430,17 +430,21 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
     const int tid = threadIdx.x, w = wave(), l = lane();
     count = uni(count);
     Prefetch<T, NX, NU> pf;
+    v4_t<T> qt[Tiles<NX, NU>::PER_WAVE];
     if (tid == 0) S.bad = 0;
     if (count > 0) {
         prefetch_stage<T, NX, NU>(pf, get(count - 1));
         commit_stage(S, pf);
-    }
-    __syncthreads();
-    for (int s = count - 1; s >= 0; --s) {
-        // stage s inputs: A, B, a, lx, lw, c in LDS; Qx/Qxw'/Qw tiles in pf.q
-        v4_t<T> qt[Tiles<NX, NU>::PER_WAVE];
 #pragma unroll
         for (int u = 0; u < Tiles<NX, NU>::PER_WAVE; ++u) qt[u] = pf.q[u];
+    }
+    lds_sync();
+    // The next stage's inputs are loaded into registers at the start of a
+    // stage and committed at the start of phase E (nothing in phase E reads
+    // A, B or the stage vectors), before phase E issues its global stores, so
+    // the only wait for the loads does not also wait for those stores.
+    for (int s = count - 1; s >= 0; --s) {
+        // stage s inputs: A, B, a, lx, lw, c in LDS; Qx/Qxw'/Qw tiles in qt
         if (s > 0) prefetch_stage<T, NX, NU>(pf, get(s - 1));
         pre(s, S);
         // ---- phase A: W = P[A B], (RED) B'V; P a, Psi - P a, (RED) V'a
@@ -481,7 +485,7 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
                 S.Vta[i] = acc;
             }
         }
-        __syncthreads();
+        lds_sync();
         // ---- phase B: F = Qx + A'W_A (lower), H' = Qxw' + B'W_A, G = Qw + B'W_B (lower)
         {
             using PF = Tiles<NX, NU>;
@@ -518,7 +522,7 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
                 S.gw[i] = acc;
             }
         }
-        __syncthreads();
+        lds_sync();
         // ---- phase C: factor and invert G (wave 0); (RED) A'V into W (waves 1-3)
         auto av_tiles = [&]() {
             if constexpr (RED) {
@@ -539,7 +543,7 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
                 av_tiles();
             }
         }
-        __syncthreads();
+        lds_sync();
         if (tid == 0 && S.bad) {
             record_failure(info, inst, fail_code, stage_base < 0 ? -1 : stage_base + s);
             S.bad = 0;
@@ -565,11 +569,16 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
                 S.z[i] = acc;
             }
         }
-        __syncthreads();
+        lds_sync();
         // ---- phase E: P = F - Y'Y, (RED) Q_w_hat += X'X, V = A'V - Y'X,
         //      (SOLVE) K = -L^{-T} Y, k = L^{-T} z;
         //      Psi = g_x - Y'z, (RED) v += V'a + X'z, cbar -= z'z/2
         {
+            if (s > 0) {
+                commit_stage(S, pf);
+#pragma unroll
+                for (int u = 0; u < Tiles<NX, NU>::PER_WAVE; ++u) qt[u] = pf.q[u];
+            }
             constexpr int TL = TX * (TX + 1) / 2, TQ = RED ? TL : 0, TV = RED ? TX * TX : 0,
                           TK = KFORM ? TU * TX : 0, TLT = LTFORM ? TU * TX : 0;
             for (int t = w; t < TL + TQ + TV + TK + TLT; t += 4) {
@@ -647,9 +656,8 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
                 const T zz = wave_sum(l < NU ? S.z[l] * S.z[l] : T(0));
                 if (l == 0) S.cbar -= T(0.5) * zz;
             }
-            if (s > 0) commit_stage(S, pf);
         }
-        __syncthreads();
+        lds_sync();
     }
 }
 

@@ -67,7 +67,12 @@ struct Op {
     }
 };
 
-__device__ __forceinline__ void wsync() { __syncthreads(); }
+// LDS-only barrier (global loads and stores stay in flight across it).
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
