@@ -126,6 +126,49 @@ __device__ __forceinline__ void lower_tile(int t, int &ti, int &tj) {
     tj = t - ti * (ti + 1) / 2;
 }
 
+// Column of lower-triangular tile t (t = ti (ti + 1) / 2 + tj).
+constexpr int lt_col(int t) {
+    int ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    return t - ti * (ti + 1) / 2;
+}
+
+// The tiles of F, H' and G (phase B enumeration) and the wave that owns each.
+// Round robin in general.  For n_u = 16 and n_x <= 32 the first three phases
+// are merged (FAST): wave 0 forms G and factors it while wave 1 + tj owns
+// column block tj of W_A = P A and the F and H' tiles in that column; then F
+// stays in its owner's registers until phase E forms P from it.
+template <int NX, int NU>
+struct Tiles {
+    static constexpr int TX = NX / 16;
+    static constexpr int TF = (NX / 16) * (NX / 16 + 1) / 2, TH = (NU / 16) * (NX / 16), TG = (NU / 16) * (NU / 16 + 1) / 2;
+    static constexpr int TILES = TF + TH + TG;
+    static constexpr bool FAST = NU == 16 && (NX == 16 || NX == 32);
+    static constexpr int col(int t) { return t < TF ? lt_col(t) : t < TF + TH ? (t - TF) % TX : 0; }
+    static constexpr int owner(int t) { return !FAST ? t % 4 : (t >= TF + TH ? 0 : 1 + col(t)); }
+    static constexpr int slot(int t) {
+        int n = 0;
+        for (int u = 0; u < t; ++u) n += owner(u) == owner(t) ? 1 : 0;
+        return n;
+    }
+    static constexpr int fslot(int t) {        // rank among the owner's F tiles
+        int n = 0;
+        for (int u = 0; u < t; ++u) n += (u < TF && owner(u) == owner(t)) ? 1 : 0;
+        return n;
+    }
+    static constexpr int max_slots() {
+        int m = 0;
+        for (int t = 0; t < TILES; ++t) m = slot(t) + 1 > m ? slot(t) + 1 : m;
+        return m;
+    }
+    static constexpr int max_fslots() {
+        int m = 1;
+        for (int t = 0; t < TF; ++t) m = fslot(t) + 1 > m ? fslot(t) + 1 : m;
+        return m;
+    }
+    static constexpr int PER_WAVE = max_slots(), PER_WAVE_F = max_fslots();
+};
+
 // ------------------------------------------------------------------- LDS
 template <class T, int NX, int NU, bool RED, bool SOLVE>
 struct MSmem {
@@ -142,6 +185,7 @@ struct MSmem {
     T Qh[RED ? NX * NX : 1];
     T BV[RED ? NU * NX : 1];   // B'V
     T X[RED ? NU * NX : 1];    // L^{-1} B'V
+    T AV[RED && Tiles<NX, NU>::FAST ? NX * NX : 1];   // A'V (merged first phase)
     T Psi[NX], av[NX], lx[NX], pt[NX], gx[NX], x[NX], ax[NX];
     T lw[NU], gw[NU], z[NU], kk[NU], wv[NU];
     T v[RED ? NX : 1], Vta[RED ? NX : 1];
@@ -179,12 +223,7 @@ struct NoEmit {
 // Per-thread registers holding the next stage's inputs until they can be
 // written to LDS (A, B, a, lx, lw, c) and the tiles of Qx, Qxw', Qw that this
 // thread's wave adds in the F / H' / G products.
-template <int NX, int NU>
-struct Tiles {
-    static constexpr int TF = (NX / 16) * (NX / 16 + 1) / 2, TH = (NU / 16) * (NX / 16), TG = (NU / 16) * (NU / 16 + 1) / 2;
-    static constexpr int TILES = TF + TH + TG;
-    static constexpr int PER_WAVE = (TILES + 3) / 4;
-};
+
 
 template <class T, int NX, int NU>
 struct Prefetch : Tiles<NX, NU> {
@@ -232,19 +271,17 @@ __device__ __forceinline__ void prefetch_stage(Prefetch<T, NX, NU> &pf, const St
     pf.c = (T)s.c;
     const int w = wave();
 #pragma unroll
-    for (int u = 0; u < PF::PER_WAVE; ++u) {
-        const int t = w + 4 * u;
+    for (int t = 0; t < PF::TILES; ++t) {
+        if (PF::owner(t) != w) continue;
         v4_t<T> q = zero4<T>();
-        if (t < PF::TILES) {
-            int kind, ti, tj;
-            phaseB_tile<NX, NU>(t, kind, ti, tj);
-            tile_for<T>(ti, tj, [&](int r, int i, int j) {
-                if (kind == 0) q[r] = (T)gload(s.Qx + i * NX + j);
-                else if (kind == 1) q[r] = s.Qxw ? (T)gload(s.Qxw + j * NU + i) : T(0);
-                else q[r] = (T)gload(s.Qw + i * NU + j);
-            });
-        }
-        pf.q[u] = q;
+        int kind, ti, tj;
+        phaseB_tile<NX, NU>(t, kind, ti, tj);
+        tile_for<T>(ti, tj, [&](int r, int i, int j) {
+            if (kind == 0) q[r] = (T)gload(s.Qx + i * NX + j);
+            else if (kind == 1) q[r] = s.Qxw ? (T)gload(s.Qxw + j * NU + i) : T(0);
+            else q[r] = (T)gload(s.Qw + i * NU + j);
+        });
+        pf.q[PF::slot(t)] = q;
     }
 }
 
@@ -404,6 +441,13 @@ __device__ __forceinline__ void chol_inv_block32(T *G, T *LiT, int *bad, Side si
 }
 
 // Wave-level sum over the 64 lanes (result in every lane).
+// Orders one wavefront's LDS accesses (no workgroup barrier).
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -447,22 +491,68 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
         // stage s inputs: A, B, a, lx, lw, c in LDS; Qx/Qxw'/Qw tiles in qt
         if (s > 0) prefetch_stage<T, NX, NU>(pf, get(s - 1));
         pre(s, S);
-        // ---- phase A: W = P[A B], (RED) B'V; P a, Psi - P a, (RED) V'a
-        {
-            constexpr int TW = TX * (TX + TU), TBV = RED ? TU * TX : 0;
-            for (int t = w; t < TW + TBV; t += 4) {
-                v4_t<T> acc = zero4<T>();
-                if (t < TW) {
-                    const int ti = t / (TX + TU), tj = t % (TX + TU);
-                    if (tj < TX)
-                        acc = mma<NX, true, false>(acc, S.P, NX, S.A, NX, ti, tj);
-                    else
-                        acc = mma<NX, true, false>(acc, S.P, NX, S.B, NU, ti, tj - TX);
+        using TT = Tiles<NX, NU>;
+        v4_t<T> fkeep[TT::PER_WAVE_F];      // F tiles of this wave (merged phase)
+        if constexpr (TT::FAST) {
+            // ---- merged phases A-C (n_u = 16): wave 0: W_B = P B, G = Qw + B'W_B, L^{-1};
+            //      wave 1 + tj: W_A column tj, F and H' tiles of column tj;
+            //      wave RW (RED): B'V, A'V, V'a; wave 3: P a, Psi - P a, cbar, g_x, g_w
+            constexpr int RW = TX == 1 ? 2 : 3;
+            if (w == 0) {
+#pragma unroll
+                for (int ti = 0; ti < TX; ++ti) {
+                    v4_t<T> acc = mma<NX, true, false>(zero4<T>(), S.P, NX, S.B, NU, ti, 0);
+                    tile_for<T>(ti, 0, [&](int r, int i, int j) { S.W[i * NW + NX + j] = acc[r]; });
+                }
+                wave_fence();
+                {
+                    constexpr int tg = TT::TF + TT::TH;
+                    v4_t<T> acc = mma<NX, true, false>(qt[TT::slot(tg)], S.B, NU, S.W + NX, NW, 0, 0);
+                    tile_for<T>(0, 0, [&](int r, int i, int j) { put_sym(S.G, NU, 0, 0, i, j, acc[r]); });
+                }
+                wave_fence();
+                const int f = chol_inv_wave<NU>(S.G, S.LiT);
+                if (f && l == 0) S.bad = 1;
+            } else if (w <= TX) {
+                const int tj = w - 1;
+#pragma unroll
+                for (int ti = 0; ti < TX; ++ti) {
+                    v4_t<T> acc = mma<NX, true, false>(zero4<T>(), S.P, NX, S.A, NX, ti, tj);
                     tile_for<T>(ti, tj, [&](int r, int i, int j) { S.W[i * NW + j] = acc[r]; });
-                } else if constexpr (RED) {
-                    const int u = t - TW, ti = u / TX, tj = u % TX;
-                    acc = mma<NX, true, false>(acc, S.B, NU, S.V, NX, ti, tj);
-                    tile_for<T>(ti, tj, [&](int r, int i, int j) { S.BV[i * NX + j] = acc[r]; });
+                }
+                wave_fence();
+#pragma unroll
+                for (int t = 0; t < TT::TF + TT::TH; ++t) {
+                    if (TT::owner(t) != w) continue;
+                    int kind, ti, tjj;
+                    phaseB_tile<NX, NU>(t, kind, ti, tjj);
+                    if (kind == 0) {
+                        fkeep[TT::fslot(t)] = mma<NX, true, false>(qt[TT::slot(t)], S.A, NX, S.W, NW, ti, tjj);
+                    } else {
+                        v4_t<T> acc = mma<NX, true, false>(qt[TT::slot(t)], S.B, NU, S.W, NW, ti, tjj);
+                        tile_for<T>(ti, tjj, [&](int r, int i, int j) { S.HT[i * NX + j] = acc[r]; });
+                    }
+                }
+            }
+            if constexpr (RED) {
+                if (w == RW) {
+#pragma unroll
+                    for (int tj = 0; tj < TX; ++tj) {
+                        v4_t<T> acc = mma<NX, true, false>(zero4<T>(), S.B, NU, S.V, NX, 0, tj);
+                        tile_for<T>(0, tj, [&](int r, int i, int j) { S.BV[i * NX + j] = acc[r]; });
+                    }
+#pragma unroll
+                    for (int t = 0; t < TX * TX; ++t) {
+                        const int ti = t / TX, tj = t % TX;
+                        v4_t<T> acc = mma<NX, true, false>(zero4<T>(), S.A, NX, S.V, NX, ti, tj);
+                        tile_for<T>(ti, tj, [&](int r, int i, int j) { S.AV[i * NX + j] = acc[r]; });
+                    }
+                    if (VEC && l < NX) {
+                        T acc = T(0);
+#pragma unroll 8
+                        for (int k = 0; k < NX; ++k) acc += S.V[k * NX + l] * S.av[k];
+                        S.Vta[l] = acc;
+                    }
                 }
             }
             if (VEC && w == 3) {
@@ -477,70 +567,116 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
                 // cbar += 1/2 a'Pa - Psi'a + c (Alg. 2, with P_{t+1}, Psi_{t+1})
                 part = wave_sum(part);
                 if (l == 0) S.cbar += part + S.c;
-            } else if (VEC && RED && tid >= 128 && tid < 128 + NX) {
-                const int i = tid - 128;
-                T acc = T(0);
+                wave_fence();
+                if (l < NX) {
+                    T acc = -S.lx[l];
 #pragma unroll 8
-                for (int k = 0; k < NX; ++k) acc += S.V[k * NX + i] * S.av[k];
-                S.Vta[i] = acc;
+                    for (int k = 0; k < NX; ++k) acc += S.A[k * NX + l] * S.pt[k];
+                    S.gx[l] = acc;
+                } else if (l < NX + NU) {
+                    const int i = l - NX;
+                    T acc = -S.lw[i];
+#pragma unroll 8
+                    for (int k = 0; k < NX; ++k) acc += S.B[k * NU + i] * S.pt[k];
+                    S.gw[i] = acc;
+                }
             }
-        }
-        lds_sync();
-        // ---- phase B: F = Qx + A'W_A (lower), H' = Qxw' + B'W_A, G = Qw + B'W_B (lower)
-        {
-            using PF = Tiles<NX, NU>;
-#pragma unroll
-            for (int u = 0; u < PF::PER_WAVE; ++u) {
-                const int t = w + 4 * u;
-                if (t < PF::TILES) {
-                    int kind, ti, tj;
-                    phaseB_tile<NX, NU>(t, kind, ti, tj);
-                    v4_t<T> acc = qt[u];
-                    if (kind == 0) {
-                        acc = mma<NX, true, false>(acc, S.A, NX, S.W, NW, ti, tj);
-                        tile_for<T>(ti, tj, [&](int r, int i, int j) { put_sym(S.F(), NX, ti, tj, i, j, acc[r]); });
-                    } else if (kind == 1) {
-                        acc = mma<NX, true, false>(acc, S.B, NU, S.W, NW, ti, tj);
-                        tile_for<T>(ti, tj, [&](int r, int i, int j) { S.HT[i * NX + j] = acc[r]; });
-                    } else {
-                        acc = mma<NX, true, false>(acc, S.B, NU, S.W + NX, NW, ti, tj);
-                        tile_for<T>(ti, tj, [&](int r, int i, int j) { put_sym(S.G, NU, ti, tj, i, j, acc[r]); });
+        } else {
+            // ---- phase A: W = P[A B], (RED) B'V; P a, Psi - P a, (RED) V'a
+            {
+                constexpr int TW = TX * (TX + TU), TBV = RED ? TU * TX : 0;
+                for (int t = w; t < TW + TBV; t += 4) {
+                    v4_t<T> acc = zero4<T>();
+                    if (t < TW) {
+                        const int ti = t / (TX + TU), tj = t % (TX + TU);
+                        if (tj < TX)
+                            acc = mma<NX, true, false>(acc, S.P, NX, S.A, NX, ti, tj);
+                        else
+                            acc = mma<NX, true, false>(acc, S.P, NX, S.B, NU, ti, tj - TX);
+                        tile_for<T>(ti, tj, [&](int r, int i, int j) { S.W[i * NW + j] = acc[r]; });
+                    } else if constexpr (RED) {
+                        const int u = t - TW, ti = u / TX, tj = u % TX;
+                        acc = mma<NX, true, false>(acc, S.B, NU, S.V, NX, ti, tj);
+                        tile_for<T>(ti, tj, [&](int r, int i, int j) { S.BV[i * NX + j] = acc[r]; });
                     }
                 }
-            }
-            if (VEC && tid >= 192 && tid < 192 + NX) {
-                const int i = tid - 192;
-                T acc = -S.lx[i];
-#pragma unroll 8
-                for (int k = 0; k < NX; ++k) acc += S.A[k * NX + i] * S.pt[k];
-                S.gx[i] = acc;
-            } else if (VEC && tid >= 128 && tid < 128 + NU) {
-                const int i = tid - 128;
-                T acc = -S.lw[i];
-#pragma unroll 8
-                for (int k = 0; k < NX; ++k) acc += S.B[k * NU + i] * S.pt[k];
-                S.gw[i] = acc;
-            }
-        }
-        lds_sync();
-        // ---- phase C: factor and invert G (wave 0); (RED) A'V into W (waves 1-3)
-        auto av_tiles = [&]() {
-            if constexpr (RED) {
-                for (int t = w - 1; t < TX * TX; t += 3) {
-                    const int ti = t / TX, tj = t % TX;
-                    v4_t<T> acc = mma<NX, true, false>(zero4<T>(), S.A, NX, S.V, NX, ti, tj);
-                    tile_for<T>(ti, tj, [&](int r, int i, int j) { S.W[i * NX + j] = acc[r]; });
+                if (VEC && w == 3) {
+                    T part = T(0);
+                    if (l < NX) {
+                        T pa = T(0);
+    #pragma unroll 8
+                        for (int k = 0; k < NX; ++k) pa += S.P[k * NX + l] * S.av[k];
+                        S.pt[l] = S.Psi[l] - pa;
+                        part = S.av[l] * (T(0.5) * pa - S.Psi[l]);
+                    }
+                    // cbar += 1/2 a'Pa - Psi'a + c (Alg. 2, with P_{t+1}, Psi_{t+1})
+                    part = wave_sum(part);
+                    if (l == 0) S.cbar += part + S.c;
+                } else if (VEC && RED && tid >= 128 && tid < 128 + NX) {
+                    const int i = tid - 128;
+                    T acc = T(0);
+    #pragma unroll 8
+                    for (int k = 0; k < NX; ++k) acc += S.V[k * NX + i] * S.av[k];
+                    S.Vta[i] = acc;
                 }
             }
-        };
-        if constexpr (NU == 32) {
-            chol_inv_block32(S.G, S.LiT, &S.bad, av_tiles);
-        } else {
-            if (w == 0) {
-                const int f = chol_inv_wave<NU>(S.G, S.LiT);
-                if (f && l == 0) S.bad = 1;
+            lds_sync();
+            // ---- phase B: F = Qx + A'W_A (lower), H' = Qxw' + B'W_A, G = Qw + B'W_B (lower)
+            {
+                using PF = Tiles<NX, NU>;
+    #pragma unroll
+                for (int u = 0; u < PF::PER_WAVE; ++u) {
+                    const int t = w + 4 * u;
+                    if (t < PF::TILES) {
+                        int kind, ti, tj;
+                        phaseB_tile<NX, NU>(t, kind, ti, tj);
+                        v4_t<T> acc = qt[u];
+                        if (kind == 0) {
+                            acc = mma<NX, true, false>(acc, S.A, NX, S.W, NW, ti, tj);
+                            tile_for<T>(ti, tj, [&](int r, int i, int j) { put_sym(S.F(), NX, ti, tj, i, j, acc[r]); });
+                        } else if (kind == 1) {
+                            acc = mma<NX, true, false>(acc, S.B, NU, S.W, NW, ti, tj);
+                            tile_for<T>(ti, tj, [&](int r, int i, int j) { S.HT[i * NX + j] = acc[r]; });
+                        } else {
+                            acc = mma<NX, true, false>(acc, S.B, NU, S.W + NX, NW, ti, tj);
+                            tile_for<T>(ti, tj, [&](int r, int i, int j) { put_sym(S.G, NU, ti, tj, i, j, acc[r]); });
+                        }
+                    }
+                }
+                if (VEC && tid >= 192 && tid < 192 + NX) {
+                    const int i = tid - 192;
+                    T acc = -S.lx[i];
+    #pragma unroll 8
+                    for (int k = 0; k < NX; ++k) acc += S.A[k * NX + i] * S.pt[k];
+                    S.gx[i] = acc;
+                } else if (VEC && tid >= 128 && tid < 128 + NU) {
+                    const int i = tid - 128;
+                    T acc = -S.lw[i];
+    #pragma unroll 8
+                    for (int k = 0; k < NX; ++k) acc += S.B[k * NU + i] * S.pt[k];
+                    S.gw[i] = acc;
+                }
+            }
+            lds_sync();
+            // ---- phase C: factor and invert G (wave 0); (RED) A'V into W (waves 1-3)
+            auto av_tiles = [&]() {
+                if constexpr (RED) {
+                    for (int t = w - 1; t < TX * TX; t += 3) {
+                        const int ti = t / TX, tj = t % TX;
+                        v4_t<T> acc = mma<NX, true, false>(zero4<T>(), S.A, NX, S.V, NX, ti, tj);
+                        tile_for<T>(ti, tj, [&](int r, int i, int j) { S.W[i * NX + j] = acc[r]; });
+                    }
+                }
+            };
+            if constexpr (NU == 32) {
+                chol_inv_block32(S.G, S.LiT, &S.bad, av_tiles);
             } else {
-                av_tiles();
+                if (w == 0) {
+                    const int f = chol_inv_wave<NU>(S.G, S.LiT);
+                    if (f && l == 0) S.bad = 1;
+                } else {
+                    av_tiles();
+                }
             }
         }
         lds_sync();
@@ -581,7 +717,32 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
             }
             constexpr int TL = TX * (TX + 1) / 2, TQ = RED ? TL : 0, TV = RED ? TX * TX : 0,
                           TK = KFORM ? TU * TX : 0, TLT = LTFORM ? TU * TX : 0;
-            for (int t = w; t < TL + TQ + TV + TK + TLT; t += 4) {
+            if constexpr (TT::FAST) {
+                // P = F - Y'Y on the waves that hold the F tiles
+#pragma unroll
+                for (int t = 0; t < TL; ++t) {
+                    if (TT::owner(t) != w) continue;
+                    int ti, tj;
+                    lower_tile(t, ti, tj);
+                    v4_t<T> acc = mma<NU, true, false>(zero4<T>(), S.Y(), NX, S.Y(), NX, ti, tj);
+                    const v4_t<T> fv = fkeep[TT::fslot(t)];
+                    tile_for<T>(ti, tj, [&](int r, int i, int j) {
+                        if (ti != tj || i >= j) {
+                            const T v = fv[r] - acc[r];
+                            S.P[i * NX + j] = v;
+                            S.P[j * NX + i] = v;
+                            if constexpr (PEMIT) {
+                                out.P(s, i, j, v);
+                                if (i != j) out.P(s, j, i, v);
+                            }
+                        }
+                    });
+                }
+            }
+            // the other tiles in wave order 0, 3, 2, 1 when the F owners
+            // already have the P tiles
+            const int first = TT::FAST ? TL + ((4 - w) & 3) : w;
+            for (int t = first; t < TL + TQ + TV + TK + TLT; t += 4) {
                 if (t < TL) {
                     int ti, tj;
                     lower_tile(t, ti, tj);
@@ -610,8 +771,9 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
                     if constexpr (RED) {
                         const int u = t - TL - TQ, ti = u / TX, tj = u % TX;
                         v4_t<T> acc = mma<NU, true, false>(zero4<T>(), S.Y(), NX, S.X, NX, ti, tj);
+                        const T *av = TT::FAST ? S.AV : S.W;       // A'V
                         tile_for<T>(ti, tj, [&](int r, int i, int j) {
-                            const T v = S.W[i * NX + j] - acc[r];
+                            const T v = av[i * NX + j] - acc[r];
                             S.V[i * NX + j] = v;
                             if constexpr (Out::VF) out.V(s, i, j, v);
                         });
