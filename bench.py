@@ -267,6 +267,58 @@ def run_precision(prec, args, data, dev):
     return res, host
 
 
+def ingest_counters(fetch_csv, write_csv, copy_bytes, workload):
+    """Write profiles/traffic.json from two rocprofv3 --pmc runs of this script
+    (FETCH_SIZE, then WRITE_SIZE, both with --copy-calibration-mib): HBM bytes
+    per dispatch of each solver kernel's first full-batch launch, scaled by the
+    factor that the plain device copy of `copy_bytes` shows on the same
+    counter."""
+    import csv
+
+    def rows(path, counter):
+        out = []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Grid_Size"]),
+                                float(r["Counter_Value"])))
+        return sorted(out)
+
+    names = ("km_leaf_up", "km_leaf_down", "km_tree", "kf_leaf_up", "kf_leaf_down", "kf_tree",
+             "kv_leaf_up", "kv_leaf_down", "kv_tree", "kr_residual")
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rr = rows(path, counter)
+        copies = [v for _, k, _, v in rr if "copyBuffer" in k]
+        if not copies:
+            raise SystemExit("no device copy dispatch in %s" % path)
+        scale = copy_bytes / (max(copies) * 1024.0)
+        for name in names:
+            mine = [(g, v) for _, k, g, v in rr if name + "<" in k]
+            if not mine:
+                continue
+            gmax = max(g for g, _ in mine)
+            first = next(v for g, v in mine if g == gmax)
+            per.setdefault(name, {})[counter] = (first, scale)
+    records = []
+    for name, c in sorted(per.items()):
+        if "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
+            continue
+        (fk, fs), (wk, ws) = c["FETCH_SIZE"], c["WRITE_SIZE"]
+        records.append({"kernel": name, "workload": workload + ("_fp64" if name.startswith("km_") else "_mixed"),
+                        "csrc_hash": csrc_hash(), "fetch_kib_raw": fk, "write_kib_raw": wk,
+                        "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+                        "bytes_per_launch": fk * 1024.0 * fs + wk * 1024.0 * ws})
+    rec = {"note": "HBM bytes per dispatch from rocprofv3 FETCH_SIZE / WRITE_SIZE (first full-batch dispatch "
+                   "of each kernel), each scaled by the factor that a plain device copy of %d bytes shows on "
+                   "the same counter" % copy_bytes, "records": records}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    for r in records:
+        log("%-14s %-45s %.3f GB/launch" % (r["kernel"], r["workload"], r["bytes_per_launch"] / 1e9))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,7 +341,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 counter collections of this "
+                         "script (run with --copy-calibration-mib) and exit")
     args = ap.parse_args()
+
+    if args.ingest_counters:
+        ingest_counters(args.ingest_counters[0], args.ingest_counters[1], args.copy_calibration_mib << 20,
+                        "uftoc_g2_nx%d_nu%d_N%d_batch%d" % (args.nx, args.nu, args.N, args.batch))
+        return
 
     if args.gpus != 1:
         print("bench.py measures one GPU only: sharding instances or a horizon across GPUs is designed "

@@ -34,6 +34,7 @@ struct Group {
     int32_t ntop = 0;                       // single-leaf instances
     size_t off_leaves = 0, off_items = 0, off_flags = 0, off_slots = 0, off_scratch = 0, off_fstore = 0,
            off_fvec = 0;
+    size_t off_lbw = 0, lbw_unit = 0;       // large-block workspace (per workgroup)
 };
 
 }  // namespace
@@ -43,6 +44,7 @@ struct rs_plan_s {
     int Ns = 16, branch = 4, top_max = 4, prec = RS_FP64, max_refine = 5;
     bool factored = false;          // workspace holds the stored factorization
     bool mixed = false;             // FP32 leaf factorization + FP64 refinement
+    bool via_factor = false;        // FP64 solve = stored factorization + solve (large-block shapes)
     int32_t total_leaves = 0;
     std::vector<InstInfo> inst;     // per instance: leaf range (refinement reductions)
     std::vector<size_t> off_cbuf;   // per instance: correction buffers (mixed)
@@ -292,6 +294,11 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         }
         const ShapeEntry *se = find_shape(nx, nu);
         const int f32 = P->mixed ? 1 : 0;
+        if (se && se->large && !P->mixed) {
+            // no fused kernels: the FP64 solve runs on the stored factorization
+            P->factored = true;
+            P->via_factor = true;
+        }
         if (!se || (P->factored && !(se->factor[f32][0] && se->vsolve[f32][0])) || (P->mixed && !se->refine[0])) {
             delete P;
             return RS_ERR_UNSUPPORTED;
@@ -356,6 +363,13 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         const size_t esz = sizeof(double);
         off = align_up(off + esz * (size_t)g.scratch_elems);
         g.leaf_stages = g.scratch_elems / g.shape->scratch_per_stage;
+        if (g.shape->large) {
+            const int64_t units = std::max<int64_t>(std::min<int64_t>((int64_t)g.leaves.size(), LB_LEAF_UNITS),
+                                                    std::min<int64_t>((int64_t)g.items.size(), LB_TREE_UNITS));
+            g.lbw_unit = large_unit_bytes(g.nx, g.nu);
+            g.off_lbw = off;
+            off = align_up(off + g.lbw_unit * (size_t)std::max<int64_t>(units, 1));
+        }
         g.off_fstore = off;
         if (P->factored) {
             const size_t rec = P->mixed ? sizeof(float) : sizeof(double);
@@ -597,6 +611,10 @@ static GroupArgs group_args(rs_plan P, char *W, size_t gi, int32_t *info, bool c
     a.ntop = g.ntop;
     a.fstore = P->factored ? W + g.off_fstore : nullptr;
     a.fvec = P->factored ? reinterpret_cast<double *>(W + g.off_fvec) : nullptr;
+    a.lbw = g.shape->large ? W + g.off_lbw : nullptr;
+    a.lbw_unit = (int64_t)g.lbw_unit;
+    a.nx = g.nx;
+    a.nu = g.nu;
     if (P->mixed) {
         a.corr = user + P->count;
         a.conv = with_conv ? reinterpret_cast<const int32_t *>(W + P->off_conv) : nullptr;
@@ -695,6 +713,10 @@ static rs_status mixed_solve(rs_plan P, char *W, int32_t *info, hipStream_t st) 
 // Kernel sequence of a call once the descriptors are bound.
 // mode 0 = rs_batch_solve, 1 = rs_factor, 2 = rs_solve.
 static rs_status run_sequence(rs_plan P, char *W, int32_t *info, hipStream_t st, int mode) {
+    if (!P->mixed && P->via_factor && mode == 0) {
+        rs_status s = launch_pass(P, W, info, st, 1, false, false, false);
+        return s == RS_OK ? launch_pass(P, W, info, st, 2, true, false, false) : s;
+    }
     if (!P->mixed) return launch_pass(P, W, info, st, mode, mode == 2, false, false);
     if (mode != 2) {
         rs_status s = launch_pass(P, W, info, st, 1, false, false, false);

@@ -362,6 +362,7 @@ const ShapeEntry *find_shape(int nx, int nu) {
             ShapeEntry e;
             e.nx = a;
             e.nu = b;
+            e.large = false;
             e.fp64[0] = mfma_leaf_up(a, b) ? mfma_leaf_up(a, b) : up;
             e.fp64[1] = mfma_tree(a) ? mfma_tree(a) : tr;
             e.fp64[2] = mfma_leaf_down(a, b) ? mfma_leaf_down(a, b) : dn;
@@ -382,7 +383,31 @@ const ShapeEntry *find_shape(int nx, int nu) {
     }
     for (int i = 0; i < n; ++i)
         if (table[i].nx == nx && table[i].nu == nu) return &table[i];
-    return nullptr;
+    // large-block family: any other multiple-of-16 shape up to 128
+    static ShapeEntry large[8][8];
+    static bool large_init = false;
+    if (!large_shape(nx, nu)) return nullptr;
+    if (!large_init) {
+        for (int a = 0; a < 8; ++a)
+            for (int b = 0; b < 8; ++b) {
+                ShapeEntry &e = large[a][b];
+                e.nx = 16 * (a + 1);
+                e.nu = 16 * (b + 1);
+                e.large = true;
+                for (int k = 0; k < 3; ++k) {
+                    e.fp64[k] = nullptr;
+                    for (int f = 0; f < 2; ++f) {
+                        e.factor[f][k] = large_factor(k, f == 1);
+                        e.vsolve[f][k] = large_vector(k, f == 1);
+                    }
+                }
+                e.refine[0] = large_refine(0);
+                e.refine[1] = large_refine(1);
+                e.scratch_per_stage = 1;      // leaf stage index = scratch offset
+            }
+        large_init = true;
+    }
+    return &large[nx / 16 - 1][nu / 16 - 1];
 }
 
 }  // namespace rs

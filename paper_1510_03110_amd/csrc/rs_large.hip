@@ -1,0 +1,1185 @@
+// Large-block kernels of the parallel Riccati solve: n_x and n_u multiples
+// of 16 up to 128 that have no register- and LDS-resident specialisation
+// (the n_x = 64 and n_x = 128 problems).  A 64 x 64 FP64 stage already needs
+// about 260 KB of working set, more than a CU's LDS, so here the matrices of a
+// work unit live in a per-workgroup workspace in global memory (L2-resident
+// while the unit runs) and only vectors use LDS.  Sizes are run-time values.
+//
+// The family implements the factor / solve split; the fused FP64 solve of
+// these shapes is the stored factorization followed by the solve on it.
+//   kl_leaf_up     one workgroup per leaf (grid-stride): matrix lines of
+//                  Alg. 4 or of the last-leaf elimination; up records and the
+//                  matrix part of the M1 message
+//   kl_tree        work-queue kernel over the master levels: Alg. 4 on master
+//                  groups (Alg. 5), elimination of the last group, and the
+//                  factorization of the top / down subproblems (Alg. 6)
+//   kl_leaf_down   whole-problem leaves: Alg. 1 with the true terminal
+//   kw_leaf_up / kw_tree / kw_leaf_down
+//                  the vector lines of the same passes and the forward
+//                  recursion (Alg. 2-3, vector part of Alg. 4), one
+//                  workgroup per unit
+//   kw_residual / kw_update
+//                  FP64 KKT residual and update of iterative refinement
+//
+// Every dense product of a stage is a list of 16x16 output tiles on the
+// matrix cores (v_mfma_f64_16x16x4f64, or the f32 form for FP32 factors),
+// tile t of a product going to wave t mod 4; products of one phase are
+// independent, and a workgroup barrier separates phases.  Per stage:
+//   W = P [A B];  (Alg. 4) B'V, A'V
+//   F = Qx + A'W_A,  H = Qxw + A'W_B,  G = Qw + B'W_B                 (Alg. 1)
+//   G = L L', L^{-1}  (blocked: 16 x 16 diagonal factorizations by one
+//                      wavefront, panels and trailing updates on MFMA)
+//   Y' = H L^{-T};  (Alg. 4) X = L^{-1} B'V
+//   P = F - Y'Y,  K = -L^{-T} Y;  (Alg. 4) Q_w_hat += X'X, V = A'V - Y'X,
+//   L_t = -L^{-T} X
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "rs_launch.hpp"
+#include "rs_mfma.hpp"
+#include "rs_vec.hpp"
+
+namespace rs {
+namespace lb {
+
+using mf::lane;
+using mf::MT;
+using mf::v4_t;
+using mf::wave;
+
+constexpr int SPIN_LIMIT = 1 << 26;
+
+__device__ __forceinline__ TreeItem load_item(const TreeItem *tab, int i) {
+    const TreeItem r = tab[i];
+    TreeItem u;
+    u.kind = uni(r.kind);
+    u.inst = uni(r.inst);
+    u.level = uni(r.level);
+    u.first = uni(r.first);
+    u.count = uni(r.count);
+    u.last = uni(r.last);
+    u.term_slot = uni(r.term_slot);
+    u.out_slot = uni(r.out_slot);
+    u.dep_first = uni(r.dep_first);
+    u.dep_count = uni(r.dep_count);
+    return u;
+}
+
+// ------------------------------------------------------------- workspace
+// Matrices of one work unit, row-major, elements of T:
+//   P V Qh F AV (n x n) | AB W (n x (n+m)) | H HY (n x m) | BV X (m x n) |
+//   G Li LiT Lp (m x m) | D DT (16 x 16) | Tm (m x 16)
+template <class T>
+struct WS {
+    int n, m, nw;
+    T *P, *V, *Qh, *F, *AV, *AB, *W, *H, *HY, *BV, *X, *G, *Li, *LiT, *Lp, *D, *DT, *Tm;
+    __device__ void bind(T *b, int n_, int m_) {
+        n = n_;
+        m = m_;
+        nw = n + m;
+        const int64_t nn = (int64_t)n * n, nm = (int64_t)n * m, mm = (int64_t)m * m, nwn = (int64_t)n * nw;
+        P = b;
+        V = P + nn;
+        Qh = V + nn;
+        F = Qh + nn;
+        AV = F + nn;
+        AB = AV + nn;
+        W = AB + nwn;
+        H = W + nwn;
+        HY = H + nm;
+        BV = HY + nm;
+        X = BV + nm;
+        G = X + nm;
+        Li = G + mm;
+        LiT = Li + mm;
+        Lp = LiT + mm;
+        D = Lp + mm;
+        DT = D + 256;
+        Tm = DT + 256;
+    }
+};
+
+}  // namespace lb
+
+size_t large_unit_bytes(int nx, int nu) {
+    // the master levels factor n x n blocks (m = n), so a unit holds the
+    // larger of the two working sets
+    auto elems = [](int64_t n, int64_t m) {
+        return 5 * n * n + 2 * n * (n + m) + 4 * n * m + 4 * m * m + 512 + 16 * m;
+    };
+    const int64_t e = std::max(elems(nx, nu), elems(nx, nx));
+    return (size_t)(((e * 8) + 255) & ~(int64_t)255);
+}
+
+namespace lb {
+
+// Orders one wavefront's global-memory traffic (stores of some lanes before
+// loads of others).
+__device__ __forceinline__ void wave_gfence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// C = opA(A) opB(B): M x N, inner size K (all multiples of 16).  opA(i,k) =
+// TA ? A[k*lda+i] : A[i*lda+k], opB(k,j) = TB ? B[j*ldb+k] : B[k*ldb+j].
+// Tile (ti, tj) goes to wave (tile index) mod 4 and is handed to epi(ti, tj,
+// acc); with `lower` only the tiles ti >= tj of a square result are formed.
+template <bool TA, bool TB, class T, class Epi>
+__device__ __forceinline__ void gemm(int M, int N, int K, const T *__restrict__ A, int lda, const T *__restrict__ B,
+                                     int ldb, bool lower, Epi epi) {
+    const int tm = M >> 4, tn = N >> 4;
+    const int nt = lower ? tm * (tm + 1) / 2 : tm * tn;
+    const int l = lane(), r16 = l & 15, k4 = l >> 4;
+    for (int t = wave(); t < nt; t += NT / 64) {
+        int ti, tj;
+        if (lower) {
+            mf::lower_tile(t, ti, tj);
+        } else {
+            ti = t / tn;
+            tj = t - ti * tn;
+        }
+        const int i = 16 * ti + r16, j = 16 * tj + r16;
+        v4_t<T> acc = mf::zero4<T>();
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            T a[4], b[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = k0 + 4 * s + k4;
+                a[s] = TA ? A[(int64_t)k * lda + i] : A[(int64_t)i * lda + k];
+                b[s] = TB ? B[(int64_t)j * ldb + k] : B[(int64_t)k * ldb + j];
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc = MT<T>::mfma(a[s], b[s], acc);
+        }
+        epi(ti, tj, acc);
+    }
+}
+
+// Blocked Cholesky factorization G = L L' ("a factorization of G", Alg. 1)
+// and the explicit inverse, for m a multiple of 16.  Right-looking over
+// 16-wide block columns: the diagonal block is factored and inverted by one
+// wavefront (chol_inv_wave), the panel below it is L_ik = G_ik L_kk^{-T},
+// and the trailing lower blocks are updated G_ij -= L_ik L_jk'.  The inverse
+// follows block row by block row: X_ii = L_ii^{-1},
+// X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj.  On return Li = L^{-1} and
+// LiT = L^{-T} (row-major, zeros above / below the diagonal); G is
+// overwritten.  *bad is set if a pivot failed.  Every thread must call it;
+// it ends with a workgroup barrier.
+template <class T>
+__device__ void chol_inv(WS<T> &S, int m, int *bad) {
+    const int nb = m >> 4, tid = threadIdx.x, w = wave(), l = lane();
+    T *G = S.G, *Li = S.Li, *Lp = S.Lp, *D = S.D, *DT = S.DT;
+    for (int kb = 0; kb < nb; ++kb) {
+        if (w == 0) {
+            for (int e = l; e < 256; e += 64) D[e] = G[(int64_t)(16 * kb + e / 16) * m + 16 * kb + e % 16];
+            wave_gfence();
+            const int f = mf::chol_inv_wave<16>(D, DT);      // D <- L_kk^{-1}, DT <- L_kk^{-T}
+            if (f && l == 0) *bad = 1;
+        }
+        __syncthreads();
+        // panel below the diagonal block, then the trailing lower blocks
+        const int np = nb - kb - 1;
+        for (int t = w; t < np; t += NT / 64) {
+            const int ib = kb + 1 + t;
+            v4_t<T> acc = mf::mma<16, false, false>(mf::zero4<T>(), G + (int64_t)16 * ib * m + 16 * kb, m, DT, 16, 0, 0);
+            mf::tile_for<T>(0, 0, [&](int r, int i, int j) { Lp[(int64_t)(16 * ib + i) * m + 16 * kb + j] = acc[r]; });
+        }
+        for (int e = tid; e < 256; e += NT) Li[(int64_t)(16 * kb + e / 16) * m + 16 * kb + e % 16] = D[e];
+        __syncthreads();
+        const int nt = np * (np + 1) / 2;
+        for (int t = w; t < nt; t += NT / 64) {
+            int a, b;
+            mf::lower_tile(t, a, b);
+            const int ib = kb + 1 + a, jb = kb + 1 + b;
+            v4_t<T> acc = mf::mma<16, false, true>(mf::zero4<T>(), Lp + (int64_t)16 * ib * m + 16 * kb, m,
+                                                    Lp + (int64_t)16 * jb * m + 16 * kb, m, 0, 0);
+            mf::tile_for<T>(0, 0, [&](int r, int i, int j) { G[(int64_t)(16 * ib + i) * m + 16 * jb + j] -= acc[r]; });
+        }
+        __syncthreads();
+    }
+    // block rows of the inverse
+    for (int ib = 1; ib < nb; ++ib) {
+        for (int jb = w; jb < ib; jb += NT / 64) {
+            v4_t<T> acc = mf::zero4<T>();
+            for (int kb = jb; kb < ib; ++kb)
+                acc = mf::mma<16, false, false>(acc, Lp + (int64_t)16 * ib * m + 16 * kb, m,
+                                                 Li + (int64_t)16 * kb * m + 16 * jb, m, 0, 0);
+            T *tm = S.Tm + 256 * jb;
+            mf::tile_for<T>(0, 0, [&](int r, int i, int j) { tm[i * 16 + j] = acc[r]; });
+            wave_gfence();
+            acc = mf::mma<16, false, false>(mf::zero4<T>(), Li + (int64_t)16 * ib * m + 16 * ib, m, tm, 16, 0, 0);
+            mf::tile_for<T>(0, 0, [&](int r, int i, int j) { Li[(int64_t)(16 * ib + i) * m + 16 * jb + j] = -acc[r]; });
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < m * m; e += NT) {
+        const int i = e / m, j = e - (e / m) * m;
+        const T v = j <= i ? Li[e] : T(0);
+        Li[e] = v;
+        S.LiT[(int64_t)j * m + i] = v;
+    }
+    __syncthreads();
+}
+
+// Where a pass's per-stage factors go.
+// Leaf records (LeafRec layout, element type T): up or down record of stage s.
+template <class T>
+struct LeafOut {
+    T *base;
+    int n, m;
+    bool up;
+    __device__ T *at(int s) const {
+        const LeafRec R{n, m};
+        return base + (int64_t)s * R.per_stage() + (up ? 0 : R.up());
+    }
+    __device__ void P(int s, int i, int j, T v) const { at(s)[LeafRec{n, m}.P() + i * n + j] = v; }
+    __device__ void K(int s, int i, int j, T v) const { at(s)[LeafRec{n, m}.K() + i * n + j] = v; }
+    __device__ void V(int s, int i, int j, T v) const { at(s)[LeafRec{n, m}.V() + i * n + j] = v; }
+    __device__ void Lt(int s, int i, int j, T v) const { at(s)[LeafRec{n, m}.Lt() + i * n + j] = v; }
+    __device__ void L(int s, const T *Li, const T *LiT) const {
+        T *d = at(s);
+        const LeafRec R{n, m};
+        for (int e = threadIdx.x; e < m * m; e += NT) {
+            d[R.L() + e] = Li[e];
+            d[R.LT() + e] = LiT[e];
+        }
+    }
+};
+
+// Master-slot factors (SlotLayout): up pass uK, uP, uV, uL, uLT; down pass
+// K, dL, dLT.
+struct SlotOut {
+    double *slots;
+    int first, n;
+    bool up;
+    __device__ double *at(int s) const { return slots + (int64_t)(first + s) * SlotLayout{n}.size(); }
+    __device__ void P(int s, int i, int j, double v) const {
+        if (up) at(s)[SlotLayout{n}.uP() + i * n + j] = v;
+    }
+    __device__ void K(int s, int i, int j, double v) const {
+        const SlotLayout L{n};
+        at(s)[(up ? L.uK() : L.K()) + i * n + j] = v;
+    }
+    __device__ void V(int s, int i, int j, double v) const {
+        if (up) at(s)[SlotLayout{n}.uV() + i * n + j] = v;
+    }
+    __device__ void Lt(int, int, int, double) const {}
+    __device__ void L(int s, const double *Li, const double *LiT) const {
+        double *d = at(s);
+        const SlotLayout SL{n};
+        const int oL = up ? SL.uL() : SL.dL(), oT = up ? SL.uLT() : SL.dLT();
+        for (int e = threadIdx.x; e < n * n; e += NT) {
+            d[oL + e] = Li[e];
+            d[oT + e] = LiT[e];
+        }
+    }
+};
+
+// Backward pass over `count` stages (local s = count-1 .. 0), matrix lines
+// only.  RED: Alg. 4 (state P, V, Q_w_hat in the workspace); otherwise Alg. 1
+// from the P in the workspace.  pre(s) runs before stage s and sees P_{s+1}.
+template <class T, bool RED, class Get, class Pre, class Out>
+__device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int stage_base, int fail_code, Pre pre,
+                      const Out &out, int *bad) {
+    const int n = S.n, m = S.m, nw = S.nw, tid = threadIdx.x;
+    count = uni(count);
+    for (int s = count - 1; s >= 0; --s) {
+        pre(s);
+        const StageSrc src = get(s);
+        for (int e = tid; e < n * nw; e += NT) {
+            const int i = e / nw, j = e - (e / nw) * nw;
+            S.AB[e] = (T)(j < n ? src.A[(int64_t)i * n + j] : src.B[(int64_t)i * m + j - n]);
+        }
+        __syncthreads();
+        // W = P [A B]; Alg. 4: B'V, A'V
+        gemm<false, false>(n, nw, n, S.P, n, S.AB, nw, false, [&](int ti, int tj, v4_t<T> acc) {
+            mf::tile_for<T>(ti, tj, [&](int r, int i, int j) { S.W[(int64_t)i * nw + j] = acc[r]; });
+        });
+        if constexpr (RED) {
+            gemm<true, false>(m, n, n, S.AB + n, nw, S.V, n, false, [&](int ti, int tj, v4_t<T> acc) {
+                mf::tile_for<T>(ti, tj, [&](int r, int i, int j) { S.BV[(int64_t)i * n + j] = acc[r]; });
+            });
+            gemm<true, false>(n, n, n, S.AB, nw, S.V, n, false, [&](int ti, int tj, v4_t<T> acc) {
+                mf::tile_for<T>(ti, tj, [&](int r, int i, int j) { S.AV[(int64_t)i * n + j] = acc[r]; });
+            });
+        }
+        __syncthreads();
+        // F = Qx + A'W_A (symmetric), H = Qxw + A'W_B, G = Qw + B'W_B (symmetric)
+        gemm<true, false>(n, n, n, S.AB, nw, S.W, nw, true, [&](int ti, int tj, v4_t<T> acc) {
+            mf::tile_for<T>(ti, tj, [&](int r, int i, int j) {
+                mf::put_sym(S.F, n, ti, tj, i, j, (T)src.Qx[(int64_t)i * n + j] + acc[r]);
+            });
+        });
+        gemm<true, false>(n, m, n, S.AB, nw, S.W + n, nw, false, [&](int ti, int tj, v4_t<T> acc) {
+            mf::tile_for<T>(ti, tj, [&](int r, int i, int j) {
+                S.H[(int64_t)i * m + j] = (src.Qxw ? (T)src.Qxw[(int64_t)i * m + j] : T(0)) + acc[r];
+            });
+        });
+        gemm<true, false>(m, m, n, S.AB + n, nw, S.W + n, nw, true, [&](int ti, int tj, v4_t<T> acc) {
+            mf::tile_for<T>(ti, tj, [&](int r, int i, int j) {
+                mf::put_sym(S.G, m, ti, tj, i, j, (T)src.Qw[(int64_t)i * m + j] + acc[r]);
+            });
+        });
+        __syncthreads();
+        chol_inv(S, m, bad);
+        if (tid == 0 && *bad) {
+            record_failure(info, inst, fail_code, stage_base < 0 ? -1 : stage_base + s);
+            *bad = 0;
+        }
+        out.L(s, S.Li, S.LiT);
+        // Y' = H L^{-T}; Alg. 4: X = L^{-1} B'V
+        gemm<false, false>(n, m, m, S.H, m, S.LiT, m, false, [&](int ti, int tj, v4_t<T> acc) {
+            mf::tile_for<T>(ti, tj, [&](int r, int i, int j) { S.HY[(int64_t)i * m + j] = acc[r]; });
+        });
+        if constexpr (RED) {
+            gemm<false, false>(m, n, m, S.Li, m, S.BV, n, false, [&](int ti, int tj, v4_t<T> acc) {
+                mf::tile_for<T>(ti, tj, [&](int r, int i, int j) { S.X[(int64_t)i * n + j] = acc[r]; });
+            });
+        }
+        __syncthreads();
+        // P = F - Y'Y (symmetric), K = -L^{-T} Y
+        gemm<false, true>(n, n, m, S.HY, m, S.HY, m, true, [&](int ti, int tj, v4_t<T> acc) {
+            mf::tile_for<T>(ti, tj, [&](int r, int i, int j) {
+                if (ti != tj || i >= j) {
+                    const T v = S.F[(int64_t)i * n + j] - acc[r];
+                    S.P[(int64_t)i * n + j] = v;
+                    S.P[(int64_t)j * n + i] = v;
+                    out.P(s, i, j, v);
+                    out.P(s, j, i, v);
+                }
+            });
+        });
+        gemm<false, true>(m, n, m, S.LiT, m, S.HY, m, false, [&](int ti, int tj, v4_t<T> acc) {
+            mf::tile_for<T>(ti, tj, [&](int r, int i, int j) { out.K(s, i, j, -acc[r]); });
+        });
+        if constexpr (RED) {
+            // Q_w_hat += X'X, V = A'V - Y'X, L_t = -L^{-T} X
+            gemm<true, false>(n, n, m, S.X, n, S.X, n, true, [&](int ti, int tj, v4_t<T> acc) {
+                mf::tile_for<T>(ti, tj, [&](int r, int i, int j) {
+                    if (ti != tj || i >= j) {
+                        const T v = S.Qh[(int64_t)i * n + j] + acc[r];
+                        S.Qh[(int64_t)i * n + j] = v;
+                        S.Qh[(int64_t)j * n + i] = v;
+                    }
+                });
+            });
+            gemm<false, false>(n, n, m, S.HY, m, S.X, n, false, [&](int ti, int tj, v4_t<T> acc) {
+                mf::tile_for<T>(ti, tj, [&](int r, int i, int j) {
+                    const T v = S.AV[(int64_t)i * n + j] - acc[r];
+                    S.V[(int64_t)i * n + j] = v;
+                    out.V(s, i, j, v);
+                });
+            });
+            gemm<false, false>(m, n, m, S.LiT, m, S.X, n, false, [&](int ti, int tj, v4_t<T> acc) {
+                mf::tile_for<T>(ti, tj, [&](int r, int i, int j) { out.Lt(s, i, j, -acc[r]); });
+            });
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ StageSrc leaf_stage(const DevProb &p, int t) { return prob_stage(p, t); }
+
+// Start of Alg. 4: P = 0, V = I, Q_w_hat = 0.
+template <class T>
+__device__ void init_red(WS<T> &S) {
+    const int n = S.n;
+    for (int e = threadIdx.x; e < n * n; e += NT) {
+        S.P[e] = T(0);
+        S.V[e] = (e / n == e % n) ? T(1) : T(0);
+        S.Qh[e] = T(0);
+    }
+    __syncthreads();
+}
+
+template <class T>
+__device__ T *unit_ws(const GroupArgs &g) {
+    return reinterpret_cast<T *>(static_cast<char *>(g.lbw) + (int64_t)blockIdx.x * g.lbw_unit);
+}
+
+// ------------------------------------------------------------ matrix side
+template <class T>
+__global__ void __launch_bounds__(NT) kl_leaf_up(GroupArgs g) {
+    __shared__ int bad;
+    const int n = g.nx, m = g.nu, tid = threadIdx.x;
+    WS<T> S;
+    S.bind(unit_ws<T>(g), n, m);
+    if (tid == 0) bad = 0;
+    const SlotLayout SL{n};
+    for (int li = blockIdx.x; li < g.nleaves; li += gridDim.x) {
+        const LeafItem it = sv::load_leaf(g.leaves, li);
+        if ((it.flags & LEAF_TOP) || inst_skipped(g.probs, it.inst)) continue;
+        const DevProb p = load_prob(g.probs, it.inst);
+        double *out = g.slots + (int64_t)it.slot * SL.size();
+        T *base = reinterpret_cast<T *>(g.fstore) + (it.scratch / g.sps) * (int64_t)LeafRec{n, m}.per_stage();
+        auto get = [&](int s) { return leaf_stage(p, it.t0 + s); };
+        const LeafOut<T> o{base, n, m, true};
+        if (!(it.flags & LEAF_LAST)) {
+            init_red(S);
+            mpass<T, true>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, o, &bad);
+            for (int e = tid; e < n * n; e += NT) {
+                const int i = e / n, j = e % n;
+                out[SL.A() + e] = (double)S.V[(int64_t)j * n + i];
+                out[SL.Qw() + e] = (double)S.Qh[e];
+                out[SL.Qx() + e] = (double)S.P[e];
+            }
+        } else {
+            for (int e = tid; e < n * n; e += NT) S.P[e] = (T)p.QxN[e];
+            __syncthreads();
+            mpass<T, false>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, o, &bad);
+            for (int e = tid; e < n * n; e += NT) out[SL.Qx() + e] = (double)S.P[e];
+        }
+        __syncthreads();
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(NT) kl_leaf_down(GroupArgs g) {
+    __shared__ int bad;
+    const int n = g.nx, m = g.nu, tid = threadIdx.x;
+    WS<T> S;
+    S.bind(unit_ws<T>(g), n, m);
+    if (tid == 0) bad = 0;
+    for (int li = blockIdx.x; li < g.nleaves; li += gridDim.x) {
+        const LeafItem it = sv::load_leaf(g.leaves, li);
+        // only whole-problem leaves need the factorization with the true
+        // terminal; the others are solved from their up records
+        if (!(it.flags & LEAF_TOP) || inst_skipped(g.probs, it.inst)) continue;
+        const DevProb p = load_prob(g.probs, it.inst);
+        T *base = reinterpret_cast<T *>(g.fstore) + (it.scratch / g.sps) * (int64_t)LeafRec{n, m}.per_stage();
+        for (int e = tid; e < n * n; e += NT) S.P[e] = (T)p.QxN[e];
+        __syncthreads();
+        auto get = [&](int s) { return leaf_stage(p, it.t0 + s); };
+        mpass<T, false>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, LeafOut<T>{base, n, m, false}, &bad);
+        __syncthreads();
+    }
+}
+
+// Waits (thread 0) until the items this one depends on carry the current
+// epoch; a bounded wait records a failure instead of hanging.
+__device__ void wait_deps(const GroupArgs &g, const TreeItem &it) {
+    if (threadIdx.x == 0) {
+        for (int d = 0; d < it.dep_count; ++d) {
+            int spins = 0;
+            while (__hip_atomic_load(&g.flags[it.dep_first + d], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) !=
+                   g.epoch) {
+                __builtin_amdgcn_s_sleep(4);
+                if (++spins > SPIN_LIMIT) {
+                    record_failure(g.info, it.inst, 6, -2);
+                    break;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__device__ void publish(const GroupArgs &g, int idx) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(&g.flags[idx], g.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(NT) kl_tree(GroupArgs g) {
+    __shared__ int s_item, bad;
+    const int n = g.nx, tid = threadIdx.x;
+    const SlotLayout SL{n};
+    WS<double> S;
+    S.bind(unit_ws<double>(g), n, n);
+    if (tid == 0) bad = 0;
+    double *slots = g.slots;
+    auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(g.queue, 1);
+        __syncthreads();
+        const int idx = uni(s_item);
+        __syncthreads();
+        if (idx >= g.nitems) break;
+        const TreeItem it = load_item(g.items, idx);
+        wait_deps(g, it);
+        auto get = [&](int s) { return slot_stage(slot(it.first + s), n); };
+        if (inst_skipped(g.probs, it.inst)) {
+            // excluded instance: only its completion flag is published
+        } else if (it.kind == ITEM_UP) {
+            init_red(S);
+            mpass<double, true>(S, get, it.count, g.info, it.inst, -1, 3, [](int) {}, SlotOut{slots, it.first, n, true},
+                                &bad);
+            double *out = slot(it.out_slot);
+            for (int e = tid; e < n * n; e += NT) {
+                const int i = e / n, j = e % n;
+                out[SL.A() + e] = S.V[(int64_t)j * n + i];
+                out[SL.Qw() + e] = S.Qh[e];
+                out[SL.Qx() + e] = S.P[e];
+            }
+        } else if (it.kind == ITEM_UP_LAST) {
+            const double *term = slot(it.term_slot);
+            for (int e = tid; e < n * n; e += NT) S.P[e] = term[SL.Qx() + e];
+            __syncthreads();
+            mpass<double, false>(S, get, it.count, g.info, it.inst, -1, 3, [](int) {},
+                                 SlotOut{slots, it.first, n, true}, &bad);
+            double *out = slot(it.out_slot);
+            for (int e = tid; e < n * n; e += NT) out[SL.Qx() + e] = S.P[e];
+        } else {
+            const bool top = it.kind == ITEM_TOP;
+            const double *msg = top ? nullptr : slot(it.out_slot);
+            const double *term = it.last ? slot(it.term_slot) : nullptr;
+            for (int e = tid; e < n * n; e += NT) S.P[e] = term ? term[SL.Qx() + e] : msg[SL.P() + e];
+            __syncthreads();
+            mpass<double, false>(
+                S, get, it.count, g.info, it.inst, -1, 3,
+                [&](int s) {      // M2 for child s: P at the end of master stage s
+                    double *d = slot(it.first + s) + SL.P();
+                    for (int e = tid; e < n * n; e += NT) d[e] = S.P[e];
+                },
+                SlotOut{slots, it.first, n, false}, &bad);
+            if (top) {
+                double *d = slot(it.term_slot) + SL.P();      // P_0, for the optimal value
+                for (int e = tid; e < n * n; e += NT) d[e] = S.P[e];
+            }
+        }
+        publish(g, idx);
+    }
+}
+
+// ------------------------------------------------------------ vector side
+constexpr int VMAX = 128;
+
+struct VS {
+    double Psi[VMAX], pt[VMAX], av[VMAX], d[VMAX], x[VMAX], gw[VMAX], z[VMAX], kk[VMAX], wv[VMAX], v[VMAX],
+        lamN[VMAX], y[VMAX];
+    double red[NT / 64];
+};
+
+__device__ __forceinline__ double block_sum(double v, VS &S) {
+    v = sv::wave_sum(v);
+    __syncthreads();
+    if (lane() == 0) S.red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += S.red[w];
+    return s;
+}
+
+// y(i) = sum_k op(M)(i,k) x[k] for i < R, k < C, handed to out(i, y) by one
+// thread per i.  COLUMN-read form op(M)(i,k) = M[k*ld+i]: one thread per
+// output, consecutive threads on consecutive words.  ROW-read form
+// op(M)(i,k) = M[i*ld+k]: one wavefront per output row, lanes over k.
+template <bool ROW, class U, class Out>
+__device__ __forceinline__ void gemv(const U *M, int ld, const double *x, int R, int C, Out out) {
+    if constexpr (!ROW) {
+        for (int i = threadIdx.x; i < R; i += NT) {
+            double acc = 0.0;
+            if (M)
+                for (int k = 0; k < C; ++k) acc += (double)M[(int64_t)k * ld + i] * x[k];
+            out(i, acc);
+        }
+    } else {
+        const int l = lane();
+        for (int i = wave(); i < R; i += NT / 64) {
+            double acc = 0.0;
+            if (M)
+                for (int k = l; k < C; k += 64) acc += (double)M[(int64_t)i * ld + k] * x[k];
+            acc = sv::wave_sum(acc);
+            if (l == 0) out(i, acc);
+        }
+    }
+}
+
+// Operands of one backward stage of the vector recursion (as in the
+// register-resident kernels): P_{t+1} (TR-typed record, FP64 terminal or
+// message, or zero), V_{t+1} (record or identity), L^{-1}, L^{-T}, K.
+template <class TR>
+struct VSrcL {
+    const TR *Pn;
+    const double *Pn64;
+    const TR *Vn;
+    const TR *Li, *LT, *K;
+    const double *A, *B, *a, *lx, *lw;
+    double c;
+};
+
+// One backward stage: P a, pt = Psi - P a, cbar += 1/2 a'Pa - Psi'a + c,
+// g_w = B' pt - l_w, z = L^{-1} g_w, Psi_t = A' pt + K' g_w - l_x,
+// cbar -= z'z / 2, k = L^{-T} z; Alg. 4: v += V_{t+1}' (a + B k).
+// cbar lives in thread 0.  Psi_t and k are left in S.Psi and S.kk.
+template <bool RED, bool WANTK, class TR>
+__device__ void vstage(VS &S, const VSrcL<TR> &q, int n, int m, double &cbar) {
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n; i += NT) S.av[i] = q.a ? q.a[i] : 0.0;
+    __syncthreads();
+    double part = 0.0;
+    if (q.Pn)
+        gemv<false>(q.Pn, n, S.av, n, n, [&](int i, double pa) {
+            S.pt[i] = S.Psi[i] - pa;
+            part += S.av[i] * (0.5 * pa - S.Psi[i]);
+        });
+    else
+        gemv<false>(q.Pn64, n, S.av, n, n, [&](int i, double pa) {
+            S.pt[i] = S.Psi[i] - pa;
+            part += S.av[i] * (0.5 * pa - S.Psi[i]);
+        });
+    const double s1 = block_sum(part, S);
+    if (tid == 0) cbar += s1 + q.c;
+    gemv<false>(q.B, m, S.pt, m, n, [&](int j, double v) { S.gw[j] = v - (q.lw ? q.lw[j] : 0.0); });
+    __syncthreads();
+    double zz = 0.0;
+    gemv<false>(q.LT, m, S.gw, m, m, [&](int i, double v) {
+        S.z[i] = v;
+        zz += v * v;
+    });
+    gemv<false>(q.A, n, S.pt, n, n, [&](int i, double v) { S.y[i] = v - (q.lx ? q.lx[i] : 0.0); });
+    __syncthreads();
+    gemv<false>(q.K, n, S.gw, n, m, [&](int i, double v) { S.Psi[i] = S.y[i] + v; });
+    const double s2 = block_sum(zz, S);
+    if (tid == 0) cbar -= 0.5 * s2;
+    if constexpr (RED || WANTK) {
+        gemv<false>(q.Li, m, S.z, m, m, [&](int i, double v) { S.kk[i] = v; });
+        __syncthreads();
+    }
+    if constexpr (RED) {
+        gemv<true>(q.B, m, S.kk, n, m, [&](int i, double v) { S.d[i] = S.av[i] + v; });
+        __syncthreads();
+        if (q.Vn)
+            gemv<false>(q.Vn, n, S.d, n, n, [&](int i, double v) { S.v[i] += v; });
+        else
+            for (int i = tid; i < n; i += NT) S.v[i] += S.d[i];
+        __syncthreads();
+    }
+}
+
+// One forward stage (Alg. 3): w = K x + k (+ L lam_N), x_{t+1} = A x + a + B w
+// and lam_t = P_t x - Psi_t (+ V_t lam_N); x, w, lam of stage t written to
+// the outputs when given.
+template <class TR>
+__device__ void fstage(VS &S, int n, int m, const TR *K, const double *kvec, const TR *Lt, const double *A,
+                       const double *B, const double *a, const TR *P, const double *Psi, const TR *Vt, double *x_out,
+                       double *w_out, double *lam_out) {
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n; i += NT)
+        if (x_out) x_out[i] = S.x[i];
+    gemv<true>(K, n, S.x, m, n, [&](int i, double v) { S.wv[i] = v + kvec[i]; });
+    gemv<true>(A, n, S.x, n, n, [&](int i, double v) { S.y[i] = v + (a ? a[i] : 0.0); });
+    if (P) gemv<false>(P, n, S.x, n, n, [&](int i, double v) { S.d[i] = v - Psi[i]; });
+    __syncthreads();
+    if (Lt) {
+        gemv<true>(Lt, n, S.lamN, m, n, [&](int i, double v) { S.wv[i] += v; });
+        gemv<true>(Vt, n, S.lamN, n, n, [&](int i, double v) { S.d[i] += v; });
+        __syncthreads();
+    }
+    for (int i = tid; i < m; i += NT)
+        if (w_out) w_out[i] = S.wv[i];
+    for (int i = tid; i < n; i += NT)
+        if (lam_out) lam_out[i] = S.d[i];
+    gemv<true>(B, m, S.wv, n, m, [&](int i, double v) { S.y[i] += v; });
+    __syncthreads();
+    for (int i = tid; i < n; i += NT) S.x[i] = S.y[i];
+    __syncthreads();
+}
+
+// 1/2 x'Px - Psi'x + cbar at the x in S.x (result in thread 0).
+template <class TP>
+__device__ double cost_to_go(VS &S, const TP *P, int n, double cbar) {
+    double part = 0.0;
+    gemv<false>(P, n, S.x, n, n, [&](int i, double v) { part += S.x[i] * (0.5 * v - S.Psi[i]); });
+    const double s = block_sum(part, S);
+    return s + cbar;
+}
+
+template <class TR>
+__device__ VSrcL<TR> prob_src(const sv::Prob &p, int t) {
+    VSrcL<TR> q;
+    q.Pn = nullptr;
+    q.Pn64 = nullptr;
+    q.Vn = nullptr;
+    q.A = p.A + (int64_t)t * p.sA;
+    q.B = p.B + (int64_t)t * p.sB;
+    q.a = p.a ? p.a + (int64_t)t * p.sa : nullptr;
+    q.lx = p.lx ? p.lx + (int64_t)t * p.slx : nullptr;
+    q.lw = p.lw ? p.lw + (int64_t)t * p.slw : nullptr;
+    q.c = p.c ? p.c[(int64_t)t * p.sc] : 0.0;
+    return q;
+}
+
+__device__ VSrcL<double> slot_src(const double *sl, int n) {
+    const SlotLayout L{n};
+    VSrcL<double> q;
+    q.Pn = nullptr;
+    q.Pn64 = nullptr;
+    q.Vn = nullptr;
+    q.A = sl + L.A();
+    q.B = sl + L.Qw();
+    q.a = sl + L.a();
+    q.lx = sl + L.lx();
+    q.lw = nullptr;
+    q.c = sl[L.c()];
+    return q;
+}
+
+template <class TR>
+__global__ void __launch_bounds__(NT) kw_leaf_up(GroupArgs g) {
+    __shared__ VS S;
+    if (sv::pass_idle(g)) return;
+    const int n = g.nx, m = g.nu, tid = threadIdx.x;
+    const LeafItem it = sv::load_leaf(g.leaves, blockIdx.x);
+    if ((it.flags & LEAF_TOP) || sv::skip_inst(g, it.inst)) return;
+    const sv::Prob p = sv::load_prob(g.probs, it.inst);
+    const LeafRec R{n, m};
+    const SlotLayout SL{n};
+    const TR *rec = reinterpret_cast<const TR *>(g.fstore) + (it.scratch / g.sps) * (int64_t)R.per_stage();
+    double *out = g.slots + (int64_t)it.slot * SL.size();
+    const bool last = (it.flags & LEAF_LAST) != 0;
+    for (int i = tid; i < n; i += NT) {
+        S.Psi[i] = (last && p.lN) ? -p.lN[i] : 0.0;
+        S.v[i] = 0.0;
+    }
+    double cbar = (last && p.cN) ? p.cN[0] : 0.0;
+    double *vec0 = g.fvec + (it.scratch / g.sps) * (int64_t)R.vec();
+    __syncthreads();
+    for (int s = uni(it.len) - 1; s >= 0; --s) {
+        VSrcL<TR> q = prob_src<TR>(p, it.t0 + s);
+        const TR *r = rec + (int64_t)s * R.per_stage();
+        const TR *rn = r + R.per_stage();
+        const bool end = s + 1 == it.len;
+        q.Li = r + R.L();
+        q.LT = r + R.LT();
+        q.K = r + R.K();
+        q.Pn = end ? nullptr : rn + R.P();
+        if (!last) {
+            q.Vn = end ? nullptr : rn + R.V();
+            vstage<true, false>(S, q, n, m, cbar);
+        } else {
+            q.Pn64 = end ? p.QxN : nullptr;
+            vstage<false, true>(S, q, n, m, cbar);
+        }
+        // Psi_t and k_{t+1} of this sweep, for the leaf solve
+        double *vec = vec0 + (int64_t)s * R.vec();
+        for (int i = tid; i < n; i += NT) vec[i] = S.Psi[i];
+        for (int i = tid; i < m; i += NT) vec[n + i] = S.kk[i];
+        __syncthreads();
+    }
+    for (int i = tid; i < n; i += NT) {
+        if (!last) out[SL.a() + i] = S.v[i];
+        out[SL.lx() + i] = -S.Psi[i];
+    }
+    if (tid == 0) out[SL.c()] = cbar;
+}
+
+// Leaf solve from the stored preliminary solution (superposition in the
+// terminal costate lam_N = P_hat x_hat_{i+1} - Psi_hat, since Psi and k are
+// affine in the terminal linear term):
+//   w_t = K x_t + k_0 + L lam_N,  lam_t = P_t x_t - Psi_0,t + V_t lam_N.
+// The last leaf was reduced with the true terminal (no lam_N terms).
+template <class TR>
+__device__ void leaf_forward(VS &S, const GroupArgs &g, const sv::Prob &p, const LeafItem &it) {
+    const int n = g.nx, m = g.nu, tid = threadIdx.x;
+    const LeafRec R{n, m};
+    const SlotLayout SL{n};
+    const int64_t stage0 = it.scratch / g.sps;
+    const TR *rec = reinterpret_cast<const TR *>(g.fstore) + stage0 * (int64_t)R.per_stage();
+    const double *vec0 = g.fvec + stage0 * (int64_t)R.vec();
+    const double *msg = g.slots + (int64_t)it.slot * SL.size();
+    const bool last = (it.flags & LEAF_LAST) != 0;
+    if (!last) {
+        const double *nxt = msg + SL.size();           // the next leaf's slot: x_hat_{i+1}
+        for (int i = tid; i < n; i += NT) S.x[i] = nxt[SL.xh() + i];
+        __syncthreads();
+        gemv<false>(msg + SL.P(), n, S.x, n, n, [&](int i, double v) { S.lamN[i] = v - msg[SL.Psi() + i]; });
+        __syncthreads();
+    }
+    for (int i = tid; i < n; i += NT) S.x[i] = msg[SL.xh() + i];
+    __syncthreads();
+    const int len = uni(it.len);
+    for (int s = 0; s < len; ++s) {
+        const int t = it.t0 + s;
+        const TR *r = rec + (int64_t)s * R.per_stage();
+        const double *vec = vec0 + (int64_t)s * R.vec();
+        fstage<TR>(S, n, m, r + R.K(), vec + n, last ? nullptr : r + R.Lt(), p.A + (int64_t)t * p.sA,
+                   p.B + (int64_t)t * p.sB, p.a ? p.a + (int64_t)t * p.sa : nullptr, r + R.P(), vec,
+                   last ? nullptr : r + R.V(), p.x + (int64_t)t * n, p.w + (int64_t)t * m, p.lam + (int64_t)t * n);
+    }
+    if (last) {
+        const int64_t t = it.t0 + len;
+        gemv<false>(p.QxN, n, S.x, n, n, [&](int i, double v) {
+            p.lam[t * n + i] = v + (p.lN ? p.lN[i] : 0.0);     // lam_N = QxN x_N + lN
+            p.x[t * n + i] = S.x[i];
+        });
+    }
+}
+
+template <class TR>
+__global__ void __launch_bounds__(NT) kw_leaf_down(GroupArgs g) {
+    __shared__ VS S;
+    if (sv::pass_idle(g)) return;
+    const int n = g.nx, m = g.nu, tid = threadIdx.x;
+    const LeafItem it = sv::load_leaf(g.leaves, blockIdx.x);
+    if (sv::skip_inst(g, it.inst)) return;
+    const sv::Prob p = sv::load_prob(g.probs, it.inst);
+    if (!(it.flags & LEAF_TOP)) {
+        leaf_forward<TR>(S, g, p, it);
+        return;
+    }
+    // whole-problem leaf: vector part of Alg. 1-2 with the true terminal on
+    // the down records, then Alg. 3
+    const LeafRec R{n, m};
+    const int64_t stage0 = it.scratch / g.sps;
+    const TR *rec = reinterpret_cast<const TR *>(g.fstore) + stage0 * (int64_t)R.per_stage();
+    double *vec0 = g.fvec + stage0 * (int64_t)R.vec();
+    for (int i = tid; i < n; i += NT) {
+        S.Psi[i] = p.lN ? -p.lN[i] : 0.0;
+        S.x[i] = p.x0[i];
+    }
+    double cbar = p.cN ? p.cN[0] : 0.0;
+    __syncthreads();
+    const int len = uni(it.len);
+    for (int s = len - 1; s >= 0; --s) {
+        VSrcL<TR> q = prob_src<TR>(p, it.t0 + s);
+        const TR *dn = rec + (int64_t)s * R.per_stage() + R.up();
+        const bool end = s + 1 == len;
+        q.Pn = end ? nullptr : dn + R.per_stage() + R.P();
+        q.Pn64 = end ? p.QxN : nullptr;
+        q.Li = dn + R.L();
+        q.LT = dn + R.LT();
+        q.K = dn + R.K();
+        vstage<false, true>(S, q, n, m, cbar);
+        double *vec = vec0 + (int64_t)s * R.vec();
+        for (int i = tid; i < n; i += NT) vec[i] = S.Psi[i];
+        for (int i = tid; i < m; i += NT) vec[n + i] = S.kk[i];
+        __syncthreads();
+    }
+    if (p.obj) {
+        const double v = cost_to_go(S, rec + R.up() + R.P(), n, cbar);
+        if (tid == 0) p.obj[0] = v;
+    }
+    __syncthreads();
+    for (int s = 0; s < len; ++s) {
+        const int t = it.t0 + s;
+        const TR *dn = rec + (int64_t)s * R.per_stage() + R.up();
+        const double *vec = vec0 + (int64_t)s * R.vec();
+        fstage<TR>(S, n, m, dn + R.K(), vec + n, nullptr, p.A + (int64_t)t * p.sA, p.B + (int64_t)t * p.sB,
+                   p.a ? p.a + (int64_t)t * p.sa : nullptr, dn + R.P(), vec, nullptr, p.x + (int64_t)t * n,
+                   p.w + (int64_t)t * m, p.lam + (int64_t)t * n);
+    }
+    const int64_t t = it.t0 + len;
+    gemv<false>(p.QxN, n, S.x, n, n, [&](int i, double v) {
+        p.lam[t * n + i] = v + (p.lN ? p.lN[i] : 0.0);         // lam_N = QxN x_N + lN
+        p.x[t * n + i] = S.x[i];
+    });
+}
+
+__global__ void __launch_bounds__(NT) kw_tree(GroupArgs g) {
+    __shared__ VS S;
+    __shared__ int s_item;
+    const int n = g.nx, tid = threadIdx.x;
+    const SlotLayout SL{n};
+    double *slots = g.slots;
+    auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
+    if (sv::pass_idle(g)) return;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(g.queue, 1);
+        __syncthreads();
+        const int idx = uni(s_item);
+        __syncthreads();
+        if (idx >= g.nitems) break;
+        const TreeItem it = load_item(g.items, idx);
+        wait_deps(g, it);
+        const int count = it.count;
+        if (sv::skip_inst(g, it.inst)) {
+            // converged or excluded: nothing to do (its dependents belong to the same instance)
+        } else if (it.kind == ITEM_UP || it.kind == ITEM_UP_LAST) {
+            const bool red = it.kind == ITEM_UP;
+            const double *term = red ? nullptr : slot(it.term_slot);
+            for (int i = tid; i < n; i += NT) {
+                S.Psi[i] = red ? 0.0 : -term[SL.lx() + i];
+                S.v[i] = 0.0;
+            }
+            double cbar = red ? 0.0 : term[SL.c()];
+            __syncthreads();
+            for (int s = count - 1; s >= 0; --s) {
+                const double *sl = slot(it.first + s);
+                VSrcL<double> q = slot_src(sl, n);
+                const double *sn = slot(it.first + s + 1);
+                const bool end = s + 1 == count;
+                q.Li = sl + SL.uL();
+                q.LT = sl + SL.uLT();
+                q.K = sl + SL.uK();
+                if (red) {
+                    q.Pn = end ? nullptr : sn + SL.uP();
+                    q.Vn = end ? nullptr : sn + SL.uV();
+                    vstage<true, false>(S, q, n, n, cbar);
+                } else {
+                    q.Pn = end ? term + SL.Qx() : sn + SL.uP();
+                    vstage<false, false>(S, q, n, n, cbar);
+                }
+                __syncthreads();
+            }
+            double *out = slot(it.out_slot);
+            for (int i = tid; i < n; i += NT) {
+                if (red) out[SL.a() + i] = S.v[i];
+                out[SL.lx() + i] = -S.Psi[i];
+            }
+            if (tid == 0) out[SL.c()] = cbar;
+        } else {
+            const bool top = it.kind == ITEM_TOP;
+            const sv::Prob p = sv::load_prob(g.probs, it.inst);
+            const double *msg = top ? nullptr : slot(it.out_slot);
+            const double *term = it.last ? slot(it.term_slot) : nullptr;
+            for (int i = tid; i < n; i += NT) {
+                S.Psi[i] = term ? -term[SL.lx() + i] : msg[SL.Psi() + i];
+                S.x[i] = top ? p.x0[i] : msg[SL.xh() + i];
+            }
+            double cbar = term ? term[SL.c()] : msg[SL.cb()];
+            __syncthreads();
+            for (int s = count - 1; s >= 0; --s) {
+                double *sl = slot(it.first + s);
+                // message to child s: cost to go at the end of master stage s
+                for (int i = tid; i < n; i += NT) sl[SL.Psi() + i] = S.Psi[i];
+                if (tid == 0) sl[SL.cb()] = cbar;
+                VSrcL<double> q = slot_src(sl, n);
+                q.Pn = sl + SL.P();
+                q.Li = sl + SL.dL();
+                q.LT = sl + SL.dLT();
+                q.K = sl + SL.K();
+                vstage<false, true>(S, q, n, n, cbar);
+                for (int i = tid; i < n; i += NT) sl[SL.k() + i] = S.kk[i];
+                __syncthreads();
+            }
+            if (top && p.obj) {
+                const double v = cost_to_go(S, slot(it.term_slot) + SL.P(), n, cbar);
+                if (tid == 0) p.obj[0] = v;
+            }
+            __syncthreads();
+            for (int s = 0; s < count; ++s) {
+                double *sl = slot(it.first + s);
+                fstage<double>(S, n, n, sl + SL.K(), sl + SL.k(), nullptr, sl + SL.A(), sl + SL.Qw(), sl + SL.a(),
+                               nullptr, nullptr, nullptr, sl + SL.xh(), nullptr, nullptr);
+            }
+            if (it.last)
+                for (int i = tid; i < n; i += NT) slot(it.term_slot)[SL.xh() + i] = S.x[i];
+        }
+        publish(g, idx);
+    }
+}
+
+// -------------------------------------------------------- refinement (FP64)
+// Residual rho = r - K z of the KKT system of P(N) (blockwise, FP64) for the
+// stages of one leaf, one stage at a time over the whole workgroup; writes
+// the correction problem's data (-rho as problem data, see the register
+// kernels) and the leaf's max |r|, max |rho| and objective part.
+__global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
+    __shared__ VS S;
+    const int n = g.nx, m = g.nu, tid = threadIdx.x;
+    const LeafItem it = sv::load_leaf(g.leaves, blockIdx.x);
+    if (sv::skip_inst(g, it.inst)) return;
+    const sv::Prob p = sv::load_prob(g.probs, it.inst);
+    const sv::Prob c = sv::load_prob(g.corr, it.inst);
+    double rhs = 0.0, res = 0.0, obj = 0.0;
+    const int len = uni(it.len);
+    double *xs = S.x, *ws = S.wv, *ls = S.lamN;
+    for (int s = 0; s < len; ++s) {
+        const int64_t t = it.t0 + s;
+        const double *x = p.x + t * n, *xn = x + n, *w = p.w + t * m;
+        const double *lam = p.lam + t * n, *lamn = lam + n;
+        const double *Qx = p.Qx + t * p.sQx, *Qw = p.Qw + t * p.sQw;
+        const double *Qxw = p.Qxw ? p.Qxw + t * p.sQxw : nullptr;
+        const double *A = p.A + t * p.sA, *B = p.B + t * p.sB;
+        for (int i = tid; i < n; i += NT) {
+            xs[i] = x[i];
+            ls[i] = lamn[i];
+        }
+        for (int i = tid; i < m; i += NT) ws[i] = w[i];
+        __syncthreads();
+        // x row: Qx x + Qxw w - lam + A' lam+ ; lam+ row: A x + B w - x+
+        gemv<true>(Qx, n, xs, n, n, [&](int i, double v) { S.pt[i] = v; });
+        gemv<true>(Qxw, m, ws, n, m, [&](int i, double v) { S.d[i] = v; });
+        gemv<false>(A, n, ls, n, n, [&](int i, double v) { S.av[i] = v; });
+        gemv<true>(A, n, xs, n, n, [&](int i, double v) { S.y[i] = v; });
+        gemv<true>(B, m, ws, n, m, [&](int i, double v) { S.Psi[i] = v; });
+        // w row: Qxw' x + Qw w + B' lam+
+        gemv<false>(Qxw, m, xs, m, n, [&](int j, double v) { S.gw[j] = v; });
+        gemv<true>(Qw, m, ws, m, m, [&](int j, double v) { S.z[j] = v; });
+        gemv<false>(B, m, ls, m, n, [&](int j, double v) { S.kk[j] = v; });
+        __syncthreads();
+        double part = 0.0;
+        for (int i = tid; i < n; i += NT) {
+            const double lxi = p.lx ? p.lx[t * p.slx + i] : 0.0, ai = p.a ? p.a[t * p.sa + i] : 0.0;
+            const double dlx = lxi + S.pt[i] + S.d[i] - lam[i] + S.av[i];
+            const double da = ai + S.y[i] + S.Psi[i] - xn[i];
+            const_cast<double *>(c.lx)[t * c.slx + i] = dlx;
+            const_cast<double *>(c.a)[t * c.sa + i] = da;
+            rhs = fmax(rhs, fmax(fabs(lxi), fabs(ai)));
+            res = fmax(res, fmax(fabs(dlx), fabs(da)));
+            part += xs[i] * (0.5 * S.pt[i] + S.d[i] + lxi);
+        }
+        for (int j = tid; j < m; j += NT) {
+            const double lwj = p.lw ? p.lw[t * p.slw + j] : 0.0;
+            const double dlw = lwj + S.gw[j] + S.z[j] + S.kk[j];
+            const_cast<double *>(c.lw)[t * c.slw + j] = dlw;
+            rhs = fmax(rhs, fabs(lwj));
+            res = fmax(res, fabs(dlw));
+            part += ws[j] * (0.5 * S.z[j] + lwj);
+        }
+        const double tot = block_sum(part, S);
+        if (tid == 0) obj += tot + (p.c ? p.c[t * p.sc] : 0.0);
+    }
+    if (it.t0 == 0) {            // lam_0 row
+        for (int i = tid; i < n; i += NT) {
+            const double d0 = p.x[i] - p.x0[i];
+            const_cast<double *>(c.x0)[i] = d0;
+            rhs = fmax(rhs, fabs(p.x0[i]));
+            res = fmax(res, fabs(d0));
+        }
+    }
+    if (it.flags & LEAF_LAST) {  // x_N row and the terminal cost
+        const int64_t N = it.t0 + len;
+        const double *x = p.x + N * n, *lam = p.lam + N * n;
+        for (int i = tid; i < n; i += NT) xs[i] = x[i];
+        __syncthreads();
+        double part = 0.0;
+        gemv<true>(p.QxN, n, xs, n, n, [&](int i, double qx) {
+            const double lNi = p.lN ? p.lN[i] : 0.0;
+            const double dN = lNi + qx - lam[i];
+            const_cast<double *>(c.lN)[i] = dN;
+            rhs = fmax(rhs, fabs(lNi));
+            res = fmax(res, fabs(dN));
+            part += x[i] * (0.5 * qx + lNi);
+        });
+        const double tot = block_sum(part, S);
+        if (tid == 0) obj += tot + (p.cN ? p.cN[0] : 0.0);
+    }
+    rhs = sv::wave_max(rhs);
+    res = sv::wave_max(res);
+    __syncthreads();
+    if (lane() == 0) {
+        S.av[wave()] = rhs;
+        S.pt[wave()] = res;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double *out = g.part + (int64_t)(g.leaf_base + blockIdx.x) * PART_N;
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < NT / 64; ++q) {
+            a = fmax(a, S.av[q]);
+            b = fmax(b, S.pt[q]);
+        }
+        out[PART_RHS] = a;
+        out[PART_RES] = b;
+        out[PART_OBJ] = obj;
+    }
+}
+
+// z += d over the leaf's stages (and x_N, lam_N for the last leaf); max |d|
+// and max |z| per block (x, w, lam).
+__global__ void __launch_bounds__(NT) kw_update(GroupArgs g) {
+    __shared__ double red[NT / 64][6];
+    const int n = g.nx, m = g.nu, tid = threadIdx.x;
+    const LeafItem it = sv::load_leaf(g.leaves, blockIdx.x);
+    if (sv::skip_inst(g, it.inst)) return;
+    const sv::Prob p = sv::load_prob(g.probs, it.inst);
+    const sv::Prob c = sv::load_prob(g.corr, it.inst);
+    const int nst = uni(it.len) + ((it.flags & LEAF_LAST) ? 1 : 0);
+    double mx[6] = {0, 0, 0, 0, 0, 0};
+    {
+        const int64_t b0 = (int64_t)it.t0 * n, cnt = (int64_t)nst * n;
+        for (int64_t e = tid; e < cnt; e += NT) {
+            const double dx = c.x[b0 + e], dl = c.lam[b0 + e];
+            const double xv = p.x[b0 + e] + dx, lv = p.lam[b0 + e] + dl;
+            p.x[b0 + e] = xv;
+            p.lam[b0 + e] = lv;
+            mx[0] = fmax(mx[0], fabs(dx));
+            mx[2] = fmax(mx[2], fabs(dl));
+            mx[3] = fmax(mx[3], fabs(xv));
+            mx[5] = fmax(mx[5], fabs(lv));
+        }
+    }
+    {
+        const int64_t b0 = (int64_t)it.t0 * m, cnt = (int64_t)it.len * m;
+        for (int64_t e = tid; e < cnt; e += NT) {
+            const double dw = c.w[b0 + e];
+            const double wv = p.w[b0 + e] + dw;
+            p.w[b0 + e] = wv;
+            mx[1] = fmax(mx[1], fabs(dw));
+            mx[4] = fmax(mx[4], fabs(wv));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) mx[q] = sv::wave_max(mx[q]);
+    if (lane() == 0)
+        for (int q = 0; q < 6; ++q) red[wave()][q] = mx[q];
+    __syncthreads();
+    if (tid == 0) {
+        double *out = g.part + (int64_t)(g.leaf_base + blockIdx.x) * PART_N;
+        for (int q = 0; q < 6; ++q) {
+            double v = 0.0;
+            for (int w = 0; w < NT / 64; ++w) v = fmax(v, red[w][q]);
+            out[PART_DX + q] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------- launchers
+int leaf_units(const GroupArgs &g) { return std::max(1, std::min<int>(g.nleaves, LB_LEAF_UNITS)); }
+
+template <class T>
+hipError_t launch_leaf_up(const GroupArgs &g, int, hipStream_t st) {
+    hipLaunchKernelGGL((kl_leaf_up<T>), dim3(leaf_units(g)), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+hipError_t launch_tree(const GroupArgs &g, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(kl_tree, dim3(std::min(grid, LB_TREE_UNITS)), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t launch_leaf_down(const GroupArgs &g, int, hipStream_t st) {
+    if (g.ntop == 0) return hipSuccess;
+    hipLaunchKernelGGL((kl_leaf_down<T>), dim3(leaf_units(g)), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+template <class TR>
+hipError_t launch_vup(const GroupArgs &g, int, hipStream_t st) {
+    hipLaunchKernelGGL((kw_leaf_up<TR>), dim3(g.nleaves), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+hipError_t launch_vtree(const GroupArgs &g, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(kw_tree, dim3(grid), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+template <class TR>
+hipError_t launch_vdown(const GroupArgs &g, int, hipStream_t st) {
+    hipLaunchKernelGGL((kw_leaf_down<TR>), dim3(g.nleaves), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+hipError_t launch_residual(const GroupArgs &g, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(kw_residual, dim3(grid), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+hipError_t launch_update(const GroupArgs &g, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(kw_update, dim3(grid), dim3(NT), 0, st, g);
+    return hipGetLastError();
+}
+
+}  // namespace lb
+
+bool large_shape(int nx, int nu) {
+    return nx >= 16 && nu >= 16 && nx <= lb::VMAX && nu <= lb::VMAX && nx % 16 == 0 && nu % 16 == 0;
+}
+
+Launcher large_factor(int which, bool fp32) {
+    if (which == 0) return fp32 ? &lb::launch_leaf_up<float> : &lb::launch_leaf_up<double>;
+    if (which == 1) return &lb::launch_tree;
+    return fp32 ? &lb::launch_leaf_down<float> : &lb::launch_leaf_down<double>;
+}
+
+Launcher large_vector(int which, bool fp32) {
+    if (which == 0) return fp32 ? &lb::launch_vup<float> : &lb::launch_vup<double>;
+    if (which == 1) return &lb::launch_vtree;
+    return fp32 ? &lb::launch_vdown<float> : &lb::launch_vdown<double>;
+}
+
+Launcher large_refine(int which) { return which == 0 ? &lb::launch_residual : &lb::launch_update; }
+
+}  // namespace rs

@@ -27,6 +27,7 @@ enum KernelKind {
 
 struct ShapeEntry {
     int nx, nu;
+    bool large;              // large-block family: no fused kernels, matrices in a global workspace
     Launcher fp64[3];        // fused: leaf up, tree, leaf down
     Launcher factor[2][3];   // stored factorization [fp32 leaves][pass] (nullptr: not available)
     Launcher vsolve[2][3];   // right-hand-side passes on the stored factorization
@@ -43,6 +44,15 @@ Launcher leaf_forward(int nx, int nu);                   // leaf solve on the st
 hipError_t launch_refine_check(const InstInfo *tab, int count, const double *part, double *stats, int32_t *conv,
                                int32_t *info, const DevProb *probs, int mode, double tol, int32_t *active,
                                int nactive, hipStream_t st);
+
+// Large-block family (n_x, n_u multiples of 16 up to 128): stored
+// factorization only, with a per-workgroup workspace of large_unit_bytes.
+constexpr int LB_LEAF_UNITS = 2048, LB_TREE_UNITS = 256;
+bool large_shape(int nx, int nu);
+size_t large_unit_bytes(int nx, int nu);
+Launcher large_factor(int which, bool fp32);
+Launcher large_vector(int which, bool fp32);
+Launcher large_refine(int which);
 
 const ShapeEntry *find_shape(int nx, int nu);
 hipError_t launch_init(int32_t *info, int count, int32_t *queues, int nq, hipStream_t st);

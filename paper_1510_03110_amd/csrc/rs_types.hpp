@@ -140,6 +140,11 @@ struct GroupArgs {
     int32_t leaf_base;      // global index of this group's first leaf
     int32_t ntop;           // leaves that are a whole instance (LEAF_TOP)
     const int32_t *active;  // refinement: instances still iterating (0: the pass has nothing to do)
+    // large-block kernels: per-workgroup matrix workspace (lbw_unit bytes per
+    // workgroup) and the group's dimensions
+    void *lbw;
+    int64_t lbw_unit;
+    int32_t nx, nu;
 };
 
 }  // namespace rs

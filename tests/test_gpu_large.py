@@ -1,0 +1,126 @@
+"""GPU parity of the large-block kernels (n_x, n_u multiples of 16 up to 128
+outside the register/LDS-resident shapes: the n_x = 64 serving shape and the
+n_x = 128 large-block configuration) against the serial FP64 oracle.  The FP64
+solve of these shapes runs on the stored factorization; mixed precision is the
+FP32 factorization with FP64 refinement.  Tolerance: relative error <= 1e-10
+per block, as for the other shapes."""
+import numpy as np
+import pytest
+
+from oracle import kkt, riccati
+from paper_1510_03110_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+RHS_KEYS = ("x0", "a", "lx", "lw", "c", "lN", "cN")
+
+
+def _rs():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1510_03110_amd import rs
+    return torch, rs
+
+
+def _batch(probs, **opt):
+    torch, rs = _rs()
+    data = {k: [p[k] for p in probs] for k in probs[0]}
+    return torch, rs, rs.Batch(data, **opt)
+
+
+def _check(prob, sol, tol=TOL):
+    ref = riccati.solve(prob)
+    err = kkt.rel_error(sol, ref)
+    assert err <= tol, "rel err %.3e" % err
+    assert abs(sol["obj"] - ref["obj"]) <= 1e-9 * max(1.0, abs(ref["obj"]))
+    return err
+
+
+@pytest.mark.parametrize("nx,nu,N,Ns,b", [(64, 32, 96, 8, 3), (48, 16, 80, 8, 4), (64, 16, 64, 8, 2),
+                                          (16, 32, 40, 4, 3), (128, 64, 48, 4, 3), (96, 48, 50, 8, 2),
+                                          (64, 64, 30, 4, 2), (112, 32, 37, 8, 3)])
+def test_large_fp64_matches_oracle(nx, nu, N, Ns, b):
+    prob = W.with_costs(W.g2(nx, nu, N, seed=nx * 7 + nu + N), seed=N)
+    torch, rs, bt = _batch([prob], Ns=Ns, branch=b)
+    bt.solve()
+    torch.cuda.synchronize()
+    assert bt.status()[0, 0] == 0
+    _check(prob, bt.result(0))
+    bt.close()
+
+
+@pytest.mark.parametrize("N,Ns", [(8, 16), (16, 16), (1, 4)])
+def test_large_whole_problem_leaf(N, Ns):
+    """A horizon that fits one leaf: Alg. 1-3 on the leaf with the true
+    terminal (no master levels)."""
+    prob = W.with_costs(W.g2(64, 32, N, seed=300 + N), seed=N)
+    torch, rs, bt = _batch([prob], Ns=Ns, branch=2)
+    bt.solve()
+    torch.cuda.synchronize()
+    assert bt.status()[0, 0] == 0
+    _check(prob, bt.result(0))
+    bt.close()
+
+
+def test_large_uneven_batch_and_mixed_shapes():
+    """Instances of several large shapes and horizons in one call, beside a
+    register-resident shape (the plan groups them by shape)."""
+    probs = [W.g2(64, 32, n, seed=400 + n) for n in (33, 100, 7)]
+    probs += [W.g2(32, 16, 50, seed=450), W.g2(48, 32, 41, seed=451)]
+    torch, rs, bt = _batch(probs, Ns=8, branch=3)
+    bt.solve()
+    torch.cuda.synchronize()
+    assert np.all(bt.status()[:, 0] == 0)
+    for i, p in enumerate(probs):
+        _check(p, bt.result(i))
+    bt.close()
+
+
+def test_large_factor_then_several_solves():
+    prob = W.g2(64, 32, 120, seed=501)
+    torch, rs, bt = _batch([prob], Ns=8, branch=4, factored=True)
+    bt.factor()
+    rng = np.random.default_rng(5)
+    for r in range(2):
+        q = dict(prob)
+        for k in RHS_KEYS:
+            q[k] = rng.standard_normal(np.shape(prob[k]))
+            bt.update(k, 0, q[k])
+        bt.solve_factored()
+        torch.cuda.synchronize()
+        assert bt.status()[0, 0] == 0
+        _check(q, bt.result(0))
+    bt.close()
+
+
+@pytest.mark.parametrize("nx,nu,N,Ns,b", [(64, 32, 200, 8, 4), (128, 64, 40, 4, 3), (64, 32, 12, 16, 2)])
+def test_large_mixed_matches_oracle_after_refinement(nx, nu, N, Ns, b):
+    prob = W.g2(nx, nu, N, seed=11 * N + nx)
+    torch, rs, bt = _batch([prob], precision=rs_mixed(), Ns=Ns, branch=b)
+    bt.solve()
+    torch.cuda.synchronize()
+    assert bt.status()[0, 0] == 0
+    _check(prob, bt.result(0))
+    st = bt.refine_stats()[0]
+    assert st[3] == 1.0 and st[0] <= TOL and 1 <= st[2] <= 5
+    bt.close()
+
+
+def rs_mixed():
+    _, rs = _rs()
+    return rs.RS_MIXED_FP32
+
+
+def test_large_not_spd_stage_reported():
+    prob = W.g1(64, 32, 40, seed=4)
+    prob["Qw"] = prob["Qw"].copy()
+    prob["Qw"][13] = -5.0 * np.eye(32)
+    prob["B"] = prob["B"].copy()
+    prob["B"][13] = 0.0
+    torch, rs, bt = _batch([prob], Ns=4, branch=2)
+    bt.solve()
+    torch.cuda.synchronize()
+    st = bt.status()
+    assert st[0, 0] == 2 and st[0, 1] == 13
+    bt.close()

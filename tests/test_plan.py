@@ -227,3 +227,26 @@ def test_per_instance_leaf_length_and_branch():
         rs.rs_plan_destroy(plan)
     with pytest.raises(rs.RsError):
         rs.rs_plan_create([(4, 2, 100, 8, 1)])       # branch 1 is invalid
+
+
+def test_large_block_shapes_plan_factored():
+    """Multiple-of-16 shapes beyond the register-resident ones (up to 128) are
+    planned with the stored factorization, on which their FP64 solve runs, and
+    a per-workgroup matrix workspace; larger or ragged shapes stay
+    unsupported."""
+    nx, nu, N = 64, 32, 256
+    p0 = rs.rs_plan_create([(nx, nu, N)], Ns=8, branch=4)
+    p1 = rs.rs_plan_create([(nx, nu, N)], Ns=8, branch=4, flags=rs.RS_PLAN_FACTORED)
+    try:
+        ws = rs.rs_plan_workspace_size(p0)
+        assert ws == rs.rs_plan_workspace_size(p1)
+        records = 8 * N * ((2 * nx * nx + 2 * nu * nu + 2 * nu * nx) + (nx * nx + 2 * nu * nu + nu * nx) + nx + nu)
+        unit = 8 * (5 * nx * nx + 2 * nx * 2 * nx + 4 * nx * nx + 4 * nx * nx + 512 + 16 * nx)   # master blocks m = n
+        assert ws >= records + (N // 8) * unit
+    finally:
+        rs.rs_plan_destroy(p0)
+        rs.rs_plan_destroy(p1)
+    for dims in [(144, 16, 64), (40, 16, 64), (64, 136, 64)]:
+        with pytest.raises(rs.RsError) as e:
+            rs.rs_plan_create([dims], Ns=16)
+        assert e.value.status == rs.RS_ERR_UNSUPPORTED
