@@ -363,7 +363,7 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         const size_t esz = sizeof(double);
         off = align_up(off + esz * (size_t)g.scratch_elems);
         g.leaf_stages = g.scratch_elems / g.shape->scratch_per_stage;
-        if (g.shape->large) {
+        if (g.shape->lb && P->factored) {
             const int64_t units = std::max<int64_t>(std::min<int64_t>((int64_t)g.leaves.size(), LB_LEAF_UNITS),
                                                     std::min<int64_t>((int64_t)g.items.size(), LB_TREE_UNITS));
             g.lbw_unit = large_unit_bytes(g.nx, g.nu);
@@ -611,7 +611,7 @@ static GroupArgs group_args(rs_plan P, char *W, size_t gi, int32_t *info, bool c
     a.ntop = g.ntop;
     a.fstore = P->factored ? W + g.off_fstore : nullptr;
     a.fvec = P->factored ? reinterpret_cast<double *>(W + g.off_fvec) : nullptr;
-    a.lbw = g.shape->large ? W + g.off_lbw : nullptr;
+    a.lbw = (g.shape->lb && P->factored) ? W + g.off_lbw : nullptr;
     a.lbw_unit = (int64_t)g.lbw_unit;
     a.nx = g.nx;
     a.nu = g.nu;

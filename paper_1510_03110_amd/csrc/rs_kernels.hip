@@ -16,6 +16,9 @@
 //                parent's P, Psi, cbar and x (Alg. 6, k = 0); writes x, w, lam.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+
 #include "rs_device.hpp"
 #include "rs_launch.hpp"
 
@@ -363,6 +366,7 @@ const ShapeEntry *find_shape(int nx, int nu) {
             e.nx = a;
             e.nu = b;
             e.large = false;
+            e.lb = false;
             e.fp64[0] = mfma_leaf_up(a, b) ? mfma_leaf_up(a, b) : up;
             e.fp64[1] = mfma_tree(a) ? mfma_tree(a) : tr;
             e.fp64[2] = mfma_leaf_down(a, b) ? mfma_leaf_down(a, b) : dn;
@@ -373,6 +377,18 @@ const ShapeEntry *find_shape(int nx, int nu) {
                 }
             e.refine[0] = refine_kernel(a, b, 0);
             e.refine[1] = refine_kernel(a, b, 1);
+            // no matrix-core form of the stored factorization: the large-block
+            // kernels serve it (and mixed precision)
+            e.lb = !e.factor[0][0] && large_shape(a, b);
+            if (e.lb) {
+                for (int f = 0; f < 2; ++f)
+                    for (int k = 0; k < 3; ++k) {
+                        e.factor[f][k] = large_factor(k, f == 1);
+                        e.vsolve[f][k] = large_vector(k, f == 1);
+                    }
+                e.refine[0] = large_refine(0);
+                e.refine[1] = large_refine(1);
+            }
             e.scratch_per_stage = mfma_leaf_down(a, b) ? scratch_per_stage_fwd(a, b) : scratch_per_stage(a, b);
             if (e.fp64[0] && e.fp64[1] && e.fp64[2]) table[n++] = e;
         };
@@ -383,31 +399,29 @@ const ShapeEntry *find_shape(int nx, int nu) {
     }
     for (int i = 0; i < n; ++i)
         if (table[i].nx == nx && table[i].nu == nu) return &table[i];
-    // large-block family: any other multiple-of-16 shape up to 128
-    static ShapeEntry large[8][8];
-    static bool large_init = false;
+    // large-block family: any other shape up to 128 (entries made on first use)
     if (!large_shape(nx, nu)) return nullptr;
-    if (!large_init) {
-        for (int a = 0; a < 8; ++a)
-            for (int b = 0; b < 8; ++b) {
-                ShapeEntry &e = large[a][b];
-                e.nx = 16 * (a + 1);
-                e.nu = 16 * (b + 1);
-                e.large = true;
-                for (int k = 0; k < 3; ++k) {
-                    e.fp64[k] = nullptr;
-                    for (int f = 0; f < 2; ++f) {
-                        e.factor[f][k] = large_factor(k, f == 1);
-                        e.vsolve[f][k] = large_vector(k, f == 1);
-                    }
-                }
-                e.refine[0] = large_refine(0);
-                e.refine[1] = large_refine(1);
-                e.scratch_per_stage = 1;      // leaf stage index = scratch offset
-            }
-        large_init = true;
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, ShapeEntry> large;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = large.find({nx, nu});
+    if (it != large.end()) return &it->second;
+    ShapeEntry e;
+    e.nx = nx;
+    e.nu = nu;
+    e.large = true;
+    e.lb = true;
+    for (int k = 0; k < 3; ++k) {
+        e.fp64[k] = nullptr;
+        for (int f = 0; f < 2; ++f) {
+            e.factor[f][k] = large_factor(k, f == 1);
+            e.vsolve[f][k] = large_vector(k, f == 1);
+        }
     }
-    return &large[nx / 16 - 1][nu / 16 - 1];
+    e.refine[0] = large_refine(0);
+    e.refine[1] = large_refine(1);
+    e.scratch_per_stage = 1;      // leaf stage index = scratch offset
+    return &large.emplace(std::make_pair(nx, nu), e).first->second;
 }
 
 }  // namespace rs

@@ -1,6 +1,7 @@
-// Large-block kernels of the parallel Riccati solve: n_x and n_u multiples
-// of 16 up to 128 that have no register- and LDS-resident specialisation
-// (the n_x = 64 and n_x = 128 problems).  A 64 x 64 FP64 stage already needs
+// Large-block kernels of the parallel Riccati solve: any n_x, n_u up to 128
+// without a register- and LDS-resident specialisation (the n_x = 64 and
+// n_x = 128 problems; also the stored factorization of the small shapes
+// whose fused solve has no matrix-core form).  A 64 x 64 FP64 stage already needs
 // about 260 KB of working set, more than a CU's LDS, so here the matrices of a
 // work unit live in a per-workgroup workspace in global memory (L2-resident
 // while the unit runs) and only vectors use LDS.  Sizes are run-time values.
@@ -122,14 +123,16 @@ __device__ __forceinline__ void wave_gfence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// C = opA(A) opB(B): M x N, inner size K (all multiples of 16).  opA(i,k) =
-// TA ? A[k*lda+i] : A[i*lda+k], opB(k,j) = TB ? B[j*ldb+k] : B[k*ldb+j].
-// Tile (ti, tj) goes to wave (tile index) mod 4 and is handed to epi(ti, tj,
-// acc); with `lower` only the tiles ti >= tj of a square result are formed.
+// C = opA(A) opB(B): M x N, inner size K (any sizes; edge tiles are padded
+// with zeros on load).  opA(i,k) = TA ? A[k*lda+i] : A[i*lda+k], opB(k,j) =
+// TB ? B[j*ldb+k] : B[k*ldb+j].  16x16 tile t goes to wave t mod 4; every
+// element (i, j) of the result with i < M, j < N is handed to epi(i, j, c).
+// With `lower` (square results) only the tiles on and below the diagonal are
+// formed, and epi must use the elements with i >= j.
 template <bool TA, bool TB, class T, class Epi>
 __device__ __forceinline__ void gemm(int M, int N, int K, const T *__restrict__ A, int lda, const T *__restrict__ B,
                                      int ldb, bool lower, Epi epi) {
-    const int tm = M >> 4, tn = N >> 4;
+    const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
     const int nt = lower ? tm * (tm + 1) / 2 : tm * tn;
     const int l = lane(), r16 = l & 15, k4 = l >> 4;
     for (int t = wave(); t < nt; t += NT / 64) {
@@ -141,39 +144,69 @@ __device__ __forceinline__ void gemm(int M, int N, int K, const T *__restrict__ 
             tj = t - ti * tn;
         }
         const int i = 16 * ti + r16, j = 16 * tj + r16;
+        const bool iv = i < M, jv = j < N;
         v4_t<T> acc = mf::zero4<T>();
+#pragma unroll 2
         for (int k0 = 0; k0 < K; k0 += 16) {
             T a[4], b[4];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int k = k0 + 4 * s + k4;
-                a[s] = TA ? A[(int64_t)k * lda + i] : A[(int64_t)i * lda + k];
-                b[s] = TB ? B[(int64_t)j * ldb + k] : B[(int64_t)k * ldb + j];
+                a[s] = (iv && k < K) ? (TA ? A[(int64_t)k * lda + i] : A[(int64_t)i * lda + k]) : T(0);
+                b[s] = (jv && k < K) ? (TB ? B[(int64_t)j * ldb + k] : B[(int64_t)k * ldb + j]) : T(0);
             }
 #pragma unroll
             for (int s = 0; s < 4; ++s) acc = MT<T>::mfma(a[s], b[s], acc);
         }
-        epi(ti, tj, acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ii = mf::trow<T>(ti, r), jj = mf::tcol(tj);
+            if (ii < M && jj < N) epi(ii, jj, acc[r]);
+        }
     }
 }
 
+// acc += opA(A) opB(B) for one 16 x 16 x 16 block with only the first ri
+// rows, rk inner indices and rj columns taken (the rest read as zero).
+// opA(i,k) = A[i*lda+k]; opB(k,j) = TB ? B[j*ldb+k] : B[k*ldb+j].
+template <bool TB, class T>
+__device__ __forceinline__ v4_t<T> blk16(v4_t<T> acc, const T *A, int lda, const T *B, int ldb, int ri, int rk,
+                                         int rj) {
+    const int l = lane(), r16 = l & 15, k4 = l >> 4;
+    T a[4], b[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = 4 * s + k4;
+        a[s] = (r16 < ri && k < rk) ? A[(int64_t)r16 * lda + k] : T(0);
+        b[s] = (r16 < rj && k < rk) ? (TB ? B[(int64_t)r16 * ldb + k] : B[(int64_t)k * ldb + r16]) : T(0);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc = MT<T>::mfma(a[s], b[s], acc);
+    return acc;
+}
+
 // Blocked Cholesky factorization G = L L' ("a factorization of G", Alg. 1)
-// and the explicit inverse, for m a multiple of 16.  Right-looking over
-// 16-wide block columns: the diagonal block is factored and inverted by one
-// wavefront (chol_inv_wave), the panel below it is L_ik = G_ik L_kk^{-T},
-// and the trailing lower blocks are updated G_ij -= L_ik L_jk'.  The inverse
-// follows block row by block row: X_ii = L_ii^{-1},
-// X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj.  On return Li = L^{-1} and
-// LiT = L^{-T} (row-major, zeros above / below the diagonal); G is
-// overwritten.  *bad is set if a pivot failed.  Every thread must call it;
-// it ends with a workgroup barrier.
+// and the explicit inverse (any m <= 128).  Right-looking over 16-wide block
+// columns: the diagonal block (padded with the identity past m) is factored
+// and inverted by one wavefront (chol_inv_wave), the panel below it is
+// L_ik = G_ik L_kk^{-T}, and the trailing lower blocks are updated
+// G_ij -= L_ik L_jk'.  The inverse follows block row by block row:
+// X_ii = L_ii^{-1}, X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj.  On return
+// Li = L^{-1} and LiT = L^{-T} (row-major, zeros above / below the
+// diagonal); G is overwritten.  *bad is set if a pivot failed.  Every thread
+// must call it; it ends with a workgroup barrier.
 template <class T>
 __device__ void chol_inv(WS<T> &S, int m, int *bad) {
-    const int nb = m >> 4, tid = threadIdx.x, w = wave(), l = lane();
+    const int nb = (m + 15) >> 4, tid = threadIdx.x, w = wave(), l = lane();
     T *G = S.G, *Li = S.Li, *Lp = S.Lp, *D = S.D, *DT = S.DT;
+    auto rows = [&](int b) { return m - 16 * b < 16 ? m - 16 * b : 16; };
     for (int kb = 0; kb < nb; ++kb) {
+        const int rk = rows(kb);
         if (w == 0) {
-            for (int e = l; e < 256; e += 64) D[e] = G[(int64_t)(16 * kb + e / 16) * m + 16 * kb + e % 16];
+            for (int e = l; e < 256; e += 64) {
+                const int i = e / 16, j = e % 16;
+                D[e] = (i < rk && j < rk) ? G[(int64_t)(16 * kb + i) * m + 16 * kb + j] : (i == j ? T(1) : T(0));
+            }
             wave_gfence();
             const int f = mf::chol_inv_wave<16>(D, DT);      // D <- L_kk^{-1}, DT <- L_kk^{-T}
             if (f && l == 0) *bad = 1;
@@ -182,35 +215,45 @@ __device__ void chol_inv(WS<T> &S, int m, int *bad) {
         // panel below the diagonal block, then the trailing lower blocks
         const int np = nb - kb - 1;
         for (int t = w; t < np; t += NT / 64) {
-            const int ib = kb + 1 + t;
-            v4_t<T> acc = mf::mma<16, false, false>(mf::zero4<T>(), G + (int64_t)16 * ib * m + 16 * kb, m, DT, 16, 0, 0);
-            mf::tile_for<T>(0, 0, [&](int r, int i, int j) { Lp[(int64_t)(16 * ib + i) * m + 16 * kb + j] = acc[r]; });
+            const int ib = kb + 1 + t, ri = rows(ib);
+            const v4_t<T> acc = blk16<false>(mf::zero4<T>(), G + (int64_t)16 * ib * m + 16 * kb, m, DT, 16, ri, rk, rk);
+            mf::tile_for<T>(0, 0, [&](int r, int i, int j) {
+                if (i < ri && j < rk) Lp[(int64_t)(16 * ib + i) * m + 16 * kb + j] = acc[r];
+            });
         }
-        for (int e = tid; e < 256; e += NT) Li[(int64_t)(16 * kb + e / 16) * m + 16 * kb + e % 16] = D[e];
+        for (int e = tid; e < 256; e += NT) {
+            const int i = e / 16, j = e % 16;
+            if (i < rk && j < rk) Li[(int64_t)(16 * kb + i) * m + 16 * kb + j] = D[e];
+        }
         __syncthreads();
         const int nt = np * (np + 1) / 2;
         for (int t = w; t < nt; t += NT / 64) {
             int a, b;
             mf::lower_tile(t, a, b);
-            const int ib = kb + 1 + a, jb = kb + 1 + b;
-            v4_t<T> acc = mf::mma<16, false, true>(mf::zero4<T>(), Lp + (int64_t)16 * ib * m + 16 * kb, m,
-                                                    Lp + (int64_t)16 * jb * m + 16 * kb, m, 0, 0);
-            mf::tile_for<T>(0, 0, [&](int r, int i, int j) { G[(int64_t)(16 * ib + i) * m + 16 * jb + j] -= acc[r]; });
+            const int ib = kb + 1 + a, jb = kb + 1 + b, ri = rows(ib), rj = rows(jb);
+            const v4_t<T> acc = blk16<true>(mf::zero4<T>(), Lp + (int64_t)16 * ib * m + 16 * kb, m,
+                                            Lp + (int64_t)16 * jb * m + 16 * kb, m, ri, rk, rj);
+            mf::tile_for<T>(0, 0, [&](int r, int i, int j) {
+                if (i < ri && j < rj) G[(int64_t)(16 * ib + i) * m + 16 * jb + j] -= acc[r];
+            });
         }
         __syncthreads();
     }
     // block rows of the inverse
     for (int ib = 1; ib < nb; ++ib) {
+        const int ri = rows(ib);
         for (int jb = w; jb < ib; jb += NT / 64) {
             v4_t<T> acc = mf::zero4<T>();
             for (int kb = jb; kb < ib; ++kb)
-                acc = mf::mma<16, false, false>(acc, Lp + (int64_t)16 * ib * m + 16 * kb, m,
-                                                 Li + (int64_t)16 * kb * m + 16 * jb, m, 0, 0);
+                acc = blk16<false>(acc, Lp + (int64_t)16 * ib * m + 16 * kb, m, Li + (int64_t)16 * kb * m + 16 * jb, m,
+                                   ri, 16, 16);
             T *tm = S.Tm + 256 * jb;
             mf::tile_for<T>(0, 0, [&](int r, int i, int j) { tm[i * 16 + j] = acc[r]; });
             wave_gfence();
-            acc = mf::mma<16, false, false>(mf::zero4<T>(), Li + (int64_t)16 * ib * m + 16 * ib, m, tm, 16, 0, 0);
-            mf::tile_for<T>(0, 0, [&](int r, int i, int j) { Li[(int64_t)(16 * ib + i) * m + 16 * jb + j] = -acc[r]; });
+            acc = blk16<false>(mf::zero4<T>(), Li + (int64_t)16 * ib * m + 16 * ib, m, tm, 16, ri, ri, 16);
+            mf::tile_for<T>(0, 0, [&](int r, int i, int j) {
+                if (i < ri) Li[(int64_t)(16 * ib + i) * m + 16 * jb + j] = -acc[r];
+            });
         }
         __syncthreads();
     }
@@ -294,33 +337,30 @@ __device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int
         }
         __syncthreads();
         // W = P [A B]; Alg. 4: B'V, A'V
-        gemm<false, false>(n, nw, n, S.P, n, S.AB, nw, false, [&](int ti, int tj, v4_t<T> acc) {
-            mf::tile_for<T>(ti, tj, [&](int r, int i, int j) { S.W[(int64_t)i * nw + j] = acc[r]; });
-        });
+        gemm<false, false>(n, nw, n, S.P, n, S.AB, nw, false, [&](int i, int j, T c) { S.W[(int64_t)i * nw + j] = c; });
         if constexpr (RED) {
-            gemm<true, false>(m, n, n, S.AB + n, nw, S.V, n, false, [&](int ti, int tj, v4_t<T> acc) {
-                mf::tile_for<T>(ti, tj, [&](int r, int i, int j) { S.BV[(int64_t)i * n + j] = acc[r]; });
-            });
-            gemm<true, false>(n, n, n, S.AB, nw, S.V, n, false, [&](int ti, int tj, v4_t<T> acc) {
-                mf::tile_for<T>(ti, tj, [&](int r, int i, int j) { S.AV[(int64_t)i * n + j] = acc[r]; });
-            });
+            gemm<true, false>(m, n, n, S.AB + n, nw, S.V, n, false,
+                              [&](int i, int j, T c) { S.BV[(int64_t)i * n + j] = c; });
+            gemm<true, false>(n, n, n, S.AB, nw, S.V, n, false, [&](int i, int j, T c) { S.AV[(int64_t)i * n + j] = c; });
         }
         __syncthreads();
         // F = Qx + A'W_A (symmetric), H = Qxw + A'W_B, G = Qw + B'W_B (symmetric)
-        gemm<true, false>(n, n, n, S.AB, nw, S.W, nw, true, [&](int ti, int tj, v4_t<T> acc) {
-            mf::tile_for<T>(ti, tj, [&](int r, int i, int j) {
-                mf::put_sym(S.F, n, ti, tj, i, j, (T)src.Qx[(int64_t)i * n + j] + acc[r]);
-            });
+        gemm<true, false>(n, n, n, S.AB, nw, S.W, nw, true, [&](int i, int j, T c) {
+            if (i >= j) {
+                const T v = (T)src.Qx[(int64_t)i * n + j] + c;
+                S.F[(int64_t)i * n + j] = v;
+                S.F[(int64_t)j * n + i] = v;
+            }
         });
-        gemm<true, false>(n, m, n, S.AB, nw, S.W + n, nw, false, [&](int ti, int tj, v4_t<T> acc) {
-            mf::tile_for<T>(ti, tj, [&](int r, int i, int j) {
-                S.H[(int64_t)i * m + j] = (src.Qxw ? (T)src.Qxw[(int64_t)i * m + j] : T(0)) + acc[r];
-            });
+        gemm<true, false>(n, m, n, S.AB, nw, S.W + n, nw, false, [&](int i, int j, T c) {
+            S.H[(int64_t)i * m + j] = (src.Qxw ? (T)src.Qxw[(int64_t)i * m + j] : T(0)) + c;
         });
-        gemm<true, false>(m, m, n, S.AB + n, nw, S.W + n, nw, true, [&](int ti, int tj, v4_t<T> acc) {
-            mf::tile_for<T>(ti, tj, [&](int r, int i, int j) {
-                mf::put_sym(S.G, m, ti, tj, i, j, (T)src.Qw[(int64_t)i * m + j] + acc[r]);
-            });
+        gemm<true, false>(m, m, n, S.AB + n, nw, S.W + n, nw, true, [&](int i, int j, T c) {
+            if (i >= j) {
+                const T v = (T)src.Qw[(int64_t)i * m + j] + c;
+                S.G[(int64_t)i * m + j] = v;
+                S.G[(int64_t)j * m + i] = v;
+            }
         });
         __syncthreads();
         chol_inv(S, m, bad);
@@ -330,51 +370,37 @@ __device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int
         }
         out.L(s, S.Li, S.LiT);
         // Y' = H L^{-T}; Alg. 4: X = L^{-1} B'V
-        gemm<false, false>(n, m, m, S.H, m, S.LiT, m, false, [&](int ti, int tj, v4_t<T> acc) {
-            mf::tile_for<T>(ti, tj, [&](int r, int i, int j) { S.HY[(int64_t)i * m + j] = acc[r]; });
-        });
+        gemm<false, false>(n, m, m, S.H, m, S.LiT, m, false, [&](int i, int j, T c) { S.HY[(int64_t)i * m + j] = c; });
         if constexpr (RED) {
-            gemm<false, false>(m, n, m, S.Li, m, S.BV, n, false, [&](int ti, int tj, v4_t<T> acc) {
-                mf::tile_for<T>(ti, tj, [&](int r, int i, int j) { S.X[(int64_t)i * n + j] = acc[r]; });
-            });
+            gemm<false, false>(m, n, m, S.Li, m, S.BV, n, false, [&](int i, int j, T c) { S.X[(int64_t)i * n + j] = c; });
         }
         __syncthreads();
         // P = F - Y'Y (symmetric), K = -L^{-T} Y
-        gemm<false, true>(n, n, m, S.HY, m, S.HY, m, true, [&](int ti, int tj, v4_t<T> acc) {
-            mf::tile_for<T>(ti, tj, [&](int r, int i, int j) {
-                if (ti != tj || i >= j) {
-                    const T v = S.F[(int64_t)i * n + j] - acc[r];
-                    S.P[(int64_t)i * n + j] = v;
-                    S.P[(int64_t)j * n + i] = v;
-                    out.P(s, i, j, v);
-                    out.P(s, j, i, v);
-                }
-            });
+        gemm<false, true>(n, n, m, S.HY, m, S.HY, m, true, [&](int i, int j, T c) {
+            if (i >= j) {
+                const T v = S.F[(int64_t)i * n + j] - c;
+                S.P[(int64_t)i * n + j] = v;
+                S.P[(int64_t)j * n + i] = v;
+                out.P(s, i, j, v);
+                out.P(s, j, i, v);
+            }
         });
-        gemm<false, true>(m, n, m, S.LiT, m, S.HY, m, false, [&](int ti, int tj, v4_t<T> acc) {
-            mf::tile_for<T>(ti, tj, [&](int r, int i, int j) { out.K(s, i, j, -acc[r]); });
-        });
+        gemm<false, true>(m, n, m, S.LiT, m, S.HY, m, false, [&](int i, int j, T c) { out.K(s, i, j, -c); });
         if constexpr (RED) {
             // Q_w_hat += X'X, V = A'V - Y'X, L_t = -L^{-T} X
-            gemm<true, false>(n, n, m, S.X, n, S.X, n, true, [&](int ti, int tj, v4_t<T> acc) {
-                mf::tile_for<T>(ti, tj, [&](int r, int i, int j) {
-                    if (ti != tj || i >= j) {
-                        const T v = S.Qh[(int64_t)i * n + j] + acc[r];
-                        S.Qh[(int64_t)i * n + j] = v;
-                        S.Qh[(int64_t)j * n + i] = v;
-                    }
-                });
+            gemm<true, false>(n, n, m, S.X, n, S.X, n, true, [&](int i, int j, T c) {
+                if (i >= j) {
+                    const T v = S.Qh[(int64_t)i * n + j] + c;
+                    S.Qh[(int64_t)i * n + j] = v;
+                    S.Qh[(int64_t)j * n + i] = v;
+                }
             });
-            gemm<false, false>(n, n, m, S.HY, m, S.X, n, false, [&](int ti, int tj, v4_t<T> acc) {
-                mf::tile_for<T>(ti, tj, [&](int r, int i, int j) {
-                    const T v = S.AV[(int64_t)i * n + j] - acc[r];
-                    S.V[(int64_t)i * n + j] = v;
-                    out.V(s, i, j, v);
-                });
+            gemm<false, false>(n, n, m, S.HY, m, S.X, n, false, [&](int i, int j, T c) {
+                const T v = S.AV[(int64_t)i * n + j] - c;
+                S.V[(int64_t)i * n + j] = v;
+                out.V(s, i, j, v);
             });
-            gemm<false, false>(m, n, m, S.LiT, m, S.X, n, false, [&](int ti, int tj, v4_t<T> acc) {
-                mf::tile_for<T>(ti, tj, [&](int r, int i, int j) { out.Lt(s, i, j, -acc[r]); });
-            });
+            gemm<false, false>(m, n, m, S.LiT, m, S.X, n, false, [&](int i, int j, T c) { out.Lt(s, i, j, -c); });
         }
         __syncthreads();
     }
@@ -552,6 +578,7 @@ struct VS {
     double Psi[VMAX], pt[VMAX], av[VMAX], d[VMAX], x[VMAX], gw[VMAX], z[VMAX], kk[VMAX], wv[VMAX], v[VMAX],
         lamN[VMAX], y[VMAX];
     double red[NT / 64];
+    double gred[NT];
 };
 
 __device__ __forceinline__ double block_sum(double v, VS &S) {
@@ -565,27 +592,46 @@ __device__ __forceinline__ double block_sum(double v, VS &S) {
     return s;
 }
 
-// y(i) = sum_k op(M)(i,k) x[k] for i < R, k < C, handed to out(i, y) by one
-// thread per i.  COLUMN-read form op(M)(i,k) = M[k*ld+i]: one thread per
-// output, consecutive threads on consecutive words.  ROW-read form
-// op(M)(i,k) = M[i*ld+k]: one wavefront per output row, lanes over k.
+// y(i) = sum_k op(M)(i,k) x[k] for i < R, k < C (R, C <= 128), handed to
+// out(i, y) by one thread per i; every thread of the workgroup must call it.
+// COLUMN-read form op(M)(i,k) = M[k*ld+i]: output i and a contiguous part of
+// the k range per thread (consecutive threads on consecutive words), the
+// parts summed in a fixed order through LDS.  ROW-read form
+// op(M)(i,k) = M[i*ld+k]: 16 lanes per output row, strided over k, summed
+// with lane shuffles.  Several loads per thread are in flight in both.
 template <bool ROW, class U, class Out>
-__device__ __forceinline__ void gemv(const U *M, int ld, const double *x, int R, int C, Out out) {
+__device__ __forceinline__ void gemv(const U *M, int ld, const double *x, int R, int C, Out out, double *red) {
+    const int tid = threadIdx.x;
     if constexpr (!ROW) {
-        for (int i = threadIdx.x; i < R; i += NT) {
-            double acc = 0.0;
-            if (M)
-                for (int k = 0; k < C; ++k) acc += (double)M[(int64_t)k * ld + i] * x[k];
-            out(i, acc);
+        int Rp = 16;
+        while (Rp < R) Rp <<= 1;
+        const int parts = NT / Rp, i = tid & (Rp - 1), p = tid / Rp;
+        const int chunk = (C + parts - 1) / parts, k0 = p * chunk, k1 = k0 + chunk < C ? k0 + chunk : C;
+        double acc = 0.0;
+        if (M && i < R) {
+#pragma unroll 8
+            for (int k = k0; k < k1; ++k) acc += (double)M[(int64_t)k * ld + i] * x[k];
         }
+        red[tid] = acc;
+        __syncthreads();
+        if (tid < R) {
+            double s = 0.0;
+            for (int q = 0; q < parts; ++q) s += red[q * Rp + tid];
+            out(tid, s);
+        }
+        __syncthreads();
     } else {
-        const int l = lane();
-        for (int i = wave(); i < R; i += NT / 64) {
+        const int l = lane(), c16 = l & 15, row = wave() * 4 + (l >> 4);
+        for (int base = 0; base < R; base += NT / 16) {
+            const int i = base + row;
             double acc = 0.0;
-            if (M)
-                for (int k = l; k < C; k += 64) acc += (double)M[(int64_t)i * ld + k] * x[k];
-            acc = sv::wave_sum(acc);
-            if (l == 0) out(i, acc);
+            if (M && i < R) {
+#pragma unroll 8
+                for (int k = c16; k < C; k += 16) acc += (double)M[(int64_t)i * ld + k] * x[k];
+            }
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+            if (c16 == 0 && i < R) out(i, acc);
         }
     }
 }
@@ -617,35 +663,35 @@ __device__ void vstage(VS &S, const VSrcL<TR> &q, int n, int m, double &cbar) {
         gemv<false>(q.Pn, n, S.av, n, n, [&](int i, double pa) {
             S.pt[i] = S.Psi[i] - pa;
             part += S.av[i] * (0.5 * pa - S.Psi[i]);
-        });
+        }, S.gred);
     else
         gemv<false>(q.Pn64, n, S.av, n, n, [&](int i, double pa) {
             S.pt[i] = S.Psi[i] - pa;
             part += S.av[i] * (0.5 * pa - S.Psi[i]);
-        });
+        }, S.gred);
     const double s1 = block_sum(part, S);
     if (tid == 0) cbar += s1 + q.c;
-    gemv<false>(q.B, m, S.pt, m, n, [&](int j, double v) { S.gw[j] = v - (q.lw ? q.lw[j] : 0.0); });
+    gemv<false>(q.B, m, S.pt, m, n, [&](int j, double v) { S.gw[j] = v - (q.lw ? q.lw[j] : 0.0); }, S.gred);
     __syncthreads();
     double zz = 0.0;
     gemv<false>(q.LT, m, S.gw, m, m, [&](int i, double v) {
         S.z[i] = v;
         zz += v * v;
-    });
-    gemv<false>(q.A, n, S.pt, n, n, [&](int i, double v) { S.y[i] = v - (q.lx ? q.lx[i] : 0.0); });
+    }, S.gred);
+    gemv<false>(q.A, n, S.pt, n, n, [&](int i, double v) { S.y[i] = v - (q.lx ? q.lx[i] : 0.0); }, S.gred);
     __syncthreads();
-    gemv<false>(q.K, n, S.gw, n, m, [&](int i, double v) { S.Psi[i] = S.y[i] + v; });
+    gemv<false>(q.K, n, S.gw, n, m, [&](int i, double v) { S.Psi[i] = S.y[i] + v; }, S.gred);
     const double s2 = block_sum(zz, S);
     if (tid == 0) cbar -= 0.5 * s2;
     if constexpr (RED || WANTK) {
-        gemv<false>(q.Li, m, S.z, m, m, [&](int i, double v) { S.kk[i] = v; });
+        gemv<false>(q.Li, m, S.z, m, m, [&](int i, double v) { S.kk[i] = v; }, S.gred);
         __syncthreads();
     }
     if constexpr (RED) {
-        gemv<true>(q.B, m, S.kk, n, m, [&](int i, double v) { S.d[i] = S.av[i] + v; });
+        gemv<true>(q.B, m, S.kk, n, m, [&](int i, double v) { S.d[i] = S.av[i] + v; }, S.gred);
         __syncthreads();
         if (q.Vn)
-            gemv<false>(q.Vn, n, S.d, n, n, [&](int i, double v) { S.v[i] += v; });
+            gemv<false>(q.Vn, n, S.d, n, n, [&](int i, double v) { S.v[i] += v; }, S.gred);
         else
             for (int i = tid; i < n; i += NT) S.v[i] += S.d[i];
         __syncthreads();
@@ -662,20 +708,20 @@ __device__ void fstage(VS &S, int n, int m, const TR *K, const double *kvec, con
     const int tid = threadIdx.x;
     for (int i = tid; i < n; i += NT)
         if (x_out) x_out[i] = S.x[i];
-    gemv<true>(K, n, S.x, m, n, [&](int i, double v) { S.wv[i] = v + kvec[i]; });
-    gemv<true>(A, n, S.x, n, n, [&](int i, double v) { S.y[i] = v + (a ? a[i] : 0.0); });
-    if (P) gemv<false>(P, n, S.x, n, n, [&](int i, double v) { S.d[i] = v - Psi[i]; });
+    gemv<true>(K, n, S.x, m, n, [&](int i, double v) { S.wv[i] = v + kvec[i]; }, S.gred);
+    gemv<true>(A, n, S.x, n, n, [&](int i, double v) { S.y[i] = v + (a ? a[i] : 0.0); }, S.gred);
+    if (P) gemv<false>(P, n, S.x, n, n, [&](int i, double v) { S.d[i] = v - Psi[i]; }, S.gred);
     __syncthreads();
     if (Lt) {
-        gemv<true>(Lt, n, S.lamN, m, n, [&](int i, double v) { S.wv[i] += v; });
-        gemv<true>(Vt, n, S.lamN, n, n, [&](int i, double v) { S.d[i] += v; });
+        gemv<true>(Lt, n, S.lamN, m, n, [&](int i, double v) { S.wv[i] += v; }, S.gred);
+        gemv<true>(Vt, n, S.lamN, n, n, [&](int i, double v) { S.d[i] += v; }, S.gred);
         __syncthreads();
     }
     for (int i = tid; i < m; i += NT)
         if (w_out) w_out[i] = S.wv[i];
     for (int i = tid; i < n; i += NT)
         if (lam_out) lam_out[i] = S.d[i];
-    gemv<true>(B, m, S.wv, n, m, [&](int i, double v) { S.y[i] += v; });
+    gemv<true>(B, m, S.wv, n, m, [&](int i, double v) { S.y[i] += v; }, S.gred);
     __syncthreads();
     for (int i = tid; i < n; i += NT) S.x[i] = S.y[i];
     __syncthreads();
@@ -685,7 +731,7 @@ __device__ void fstage(VS &S, int n, int m, const TR *K, const double *kvec, con
 template <class TP>
 __device__ double cost_to_go(VS &S, const TP *P, int n, double cbar) {
     double part = 0.0;
-    gemv<false>(P, n, S.x, n, n, [&](int i, double v) { part += S.x[i] * (0.5 * v - S.Psi[i]); });
+    gemv<false>(P, n, S.x, n, n, [&](int i, double v) { part += S.x[i] * (0.5 * v - S.Psi[i]); }, S.gred);
     const double s = block_sum(part, S);
     return s + cbar;
 }
@@ -788,7 +834,7 @@ __device__ void leaf_forward(VS &S, const GroupArgs &g, const sv::Prob &p, const
         const double *nxt = msg + SL.size();           // the next leaf's slot: x_hat_{i+1}
         for (int i = tid; i < n; i += NT) S.x[i] = nxt[SL.xh() + i];
         __syncthreads();
-        gemv<false>(msg + SL.P(), n, S.x, n, n, [&](int i, double v) { S.lamN[i] = v - msg[SL.Psi() + i]; });
+        gemv<false>(msg + SL.P(), n, S.x, n, n, [&](int i, double v) { S.lamN[i] = v - msg[SL.Psi() + i]; }, S.gred);
         __syncthreads();
     }
     for (int i = tid; i < n; i += NT) S.x[i] = msg[SL.xh() + i];
@@ -807,7 +853,7 @@ __device__ void leaf_forward(VS &S, const GroupArgs &g, const sv::Prob &p, const
         gemv<false>(p.QxN, n, S.x, n, n, [&](int i, double v) {
             p.lam[t * n + i] = v + (p.lN ? p.lN[i] : 0.0);     // lam_N = QxN x_N + lN
             p.x[t * n + i] = S.x[i];
-        });
+        }, S.gred);
     }
 }
 
@@ -868,7 +914,7 @@ __global__ void __launch_bounds__(NT) kw_leaf_down(GroupArgs g) {
     gemv<false>(p.QxN, n, S.x, n, n, [&](int i, double v) {
         p.lam[t * n + i] = v + (p.lN ? p.lN[i] : 0.0);         // lam_N = QxN x_N + lN
         p.x[t * n + i] = S.x[i];
-    });
+    }, S.gred);
 }
 
 __global__ void __launch_bounds__(NT) kw_tree(GroupArgs g) {
@@ -994,15 +1040,15 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
         for (int i = tid; i < m; i += NT) ws[i] = w[i];
         __syncthreads();
         // x row: Qx x + Qxw w - lam + A' lam+ ; lam+ row: A x + B w - x+
-        gemv<true>(Qx, n, xs, n, n, [&](int i, double v) { S.pt[i] = v; });
-        gemv<true>(Qxw, m, ws, n, m, [&](int i, double v) { S.d[i] = v; });
-        gemv<false>(A, n, ls, n, n, [&](int i, double v) { S.av[i] = v; });
-        gemv<true>(A, n, xs, n, n, [&](int i, double v) { S.y[i] = v; });
-        gemv<true>(B, m, ws, n, m, [&](int i, double v) { S.Psi[i] = v; });
+        gemv<true>(Qx, n, xs, n, n, [&](int i, double v) { S.pt[i] = v; }, S.gred);
+        gemv<true>(Qxw, m, ws, n, m, [&](int i, double v) { S.d[i] = v; }, S.gred);
+        gemv<false>(A, n, ls, n, n, [&](int i, double v) { S.av[i] = v; }, S.gred);
+        gemv<true>(A, n, xs, n, n, [&](int i, double v) { S.y[i] = v; }, S.gred);
+        gemv<true>(B, m, ws, n, m, [&](int i, double v) { S.Psi[i] = v; }, S.gred);
         // w row: Qxw' x + Qw w + B' lam+
-        gemv<false>(Qxw, m, xs, m, n, [&](int j, double v) { S.gw[j] = v; });
-        gemv<true>(Qw, m, ws, m, m, [&](int j, double v) { S.z[j] = v; });
-        gemv<false>(B, m, ls, m, n, [&](int j, double v) { S.kk[j] = v; });
+        gemv<false>(Qxw, m, xs, m, n, [&](int j, double v) { S.gw[j] = v; }, S.gred);
+        gemv<true>(Qw, m, ws, m, m, [&](int j, double v) { S.z[j] = v; }, S.gred);
+        gemv<false>(B, m, ls, m, n, [&](int j, double v) { S.kk[j] = v; }, S.gred);
         __syncthreads();
         double part = 0.0;
         for (int i = tid; i < n; i += NT) {
@@ -1047,7 +1093,7 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
             rhs = fmax(rhs, fabs(lNi));
             res = fmax(res, fabs(dN));
             part += x[i] * (0.5 * qx + lNi);
-        });
+        }, S.gred);
         const double tot = block_sum(part, S);
         if (tid == 0) obj += tot + (p.cN ? p.cN[0] : 0.0);
     }
@@ -1164,9 +1210,7 @@ hipError_t launch_update(const GroupArgs &g, int grid, hipStream_t st) {
 
 }  // namespace lb
 
-bool large_shape(int nx, int nu) {
-    return nx >= 16 && nu >= 16 && nx <= lb::VMAX && nu <= lb::VMAX && nx % 16 == 0 && nu % 16 == 0;
-}
+bool large_shape(int nx, int nu) { return nx >= 1 && nu >= 1 && nx <= lb::VMAX && nu <= lb::VMAX; }
 
 Launcher large_factor(int which, bool fp32) {
     if (which == 0) return fp32 ? &lb::launch_leaf_up<float> : &lb::launch_leaf_up<double>;

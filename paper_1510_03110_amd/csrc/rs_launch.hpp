@@ -27,7 +27,8 @@ enum KernelKind {
 
 struct ShapeEntry {
     int nx, nu;
-    bool large;              // large-block family: no fused kernels, matrices in a global workspace
+    bool large;              // no fused kernels: the FP64 solve runs on the stored factorization
+    bool lb;                 // the stored factorization uses the large-block kernels (global workspace)
     Launcher fp64[3];        // fused: leaf up, tree, leaf down
     Launcher factor[2][3];   // stored factorization [fp32 leaves][pass] (nullptr: not available)
     Launcher vsolve[2][3];   // right-hand-side passes on the stored factorization
@@ -45,8 +46,8 @@ hipError_t launch_refine_check(const InstInfo *tab, int count, const double *par
                                int32_t *info, const DevProb *probs, int mode, double tol, int32_t *active,
                                int nactive, hipStream_t st);
 
-// Large-block family (n_x, n_u multiples of 16 up to 128): stored
-// factorization only, with a per-workgroup workspace of large_unit_bytes.
+// Large-block family (any n_x, n_u up to 128): stored factorization with a
+// per-workgroup workspace of large_unit_bytes.
 constexpr int LB_LEAF_UNITS = 2048, LB_TREE_UNITS = 256;
 bool large_shape(int nx, int nu);
 size_t large_unit_bytes(int nx, int nu);

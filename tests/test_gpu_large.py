@@ -124,3 +124,56 @@ def test_large_not_spd_stage_reported():
     st = bt.status()
     assert st[0, 0] == 2 and st[0, 1] == 13
     bt.close()
+
+
+@pytest.mark.parametrize("nx,nu,N,Ns,b", [(24, 12, 50, 4, 3), (5, 5, 40, 4, 2), (40, 16, 60, 8, 2),
+                                          (100, 60, 30, 4, 2), (7, 3, 33, 4, 4)])
+def test_large_ragged_shapes_fp64(nx, nu, N, Ns, b):
+    """Dimensions that are not multiples of the 16-wide tiles (edge tiles are
+    padded with zeros, the diagonal blocks of the Cholesky with the identity)."""
+    prob = W.with_costs(W.g2(nx, nu, N, seed=nx * 13 + nu + N), seed=N)
+    torch, rs, bt = _batch([prob], Ns=Ns, branch=b)
+    bt.solve()
+    torch.cuda.synchronize()
+    assert bt.status()[0, 0] == 0
+    _check(prob, bt.result(0))
+    bt.close()
+
+
+@pytest.mark.parametrize("nx,nu,N,Ns,b", [(16, 8, 300, 16, 4), (8, 4, 200, 8, 3), (20, 10, 256, 8, 4),
+                                          (4, 2, 64, 4, 2), (24, 12, 10, 16, 2)])
+def test_mixed_precision_small_shapes(nx, nu, N, Ns, b):
+    """Mixed precision for the shapes whose fused solve has no matrix-core
+    form: FP32 factorization by the large-block kernels, FP64 refinement."""
+    prob = W.g2(nx, nu, N, seed=17 * N + nx)
+    torch, rs, bt = _batch([prob], precision=rs_mixed(), Ns=Ns, branch=b)
+    bt.solve()
+    torch.cuda.synchronize()
+    assert bt.status()[0, 0] == 0
+    _check(prob, bt.result(0))
+    st = bt.refine_stats()[0]
+    assert st[3] == 1.0 and st[0] <= TOL and 1 <= st[2] <= 5
+    bt.close()
+
+
+def test_batching_config_mixed_precision_sampled():
+    """4096 instances of n_x=16, n_u=8 with horizons uniform in [32, 2048]
+    (G1, time-invariant A and B given once) in mixed precision: FP32
+    factorization, FP64 master levels and refinement to 1e-10; every instance
+    converges and sampled instances match the oracle."""
+    torch, rs = _rs()
+    rng = np.random.default_rng(W.seed_for(2))
+    Ns_all = rng.integers(32, 2049, size=4096)
+    probs = [W.g1_invariant(16, 8, int(n), seed=W.seed_for(2, i)) for i, n in enumerate(Ns_all)]
+    data = {k: [p[k] for p in probs] for k in probs[0]}
+    b = rs.Batch(data, precision=rs.RS_MIXED_FP32, Ns=16, branch=4)
+    b.solve()
+    torch.cuda.synchronize()
+    assert np.all(b.status()[:, 0] == 0)
+    st = b.refine_stats()
+    assert np.all(st[:, 3] == 1.0) and st[:, 0].max() <= TOL
+    pick = sorted({0, 4095, int(np.argmin(Ns_all)), int(np.argmax(Ns_all))} |
+                  set(int(i) for i in rng.integers(0, 4096, size=30)))
+    for i in pick:
+        _check(W.materialize(probs[i]), b.result(i))
+    b.close()

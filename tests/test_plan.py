@@ -159,7 +159,7 @@ def test_plan_rejects_bad_arguments():
     with pytest.raises(rs.RsError):
         rs.rs_plan_create([(0, 1, 64)])
     with pytest.raises(rs.RsError):
-        rs.rs_plan_create([(5, 5, 64)])                # no kernel for this shape
+        rs.rs_plan_create([(130, 65, 64)])             # no kernel for this shape
     with pytest.raises(rs.RsError):
         rs.rs_plan_create([(4, 2, 3)], Ns=1)           # Ns*nu < nx on a multi-leaf problem
     p = rs.rs_plan_create([(4, 2, 1)], Ns=1)           # a single leaf needs no reduction
@@ -167,8 +167,7 @@ def test_plan_rejects_bad_arguments():
 
 
 def test_factored_plan_workspace_and_shape_support():
-    """The stored factorization adds LeafRec doubles per leaf stage; it exists
-    for matrix-core shapes only."""
+    """The stored factorization adds LeafRec doubles per leaf stage."""
     dims = [(32, 16, 1024)]
     p0 = rs.rs_plan_create(dims, Ns=16, branch=4)
     p1 = rs.rs_plan_create(dims, Ns=16, branch=4, flags=rs.RS_PLAN_FACTORED)
@@ -180,9 +179,10 @@ def test_factored_plan_workspace_and_shape_support():
     finally:
         rs.rs_plan_destroy(p0)
         rs.rs_plan_destroy(p1)
-    with pytest.raises(rs.RsError) as e:
-        rs.rs_plan_create([(4, 2, 64)], flags=rs.RS_PLAN_FACTORED)
-    assert e.value.status == rs.RS_ERR_UNSUPPORTED
+    # shapes without a matrix-core form store their factorization with the
+    # large-block kernels
+    p2 = rs.rs_plan_create([(4, 2, 64)], flags=rs.RS_PLAN_FACTORED)
+    rs.rs_plan_destroy(p2)
 
 
 def test_factor_needs_factored_plan():
@@ -230,10 +230,9 @@ def test_per_instance_leaf_length_and_branch():
 
 
 def test_large_block_shapes_plan_factored():
-    """Multiple-of-16 shapes beyond the register-resident ones (up to 128) are
-    planned with the stored factorization, on which their FP64 solve runs, and
-    a per-workgroup matrix workspace; larger or ragged shapes stay
-    unsupported."""
+    """Shapes up to 128 beyond the register-resident ones are planned with the
+    stored factorization, on which their FP64 solve runs, and a per-workgroup
+    matrix workspace; larger shapes stay unsupported."""
     nx, nu, N = 64, 32, 256
     p0 = rs.rs_plan_create([(nx, nu, N)], Ns=8, branch=4)
     p1 = rs.rs_plan_create([(nx, nu, N)], Ns=8, branch=4, flags=rs.RS_PLAN_FACTORED)
@@ -246,7 +245,7 @@ def test_large_block_shapes_plan_factored():
     finally:
         rs.rs_plan_destroy(p0)
         rs.rs_plan_destroy(p1)
-    for dims in [(144, 16, 64), (40, 16, 64), (64, 136, 64)]:
+    for dims in [(144, 16, 64), (64, 136, 64), (129, 64, 64)]:
         with pytest.raises(rs.RsError) as e:
             rs.rs_plan_create([dims], Ns=16)
         assert e.value.status == rs.RS_ERR_UNSUPPORTED
