@@ -30,6 +30,9 @@ METRIC = "KKT Newton solves/s at n_x=32,N=1024 (FP64 vs mixed) + p50/p99 latency
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector (and FP64 matrix) peak
 FP32_PEAK_TFLOPS = 157.3         # MI355X FP32 vector / FP32 matrix (dense) peak
 HBM_PEAK_GBS = 8000.0
+# shapes with register/LDS-resident matrix-core kernels; the others run the
+# large-block kernels (matrices in a per-workgroup global workspace)
+MATRIX_CORE_SHAPES = {(16, 16), (32, 16), (32, 32)}
 
 
 def log(*a):
@@ -193,19 +196,24 @@ def run_precision(prec, args, data, dev):
 
     # ------------------------------------------------ roofline (dominant)
     leaves = rs.rs_plan_export(batch.plan, 0)
-    if not mixed:
+    fused = "leaf_up" in per_step          # otherwise the solve runs on the stored factorization
+    matrix_core = (n, m) in MATRIX_CORE_SHAPES
+    if fused:
         up, down = leaf_work(leaves, n, m, flops_reduce, flops_elim, flops_forward, flops_solve)
         work = {"leaf_up": ("alu", up, FP64_PEAK_TFLOPS, "km_leaf_up"),
                 "leaf_down": ("alu", down, FP64_PEAK_TFLOPS, "km_leaf_down")}
     else:
-        up, down = leaf_work(leaves, n, m, flops_factor_reduce, flops_factor_elim, flops_factor_elim)
-        stages = float(leaves[:, 2].sum())
+        # the factorization's leaf-down kernel serves whole-problem leaves only
+        up, down = leaf_work(leaves, n, m, flops_factor_reduce, flops_factor_elim, lambda a, b: 0.0,
+                             flops_factor_elim)
+        peak = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
+        pre = "kf_" if matrix_core else "kl_"
         # kernels launched once per step (the refinement kernels skip
         # converged instances, so their per-launch work is not fixed)
-        work = {"factor_leaf_up": ("alu", up, FP32_PEAK_TFLOPS, "kf_leaf_up"),
-                "factor_leaf_down": ("alu", down, FP32_PEAK_TFLOPS, "kf_leaf_down")}
-    avg = {k: kt[k][0] / max(kt[k][1], 1) for k in work}
-    dom = max(work, key=lambda k: per_step.get(k, 0.0))
+        work = {"factor_leaf_up": ("alu", up, peak, pre + "leaf_up"),
+                "factor_leaf_down": ("alu", down, peak, pre + "leaf_down")}
+    avg = {k: kt[k][0] / max(kt[k][1], 1) for k in work if k in kt}
+    dom = max(avg, key=lambda k: per_step.get(k, 0.0))
     bound, amount, peak, kname = work[dom]
     if bound == "hbm":
         achieved = amount / (avg[dom] * 1e-3) / 1e9

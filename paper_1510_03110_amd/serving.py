@@ -36,6 +36,8 @@ arrival process) to the host's observation of its launch's completion event.
 import time
 from collections import deque
 
+import sys
+
 import numpy as np
 
 from . import rs
@@ -369,10 +371,10 @@ def main(argv=None):
     ap.add_argument("--seconds", type=float, default=10.0)
     ap.add_argument("--warmup-seconds", type=float, default=1.0)
     ap.add_argument("--sessions", type=int, default=64)
-    ap.add_argument("--nx", default="8,16,32", help="state dimensions; n_u = n_x / 2")
+    ap.add_argument("--nx", default="8,32,64", help="state dimensions; n_u = n_x / 2")
     ap.add_argument("--Nmin", type=int, default=64)
     ap.add_argument("--Nmax", type=int, default=4096)
-    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="mixed")
     ap.add_argument("--lanes", type=int, default=2)
     ap.add_argument("--seed", type=int, default=W.seed_for(3))
     args = ap.parse_args(argv)
@@ -388,6 +390,8 @@ def main(argv=None):
         sid = eng.add_session(W.g2(nx, nx // 2, N, seed=args.seed + 17 * i))
         if sid is not None:
             shapes.append((nx, nx // 2))
+    print("serving: %d sessions admitted (%s)" % (len(shapes), ", ".join(sorted(set("%dx%d" % s for s in shapes)))),
+          file=sys.stderr, flush=True)
     pools = {sh: stage_pool(sh[0], sh[1], 64, seed=args.seed + sh[0]) for sh in set(shapes)}
     warm = poisson_trace(args.rate, args.warmup_seconds, len(shapes), pools, shapes, args.seed + 1)
     eng.run(warm)

@@ -24,7 +24,9 @@ def _engine(precision, record=True):
 
 
 @pytest.mark.parametrize("precision,shapes", [(0, [(4, 2), (8, 4), (32, 16), (16, 16)]),
-                                              (1, [(32, 16), (16, 16)])])
+                                              (1, [(32, 16), (16, 16)]),
+                                              (1, [(8, 4), (32, 16), (64, 32)]),
+                                              (0, [(64, 32), (8, 4)])])
 def test_serving_mix_equals_alone_and_oracle(precision, shapes):
     torch, serving, eng = _engine(precision)
     probs = [W.g2(nx, nu, 40 + 23 * i, seed=300 + i) for i, (nx, nu) in enumerate(shapes)]
