@@ -142,6 +142,32 @@ rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *o
 rs_status rs_plan_create_ex(int32_t count, const int32_t *dims5, const rs_options *opt,
                             rs_plan *plan_out);
 
+/*
+ * Receding-horizon plan (serving): dims8 holds per instance
+ *   (nx, nu, N, Ns, branch, start, reuse_lo, reuse_hi)
+ * where `start` >= 0 is the absolute index of the window's first stage.  The
+ * leaves are laid out on absolute stage boundaries (multiples of Ns, as in
+ * the subinterval split of Sec. 4.1): the first leaf runs from `start` to the
+ * second boundary after it (the first if `start` is on a boundary), so every
+ * leaf but the last keeps at least Ns stages; then full interior leaves
+ * a = [a Ns, (a+1) Ns); the last leaf ends with the window and carries the
+ * terminal cost.  The stored factorization of interior leaf a lives in ring
+ * block a mod (N / Ns + 1) of its instance, at a place in the workspace that
+ * depends only on (nx, nu, N, Ns) of the instances in order, so consecutive
+ * plans with the same instance list share one workspace and its factors.
+ * Interior leaves with reuse_lo <= a < reuse_hi are not factored again: their
+ * stored factors and reduced form (Alg. 4 output) from an earlier call on the
+ * same workspace are used.  The caller guarantees that the stage matrices of
+ * those leaves are unchanged since that call; after a call with window start
+ * s, the leaves a in [first_end / Ns, (s + N - 1) / Ns) hold current factors,
+ * with first_end = (s / Ns + (s % Ns == 0 ? 1 : 2)) Ns (integer division;
+ * none if s + N <= first_end).  The vector passes and the master levels run
+ * in full on every call; the FP64 solve always uses the stored factorization.
+ * Errors as rs_plan_create, and RS_ERR_ARG for start < 0.
+ */
+rs_status rs_plan_create_ring(int32_t count, const int32_t *dims8, const rs_options *opt,
+                              rs_plan *plan_out);
+
 /* Device workspace bytes the plan needs (caller allocates, 256-byte aligned). */
 rs_status rs_plan_workspace_size(rs_plan plan, size_t *bytes);
 

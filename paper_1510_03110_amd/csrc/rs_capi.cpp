@@ -35,6 +35,12 @@ struct Group {
     size_t off_leaves = 0, off_items = 0, off_flags = 0, off_slots = 0, off_scratch = 0, off_fstore = 0,
            off_fvec = 0;
     size_t off_lbw = 0, lbw_unit = 0;       // large-block workspace (per workgroup)
+    int64_t ring_stages = 0;                // receding-horizon plans: record stages of the group
+    int ring_m1 = 0;                        // and M1 cache blocks (3 n^2 doubles each)
+    size_t off_m1 = 0;
+    // receding-horizon plans: table and slot counts reserved for any window
+    // position, so that the workspace size does not depend on it
+    int64_t res_leaves = 0, res_items = 0, res_slots = 0;
 };
 
 }  // namespace
@@ -45,6 +51,8 @@ struct rs_plan_s {
     bool factored = false;          // workspace holds the stored factorization
     bool mixed = false;             // FP32 leaf factorization + FP64 refinement
     bool via_factor = false;        // FP64 solve = stored factorization + solve (large-block shapes)
+    bool receding = false;          // receding-horizon layout (rs_plan_create_ring)
+    std::vector<int64_t> inst_start, inst_lo, inst_hi;
     int32_t total_leaves = 0;
     std::vector<InstInfo> inst;     // per instance: leaf range (refinement reductions)
     std::vector<size_t> off_cbuf;   // per instance: correction buffers (mixed)
@@ -83,12 +91,20 @@ namespace {
 // the terminal cost (Sec. 4.2).  Level k >= 1 has S_k master stages plus a
 // terminal; while S_k exceeds the top size its stages are grouped b at a time
 // into master subproblems, the last group taking the terminal.
+// Receding-horizon plans: interior ring blocks per instance (a window of N
+// stages has at most N / Ns interior leaves) and the stages of its records
+// (ring, then first-leaf and last-leaf areas of 2 Ns stages each).
+int ring_blocks(int N, int Ns) { return N / Ns + 1; }
+int64_t ring_stages(int N, int Ns) { return ((int64_t)ring_blocks(N, Ns) + 4) * Ns; }
+
 struct Tmp {
     TreeItem it;
     int phase, level, inst, node;
     int dep_level, dep_lo, dep_hi;   // UP/TOP: child nodes at dep_level; DOWN: parent node
     bool dep_top;
 };
+
+void build_tree(Group &g, int inst, int L0, int base1, int b, int top_max, std::vector<Tmp> &tmp);
 
 void build_instance(Group &g, int inst, int N, int Ns, int b, int top_max, std::vector<Tmp> &tmp) {
     const int L0 = (N + Ns - 1) / Ns;
@@ -107,6 +123,51 @@ void build_instance(Group &g, int inst, int N, int Ns, int b, int top_max, std::
         g.leaves.push_back(lf);
         g.scratch_elems += (int64_t)len * sps;
     }
+    build_tree(g, inst, L0, base1, b, top_max, tmp);
+}
+
+// Receding-horizon layout of one instance whose window starts at absolute
+// stage `start`: leaf boundaries sit at absolute multiples of Ns, so a shift
+// of the window leaves the interior leaves unchanged.  The first leaf runs
+// from the window start to the second boundary after it (to the first if the
+// start is on a boundary), so that every leaf but the last has at least Ns
+// stages (Ns nu >= nx); the last leaf ends with the window.  Interior leaf a
+// (stages [a Ns, (a+1) Ns)) keeps its stored factorization in ring block
+// a mod ring_blocks; the first and last leaves use areas of their own.
+// Interior leaves with a in [lo, hi) are marked LEAF_REUSE.
+// Stage offsets are relative to the instance's record base `rbase` (stages);
+// `mbase` is its first M1 cache block.
+void build_instance_ring(Group &g, int inst, int N, int Ns, int b, int top_max, int64_t start, int64_t lo,
+                         int64_t hi, int64_t rbase, int mbase, std::vector<Tmp> &tmp) {
+    const int sps = g.shape->scratch_per_stage;
+    const int nblocks = ring_blocks(N, Ns);
+    const int64_t first_end = (start / Ns + (start % Ns == 0 ? 1 : 2)) * (int64_t)Ns, end = start + N;
+    const int64_t edge_first = rbase + (int64_t)nblocks * Ns, edge_last = edge_first + 2 * (int64_t)Ns;
+    if (end <= first_end) {
+        LeafItem lf{inst, 0, N, LEAF_LAST | LEAF_TOP, -1, -1, edge_first * sps};
+        g.leaves.push_back(lf);
+        return;
+    }
+    const int64_t last_a = (end - 1) / Ns;          // block of the last stage
+    const int L0 = 1 + (int)(last_a - first_end / Ns) + 1 - (last_a * Ns < first_end ? 1 : 0);
+    const int base1 = (int)g.nslots;
+    g.nslots += L0;
+    int i = 0;
+    g.leaves.push_back(LeafItem{inst, 0, (int)(first_end - start), L0 == 1 ? LEAF_LAST : 0, base1 + i++, -1,
+                                edge_first * sps});
+    for (int64_t a = first_end / Ns; a < last_a; ++a) {
+        const int blk = (int)(a % nblocks);
+        const int flags = (a >= lo && a < hi) ? LEAF_REUSE : 0;
+        g.leaves.push_back(LeafItem{inst, (int)(a * Ns - start), Ns, flags, base1 + i++, mbase + blk,
+                                    (rbase + (int64_t)blk * Ns) * sps});
+    }
+    if (last_a * Ns >= first_end)
+        g.leaves.push_back(LeafItem{inst, (int)(last_a * Ns - start), (int)(end - last_a * Ns), LEAF_LAST, base1 + i++,
+                                    -1, edge_last * sps});
+    build_tree(g, inst, L0, base1, b, top_max, tmp);
+}
+
+void build_tree(Group &g, int inst, int L0, int base1, int b, int top_max, std::vector<Tmp> &tmp) {
     int level = 1, S = L0 - 1, lvl_base = base1, prev_nodes = L0;
     for (;;) {
         if (S <= top_max) {
@@ -276,6 +337,23 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         }
         P->inst_Ns[i] = ns > 0 ? ns : P->Ns;
         P->inst_branch[i] = br > 0 ? br : P->branch;
+        if (stride >= 8) {
+            const int32_t *d = dims_in + (size_t)stride * i;
+            if (d[5] < 0) {
+                delete P;
+                return RS_ERR_ARG;
+            }
+            P->inst_start.push_back(d[5]);
+            P->inst_lo.push_back(d[6]);
+            P->inst_hi.push_back(d[7]);
+        }
+    }
+    if (stride >= 8) {
+        // records live at fixed places across calls: the solve always runs on
+        // the stored factorization
+        P->receding = true;
+        P->factored = true;
+        P->via_factor = !P->mixed;
     }
     const int32_t *dims = P->dims.data();
     std::map<std::pair<int, int>, int> gidx;
@@ -321,8 +399,31 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         g.leaf_base = P->total_leaves;
         for (int inst : g.insts) {
             const int before = (int)g.leaves.size();
-            build_instance(g, inst, dims[3 * inst + 2], P->inst_Ns[inst], P->inst_branch[inst], P->inst_branch[inst],
-                           tmp);
+            if (P->receding) {
+                const int N = dims[3 * inst + 2], Ns = P->inst_Ns[inst];
+                build_instance_ring(g, inst, N, Ns, P->inst_branch[inst], P->inst_branch[inst], P->inst_start[inst],
+                                    P->inst_lo[inst], P->inst_hi[inst], g.ring_stages, g.ring_m1, tmp);
+                g.ring_stages += ring_stages(N, Ns);
+                g.ring_m1 += ring_blocks(N, Ns);
+                // a window has between N/Ns - 1 and N/Ns + 2 leaves
+                int64_t mi = 0, ms = 0;
+                for (int L = std::max(1, N / Ns - 2); L <= N / Ns + 2; ++L) {
+                    if (L == 1) continue;
+                    Group d;
+                    d.shape = g.shape;
+                    d.nslots = L;
+                    std::vector<Tmp> t;
+                    build_tree(d, 0, L, 0, P->inst_branch[inst], P->inst_branch[inst], t);
+                    mi = std::max<int64_t>(mi, (int64_t)t.size());
+                    ms = std::max<int64_t>(ms, d.nslots);
+                }
+                g.res_leaves += N / Ns + 2;
+                g.res_items += mi;
+                g.res_slots += ms;
+            } else {
+                build_instance(g, inst, dims[3 * inst + 2], P->inst_Ns[inst], P->inst_branch[inst],
+                               P->inst_branch[inst], tmp);
+            }
             InstInfo &in = P->inst[inst];
             in.first_leaf = g.leaf_base + before;
             in.nleaves = (int)g.leaves.size() - before;
@@ -342,34 +443,51 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
     off = align_up(off + sizeof(int32_t) * 2 * count);
     P->off_queues = off;
     off = align_up(off + sizeof(int32_t) * P->groups.size());
+    if (P->receding) {
+        // the stored factorization first: its place depends only on the
+        // instances' shapes, horizons and leaf lengths, not on the window
+        // positions, so consecutive receding-horizon plans share it
+        for (auto &g : P->groups) {
+            const size_t rec = P->mixed ? sizeof(float) : sizeof(double);
+            g.leaf_stages = g.ring_stages;
+            g.off_fstore = off;
+            off = align_up(off + rec * (size_t)g.leaf_stages * LeafRec{g.nx, g.nu}.per_stage());
+            g.off_fvec = off;
+            off = align_up(off + sizeof(double) * (size_t)g.leaf_stages * LeafRec{g.nx, g.nu}.vec());
+            g.off_m1 = off;
+            off = align_up(off + sizeof(double) * 3 * (size_t)g.nx * g.nx * (size_t)g.ring_m1);
+        }
+    }
     P->off_tables = off;
     for (auto &g : P->groups) {
         g.off_leaves = off;
-        off = align_up(off + sizeof(LeafItem) * g.leaves.size());
+        off = align_up(off + sizeof(LeafItem) * std::max<size_t>(g.leaves.size(), (size_t)g.res_leaves));
         g.off_items = off;
-        off = align_up(off + sizeof(TreeItem) * g.items.size());
+        off = align_up(off + sizeof(TreeItem) * std::max<size_t>(g.items.size(), (size_t)g.res_items));
     }
     P->off_inst = off;
     off = align_up(off + sizeof(InstInfo) * count);
     P->tables_bytes = off - P->off_tables;
     for (auto &g : P->groups) {
         g.off_flags = off;
-        off = align_up(off + sizeof(int32_t) * std::max<size_t>(1, g.items.size()));
+        off = align_up(off + sizeof(int32_t) * std::max<size_t>({(size_t)1, g.items.size(), (size_t)g.res_items}));
     }
     for (auto &g : P->groups) {
         g.off_slots = off;
-        off = align_up(off + sizeof(double) * SlotLayout{g.nx}.size() * (size_t)g.nslots);
+        off = align_up(off + sizeof(double) * SlotLayout{g.nx}.size() * (size_t)std::max(g.nslots, g.res_slots));
         g.off_scratch = off;
         const size_t esz = sizeof(double);
         off = align_up(off + esz * (size_t)g.scratch_elems);
-        g.leaf_stages = g.scratch_elems / g.shape->scratch_per_stage;
+        if (!P->receding) g.leaf_stages = g.scratch_elems / g.shape->scratch_per_stage;
         if (g.shape->lb && P->factored) {
-            const int64_t units = std::max<int64_t>(std::min<int64_t>((int64_t)g.leaves.size(), LB_LEAF_UNITS),
-                                                    std::min<int64_t>((int64_t)g.items.size(), LB_TREE_UNITS));
+            const int64_t units =
+                std::max<int64_t>(std::min<int64_t>(std::max<int64_t>((int64_t)g.leaves.size(), g.res_leaves), LB_LEAF_UNITS),
+                                  std::min<int64_t>(std::max<int64_t>((int64_t)g.items.size(), g.res_items), LB_TREE_UNITS));
             g.lbw_unit = large_unit_bytes(g.nx, g.nu);
             g.off_lbw = off;
             off = align_up(off + g.lbw_unit * (size_t)std::max<int64_t>(units, 1));
         }
+        if (P->receding) continue;
         g.off_fstore = off;
         if (P->factored) {
             const size_t rec = P->mixed ? sizeof(float) : sizeof(double);
@@ -384,7 +502,9 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         P->off_stats = off;
         off = align_up(off + sizeof(double) * ST_N * count);
         P->off_part = off;
-        off = align_up(off + sizeof(double) * PART_N * (size_t)P->total_leaves);
+        int64_t res_total = 0;
+        for (auto &g : P->groups) res_total += std::max<int64_t>((int64_t)g.leaves.size(), g.res_leaves);
+        off = align_up(off + sizeof(double) * PART_N * (size_t)res_total);
         // per instance: xbar0' nx | a' N nx | lx' N nx | lw' N nu | lN' nx | dx (N+1) nx | dw N nu | dlam (N+1) nx
         P->off_cbuf.resize(count);
         for (int i = 0; i < count; ++i) {
@@ -414,6 +534,10 @@ rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *o
 
 rs_status rs_plan_create_ex(int32_t count, const int32_t *dims5, const rs_options *opt, rs_plan *out) {
     return plan_create(count, dims5, 5, opt, out);
+}
+
+rs_status rs_plan_create_ring(int32_t count, const int32_t *dims8, const rs_options *opt, rs_plan *out) {
+    return plan_create(count, dims8, 8, opt, out);
 }
 
 rs_status rs_plan_workspace_size(rs_plan P, size_t *bytes) {
@@ -613,6 +737,7 @@ static GroupArgs group_args(rs_plan P, char *W, size_t gi, int32_t *info, bool c
     a.fvec = P->factored ? reinterpret_cast<double *>(W + g.off_fvec) : nullptr;
     a.lbw = (g.shape->lb && P->factored) ? W + g.off_lbw : nullptr;
     a.lbw_unit = (int64_t)g.lbw_unit;
+    a.m1cache = P->receding ? reinterpret_cast<double *>(W + g.off_m1) : nullptr;
     a.nx = g.nx;
     a.nu = g.nu;
     if (P->mixed) {

@@ -49,7 +49,7 @@ __device__ __forceinline__ LeafItem load_leaf(const LeafItem *tab, int i) {
     u.len = uni(r.len);
     u.flags = uni(r.flags);
     u.slot = uni(r.slot);
-    u.pad = 0;
+    u.m1 = uni(r.m1);
     u.scratch = ((int64_t)uni((int)(r.scratch >> 32)) << 32) | (uint32_t)uni((int)(r.scratch & 0xffffffff));
     return u;
 }

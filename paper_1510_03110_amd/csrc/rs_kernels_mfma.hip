@@ -22,7 +22,7 @@ __device__ __forceinline__ LeafItem load_leaf_u(const LeafItem *tab, int i) {
     u.len = uni(r.len);
     u.flags = uni(r.flags);
     u.slot = uni(r.slot);
-    u.pad = 0;
+    u.m1 = uni(r.m1);
     u.scratch = ((int64_t)uni((int)(r.scratch >> 32)) << 32) | (uint32_t)uni((int)(r.scratch & 0xffffffff));
     return u;
 }
@@ -577,6 +577,14 @@ __global__ void __launch_bounds__(NT, 2) kf_leaf_up(GroupArgs g) {
     T *base = reinterpret_cast<T *>(g.fstore) + (it.scratch / g.sps) * (int64_t)LeafRec{NX, NU}.per_stage();
     auto get = [&](int s) { return prob_stage(p, it.t0 + s); };
     const int tid = threadIdx.x;
+    if (it.flags & LEAF_REUSE) {
+        // stored factorization current (receding-horizon plans): only its
+        // cached M1 goes to this call's slot
+        const double *c = g.m1cache + (int64_t)it.m1 * 3 * NX * NX;
+        for (int e = tid; e < 3 * NX * NX; e += NT) out[e] = c[e];
+        return;
+    }
+    double *cache = (g.m1cache && it.m1 >= 0) ? g.m1cache + (int64_t)it.m1 * 3 * NX * NX : nullptr;
     if (!(it.flags & LEAF_LAST)) {
         auto &S = *reinterpret_cast<MSmem<T, NX, NU, true, false> *>(raw);
         for (int e = tid; e < NX * NX; e += NT) {
@@ -589,9 +597,15 @@ __global__ void __launch_bounds__(NT, 2) kf_leaf_up(GroupArgs g) {
                   LeafFacOut<T, NX, NU, true>{{}, base});
         for (int e = tid; e < NX * NX; e += NT) {
             const int i = e / NX, j = e % NX;
-            out[SL.A() + e] = S.V[j * NX + i];
-            out[SL.Qw() + e] = S.Qh[e];
-            out[SL.Qx() + e] = S.P[e];
+            const double a = S.V[j * NX + i], q = S.Qh[e], x = S.P[e];
+            out[SL.A() + e] = a;
+            out[SL.Qw() + e] = q;
+            out[SL.Qx() + e] = x;
+            if (cache) {
+                cache[SL.A() + e] = a;
+                cache[SL.Qw() + e] = q;
+                cache[SL.Qx() + e] = x;
+            }
         }
     } else {
         auto &S = *reinterpret_cast<MSmem<T, NX, NU, false, false> *>(raw);

@@ -439,6 +439,14 @@ __global__ void __launch_bounds__(NT) kl_leaf_up(GroupArgs g) {
         if ((it.flags & LEAF_TOP) || inst_skipped(g.probs, it.inst)) continue;
         const DevProb p = load_prob(g.probs, it.inst);
         double *out = g.slots + (int64_t)it.slot * SL.size();
+        if (it.flags & LEAF_REUSE) {
+            // stored factorization current (receding-horizon plans): only its
+            // cached M1 goes to this call's slot
+            const double *c = g.m1cache + (int64_t)it.m1 * 3 * n * n;
+            for (int e = tid; e < 3 * n * n; e += NT) out[e] = c[e];
+            continue;
+        }
+        double *cache = (g.m1cache && it.m1 >= 0) ? g.m1cache + (int64_t)it.m1 * 3 * n * n : nullptr;
         T *base = reinterpret_cast<T *>(g.fstore) + (it.scratch / g.sps) * (int64_t)LeafRec{n, m}.per_stage();
         auto get = [&](int s) { return leaf_stage(p, it.t0 + s); };
         const LeafOut<T> o{base, n, m, true};
@@ -447,9 +455,15 @@ __global__ void __launch_bounds__(NT) kl_leaf_up(GroupArgs g) {
             mpass<T, true>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, o, &bad);
             for (int e = tid; e < n * n; e += NT) {
                 const int i = e / n, j = e % n;
-                out[SL.A() + e] = (double)S.V[(int64_t)j * n + i];
-                out[SL.Qw() + e] = (double)S.Qh[e];
-                out[SL.Qx() + e] = (double)S.P[e];
+                const double a = (double)S.V[(int64_t)j * n + i], q = (double)S.Qh[e], x = (double)S.P[e];
+                out[SL.A() + e] = a;
+                out[SL.Qw() + e] = q;
+                out[SL.Qx() + e] = x;
+                if (cache) {
+                    cache[SL.A() + e] = a;
+                    cache[SL.Qw() + e] = q;
+                    cache[SL.Qx() + e] = x;
+                }
             }
         } else {
             for (int e = tid; e < n * n; e += NT) S.P[e] = (T)p.QxN[e];

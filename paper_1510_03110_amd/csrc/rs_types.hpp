@@ -26,10 +26,12 @@ struct LeafItem {
     int32_t flags;     // LEAF_LAST: holds the terminal cost; LEAF_TOP: whole problem
     int32_t slot;      // level-1 slot: receives its reduced form (up), holds the
                        // parent's solution for it (down)
-    int32_t pad;
+    int32_t m1;        // receding-horizon plans: M1 cache block of an interior leaf (-1: none)
     int64_t scratch;   // element offset of its per-stage factor storage
 };
-enum { LEAF_LAST = 1, LEAF_TOP = 2 };
+// LEAF_REUSE: its stored factorization and reduced form (M1 cache) are
+// current; the factorization pass only copies the cached M1 into its slot.
+enum { LEAF_LAST = 1, LEAF_TOP = 2, LEAF_REUSE = 4 };
 
 // One master-level work item of the tree (Alg. 5 reduce / Alg. 6 solve).
 struct TreeItem {
@@ -145,6 +147,9 @@ struct GroupArgs {
     void *lbw;
     int64_t lbw_unit;
     int32_t nx, nu;
+    // receding-horizon plans: per interior ring block, the matrix part of the
+    // leaf's M1 message (A_hat | Q_w_hat | Q_x_hat, 3 n^2 doubles)
+    double *m1cache;
 };
 
 }  // namespace rs

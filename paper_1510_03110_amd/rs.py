@@ -62,6 +62,7 @@ def library():
         i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         lib.rs_plan_create.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(rs_options), ctypes.POINTER(_P)]
         lib.rs_plan_create_ex.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(rs_options), ctypes.POINTER(_P)]
+        lib.rs_plan_create_ring.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(rs_options), ctypes.POINTER(_P)]
         lib.rs_graph_create.argtypes = [_P, i32, ctypes.POINTER(rs_problem), _P, sz, _P, _P, ctypes.POINTER(_P)]
         lib.rs_graph_launch.argtypes = [_P, _P]
         lib.rs_graph_destroy.argtypes = [_P]
@@ -81,7 +82,8 @@ def library():
         lib.rs_refine_stats.restype = i32
         lib.rs_status_string.argtypes = [i32]
         lib.rs_status_string.restype = ctypes.c_char_p
-        for name in ("rs_plan_create", "rs_plan_create_ex", "rs_plan_workspace_size", "rs_plan_destroy",
+        for name in ("rs_plan_create", "rs_plan_create_ex", "rs_plan_create_ring", "rs_plan_workspace_size",
+                     "rs_plan_destroy",
                      "rs_batch_solve", "rs_factor", "rs_solve", "rs_graph_create", "rs_graph_launch",
                      "rs_graph_destroy"):
             getattr(lib, name).restype = i32
@@ -111,6 +113,28 @@ def rs_plan_create(dims, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.
     st = fn(arr.shape[0], arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(opt), ctypes.byref(h))
     _check(st, "rs_plan_create")
     return h
+
+
+def rs_plan_create_ring(dims8, precision=RS_FP64, max_refine=0, tol=0.0):
+    """Receding-horizon plan: dims8 rows (nx, nu, N, Ns, branch, start,
+    reuse_lo, reuse_hi); see ring_current_leaves for the reuse range a call
+    leaves behind."""
+    arr = np.ascontiguousarray(np.asarray(dims8, dtype=np.int32).reshape(-1, 8))
+    opt = rs_options(precision, 0, 0, max_refine, tol, 0, 0)
+    h = _P()
+    st = library().rs_plan_create_ring(arr.shape[0], arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       ctypes.byref(opt), ctypes.byref(h))
+    _check(st, "rs_plan_create_ring")
+    return h
+
+
+def ring_current_leaves(start, N, Ns):
+    """Absolute interior leaves [lo, hi) whose stored factorization a
+    receding-horizon call with window start `start` leaves current."""
+    first_end = (start // Ns + (1 if start % Ns == 0 else 2)) * Ns
+    if start + N <= first_end:
+        return 0, 0
+    return first_end // Ns, (start + N - 1) // Ns
 
 
 def rs_plan_workspace_size(plan):

@@ -249,3 +249,43 @@ def test_large_block_shapes_plan_factored():
         with pytest.raises(rs.RsError) as e:
             rs.rs_plan_create([dims], Ns=16)
         assert e.value.status == rs.RS_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("N,Ns", [(200, 16), (37, 8), (64, 16), (20, 16)])
+def test_receding_horizon_plan_layout(N, Ns):
+    """Receding-horizon plans: leaves on absolute multiples of Ns (first leaf
+    at least Ns stages, last leaf ends with the window), the reuse range
+    marks exactly the interior leaves an earlier window left current, each
+    interior leaf keeps its record offset across windows, and the workspace
+    size does not depend on the window position."""
+    nx, nu = 32, 16
+    sizes, where = set(), {}
+    prev = (0, 0)
+    for start in list(range(0, 40)) + [1000, 1001]:
+        lo, hi = prev
+        p = rs.rs_plan_create_ring([(nx, nu, N, Ns, 4, start, lo, hi)])
+        try:
+            sizes.add(rs.rs_plan_workspace_size(p))
+            leaves = rs.rs_plan_export(p, 0)      # inst, t0, len, flags, slot, scratch, group
+        finally:
+            rs.rs_plan_destroy(p)
+        assert int(leaves[:, 2].sum()) == N and leaves[0, 1] == 0
+        assert np.all(leaves[1:, 1] == np.cumsum(leaves[:-1, 2]))
+        if len(leaves) == 1:
+            assert leaves[0, 3] == 3                       # LEAF_LAST | LEAF_TOP
+        else:
+            assert Ns <= leaves[0, 2] < 2 * Ns and leaves[0, 3] == 0
+            assert leaves[-1, 3] == 1 and (start + leaves[-1, 1]) % Ns == 0 and 1 <= leaves[-1, 2] <= Ns
+            for lf in leaves[1:-1]:
+                a = (start + int(lf[1])) // Ns
+                assert (start + int(lf[1])) % Ns == 0 and lf[2] == Ns
+                assert bool(lf[3] & 4) == (lo <= a < hi)
+                if a in where:
+                    assert where[a] == lf[5]                  # same record offset
+                where[a] = lf[5]
+            cur = rs.ring_current_leaves(start, N, Ns)
+            assert cur == ((start + int(leaves[1, 1])) // Ns, (start + int(leaves[-1, 1])) // Ns)
+        prev = rs.ring_current_leaves(start, N, Ns)
+        if start == 39:
+            prev = (0, 0)                                  # a jump: nothing current
+    assert len(sizes) == 1
