@@ -168,6 +168,18 @@ rs_status rs_plan_create_ex(int32_t count, const int32_t *dims5, const rs_option
 rs_status rs_plan_create_ring(int32_t count, const int32_t *dims8, const rs_options *opt,
                               rs_plan *plan_out);
 
+/*
+ * Move a receding-horizon plan to new window positions and reuse ranges
+ * (dims8 as for rs_plan_create_ring, with the same (nx, nu, N, Ns, branch)
+ * rows): its tables are rebuilt on the host and uploaded by the next call;
+ * pinned buffers, events and the bound workspace are kept, so a serving loop
+ * neither allocates nor frees host memory per request.  Must not be called
+ * while a call on the plan is still to be queued by another thread.
+ * Errors: RS_ERR_ARG (not a receding-horizon plan, or rows whose shapes,
+ * horizons or leaf lengths differ from the plan's), as rs_plan_create_ring.
+ */
+rs_status rs_plan_ring_update(rs_plan plan, const int32_t *dims8);
+
 /* Device workspace bytes the plan needs (caller allocates, 256-byte aligned). */
 rs_status rs_plan_workspace_size(rs_plan plan, size_t *bytes);
 

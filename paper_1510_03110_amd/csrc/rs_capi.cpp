@@ -52,6 +52,9 @@ struct rs_plan_s {
     bool mixed = false;             // FP32 leaf factorization + FP64 refinement
     bool via_factor = false;        // FP64 solve = stored factorization + solve (large-block shapes)
     bool receding = false;          // receding-horizon layout (rs_plan_create_ring)
+    rs_options opt{};               // options the plan was made with
+    bool tables_dirty = false;      // host tables changed since the last upload
+    hipEvent_t tables_ev = nullptr; // completion of the last table upload
     std::vector<int64_t> inst_start, inst_lo, inst_hi;
     int32_t total_leaves = 0;
     std::vector<InstInfo> inst;     // per instance: leaf range (refinement reductions)
@@ -322,6 +325,7 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         P->max_refine = opt->max_refine > 0 ? opt->max_refine : 5;
         if (opt->tol > 0) P->tol = opt->tol;
     }
+    if (opt) P->opt = *opt;
     P->top_max = P->branch;
     P->count = count;
     P->dims.resize(3 * (size_t)count);
@@ -540,6 +544,38 @@ rs_status rs_plan_create_ring(int32_t count, const int32_t *dims8, const rs_opti
     return plan_create(count, dims8, 8, opt, out);
 }
 
+rs_status rs_plan_ring_update(rs_plan P, const int32_t *dims8) {
+    if (!P || !P->receding || !dims8) return RS_ERR_ARG;
+    rs_plan Q = nullptr;
+    rs_status s = plan_create(P->count, dims8, 8, &P->opt, &Q);
+    if (s != RS_OK) return s;
+    // the instance list and every workspace offset must be unchanged
+    bool same = Q->total == P->total && Q->dims == P->dims && Q->groups.size() == P->groups.size() &&
+                Q->off_tables == P->off_tables && Q->tables_bytes == P->tables_bytes;
+    for (size_t i = 0; same && i < P->groups.size(); ++i) {
+        const Group &a = P->groups[i], &b = Q->groups[i];
+        same = a.nx == b.nx && a.nu == b.nu && a.off_fstore == b.off_fstore && a.off_m1 == b.off_m1 &&
+               a.off_slots == b.off_slots && a.off_flags == b.off_flags && a.off_lbw == b.off_lbw &&
+               a.insts == b.insts;
+    }
+    if (!same) {
+        rs_plan_destroy(Q);
+        return RS_ERR_ARG;
+    }
+    // new leaves, tree items and instance tables; pinned buffers, events and
+    // the bound workspace (with its stored factorization) stay
+    std::swap(P->groups, Q->groups);
+    std::swap(P->inst, Q->inst);
+    std::swap(P->tables, Q->tables);
+    std::swap(P->inst_start, Q->inst_start);
+    std::swap(P->inst_lo, Q->inst_lo);
+    std::swap(P->inst_hi, Q->inst_hi);
+    P->total_leaves = Q->total_leaves;
+    P->tables_dirty = true;
+    rs_plan_destroy(Q);
+    return RS_OK;
+}
+
 rs_status rs_plan_workspace_size(rs_plan P, size_t *bytes) {
     if (!P || !bytes) return RS_ERR_ARG;
     *bytes = P->total;
@@ -556,6 +592,10 @@ rs_status rs_plan_destroy(rs_plan P) {
         if (P->pinned_probs[i]) (void)hipHostFree(P->pinned_probs[i]);
     }
     if (P->pinned_tables) (void)hipHostFree(P->pinned_tables);
+    if (P->tables_ev) {
+        (void)hipEventSynchronize(P->tables_ev);
+        (void)hipEventDestroy(P->tables_ev);
+    }
     for (auto &r : P->recs) {
         (void)hipEventSynchronize(r.b);
         P->pool.push_back(r.a);
@@ -661,15 +701,20 @@ static rs_status bind_and_upload(rs_plan P, const rs_problem *probs, char *work,
     }
     const size_t nprob = dp.size();
     const bool rebind = P->bound_work != work;
-    if (rebind) {
-        if (!P->pinned_tables && P->tables_bytes) {
+    if ((rebind || P->tables_dirty) && P->tables_bytes) {
+        if (!P->pinned_tables) {
             if (hipHostMalloc(&P->pinned_tables, P->tables_bytes) != hipSuccess) return RS_ERR_HIP;
-            std::memcpy(P->pinned_tables, P->tables.data(), P->tables_bytes);
+            if (hipEventCreateWithFlags(&P->tables_ev, hipEventDisableTiming) != hipSuccess) return RS_ERR_HIP;
+        } else if (hipEventSynchronize(P->tables_ev) != hipSuccess) {   // the last upload has read it
+            return RS_ERR_HIP;
         }
-        if (P->tables_bytes) {
-            e = hipMemcpyAsync(work + P->off_tables, P->pinned_tables, P->tables_bytes, hipMemcpyHostToDevice, st);
-            if (e != hipSuccess) return RS_ERR_HIP;
-        }
+        std::memcpy(P->pinned_tables, P->tables.data(), P->tables_bytes);
+        e = hipMemcpyAsync(work + P->off_tables, P->pinned_tables, P->tables_bytes, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return RS_ERR_HIP;
+        if (hipEventRecord(P->tables_ev, st) != hipSuccess) return RS_ERR_HIP;
+        P->tables_dirty = false;
+    }
+    if (rebind) {
         for (auto &g : P->groups) {
             e = launch_fill_i32(reinterpret_cast<int32_t *>(work + g.off_flags),
                                 (int64_t)std::max<size_t>(1, g.items.size()), 0, st);

@@ -420,6 +420,10 @@ const ShapeEntry *find_shape(int nx, int nu) {
     }
     e.refine[0] = large_refine(0);
     e.refine[1] = large_refine(1);
+    if (mfma_factor_leaf32(nx, nu, 0)) {
+        e.factor[1][0] = mfma_factor_leaf32(nx, nu, 0);
+        e.factor[1][2] = mfma_factor_leaf32(nx, nu, 2);
+    }
     e.scratch_per_stage = 1;      // leaf stage index = scratch offset
     return &large.emplace(std::make_pair(nx, nu), e).first->second;
 }

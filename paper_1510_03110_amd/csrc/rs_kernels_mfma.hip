@@ -775,6 +775,18 @@ Launcher mfma_factor(int nx, int nu, int which, bool fp32) {
     return nullptr;
 }
 
+// FP32 leaf factorization of the state dimension 64 (mixed precision): the
+// FP32 working set of a stage fits in LDS while the FP64 one does not, so
+// the leaves run on the matrix-core engine and the master levels and vector
+// passes of these shapes on the large-block kernels (same record layouts).
+Launcher mfma_factor_leaf32(int nx, int nu, int which) {
+    if (nx == 64 && nu == 32)
+        return which == 0 ? &mf::launch_factor_leaf_up<float, 64, 32> : &mf::launch_factor_leaf_down<float, 64, 32>;
+    if (nx == 64 && nu == 16)
+        return which == 0 ? &mf::launch_factor_leaf_up<float, 64, 16> : &mf::launch_factor_leaf_down<float, 64, 16>;
+    return nullptr;
+}
+
 // MFMA launchers for the shapes that have them (nullptr: use the generic kernel).
 Launcher mfma_leaf_up(int nx, int nu) {
     if (nx == 16 && nu == 16) return &mf::launch_leaf_up_m<16, 16>;

@@ -54,6 +54,7 @@ size_t large_unit_bytes(int nx, int nu);
 Launcher large_factor(int which, bool fp32);
 Launcher large_vector(int which, bool fp32);
 Launcher large_refine(int which);
+Launcher mfma_factor_leaf32(int nx, int nu, int which);   // FP32 leaves of n_x = 64 (which 0 up, 2 down)
 
 const ShapeEntry *find_shape(int nx, int nu);
 hipError_t launch_init(int32_t *info, int count, int32_t *queues, int nq, hipStream_t st);

@@ -63,6 +63,7 @@ def library():
         lib.rs_plan_create.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(rs_options), ctypes.POINTER(_P)]
         lib.rs_plan_create_ex.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(rs_options), ctypes.POINTER(_P)]
         lib.rs_plan_create_ring.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(rs_options), ctypes.POINTER(_P)]
+        lib.rs_plan_ring_update.argtypes = [_P, ctypes.POINTER(i32)]
         lib.rs_graph_create.argtypes = [_P, i32, ctypes.POINTER(rs_problem), _P, sz, _P, _P, ctypes.POINTER(_P)]
         lib.rs_graph_launch.argtypes = [_P, _P]
         lib.rs_graph_destroy.argtypes = [_P]
@@ -82,7 +83,8 @@ def library():
         lib.rs_refine_stats.restype = i32
         lib.rs_status_string.argtypes = [i32]
         lib.rs_status_string.restype = ctypes.c_char_p
-        for name in ("rs_plan_create", "rs_plan_create_ex", "rs_plan_create_ring", "rs_plan_workspace_size",
+        for name in ("rs_plan_create", "rs_plan_create_ex", "rs_plan_create_ring", "rs_plan_ring_update",
+                     "rs_plan_workspace_size",
                      "rs_plan_destroy",
                      "rs_batch_solve", "rs_factor", "rs_solve", "rs_graph_create", "rs_graph_launch",
                      "rs_graph_destroy"):
@@ -126,6 +128,13 @@ def rs_plan_create_ring(dims8, precision=RS_FP64, max_refine=0, tol=0.0):
                                        ctypes.byref(opt), ctypes.byref(h))
     _check(st, "rs_plan_create_ring")
     return h
+
+
+def rs_plan_ring_update(plan, dims8):
+    """New window positions / reuse ranges for a receding-horizon plan."""
+    arr = np.ascontiguousarray(np.asarray(dims8, dtype=np.int32).reshape(-1, 8))
+    _check(library().rs_plan_ring_update(plan, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+           "rs_plan_ring_update")
 
 
 def ring_current_leaves(start, N, Ns):

@@ -16,18 +16,26 @@ surviving records are moved to the front with one device copy, so the cost
 per request stays one record on average.
 
 Continuous batching.  The engine keeps a small number of lanes (a stream, a
-plan over all sessions, a workspace and a status array each).  A launch on a
-lane solves the sessions whose request is ready; every other session carries
-RS_PROB_SKIP for that call, so the plan never has to be rebuilt for a new
-mix and each instance's tree depends only on itself (results are the same
-alone and in any mix).  While one lane's launch runs, newly ready sessions
-go to the next idle lane, so their work overlaps on the device.  A session
-has at most one request in flight (its next window needs this solution's
-x_1); later requests for it wait in its queue.
+workspace and a status array each); every session belongs to one lane.  A
+launch on a lane solves the lane's sessions whose request is ready; every
+other session of the lane carries RS_PROB_SKIP for that call, and each
+instance's tree depends only on itself (results are the same alone and in
+any mix).  While one lane's launch runs, newly ready sessions of the other
+lanes start on their streams, so their work overlaps on the device.  A
+session has at most one request in flight (its next window needs this
+solution's x_1); later requests for it wait in its queue.
+
+Factorizations across shifts.  Each launch uses a receding-horizon plan
+(rs_plan_create_ring): leaf boundaries sit on absolute stage indices, so a
+one-stage shift changes only the window's first and last leaves.  The
+interior leaves keep their stored factorization (Alg. 4 records and reduced
+form) in the lane's workspace from the session's previous request and are
+not factored again; the master levels, the vector passes and the leaf
+solves run in full.
 
 Admission.  A session is admitted only while the projected HBM footprint of
 all admitted sessions (window buffers, solution arrays and their share of
-every lane's workspace) stays within a fraction (0.9) of the device memory
+their lane's workspace) stays within a fraction (0.9) of the device memory
 that is not already in use when the engine starts.
 
 Latency is measured from a request's arrival (its scheduled time in the
@@ -115,6 +123,9 @@ class Session:
         self.solved = False
         self.busy = False
         self.queue = deque()
+        self.t_abs = 0            # absolute index of the window's first stage
+        self.current = (0, 0)     # interior leaves whose stored factorization is current
+        self.lane = 0
 
     def footprint(self):
         return 8 * (self.cap * self.E + 2 * (self.N + 1) * self.nx + self.N * self.nu + self.nx * self.nx
@@ -132,6 +143,7 @@ class Session:
             self.staging.numpy()[:] = record
             self.ring[self.start + self.N].copy_(self.staging, non_blocking=True)
             self.start += 1
+            self.t_abs += 1
             if self.solved:
                 self.x0.copy_(self.x[1])
 
@@ -168,6 +180,7 @@ class Lane:
         import torch
         self.stream = torch.cuda.Stream(device=device)
         self.plan = None
+        self.sessions = []        # sessions served by this lane (instance order of its plans)
         self.version = -1
         self.work = None
         self.work_ptr = 0
@@ -182,7 +195,7 @@ class ServingEngine:
     """Continuous-batching solver for receding-horizon sessions."""
 
     def __init__(self, precision=rs.RS_FP64, lanes=2, max_batch=1 << 30, hbm_fraction=0.9, tuner=None,
-                 device="cuda", record=False):
+                 device="cuda", record=False, timing=False):
         import torch
         self.torch = torch
         self.device = device
@@ -202,11 +215,14 @@ class ServingEngine:
         self.results = {}
         self.launches = 0
         self.batch_sizes = []
+        self.timing = timing          # per-kernel-kind device time of every launch (HIP events)
+        self.kernel_ms = {}
+        self.host_s = 0.0             # host time spent preparing launches
 
     # ------------------------------------------------------------ admission
     def _workspace_per_instance(self, nx, nu, N):
         Ns, br = self.tuner.choose(nx, nu, N, self.precision)
-        plan = rs.rs_plan_create([(nx, nu, N, Ns, br)], precision=self.precision)
+        plan = rs.rs_plan_create_ring([(nx, nu, N, Ns, br, 0, 0, 0)], precision=self.precision)
         try:
             return rs.rs_plan_workspace_size(plan)
         finally:
@@ -220,34 +236,46 @@ class ServingEngine:
         except rs.RsError:          # no kernel for this shape and precision
             self.rejected += 1
             return None
-        need = 8 * (2 * N * record_len(nx, nu) + 2 * (N + 1) * nx + N * nu) + len(self.lanes) * ws
+        need = 8 * (2 * N * record_len(nx, nu) + 2 * (N + 1) * nx + N * nu) + ws
         if self.used + need > self.budget:
             self.rejected += 1
             return None
         s = Session(len(self.sessions), prob, self.device)
+        # a session always runs on the same lane, whose workspace keeps its
+        # stored factorization between requests
+        s.lane = s.sid % len(self.lanes)
+        self.lanes[s.lane].sessions.append(s)
         self.sessions.append(s)
         self.used += need
         self.version += 1
         return s.sid
 
     # --------------------------------------------------------------- plans
-    def _ensure_plan(self, lane):
+    def _dims(self, lane):
+        """Receding-horizon plan rows of the lane's sessions: window start and
+        the interior leaves whose factorization the last request left."""
+        rows = []
+        for s in lane.sessions:
+            Ns, br = self.tuner.choose(s.nx, s.nu, s.N, self.precision)
+            rows.append((s.nx, s.nu, s.N, Ns, br, s.t_abs) + tuple(s.current))
+        return rows
+
+    def _ensure_workspace(self, lane):
         if lane.version == self.version:
             return
         torch = self.torch
         if lane.plan is not None:
             rs.rs_plan_destroy(lane.plan)
-        dims = [(s.nx, s.nu, s.N) + tuple(self.tuner.choose(s.nx, s.nu, s.N, self.precision))
-                for s in self.sessions]
-        lane.plan = rs.rs_plan_create(dims, precision=self.precision)
+        lane.plan = rs.rs_plan_create_ring(self._dims(lane), precision=self.precision)
         lane.work_bytes = rs.rs_plan_workspace_size(lane.plan)
         lane.work = torch.empty(lane.work_bytes + 256, dtype=torch.uint8, device=self.device)
         lane.work_ptr = (lane.work.data_ptr() + 255) // 256 * 256
-        lane.info = torch.zeros(2 * len(self.sessions), dtype=torch.int32, device=self.device)
-        lane.probs = (rs.rs_problem * len(self.sessions))()
-        for s in self.sessions:
-            s.fill_descriptor(lane.probs[s.sid])
-            lane.probs[s.sid].flags = rs.RS_PROB_SKIP
+        lane.info = torch.zeros(2 * len(lane.sessions), dtype=torch.int32, device=self.device)
+        lane.probs = (rs.rs_problem * len(lane.sessions))()
+        for i, s in enumerate(lane.sessions):
+            s.fill_descriptor(lane.probs[i])
+            lane.probs[i].flags = rs.RS_PROB_SKIP
+            s.current = (0, 0)         # a new workspace holds no factors yet
         lane.version = self.version
 
     # ------------------------------------------------------------ requests
@@ -256,26 +284,43 @@ class ServingEngine:
 
     def _launch(self, lane, ready):
         torch = self.torch
-        self._ensure_plan(lane)
-        for s in self.sessions:
-            lane.probs[s.sid].flags = rs.RS_PROB_SKIP
+        h0 = time.perf_counter()
+        self._ensure_workspace(lane)
+        idx = {id(s): i for i, s in enumerate(lane.sessions)}
+        for i in range(len(lane.sessions)):
+            lane.probs[i].flags = rs.RS_PROB_SKIP
         lane.members = []
         for s in ready:
             record, arrival = s.queue.popleft()
             s.busy = True
             s.shift(record, lane.stream)
-            s.fill_descriptor(lane.probs[s.sid])
-            lane.probs[s.sid].flags = 0
+            i = idx[id(s)]
+            s.fill_descriptor(lane.probs[i])
+            lane.probs[i].flags = 0
             lane.members.append((s, arrival))
+        # the lane's receding-horizon plan moved to this launch's windows: the
+        # leaves whose stage data the shifts left unchanged keep their stored
+        # factorization
+        rs.rs_plan_ring_update(lane.plan, self._dims(lane))
+        if self.timing:
+            rs.rs_plan_set_timing(lane.plan, True)
         rs.rs_batch_solve(lane.plan, lane.probs, lane.work_ptr, lane.work_bytes, lane.stream.cuda_stream,
                           lane.info.data_ptr())
+        for s, _ in lane.members:
+            Ns, _br = self.tuner.choose(s.nx, s.nu, s.N, self.precision)
+            s.current = rs.ring_current_leaves(s.t_abs, s.N, Ns)
         self.launches += 1
         self.batch_sizes.append(len(ready))
         lane.event = torch.cuda.Event()
         lane.event.record(lane.stream)
+        self.host_s += time.perf_counter() - h0
 
     def _complete(self, lane, now):
         st = None
+        if self.timing:
+            for k, (ms, n) in rs.rs_plan_kernel_times(lane.plan, reset=True).items():
+                if n:
+                    self.kernel_ms[k] = self.kernel_ms.get(k, 0.0) + ms
         for s, arrival in lane.members:
             s.busy = False
             s.solved = True
@@ -284,9 +329,10 @@ class ServingEngine:
             if self.record:
                 if st is None:
                     st = lane.info.view(-1, 2).cpu().numpy()
+                i = lane.sessions.index(s)
                 self.results.setdefault(s.sid, []).append(
                     dict(x=s.x.cpu().numpy(), w=s.w.cpu().numpy(), lam=s.lam.cpu().numpy(),
-                         obj=float(s.obj.cpu()[0]), status=int(st[s.sid, 0]), window=s.window_host()))
+                         obj=float(s.obj.cpu()[0]), status=int(st[i, 0]), window=s.window_host()))
         lane.members = []
         lane.event = None
 
@@ -298,10 +344,9 @@ class ServingEngine:
         for lane in self.lanes:
             if lane.event is not None:
                 continue
-            ready = [s for s in self.sessions if not s.busy and s.queue][:self.max_batch]
-            if not ready:
-                break
-            self._launch(lane, ready)
+            ready = [s for s in lane.sessions if not s.busy and s.queue][:self.max_batch]
+            if ready:
+                self._launch(lane, ready)
 
     def busy(self):
         return any(l.event is not None for l in self.lanes) or any(s.queue for s in self.sessions)
@@ -329,7 +374,9 @@ class ServingEngine:
                 "launches": self.launches - launches0,
                 "mean_batch": round(float(np.mean(sizes)), 2) if sizes else None,
                 "sessions": len(self.sessions), "rejected_sessions": self.rejected,
-                "hbm_projected_gb": round(self.used / 1e9, 3), "hbm_budget_gb": round(self.budget / 1e9, 3)}
+                "hbm_projected_gb": round(self.used / 1e9, 3), "hbm_budget_gb": round(self.budget / 1e9, 3),
+                "host_launch_s": round(self.host_s, 3),
+                "kernel_ms_total": {k: round(v, 1) for k, v in self.kernel_ms.items()} if self.timing else None}
 
     def close(self):
         for lane in self.lanes:
@@ -339,6 +386,21 @@ class ServingEngine:
 
 
 # --------------------------------------------------------- synthetic stream
+class FixedChoice(Tuner):
+    """The same leaf length (raised until the shape allows it) and branch
+    for every session."""
+
+    def __init__(self, Ns, branch):
+        super().__init__("/nonexistent/fixed-choice.json")
+        self.fixed = (Ns, branch if branch > 0 else 4)
+
+    def choose(self, nx, nu, N, precision):
+        Ns, br = self.fixed
+        while Ns * nu < nx:
+            Ns *= 2
+        return Ns, br
+
+
 def poisson_trace(rate, seconds, nsessions, pools, session_shapes, seed):
     """Arrival times of a Poisson process (exponential gaps) with a uniformly
     chosen session per request; the new stage record is drawn from the
@@ -377,12 +439,16 @@ def main(argv=None):
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="mixed")
     ap.add_argument("--lanes", type=int, default=2)
     ap.add_argument("--seed", type=int, default=W.seed_for(3))
+    ap.add_argument("--timing", action="store_true", help="report device time per kernel kind")
+XX
+    ap.add_argument("--branch", type=int, default=0, help="master branch for every session (0: the tuner's)")
     args = ap.parse_args(argv)
     import torch
     rng = np.random.default_rng(args.seed)
     nxs = [int(v) for v in args.nx.split(",")]
     prec = rs.RS_FP64 if args.precision == "fp64" else rs.RS_MIXED_FP32
-    eng = ServingEngine(precision=prec, lanes=args.lanes)
+    tuner = FixedChoice(args.Ns, args.branch) if args.Ns > 0 else None
+    eng = ServingEngine(precision=prec, lanes=args.lanes, timing=args.timing, tuner=tuner)
     shapes = []
     for i in range(args.sessions):
         nx = nxs[int(rng.integers(0, len(nxs)))]
@@ -396,7 +462,7 @@ def main(argv=None):
     warm = poisson_trace(args.rate, args.warmup_seconds, len(shapes), pools, shapes, args.seed + 1)
     eng.run(warm)
     torch.cuda.synchronize()
-    eng.lat, eng.done = [], 0
+    eng.lat, eng.done, eng.kernel_ms, eng.host_s = [], 0, {}, 0.0
     trace = poisson_trace(args.rate, args.seconds, len(shapes), pools, shapes, args.seed + 2)
     out = eng.run(trace)
     out.update({"rate_req_s": args.rate, "precision": args.precision,

@@ -77,18 +77,21 @@ def test_receding_horizon_reuse(prec, nx, nu, N, Ns):
     torch, rs = _rs()
     K = 2 * Ns + 3
     seq = _Seq(torch, rs, W.with_costs(W.g2(nx, nu, N + K, seed=nx + N + prec), seed=3), N)
-    size = None
-    work = fresh = None
     lo, hi = 0, 0
+    # one plan moved along the sequence (odd instantiations: a new plan per
+    # window on the same workspace); both keep the stored factorization
+    keep = rs.rs_plan_create_ring([(nx, nu, N, Ns, 4, 0, 0, 0)], precision=prec)
+    size = rs.rs_plan_workspace_size(keep)
+    work = torch.empty(size + 256, dtype=torch.uint8, device="cuda")
+    fresh = torch.empty(size + 256, dtype=torch.uint8, device="cuda")
     for s in range(K):
-        plan = rs.rs_plan_create_ring([(nx, nu, N, Ns, 4, s, lo, hi)], precision=prec)
+        if s % 2 == 0:
+            rs.rs_plan_ring_update(keep, [(nx, nu, N, Ns, 4, s, lo, hi)])
+            plan = keep
+        else:
+            plan = rs.rs_plan_create_ring([(nx, nu, N, Ns, 4, s, lo, hi)], precision=prec)
         try:
-            b = rs.rs_plan_workspace_size(plan)
-            if size is None:
-                size = b
-                work = torch.empty(b + 256, dtype=torch.uint8, device="cuda")
-                fresh = torch.empty(b + 256, dtype=torch.uint8, device="cuda")
-            assert b == size
+            assert rs.rs_plan_workspace_size(plan) == size
             out = seq.outputs()
             assert _solve(rs, torch, seq, plan, work, s, out) == 0
             win = seq.window(s)
@@ -98,7 +101,8 @@ def test_receding_horizon_reuse(prec, nx, nu, N, Ns):
             assert kkt.rel_error(sol, ref) <= TOL
             assert abs(sol["obj"] - ref["obj"]) <= 1e-9 * max(1.0, abs(ref["obj"]))
         finally:
-            rs.rs_plan_destroy(plan)
+            if plan is not keep:
+                rs.rs_plan_destroy(plan)
         if s % 4 == 3 or s == K - 1:
             # the same window factored from scratch on a fresh workspace
             plan = rs.rs_plan_create_ring([(nx, nu, N, Ns, 4, s, 0, 0)], precision=prec)
@@ -111,3 +115,4 @@ def test_receding_horizon_reuse(prec, nx, nu, N, Ns):
             finally:
                 rs.rs_plan_destroy(plan)
         lo, hi = rs.ring_current_leaves(s, N, Ns)
+    rs.rs_plan_destroy(keep)

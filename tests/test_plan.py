@@ -289,3 +289,29 @@ def test_receding_horizon_plan_layout(N, Ns):
         if start == 39:
             prev = (0, 0)                                  # a jump: nothing current
     assert len(sizes) == 1
+
+
+def test_receding_horizon_plan_update_checks_layout():
+    """rs_plan_ring_update moves a receding-horizon plan to new window
+    positions; rows with another horizon or leaf length, or a plan of
+    another kind, are argument errors."""
+    rows = [(32, 16, 100, 8, 4, 0, 0, 0), (16, 8, 60, 8, 4, 3, 0, 0)]
+    p = rs.rs_plan_create_ring(rows)
+    q = rs.rs_plan_create([(32, 16, 100)])
+    try:
+        size = rs.rs_plan_workspace_size(p)
+        rs.rs_plan_ring_update(p, [(32, 16, 100, 8, 4, 7, 1, 5), (16, 8, 60, 8, 4, 9, 0, 0)])
+        assert rs.rs_plan_workspace_size(p) == size
+        leaves = rs.rs_plan_export(p, 0)
+        assert leaves[0, 2] == 9                        # first leaf of the window at 7: [7, 16)
+        for bad in ([(32, 16, 101, 8, 4, 7, 0, 0), (16, 8, 60, 8, 4, 9, 0, 0)],
+                    [(32, 16, 100, 16, 4, 7, 0, 0), (16, 8, 60, 8, 4, 9, 0, 0)]):
+            with pytest.raises(rs.RsError) as e:
+                rs.rs_plan_ring_update(p, bad)
+            assert e.value.status == rs.RS_ERR_ARG
+        with pytest.raises(rs.RsError) as e:
+            rs.rs_plan_ring_update(q, rows)
+        assert e.value.status == rs.RS_ERR_ARG
+    finally:
+        rs.rs_plan_destroy(p)
+        rs.rs_plan_destroy(q)
