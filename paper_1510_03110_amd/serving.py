@@ -440,8 +440,8 @@ def main(argv=None):
     ap.add_argument("--lanes", type=int, default=2)
     ap.add_argument("--seed", type=int, default=W.seed_for(3))
     ap.add_argument("--timing", action="store_true", help="report device time per kernel kind")
-XX
-    ap.add_argument("--branch", type=int, default=0, help="master branch for every session (0: the tuner's)")
+    ap.add_argument("--Ns", type=int, default=32, help="leaf length for every session (0: the tuner's choice)")
+    ap.add_argument("--branch", type=int, default=8, help="master branch for every session (0: the tuner's)")
     args = ap.parse_args(argv)
     import torch
     rng = np.random.default_rng(args.seed)
