@@ -177,3 +177,45 @@ def test_batching_config_mixed_precision_sampled():
     for i in pick:
         _check(W.materialize(probs[i]), b.result(i))
     b.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_large_block_config_full_horizon(prec):
+    """The large-block configuration's single instance at full size:
+    n_x = 128, n_u = 64, N = 16384 (time-varying G2 data drawn on the device).
+    The serial oracle needs minutes here, so the check is the property that
+    holds at any size: the relative KKT residual of the returned solution,
+    evaluated by the oracle's blockwise residual in FP64, is <= 1e-10 (and
+    the mixed-precision solve reports convergence)."""
+    torch, rs = _rs()
+    data = W.g2_torch(128, 64, 16384, 1, seed=W.seed_for(4), device="cuda")
+    bt = rs.Batch(data, precision=prec, Ns=64, branch=8)
+    bt.solve()
+    torch.cuda.synchronize()
+    assert bt.status()[0, 0] == 0
+    sol = bt.result(0)
+    if prec == 1:
+        st = bt.refine_stats()[0]
+        assert st[3] == 1.0 and st[0] <= TOL
+    bt.close()
+    prob = W.instance_to_numpy(data, 0)
+    del data
+    torch.cuda.empty_cache()
+    assert kkt.rel_residual(prob, sol["x"], sol["w"], sol["lam"]) <= TOL
+
+
+def test_large_block_config_batch64_sampled():
+    """Batch of 64 instances of n_x = 128, n_u = 64 (the configuration's
+    batch; horizon 256 so that the oracle finishes in seconds), mixed
+    precision; sampled instances against the oracle."""
+    torch, rs = _rs()
+    data = W.g2_torch(128, 64, 256, 64, seed=W.seed_for(4, 1), device="cuda")
+    bt = rs.Batch(data, precision=rs.RS_MIXED_FP32, Ns=16, branch=4)
+    bt.solve()
+    torch.cuda.synchronize()
+    assert np.all(bt.status()[:, 0] == 0)
+    st = bt.refine_stats()
+    assert np.all(st[:, 3] == 1.0) and st[:, 0].max() <= TOL
+    for i in (0, 17, 63):
+        _check(W.instance_to_numpy(data, i), bt.result(i))
+    bt.close()
