@@ -64,8 +64,12 @@ typedef enum rs_status {
 
 typedef enum rs_precision {
     RS_FP64 = 0,        /* every step in FP64                                         */
-    RS_MIXED_FP32 = 1   /* leaf Riccati in FP32, master levels and the KKT residual
+    RS_MIXED_FP32 = 1,  /* leaf Riccati in FP32, master levels and the KKT residual
                            in FP64, iterative refinement to the requested tolerance  */
+    RS_MIXED_BF16 = 2   /* as RS_MIXED_FP32, with the products P [A B], A'PA, A'PB
+                           and B'PB of the leaf stages on BF16 matrix cores (FP32
+                           accumulation); shapes served by the large-block kernels
+                           only (RS_ERR_UNSUPPORTED otherwise); max_refine default 20 */
 } rs_precision;
 
 /* rs_problem.flags: the instance is left untouched by this call (its outputs

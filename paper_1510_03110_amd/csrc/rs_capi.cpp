@@ -50,6 +50,7 @@ struct rs_plan_s {
     int Ns = 16, branch = 4, top_max = 4, prec = RS_FP64, max_refine = 5;
     bool factored = false;          // workspace holds the stored factorization
     bool mixed = false;             // FP32 leaf factorization + FP64 refinement
+    bool bf16 = false;              // ... with BF16 matrix-core products in the leaf stages
     bool via_factor = false;        // FP64 solve = stored factorization + solve (large-block shapes)
     bool receding = false;          // receding-horizon layout (rs_plan_create_ring)
     rs_options opt{};               // options the plan was made with
@@ -313,16 +314,17 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
             delete P;
             return RS_ERR_ARG;
         }
-        if (opt->precision != RS_FP64 && opt->precision != RS_MIXED_FP32) {
+        if (opt->precision != RS_FP64 && opt->precision != RS_MIXED_FP32 && opt->precision != RS_MIXED_BF16) {
             delete P;
             return RS_ERR_UNSUPPORTED;
         }
         P->prec = opt->precision;
-        P->mixed = opt->precision == RS_MIXED_FP32;
+        P->mixed = opt->precision == RS_MIXED_FP32 || opt->precision == RS_MIXED_BF16;
+        P->bf16 = opt->precision == RS_MIXED_BF16;
         P->factored = P->mixed || (opt->flags & RS_PLAN_FACTORED) != 0;
         if (opt->Ns > 0) P->Ns = opt->Ns;
         if (opt->branch > 0) P->branch = opt->branch;
-        P->max_refine = opt->max_refine > 0 ? opt->max_refine : 5;
+        P->max_refine = opt->max_refine > 0 ? opt->max_refine : (P->bf16 ? 20 : 5);
         if (opt->tol > 0) P->tol = opt->tol;
     }
     if (opt) P->opt = *opt;
@@ -375,13 +377,13 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
             return RS_ERR_ARG;
         }
         const ShapeEntry *se = find_shape(nx, nu);
-        const int f32 = P->mixed ? 1 : 0;
+        const int f32 = P->mixed ? 1 : 0, fac = P->bf16 ? 2 : f32;
         if (se && se->large && !P->mixed) {
             // no fused kernels: the FP64 solve runs on the stored factorization
             P->factored = true;
             P->via_factor = true;
         }
-        if (!se || (P->factored && !(se->factor[f32][0] && se->vsolve[f32][0])) || (P->mixed && !se->refine[0])) {
+        if (!se || (P->factored && !(se->factor[fac][0] && se->vsolve[f32][0])) || (P->mixed && !se->refine[0])) {
             delete P;
             return RS_ERR_UNSUPPORTED;
         }
@@ -809,11 +811,11 @@ static rs_status launch_pass(rs_plan P, char *W, int32_t *info, hipStream_t st, 
     const int ninfo = keep_status ? 0 : P->count;
     hipError_t e = timed(P, KK_INIT, st, [&] { return launch_init(info, ninfo, queues, (int)P->groups.size(), st); });
     if (e != hipSuccess) return RS_ERR_HIP;
-    const int f32 = P->mixed ? 1 : 0;
+    const int f32 = P->mixed ? 1 : 0, fac = P->bf16 ? 2 : f32;
     for (size_t gi = 0; gi < P->groups.size(); ++gi) {
         Group &g = P->groups[gi];
         GroupArgs a = group_args(P, W, gi, info, corr, with_conv, iter);
-        const Launcher *L = pass == 0 ? g.shape->fp64 : pass == 1 ? g.shape->factor[f32] : g.shape->vsolve[f32];
+        const Launcher *L = pass == 0 ? g.shape->fp64 : pass == 1 ? g.shape->factor[fac] : g.shape->vsolve[f32];
         // the vector passes run one wavefront per work item
         const int cap = pass == 2 ? 1024 : 256;
         const int tree_grid = std::max(1, std::min<int>((int)g.items.size(), cap));

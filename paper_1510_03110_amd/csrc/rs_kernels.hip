@@ -375,6 +375,7 @@ const ShapeEntry *find_shape(int nx, int nu) {
                     e.factor[f][k] = mfma_factor(a, b, k, f == 1);
                     e.vsolve[f][k] = vector_solve(a, b, k, f == 1);
                 }
+            for (int k = 0; k < 3; ++k) e.factor[2][k] = nullptr;
             e.refine[0] = refine_kernel(a, b, 0);
             e.refine[1] = refine_kernel(a, b, 1);
             // no matrix-core form of the stored factorization: the large-block
@@ -386,6 +387,7 @@ const ShapeEntry *find_shape(int nx, int nu) {
                         e.factor[f][k] = large_factor(k, f == 1);
                         e.vsolve[f][k] = large_vector(k, f == 1);
                     }
+                for (int k = 0; k < 3; ++k) e.factor[2][k] = large_factor(k, true, true);
                 e.refine[0] = large_refine(0);
                 e.refine[1] = large_refine(1);
             }
@@ -417,6 +419,7 @@ const ShapeEntry *find_shape(int nx, int nu) {
             e.factor[f][k] = large_factor(k, f == 1);
             e.vsolve[f][k] = large_vector(k, f == 1);
         }
+        e.factor[2][k] = large_factor(k, true, true);
     }
     e.refine[0] = large_refine(0);
     e.refine[1] = large_refine(1);

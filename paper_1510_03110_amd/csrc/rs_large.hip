@@ -166,6 +166,64 @@ __device__ __forceinline__ void gemm(int M, int N, int K, const T *__restrict__ 
     }
 }
 
+// BF16 operands (round to nearest even of the FP32 value; finite inputs).
+__device__ __forceinline__ short to_bf16(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+// gemm with operands rounded to BF16 and FP32 accumulation
+// (v_mfma_f32_16x16x16_bf16: lane l holds A(l % 16, 4 (l / 16) + q) and
+// B(4 (l / 16) + q, l % 16), q = 0..3; the result layout is the FP32 one).
+template <bool TA, bool TB, class Epi>
+__device__ __forceinline__ void gemm_bf16(int M, int N, int K, const float *__restrict__ A, int lda,
+                                          const float *__restrict__ B, int ldb, bool lower, Epi epi) {
+    typedef short s4 __attribute__((ext_vector_type(4)));
+    const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
+    const int nt = lower ? tm * (tm + 1) / 2 : tm * tn;
+    const int l = lane(), r16 = l & 15, k4 = l >> 4;
+    for (int t = wave(); t < nt; t += NT / 64) {
+        int ti, tj;
+        if (lower) {
+            mf::lower_tile(t, ti, tj);
+        } else {
+            ti = t / tn;
+            tj = t - ti * tn;
+        }
+        const int i = 16 * ti + r16, j = 16 * tj + r16;
+        const bool iv = i < M, jv = j < N;
+        v4_t<float> acc = mf::zero4<float>();
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            s4 a, b;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = k0 + 4 * k4 + q;
+                const float av = (iv && k < K) ? (TA ? A[(int64_t)k * lda + i] : A[(int64_t)i * lda + k]) : 0.0f;
+                const float bv = (jv && k < K) ? (TB ? B[(int64_t)j * ldb + k] : B[(int64_t)k * ldb + j]) : 0.0f;
+                a[q] = to_bf16(av);
+                b[q] = to_bf16(bv);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ii = mf::trow<float>(ti, r), jj = mf::tcol(tj);
+            if (ii < M && jj < N) epi(ii, jj, acc[r]);
+        }
+    }
+}
+
+// The products of the stage that may run on BF16 operands.
+template <bool BF, bool TA, bool TB, class T, class Epi>
+__device__ __forceinline__ void gemm_big(int M, int N, int K, const T *A, int lda, const T *B, int ldb, bool lower,
+                                         Epi epi) {
+    if constexpr (BF)
+        gemm_bf16<TA, TB>(M, N, K, A, lda, B, ldb, lower, epi);
+    else
+        gemm<TA, TB>(M, N, K, A, lda, B, ldb, lower, epi);
+}
+
 // acc += opA(A) opB(B) for one 16 x 16 x 16 block with only the first ri
 // rows, rk inner indices and rj columns taken (the rest read as zero).
 // opA(i,k) = A[i*lda+k]; opB(k,j) = TB ? B[j*ldb+k] : B[k*ldb+j].
@@ -323,9 +381,11 @@ struct SlotOut {
 // Backward pass over `count` stages (local s = count-1 .. 0), matrix lines
 // only.  RED: Alg. 4 (state P, V, Q_w_hat in the workspace); otherwise Alg. 1
 // from the P in the workspace.  pre(s) runs before stage s and sees P_{s+1}.
-template <class T, bool RED, class Get, class Pre, class Out>
+// BF: P [A B], A'W_A, A'W_B and B'W_B (A'PA, A'PB, B'PB) on BF16 operands.
+template <class T, bool RED, bool BF, class Get, class Pre, class Out>
 __device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int stage_base, int fail_code, Pre pre,
                       const Out &out, int *bad) {
+    static_assert(!BF || sizeof(T) == 4, "BF16 products accumulate in FP32");
     const int n = S.n, m = S.m, nw = S.nw, tid = threadIdx.x;
     count = uni(count);
     for (int s = count - 1; s >= 0; --s) {
@@ -337,7 +397,8 @@ __device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int
         }
         __syncthreads();
         // W = P [A B]; Alg. 4: B'V, A'V
-        gemm<false, false>(n, nw, n, S.P, n, S.AB, nw, false, [&](int i, int j, T c) { S.W[(int64_t)i * nw + j] = c; });
+        gemm_big<BF, false, false>(n, nw, n, S.P, n, S.AB, nw, false,
+                                   [&](int i, int j, T c) { S.W[(int64_t)i * nw + j] = c; });
         if constexpr (RED) {
             gemm<true, false>(m, n, n, S.AB + n, nw, S.V, n, false,
                               [&](int i, int j, T c) { S.BV[(int64_t)i * n + j] = c; });
@@ -345,17 +406,17 @@ __device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int
         }
         __syncthreads();
         // F = Qx + A'W_A (symmetric), H = Qxw + A'W_B, G = Qw + B'W_B (symmetric)
-        gemm<true, false>(n, n, n, S.AB, nw, S.W, nw, true, [&](int i, int j, T c) {
+        gemm_big<BF, true, false>(n, n, n, S.AB, nw, S.W, nw, true, [&](int i, int j, T c) {
             if (i >= j) {
                 const T v = (T)src.Qx[(int64_t)i * n + j] + c;
                 S.F[(int64_t)i * n + j] = v;
                 S.F[(int64_t)j * n + i] = v;
             }
         });
-        gemm<true, false>(n, m, n, S.AB, nw, S.W + n, nw, false, [&](int i, int j, T c) {
+        gemm_big<BF, true, false>(n, m, n, S.AB, nw, S.W + n, nw, false, [&](int i, int j, T c) {
             S.H[(int64_t)i * m + j] = (src.Qxw ? (T)src.Qxw[(int64_t)i * m + j] : T(0)) + c;
         });
-        gemm<true, false>(m, m, n, S.AB + n, nw, S.W + n, nw, true, [&](int i, int j, T c) {
+        gemm_big<BF, true, false>(m, m, n, S.AB + n, nw, S.W + n, nw, true, [&](int i, int j, T c) {
             if (i >= j) {
                 const T v = (T)src.Qw[(int64_t)i * m + j] + c;
                 S.G[(int64_t)i * m + j] = v;
@@ -426,7 +487,7 @@ __device__ T *unit_ws(const GroupArgs &g) {
 }
 
 // ------------------------------------------------------------ matrix side
-template <class T>
+template <class T, bool BF>
 __global__ void __launch_bounds__(NT) kl_leaf_up(GroupArgs g) {
     __shared__ int bad;
     const int n = g.nx, m = g.nu, tid = threadIdx.x;
@@ -452,7 +513,7 @@ __global__ void __launch_bounds__(NT) kl_leaf_up(GroupArgs g) {
         const LeafOut<T> o{base, n, m, true};
         if (!(it.flags & LEAF_LAST)) {
             init_red(S);
-            mpass<T, true>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, o, &bad);
+            mpass<T, true, BF>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, o, &bad);
             for (int e = tid; e < n * n; e += NT) {
                 const int i = e / n, j = e % n;
                 const double a = (double)S.V[(int64_t)j * n + i], q = (double)S.Qh[e], x = (double)S.P[e];
@@ -468,14 +529,14 @@ __global__ void __launch_bounds__(NT) kl_leaf_up(GroupArgs g) {
         } else {
             for (int e = tid; e < n * n; e += NT) S.P[e] = (T)p.QxN[e];
             __syncthreads();
-            mpass<T, false>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, o, &bad);
+            mpass<T, false, BF>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, o, &bad);
             for (int e = tid; e < n * n; e += NT) out[SL.Qx() + e] = (double)S.P[e];
         }
         __syncthreads();
     }
 }
 
-template <class T>
+template <class T, bool BF>
 __global__ void __launch_bounds__(NT) kl_leaf_down(GroupArgs g) {
     __shared__ int bad;
     const int n = g.nx, m = g.nu, tid = threadIdx.x;
@@ -492,7 +553,8 @@ __global__ void __launch_bounds__(NT) kl_leaf_down(GroupArgs g) {
         for (int e = tid; e < n * n; e += NT) S.P[e] = (T)p.QxN[e];
         __syncthreads();
         auto get = [&](int s) { return leaf_stage(p, it.t0 + s); };
-        mpass<T, false>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, LeafOut<T>{base, n, m, false}, &bad);
+        mpass<T, false, BF>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, LeafOut<T>{base, n, m, false},
+                            &bad);
         __syncthreads();
     }
 }
@@ -546,7 +608,7 @@ __global__ void __launch_bounds__(NT) kl_tree(GroupArgs g) {
             // excluded instance: only its completion flag is published
         } else if (it.kind == ITEM_UP) {
             init_red(S);
-            mpass<double, true>(S, get, it.count, g.info, it.inst, -1, 3, [](int) {}, SlotOut{slots, it.first, n, true},
+            mpass<double, true, false>(S, get, it.count, g.info, it.inst, -1, 3, [](int) {}, SlotOut{slots, it.first, n, true},
                                 &bad);
             double *out = slot(it.out_slot);
             for (int e = tid; e < n * n; e += NT) {
@@ -559,7 +621,7 @@ __global__ void __launch_bounds__(NT) kl_tree(GroupArgs g) {
             const double *term = slot(it.term_slot);
             for (int e = tid; e < n * n; e += NT) S.P[e] = term[SL.Qx() + e];
             __syncthreads();
-            mpass<double, false>(S, get, it.count, g.info, it.inst, -1, 3, [](int) {},
+            mpass<double, false, false>(S, get, it.count, g.info, it.inst, -1, 3, [](int) {},
                                  SlotOut{slots, it.first, n, true}, &bad);
             double *out = slot(it.out_slot);
             for (int e = tid; e < n * n; e += NT) out[SL.Qx() + e] = S.P[e];
@@ -569,7 +631,7 @@ __global__ void __launch_bounds__(NT) kl_tree(GroupArgs g) {
             const double *term = it.last ? slot(it.term_slot) : nullptr;
             for (int e = tid; e < n * n; e += NT) S.P[e] = term ? term[SL.Qx() + e] : msg[SL.P() + e];
             __syncthreads();
-            mpass<double, false>(
+            mpass<double, false, false>(
                 S, get, it.count, g.info, it.inst, -1, 3,
                 [&](int s) {      // M2 for child s: P at the end of master stage s
                     double *d = slot(it.first + s) + SL.P();
@@ -1184,19 +1246,19 @@ __global__ void __launch_bounds__(NT) kw_update(GroupArgs g) {
 // ------------------------------------------------------------- launchers
 int leaf_units(const GroupArgs &g) { return std::max(1, std::min<int>(g.nleaves, LB_LEAF_UNITS)); }
 
-template <class T>
+template <class T, bool BF = false>
 hipError_t launch_leaf_up(const GroupArgs &g, int, hipStream_t st) {
-    hipLaunchKernelGGL((kl_leaf_up<T>), dim3(leaf_units(g)), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL((kl_leaf_up<T, BF>), dim3(leaf_units(g)), dim3(NT), 0, st, g);
     return hipGetLastError();
 }
 hipError_t launch_tree(const GroupArgs &g, int grid, hipStream_t st) {
     hipLaunchKernelGGL(kl_tree, dim3(std::min(grid, LB_TREE_UNITS)), dim3(NT), 0, st, g);
     return hipGetLastError();
 }
-template <class T>
+template <class T, bool BF = false>
 hipError_t launch_leaf_down(const GroupArgs &g, int, hipStream_t st) {
     if (g.ntop == 0) return hipSuccess;
-    hipLaunchKernelGGL((kl_leaf_down<T>), dim3(leaf_units(g)), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL((kl_leaf_down<T, BF>), dim3(leaf_units(g)), dim3(NT), 0, st, g);
     return hipGetLastError();
 }
 template <class TR>
@@ -1226,9 +1288,10 @@ hipError_t launch_update(const GroupArgs &g, int grid, hipStream_t st) {
 
 bool large_shape(int nx, int nu) { return nx >= 1 && nu >= 1 && nx <= lb::VMAX && nu <= lb::VMAX; }
 
-Launcher large_factor(int which, bool fp32) {
-    if (which == 0) return fp32 ? &lb::launch_leaf_up<float> : &lb::launch_leaf_up<double>;
+Launcher large_factor(int which, bool fp32, bool bf16) {
     if (which == 1) return &lb::launch_tree;
+    if (bf16) return which == 0 ? &lb::launch_leaf_up<float, true> : &lb::launch_leaf_down<float, true>;
+    if (which == 0) return fp32 ? &lb::launch_leaf_up<float> : &lb::launch_leaf_up<double>;
     return fp32 ? &lb::launch_leaf_down<float> : &lb::launch_leaf_down<double>;
 }
 

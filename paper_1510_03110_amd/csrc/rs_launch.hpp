@@ -30,7 +30,7 @@ struct ShapeEntry {
     bool large;              // no fused kernels: the FP64 solve runs on the stored factorization
     bool lb;                 // the stored factorization uses the large-block kernels (global workspace)
     Launcher fp64[3];        // fused: leaf up, tree, leaf down
-    Launcher factor[2][3];   // stored factorization [fp32 leaves][pass] (nullptr: not available)
+    Launcher factor[3][3];   // stored factorization [fp64, fp32, bf16-product leaves][pass] (nullptr: none)
     Launcher vsolve[2][3];   // right-hand-side passes on the stored factorization
     Launcher refine[2];      // FP64 residual, refinement update
     int scratch_per_stage;
@@ -51,7 +51,7 @@ hipError_t launch_refine_check(const InstInfo *tab, int count, const double *par
 constexpr int LB_LEAF_UNITS = 2048, LB_TREE_UNITS = 256;
 bool large_shape(int nx, int nu);
 size_t large_unit_bytes(int nx, int nu);
-Launcher large_factor(int which, bool fp32);
+Launcher large_factor(int which, bool fp32, bool bf16 = false);
 Launcher large_vector(int which, bool fp32);
 Launcher large_refine(int which);
 Launcher mfma_factor_leaf32(int nx, int nu, int which);   // FP32 leaves of n_x = 64 (which 0 up, 2 down)

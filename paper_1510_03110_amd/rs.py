@@ -17,7 +17,7 @@ from . import build as _build
 
 RS_OK, RS_ERR_ARG, RS_ERR_NOT_SPD, RS_ERR_SINGULAR_MASTER, RS_ERR_NOT_CONVERGED, \
     RS_ERR_NOMEM, RS_ERR_HIP, RS_ERR_UNSUPPORTED = range(8)
-RS_FP64, RS_MIXED_FP32 = 0, 1
+RS_FP64, RS_MIXED_FP32, RS_MIXED_BF16 = 0, 1, 2
 RS_PLAN_FACTORED = 1
 RS_PROB_SKIP = 1
 RS_KERNEL_KINDS = 16

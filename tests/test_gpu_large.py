@@ -179,14 +179,15 @@ def test_batching_config_mixed_precision_sampled():
     b.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_large_block_config_full_horizon(prec):
     """The large-block configuration's single instance at full size:
     n_x = 128, n_u = 64, N = 16384 (time-varying G2 data drawn on the device).
     The serial oracle needs minutes here, so the check is the property that
     holds at any size: the relative KKT residual of the returned solution,
     evaluated by the oracle's blockwise residual in FP64, is <= 1e-10 (and
-    the mixed-precision solve reports convergence)."""
+    the mixed-precision solves report convergence; BF16 products need more
+    corrections)."""
     torch, rs = _rs()
     data = W.g2_torch(128, 64, 16384, 1, seed=W.seed_for(4), device="cuda")
     bt = rs.Batch(data, precision=prec, Ns=64, branch=8)
@@ -194,7 +195,7 @@ def test_large_block_config_full_horizon(prec):
     torch.cuda.synchronize()
     assert bt.status()[0, 0] == 0
     sol = bt.result(0)
-    if prec == 1:
+    if prec >= 1:
         st = bt.refine_stats()[0]
         assert st[3] == 1.0 and st[0] <= TOL
     bt.close()
@@ -218,4 +219,22 @@ def test_large_block_config_batch64_sampled():
     assert np.all(st[:, 3] == 1.0) and st[:, 0].max() <= TOL
     for i in (0, 17, 63):
         _check(W.instance_to_numpy(data, i), bt.result(i))
+    bt.close()
+
+
+@pytest.mark.parametrize("nx,nu,N,Ns,b", [(128, 64, 40, 4, 3), (64, 32, 200, 8, 4), (48, 16, 64, 8, 2),
+                                          (64, 32, 10, 16, 2)])
+def test_bf16_products_match_oracle_after_refinement(nx, nu, N, Ns, b):
+    """RS_MIXED_BF16: P [A B], A'PA, A'PB, B'PB of the leaf stages on BF16
+    matrix cores with FP32 accumulation; refinement in FP64 reaches the same
+    1e-10 bound, with more corrections than the FP32 products need."""
+    torch, rs = _rs()
+    prob = W.g2(nx, nu, N, seed=23 * N + nx)
+    _, _, bt = _batch([prob], precision=rs.RS_MIXED_BF16, Ns=Ns, branch=b)
+    bt.solve()
+    torch.cuda.synchronize()
+    assert bt.status()[0, 0] == 0
+    _check(prob, bt.result(0))
+    st = bt.refine_stats()[0]
+    assert st[3] == 1.0 and st[0] <= TOL and 1 <= st[2] <= 20
     bt.close()

@@ -315,3 +315,13 @@ def test_receding_horizon_plan_update_checks_layout():
     finally:
         rs.rs_plan_destroy(p)
         rs.rs_plan_destroy(q)
+
+
+def test_bf16_precision_only_for_large_block_shapes():
+    """RS_MIXED_BF16 runs on the large-block kernels; shapes served by the
+    register-resident matrix-core kernels report RS_ERR_UNSUPPORTED."""
+    p = rs.rs_plan_create([(128, 64, 256)], precision=rs.RS_MIXED_BF16, Ns=16)
+    rs.rs_plan_destroy(p)
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_plan_create([(32, 16, 256)], precision=rs.RS_MIXED_BF16, Ns=16)
+    assert e.value.status == rs.RS_ERR_UNSUPPORTED
