@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "KKT Newton solves/s at n_x=32,N=1024 (FP64 vs mixed) + p50/p99 latency"
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector (and FP64 matrix) peak
 FP32_PEAK_TFLOPS = 157.3         # MI355X FP32 vector / FP32 matrix (dense) peak
+BF16_PEAK_TFLOPS = 2500.0        # MI355X BF16 matrix (dense) peak
 HBM_PEAK_GBS = 8000.0
 # shapes with register/LDS-resident matrix-core kernels; the others run the
 # large-block kernels (matrices in a per-workgroup global workspace)
@@ -161,8 +162,8 @@ def run_precision(prec, args, data, dev):
     from oracle import kkt, riccati
 
     n, m, N, B = args.nx, args.nu, args.N, args.batch
-    mixed = prec == "mixed"
-    pc = rs.RS_MIXED_FP32 if mixed else rs.RS_FP64
+    mixed = prec != "fp64"
+    pc = {"fp64": rs.RS_FP64, "mixed": rs.RS_MIXED_FP32, "bf16": rs.RS_MIXED_BF16}[prec]
     batch = rs.Batch(data, precision=pc, Ns=args.Ns, branch=args.branch, device=dev)
     log("[%s] workspace %.2f GB, leaves %d, tree items %d, depth %d" % (
         prec, batch.work_bytes / 1e9, rs.rs_plan_query(batch.plan, 0), rs.rs_plan_query(batch.plan, 1),
@@ -206,7 +207,8 @@ def run_precision(prec, args, data, dev):
         # the factorization's leaf-down kernel serves whole-problem leaves only
         up, down = leaf_work(leaves, n, m, flops_factor_reduce, flops_factor_elim, lambda a, b: 0.0,
                              flops_factor_elim)
-        peak = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
+        # BF16 plans: the dominant products run on BF16 matrix cores
+        peak = BF16_PEAK_TFLOPS if prec == "bf16" else FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
         pre = "kf_" if matrix_core else "kl_"
         # kernels launched once per step (the refinement kernels skip
         # converged instances, so their per-launch work is not fixed)
@@ -341,7 +343,8 @@ def main():
     # (16, branch 4), where the O(log N) tree is what lowers the latency.
     ap.add_argument("--Ns", type=int, default=128)
     ap.add_argument("--branch", type=int, default=8)
-    ap.add_argument("--precision", choices=("both", "fp64", "mixed"), default="both")
+    ap.add_argument("--precision", choices=("both", "fp64", "mixed", "bf16", "all"), default="both",
+                    help="both = fp64 and mixed; all adds bf16 (large-block shapes only)")
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--latency-Ns", type=int, default=16, help="leaf length of the B=1 latency plan")
     ap.add_argument("--latency-branch", type=int, default=4, help="branch of the B=1 latency plan")
@@ -377,7 +380,7 @@ def main():
     torch.cuda.synchronize()
     log("generated inputs in %.1fs (%.1f GB)" % (time.perf_counter() - t0,
                                                  sum(v.numel() * 8 for v in data.values()) / 1e9))
-    precs = ("fp64", "mixed") if args.precision == "both" else (args.precision,)
+    precs = {"both": ("fp64", "mixed"), "all": ("fp64", "mixed", "bf16")}.get(args.precision, (args.precision,))
     results, host = {}, None
     for prec in precs:
         results[prec], host = run_precision(prec, args, data, dev)
@@ -398,7 +401,7 @@ def main():
         "metric": METRIC, "value": r["value"], "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if head == "fp64" else "f32+f64",
+        "dtype": {"fp64": "f64", "mixed": "f32+f64", "bf16": "bf16+f32+f64"}[head],
         "data": "synthetic: seeded G2 generator drawn on the device",
         "config": {"workload": workload, "nx": n, "nu": m, "N": N, "batch": B, "Ns": args.Ns,
                    "branch": args.branch, "precision": head},

@@ -115,6 +115,13 @@ size_t large_unit_bytes(int nx, int nu) {
 
 namespace lb {
 
+// Threads and wavefronts of the workgroup: the matrix kernels run LB_MT
+// threads (8 wavefronts), so twice as many 16x16 tiles of a product are in
+// flight per work unit as with 4.
+constexpr int LB_MT = 512;
+__device__ __forceinline__ int nthr() { return (int)blockDim.x; }
+__device__ __forceinline__ int nwav() { return (int)(blockDim.x >> 6); }
+
 // Orders one wavefront's global-memory traffic (stores of some lanes before
 // loads of others).
 __device__ __forceinline__ void wave_gfence() {
@@ -135,7 +142,7 @@ __device__ __forceinline__ void gemm(int M, int N, int K, const T *__restrict__ 
     const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
     const int nt = lower ? tm * (tm + 1) / 2 : tm * tn;
     const int l = lane(), r16 = l & 15, k4 = l >> 4;
-    for (int t = wave(); t < nt; t += NT / 64) {
+    for (int t = wave(); t < nt; t += nwav()) {
         int ti, tj;
         if (lower) {
             mf::lower_tile(t, ti, tj);
@@ -183,7 +190,7 @@ __device__ __forceinline__ void gemm_bf16(int M, int N, int K, const float *__re
     const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
     const int nt = lower ? tm * (tm + 1) / 2 : tm * tn;
     const int l = lane(), r16 = l & 15, k4 = l >> 4;
-    for (int t = wave(); t < nt; t += NT / 64) {
+    for (int t = wave(); t < nt; t += nwav()) {
         int ti, tj;
         if (lower) {
             mf::lower_tile(t, ti, tj);
@@ -272,20 +279,20 @@ __device__ void chol_inv(WS<T> &S, int m, int *bad) {
         __syncthreads();
         // panel below the diagonal block, then the trailing lower blocks
         const int np = nb - kb - 1;
-        for (int t = w; t < np; t += NT / 64) {
+        for (int t = w; t < np; t += nwav()) {
             const int ib = kb + 1 + t, ri = rows(ib);
             const v4_t<T> acc = blk16<false>(mf::zero4<T>(), G + (int64_t)16 * ib * m + 16 * kb, m, DT, 16, ri, rk, rk);
             mf::tile_for<T>(0, 0, [&](int r, int i, int j) {
                 if (i < ri && j < rk) Lp[(int64_t)(16 * ib + i) * m + 16 * kb + j] = acc[r];
             });
         }
-        for (int e = tid; e < 256; e += NT) {
+        for (int e = tid; e < 256; e += nthr()) {
             const int i = e / 16, j = e % 16;
             if (i < rk && j < rk) Li[(int64_t)(16 * kb + i) * m + 16 * kb + j] = D[e];
         }
         __syncthreads();
         const int nt = np * (np + 1) / 2;
-        for (int t = w; t < nt; t += NT / 64) {
+        for (int t = w; t < nt; t += nwav()) {
             int a, b;
             mf::lower_tile(t, a, b);
             const int ib = kb + 1 + a, jb = kb + 1 + b, ri = rows(ib), rj = rows(jb);
@@ -300,7 +307,7 @@ __device__ void chol_inv(WS<T> &S, int m, int *bad) {
     // block rows of the inverse
     for (int ib = 1; ib < nb; ++ib) {
         const int ri = rows(ib);
-        for (int jb = w; jb < ib; jb += NT / 64) {
+        for (int jb = w; jb < ib; jb += nwav()) {
             v4_t<T> acc = mf::zero4<T>();
             for (int kb = jb; kb < ib; ++kb)
                 acc = blk16<false>(acc, Lp + (int64_t)16 * ib * m + 16 * kb, m, Li + (int64_t)16 * kb * m + 16 * jb, m,
@@ -315,7 +322,7 @@ __device__ void chol_inv(WS<T> &S, int m, int *bad) {
         }
         __syncthreads();
     }
-    for (int e = tid; e < m * m; e += NT) {
+    for (int e = tid; e < m * m; e += nthr()) {
         const int i = e / m, j = e - (e / m) * m;
         const T v = j <= i ? Li[e] : T(0);
         Li[e] = v;
@@ -342,7 +349,7 @@ struct LeafOut {
     __device__ void L(int s, const T *Li, const T *LiT) const {
         T *d = at(s);
         const LeafRec R{n, m};
-        for (int e = threadIdx.x; e < m * m; e += NT) {
+        for (int e = threadIdx.x; e < m * m; e += nthr()) {
             d[R.L() + e] = Li[e];
             d[R.LT() + e] = LiT[e];
         }
@@ -371,7 +378,7 @@ struct SlotOut {
         double *d = at(s);
         const SlotLayout SL{n};
         const int oL = up ? SL.uL() : SL.dL(), oT = up ? SL.uLT() : SL.dLT();
-        for (int e = threadIdx.x; e < n * n; e += NT) {
+        for (int e = threadIdx.x; e < n * n; e += nthr()) {
             d[oL + e] = Li[e];
             d[oT + e] = LiT[e];
         }
@@ -391,7 +398,7 @@ __device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int
     for (int s = count - 1; s >= 0; --s) {
         pre(s);
         const StageSrc src = get(s);
-        for (int e = tid; e < n * nw; e += NT) {
+        for (int e = tid; e < n * nw; e += nthr()) {
             const int i = e / nw, j = e - (e / nw) * nw;
             S.AB[e] = (T)(j < n ? src.A[(int64_t)i * n + j] : src.B[(int64_t)i * m + j - n]);
         }
@@ -473,7 +480,7 @@ __device__ __forceinline__ StageSrc leaf_stage(const DevProb &p, int t) { return
 template <class T>
 __device__ void init_red(WS<T> &S) {
     const int n = S.n;
-    for (int e = threadIdx.x; e < n * n; e += NT) {
+    for (int e = threadIdx.x; e < n * n; e += nthr()) {
         S.P[e] = T(0);
         S.V[e] = (e / n == e % n) ? T(1) : T(0);
         S.Qh[e] = T(0);
@@ -488,7 +495,7 @@ __device__ T *unit_ws(const GroupArgs &g) {
 
 // ------------------------------------------------------------ matrix side
 template <class T, bool BF>
-__global__ void __launch_bounds__(NT) kl_leaf_up(GroupArgs g) {
+__global__ void __launch_bounds__(LB_MT) kl_leaf_up(GroupArgs g) {
     __shared__ int bad;
     const int n = g.nx, m = g.nu, tid = threadIdx.x;
     WS<T> S;
@@ -504,7 +511,7 @@ __global__ void __launch_bounds__(NT) kl_leaf_up(GroupArgs g) {
             // stored factorization current (receding-horizon plans): only its
             // cached M1 goes to this call's slot
             const double *c = g.m1cache + (int64_t)it.m1 * 3 * n * n;
-            for (int e = tid; e < 3 * n * n; e += NT) out[e] = c[e];
+            for (int e = tid; e < 3 * n * n; e += nthr()) out[e] = c[e];
             continue;
         }
         double *cache = (g.m1cache && it.m1 >= 0) ? g.m1cache + (int64_t)it.m1 * 3 * n * n : nullptr;
@@ -514,7 +521,7 @@ __global__ void __launch_bounds__(NT) kl_leaf_up(GroupArgs g) {
         if (!(it.flags & LEAF_LAST)) {
             init_red(S);
             mpass<T, true, BF>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, o, &bad);
-            for (int e = tid; e < n * n; e += NT) {
+            for (int e = tid; e < n * n; e += nthr()) {
                 const int i = e / n, j = e % n;
                 const double a = (double)S.V[(int64_t)j * n + i], q = (double)S.Qh[e], x = (double)S.P[e];
                 out[SL.A() + e] = a;
@@ -527,17 +534,17 @@ __global__ void __launch_bounds__(NT) kl_leaf_up(GroupArgs g) {
                 }
             }
         } else {
-            for (int e = tid; e < n * n; e += NT) S.P[e] = (T)p.QxN[e];
+            for (int e = tid; e < n * n; e += nthr()) S.P[e] = (T)p.QxN[e];
             __syncthreads();
             mpass<T, false, BF>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, o, &bad);
-            for (int e = tid; e < n * n; e += NT) out[SL.Qx() + e] = (double)S.P[e];
+            for (int e = tid; e < n * n; e += nthr()) out[SL.Qx() + e] = (double)S.P[e];
         }
         __syncthreads();
     }
 }
 
 template <class T, bool BF>
-__global__ void __launch_bounds__(NT) kl_leaf_down(GroupArgs g) {
+__global__ void __launch_bounds__(LB_MT) kl_leaf_down(GroupArgs g) {
     __shared__ int bad;
     const int n = g.nx, m = g.nu, tid = threadIdx.x;
     WS<T> S;
@@ -550,7 +557,7 @@ __global__ void __launch_bounds__(NT) kl_leaf_down(GroupArgs g) {
         if (!(it.flags & LEAF_TOP) || inst_skipped(g.probs, it.inst)) continue;
         const DevProb p = load_prob(g.probs, it.inst);
         T *base = reinterpret_cast<T *>(g.fstore) + (it.scratch / g.sps) * (int64_t)LeafRec{n, m}.per_stage();
-        for (int e = tid; e < n * n; e += NT) S.P[e] = (T)p.QxN[e];
+        for (int e = tid; e < n * n; e += nthr()) S.P[e] = (T)p.QxN[e];
         __syncthreads();
         auto get = [&](int s) { return leaf_stage(p, it.t0 + s); };
         mpass<T, false, BF>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, LeafOut<T>{base, n, m, false},
@@ -586,7 +593,7 @@ __device__ void publish(const GroupArgs &g, int idx) {
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(NT) kl_tree(GroupArgs g) {
+__global__ void __launch_bounds__(LB_MT) kl_tree(GroupArgs g) {
     __shared__ int s_item, bad;
     const int n = g.nx, tid = threadIdx.x;
     const SlotLayout SL{n};
@@ -611,7 +618,7 @@ __global__ void __launch_bounds__(NT) kl_tree(GroupArgs g) {
             mpass<double, true, false>(S, get, it.count, g.info, it.inst, -1, 3, [](int) {}, SlotOut{slots, it.first, n, true},
                                 &bad);
             double *out = slot(it.out_slot);
-            for (int e = tid; e < n * n; e += NT) {
+            for (int e = tid; e < n * n; e += nthr()) {
                 const int i = e / n, j = e % n;
                 out[SL.A() + e] = S.V[(int64_t)j * n + i];
                 out[SL.Qw() + e] = S.Qh[e];
@@ -619,28 +626,28 @@ __global__ void __launch_bounds__(NT) kl_tree(GroupArgs g) {
             }
         } else if (it.kind == ITEM_UP_LAST) {
             const double *term = slot(it.term_slot);
-            for (int e = tid; e < n * n; e += NT) S.P[e] = term[SL.Qx() + e];
+            for (int e = tid; e < n * n; e += nthr()) S.P[e] = term[SL.Qx() + e];
             __syncthreads();
             mpass<double, false, false>(S, get, it.count, g.info, it.inst, -1, 3, [](int) {},
                                  SlotOut{slots, it.first, n, true}, &bad);
             double *out = slot(it.out_slot);
-            for (int e = tid; e < n * n; e += NT) out[SL.Qx() + e] = S.P[e];
+            for (int e = tid; e < n * n; e += nthr()) out[SL.Qx() + e] = S.P[e];
         } else {
             const bool top = it.kind == ITEM_TOP;
             const double *msg = top ? nullptr : slot(it.out_slot);
             const double *term = it.last ? slot(it.term_slot) : nullptr;
-            for (int e = tid; e < n * n; e += NT) S.P[e] = term ? term[SL.Qx() + e] : msg[SL.P() + e];
+            for (int e = tid; e < n * n; e += nthr()) S.P[e] = term ? term[SL.Qx() + e] : msg[SL.P() + e];
             __syncthreads();
             mpass<double, false, false>(
                 S, get, it.count, g.info, it.inst, -1, 3,
                 [&](int s) {      // M2 for child s: P at the end of master stage s
                     double *d = slot(it.first + s) + SL.P();
-                    for (int e = tid; e < n * n; e += NT) d[e] = S.P[e];
+                    for (int e = tid; e < n * n; e += nthr()) d[e] = S.P[e];
                 },
                 SlotOut{slots, it.first, n, false}, &bad);
             if (top) {
                 double *d = slot(it.term_slot) + SL.P();      // P_0, for the optimal value
-                for (int e = tid; e < n * n; e += NT) d[e] = S.P[e];
+                for (int e = tid; e < n * n; e += nthr()) d[e] = S.P[e];
             }
         }
         publish(g, idx);
@@ -1248,17 +1255,17 @@ int leaf_units(const GroupArgs &g) { return std::max(1, std::min<int>(g.nleaves,
 
 template <class T, bool BF = false>
 hipError_t launch_leaf_up(const GroupArgs &g, int, hipStream_t st) {
-    hipLaunchKernelGGL((kl_leaf_up<T, BF>), dim3(leaf_units(g)), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL((kl_leaf_up<T, BF>), dim3(leaf_units(g)), dim3(LB_MT), 0, st, g);
     return hipGetLastError();
 }
 hipError_t launch_tree(const GroupArgs &g, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(kl_tree, dim3(std::min(grid, LB_TREE_UNITS)), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL(kl_tree, dim3(std::min(grid, LB_TREE_UNITS)), dim3(LB_MT), 0, st, g);
     return hipGetLastError();
 }
 template <class T, bool BF = false>
 hipError_t launch_leaf_down(const GroupArgs &g, int, hipStream_t st) {
     if (g.ntop == 0) return hipSuccess;
-    hipLaunchKernelGGL((kl_leaf_down<T, BF>), dim3(leaf_units(g)), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL((kl_leaf_down<T, BF>), dim3(leaf_units(g)), dim3(LB_MT), 0, st, g);
     return hipGetLastError();
 }
 template <class TR>
