@@ -202,7 +202,7 @@ def run_precision(prec, args, data, dev):
     if fused:
         up, down = leaf_work(leaves, n, m, flops_reduce, flops_elim, flops_forward, flops_solve)
         work = {"leaf_up": ("alu", up, FP64_PEAK_TFLOPS, "km_leaf_up"),
-                "leaf_down": ("alu", down, FP64_PEAK_TFLOPS, "km_leaf_down")}
+                "leaf_down": ("alu", down, FP64_PEAK_TFLOPS, "kv_leaf_fwd")}
     else:
         # the factorization's leaf-down kernel serves whole-problem leaves only
         up, down = leaf_work(leaves, n, m, flops_factor_reduce, flops_factor_elim, lambda a, b: 0.0,
@@ -294,7 +294,7 @@ def ingest_counters(fetch_csv, write_csv, copy_bytes, workload):
                                 float(r["Counter_Value"])))
         return sorted(out)
 
-    names = ("km_leaf_up", "km_leaf_down", "km_tree", "kf_leaf_up", "kf_leaf_down", "kf_tree",
+    names = ("km_leaf_up", "km_leaf_down", "km_tree", "kv_leaf_fwd", "kf_leaf_up", "kf_leaf_down", "kf_tree",
              "kv_leaf_up", "kv_leaf_down", "kv_tree", "kr_residual")
     per = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
@@ -315,7 +315,8 @@ def ingest_counters(fetch_csv, write_csv, copy_bytes, workload):
         if "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
             continue
         (fk, fs), (wk, ws) = c["FETCH_SIZE"], c["WRITE_SIZE"]
-        records.append({"kernel": name, "workload": workload + ("_fp64" if name.startswith("km_") else "_mixed"),
+        fp64 = name.startswith("km_") or name == "kv_leaf_fwd"      # the fused FP64 solve's kernels
+        records.append({"kernel": name, "workload": workload + ("_fp64" if fp64 else "_mixed"),
                         "csrc_hash": csrc_hash(), "fetch_kib_raw": fk, "write_kib_raw": wk,
                         "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
                         "bytes_per_launch": fk * 1024.0 * fs + wk * 1024.0 * ws})
