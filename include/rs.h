@@ -184,6 +184,50 @@ rs_status rs_plan_create_ring(int32_t count, const int32_t *dims8, const rs_opti
  */
 rs_status rs_plan_ring_update(rs_plan plan, const int32_t *dims8);
 
+/*
+ * MHE front-end (Sec. 2, eq. org_mhe): one moving-horizon estimation problem
+ * with samples k = 0..Nmhe, device pointers, FP64, row-major blocks, element
+ * strides between samples (0 = the same block for every sample):
+ *   x_{k+1} = A_k x_k + B_k w_k + a_k,  y_k = C_k x_k + v_k + d_k,
+ * (w_k, v_k) with nominal values (wtil_k, vtil_k) and joint covariance
+ * [[Qw_k, Qwv_k], [Qwv_k', Qv_k]], x_0 with estimate xtil0 and covariance Ptil0.
+ * The process noise has the state dimension (n_w = n_x).
+ */
+typedef struct rs_mhe {
+    int32_t nx, ny, Nmhe, reserved;
+    const double *A;    int64_t sA;      /* nx*nx                                  */
+    const double *B;    int64_t sB;      /* nx*nx (n_w = n_x)                      */
+    const double *a;    int64_t sa;      /* nx; NULL = zero                        */
+    const double *C;    int64_t sC;      /* ny*nx                                  */
+    const double *d;    int64_t sd;      /* ny; NULL = zero                        */
+    const double *y;    int64_t sy;      /* ny measurements                        */
+    const double *wtil; int64_t swtil;   /* nx; NULL = zero                        */
+    const double *vtil; int64_t svtil;   /* ny; NULL = zero                        */
+    const double *Qw;   int64_t sQw;     /* nx*nx process noise covariance, SPD     */
+    const double *Qv;   int64_t sQv;     /* ny*ny measurement noise covariance      */
+    const double *Qwv;  int64_t sQwv;    /* nx*ny cross covariance; NULL = zero     */
+    const double *xtil0;                 /* nx                                     */
+    const double *Ptil0;                 /* nx*nx, SPD                             */
+} rs_mhe;
+
+/*
+ * Write the UFTOC problem P(N), N = Nmhe + 2, of each MHE problem into the
+ * arrays named by out[i] (Sec. 2: the state x_{-1} = xtil0 and the noise
+ * w_{-1} = x_0 - xtil0 are prepended and time is shifted by one; stage 0 holds
+ * the arrival cost with Q_w = Ptil0^{-1}, stage k + 1 the cost of sample k with
+ * the inverse joint noise covariance; zero terminal cost).  Written: Qx, Qw,
+ * Qxw (if non-NULL), A, B (blocks of out[i]'s strides), a, lx, lw, c, QxN,
+ * lN, cN and x0 (= xtil0), through out[i]'s pointers; out[i].nx = nx,
+ * out[i].nu = nx, out[i].N = Nmhe + 2.  The result is then solved with
+ * rs_batch_solve; x_t of the solution is the estimate of x_{t-1}.
+ * Asynchronous on `stream`.  nx + ny <= 48.  A covariance that is not
+ * positive definite sets info_dev[2i] = RS_ERR_NOT_SPD, info_dev[2i+1] = k
+ * (-1 for Ptil0) when info_dev is given.  Errors: RS_ERR_ARG (sizes, NULL
+ * required pointers, Qwv without an out.Qxw array).
+ */
+rs_status rs_mhe_to_uftoc(int32_t count, const rs_mhe *mhe, const rs_problem *out, void *stream,
+                          int32_t *info_dev);
+
 /* Device workspace bytes the plan needs (caller allocates, 256-byte aligned). */
 rs_status rs_plan_workspace_size(rs_plan plan, size_t *bytes);
 

@@ -36,6 +36,14 @@ class rs_problem(ctypes.Structure):
                 ("sa", ctypes.c_int64), ("slx", ctypes.c_int64), ("slw", ctypes.c_int64), ("sc", ctypes.c_int64)]
 
 
+class rs_mhe(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("Nmhe", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)] + \
+               [f for k in ("A", "B", "a", "C", "d", "y", "wtil", "vtil", "Qw", "Qv", "Qwv")
+                for f in ((k, _P), ("s" + k, ctypes.c_int64))] + \
+               [("xtil0", _P), ("Ptil0", _P)]
+
+
 class rs_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("Ns", ctypes.c_int32), ("branch", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("tol", ctypes.c_double), ("flags", ctypes.c_int32),
@@ -64,6 +72,8 @@ def library():
         lib.rs_plan_create_ex.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(rs_options), ctypes.POINTER(_P)]
         lib.rs_plan_create_ring.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(rs_options), ctypes.POINTER(_P)]
         lib.rs_plan_ring_update.argtypes = [_P, ctypes.POINTER(i32)]
+        lib.rs_mhe_to_uftoc.argtypes = [i32, ctypes.POINTER(rs_mhe), ctypes.POINTER(rs_problem), _P, _P]
+        lib.rs_mhe_to_uftoc.restype = i32
         lib.rs_graph_create.argtypes = [_P, i32, ctypes.POINTER(rs_problem), _P, sz, _P, _P, ctypes.POINTER(_P)]
         lib.rs_graph_launch.argtypes = [_P, _P]
         lib.rs_graph_destroy.argtypes = [_P]
@@ -135,6 +145,11 @@ def rs_plan_ring_update(plan, dims8):
     arr = np.ascontiguousarray(np.asarray(dims8, dtype=np.int32).reshape(-1, 8))
     _check(library().rs_plan_ring_update(plan, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
            "rs_plan_ring_update")
+
+
+def rs_mhe_to_uftoc(mhe, probs, stream_ptr=None, info_ptr=None):
+    """Device MHE -> UFTOC conversion; mhe, probs: ctypes arrays of equal length."""
+    _check(library().rs_mhe_to_uftoc(len(mhe), mhe, probs, stream_ptr, info_ptr), "rs_mhe_to_uftoc")
 
 
 def ring_current_leaves(start, N, Ns):

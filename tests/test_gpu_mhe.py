@@ -1,0 +1,139 @@
+"""MHE front-end on the GPU (Sec. 2, eq. org_mhe): rs_mhe_to_uftoc writes the
+UFTOC problem of an MHE problem on the device.  Checked against the oracle's
+conversion element by element (relative 1e-12: a Gauss-Jordan inverse of the
+joint noise covariance against the oracle's LU inverse), and end to end: the
+converted problem solved by the parallel Riccati solver gives the
+Rauch-Tung-Striebel smoothed state means (linear-Gaussian case, uncorrelated
+noise) and the oracle's solution of the oracle's conversion (correlated noise),
+to 1e-10."""
+import numpy as np
+import pytest
+
+from oracle import kkt, mhe, riccati
+from paper_1510_03110_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+UFTOC_KEYS = ("Qx", "Qw", "Qxw", "A", "B", "a", "lx", "lw", "c", "QxN", "lN", "cN", "x0")
+
+
+def _rs():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1510_03110_amd import rs
+    return torch, rs
+
+
+def _convert(torch, rs, m, invariant_cov=False):
+    """Device conversion of the MHE dict m; returns (device UFTOC dict, info)."""
+    nx, ny = m["A"].shape[1], m["C"].shape[1]
+    Nm = m["A"].shape[0] - 1
+    N = Nm + 2
+    f64 = dict(device="cuda", dtype=torch.float64)
+    dev = {k: torch.as_tensor(np.ascontiguousarray(v)).to(**f64) for k, v in m.items() if v is not None}
+    if invariant_cov:
+        for k in ("Qw", "Qv"):
+            dev[k] = dev[k][:1].contiguous()
+    out = dict(Qx=torch.full((N, nx, nx), np.nan, **f64), Qw=torch.full((N, nx, nx), np.nan, **f64),
+               Qxw=torch.full((N, nx, nx), np.nan, **f64), A=torch.full((N, nx, nx), np.nan, **f64),
+               B=torch.full((N, nx, nx), np.nan, **f64), a=torch.full((N, nx), np.nan, **f64),
+               lx=torch.full((N, nx), np.nan, **f64), lw=torch.full((N, nx), np.nan, **f64),
+               c=torch.full((N,), np.nan, **f64), QxN=torch.full((nx, nx), np.nan, **f64),
+               lN=torch.full((nx,), np.nan, **f64), cN=torch.full((1,), np.nan, **f64),
+               x0=torch.full((nx,), np.nan, **f64))
+    mm = (rs.rs_mhe * 1)()
+    q = mm[0]
+    q.nx, q.ny, q.Nmhe = nx, ny, Nm
+    blocks = dict(A=nx * nx, B=nx * nx, a=nx, C=ny * nx, d=ny, y=ny, wtil=nx, vtil=ny, Qw=nx * nx, Qv=ny * ny,
+                  Qwv=nx * ny)
+    for k, bs in blocks.items():
+        t = dev.get(k)
+        setattr(q, k, t.data_ptr() if t is not None else None)
+        setattr(q, "s" + k, 0 if (t is not None and t.shape[0] == 1 and Nm > 0) else bs)
+    q.xtil0, q.Ptil0 = dev["xtil0"].data_ptr(), dev["Ptil0"].data_ptr()
+    pp = (rs.rs_problem * 1)()
+    p = pp[0]
+    p.nx, p.nu, p.N = nx, nx, N
+    for k, bs in (("Qx", nx * nx), ("Qw", nx * nx), ("Qxw", nx * nx), ("A", nx * nx), ("B", nx * nx)):
+        setattr(p, k, out[k].data_ptr())
+        setattr(p, "s" + k, bs)
+    for k, bs in (("a", nx), ("lx", nx), ("lw", nx), ("c", 1)):
+        setattr(p, k, out[k].data_ptr())
+        setattr(p, "s" + k, bs)
+    for k in ("QxN", "lN", "cN", "x0"):
+        setattr(p, k, out[k].data_ptr())
+    info = torch.zeros(2, dtype=torch.int32, device="cuda")
+    rs.rs_mhe_to_uftoc(mm, pp, torch.cuda.current_stream().cuda_stream, info.data_ptr())
+    torch.cuda.synchronize()
+    return out, info.cpu().numpy()
+
+
+def _oracle_args(m):
+    K = m["A"].shape[0]
+    lst = lambda k: [m[k][i] for i in range(K)]
+    return (lst("A"), lst("B"), lst("a"), lst("C"), lst("d"), lst("y"), m["xtil0"], m["Ptil0"], lst("wtil"),
+            lst("vtil"), lst("Qw"), lst("Qv"), lst("Qwv") if m["Qwv"] is not None else None)
+
+
+@pytest.mark.parametrize("nx,ny,Nm,corr", [(20, 20, 100, False), (20, 20, 60, True), (4, 2, 10, False),
+                                           (3, 5, 0, True), (8, 8, 33, True)])
+def test_mhe_conversion_matches_oracle(nx, ny, Nm, corr):
+    torch, rs = _rs()
+    m = W.mhe_problem(nx, ny, Nm, seed=W.seed_for(6, nx * 100 + Nm), correlated=corr)
+    out, info = _convert(torch, rs, m)
+    assert info[0] == 0
+    ref = mhe.mhe_to_uftoc(*_oracle_args(m))
+    for k in UFTOC_KEYS:
+        got = out[k].cpu().numpy().reshape(np.shape(ref[k]) if np.ndim(ref[k]) else ())
+        r = np.asarray(ref[k], dtype=np.float64)
+        scale = max(1.0, float(np.abs(r).max()))
+        assert np.abs(got - r).max() <= 1e-12 * scale, k
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mhe_end_to_end_equals_rts_smoother(prec):
+    """Uncorrelated noise: the converted problem's states x_1..x_N are the
+    RTS-smoothed means of x_0..x_{Nmhe+1}; x_0 = xtil_0 (paper's size
+    n_x = n_w = n_y = 20, horizon 300, leaf length 16)."""
+    torch, rs = _rs()
+    m = W.mhe_problem(20, 20, 298, seed=W.seed_for(6, 1))
+    out, info = _convert(torch, rs, m, invariant_cov=False)
+    assert info[0] == 0
+    bt = rs.Batch({k: [v] for k, v in out.items()}, precision=prec, Ns=16, branch=4)
+    bt.solve()
+    torch.cuda.synchronize()
+    assert bt.status()[0, 0] == 0
+    sol = bt.result(0)
+    bt.close()
+    ms = mhe.rts_smoother(*_oracle_args(m)[:12])
+    err = np.abs(sol["x"][1:] - ms).max() / np.abs(ms).max()
+    assert err <= TOL, err
+    np.testing.assert_array_equal(sol["x"][0], m["xtil0"])
+
+
+def test_mhe_end_to_end_correlated_noise_and_invariant_covariances():
+    """Correlated noise and covariances given once (stride 0): the GPU solve
+    of the GPU conversion equals the oracle's solve of the oracle's
+    conversion."""
+    torch, rs = _rs()
+    m = W.mhe_problem(8, 6, 120, seed=W.seed_for(6, 2), correlated=True)
+    for k in ("Qw", "Qv"):
+        m[k] = np.broadcast_to(m[k][:1], m[k].shape).copy()
+    out, info = _convert(torch, rs, m, invariant_cov=True)
+    assert info[0] == 0
+    bt = rs.Batch({k: [v] for k, v in out.items()}, Ns=8, branch=4)
+    bt.solve()
+    torch.cuda.synchronize()
+    sol = bt.result(0)
+    bt.close()
+    ref = riccati.solve(mhe.mhe_to_uftoc(*_oracle_args(m)))
+    assert kkt.rel_error(sol, ref) <= TOL
+
+
+def test_mhe_covariance_not_positive_definite_reported():
+    torch, rs = _rs()
+    m = W.mhe_problem(4, 3, 12, seed=5)
+    m["Qv"][7] = -np.eye(3)
+    _, info = _convert(torch, rs, m)
+    assert info[0] == 2 and info[1] == 7
