@@ -36,6 +36,7 @@ struct VSmem {
     double Psi[NX], pt[NX], av[NX], d[NX], x[NX];
     double gw[NU], z[NU], kk[NU], wv[NU];
     double v[NX];
+    double fk[NU], fl[NU], fa[NX], fv[NX], fb[NX];   // forward-sweep products
 };
 
 // Where a backward stage's operands live.  Stored factors are of type TR
@@ -244,27 +245,33 @@ __device__ __forceinline__ void leaf_forward_sweep(VSmem<NX, NU> &S, double *lam
     const int len = uni(it.len);
     for (int s = 0; s < len; ++s) {
         const int t = it.t0 + s;
-        Op<NU, NX> oK, oL;
-        Op<NX, NX> oA, oP, oV;
-        Op<NX, NU> oB;
-        oK.template load<true>(rec.K(s), NX);
-        oA.template load<true>(p.A + (int64_t)t * p.sA, NX);
-        oB.template load<true>(p.B + (int64_t)t * p.sB, NU);
+        // row operands with contiguous loads; P (symmetric) read by columns
+        RowOp<NU, NX> rK, rL;
+        RowOp<NX, NX> rA, rV;
+        RowOp<NX, NU> rB;
+        Op<NX, NX> oP;
+        rK.load(rec.K(s), NX);
+        rA.load(p.A + (int64_t)t * p.sA, NX);
+        rB.load(p.B + (int64_t)t * p.sB, NU);
         oP.template load<false>(rec.P(s), NX);
         if (!last) {
-            oL.template load<true>(rec.L(s), NX);
-            oV.template load<true>(rec.V(s), NX);
+            rL.load(rec.L(s), NX);
+            rV.load(rec.V(s), NX);
         }
         const double kk = l < NU ? (double)rec.k(s)[l] : 0.0;
         const double psi = l < NX ? (double)rec.Psi(s)[l] : 0.0;
         const double av = (l < NX && p.a) ? p.a[(int64_t)t * p.sa + l] : 0.0;
-        double wv = oK.apply(S.x) + kk;
-        double lam = oP.apply(S.x) - psi;
+        rK.apply(S.x, [&](int i, double v) { S.fk[i] = v; });
+        rA.apply(S.x, [&](int i, double v) { S.fa[i] = v; });
         if (!last) {
-            wv += oL.apply(lamN);
-            lam += oV.apply(lamN);
+            rL.apply(lamN, [&](int i, double v) { S.fl[i] = v; });
+            rV.apply(lamN, [&](int i, double v) { S.fv[i] = v; });
         }
-        const double ax = oA.apply(S.x) + av;
+        double lam = oP.apply(S.x) - psi;
+        wsync();
+        double wv = 0.0;
+        if (l < NU) wv = S.fk[l] + kk + (last ? 0.0 : S.fl[l]);
+        if (!last && l < NX) lam += S.fv[l];
         if (l < NX) {
             p.x[(int64_t)t * NX + l] = S.x[l];
             p.lam[(int64_t)t * NX + l] = lam;
@@ -274,9 +281,9 @@ __device__ __forceinline__ void leaf_forward_sweep(VSmem<NX, NU> &S, double *lam
             p.w[(int64_t)t * NU + l] = wv;
         }
         wsync();
-        const double xn = ax + oB.apply(S.wv);
+        rB.apply(S.wv, [&](int i, double v) { S.fb[i] = v; });
         wsync();
-        if (l < NX) S.x[l] = xn;
+        if (l < NX) S.x[l] = S.fa[l] + av + S.fb[l];
         wsync();
     }
     if (last) {

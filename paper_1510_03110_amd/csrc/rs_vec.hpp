@@ -67,6 +67,43 @@ struct Op {
     }
 };
 
+// Row-major matrix operand of y = M x read with contiguous loads: LC = C / 2
+// lanes share a row, each holding two consecutive columns, so one load
+// instruction of the wavefront covers RPI = 64 / LC whole rows (for a dense
+// matrix a contiguous block).  apply() sums the LC partial products of a row
+// with lane shuffles and hands y_i to out(i, y_i) from lane (i mod RPI) LC.
+template <int R, int C>
+struct RowOp {
+    static constexpr int LC = C / 2, RPI = 64 / LC, NI = (R + RPI - 1) / RPI;
+    static_assert(C % 2 == 0 && LC >= 1 && LC <= 64 && (LC & (LC - 1)) == 0, "C / 2 a power of two <= 64");
+    double m0[NI], m1[NI];
+
+    template <class U>
+    __device__ __forceinline__ void load(const U *M, int ld) {
+        const int l = lane(), c = 2 * (l % LC), r0 = l / LC;
+#pragma unroll
+        for (int ii = 0; ii < NI; ++ii) {
+            const int row = ii * RPI + r0;
+            const bool ok = M && row < R;
+            m0[ii] = ok ? (double)M[row * ld + c] : 0.0;
+            m1[ii] = ok ? (double)M[row * ld + c + 1] : 0.0;
+        }
+    }
+    template <class Out>
+    __device__ __forceinline__ void apply(const double *x, Out out) const {
+        const int l = lane(), c = 2 * (l % LC), r0 = l / LC;
+        const double x0 = x[c], x1 = x[c + 1];
+#pragma unroll
+        for (int ii = 0; ii < NI; ++ii) {
+            double p = m0[ii] * x0 + m1[ii] * x1;
+#pragma unroll
+            for (int o = LC / 2; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+            const int row = ii * RPI + r0;
+            if (l % LC == 0 && row < R) out(row, p);
+        }
+    }
+};
+
 // LDS-only barrier (global loads and stores stay in flight across it).
 __device__ __forceinline__ void wsync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
