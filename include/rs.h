@@ -228,6 +228,39 @@ typedef struct rs_mhe {
 rs_status rs_mhe_to_uftoc(int32_t count, const rs_mhe *mhe, const rs_problem *out, void *stream,
                           int32_t *info_dev);
 
+/*
+ * Interior-point kernels for P(N) with input bounds wlo_t <= w_t <= whi_t (the
+ * inequality-constrained MHE problem whose Newton steps P(N) gives, Sec. 3).
+ * A primal-dual iteration (Mehrotra predictor-corrector) is, on the caller's
+ * stream: rs_ip_newton(phase 0) [residuals, Q_w + Sigma, Newton right-hand
+ * side; stats[0..4] = max |r_x|, max |r_w|, max |r_l| (and |x_0 - xbar_0|),
+ * sum of slack * multiplier, number of finite bounds], rs_factor and rs_solve
+ * on `newton` (a plan with RS_PLAN_FACTORED), rs_ip_step(phase 0) [stats[5],
+ * stats[6] = largest primal / dual step in (0, 1]], rs_ip_mu [stats[7] =
+ * complementarity at the affine step], rs_ip_newton(phase 1, sigma mu)
+ * [corrector right-hand side], rs_solve, rs_ip_step(phase 1, sigma mu),
+ * rs_ip_update.  All arrays are device FP64, stage-major and dense (stride
+ * nu for the bounds unless 0).  `newton` describes the Newton system: the
+ * problem's Qx, Qxw, A, B, QxN; its own Qw (N nu*nu, written), a, lx, lw, c,
+ * lN, x0 (written) and x, w, lam (the step, written by rs_solve).
+ */
+typedef struct rs_ip {
+    int32_t nx, nu, N, reserved;     /* nx, nu <= 64                                    */
+    rs_problem prob;                 /* P(N); its x, w, lam hold the current iterate    */
+    const double *wlo; int64_t swlo; /* N blocks of nu: lower bounds (<= -1e300: none)  */
+    const double *whi; int64_t swhi; /* upper bounds (>= 1e300: none)                   */
+    double *ml, *mu;                 /* N nu multipliers of the lower / upper bounds    */
+    rs_problem newton;               /* the Newton system (see above)                   */
+    double *dw_aff, *dml, *dmu;      /* N nu: affine input step, multiplier steps       */
+    double *part;                    /* (N + 1) * 8 per-stage partial results           */
+    double *stats;                   /* 8 results (see above)                           */
+} rs_ip;
+
+rs_status rs_ip_newton(const rs_ip *ip, int32_t phase, double sigma_mu, void *stream);
+rs_status rs_ip_step(const rs_ip *ip, int32_t phase, double sigma_mu, void *stream);
+rs_status rs_ip_mu(const rs_ip *ip, double alpha_p, double alpha_d, void *stream);
+rs_status rs_ip_update(const rs_ip *ip, double alpha_p, double alpha_d, void *stream);
+
 /* Device workspace bytes the plan needs (caller allocates, 256-byte aligned). */
 rs_status rs_plan_workspace_size(rs_plan plan, size_t *bytes);
 

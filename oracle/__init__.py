@@ -17,6 +17,9 @@ Contents (each function cites the passage of the paper it follows):
                   solution by the paper's product and sum formulas.
 * ``mhe``       - MHE problem to UFTOC conversion (Sec. 2) and the RTS
                   smoother, used as an independent closed-form pin.
+* ``boxqp``     - minimiser of P(N) with bounds on the inputs (the
+                  inequality-constrained problem of Sec. 3) by condensing and
+                  bounded-variable least squares.
 
 Problems are dicts of float64 numpy arrays, row-major blocks:
 ``Qx (N,nx,nx)  Qw (N,nu,nu)  Qxw (N,nx,nu)  A (N,nx,nx)  B (N,nx,nu)

@@ -44,6 +44,13 @@ class rs_mhe(ctypes.Structure):
                [("xtil0", _P), ("Ptil0", _P)]
 
 
+class rs_ip(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nu", ctypes.c_int32), ("N", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("prob", rs_problem), ("wlo", _P), ("swlo", ctypes.c_int64), ("whi", _P), ("swhi", ctypes.c_int64),
+                ("ml", _P), ("mu", _P), ("newton", rs_problem), ("dw_aff", _P), ("dml", _P), ("dmu", _P),
+                ("part", _P), ("stats", _P)]
+
+
 class rs_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("Ns", ctypes.c_int32), ("branch", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("tol", ctypes.c_double), ("flags", ctypes.c_int32),
@@ -74,6 +81,11 @@ def library():
         lib.rs_plan_ring_update.argtypes = [_P, ctypes.POINTER(i32)]
         lib.rs_mhe_to_uftoc.argtypes = [i32, ctypes.POINTER(rs_mhe), ctypes.POINTER(rs_problem), _P, _P]
         lib.rs_mhe_to_uftoc.restype = i32
+        for name, extra in (("rs_ip_newton", [i32, ctypes.c_double]), ("rs_ip_step", [i32, ctypes.c_double]),
+                            ("rs_ip_mu", [ctypes.c_double, ctypes.c_double]),
+                            ("rs_ip_update", [ctypes.c_double, ctypes.c_double])):
+            getattr(lib, name).argtypes = [ctypes.POINTER(rs_ip)] + extra + [_P]
+            getattr(lib, name).restype = i32
         lib.rs_graph_create.argtypes = [_P, i32, ctypes.POINTER(rs_problem), _P, sz, _P, _P, ctypes.POINTER(_P)]
         lib.rs_graph_launch.argtypes = [_P, _P]
         lib.rs_graph_destroy.argtypes = [_P]

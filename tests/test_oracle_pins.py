@@ -225,3 +225,26 @@ def test_mhe_conversion_correlated_noise_matches_direct_map():
     u = np.linalg.lstsq(np.vstack(rows), np.concatenate(rhs), rcond=None)[0]
     for k, (Xm, xc) in enumerate(xs):
         np.testing.assert_allclose(sol["x"][k + 1], Xm @ u + xc, rtol=1e-9, atol=1e-9)
+
+
+def test_box_constrained_reference_pins():
+    """oracle.boxqp: with infinite bounds it is the unconstrained solution;
+    with active bounds the reduced gradient has the sign pattern of a
+    minimiser (zero on free inputs, >= 0 at lower, <= 0 at upper bounds) and
+    no bound is violated."""
+    from oracle import boxqp
+    prob = W.g2(4, 2, 12, seed=77)
+    inf = np.full((12, 2), np.inf)
+    ref = riccati.solve(prob)
+    r = boxqp.solve(prob, -inf, inf)
+    np.testing.assert_allclose(r["w"], ref["w"], rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(r["x"], ref["x"], rtol=1e-9, atol=1e-10)
+    lo, hi = np.full((12, 2), -0.4), np.full((12, 2), 0.3)
+    c = boxqp.solve(prob, lo, hi)
+    w, gr = c["w"], c["grad"]
+    assert np.all(w >= lo - 1e-12) and np.all(w <= hi + 1e-12)
+    at_lo, at_hi = np.isclose(w, lo, atol=1e-9), np.isclose(w, hi, atol=1e-9)
+    assert at_lo.any() and at_hi.any()
+    free = ~(at_lo | at_hi)
+    assert np.abs(gr[free]).max() <= 1e-8
+    assert np.all(gr[at_lo] >= -1e-8) and np.all(gr[at_hi] <= 1e-8)
