@@ -24,11 +24,35 @@ __device__ __forceinline__ int64_t uni64(int64_t v) {
     return ((int64_t)uni((int)(v >> 32)) << 32) | (uint32_t)uni((int)(v & 0xffffffff));
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// A double moved between lanes of a row of 16 by a DPP permutation (CTRL is
+// the dpp_ctrl code), without the LDS crossbar round trip of ds_bpermute.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
+                            __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
+}
+
+// Sum over aligned groups of G consecutive lanes (G a power of two <= 64);
+// every lane of a group receives the group's sum.  Inside a row of 16:
+// mirror (lane i <- 15 - i) pairs lanes whose indices sum to 15, half mirror
+// (i <- 7 - i within each 8) then leaves every quad holding one partial sum
+// of each of four disjoint classes that together cover the row, and the two
+// quad swaps (xor 1, xor 2) add those up.  Groups wider than a row add the
+// rows with lane shuffles.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "G a power of two <= 64");
+    if constexpr (G >= 16) v += dpp_move<0x140>(v);      // row_mirror
+    if constexpr (G >= 8) v += dpp_move<0x141>(v);       // row_half_mirror
+    if constexpr (G >= 2) v += dpp_move<0xB1>(v);        // quad_perm [1, 0, 3, 2]
+    if constexpr (G >= 4) v += dpp_move<0x4E>(v);        // quad_perm [2, 3, 0, 1]
+    if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+    if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
     return v;
 }
+
+__device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
 
 // Matrix operand of one product y = M x with R outputs and C inputs, held in
 // registers.  The wavefront is split into 64 / Rp parts (Rp = R rounded up to
@@ -71,7 +95,7 @@ struct Op {
 // lanes share a row, each holding two consecutive columns, so one load
 // instruction of the wavefront covers RPI = 64 / LC whole rows (for a dense
 // matrix a contiguous block).  apply() sums the LC partial products of a row
-// with lane shuffles and hands y_i to out(i, y_i) from lane (i mod RPI) LC.
+// with DPP lane permutations and hands y_i to out(i, y_i) from lane (i mod RPI) LC.
 template <int R, int C>
 struct RowOp {
     static constexpr int LC = C / 2, RPI = 64 / LC, NI = (R + RPI - 1) / RPI;
@@ -95,9 +119,7 @@ struct RowOp {
         const double x0 = x[c], x1 = x[c + 1];
 #pragma unroll
         for (int ii = 0; ii < NI; ++ii) {
-            double p = m0[ii] * x0 + m1[ii] * x1;
-#pragma unroll
-            for (int o = LC / 2; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+            const double p = group_sum<LC>(m0[ii] * x0 + m1[ii] * x1);
             const int row = ii * RPI + r0;
             if (l % LC == 0 && row < R) out(row, p);
         }
