@@ -14,7 +14,10 @@ Contents (each function cites the passage of the paper it follows):
                   problems; golden fixtures).
 * ``reduction`` - closed-form reduced subproblem of Theorem 1 and the master
                   problem of Sec. 4.3, built from the preliminary Riccati
-                  solution by the paper's product and sum formulas.
+                  solution by the paper's product and sum formulas; the
+                  rank-revealing form with the U_1 basis (n_uo <= n_x
+                  inputs per master stage) and a dense KKT solve of master
+                  problems whose stages have different input dimensions.
 * ``mhe``       - MHE problem to UFTOC conversion (Sec. 2) and the RTS
                   smoother, used as an independent closed-form pin.
 * ``boxqp``     - minimiser of P(N) with bounds on the inputs (the

@@ -22,6 +22,17 @@ block tau is the product over t = tau+1..N-1 times B_tau.
 The last subinterval, whose terminal cost is known, is eliminated entirely
 (Sec. 4.2, last paragraph): its reduced form is the terminal cost
 (P_0, -Psi_0, cbar_0) of a Riccati pass with the true terminal.
+
+The rank-revealing form (Sec. 4.2, eqs. Bh_def and Gh_Hh_def) takes an
+orthonormal basis U_1 of range(S') with n_uo = rank(S') <= n_x columns:
+    Qw_hat = U_1' Qbar^{-1} U_1  (n_uo x n_uo, positive definite),
+    B_hat  = S Qbar^{-1} U_1     (n_x x n_uo),
+so that the master stage has n_uo inputs and its G_hat is nonsingular even
+when S' is rank deficient (N_s n_u < n_x, or a subinterval whose inputs do
+not reach every state direction).  U_1 comes from the singular value
+decomposition of S' with numpy's rank rule (singular values above
+max(dims) eps sigma_max).  Master problems whose stages have different input
+dimensions are solved here from their KKT system written out densely.
 """
 import numpy as np
 
@@ -106,3 +117,79 @@ def master_problem(prob, bounds):
         c=np.array([s["c"] for s in stages]).reshape(p),
         QxN=QxN, lN=lN, cN=cN, x0=np.asarray(prob["x0"]))
     return m
+
+
+def reduce_rank_revealing(sub):
+    """Reduced form of a subproblem with the U_1 basis (eq. Bh_def).
+    Returns dict(A, B (nx x nuo), a, Qx, Qw (nuo x nuo), lx, c, nuo)."""
+    red = reduce_closed_form(sub)
+    S, Qbar = red["S"], red["Qbar"]
+    U, sv, _ = np.linalg.svd(S.T, full_matrices=False)
+    tol = (sv[0] * max(S.shape) * np.finfo(float).eps) if sv.size else 0.0
+    r = int(np.sum(sv > tol))
+    U1 = U[:, :r]
+    QinvU1 = np.linalg.solve(Qbar, U1)
+    return dict(A=red["A"], B=S @ QinvU1, a=red["a"], Qx=red["Qx"], Qw=U1.T @ QinvU1,
+                lx=red["lx"], c=red["c"], nuo=r)
+
+
+def master_problem_rr(prob, bounds):
+    """Master problem with rank-revealing stages: a list of per-stage dicts
+    (A, B, a, Qx, Qw, lx, c, nuo) and the terminal (QxN, lN, cN), x0."""
+    nx = prob["QxN"].shape[0]
+    p = len(bounds) - 2
+    stages = [reduce_rank_revealing(sub_problem(prob, bounds[i], bounds[i + 1])) for i in range(p)]
+    last = sub_problem(prob, bounds[p], bounds[p + 1],
+                       terminal=(prob["QxN"], -np.asarray(prob.get("lN", np.zeros(nx))),
+                                 float(prob.get("cN", 0.0))))
+    QxN, lN, cN = eliminate_last(last)
+    return dict(stages=stages, QxN=QxN, lN=lN, cN=cN, x0=np.asarray(prob["x0"]))
+
+
+def solve_master_dense(m):
+    """Solve a master problem from master_problem_rr by its KKT system:
+    minimise sum_i (1/2 x_i'Qx_i x_i + 1/2 w_i'Qw_i w_i + lx_i'x_i + c_i)
+    + 1/2 x_p'QxN x_p + lN'x_p + cN subject to x_0 = x0 and
+    x_{i+1} = A_i x_i + B_i w_i + a_i.  Returns x (p+1, nx), w (list),
+    lam (p+1, nx) with the sign convention of P(N) (lam_i is the multiplier
+    of the dynamics into x_i, lam_0 that of the initial condition) and obj."""
+    st = m["stages"]
+    p = len(st)
+    nx = m["QxN"].shape[0]
+    nus = [s["nuo"] for s in st]
+    xo = [i * nx for i in range(p + 1)]
+    wo, o = [], (p + 1) * nx
+    for r in nus:
+        wo.append(o)
+        o += r
+    nz, nc = o, (p + 1) * nx
+    H = np.zeros((nz, nz))
+    g = np.zeros(nz)
+    const = float(m["cN"]) + sum(float(s["c"]) for s in st)
+    C = np.zeros((nc, nz))
+    b = np.zeros(nc)
+    for i, s in enumerate(st):
+        H[xo[i]:xo[i] + nx, xo[i]:xo[i] + nx] = s["Qx"]
+        H[wo[i]:wo[i] + nus[i], wo[i]:wo[i] + nus[i]] = s["Qw"]
+        g[xo[i]:xo[i] + nx] = s["lx"]
+    H[xo[p]:xo[p] + nx, xo[p]:xo[p] + nx] = m["QxN"]
+    g[xo[p]:xo[p] + nx] = m["lN"]
+    # constraint rows: x_0 = x0; then x_{i+1} - A_i x_i - B_i w_i = a_i
+    C[0:nx, 0:nx] = np.eye(nx)
+    b[0:nx] = m["x0"]
+    for i, s in enumerate(st):
+        r = slice((i + 1) * nx, (i + 2) * nx)
+        C[r, xo[i + 1]:xo[i + 1] + nx] = np.eye(nx)
+        C[r, xo[i]:xo[i] + nx] = -s["A"]
+        C[r, wo[i]:wo[i] + nus[i]] = -s["B"]
+        b[r] = s["a"]
+    K = np.block([[H, C.T], [C, np.zeros((nc, nc))]])
+    sol = np.linalg.solve(K, np.concatenate([-g, b]))
+    z, nu_ = sol[:nz], sol[nz:]
+    x = np.array([z[xo[i]:xo[i] + nx] for i in range(p + 1)])
+    w = [z[wo[i]:wo[i] + nus[i]] for i in range(p)]
+    obj = 0.5 * z @ H @ z + g @ z + const
+    # stationarity in x_i: Qx_i x_i + lx_i + nu_i - A_i' nu_{i+1} = 0; with
+    # lam = -nu this is the x row of P(N): Qx x + lx - lam_i + A' lam_{i+1} = 0
+    lam = -nu_.reshape(p + 1, nx)
+    return dict(x=x, w=w, lam=lam, obj=float(obj))

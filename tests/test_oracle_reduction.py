@@ -89,3 +89,71 @@ def test_two_level_tree_equals_original():
         t = b0[s]
         np.testing.assert_allclose(s2["x"][i], full["x"][t], rtol=1e-8, atol=1e-8)
         np.testing.assert_allclose(s2["P"][i], full["P"][t], rtol=1e-8, atol=1e-8)
+
+
+def _zero_inputs(prob, t0, t1):
+    q = dict(prob)
+    q["B"] = np.array(prob["B"], copy=True)
+    q["B"][t0:t1] = 0.0
+    if q.get("Qxw") is not None:
+        q["Qxw"] = np.array(q["Qxw"], copy=True)
+        q["Qxw"][t0:t1] = 0.0
+    return q
+
+
+@pytest.mark.parametrize("nx,nu,N,Ns,gap", [(6, 1, 12, 2, None), (8, 2, 17, 3, None), (5, 1, 10, 1, None),
+                                            (4, 2, 12, 4, None), (6, 2, 16, 4, (4, 8))])
+def test_rank_revealing_master_equals_original(nx, nu, N, Ns, gap):
+    """Master problem with the U_1 basis (eqs. Bh_def, Gh_Hh_def): stage i has
+    n_uo = rank(S') inputs (min(N_s n_u, n_x) for generic data; 0 for a
+    subinterval whose inputs act on nothing), and the master solution still
+    gives x_hat_i = x_{t_i}, lam_hat_i = lam_{t_i} and the optimal value of
+    P(N), also where the reduced input weight of the plain form is singular."""
+    prob = W.with_costs(W.g2(nx, nu, N, seed=N * 3 + nx), seed=4)
+    if gap is not None:
+        prob = _zero_inputs(prob, *gap)
+    full = riccati.solve(prob, want_factors=True)
+    bounds = list(range(0, N, Ns)) + [N]
+    m = reduction.master_problem_rr(prob, bounds)
+    for i, s in enumerate(m["stages"]):
+        want = min(Ns * nu, nx)
+        if gap is not None and gap[0] <= bounds[i] and bounds[i + 1] <= gap[1]:
+            want = 0
+        assert s["nuo"] == want
+        assert s["B"].shape == (nx, want) and s["Qw"].shape == (want, want)
+        if want:
+            assert np.linalg.eigvalsh(s["Qw"]).min() > 0
+        # the plain form S Qbar^{-1} S' has rank n_uo: singular when n_uo < n_x
+        plain = reduction.reduce_closed_form(reduction.sub_problem(prob, bounds[i], bounds[i + 1]))["Qw"]
+        ev = np.linalg.eigvalsh(plain)
+        assert np.sum(ev > 1e-9 * max(1.0, ev.max())) == want
+    ms = reduction.solve_master_dense(m)
+    for i, t in enumerate(bounds[:-1]):
+        np.testing.assert_allclose(ms["x"][i], full["x"][t], rtol=1e-9, atol=1e-9)
+        np.testing.assert_allclose(ms["lam"][i], full["lam"][t], rtol=1e-8, atol=1e-8)
+    assert abs(ms["obj"] - full["obj"]) < 1e-9 * max(1, abs(full["obj"]))
+
+
+def test_rank_revealing_stage_depends_on_B_Qinv_Bt_only():
+    """B_hat Qw_hat^{-1} B_hat' of the U_1 stage equals the plain form's
+    S Qbar^{-1} S', and a master whose stages take any other factor of that
+    matrix as B with Q_w = I (here one from an eigendecomposition) has the same
+    solution: the input parametrisation of a master stage does not matter."""
+    nx, nu, N, Ns = 6, 1, 12, 2
+    prob = W.with_costs(W.g2(nx, nu, N, seed=41), seed=6)
+    full = riccati.solve(prob)
+    bounds = list(range(0, N, Ns)) + [N]
+    m = reduction.master_problem_rr(prob, bounds)
+    for i, s in enumerate(m["stages"]):
+        plain = reduction.reduce_closed_form(reduction.sub_problem(prob, bounds[i], bounds[i + 1]))["Qw"]
+        M = s["B"] @ np.linalg.solve(s["Qw"], s["B"].T)
+        np.testing.assert_allclose(M, plain, rtol=1e-9, atol=1e-11 * np.abs(plain).max())
+        ev, U = np.linalg.eigh(plain)
+        keep = ev > 1e-9 * ev.max()
+        s["B"] = U[:, keep] * np.sqrt(ev[keep])
+        s["Qw"] = np.eye(int(keep.sum()))
+        s["nuo"] = int(keep.sum())
+    ms = reduction.solve_master_dense(m)
+    for i, t in enumerate(bounds[:-1]):
+        np.testing.assert_allclose(ms["x"][i], full["x"][t], rtol=1e-9, atol=1e-9)
+    assert abs(ms["obj"] - full["obj"]) < 1e-9 * max(1, abs(full["obj"]))
