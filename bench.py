@@ -164,7 +164,7 @@ def run_precision(prec, args, data, dev):
     n, m, N, B = args.nx, args.nu, args.N, args.batch
     mixed = prec != "fp64"
     pc = {"fp64": rs.RS_FP64, "mixed": rs.RS_MIXED_FP32, "bf16": rs.RS_MIXED_BF16}[prec]
-    batch = rs.Batch(data, precision=pc, Ns=args.Ns, branch=args.branch, device=dev)
+    batch = rs.Batch(data, precision=pc, Ns=args.Ns, branch=args.branch, device=dev, rank_reveal=args.rank_reveal)
     log("[%s] workspace %.2f GB, leaves %d, tree items %d, depth %d" % (
         prec, batch.work_bytes / 1e9, rs.rs_plan_query(batch.plan, 0), rs.rs_plan_query(batch.plan, 1),
         rs.rs_plan_query(batch.plan, 2)))
@@ -223,7 +223,7 @@ def run_precision(prec, args, data, dev):
     else:
         achieved = amount / (avg[dom] * 1e-3) / 1e12
         unit = "TFLOP/s"
-    workload = "uftoc_g2_nx%d_nu%d_N%d_batch%d" % (n, m, N, B)
+    workload = "uftoc_g2_nx%d_nu%d_N%d_batch%d" % (n, m, N, B) + ("_rr" if args.rank_reveal else "")
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": load_traffic(kname, workload + "_" + prec),
                 "kernel": kname, "avg_launch_ms": round(avg[dom], 4),
@@ -233,7 +233,7 @@ def run_precision(prec, args, data, dev):
     lat = None
     if args.latency_reps > 0:
         one = rs.Batch({k: v[:1] for k, v in data.items()}, precision=pc, Ns=args.latency_Ns or args.Ns,
-                       branch=args.latency_branch or args.branch, device=dev)
+                       branch=args.latency_branch or args.branch, device=dev, rank_reveal=args.rank_reveal)
         for _ in range(5):
             one.solve()
         torch.cuda.synchronize()
@@ -350,6 +350,8 @@ def main():
     ap.add_argument("--latency-Ns", type=int, default=16, help="leaf length of the B=1 latency plan")
     ap.add_argument("--latency-branch", type=int, default=4, help="branch of the B=1 latency plan")
     ap.add_argument("--verify", type=int, default=4, help="sampled instances checked against the oracle")
+    ap.add_argument("--rank-reveal", action="store_true",
+                    help="rank-revealing master stages (allows Ns * nu < nx)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
@@ -374,7 +376,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
     n, m, N, B = args.nx, args.nu, args.N, args.batch
-    workload = "uftoc_g2_nx%d_nu%d_N%d_batch%d" % (n, m, N, B)
+    workload = "uftoc_g2_nx%d_nu%d_N%d_batch%d" % (n, m, N, B) + ("_rr" if args.rank_reveal else "")
     log("workload", workload, "Ns", args.Ns, "branch", args.branch)
     t0 = time.perf_counter()
     data = W.g2_torch(n, m, N, B, seed=W.seed_for(5), device=dev)
@@ -395,7 +397,8 @@ def main():
         done, cel, threads = cpu_baseline(host, args.cpu_seconds)
         cpu = {"value": round(done / cel, 3), "unit": "solves/s", "cores": threads, "kind": "oracle",
                "sample": "%d solves of instances %s of the same workload (serial FP64 Riccati, C) "
-                         "in %.1fs on %d host threads" % (done, r["sampled_instances"], cel, threads)}
+                         "in %.1fs on %d host threads" % (done, [int(i) for i in r["sampled_instances"]], cel,
+                                                          threads)}
         log("cpu baseline:", cpu)
 
     out = {
@@ -405,7 +408,7 @@ def main():
         "dtype": {"fp64": "f64", "mixed": "f32+f64", "bf16": "bf16+f32+f64"}[head],
         "data": "synthetic: seeded G2 generator drawn on the device",
         "config": {"workload": workload, "nx": n, "nu": m, "N": N, "batch": B, "Ns": args.Ns,
-                   "branch": args.branch, "precision": head},
+                   "branch": args.branch, "precision": head, "rank_reveal": bool(args.rank_reveal)},
         "latency": r["latency"],
         "max_rel_err_sampled": r["max_rel_err_sampled"],
         "roofline": r["roofline"],

@@ -122,15 +122,30 @@ typedef struct rs_options {
  * per stage more).  Implied by RS_MIXED_FP32. */
 #define RS_PLAN_FACTORED 1
 
+/* rs_options.flags: rank-revealing master stages (Sec. 4.2, the reduction
+ * with a basis U_1 of range(S'), eqs. Bh_def and Gh_Hh_def).  Every reduced
+ * subproblem's M = S Qbar^{-1} S' is factored by Cholesky with diagonal
+ * pivoting, M = B B' up to the rank n_uo = rank(S'), stopped once the
+ * largest remaining pivot is at most n_x eps max_i M_ii (eps of the
+ * precision M was formed in); the master stage takes that B (n_x x n_x, zero
+ * columns after n_uo) as its input matrix and the identity as its input
+ * weight.  It has the same B Q_w^{-1} B' = M as the U_1 stage, hence the same
+ * master solution, and a positive definite G_hat also when Ns*nu < nx (then
+ * allowed, down to Ns = 1) or when a subinterval's inputs leave some state
+ * directions unreached.  Costs one n_x^3 / 3 factorization per leaf and per
+ * master subproblem.  A receding-horizon plan reuses stored M1 messages only
+ * from calls with the same flag. */
+#define RS_PLAN_RANK_REVEAL 2
+
 typedef struct rs_plan_s *rs_plan;
 
 /*
  * Build the tree plan (Alg. 5/6 levels, leaves, work lists) for a batch of
  * `count` instances whose shapes are dims[3*i+0..2] = (nx, nu, N).  Host only:
  * nothing is launched.  Errors: RS_ERR_ARG (count < 1, nx < 1, nu < 1, N < 1,
- * Ns*nu < nx for a multi-leaf instance, which would make the reduced input
- * weight singular, Sec. 4.2 remark), RS_ERR_UNSUPPORTED (no kernel for a
- * shape/precision).
+ * Ns*nu < nx for a multi-leaf instance without RS_PLAN_RANK_REVEAL, which
+ * would make the reduced input weight singular, Sec. 4.2 remark),
+ * RS_ERR_UNSUPPORTED (no kernel for a shape/precision).
  */
 rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *opt,
                          rs_plan *plan_out);

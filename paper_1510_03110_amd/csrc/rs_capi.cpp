@@ -38,6 +38,7 @@ struct Group {
     int64_t ring_stages = 0;                // receding-horizon plans: record stages of the group
     int ring_m1 = 0;                        // and M1 cache blocks (3 n^2 doubles each)
     size_t off_m1 = 0;
+    size_t off_ident = 0;                   // rank-revealing plans: n_x x n_x identity (in the tables)
     // receding-horizon plans: table and slot counts reserved for any window
     // position, so that the workspace size does not depend on it
     int64_t res_leaves = 0, res_items = 0, res_slots = 0;
@@ -53,6 +54,7 @@ struct rs_plan_s {
     bool bf16 = false;              // ... with BF16 matrix-core products in the leaf stages
     bool via_factor = false;        // FP64 solve = stored factorization + solve (large-block shapes)
     bool receding = false;          // receding-horizon layout (rs_plan_create_ring)
+    bool rank_reveal = false;       // rank-revealing master stages (RS_PLAN_RANK_REVEAL)
     rs_options opt{};               // options the plan was made with
     bool tables_dirty = false;      // host tables changed since the last upload
     hipEvent_t tables_ev = nullptr; // completion of the last table upload
@@ -322,6 +324,7 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         P->mixed = opt->precision == RS_MIXED_FP32 || opt->precision == RS_MIXED_BF16;
         P->bf16 = opt->precision == RS_MIXED_BF16;
         P->factored = P->mixed || (opt->flags & RS_PLAN_FACTORED) != 0;
+        P->rank_reveal = (opt->flags & RS_PLAN_RANK_REVEAL) != 0;
         if (opt->Ns > 0) P->Ns = opt->Ns;
         if (opt->branch > 0) P->branch = opt->branch;
         P->max_refine = opt->max_refine > 0 ? opt->max_refine : (P->bf16 ? 20 : 5);
@@ -370,9 +373,10 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
             delete P;
             return RS_ERR_ARG;
         }
-        // a multi-leaf instance needs Ns*nu >= nx or the reduced input weight
-        // Q_w_hat = S Qbar^{-1} S' is singular (Sec. 4.2 remark)
-        if (N > P->inst_Ns[i] && (int64_t)P->inst_Ns[i] * nu < nx) {
+        // without the rank-revealing form a multi-leaf instance needs
+        // Ns*nu >= nx or the reduced input weight Q_w_hat = S Qbar^{-1} S' is
+        // singular (Sec. 4.2 remark)
+        if (!P->rank_reveal && N > P->inst_Ns[i] && (int64_t)P->inst_Ns[i] * nu < nx) {
             delete P;
             return RS_ERR_ARG;
         }
@@ -470,6 +474,10 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         off = align_up(off + sizeof(LeafItem) * std::max<size_t>(g.leaves.size(), (size_t)g.res_leaves));
         g.off_items = off;
         off = align_up(off + sizeof(TreeItem) * std::max<size_t>(g.items.size(), (size_t)g.res_items));
+        if (P->rank_reveal) {
+            g.off_ident = off;
+            off = align_up(off + sizeof(double) * (size_t)g.nx * g.nx);
+        }
     }
     P->off_inst = off;
     off = align_up(off + sizeof(InstInfo) * count);
@@ -529,6 +537,10 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         if (!g.items.empty())
             std::memcpy(P->tables.data() + (g.off_items - P->off_tables), g.items.data(),
                         sizeof(TreeItem) * g.items.size());
+        if (P->rank_reveal) {
+            double *I = reinterpret_cast<double *>(P->tables.data() + (g.off_ident - P->off_tables));
+            for (int i = 0; i < g.nx; ++i) I[(size_t)i * g.nx + i] = 1.0;
+        }
     }
     *out = P;
     return RS_OK;
@@ -785,6 +797,7 @@ static GroupArgs group_args(rs_plan P, char *W, size_t gi, int32_t *info, bool c
     a.lbw = (g.shape->lb && P->factored) ? W + g.off_lbw : nullptr;
     a.lbw_unit = (int64_t)g.lbw_unit;
     a.m1cache = P->receding ? reinterpret_cast<double *>(W + g.off_m1) : nullptr;
+    a.ident = P->rank_reveal ? reinterpret_cast<const double *>(W + g.off_ident) : nullptr;
     a.nx = g.nx;
     a.nu = g.nu;
     if (P->mixed) {

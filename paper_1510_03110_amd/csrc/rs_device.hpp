@@ -256,11 +256,15 @@ __device__ __forceinline__ StageSrc prob_stage(const DevProb &p, int t) {
     return s;
 }
 
-__device__ __forceinline__ StageSrc slot_stage(const double *slot, int n) {
+// A master stage (Sec. 4.3, eq. red_mpc_problem) read from the M1 message
+// in its slot: B = Q_w = Q_w_hat (the form of eq. Qh_Bh_alternative_def), or,
+// with `ident` (an n x n identity), B = the rank-revealing factor written in
+// the Q_w_hat place and Q_w = I (see rank_reveal).
+__device__ __forceinline__ StageSrc slot_stage(const double *slot, int n, const double *ident) {
     const SlotLayout L{n};
     StageSrc s;
     s.Qx = slot + L.Qx();
-    s.Qw = slot + L.Qw();
+    s.Qw = ident ? ident : slot + L.Qw();
     s.Qxw = nullptr;
     s.A = slot + L.A();
     s.B = slot + L.Qw();
@@ -269,6 +273,98 @@ __device__ __forceinline__ StageSrc slot_stage(const double *slot, int n) {
     s.lw = nullptr;
     s.c = slot[L.c()];
     return s;
+}
+
+// Rank-revealing form of a reduced subproblem (Sec. 4.2, eqs. Bh_def and
+// Gh_Hh_def).  The reduction (Alg. 4) leaves M = S Qbar^{-1} S' in `M`
+// (n x n, row-major, positive semidefinite of rank n_uo = rank(S')).  This
+// factors it by Cholesky with diagonal pivoting, M ~= B B' with column c of
+// B the c-th pivot column, and stops once the largest remaining diagonal
+// entry is at most n eps max_i M_ii (the usual stopping rule of pivoted
+// Cholesky; the remaining Schur complement, positive semidefinite, is then
+// below that bound entrywise).  Columns from the rank on are zero.
+// A master stage with input matrix B and input weight I has
+// B I^{-1} B' = M, as does the stage of the U_1 basis
+// (B_hat Q_w_hat^{-1} B_hat' = S Qbar^{-1} S'); a master stage enters the
+// master problem only through that product (minimising its input cost for a
+// given state step), so both master problems have the same states and
+// costates, and G = I + B'PB of the stage is positive definite even when
+// N_s n_u < n_x or the subinterval's inputs leave state directions
+// unreached.  Zero columns are inputs that move nothing and stay 0.
+// B goes to out (and cache if given), row-major n x n; M is overwritten.
+// Every thread of the workgroup calls; thread i owns row i
+// (n <= blockDim.x, n <= 128, at most 16 wavefronts).
+template <class T>
+__device__ __attribute__((noinline)) void rank_reveal(T *M, int n, double eps, double *out, double *cache) {
+    __shared__ double s_val[2][16];
+    __shared__ int s_idx[2][16];
+    const int tid = threadIdx.x, nw = (int)(blockDim.x + 63) >> 6, w = tid >> 6, l = tid & 63;
+    const bool own = tid < n;
+    uint64_t done0 = 0, done1 = 0;            // pivots taken (the same in every thread)
+    auto done = [&](int i) { return (((i < 64) ? (done0 >> i) : (done1 >> (i - 64))) & 1) != 0; };
+    auto put = [&](int i, int c, double v) {
+        out[i * n + c] = v;
+        if (cache) cache[i * n + c] = v;
+    };
+    double tol = 0.0;
+    int c = 0;
+    __syncthreads();
+    for (; c < n; ++c) {
+        // largest remaining diagonal entry; ties go to the smaller index
+        double v = (own && !done(tid)) ? (double)M[tid * n + tid] : -1.0;
+        int p = tid;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double v2 = __shfl_xor(v, o, 64);
+            const int p2 = __shfl_xor(p, o, 64);
+            if (v2 > v || (v2 == v && p2 < p)) {
+                v = v2;
+                p = p2;
+            }
+        }
+        if (l == 0) {
+            s_val[c & 1][w] = v;
+            s_idx[c & 1][w] = p;
+        }
+        __syncthreads();
+        v = s_val[c & 1][0];
+        p = s_idx[c & 1][0];
+        for (int u = 1; u < nw; ++u) {
+            const double v2 = s_val[c & 1][u];
+            const int p2 = s_idx[c & 1][u];
+            if (v2 > v || (v2 == v && p2 < p)) {
+                v = v2;
+                p = p2;
+            }
+        }
+        if (c == 0) tol = (double)n * eps * v;
+        if (!(v > tol)) break;                // rank reached (also an all-zero M)
+        const double s = 1.0 / sqrt(v);
+        if (own) {
+            if (done(tid)) {
+                put(tid, c, 0.0);
+            } else if (tid == p) {
+                put(tid, c, v * s);
+            } else {
+                const double li = (double)M[tid * n + p] * s;
+                put(tid, c, li);
+                for (int k = 0; k < n; ++k)
+                    if (k != p && !done(k)) M[tid * n + k] = (T)((double)M[tid * n + k] - li * ((double)M[p * n + k] * s));
+            }
+        }
+        if (p < 64)
+            done0 |= 1ull << p;
+        else
+            done1 |= 1ull << (p - 64);
+        __syncthreads();
+    }
+    if (own)
+        for (int cc = c; cc < n; ++cc) put(tid, cc, 0.0);
+}
+
+template <class T>
+__device__ __forceinline__ constexpr double unit_roundoff() {
+    return sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
 }
 
 // ---------------------------------------------------------------- LDS
@@ -328,7 +424,7 @@ __device__ __forceinline__ void record_failure(int32_t *info, int inst, int code
 // the update of Alg. 2 (Alg. 4 uses c_hat = cbar_0 without listing it).
 template <class T, int NX, int NU, class Get>
 __device__ void reduce_pass(Smem<T, NX, NU, true> &S, Get get, int count, double *out, int32_t *info,
-                            int inst, int stage_base) {
+                            int inst, int stage_base, bool rr) {
     constexpr int NW = NX + NU;
     const int tid = threadIdx.x;
     count = uni(count);
@@ -449,7 +545,7 @@ __device__ void reduce_pass(Smem<T, NX, NU, true> &S, Get get, int count, double
     for (int e = tid; e < NX * NX; e += NT) {
         const int i = e / NX, j = e % NX;
         out[L.A() + e] = (double)S.V[j * NX + i];     // A_hat = V_0'
-        out[L.Qw() + e] = (double)S.Qh[e];
+        if (!rr) out[L.Qw() + e] = (double)S.Qh[e];
         out[L.Qx() + e] = (double)S.P[e];
     }
     for (int i = tid; i < NX; i += NT) {
@@ -457,6 +553,7 @@ __device__ void reduce_pass(Smem<T, NX, NU, true> &S, Get get, int count, double
         out[L.lx() + i] = -(double)S.Psi[i];
     }
     if (tid == 0) out[L.c()] = (double)S.cbar;
+    if (rr) rank_reveal(S.Qh, NX, unit_roundoff<T>(), out + L.Qw(), nullptr);
 }
 
 // ========================================================= Alg. 1-2 (-3)

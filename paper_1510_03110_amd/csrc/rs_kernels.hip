@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(NT) k_leaf_up(GroupArgs g) {
     auto get = [&](int s) { return prob_stage(p, it.t0 + s); };
     if (!(it.flags & LEAF_LAST)) {
         auto &S = *reinterpret_cast<Smem<T, NX, NU, true> *>(raw);
-        reduce_pass<T, NX, NU>(S, get, it.len, out, g.info, it.inst, it.t0);
+        reduce_pass<T, NX, NU>(S, get, it.len, out, g.info, it.inst, it.t0, g.ident != nullptr);
     } else {
         auto &S = *reinterpret_cast<Smem<T, NX, NU, false> *>(raw);
         const int tid = threadIdx.x;
@@ -199,7 +199,7 @@ __device__ void tree_solve_item(Smem<double, NX, NX, false> &S, const TreeItem &
         S.x[i] = top ? p.x0[i] : msg[SL.xh() + i];
     }
     if (tid == 0) S.cbar = term ? term[SL.c()] : msg[SL.cb()];
-    auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };
+    auto get = [&](int s) { return slot_stage(slot(it.first + s), NX, g.ident); };
     backward_pass<true, double, NX, NX>(
         S, get, it.count, g.info, it.inst, -1, 3,
         [&](int s, auto &Sm) {          // M2 for child s: cost to go at the end of stage s
@@ -273,12 +273,12 @@ __global__ void __launch_bounds__(NT) k_tree(GroupArgs g) {
         const DevProb p = load_prob(g.probs, it.inst);
         double *slots = g.slots;
         auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
-        auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };
+        auto get = [&](int s) { return slot_stage(slot(it.first + s), NX, g.ident); };
         if (inst_skipped(g.probs, it.inst)) {
             // excluded instance: only its completion flag is published
         } else if (it.kind == ITEM_UP) {
             auto &S = *reinterpret_cast<Smem<double, NX, NX, true> *>(raw);
-            reduce_pass<double, NX, NX>(S, get, it.count, slot(it.out_slot), g.info, it.inst, -1);
+            reduce_pass<double, NX, NX>(S, get, it.count, slot(it.out_slot), g.info, it.inst, -1, g.ident != nullptr);
         } else if (it.kind == ITEM_UP_LAST) {
             auto &S = *reinterpret_cast<Smem<double, NX, NX, false> *>(raw);
             const double *term = slot(it.term_slot);

@@ -53,7 +53,7 @@ struct Sizes {
 // Reduce (Alg. 4) and write the M1 message.
 template <int NX, int NU, class Get, class Out = NoEmit>
 __device__ void reduce_to(MSmem<double, NX, NU, true, false> &S, Get get, int count, double *out, int32_t *info, int inst,
-                          int stage_base, int fail_code, Out emit = Out{}) {
+                          int stage_base, int fail_code, bool rr, Out emit = Out{}) {
     const int tid = threadIdx.x;
     for (int e = tid; e < NX * NX; e += NT) {
         S.P[e] = 0.0;
@@ -71,7 +71,7 @@ __device__ void reduce_to(MSmem<double, NX, NU, true, false> &S, Get get, int co
     for (int e = tid; e < NX * NX; e += NT) {
         const int i = e / NX, j = e % NX;
         out[SL.A() + e] = S.V[j * NX + i];     // A_hat = V_0'
-        out[SL.Qw() + e] = S.Qh[e];
+        if (!rr) out[SL.Qw() + e] = S.Qh[e];
         out[SL.Qx() + e] = S.P[e];
     }
     for (int i = tid; i < NX; i += NT) {
@@ -79,6 +79,7 @@ __device__ void reduce_to(MSmem<double, NX, NU, true, false> &S, Get get, int co
         out[SL.lx() + i] = -S.Psi[i];
     }
     if (tid == 0) out[SL.c()] = S.cbar;
+    if (rr) rank_reveal(S.Qh, NX, unit_roundoff<double>(), out + SL.Qw(), nullptr);
 }
 
 // Eliminate a subproblem with known terminal (already in S) and write the
@@ -282,7 +283,8 @@ __global__ void __launch_bounds__(NT, 2) km_leaf_up(GroupArgs g) {
     double *rec = reinterpret_cast<double *>(g.leaf_scratch) + it.scratch;
     if (!(it.flags & LEAF_LAST)) {
         auto &S = *reinterpret_cast<MSmem<double, NX, NU, true, false> *>(raw);
-        reduce_to<NX, NU>(S, get, it.len, out, g.info, it.inst, it.t0, 2, LeafRecOut<NX, NU, true>{{}, rec});
+        reduce_to<NX, NU>(S, get, it.len, out, g.info, it.inst, it.t0, 2, g.ident != nullptr,
+                          LeafRecOut<NX, NU, true>{{}, rec});
     } else {
         auto &S = *reinterpret_cast<MSmem<double, NX, NU, false, false> *>(raw);
         const int tid = threadIdx.x;
@@ -403,7 +405,7 @@ __device__ void tree_solve_m(MSmem<double, NX, NX, false, true> &S, const TreeIt
     }
     if (tid == 0) S.cbar = term ? term[SL.c()] : msg[SL.cb()];
     __syncthreads();
-    auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };
+    auto get = [&](int s) { return slot_stage(slot(it.first + s), NX, g.ident); };
     mfma_pass(
         S, get, it.count, g.info, it.inst, -1, 3,
         [&](int s, auto &Sm) {          // M2 for child s: cost to go at the end of stage s
@@ -474,12 +476,12 @@ __global__ void __launch_bounds__(NT) km_tree(GroupArgs g) {
         const DevProb p = load_prob(g.probs, it.inst);
         double *slots = g.slots;
         auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
-        auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };
+        auto get = [&](int s) { return slot_stage(slot(it.first + s), NX, g.ident); };
         if (inst_skipped(g.probs, it.inst)) {
             // excluded instance: only its completion flag is published
         } else if (it.kind == ITEM_UP) {
             auto &S = *reinterpret_cast<MSmem<double, NX, NX, true, false> *>(raw);
-            reduce_to<NX, NX>(S, get, it.count, slot(it.out_slot), g.info, it.inst, -1, 3);
+            reduce_to<NX, NX>(S, get, it.count, slot(it.out_slot), g.info, it.inst, -1, 3, g.ident != nullptr);
         } else if (it.kind == ITEM_UP_LAST) {
             auto &S = *reinterpret_cast<MSmem<double, NX, NX, false, false> *>(raw);
             const double *term = slot(it.term_slot);
@@ -599,14 +601,15 @@ __global__ void __launch_bounds__(NT, 2) kf_leaf_up(GroupArgs g) {
             const int i = e / NX, j = e % NX;
             const double a = S.V[j * NX + i], q = S.Qh[e], x = S.P[e];
             out[SL.A() + e] = a;
-            out[SL.Qw() + e] = q;
+            if (!g.ident) out[SL.Qw() + e] = q;
             out[SL.Qx() + e] = x;
             if (cache) {
                 cache[SL.A() + e] = a;
-                cache[SL.Qw() + e] = q;
+                if (!g.ident) cache[SL.Qw() + e] = q;
                 cache[SL.Qx() + e] = x;
             }
         }
+        if (g.ident) rank_reveal(S.Qh, NX, unit_roundoff<T>(), out + SL.Qw(), cache ? cache + SL.Qw() : nullptr);
     } else {
         auto &S = *reinterpret_cast<MSmem<T, NX, NU, false, false> *>(raw);
         for (int e = tid; e < NX * NX; e += NT) S.P[e] = (T)p.QxN[e];
@@ -666,7 +669,7 @@ __global__ void __launch_bounds__(NT) kf_tree(GroupArgs g) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         double *slots = g.slots;
         auto slot = [&](int s) { return slots + (int64_t)s * SL.size(); };
-        auto get = [&](int s) { return slot_stage(slot(it.first + s), NX); };
+        auto get = [&](int s) { return slot_stage(slot(it.first + s), NX, g.ident); };
         if (inst_skipped(g.probs, it.inst)) {
             // excluded instance: only its completion flag is published
         } else if (it.kind == ITEM_UP) {
@@ -683,9 +686,10 @@ __global__ void __launch_bounds__(NT) kf_tree(GroupArgs g) {
             for (int e = tid; e < NX * NX; e += NT) {
                 const int i = e / NX, j = e % NX;
                 out[SL.A() + e] = S.V[j * NX + i];
-                out[SL.Qw() + e] = S.Qh[e];
+                if (!g.ident) out[SL.Qw() + e] = S.Qh[e];
                 out[SL.Qx() + e] = S.P[e];
             }
+            if (g.ident) rank_reveal(S.Qh, NX, unit_roundoff<double>(), out + SL.Qw(), nullptr);
         } else if (it.kind == ITEM_UP_LAST) {
             auto &S = *reinterpret_cast<MSmem<double, NX, NX, false, false> *>(raw);
             const double *term = slot(it.term_slot);

@@ -525,14 +525,15 @@ __global__ void __launch_bounds__(LB_MT) kl_leaf_up(GroupArgs g) {
                 const int i = e / n, j = e % n;
                 const double a = (double)S.V[(int64_t)j * n + i], q = (double)S.Qh[e], x = (double)S.P[e];
                 out[SL.A() + e] = a;
-                out[SL.Qw() + e] = q;
+                if (!g.ident) out[SL.Qw() + e] = q;
                 out[SL.Qx() + e] = x;
                 if (cache) {
                     cache[SL.A() + e] = a;
-                    cache[SL.Qw() + e] = q;
+                    if (!g.ident) cache[SL.Qw() + e] = q;
                     cache[SL.Qx() + e] = x;
                 }
             }
+            if (g.ident) rank_reveal(S.Qh, n, unit_roundoff<T>(), out + SL.Qw(), cache ? cache + SL.Qw() : nullptr);
         } else {
             for (int e = tid; e < n * n; e += nthr()) S.P[e] = (T)p.QxN[e];
             __syncthreads();
@@ -610,7 +611,7 @@ __global__ void __launch_bounds__(LB_MT) kl_tree(GroupArgs g) {
         if (idx >= g.nitems) break;
         const TreeItem it = load_item(g.items, idx);
         wait_deps(g, it);
-        auto get = [&](int s) { return slot_stage(slot(it.first + s), n); };
+        auto get = [&](int s) { return slot_stage(slot(it.first + s), n, g.ident); };
         if (inst_skipped(g.probs, it.inst)) {
             // excluded instance: only its completion flag is published
         } else if (it.kind == ITEM_UP) {
@@ -621,9 +622,10 @@ __global__ void __launch_bounds__(LB_MT) kl_tree(GroupArgs g) {
             for (int e = tid; e < n * n; e += nthr()) {
                 const int i = e / n, j = e % n;
                 out[SL.A() + e] = S.V[(int64_t)j * n + i];
-                out[SL.Qw() + e] = S.Qh[e];
+                if (!g.ident) out[SL.Qw() + e] = S.Qh[e];
                 out[SL.Qx() + e] = S.P[e];
             }
+            if (g.ident) rank_reveal(S.Qh, n, unit_roundoff<double>(), out + SL.Qw(), nullptr);
         } else if (it.kind == ITEM_UP_LAST) {
             const double *term = slot(it.term_slot);
             for (int e = tid; e < n * n; e += nthr()) S.P[e] = term[SL.Qx() + e];

@@ -150,6 +150,9 @@ struct GroupArgs {
     // receding-horizon plans: per interior ring block, the matrix part of the
     // leaf's M1 message (A_hat | Q_w_hat | Q_x_hat, 3 n^2 doubles)
     double *m1cache;
+    // rank-revealing master stages: an n_x x n_x identity (the master input
+    // weight), nullptr for the plain form B = Q_w = Q_w_hat
+    const double *ident;
 };
 
 }  // namespace rs

@@ -19,6 +19,7 @@ RS_OK, RS_ERR_ARG, RS_ERR_NOT_SPD, RS_ERR_SINGULAR_MASTER, RS_ERR_NOT_CONVERGED,
     RS_ERR_NOMEM, RS_ERR_HIP, RS_ERR_UNSUPPORTED = range(8)
 RS_FP64, RS_MIXED_FP32, RS_MIXED_BF16 = 0, 1, 2
 RS_PLAN_FACTORED = 1
+RS_PLAN_RANK_REVEAL = 2
 RS_PROB_SKIP = 1
 RS_KERNEL_KINDS = 16
 
@@ -139,12 +140,12 @@ def rs_plan_create(dims, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.
     return h
 
 
-def rs_plan_create_ring(dims8, precision=RS_FP64, max_refine=0, tol=0.0):
+def rs_plan_create_ring(dims8, precision=RS_FP64, max_refine=0, tol=0.0, flags=0):
     """Receding-horizon plan: dims8 rows (nx, nu, N, Ns, branch, start,
     reuse_lo, reuse_hi); see ring_current_leaves for the reuse range a call
     leaves behind."""
     arr = np.ascontiguousarray(np.asarray(dims8, dtype=np.int32).reshape(-1, 8))
-    opt = rs_options(precision, 0, 0, max_refine, tol, 0, 0)
+    opt = rs_options(precision, 0, 0, max_refine, tol, flags, 0)
     h = _P()
     st = library().rs_plan_create_ring(arr.shape[0], arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                        ctypes.byref(opt), ctypes.byref(h))
@@ -270,11 +271,14 @@ class Batch:
     Outputs ``x``, ``w``, ``lam``, ``obj`` are allocated here.  Time-invariant
     matrices may be given with a stage axis of length 1; they are passed with
     stride 0.  ``factored=True`` reserves the stored factorization so that
-    ``factor()`` / ``solve_factored()`` can be used.
+    ``factor()`` / ``solve_factored()`` can be used.  ``rank_reveal=True``
+    gives the master problems rank-revealing stages (RS_PLAN_RANK_REVEAL), so
+    that leaves with Ns * nu < nx, or whose inputs leave state directions
+    unreached, are allowed.
     """
 
     def __init__(self, data, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.0,
-                 device="cuda", factored=False, per_instance=None):
+                 device="cuda", factored=False, per_instance=None, rank_reveal=False):
         import torch
         self.torch = torch
         keys = set(data)
@@ -301,7 +305,8 @@ class Batch:
         self.info = torch.zeros(2 * self.count, dtype=torch.int32, device=device)
         pdims = dims if per_instance is None else [d + tuple(pi) for d, pi in zip(dims, per_instance)]
         self.plan = rs_plan_create(pdims, precision, Ns, branch, max_refine, tol,
-                                   RS_PLAN_FACTORED if factored else 0)
+                                   (RS_PLAN_FACTORED if factored else 0) |
+                                   (RS_PLAN_RANK_REVEAL if rank_reveal else 0))
         self.graphs = []
         self.work_bytes = rs_plan_workspace_size(self.plan)
         self.work = torch.empty(self.work_bytes + 256, dtype=torch.uint8, device=device)

@@ -71,16 +71,20 @@ def _solve(rs, torch, seq, plan, work, s, out):
     return int(info[0])
 
 
-@pytest.mark.parametrize("prec,nx,nu,N,Ns", [(0, 32, 16, 150, 16), (1, 32, 16, 150, 16), (0, 64, 32, 70, 8),
-                                             (1, 16, 8, 90, 8), (0, 16, 16, 40, 16), (1, 64, 32, 50, 8)])
-def test_receding_horizon_reuse(prec, nx, nu, N, Ns):
+@pytest.mark.parametrize("prec,nx,nu,N,Ns,rr", [(0, 32, 16, 150, 16, 0), (1, 32, 16, 150, 16, 0), (0, 64, 32, 70, 8, 0),
+                                                (1, 16, 8, 90, 8, 0), (0, 16, 16, 40, 16, 0), (1, 64, 32, 50, 8, 0),
+                                                (0, 32, 16, 60, 1, 1), (1, 16, 8, 40, 1, 1), (0, 64, 16, 40, 2, 1)])
+def test_receding_horizon_reuse(prec, nx, nu, N, Ns, rr):
+    """rr: rank-revealing master stages (leaves with Ns * nu < nx); the
+    stored M1 messages then hold the rank-revealing factor."""
     torch, rs = _rs()
+    flags = rs.RS_PLAN_RANK_REVEAL if rr else 0
     K = 2 * Ns + 3
     seq = _Seq(torch, rs, W.with_costs(W.g2(nx, nu, N + K, seed=nx + N + prec), seed=3), N)
     lo, hi = 0, 0
     # one plan moved along the sequence (odd instantiations: a new plan per
     # window on the same workspace); both keep the stored factorization
-    keep = rs.rs_plan_create_ring([(nx, nu, N, Ns, 4, 0, 0, 0)], precision=prec)
+    keep = rs.rs_plan_create_ring([(nx, nu, N, Ns, 4, 0, 0, 0)], precision=prec, flags=flags)
     size = rs.rs_plan_workspace_size(keep)
     work = torch.empty(size + 256, dtype=torch.uint8, device="cuda")
     fresh = torch.empty(size + 256, dtype=torch.uint8, device="cuda")
@@ -89,7 +93,7 @@ def test_receding_horizon_reuse(prec, nx, nu, N, Ns):
             rs.rs_plan_ring_update(keep, [(nx, nu, N, Ns, 4, s, lo, hi)])
             plan = keep
         else:
-            plan = rs.rs_plan_create_ring([(nx, nu, N, Ns, 4, s, lo, hi)], precision=prec)
+            plan = rs.rs_plan_create_ring([(nx, nu, N, Ns, 4, s, lo, hi)], precision=prec, flags=flags)
         try:
             assert rs.rs_plan_workspace_size(plan) == size
             out = seq.outputs()
@@ -105,7 +109,7 @@ def test_receding_horizon_reuse(prec, nx, nu, N, Ns):
                 rs.rs_plan_destroy(plan)
         if s % 4 == 3 or s == K - 1:
             # the same window factored from scratch on a fresh workspace
-            plan = rs.rs_plan_create_ring([(nx, nu, N, Ns, 4, s, 0, 0)], precision=prec)
+            plan = rs.rs_plan_create_ring([(nx, nu, N, Ns, 4, s, 0, 0)], precision=prec, flags=flags)
             try:
                 out2 = seq.outputs()
                 fresh.zero_()

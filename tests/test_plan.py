@@ -166,6 +166,29 @@ def test_plan_rejects_bad_arguments():
     rs.rs_plan_destroy(p)
 
 
+def test_rank_revealing_plan_allows_short_leaves():
+    """With RS_PLAN_RANK_REVEAL the master stages take a rank-revealing
+    factor of the reduced input weight, so Ns * nu < nx is allowed (down to
+    Ns = 1); the plan adds one nx x nx identity per shape group (the master
+    input weight) to the uploaded tables."""
+    for dims, Ns in (([(4, 1, 64)], 2), ([(4, 2, 3)], 1), ([(32, 16, 100), (128, 64, 40)], 1)):
+        with pytest.raises(rs.RsError):
+            rs.rs_plan_create(dims, Ns=Ns)
+        p = rs.rs_plan_create(dims, Ns=Ns, flags=rs.RS_PLAN_RANK_REVEAL)
+        rs.rs_plan_destroy(p)
+    dims = [(32, 16, 256), (20, 10, 100)]
+    p0 = rs.rs_plan_create(dims, Ns=8, branch=4)
+    p1 = rs.rs_plan_create(dims, Ns=8, branch=4, flags=rs.RS_PLAN_RANK_REVEAL)
+    try:
+        extra = rs.rs_plan_workspace_size(p1) - rs.rs_plan_workspace_size(p0)
+        assert 8 * (32 * 32 + 20 * 20) <= extra <= 8 * (32 * 32 + 20 * 20) + 2 * 256
+    finally:
+        rs.rs_plan_destroy(p0)
+        rs.rs_plan_destroy(p1)
+    r = rs.rs_plan_create_ring([(32, 16, 64, 1, 4, 0, 0, 0)], flags=rs.RS_PLAN_RANK_REVEAL)
+    rs.rs_plan_destroy(r)
+
+
 def test_factored_plan_workspace_and_shape_support():
     """The stored factorization adds LeafRec doubles per leaf stage."""
     dims = [(32, 16, 1024)]
