@@ -330,6 +330,56 @@ def ingest_counters(fetch_csv, write_csv, copy_bytes, workload):
         log("%-14s %-45s %.3f GB/launch" % (r["kernel"], r["workload"], r["bytes_per_launch"] / 1e9))
 
 
+def run_ip(args):
+    """Interior-point mode: one problem of the workload's shape (G2) with
+    bounds on every input at +-0.3 of the largest |w| of its unconstrained
+    solution (solved on the GPU first), solved by the Mehrotra iteration on the
+    factor / solve split (one rs_factor and two rs_solve per iteration) with
+    the single-instance tree (--latency-Ns, --latency-branch).  Prints one
+    JSON line: solves/s, iterations, ms per iteration, active bounds."""
+    import numpy as np
+    import torch
+    from paper_1510_03110_amd import ip, rs
+    from paper_1510_03110_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    n, m, N = args.nx, args.nu, args.N
+    prec = "mixed" if args.precision == "mixed" else "fp64"
+    pc = rs.RS_MIXED_FP32 if prec == "mixed" else rs.RS_FP64
+    Ns, br = args.latency_Ns or args.Ns, args.latency_branch or args.branch
+    prob = W.g2(n, m, N, seed=W.seed_for(6))
+    one = rs.Batch({k: [prob[k]] for k in prob}, precision=pc, Ns=Ns, branch=br)
+    one.solve()
+    torch.cuda.synchronize()
+    scale = float(np.abs(one.result(0)["w"]).max())
+    one.close()
+    lo, hi = np.full((N, m), -0.3 * scale), np.full((N, m), 0.3 * scale)
+    box = ip.BoxIP(prob, lo, hi, precision=pc, Ns=Ns, branch=br)
+    for _ in range(args.warmup):
+        box.solve(tol=1e-9)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = 0
+    for _ in range(args.steps):
+        r = box.solve(tol=1e-9)
+        its += r["iterations"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    box.close()
+    act = int((np.isclose(r["w"], lo, atol=1e-7) | np.isclose(r["w"], hi, atol=1e-7)).sum())
+    out = {"metric": "box-constrained P(N) solves/s by the interior-point method", "value": round(args.steps / el, 3),
+           "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1e3 * el / args.steps, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if prec == "fp64" else "f32+f64",
+           "data": "synthetic: seeded G2 generator, bounds +-0.3 max |w| of the unconstrained solution",
+           "config": {"workload": "uftoc_g2_box_nx%d_nu%d_N%d" % (n, m, N), "Ns": Ns, "branch": br,
+                      "precision": prec},
+           "iterations_per_solve": its / args.steps, "ms_per_iteration": round(1e3 * el / max(its, 1), 4),
+           "active_bounds": act, "final_residual": r["history"][-1][0], "final_mu": r["history"][-1][1],
+           "status": r["status"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,6 +400,8 @@ def main():
     ap.add_argument("--latency-Ns", type=int, default=16, help="leaf length of the B=1 latency plan")
     ap.add_argument("--latency-branch", type=int, default=4, help="branch of the B=1 latency plan")
     ap.add_argument("--verify", type=int, default=4, help="sampled instances checked against the oracle")
+    ap.add_argument("--ip", action="store_true",
+                    help="interior-point mode: one problem with input bounds (see run_ip)")
     ap.add_argument("--rank-reveal", action="store_true",
                     help="rank-revealing master stages (allows Ns * nu < nx)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -369,6 +421,9 @@ def main():
         print("bench.py measures one GPU only: sharding instances or a horizon across GPUs is designed "
               "but not built; --gpus %d is not supported." % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.ip:
+        run_ip(args)
+        return
 
     import torch
     from paper_1510_03110_amd import workloads as W

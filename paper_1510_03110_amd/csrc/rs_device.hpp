@@ -362,6 +362,79 @@ __device__ __attribute__((noinline)) void rank_reveal(T *M, int n, double eps, d
         for (int cc = c; cc < n; ++cc) put(tid, cc, 0.0);
 }
 
+// The same factorization for n <= NM <= 64 (NM known at compile time): the
+// thread of row i keeps that row in registers, the pivot column goes through
+// a short LDS vector, and M is only read.
+template <int NM, class T>
+__device__ __attribute__((noinline)) void rank_reveal_rows(const T *M, int n, double eps, double *out,
+                                                           double *cache) {
+    static_assert(NM >= 1 && NM <= 64, "one register row of at most 64");
+    __shared__ double s_val[16], s_l[NM];
+    __shared__ int s_idx[16];
+    const int tid = threadIdx.x, nw = (int)(blockDim.x + 63) >> 6, w = tid >> 6, l = tid & 63;
+    const bool own = tid < n;
+    auto put = [&](int i, int c, double v) {
+        out[i * n + c] = v;
+        if (cache) cache[i * n + c] = v;
+    };
+    double r[NM];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NM; ++k) r[k] = (own && k < n) ? (double)M[tid * n + k] : 0.0;
+    uint64_t done = 0;                        // pivots taken (the same in every thread)
+    double tol = 0.0;
+    int c = 0;
+    for (; c < n; ++c) {
+        const bool live = own && !((done >> tid) & 1);
+        double d = 0.0;
+#pragma unroll
+        for (int k = 0; k < NM; ++k) d = (k == tid) ? r[k] : d;
+        double v = live ? d : -1.0;
+        int p = tid;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double v2 = __shfl_xor(v, o, 64);
+            const int p2 = __shfl_xor(p, o, 64);
+            if (v2 > v || (v2 == v && p2 < p)) {
+                v = v2;
+                p = p2;
+            }
+        }
+        if (l == 0) {
+            s_val[w] = v;
+            s_idx[w] = p;
+        }
+        __syncthreads();
+        v = s_val[0];
+        p = s_idx[0];
+        for (int u = 1; u < nw; ++u) {
+            const double v2 = s_val[u];
+            const int p2 = s_idx[u];
+            if (v2 > v || (v2 == v && p2 < p)) {
+                v = v2;
+                p = p2;
+            }
+        }
+        if (c == 0) tol = (double)n * eps * v;
+        if (!(v > tol)) break;                // rank reached (also an all-zero M)
+        const double s = 1.0 / sqrt(v);
+        double rp = 0.0;
+#pragma unroll
+        for (int k = 0; k < NM; ++k) rp = (k == p) ? r[k] : rp;
+        const double li = (live && tid != p) ? rp * s : 0.0;
+        if (own) put(tid, c, !live ? 0.0 : (tid == p ? v * s : li));
+        if (tid < NM) s_l[tid] = li;          // 0 for the pivot row and rows already taken
+        __syncthreads();
+        if (live && tid != p) {
+#pragma unroll
+            for (int k = 0; k < NM; ++k) r[k] -= li * s_l[k];
+        }
+        done |= 1ull << p;
+    }
+    if (own)
+        for (int cc = c; cc < n; ++cc) put(tid, cc, 0.0);
+}
+
 template <class T>
 __device__ __forceinline__ constexpr double unit_roundoff() {
     return sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
@@ -553,7 +626,7 @@ __device__ void reduce_pass(Smem<T, NX, NU, true> &S, Get get, int count, double
         out[L.lx() + i] = -(double)S.Psi[i];
     }
     if (tid == 0) out[L.c()] = (double)S.cbar;
-    if (rr) rank_reveal(S.Qh, NX, unit_roundoff<T>(), out + L.Qw(), nullptr);
+    if (rr) rank_reveal_rows<NX>(S.Qh, NX, unit_roundoff<T>(), out + L.Qw(), nullptr);
 }
 
 // ========================================================= Alg. 1-2 (-3)

@@ -79,7 +79,7 @@ __device__ void reduce_to(MSmem<double, NX, NU, true, false> &S, Get get, int co
         out[SL.lx() + i] = -S.Psi[i];
     }
     if (tid == 0) out[SL.c()] = S.cbar;
-    if (rr) rank_reveal(S.Qh, NX, unit_roundoff<double>(), out + SL.Qw(), nullptr);
+    if (rr) rank_reveal_rows<NX>(S.Qh, NX, unit_roundoff<double>(), out + SL.Qw(), nullptr);
 }
 
 // Eliminate a subproblem with known terminal (already in S) and write the
@@ -609,7 +609,7 @@ __global__ void __launch_bounds__(NT, 2) kf_leaf_up(GroupArgs g) {
                 cache[SL.Qx() + e] = x;
             }
         }
-        if (g.ident) rank_reveal(S.Qh, NX, unit_roundoff<T>(), out + SL.Qw(), cache ? cache + SL.Qw() : nullptr);
+        if (g.ident) rank_reveal_rows<NX>(S.Qh, NX, unit_roundoff<T>(), out + SL.Qw(), cache ? cache + SL.Qw() : nullptr);
     } else {
         auto &S = *reinterpret_cast<MSmem<T, NX, NU, false, false> *>(raw);
         for (int e = tid; e < NX * NX; e += NT) S.P[e] = (T)p.QxN[e];
@@ -689,7 +689,7 @@ __global__ void __launch_bounds__(NT) kf_tree(GroupArgs g) {
                 if (!g.ident) out[SL.Qw() + e] = S.Qh[e];
                 out[SL.Qx() + e] = S.P[e];
             }
-            if (g.ident) rank_reveal(S.Qh, NX, unit_roundoff<double>(), out + SL.Qw(), nullptr);
+            if (g.ident) rank_reveal_rows<NX>(S.Qh, NX, unit_roundoff<double>(), out + SL.Qw(), nullptr);
         } else if (it.kind == ITEM_UP_LAST) {
             auto &S = *reinterpret_cast<MSmem<double, NX, NX, false, false> *>(raw);
             const double *term = slot(it.term_slot);
