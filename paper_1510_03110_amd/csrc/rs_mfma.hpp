@@ -251,8 +251,9 @@ __device__ __forceinline__ void phaseB_tile(int t, int &kind, int &ti, int &tj) 
     }
 }
 
+// The next stage's A, B and vectors (loaded at the start of a stage) ...
 template <class T, int NX, int NU>
-__device__ __forceinline__ void prefetch_stage(Prefetch<T, NX, NU> &pf, const StageSrc &s) {
+__device__ __forceinline__ void prefetch_mats(Prefetch<T, NX, NU> &pf, const StageSrc &s) {
     using PF = Prefetch<T, NX, NU>;
     const int tid = threadIdx.x;
 #pragma unroll
@@ -269,6 +270,14 @@ __device__ __forceinline__ void prefetch_stage(Prefetch<T, NX, NU> &pf, const St
     pf.lx = (tid < NX && s.lx) ? (T)gload(s.lx + tid) : T(0);
     pf.lw = (tid < NU && s.lw) ? (T)gload(s.lw + tid) : T(0);
     pf.c = (T)s.c;
+}
+
+// ... and its Qx / Qxw' / Qw tiles, loaded once this stage's tiles are no
+// longer needed (after phase C), so that the two sets of tiles are never live
+// together; their loads still have phases D and E to arrive.
+template <class T, int NX, int NU>
+__device__ __forceinline__ void prefetch_q(Prefetch<T, NX, NU> &pf, const StageSrc &s) {
+    using PF = Prefetch<T, NX, NU>;
     const int w = wave();
 #pragma unroll
     for (int t = 0; t < PF::TILES; ++t) {
@@ -283,6 +292,12 @@ __device__ __forceinline__ void prefetch_stage(Prefetch<T, NX, NU> &pf, const St
         });
         pf.q[PF::slot(t)] = q;
     }
+}
+
+template <class T, int NX, int NU>
+__device__ __forceinline__ void prefetch_stage(Prefetch<T, NX, NU> &pf, const StageSrc &s) {
+    prefetch_mats(pf, s);
+    prefetch_q(pf, s);
 }
 
 template <class T, int NX, int NU, bool RED, bool SOLVE>
@@ -345,13 +360,17 @@ __device__ __forceinline__ int chol_inv_wave(T *G, T *LiT) {
 #pragma unroll
         for (int k = j + 1; k < M; ++k) g[k] -= lij * bcast_lane(lij, k);
     }
-    // lane c: column c of L^{-1}, from L x = e_c
+    // lane c: column c of L^{-1}, from L x = e_c.  x starts at zero and its
+    // c-th entry is set to 1 / L[c][c] at step c (where e_c would be scaled),
+    // so no lane-dependent start vector is formed ahead of time (such a
+    // vector, invariant across stages, is otherwise kept in scratch).
     T x[M];
 #pragma unroll
-    for (int i = 0; i < M; ++i) x[i] = (ln == i) ? T(1) : T(0);
+    for (int i = 0; i < M; ++i) x[i] = T(0);
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-        x[k] *= bcast_lane(invd, k);
+        const T ik = bcast_lane(invd, k);
+        x[k] = (ln == k) ? ik : x[k] * ik;
 #pragma unroll
         for (int i = k + 1; i < M; ++i) x[i] -= bcast_lane(g[k], i) * x[k];
     }
@@ -489,7 +508,9 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
     // the only wait for the loads does not also wait for those stores.
     for (int s = count - 1; s >= 0; --s) {
         // stage s inputs: A, B, a, lx, lw, c in LDS; Qx/Qxw'/Qw tiles in qt
-        if (s > 0) prefetch_stage<T, NX, NU>(pf, get(s - 1));
+        // the next stage's source (pointers and c), formed once per stage
+        const StageSrc nxt = s > 0 ? get(s - 1) : StageSrc{};
+        if (s > 0) prefetch_mats<T, NX, NU>(pf, nxt);
         pre(s, S);
         using TT = Tiles<NX, NU>;
         v4_t<T> fkeep[TT::PER_WAVE_F];      // F tiles of this wave (merged phase)
@@ -679,6 +700,7 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
                 }
             }
         }
+        if (s > 0) prefetch_q<T, NX, NU>(pf, nxt);
         lds_sync();
         if (tid == 0 && S.bad) {
             record_failure(info, inst, fail_code, stage_base < 0 ? -1 : stage_base + s);
@@ -731,12 +753,8 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
                             const T v = fv[r] - acc[r];
                             S.P[i * NX + j] = v;
                             S.P[j * NX + i] = v;
-                            if constexpr (PEMIT) {
-                                out.P(s, i, j, v);
-                                if (i != j) out.P(s, j, i, v);
-                            }
                         }
-                    });
+                    });          // the P_t record is written from LDS after the stage
                 }
             }
             // the other tiles in wave order 0, 3, 2, 1 when the F owners
@@ -820,6 +838,12 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
             }
         }
         lds_sync();
+        if constexpr (PEMIT && TT::FAST) {
+            // P_t record row by row from LDS: consecutive threads store
+            // consecutive elements, and no per-tile store offsets stay live
+            // across the stage (S.P is next written in the next phase E)
+            for (int e = tid; e < NX * NX; e += NT) out.P(s, e / NX, e % NX, S.P[e]);
+        }
     }
 }
 
