@@ -162,6 +162,25 @@ rs_status rs_plan_create_ex(int32_t count, const int32_t *dims5, const rs_option
                             rs_plan *plan_out);
 
 /*
+ * Plan with subintervals and master groups of chosen sizes (Sec. 4.1: the
+ * subintervals i = 0..p need not have equal lengths N_i; Alg. 5: each level's
+ * master problem is split into batches of any size).  For instance i,
+ * dims[3*i+0..2] = (nx, nu, N); its leaf lengths, in stage order, are
+ * leaf_len[leaf_off[i] .. leaf_off[i+1]) (each >= 1, summing to N; the last
+ * leaf carries the terminal cost); its master group sizes for levels 1, 2,
+ * ... are branch[branch_off[i] .. branch_off[i+1]) (each >= 2, at least one;
+ * the last repeats for deeper levels, and a level with at most that many
+ * stages is the top problem).  leaf_off and branch_off have count + 1
+ * entries.  opt.Ns and opt.branch are not used.  Host only.  Errors as
+ * rs_plan_create, and RS_ERR_ARG when the lengths do not sum to N, a length
+ * or group size is out of range, or, without RS_PLAN_RANK_REVEAL, a leaf
+ * other than the last has length * nu < nx.
+ */
+rs_status rs_plan_create_split(int32_t count, const int32_t *dims, const int32_t *leaf_off,
+                               const int32_t *leaf_len, const int32_t *branch_off,
+                               const int32_t *branch, const rs_options *opt, rs_plan *plan_out);
+
+/*
  * Receding-horizon plan (serving): dims8 holds per instance
  *   (nx, nu, N, Ns, branch, start, reuse_lo, reuse_hi)
  * where `start` >= 0 is the absolute index of the window's first stage.  The

@@ -66,6 +66,9 @@ struct rs_plan_s {
     double tol = 1e-10;
     std::vector<int32_t> dims;          // (nx, nu, N) per instance
     std::vector<int32_t> inst_Ns, inst_branch;   // leaf length and branch per instance
+    // rs_plan_create_split: leaf lengths and per-level master group sizes per
+    // instance (empty: uniform Ns and branch)
+    std::vector<std::vector<int32_t>> inst_lens, inst_brs;
     std::vector<Group> groups;
     size_t off_probs = 0, off_info = 0, off_queues = 0, off_tables = 0, tables_bytes = 0;
     size_t total = 0;
@@ -110,7 +113,33 @@ struct Tmp {
     bool dep_top;
 };
 
-void build_tree(Group &g, int inst, int L0, int base1, int b, int top_max, std::vector<Tmp> &tmp);
+void build_tree(Group &g, int inst, int L0, int base1, int b, int top_max, std::vector<Tmp> &tmp,
+                const std::vector<int32_t> *brs = nullptr);
+
+// Leaves of the given lengths (in stage order, summing to N) and master
+// levels whose group size is brs[level - 1] (the last entry for deeper
+// levels; the top problem of a level takes up to that many stages).
+void build_instance_split(Group &g, int inst, const std::vector<int32_t> &lens, const std::vector<int32_t> &brs,
+                          std::vector<Tmp> &tmp) {
+    const int L0 = (int)lens.size();
+    const int sps = g.shape->scratch_per_stage;
+    if (L0 == 1) {
+        LeafItem lf{inst, 0, lens[0], LEAF_LAST | LEAF_TOP, -1, 0, g.scratch_elems};
+        g.leaves.push_back(lf);
+        g.scratch_elems += (int64_t)lens[0] * sps;
+        return;
+    }
+    const int base1 = (int)g.nslots;
+    g.nslots += L0;
+    int t0 = 0;
+    for (int i = 0; i < L0; ++i) {
+        LeafItem lf{inst, t0, lens[i], i == L0 - 1 ? LEAF_LAST : 0, base1 + i, 0, g.scratch_elems};
+        g.leaves.push_back(lf);
+        g.scratch_elems += (int64_t)lens[i] * sps;
+        t0 += lens[i];
+    }
+    build_tree(g, inst, L0, base1, 0, 0, tmp, &brs);
+}
 
 void build_instance(Group &g, int inst, int N, int Ns, int b, int top_max, std::vector<Tmp> &tmp) {
     const int L0 = (N + Ns - 1) / Ns;
@@ -173,10 +202,15 @@ void build_instance_ring(Group &g, int inst, int N, int Ns, int b, int top_max, 
     build_tree(g, inst, L0, base1, b, top_max, tmp);
 }
 
-void build_tree(Group &g, int inst, int L0, int base1, int b, int top_max, std::vector<Tmp> &tmp) {
+void build_tree(Group &g, int inst, int L0, int base1, int b, int top_max, std::vector<Tmp> &tmp,
+                const std::vector<int32_t> *brs) {
+    // group size and largest top problem of a level (uniform unless brs)
+    auto br = [&](int lev) { return brs ? (*brs)[std::min<size_t>((size_t)lev - 1, brs->size() - 1)] : b; };
+    auto tmx = [&](int lev) { return brs ? br(lev) : top_max; };
     int level = 1, S = L0 - 1, lvl_base = base1, prev_nodes = L0;
     for (;;) {
-        if (S <= top_max) {
+        const int bl = br(level);
+        if (S <= tmx(level)) {
             Tmp t{};
             t.it = TreeItem{ITEM_TOP, inst, level, lvl_base, S, 1, lvl_base + S, -1, 0, 0};
             t.phase = 0;
@@ -190,14 +224,15 @@ void build_tree(Group &g, int inst, int L0, int base1, int b, int top_max, std::
             g.max_depth = std::max(g.max_depth, level);
             break;
         }
-        const int Lk = (S + b - 1) / b;
+        const int Lk = (S + bl - 1) / bl;
         const int nb = (int)g.nslots;
         g.nslots += Lk;
         const int Lnext = Lk - 1;                 // stages at the next level
-        const bool next_is_top = Lnext <= top_max;
-        const int Lnext_nodes = next_is_top ? 1 : (Lnext + b - 1) / b;
+        const int bn = br(level + 1);
+        const bool next_is_top = Lnext <= tmx(level + 1);
+        const int Lnext_nodes = next_is_top ? 1 : (Lnext + bn - 1) / bn;
         for (int j = 0; j < Lk; ++j) {
-            const int first = lvl_base + j * b, count = std::min(b, S - j * b);
+            const int first = lvl_base + j * bl, count = std::min(bl, S - j * bl);
             const int last = (j == Lk - 1) ? 1 : 0;
             Tmp u{};
             u.it = TreeItem{last ? ITEM_UP_LAST : ITEM_UP, inst, level, first, count, last,
@@ -207,15 +242,15 @@ void build_tree(Group &g, int inst, int L0, int base1, int b, int top_max, std::
             u.inst = inst;
             u.node = j;
             u.dep_level = level - 1;
-            u.dep_lo = j * b;
-            u.dep_hi = level > 1 ? j * b + count + last : 0;
+            u.dep_lo = j * bl;
+            u.dep_hi = level > 1 ? j * bl + count + last : 0;
             tmp.push_back(u);
             Tmp d = u;
             d.it.kind = ITEM_DOWN;
             d.phase = 1;
             d.dep_level = level + 1;
             d.dep_top = next_is_top;
-            d.dep_lo = next_is_top ? 0 : std::min(j / b, Lnext_nodes - 1);
+            d.dep_lo = next_is_top ? 0 : std::min(j / bn, Lnext_nodes - 1);
             d.dep_hi = d.dep_lo + 1;
             tmp.push_back(d);
         }
@@ -306,7 +341,8 @@ const char *rs_status_string(rs_status s) {
 }
 
 static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, const rs_options *opt,
-                             rs_plan *out) {
+                             rs_plan *out, const int32_t *leaf_off = nullptr, const int32_t *leaf_len = nullptr,
+                             const int32_t *branch_off = nullptr, const int32_t *branch = nullptr) {
     if (!out || !dims_in || count < 1) return RS_ERR_ARG;
     *out = nullptr;
     rs_plan_s *P = new (std::nothrow) rs_plan_s();
@@ -335,6 +371,8 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
     P->count = count;
     P->dims.resize(3 * (size_t)count);
     P->inst_Ns.resize(count);
+    P->inst_lens.resize(count);
+    P->inst_brs.resize(count);
     P->inst_branch.resize(count);
     for (int i = 0; i < count; ++i) {
         for (int k = 0; k < 3; ++k) P->dims[3 * i + k] = dims_in[(size_t)stride * i + k];
@@ -376,7 +414,29 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         // without the rank-revealing form a multi-leaf instance needs
         // Ns*nu >= nx or the reduced input weight Q_w_hat = S Qbar^{-1} S' is
         // singular (Sec. 4.2 remark)
-        if (!P->rank_reveal && N > P->inst_Ns[i] && (int64_t)P->inst_Ns[i] * nu < nx) {
+        if (leaf_off) {
+            const int nl = leaf_off[i + 1] - leaf_off[i], nbr = branch_off[i + 1] - branch_off[i];
+            if (nl < 1 || nbr < 1) {
+                delete P;
+                return RS_ERR_ARG;
+            }
+            std::vector<int32_t> lens(leaf_len + leaf_off[i], leaf_len + leaf_off[i + 1]);
+            std::vector<int32_t> brs(branch + branch_off[i], branch + branch_off[i + 1]);
+            int64_t sum = 0;
+            bool ok = true;
+            for (int k = 0; k < nl; ++k) {
+                ok = ok && lens[k] >= 1;
+                sum += lens[k];
+                if (!P->rank_reveal && nl > 1 && k < nl - 1 && (int64_t)lens[k] * nu < nx) ok = false;
+            }
+            for (int32_t v : brs) ok = ok && v >= 2;
+            if (!ok || sum != N) {
+                delete P;
+                return RS_ERR_ARG;
+            }
+            P->inst_lens[i] = std::move(lens);
+            P->inst_brs[i] = std::move(brs);
+        } else if (!P->rank_reveal && N > P->inst_Ns[i] && (int64_t)P->inst_Ns[i] * nu < nx) {
             delete P;
             return RS_ERR_ARG;
         }
@@ -430,6 +490,8 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
                 g.res_leaves += N / Ns + 2;
                 g.res_items += mi;
                 g.res_slots += ms;
+            } else if (!P->inst_lens[inst].empty()) {
+                build_instance_split(g, inst, P->inst_lens[inst], P->inst_brs[inst], tmp);
             } else {
                 build_instance(g, inst, dims[3 * inst + 2], P->inst_Ns[inst], P->inst_branch[inst],
                                P->inst_branch[inst], tmp);
@@ -556,6 +618,12 @@ rs_status rs_plan_create_ex(int32_t count, const int32_t *dims5, const rs_option
 
 rs_status rs_plan_create_ring(int32_t count, const int32_t *dims8, const rs_options *opt, rs_plan *out) {
     return plan_create(count, dims8, 8, opt, out);
+}
+
+rs_status rs_plan_create_split(int32_t count, const int32_t *dims, const int32_t *leaf_off, const int32_t *leaf_len,
+                               const int32_t *branch_off, const int32_t *branch, const rs_options *opt, rs_plan *out) {
+    if (!leaf_off || !leaf_len || !branch_off || !branch) return RS_ERR_ARG;
+    return plan_create(count, dims, 3, opt, out, leaf_off, leaf_len, branch_off, branch);
 }
 
 rs_status rs_plan_ring_update(rs_plan P, const int32_t *dims8) {

@@ -78,6 +78,9 @@ def library():
         i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         lib.rs_plan_create.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(rs_options), ctypes.POINTER(_P)]
         lib.rs_plan_create_ex.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(rs_options), ctypes.POINTER(_P)]
+        lib.rs_plan_create_split.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                             ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(rs_options),
+                                             ctypes.POINTER(_P)]
         lib.rs_plan_create_ring.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(rs_options), ctypes.POINTER(_P)]
         lib.rs_plan_ring_update.argtypes = [_P, ctypes.POINTER(i32)]
         lib.rs_mhe_to_uftoc.argtypes = [i32, ctypes.POINTER(rs_mhe), ctypes.POINTER(rs_problem), _P, _P]
@@ -106,7 +109,8 @@ def library():
         lib.rs_refine_stats.restype = i32
         lib.rs_status_string.argtypes = [i32]
         lib.rs_status_string.restype = ctypes.c_char_p
-        for name in ("rs_plan_create", "rs_plan_create_ex", "rs_plan_create_ring", "rs_plan_ring_update",
+        for name in ("rs_plan_create", "rs_plan_create_ex", "rs_plan_create_split", "rs_plan_create_ring",
+                     "rs_plan_ring_update",
                      "rs_plan_workspace_size",
                      "rs_plan_destroy",
                      "rs_batch_solve", "rs_factor", "rs_solve", "rs_graph_create", "rs_graph_launch",
@@ -123,6 +127,25 @@ def rs_status_string(status):
 def _check(status, where):
     if status != RS_OK:
         raise RsError(status, where)
+
+
+def rs_plan_create_split(dims, leaf_lens, branches, precision=RS_FP64, max_refine=0, tol=0.0, flags=0):
+    """dims: sequence of (nx, nu, N); leaf_lens[i]: the leaf lengths of
+    instance i in stage order (summing to N); branches[i]: its master group
+    sizes for levels 1, 2, ... (the last repeats)."""
+    d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 3))
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    lo = np.ascontiguousarray(np.concatenate([[0], np.cumsum([len(v) for v in leaf_lens])]).astype(np.int32))
+    ll = np.ascontiguousarray(np.concatenate([np.asarray(v, dtype=np.int32) for v in leaf_lens]).astype(np.int32))
+    bo = np.ascontiguousarray(np.concatenate([[0], np.cumsum([len(v) for v in branches])]).astype(np.int32))
+    bb = np.ascontiguousarray(np.concatenate([np.asarray(v, dtype=np.int32) for v in branches]).astype(np.int32))
+    opt = rs_options(precision, 0, 0, max_refine, tol, flags, 0)
+    h = _P()
+    st = library().rs_plan_create_split(d.shape[0], d.ctypes.data_as(P32), lo.ctypes.data_as(P32),
+                                        ll.ctypes.data_as(P32), bo.ctypes.data_as(P32), bb.ctypes.data_as(P32),
+                                        ctypes.byref(opt), ctypes.byref(h))
+    _check(st, "rs_plan_create_split")
+    return h
 
 
 def rs_plan_create(dims, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.0, flags=0):
@@ -274,11 +297,13 @@ class Batch:
     ``factor()`` / ``solve_factored()`` can be used.  ``rank_reveal=True``
     gives the master problems rank-revealing stages (RS_PLAN_RANK_REVEAL), so
     that leaves with Ns * nu < nx, or whose inputs leave state directions
-    unreached, are allowed.
+    unreached, are allowed.  ``split=(leaf_lens, branches)`` gives every
+    instance its own leaf lengths and per-level master group sizes
+    (rs_plan_create_split).
     """
 
     def __init__(self, data, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.0,
-                 device="cuda", factored=False, per_instance=None, rank_reveal=False):
+                 device="cuda", factored=False, per_instance=None, rank_reveal=False, split=None):
         import torch
         self.torch = torch
         keys = set(data)
@@ -304,9 +329,11 @@ class Batch:
         self.obj = torch.zeros(self.count, **f64)
         self.info = torch.zeros(2 * self.count, dtype=torch.int32, device=device)
         pdims = dims if per_instance is None else [d + tuple(pi) for d, pi in zip(dims, per_instance)]
-        self.plan = rs_plan_create(pdims, precision, Ns, branch, max_refine, tol,
-                                   (RS_PLAN_FACTORED if factored else 0) |
-                                   (RS_PLAN_RANK_REVEAL if rank_reveal else 0))
+        flags = (RS_PLAN_FACTORED if factored else 0) | (RS_PLAN_RANK_REVEAL if rank_reveal else 0)
+        if split is not None:
+            self.plan = rs_plan_create_split(dims, split[0], split[1], precision, max_refine, tol, flags)
+        else:
+            self.plan = rs_plan_create(pdims, precision, Ns, branch, max_refine, tol, flags)
         self.graphs = []
         self.work_bytes = rs_plan_workspace_size(self.plan)
         self.work = torch.empty(self.work_bytes + 256, dtype=torch.uint8, device=device)

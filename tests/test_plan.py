@@ -348,3 +348,62 @@ def test_bf16_precision_only_for_large_block_shapes():
     with pytest.raises(rs.RsError) as e:
         rs.rs_plan_create([(32, 16, 256)], precision=rs.RS_MIXED_BF16, Ns=16)
     assert e.value.status == rs.RS_ERR_UNSUPPORTED
+
+
+def _split_tables(dims, lens, brs, flags=0):
+    plan = rs.rs_plan_create_split(dims, lens, brs, flags=flags)
+    try:
+        return rs.rs_plan_export(plan, 0), rs.rs_plan_export(plan, 1)
+    finally:
+        rs.rs_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("nx,nu,lens,brs", [
+    (3, 2, [5, 2, 9, 3, 4, 2, 7, 6], [3, 2]),
+    (4, 2, [2, 2, 11, 2, 3, 8, 2, 2, 5, 3, 7], [2, 4, 3]),
+    (2, 1, [3, 4, 2, 6, 2, 5], [5]),
+    (4, 4, [1, 1, 1, 1, 1, 1, 1], [2]),
+    (3, 2, [4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 1], [2, 6]),
+])
+def test_split_plan_emulated_with_oracle_matches_serial(nx, nu, lens, brs):
+    """rs_plan_create_split: leaves of the given lengths in order and master
+    levels grouped by the given per-level sizes; executed on the CPU with the
+    oracle's reductions, the plan reproduces the serial solution."""
+    N = sum(lens)
+    prob = W.g2(nx, nu, N, seed=N + 7 * nx)
+    leaves, items = _split_tables([(nx, nu, N)], [lens], [brs])
+    assert [int(lf[2]) for lf in leaves] == lens
+    assert [int(lf[1]) for lf in leaves] == list(np.cumsum([0] + lens[:-1]))
+    for i, it in enumerate(items):
+        assert it[8] + it[9] <= i
+    # the first level groups master stages by brs[0]
+    lev1 = [it for it in items if it[2] == 1 and it[0] in (UP, UP_LAST)]
+    if lev1:
+        assert max(int(it[4]) for it in lev1) <= brs[0]
+    emu = _emulate(prob, leaves, items)
+    ref = riccati.solve(prob)
+    assert kkt.rel_error(emu, ref) < 1e-9
+
+
+@pytest.mark.parametrize("N,Ns,b", [(1024, 16, 4), (37, 4, 3), (100, 8, 2), (17, 4, 4)])
+def test_split_plan_with_uniform_lengths_equals_uniform_plan(N, Ns, b):
+    lens = [Ns] * (N // Ns) + ([N % Ns] if N % Ns else [])
+    l1, i1 = _split_tables([(4, 4, N)], [lens], [[b]])
+    l0, i0, _ = _tables([(4, 4, N)], Ns, b)
+    np.testing.assert_array_equal(l1, l0)
+    np.testing.assert_array_equal(i1, i0)
+
+
+def test_split_plan_rejects_bad_arguments():
+    with pytest.raises(rs.RsError):
+        rs.rs_plan_create_split([(4, 2, 10)], [[4, 5]], [[2]])        # lengths sum to 9
+    with pytest.raises(rs.RsError):
+        rs.rs_plan_create_split([(4, 2, 10)], [[0, 10]], [[2]])       # empty leaf
+    with pytest.raises(rs.RsError):
+        rs.rs_plan_create_split([(4, 2, 10)], [[5, 5]], [[1]])        # group size 1
+    with pytest.raises(rs.RsError):
+        rs.rs_plan_create_split([(4, 2, 10)], [[1, 9]], [[2]])        # 1 * nu < nx, plain form
+    p = rs.rs_plan_create_split([(4, 2, 10)], [[1, 9]], [[2]], flags=rs.RS_PLAN_RANK_REVEAL)
+    rs.rs_plan_destroy(p)
+    p = rs.rs_plan_create_split([(4, 2, 10)], [[9, 1]], [[2]])        # a short last leaf is fine
+    rs.rs_plan_destroy(p)
