@@ -91,9 +91,13 @@ def residual_bytes_stage(n, m):
 
 
 def csrc_hash():
+    """Hash of the device sources (.hip, .hpp): the kernels the counters
+    describe; host-only changes of the library leave it unchanged."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1510_03110_amd", "csrc")
     for f in sorted(os.listdir(d)):
+        if not f.endswith((".hip", ".hpp")):
+            continue
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode())
             h.update(fh.read())
