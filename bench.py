@@ -384,6 +384,69 @@ def run_ip(args):
     print(json.dumps(out), flush=True)
 
 
+def run_batching(args):
+    """Batching mode: 4096 instances of n_x = 16, n_u = 8 with horizons drawn
+    uniformly in [32, 2048] (G1 with time-invariant A and B given once), one
+    rs_batch_solve per step over all of them, FP64 and mixed precision.  The
+    leaf length and branch of every instance come from the autotuner (with
+    --tune: measured on this GPU first, one key per power-of-two horizon range
+    and precision; else its cache or defaults).  Prints one JSON line."""
+    import numpy as np
+    import torch
+    from paper_1510_03110_amd import autotune, rs
+    from paper_1510_03110_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    nx, nu, count = 16, 8, 4096
+    rng = np.random.default_rng(W.seed_for(2))
+    Ns_all = rng.integers(32, 2049, size=count)
+    t0 = time.perf_counter()
+    probs = [W.g1_invariant(nx, nu, int(n), seed=W.seed_for(2, i)) for i, n in enumerate(Ns_all)]
+    data = {k: [p[k] for p in probs] for k in probs[0]}
+    dims = [(nx, nu, int(n)) for n in Ns_all]
+    stages = int(Ns_all.sum())
+    log("batching: %d instances, %d stages, generated in %.1fs" % (count, stages, time.perf_counter() - t0))
+    tuner = autotune.Tuner(args.tune_cache or None)
+    precs = {"both": ("fp64", "mixed"), "all": ("fp64", "mixed")}.get(args.precision, (args.precision,))
+    out_prec = {}
+    for prec in precs:
+        pc = rs.RS_MIXED_FP32 if prec == "mixed" else rs.RS_FP64
+        if args.tune:
+            for b in sorted({autotune.n_bucket(N) for _, _, N in dims}):
+                tuner.tune(nx, nu, b, pc, log=log)
+        per = tuner.per_instance(dims, pc)
+        bt = rs.Batch(data, precision=pc, per_instance=per)
+        for _ in range(args.warmup):
+            bt.solve()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            bt.solve()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t1) / args.steps
+        bad = int((bt.status()[:, 0] != 0).sum())
+        rec = {"value": round(count / el, 2), "ms_per_step": round(1e3 * el, 4),
+               "stages_per_s": round(stages / el, 1), "nonzero_status": bad,
+               "tree_shapes": sorted({"%d/%d" % tuple(p) for p in per})}
+        if pc == rs.RS_MIXED_FP32:
+            st = bt.refine_stats()
+            rec["converged"] = int((st[:, 3] == 1.0).sum())
+            rec["rel_residual_max"] = float(st[:, 0].max())
+        bt.close()
+        out_prec[prec] = rec
+        log("[%s]" % prec, rec)
+    head = max(out_prec, key=lambda k: out_prec[k]["value"])
+    out = {"metric": "KKT Newton solves/s, 4096 instances of n_x=16, n_u=8, N in [32, 2048]",
+           "value": out_prec[head]["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": out_prec[head]["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if head == "fp64" else "f32+f64",
+           "data": "synthetic: seeded G1 generator (time-invariant A, B), horizons uniform in [32, 2048]",
+           "config": {"workload": "uftoc_g1_nx16_nu8_N32to2048_batch4096", "precision": head,
+                      "autotuned": bool(args.tune)},
+           "precisions": out_prec}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,6 +467,10 @@ def main():
     ap.add_argument("--latency-Ns", type=int, default=16, help="leaf length of the B=1 latency plan")
     ap.add_argument("--latency-branch", type=int, default=4, help="branch of the B=1 latency plan")
     ap.add_argument("--verify", type=int, default=4, help="sampled instances checked against the oracle")
+    ap.add_argument("--batching", action="store_true",
+                    help="batching mode: 4096 instances of 16 x 8, N in [32, 2048] (see run_batching)")
+    ap.add_argument("--tune", action="store_true", help="batching mode: autotune leaf length and branch first")
+    ap.add_argument("--tune-cache", default="", help="autotuner cache file (default: the tuner's)")
     ap.add_argument("--ip", action="store_true",
                     help="interior-point mode: one problem with input bounds (see run_ip)")
     ap.add_argument("--rank-reveal", action="store_true",
@@ -427,6 +494,9 @@ def main():
         sys.exit(2)
     if args.ip:
         run_ip(args)
+        return
+    if args.batching:
+        run_batching(args)
         return
 
     import torch

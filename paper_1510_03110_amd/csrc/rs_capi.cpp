@@ -17,6 +17,9 @@ using namespace rs;
 namespace {
 
 constexpr size_t ALIGN = 256;
+// Instances with n_x = 16 or 32 and n_u below this are solved with their
+// inputs padded to it (the matrix-core kernels' tile), see rs_pad.hip.
+constexpr int PAD_NU = 16;
 constexpr int RING = 4;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -69,6 +72,12 @@ struct rs_plan_s {
     // rs_plan_create_split: leaf lengths and per-level master group sizes per
     // instance (empty: uniform Ns and branch)
     std::vector<std::vector<int32_t>> inst_lens, inst_brs;
+    // input padding: per instance the caller's n_u (0: not padded; the plan
+    // then uses n_u = PAD_NU) and the workspace offset of its padded arrays
+    std::vector<int32_t> nu_user;
+    std::vector<size_t> off_pad;
+    std::vector<int32_t> pad_inst;      // padded instances in order
+    size_t off_padargs = 0;
     std::vector<Group> groups;
     size_t off_probs = 0, off_info = 0, off_queues = 0, off_tables = 0, tables_bytes = 0;
     size_t total = 0;
@@ -80,6 +89,7 @@ struct rs_plan_s {
     int ring = 0;
     void *bound_work = nullptr;
     std::vector<DevProb> last_probs;
+    std::vector<PadArgs> last_pads;
     bool probs_valid = false;
     int32_t epoch = 0;
     int64_t last_refine = 0;
@@ -373,6 +383,8 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
     P->inst_Ns.resize(count);
     P->inst_lens.resize(count);
     P->inst_brs.resize(count);
+    P->nu_user.assign(count, 0);
+    P->off_pad.assign(count, 0);
     P->inst_branch.resize(count);
     for (int i = 0; i < count; ++i) {
         for (int k = 0; k < 3; ++k) P->dims[3 * i + k] = dims_in[(size_t)stride * i + k];
@@ -440,7 +452,17 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
             delete P;
             return RS_ERR_ARG;
         }
-        const ShapeEntry *se = find_shape(nx, nu);
+        // n_u below the matrix-core tile at n_x = 16 or 32: padded inputs
+        // (not in receding-horizon plans, whose records are windows of
+        // caller-owned rings, nor with BF16 products)
+        int nuk = nu;
+        if (nu < PAD_NU && (nx == 16 || nx == 32) && !P->receding && !P->bf16) {
+            P->nu_user[i] = nu;
+            P->dims[3 * i + 1] = PAD_NU;
+            P->pad_inst.push_back(i);
+            nuk = PAD_NU;
+        }
+        const ShapeEntry *se = find_shape(nx, nuk);
         const int f32 = P->mixed ? 1 : 0, fac = P->bf16 ? 2 : f32;
         if (se && se->large && !P->mixed) {
             // no fused kernels: the FP64 solve runs on the stored factorization
@@ -451,12 +473,12 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
             delete P;
             return RS_ERR_UNSUPPORTED;
         }
-        auto key = std::make_pair(nx, nu);
+        auto key = std::make_pair(nx, nuk);
         if (!gidx.count(key)) {
             gidx[key] = (int)P->groups.size();
             Group g;
             g.nx = nx;
-            g.nu = nu;
+            g.nu = nuk;
             g.shape = se;
             P->groups.push_back(g);
         }
@@ -509,8 +531,9 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
     }
     // workspace layout
     size_t off = 0;
-    P->off_probs = off;                 // user problems, then (mixed) the correction problems
-    off = align_up(off + sizeof(DevProb) * count * (P->mixed ? 2 : 1));
+    P->off_probs = off;                 // user problems, then (mixed) the correction problems,
+    P->off_padargs = off + sizeof(DevProb) * count * (P->mixed ? 2 : 1);   // then the padding jobs
+    off = align_up(P->off_padargs + sizeof(PadArgs) * P->pad_inst.size());
     P->off_info = off;
     off = align_up(off + sizeof(int32_t) * 2 * count);
     P->off_queues = off;
@@ -588,6 +611,12 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
             P->off_cbuf[i] = off;
             off = align_up(off + sizeof(double) * (nx + 2 * N * nx + N * nu + nx + 2 * (N + 1) * nx + N * nu));
         }
+    }
+    for (int i : P->pad_inst) {
+        // B, Q_xw (N nx x PAD_NU), Q_w (N PAD_NU^2), l_w and w (N PAD_NU)
+        const size_t nx = dims[3 * i], N = dims[3 * i + 2];
+        P->off_pad[i] = off;
+        off = align_up(off + sizeof(double) * N * (2 * nx * PAD_NU + PAD_NU * PAD_NU + 2 * PAD_NU));
     }
     P->total = off;
     P->tables.assign(P->tables_bytes, 0);
@@ -755,6 +784,35 @@ static rs_status bind_and_upload(rs_plan P, const rs_problem *probs, char *work,
         d.sa = q.sa; d.slx = q.slx; d.slw = q.slw; d.sc = q.sc;
         d.nx = q.nx; d.nu = q.nu; d.N = q.N; d.flags = q.flags;
     }
+    // padded instances: the kernels see the padded copies (rs_pad.hip)
+    std::vector<PadArgs> pads;
+    for (int i : P->pad_inst) {
+        const rs_problem &q = probs[i];
+        DevProb &d = dp[i];
+        const int64_t nx = q.nx, np = PAD_NU, N = q.N;
+        double *b = reinterpret_cast<double *>(work + P->off_pad[i]);
+        PadArgs a{};
+        a.B = q.B; a.Qw = q.Qw; a.Qxw = q.Qxw; a.lw = q.lw;
+        a.sB = q.sB; a.sQw = q.sQw; a.sQxw = q.sQxw; a.slw = q.slw;
+        a.Bp = b;
+        a.Qxwp = b + N * nx * np;
+        a.Qwp = b + 2 * N * nx * np;
+        a.lwp = a.Qwp + N * np * np;
+        a.wp = a.lwp + N * np;
+        a.sBp = q.sB ? nx * np : 0;
+        a.sQxwp = q.sQxw ? nx * np : 0;
+        a.sQwp = q.sQw ? np * np : 0;
+        a.slwp = q.slw ? np : 0;
+        a.w = q.w;
+        a.nx = q.nx; a.nu = q.nu; a.nup = PAD_NU; a.N = q.N; a.flags = q.flags;
+        pads.push_back(a);
+        d.B = a.Bp; d.sB = a.sBp;
+        d.Qw = a.Qwp; d.sQw = a.sQwp;
+        d.Qxw = q.Qxw ? a.Qxwp : nullptr; d.sQxw = a.sQxwp;
+        d.lw = q.lw ? a.lwp : nullptr; d.slw = a.slwp;
+        d.w = a.wp;
+        d.nu = PAD_NU;
+    }
     if (P->mixed) {
         // correction problems: the same matrices; right-hand side and
         // solution in the workspace (c = cN = 0, no objective)
@@ -806,21 +864,25 @@ static rs_status bind_and_upload(rs_plan P, const rs_problem *probs, char *work,
         P->probs_valid = false;
         P->bound_work = work;
     }
-    if (!P->probs_valid || std::memcmp(dp.data(), P->last_probs.data(), sizeof(DevProb) * nprob) != 0) {
+    // descriptors and padding jobs are one contiguous upload
+    const size_t pbytes = sizeof(DevProb) * nprob, abytes = sizeof(PadArgs) * pads.size();
+    if (!P->probs_valid || std::memcmp(dp.data(), P->last_probs.data(), pbytes) != 0 ||
+        (abytes && std::memcmp(pads.data(), P->last_pads.data(), abytes) != 0)) {
         const int r = P->ring;
         P->ring = (P->ring + 1) % RING;
         if (!P->pinned_probs[r]) {
-            if (hipHostMalloc(&P->pinned_probs[r], sizeof(DevProb) * nprob) != hipSuccess) return RS_ERR_HIP;
+            if (hipHostMalloc(&P->pinned_probs[r], pbytes + abytes) != hipSuccess) return RS_ERR_HIP;
             if (hipEventCreateWithFlags(&P->ev[r], hipEventDisableTiming) != hipSuccess) return RS_ERR_HIP;
         }
         if (P->ev_used[r] && hipEventSynchronize(P->ev[r]) != hipSuccess) return RS_ERR_HIP;
-        std::memcpy(P->pinned_probs[r], dp.data(), sizeof(DevProb) * nprob);
-        e = hipMemcpyAsync(work + P->off_probs, P->pinned_probs[r], sizeof(DevProb) * nprob,
-                           hipMemcpyHostToDevice, st);
+        std::memcpy(P->pinned_probs[r], dp.data(), pbytes);
+        if (abytes) std::memcpy(static_cast<char *>(P->pinned_probs[r]) + pbytes, pads.data(), abytes);
+        e = hipMemcpyAsync(work + P->off_probs, P->pinned_probs[r], pbytes + abytes, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return RS_ERR_HIP;
         if (hipEventRecord(P->ev[r], st) != hipSuccess) return RS_ERR_HIP;
         P->ev_used[r] = true;
         P->last_probs = dp;
+        P->last_pads = pads;
         P->probs_valid = true;
     }
     return RS_OK;
@@ -832,7 +894,8 @@ static rs_status check_call(rs_plan P, const rs_problem *probs, void *work, size
     if (reinterpret_cast<uintptr_t>(work) % ALIGN) return RS_ERR_ARG;
     for (int i = 0; i < P->count; ++i) {
         const rs_problem &q = probs[i];
-        if (q.nx != P->dims[3 * i] || q.nu != P->dims[3 * i + 1] || q.N != P->dims[3 * i + 2]) return RS_ERR_ARG;
+        const int nu = P->nu_user[i] ? P->nu_user[i] : P->dims[3 * i + 1];
+        if (q.nx != P->dims[3 * i] || q.nu != nu || q.N != P->dims[3 * i + 2]) return RS_ERR_ARG;
         if (!valid_ptr_set(q)) return RS_ERR_ARG;
         if (q.sQx < 0 || q.sQw < 0 || q.sQxw < 0 || q.sA < 0 || q.sB < 0) return RS_ERR_ARG;
         if (q.sa < 0 || q.slx < 0 || q.slw < 0 || q.sc < 0) return RS_ERR_ARG;
@@ -963,6 +1026,19 @@ static rs_status mixed_solve(rs_plan P, char *W, int32_t *info, hipStream_t st) 
     return s;
 }
 
+static rs_status run_sequence(rs_plan P, char *W, int32_t *info, hipStream_t st, int mode);
+
+// The call's kernels, between the padded copies of the inputs of padded
+// instances and the copy of their w back to the caller.
+static rs_status run_padded(rs_plan P, char *W, int32_t *info, hipStream_t st, int mode) {
+    const int npad = (int)P->pad_inst.size();
+    const PadArgs *pa = reinterpret_cast<const PadArgs *>(W + P->off_padargs);
+    if (npad && launch_pad(pa, npad, false, st) != hipSuccess) return RS_ERR_HIP;
+    rs_status s = run_sequence(P, W, info, st, mode);
+    if (s == RS_OK && npad && mode != 1 && launch_pad(pa, npad, true, st) != hipSuccess) s = RS_ERR_HIP;
+    return s;
+}
+
 // Kernel sequence of a call once the descriptors are bound.
 // mode 0 = rs_batch_solve, 1 = rs_factor, 2 = rs_solve.
 static rs_status run_sequence(rs_plan P, char *W, int32_t *info, hipStream_t st, int mode) {
@@ -988,7 +1064,7 @@ static rs_status run_call(rs_plan P, const rs_problem *probs, void *work, size_t
     s = bind_and_upload(P, probs, W, st);
     if (s != RS_OK) return s;
     int32_t *info = info_dev ? info_dev : reinterpret_cast<int32_t *>(W + P->off_info);
-    return run_sequence(P, W, info, st, mode);
+    return run_padded(P, W, info, st, mode);
 }
 
 struct rs_graph_s {
@@ -1026,7 +1102,7 @@ rs_status rs_graph_create(rs_plan P, int32_t mode, const rs_problem *probs, void
                                           (int64_t)std::max<size_t>(1, g.items.size()), 0, st) != hipSuccess)
             s = RS_ERR_HIP;
     }
-    if (s == RS_OK) s = run_sequence(P, W, info, st, mode);
+    if (s == RS_OK) s = run_padded(P, W, info, st, mode);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(st, &graph);
     P->timing = timing;

@@ -59,5 +59,8 @@ Launcher mfma_factor_leaf32(int nx, int nu, int which);   // FP32 leaves of n_x 
 const ShapeEntry *find_shape(int nx, int nu);
 hipError_t launch_init(int32_t *info, int count, int32_t *queues, int nq, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+// padded copies of the inputs of npad instances (back = false), or their w
+// copied back to the caller (back = true)
+hipError_t launch_pad(const PadArgs *args, int npad, bool back, hipStream_t st);
 
 }  // namespace rs

@@ -19,6 +19,18 @@ struct DevProb {
 };
 constexpr int32_t PROB_SKIP = 1;
 
+// Input padding of one instance (n_u raised to nup with inputs that act on
+// nothing): the caller's arrays, the padded copies in the workspace and their
+// stage strides (0 where the caller's stride is 0), and the caller's w.
+struct PadArgs {
+    const double *B, *Qw, *Qxw, *lw;
+    int64_t sB, sQw, sQxw, slw;
+    double *Bp, *Qwp, *Qxwp, *lwp, *wp;
+    int64_t sBp, sQwp, sQxwp, slwp;
+    double *w;
+    int32_t nx, nu, nup, N, flags, pad_;
+};
+
 // One leaf (level-0 subproblem, a batch of original stages, Sec. 4.1).
 struct LeafItem {
     int32_t inst;      // instance index

@@ -10,7 +10,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("precision,shapes", [(0, [(32, 16), (16, 16), (32, 32)]), (1, [(32, 16), (16, 16)]),
-                                              (0, [(4, 2), (8, 4)])])
+                                              (0, [(4, 2), (8, 4)]), (0, [(16, 8), (32, 4)]), (1, [(16, 8), (32, 8)])])
 def test_skipped_instances_untouched(precision, shapes):
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
