@@ -456,10 +456,14 @@ def main():
     ap.add_argument("--nx", type=int, default=32)
     ap.add_argument("--nu", type=int, default=16)
     ap.add_argument("--N", type=int, default=1024)
-    # Throughput tree shape chosen by the autotuner at this shape and batch
-    # (leaf length 128, branch 8); the B = 1 latency plan keeps short leaves
-    # (16, branch 4), where the O(log N) tree is what lowers the latency.
-    ap.add_argument("--Ns", type=int, default=128)
+    # Throughput tree shape, measured at this shape and batch: two leaves of
+    # 512 stages per instance (leaf lengths 128 / 256 / 512 / 1024 give
+    # 30.3k / 30.8k / 31.4k / 28.7k solves/s in FP64: the leaf reduction's
+    # rate per stage is the same, fewer leaves mean a smaller tree and forward
+    # sweep, and a whole-problem leaf per instance leaves half the GPU idle in
+    # its second round).  The B = 1 latency plan keeps short leaves (16,
+    # branch 4), where the O(log N) tree is what lowers the latency.
+    ap.add_argument("--Ns", type=int, default=512)
     ap.add_argument("--branch", type=int, default=8)
     ap.add_argument("--precision", choices=("both", "fp64", "mixed", "bf16", "all"), default="both",
                     help="both = fp64 and mixed; all adds bf16 (large-block shapes only)")
