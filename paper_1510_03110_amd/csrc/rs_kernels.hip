@@ -368,7 +368,9 @@ const ShapeEntry *find_shape(int nx, int nu) {
             e.large = false;
             e.lb = false;
             e.fp64[0] = mfma_leaf_up(a, b) ? mfma_leaf_up(a, b) : up;
-            e.fp64[1] = mfma_tree(a) ? mfma_tree(a) : tr;
+            // the matrix-core tree sends its children their terminal costate,
+            // which only the matrix-core leaf solve reads
+            e.fp64[1] = (mfma_leaf_down(a, b) && mfma_tree(a)) ? mfma_tree(a) : tr;
             e.fp64[2] = mfma_leaf_down(a, b) ? mfma_leaf_down(a, b) : dn;
             for (int f = 0; f < 2; ++f)
                 for (int k = 0; k < 3; ++k) {

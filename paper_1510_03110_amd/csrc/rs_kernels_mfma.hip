@@ -389,6 +389,109 @@ struct SlotOut : NoEmit {
     __device__ void k(int s, int i, double v) const { at(s)[SlotLayout{NX}.k() + i] = v; }
 };
 
+// Records of the master stages of an up item (Alg. 4 on the master stages
+// with the preliminary terminal; for the last item of a level, the
+// elimination with its true terminal), kept in the stages' slots for the down
+// sweep: K, k_0, P_t, Psi_0,t and (reduction) V_t, L = -G^{-1} B'V, in the
+// slot areas the factored plans use for their up records.
+template <int NX, bool RED>
+struct SlotRecOut : NoEmit {
+    static constexpr bool KF = true, PF = true, VF = RED, LTF = RED, PSF = true, KVF = true;
+    double *slots;
+    int first;
+    __device__ double *at(int s) const { return slots + (int64_t)(first + s) * SlotLayout{NX}.size(); }
+    __device__ void K(int s, int i, int j, double v) const { at(s)[SlotLayout{NX}.uK() + i * NX + j] = v; }
+    __device__ void k(int s, int i, double v) const { at(s)[SlotLayout{NX}.k() + i] = v; }
+    __device__ void P(int s, int i, int j, double v) const { at(s)[SlotLayout{NX}.uP() + i * NX + j] = v; }
+    __device__ void Psi(int s, int i, double v) const { at(s)[SlotLayout{NX}.Psi() + i] = v; }
+    __device__ void V(int s, int i, int j, double v) const { at(s)[SlotLayout{NX}.uV() + i * NX + j] = v; }
+    __device__ void Lt(int s, int i, int j, double v) const { at(s)[SlotLayout{NX}.uL() + i * NX + j] = v; }
+};
+
+// Down pass of a master subproblem below the top (Alg. 6, k >= 1) as a
+// forward sweep on the records of its up pass, the superposition of the leaf
+// solve: with the item's terminal costate lam_N (from its parent),
+//   w = K x + k_0 + L lam_N,  lam = P x - Psi_0 + V lam_N,
+//   x+ = A_hat x + B_hat w + a_hat;
+// the last item of a level holds final records (no lam_N terms) and its
+// terminal costate is that of the level's terminal node.  Child s receives
+// its initial state x_s and its terminal costate lam_{s+1}.
+template <int NX>
+__device__ __attribute__((noinline)) void tree_sweep_m(MSmem<double, NX, NX, false, true> &S, const TreeItem &it,
+                                                    GroupArgs &g) {
+    const SlotLayout SL{NX};
+    const int tid = threadIdx.x;
+    auto slot = [&](int s) { return g.slots + (int64_t)s * SL.size(); };
+    const double *msg = slot(it.out_slot);
+    const bool last = it.last != 0;
+    double *lamN = S.pt, *lam = S.gx, *xn = S.ax;
+    double *Km = S.W, *Lm = S.W + NX * NX, *Vm = S.HT;
+    for (int i = tid; i < NX; i += NT) {
+        S.x[i] = msg[SL.xh() + i];
+        lamN[i] = last ? 0.0 : msg[SL.lamN() + i];
+    }
+    for (int s = 0; s < it.count; ++s) {
+        const double *r = slot(it.first + s);
+        const StageSrc src = slot_stage(r, NX, g.ident);
+        for (int e = tid; e < NX * NX; e += NT) {
+            Km[e] = r[SL.uK() + e];
+            S.P[e] = r[SL.uP() + e];
+            S.A[e] = src.A[e];
+            S.B[e] = src.B[e];
+            if (!last) {
+                Lm[e] = r[SL.uL() + e];
+                Vm[e] = r[SL.uV() + e];
+            }
+        }
+        for (int i = tid; i < NX; i += NT) {
+            S.kk[i] = r[SL.k() + i];
+            S.Psi[i] = r[SL.Psi() + i];
+            S.av[i] = src.a[i];
+        }
+        __syncthreads();
+        if (tid < NX) {
+            const int i = tid;
+            double w = S.kk[i];
+            for (int k = 0; k < NX; ++k) w += Km[i * NX + k] * S.x[k];
+            if (!last)
+                for (int k = 0; k < NX; ++k) w += Lm[i * NX + k] * lamN[k];
+            S.wv[i] = w;
+        } else if (tid >= 64 && tid < 64 + NX) {
+            const int i = tid - 64;
+            double l = -S.Psi[i];
+            for (int k = 0; k < NX; ++k) l += S.P[i * NX + k] * S.x[k];
+            if (!last)
+                for (int k = 0; k < NX; ++k) l += Vm[i * NX + k] * lamN[k];
+            lam[i] = l;
+        }
+        __syncthreads();
+        if (tid < NX) {
+            const int i = tid;
+            double v = S.av[i];
+            for (int k = 0; k < NX; ++k) v += S.A[i * NX + k] * S.x[k] + S.B[i * NX + k] * S.wv[k];
+            xn[i] = v;
+            slot(it.first + s)[SL.xh() + i] = S.x[i];                 // child s starts at x_s
+            if (s > 0) slot(it.first + s - 1)[SL.lamN() + i] = lam[i];  // child s-1 ends at lam_s
+        }
+        __syncthreads();
+        if (tid < NX) S.x[tid] = xn[tid];
+        __syncthreads();
+    }
+    // the last child ends where the item does
+    if (last) {
+        const double *term = slot(it.term_slot);
+        if (tid < NX) {
+            const int i = tid;
+            double l = term[SL.lx() + i];                  // lam_end = P_term x_end - Psi_term
+            for (int k = 0; k < NX; ++k) l += term[SL.Qx() + i * NX + k] * S.x[k];
+            slot(it.first + it.count - 1)[SL.lamN() + i] = l;
+            slot(it.term_slot)[SL.xh() + i] = S.x[i];
+        }
+    } else if (tid < NX) {
+        slot(it.first + it.count - 1)[SL.lamN() + tid] = lamN[tid];
+    }
+}
+
 template <int NX>
 __device__ void tree_solve_m(MSmem<double, NX, NX, false, true> &S, const TreeItem &it, const DevProb &p, GroupArgs &g) {
     const SlotLayout SL{NX};
@@ -443,6 +546,18 @@ __device__ void tree_solve_m(MSmem<double, NX, NX, false, true> &S, const TreeIt
         double *d = slot(it.term_slot);
         for (int i = tid; i < NX; i += NT) d[SL.xh() + i] = S.x[i];
     }
+    // terminal costate of child s: lam_{s+1} = P_{s+1} x_{s+1} - Psi_{s+1}
+    // from the cost to go sent to it and the next child's initial state
+    __threadfence_block();
+    __syncthreads();
+    for (int e = tid; e < it.count * NX; e += NT) {
+        const int s = e / NX, i = e - (e / NX) * NX;
+        double *d = slot(it.first + s);
+        const double *xn = (s + 1 < it.count) ? slot(it.first + s + 1) + SL.xh() : slot(it.term_slot) + SL.xh();
+        double l = -d[SL.Psi() + i];
+        for (int k = 0; k < NX; ++k) l += d[SL.P() + i * NX + k] * xn[k];
+        d[SL.lamN() + i] = l;
+    }
 }
 
 template <int NX>
@@ -481,7 +596,8 @@ __global__ void __launch_bounds__(NT) km_tree(GroupArgs g) {
             // excluded instance: only its completion flag is published
         } else if (it.kind == ITEM_UP) {
             auto &S = *reinterpret_cast<MSmem<double, NX, NX, true, false> *>(raw);
-            reduce_to<NX, NX>(S, get, it.count, slot(it.out_slot), g.info, it.inst, -1, 3, g.ident != nullptr);
+            reduce_to<NX, NX>(S, get, it.count, slot(it.out_slot), g.info, it.inst, -1, 3, g.ident != nullptr,
+                              SlotRecOut<NX, true>{{}, slots, it.first});
         } else if (it.kind == ITEM_UP_LAST) {
             auto &S = *reinterpret_cast<MSmem<double, NX, NX, false, false> *>(raw);
             const double *term = slot(it.term_slot);
@@ -489,10 +605,14 @@ __global__ void __launch_bounds__(NT) km_tree(GroupArgs g) {
             for (int i = tid; i < NX; i += NT) S.Psi[i] = -term[SL.lx() + i];
             if (tid == 0) S.cbar = term[SL.c()];
             __syncthreads();
-            eliminate_to<NX, NX>(S, get, it.count, slot(it.out_slot), g.info, it.inst, -1, 3);
-        } else {
+            eliminate_to<NX, NX>(S, get, it.count, slot(it.out_slot), g.info, it.inst, -1, 3,
+                                 SlotRecOut<NX, false>{{}, slots, it.first});
+        } else if (it.kind == ITEM_TOP) {
             auto &S = *reinterpret_cast<MSmem<double, NX, NX, false, true> *>(raw);
             tree_solve_m<NX>(S, it, p, g);
+        } else {
+            auto &S = *reinterpret_cast<MSmem<double, NX, NX, false, true> *>(raw);
+            tree_sweep_m<NX>(S, it, g);
         }
         __threadfence();
         __syncthreads();

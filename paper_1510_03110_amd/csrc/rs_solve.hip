@@ -224,13 +224,18 @@ __device__ __forceinline__ VSrc<double> slot_src(const double *sl) {
 //   x_{t+1} = A x_t + B w_t + a_t.
 // The last leaf was reduced with the true terminal, so its records are
 // final (no V, L terms).  `rec` gives the stage pointers K, k, P, Psi, V, L.
-template <int NX, int NU, class Rec>
+// LAMN: the parent sent lam_N itself (the fused matrix-core tree) rather than
+// its cost to go P_hat, Psi_hat.
+template <int NX, int NU, bool LAMN = false, class Rec>
 __device__ __forceinline__ void leaf_forward_sweep(VSmem<NX, NU> &S, double *lamN, const Prob &p,
                                                    const LeafItem &it, const double *msg, Rec rec) {
     const SlotLayout SL{NX};
     const bool last = (it.flags & LEAF_LAST) != 0;
     const int l = lane();
-    if (!last) {
+    if (LAMN && !last) {
+        if (l < NX) lamN[l] = msg[SL.lamN() + l];
+        wsync();
+    } else if (!last) {
         const double *nxt = msg + SL.size();           // the next leaf's slot: x_hat_{i+1}
         if (l < NX) S.x[l] = nxt[SL.xh() + l];
         wsync();
@@ -466,8 +471,8 @@ __global__ void __launch_bounds__(WT) kv_leaf_fwd(GroupArgs g) {
     if ((it.flags & LEAF_TOP) || skip_inst(g, it.inst)) return;
     const Prob p = load_prob(g.probs, it.inst);
     const double *msg = g.slots + (int64_t)it.slot * SlotLayout{NX}.size();
-    leaf_forward_sweep<NX, NU>(S, lamN, p, it, msg,
-                               FusedRecs<NX, NU>{reinterpret_cast<const double *>(g.leaf_scratch) + it.scratch});
+    leaf_forward_sweep<NX, NU, true>(S, lamN, p, it, msg,
+                                     FusedRecs<NX, NU>{reinterpret_cast<const double *>(g.leaf_scratch) + it.scratch});
 }
 
 template <int NX, int NU>

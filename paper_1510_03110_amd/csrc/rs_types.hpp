@@ -88,7 +88,10 @@ struct SlotLayout {
     __host__ __device__ int uV() const { return 9 * n * n + 5 * n + 2; }
     __host__ __device__ int dL() const { return 10 * n * n + 5 * n + 2; }
     __host__ __device__ int dLT() const { return 11 * n * n + 5 * n + 2; }
-    __host__ __device__ int size() const { return ((12 * n * n + 5 * n + 2) + 7) & ~7; }
+    // costate at the end of the node's subproblem (its terminal lam_N), sent
+    // down by the fused matrix-core tree
+    __host__ __device__ int lamN() const { return 12 * n * n + 5 * n + 2; }
+    __host__ __device__ int size() const { return ((12 * n * n + 6 * n + 2) + 7) & ~7; }
 };
 
 // Stored factorization of one leaf stage (factor / solve split), in the
