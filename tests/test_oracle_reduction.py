@@ -157,3 +157,26 @@ def test_rank_revealing_stage_depends_on_B_Qinv_Bt_only():
     for i, t in enumerate(bounds[:-1]):
         np.testing.assert_allclose(ms["x"][i], full["x"][t], rtol=1e-9, atol=1e-9)
     assert abs(ms["obj"] - full["obj"]) < 1e-9 * max(1, abs(full["obj"]))
+
+
+@pytest.mark.parametrize("nx,nu,N", [(3, 2, 6), (4, 2, 9), (2, 3, 4)])
+def test_linearised_terminal_gives_the_same_solution(nx, nu, N):
+    """A subproblem with terminal cost 1/2 x'P_hat x - Psi_hat'x and the one
+    whose terminal cost is the linear lam_N'x_N, lam_N = P_hat x_N* - Psi_hat
+    taken at its optimum, have the same solution (the KKT conditions coincide
+    at that point and both problems are strictly convex in the inputs): the
+    down passes solve every leaf and master subproblem below the top this
+    way, with the preliminary factorization (P_N = 0) and lam_N from the
+    parent."""
+    rng = np.random.default_rng(nx * 17 + N)
+    prob = W.with_costs(W.g2(nx, nu, N, seed=N + 3), seed=1)
+    Ph, Psih, ch = _terminal(rng, nx)
+    sub = reduction.sub_problem(prob, 0, N, terminal=(Ph, Psih, ch))
+    sub["x0"] = rng.standard_normal(nx)
+    full = riccati.solve(sub)
+    lamN = Ph @ full["x"][N] - Psih
+    lin = dict(sub)
+    lin["QxN"], lin["lN"], lin["cN"] = np.zeros((nx, nx)), lamN, 0.0
+    sol = riccati.solve(lin)
+    for k in ("x", "w", "lam"):
+        np.testing.assert_allclose(sol[k], full[k], rtol=1e-9, atol=1e-10)
