@@ -45,7 +45,73 @@ __device__ __forceinline__ void wave_sync() {
 template <int NX, int NU>
 struct RSmem {
     double x[4][NX], w[4][NU], ln[4][NX];
+    double cx[4][NX], cw[4][NU], ax[4][NX], qw[4][NX], bw[4][NX];
     double red[4][3];
+};
+
+// R x C row-major matrix held by one wavefront, read with contiguous loads:
+// LC = C / 2 lanes share a row, lane l holds columns col() and col() + 1 of
+// the rows row(ii) = ii * RPI + l / LC.  From the same registers the
+// wavefront forms row sums (M x: a sum over the LC lanes of a row) and
+// column sums (M'v: a sum over the RPI lanes that hold one column pair), so
+// every matrix of a stage is read from memory once.
+template <int R, int C>
+struct Tile {
+    static constexpr int LC = C / 2, RPI = 64 / LC, NI = R / RPI;
+    static_assert(C % 2 == 0 && (LC & (LC - 1)) == 0 && LC <= 64 && R % RPI == 0, "tile shape");
+    double m0[NI], m1[NI];
+
+    __device__ static int col() { return 2 * (lane() % LC); }
+    __device__ static int row(int ii) { return ii * RPI + lane() / LC; }
+    __device__ __forceinline__ void load(const double *M) {
+        const int c = col();
+#pragma unroll
+        for (int ii = 0; ii < NI; ++ii) {
+            const int r = row(ii);
+            m0[ii] = M ? M[r * C + c] : 0.0;
+            m1[ii] = M ? M[r * C + c + 1] : 0.0;
+        }
+    }
+    // Lane partial of M'v for the lane's two columns (summed by colsum()).
+    __device__ __forceinline__ void tpart(const double *v, double &p0, double &p1) const {
+#pragma unroll
+        for (int ii = 0; ii < NI; ++ii) {
+            const double vr = v[row(ii)];
+            p0 += m0[ii] * vr;
+            p1 += m1[ii] * vr;
+        }
+    }
+    // Lane partial of u'M v (no reduction: the caller sums it over the wave).
+    __device__ __forceinline__ double bilinear(const double *u, const double *v) const {
+        const int c = col();
+        const double v0 = v[c], v1 = v[c + 1];
+        double s = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < NI; ++ii) s += u[row(ii)] * (m0[ii] * v0 + m1[ii] * v1);
+        return s;
+    }
+    // y = M v into y[0..R) (written by one lane per row); every lane calls it.
+    __device__ __forceinline__ void rowsum(const double *v, double *y) const {
+        const int c = col();
+        const double v0 = v[c], v1 = v[c + 1];
+#pragma unroll
+        for (int ii = 0; ii < NI; ++ii) {
+            const double s = group_sum<LC>(m0[ii] * v0 + m1[ii] * v1);
+            if (lane() % LC == 0) y[row(ii)] = s;
+        }
+    }
+    // Column sums of the lane partials into y[0..C) (all lanes call it).
+    __device__ __forceinline__ static void colsum(double p0, double p1, double *y) {
+#pragma unroll
+        for (int o = LC; o < 64; o <<= 1) {
+            p0 += __shfl_xor(p0, o, 64);
+            p1 += __shfl_xor(p1, o, 64);
+        }
+        if (lane() < LC) {
+            y[col()] = p0;
+            y[col() + 1] = p1;
+        }
+    }
 };
 
 template <int NX, int NU>
@@ -59,25 +125,21 @@ __global__ void __launch_bounds__(RT) kr_residual(GroupArgs g) {
     double rhs = 0.0, res = 0.0, obj = 0.0;
     double *xs = S.x[wv], *ws = S.w[wv], *ls = S.ln[wv];
     const int len = uni(it.len);
+    using TX = Tile<NX, NX>;      // Q_x, A
+    using TU = Tile<NX, NU>;      // Q_xw, B
+    using TW = Tile<NU, NU>;      // Q_w (same column pairs per lane as TU)
     for (int s = wv; s < len; s += 4) {
         const int t = it.t0 + s;
         const double *x = p.x + (int64_t)t * NX, *xn = x + NX, *w = p.w + (int64_t)t * NU;
         const double *lam = p.lam + (int64_t)t * NX, *lamn = lam + NX;
-        const double *Qx = p.Qx + (int64_t)t * p.sQx, *Qw = p.Qw + (int64_t)t * p.sQw;
-        const double *Qxw = p.Qxw ? p.Qxw + (int64_t)t * p.sQxw : nullptr;
-        const double *A = p.A + (int64_t)t * p.sA, *B = p.B + (int64_t)t * p.sB;
-        Op<NX, NX> oQx, oAT, oA;
-        Op<NX, NU> oQxw, oB;
-        Op<NU, NX> oQxwT, oBT;
-        Op<NU, NU> oQw;
-        oQx.template load<false>(Qx, NX);
-        oAT.template load<false>(A, NX);
-        oA.template load<true>(A, NX);
-        oQxw.template load<true>(Qxw, NU);
-        oB.template load<true>(B, NU);
-        oQxwT.template load<false>(Qxw, NU);
-        oBT.template load<false>(B, NU);
-        oQw.template load<false>(Qw, NU);
+        TX mQx, mA;
+        TU mQxw, mB;
+        TW mQw;
+        mQx.load(p.Qx + (int64_t)t * p.sQx);
+        mA.load(p.A + (int64_t)t * p.sA);
+        mQxw.load(p.Qxw ? p.Qxw + (int64_t)t * p.sQxw : nullptr);
+        mB.load(p.B + (int64_t)t * p.sB);
+        mQw.load(p.Qw + (int64_t)t * p.sQw);
         const double xi = l < NX ? x[l] : 0.0, wi = l < NU ? w[l] : 0.0;
         const double lami = l < NX ? lam[l] : 0.0, xni = l < NX ? xn[l] : 0.0;
         const double lxi = (l < NX && p.lx) ? p.lx[(int64_t)t * p.slx + l] : 0.0;
@@ -90,28 +152,39 @@ __global__ void __launch_bounds__(RT) kr_residual(GroupArgs g) {
         }
         if (l < NU) ws[l] = wi;
         wave_sync();
-        const double qx = oQx.apply(xs), qxw = oQxw.apply(ws), atl = oAT.apply(ls);
-        const double ax = oA.apply(xs), bw = oB.apply(ws);
-        const double qxwt = oQxwT.apply(xs), qw = oQw.apply(ws), btl = oBT.apply(ls);
+        // Q_x'x + A'lam_{t+1} (x row), Q_xw'x + B'lam_{t+1} + Q_w'w (w row)
+        double p0 = 0.0, p1 = 0.0, q0 = 0.0, q1 = 0.0;
+        mQx.tpart(xs, p0, p1);
+        mA.tpart(ls, p0, p1);
+        mQxw.tpart(xs, q0, q1);
+        mB.tpart(ls, q0, q1);
+        mQw.tpart(ws, q0, q1);
+        // objective: 1/2 x'Q_x x + x'Q_xw w + 1/2 w'Q_w w (lane parts)
+        double part = 0.5 * mQx.bilinear(xs, xs) + mQxw.bilinear(xs, ws) + 0.5 * mQw.bilinear(ws, ws);
+        TX::colsum(p0, p1, S.cx[wv]);
+        TU::colsum(q0, q1, S.cw[wv]);
+        mA.rowsum(xs, S.ax[wv]);
+        mQxw.rowsum(ws, S.qw[wv]);
+        mB.rowsum(ws, S.bw[wv]);
         wave_sync();
-        double part = 0.0;
         if (l < NX) {
-            const double dlx = lxi + qx + qxw - lami + atl;
-            const double da = ai + ax + bw - xni;
+            const double dlx = lxi + S.cx[wv][l] + S.qw[wv][l] - lami;
+            const double da = ai + S.ax[wv][l] + S.bw[wv][l] - xni;
             const_cast<double *>(c.lx)[(int64_t)t * c.slx + l] = dlx;
             const_cast<double *>(c.a)[(int64_t)t * c.sa + l] = da;
             rhs = fmax(rhs, fmax(fabs(lxi), fabs(ai)));
             res = fmax(res, fmax(fabs(dlx), fabs(da)));
-            part += xi * (0.5 * qx + qxw + lxi);
+            part += xi * lxi;
         }
         if (l < NU) {
-            const double dlw = lwi + qxwt + qw + btl;
+            const double dlw = lwi + S.cw[wv][l];
             const_cast<double *>(c.lw)[(int64_t)t * c.slw + l] = dlw;
             rhs = fmax(rhs, fabs(lwi));
             res = fmax(res, fabs(dlw));
-            part += wi * (0.5 * qw + lwi);
+            part += wi * lwi;
         }
         obj += wave_sum(part) + ct;
+        wave_sync();
     }
     if (wv == 0 && it.t0 == 0) {            // lam_0 row
         if (l < NX) {

@@ -63,7 +63,7 @@ __device__ __forceinline__ void vstage(VSmem<NX, NU> &S, const VSrc<TR> &q, doub
     Op<NX, NX> oP, oA, oV;
     Op<NU, NX> oB;
     Op<NU, NU> oLT, oLi;
-    Op<NX, NU> oK, oBr;
+    Op<NX, NU> oK;
     if (q.Pn)
         oP.template load<false>(q.Pn, NX);
     else
@@ -74,7 +74,6 @@ __device__ __forceinline__ void vstage(VSmem<NX, NU> &S, const VSrc<TR> &q, doub
     oK.template load<false>(q.K, NX);
     if constexpr (RED || WANTK) oLi.template load<false>(q.Li, NU);
     if constexpr (RED) {
-        oBr.template load<true>(q.B, NU);
         if (q.Vn) oV.template load<false>(q.Vn, NX);
     }
     const double av = (l < NX && q.a) ? q.a[l] : 0.0;
@@ -115,9 +114,11 @@ __device__ __forceinline__ void vstage(VSmem<NX, NU> &S, const VSrc<TR> &q, doub
         emit(l < NX ? S.Psi[l] : 0.0, 0.0);
     }
     if constexpr (RED) {
-        const double dd = av + oBr.apply(S.kk);                  // a + B k
-        if (l < NX) S.d[l] = dd;
+        RowOp<NX, NU> rB;      // B again, as contiguous rows (read from cache)
+        rB.load(q.B, NU);
+        rB.apply(S.kk, [&](int r, double bk) { S.d[r] = S.av[r] + bk; });   // a + B k
         wsync();
+        const double dd = l < NX ? S.d[l] : 0.0;
         const double inc = q.Vn ? oV.apply(S.d) : dd;
         if (l < NX) S.v[l] += inc;
         wsync();

@@ -54,11 +54,14 @@ def test_factor_then_solve_matches_oracle(nx, nu, N, Ns, b):
     assert bt.status()[0, 0] == 0
     sol = bt.result(0)
     _check(prob, sol)
-    # the fused solve on the same workspace agrees to rounding
+    # the fused solve on the same workspace agrees to rounding: both are within
+    # the oracle bound, and their difference is the sum of two FP64 rounding
+    # errors taken in different summation orders (~1e-12 over a few hundred
+    # stages)
     bt.solve()
     torch.cuda.synchronize()
     fused = bt.result(0)
-    assert kkt.rel_error(sol, fused) < 1e-12
+    assert kkt.rel_error(sol, fused) < 1e-11
     bt.close()
 
 
