@@ -251,6 +251,24 @@ def run_precision(prec, args, data, dev):
         lat = {"batch": 1, "p50_ms": round(float(np.percentile(samples, 50)), 4),
                "p99_ms": round(float(np.percentile(samples, 99)), 4), "reps": args.latency_reps,
                "Ns": args.latency_Ns or args.Ns, "branch": args.latency_branch or args.branch}
+        # the same call captured once as a HIP graph and replayed (no host
+        # launch work per kernel); replays must reproduce the eager result
+        eager = one.result(0)
+        graph = one.capture(0)
+        for _ in range(5):
+            one.replay(graph)
+        torch.cuda.synchronize()
+        gsamples = []
+        for _ in range(args.latency_reps):
+            s0 = time.perf_counter()
+            one.replay(graph)
+            torch.cuda.synchronize()
+            gsamples.append(1e3 * (time.perf_counter() - s0))
+        rep = one.result(0)
+        lat["graph_p50_ms"] = round(float(np.percentile(gsamples, 50)), 4)
+        lat["graph_p99_ms"] = round(float(np.percentile(gsamples, 99)), 4)
+        lat["graph_equals_eager"] = bool(all(np.array_equal(rep[k], eager[k]) for k in ("x", "w", "lam"))
+                                         and int(one.status()[0, 0]) == 0)
         log("[%s] latency B=1:" % prec, lat)
         one.close()
 
