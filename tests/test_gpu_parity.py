@@ -171,3 +171,27 @@ def test_batching_config_uneven_horizons_sampled():
     for i in pick:
         _check(W.materialize(probs[i]), b.result(i))
     b.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_headline_batch_in_the_bench_launch_configuration(precision):
+    """The benchmarked workload at full size: 1024 instances of n_x = 32,
+    n_u = 16, N = 1024 (G2 drawn on the device, the bench's seed), leaf
+    length 512 and branch 8, FP64 and mixed.  Every instance reports success
+    (mixed: converged), and sampled instances match the serial oracle at
+    1e-10 (the oracle needs about a second per instance, so not all 1024)."""
+    torch, rs = _rs()
+    data = W.g2_torch(32, 16, 1024, 1024, seed=W.seed_for(5), device="cuda")
+    bt = rs.Batch(data, precision=precision, Ns=512, branch=8)
+    bt.solve()
+    torch.cuda.synchronize()
+    assert np.all(bt.status()[:, 0] == 0)
+    if precision == 1:
+        st = bt.refine_stats()
+        assert np.all(st[:, 3] == 1.0) and st[:, 0].max() <= TOL
+    rng = np.random.default_rng(11)
+    for i in sorted({0, 511, 1023} | set(int(j) for j in rng.integers(0, 1024, size=3))):
+        _check(W.instance_to_numpy(data, i), bt.result(i))
+    bt.close()
+    del data
+    torch.cuda.empty_cache()
