@@ -721,6 +721,59 @@ __device__ __forceinline__ void gemv(const U *M, int ld, const double *x, int R,
     }
 }
 
+// Both products of one row-major matrix M (rows x cols, leading dimension
+// ld) from a single read: M'v (outputs i < cols, handed to ocol(i, y)) and
+// M u (outputs k < rows, handed to orow(k, y)).  The threads form groups of
+// G = cols rounded up to a power of two (16, 32 or 64, inside one
+// wavefront); thread i of group p reads M(k, i) for the rows k of the
+// group's chunk, adds M(k, i) v_k to its column sum and passes M(k, i) u_i
+// through a DPP sum over the group for the row sum of k.  Every group runs
+// the same number of iterations, so the sums run with all lanes active.
+// The column sums of the groups are added through LDS (red, NT doubles) in a
+// fixed order; all threads of the workgroup must call it.
+template <int G, class OC, class OR>
+__device__ __forceinline__ void gemv_dual(const double *M, int ld, const double *v, const double *u, int rows,
+                                          int cols, OC ocol, OR orow, double *red) {
+    const int tid = threadIdx.x, parts = NT / G, i = tid & (G - 1), p = tid / G;
+    const int chunk = (rows + parts - 1) / parts, k0 = p * chunk;
+    const bool col = i < cols;
+    const double ui = col ? u[i] : 0.0;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < chunk; ++q) {
+        const int k = k0 + q;
+        const bool ok = col && k < rows;
+        const double mk = ok ? M[(int64_t)k * ld + i] : 0.0;
+        acc += ok ? mk * v[k] : 0.0;
+        const double r = sv::group_sum<G>(mk * ui);
+        if (i == 0 && k < rows) orow(k, r);
+    }
+    red[tid] = acc;
+    __syncthreads();
+    if (tid < cols) {
+        double s = 0.0;
+        for (int q = 0; q < parts; ++q) s += red[q * G + tid];
+        ocol(tid, s);
+    }
+    __syncthreads();
+}
+
+// gemv_dual for any cols <= 64; larger matrices take the two reads of gemv.
+template <class OC, class OR>
+__device__ __forceinline__ void gemv_both(const double *M, int ld, const double *v, const double *u, int rows,
+                                          int cols, OC ocol, OR orow, double *red) {
+    if (cols <= 16)
+        gemv_dual<16>(M, ld, v, u, rows, cols, ocol, orow, red);
+    else if (cols <= 32)
+        gemv_dual<32>(M, ld, v, u, rows, cols, ocol, orow, red);
+    else if (cols <= 64)
+        gemv_dual<64>(M, ld, v, u, rows, cols, ocol, orow, red);
+    else {
+        gemv<false>(M, ld, v, cols, rows, ocol, red);
+        gemv<true>(M, ld, u, rows, cols, orow, red);
+    }
+}
+
 // Operands of one backward stage of the vector recursion (as in the
 // register-resident kernels): P_{t+1} (TR-typed record, FP64 terminal or
 // message, or zero), V_{t+1} (record or identity), L^{-1}, L^{-T}, K.
@@ -1124,16 +1177,22 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
         }
         for (int i = tid; i < m; i += NT) ws[i] = w[i];
         __syncthreads();
-        // x row: Qx x + Qxw w - lam + A' lam+ ; lam+ row: A x + B w - x+
-        gemv<true>(Qx, n, xs, n, n, [&](int i, double v) { S.pt[i] = v; }, S.gred);
-        gemv<true>(Qxw, m, ws, n, m, [&](int i, double v) { S.d[i] = v; }, S.gred);
-        gemv<false>(A, n, ls, n, n, [&](int i, double v) { S.av[i] = v; }, S.gred);
-        gemv<true>(A, n, xs, n, n, [&](int i, double v) { S.y[i] = v; }, S.gred);
-        gemv<true>(B, m, ws, n, m, [&](int i, double v) { S.Psi[i] = v; }, S.gred);
-        // w row: Qxw' x + Qw w + B' lam+
-        gemv<false>(Qxw, m, xs, m, n, [&](int j, double v) { S.gw[j] = v; }, S.gred);
-        gemv<true>(Qw, m, ws, m, m, [&](int j, double v) { S.z[j] = v; }, S.gred);
-        gemv<false>(B, m, ls, m, n, [&](int j, double v) { S.kk[j] = v; }, S.gred);
+        // x row: Qx x + Qxw w - lam + A' lam+ ; lam+ row: A x + B w - x+ ;
+        // w row: Qxw' x + Qw w + B' lam+.  A, B and Qxw are read once for
+        // both of their products; Qx and Qw (symmetric) by columns.
+        gemv<false>(Qx, n, xs, n, n, [&](int i, double v) { S.pt[i] = v; }, S.gred);
+        gemv_both(A, n, ls, xs, n, n, [&](int i, double v) { S.av[i] = v; }, [&](int k, double v) { S.y[k] = v; },
+                  S.gred);
+        gemv_both(B, m, ls, ws, n, m, [&](int j, double v) { S.kk[j] = v; },
+                  [&](int k, double v) { S.Psi[k] = v; }, S.gred);
+        if (Qxw) {
+            gemv_both(Qxw, m, xs, ws, n, m, [&](int j, double v) { S.gw[j] = v; },
+                      [&](int k, double v) { S.d[k] = v; }, S.gred);
+        } else {
+            for (int i = tid; i < n; i += NT) S.d[i] = 0.0;
+            for (int j = tid; j < m; j += NT) S.gw[j] = 0.0;
+        }
+        gemv<false>(Qw, m, ws, m, m, [&](int j, double v) { S.z[j] = v; }, S.gred);
         __syncthreads();
         double part = 0.0;
         for (int i = tid; i < n; i += NT) {
