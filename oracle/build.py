@@ -16,7 +16,7 @@ SOURCES = [os.path.join(HERE, "riccati_ref.c")]
 def build(verbose=False):
     os.makedirs(BUILD_DIR, exist_ok=True)
     tmp = LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp] + SOURCES + ["-lm"]
+    cmd = ["gcc", "-O3", "-std=c99", "-fPIC", "-shared", "-o", tmp] + SOURCES + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)

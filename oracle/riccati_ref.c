@@ -39,36 +39,45 @@ static void mat_vec(int n, int m, const double *M, const double *v, double *y)
     }
 }
 
-/* y (m) = M' v, M is n x m */
+/* y (m) = M' v, M is n x m.  Every y[j] is summed over i in ascending
+ * order; the loops run row by row of M for contiguous reads. */
 static void matT_vec(int n, int m, const double *M, const double *v, double *y)
 {
-    for (int j = 0; j < m; ++j) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += M[i * m + j] * v[i];
-        y[j] = s;
+    for (int j = 0; j < m; ++j) y[j] = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double vi = v[i];
+        for (int j = 0; j < m; ++j) y[j] += M[i * m + j] * vi;
     }
 }
 
-/* C (p x q) = X' (p x r)' ... : C = X' Y with X r-by-p and Y r-by-q */
+/* C (p x q) = X' Y with X r-by-p and Y r-by-q.  Every C[i][j] is summed over
+ * k in ascending order starting from zero (the plain definition); the loops
+ * run k outermost so that rows of X and Y are read contiguously. */
 static void matT_mat(int r, int p, int q, const double *X, const double *Y, double *C)
 {
-    for (int i = 0; i < p; ++i)
-        for (int j = 0; j < q; ++j) {
-            double s = 0.0;
-            for (int k = 0; k < r; ++k) s += X[k * p + i] * Y[k * q + j];
-            C[i * q + j] = s;
+    for (int e = 0; e < p * q; ++e) C[e] = 0.0;
+    for (int k = 0; k < r; ++k)
+        for (int i = 0; i < p; ++i) {
+            const double xki = X[k * p + i];
+            double *Ci = C + i * q;
+            const double *Yk = Y + k * q;
+            for (int j = 0; j < q; ++j) Ci[j] += xki * Yk[j];
         }
 }
 
-/* C (p x q) = X Y with X p-by-r and Y r-by-q */
+/* C (p x q) = X Y with X p-by-r and Y r-by-q; C[i][j] summed over k in
+ * ascending order, rows of Y read contiguously. */
 static void mat_mat(int p, int r, int q, const double *X, const double *Y, double *C)
 {
-    for (int i = 0; i < p; ++i)
-        for (int j = 0; j < q; ++j) {
-            double s = 0.0;
-            for (int k = 0; k < r; ++k) s += X[i * r + k] * Y[k * q + j];
-            C[i * q + j] = s;
+    for (int i = 0; i < p; ++i) {
+        double *Ci = C + i * q;
+        for (int j = 0; j < q; ++j) Ci[j] = 0.0;
+        for (int k = 0; k < r; ++k) {
+            const double xik = X[i * r + k];
+            const double *Yk = Y + k * q;
+            for (int j = 0; j < q; ++j) Ci[j] += xik * Yk[j];
         }
+    }
 }
 
 /* Cholesky G = L L' (lower, row-major, n x n).  Returns 0 on success, -1 if

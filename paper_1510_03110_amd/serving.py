@@ -189,6 +189,7 @@ class Lane:
         self.probs = None
         self.members = []
         self.event = None
+        self.info_host = None     # pinned copy of the status words of the launch in flight
 
 
 class ServingEngine:
@@ -210,6 +211,7 @@ class ServingEngine:
         self.lanes = [Lane(device) for _ in range(lanes)]
         self.lat = []
         self.done = 0
+        self.failed = 0               # requests whose solve reported a numerical failure
         self.rejected = 0
         self.record = record
         self.results = {}
@@ -271,11 +273,15 @@ class ServingEngine:
         lane.work = torch.empty(lane.work_bytes + 256, dtype=torch.uint8, device=self.device)
         lane.work_ptr = (lane.work.data_ptr() + 255) // 256 * 256
         lane.info = torch.zeros(2 * len(lane.sessions), dtype=torch.int32, device=self.device)
+        lane.info_host = torch.zeros(2 * len(lane.sessions), dtype=torch.int32, pin_memory=True)
         lane.probs = (rs.rs_problem * len(lane.sessions))()
         for i, s in enumerate(lane.sessions):
             s.fill_descriptor(lane.probs[i])
             lane.probs[i].flags = rs.RS_PROB_SKIP
             s.current = (0, 0)         # a new workspace holds no factors yet
+        # the status array and the arrays of newly admitted sessions were
+        # filled on the current stream; the lane's stream waits for that
+        lane.stream.wait_stream(torch.cuda.current_stream())
         lane.version = self.version
 
     # ------------------------------------------------------------ requests
@@ -306,6 +312,8 @@ class ServingEngine:
             rs.rs_plan_set_timing(lane.plan, True)
         rs.rs_batch_solve(lane.plan, lane.probs, lane.work_ptr, lane.work_bytes, lane.stream.cuda_stream,
                           lane.info.data_ptr())
+        with torch.cuda.stream(lane.stream):
+            lane.info_host.copy_(lane.info, non_blocking=True)
         for s, _ in lane.members:
             Ns, _br = self.tuner.choose(s.nx, s.nu, s.N, self.precision)
             s.current = rs.ring_current_leaves(s.t_abs, s.N, Ns)
@@ -316,23 +324,34 @@ class ServingEngine:
         self.host_s += time.perf_counter() - h0
 
     def _complete(self, lane, now):
-        st = None
         if self.timing:
             for k, (ms, n) in rs.rs_plan_kernel_times(lane.plan, reset=True).items():
                 if n:
                     self.kernel_ms[k] = self.kernel_ms.get(k, 0.0) + ms
+        # the launch's event has completed, so the pinned status copy queued
+        # behind the solve on the lane's stream is complete too
+        st = lane.info_host.view(-1, 2).numpy()
+        idx = {id(s): i for i, s in enumerate(lane.sessions)}
         for s, arrival in lane.members:
+            i = idx[id(s)]
+            status = int(st[i, 0])
             s.busy = False
-            s.solved = True
-            self.lat.append(now - arrival)
-            self.done += 1
+            if status == 0:
+                s.solved = True
+                self.lat.append(now - arrival)
+                self.done += 1
+            else:
+                # a failed solve leaves no usable factors and no x_1: the
+                # session's next request factors every leaf again and keeps
+                # its initial state
+                s.solved = False
+                s.current = (0, 0)
+                self.failed += 1
             if self.record:
-                if st is None:
-                    st = lane.info.view(-1, 2).cpu().numpy()
-                i = lane.sessions.index(s)
                 self.results.setdefault(s.sid, []).append(
                     dict(x=s.x.cpu().numpy(), w=s.w.cpu().numpy(), lam=s.lam.cpu().numpy(),
-                         obj=float(s.obj.cpu()[0]), status=int(st[i, 0]), window=s.window_host()))
+                         obj=float(s.obj.cpu()[0]), status=status, stage=int(st[i, 1]),
+                         window=s.window_host()))
         lane.members = []
         lane.event = None
 
@@ -367,7 +386,7 @@ class ServingEngine:
         el = time.perf_counter() - t0
         sizes = self.batch_sizes[sizes0:]
         lat = np.array(self.lat) * 1e3
-        return {"requests": n, "completed": self.done, "elapsed_s": round(el, 3),
+        return {"requests": n, "completed": self.done, "failed": self.failed, "elapsed_s": round(el, 3),
                 "solves_per_s": round(self.done / el, 1) if el > 0 else None,
                 "p50_ms": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
                 "p99_ms": round(float(np.percentile(lat, 99)), 3) if len(lat) else None,
@@ -462,7 +481,7 @@ def main(argv=None):
     warm = poisson_trace(args.rate, args.warmup_seconds, len(shapes), pools, shapes, args.seed + 1)
     eng.run(warm)
     torch.cuda.synchronize()
-    eng.lat, eng.done, eng.kernel_ms, eng.host_s = [], 0, {}, 0.0
+    eng.lat, eng.done, eng.failed, eng.kernel_ms, eng.host_s = [], 0, 0, {}, 0.0
     trace = poisson_trace(args.rate, args.seconds, len(shapes), pools, shapes, args.seed + 2)
     out = eng.run(trace)
     out.update({"rate_req_s": args.rate, "precision": args.precision,
