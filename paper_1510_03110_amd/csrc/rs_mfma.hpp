@@ -222,16 +222,25 @@ struct NoEmit {
 
 // Per-thread registers holding the next stage's inputs until they can be
 // written to LDS (A, B, a, lx, lw, c) and the tiles of Qx, Qxw', Qw that this
-// thread's wave adds in the F / H' / G products.
-
-
+// thread's wave adds in the F / H' / G products.  They hold the FP64 values
+// as loaded: a conversion to the working precision at load time would make
+// the wave wait for the load right there.
 template <class T, int NX, int NU>
 struct Prefetch : Tiles<NX, NU> {
     static constexpr int NA = (NX * NX + NT - 1) / NT, NB = (NX * NU + NT - 1) / NT;
-    T a_[NA], b_[NB];
-    T av, lx, lw, c;
-    v4_t<T> q[Tiles<NX, NU>::PER_WAVE];
+    double a_[NA], b_[NB];
+    double av, lx, lw, c;
+    d4 q[Tiles<NX, NU>::PER_WAVE];
 };
+
+// Waits until every global load and store this wave issued has completed
+// (vmcnt(0); expcnt and lgkmcnt left at their maxima).  Issued where the
+// only loads still in flight are the next stage's prefetch, started a whole
+// phase sequence earlier, so the wait costs little; afterwards no register
+// that a phase reads is tied to an outstanding load, and the compiler needs
+// no conservative full wait inside the phases (where it would also wait for
+// the loads issued at the start of the stage).
+__device__ __forceinline__ void wait_global() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // Tile t of phase B: F lower tiles, then H' tiles, then G lower tiles.
 template <int NX, int NU>
@@ -259,22 +268,20 @@ __device__ __forceinline__ void prefetch_mats(Prefetch<T, NX, NU> &pf, const Sta
 #pragma unroll
     for (int q = 0; q < PF::NA; ++q) {
         const int e = tid + q * NT;
-        pf.a_[q] = e < NX * NX ? (T)gload(s.A + e) : T(0);
+        pf.a_[q] = e < NX * NX ? gload(s.A + e) : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < PF::NB; ++q) {
         const int e = tid + q * NT;
-        pf.b_[q] = e < NX * NU ? (T)gload(s.B + e) : T(0);
+        pf.b_[q] = e < NX * NU ? gload(s.B + e) : 0.0;
     }
-    pf.av = (tid < NX && s.a) ? (T)gload(s.a + tid) : T(0);
-    pf.lx = (tid < NX && s.lx) ? (T)gload(s.lx + tid) : T(0);
-    pf.lw = (tid < NU && s.lw) ? (T)gload(s.lw + tid) : T(0);
-    pf.c = (T)s.c;
+    pf.av = (tid < NX && s.a) ? gload(s.a + tid) : 0.0;
+    pf.lx = (tid < NX && s.lx) ? gload(s.lx + tid) : 0.0;
+    pf.lw = (tid < NU && s.lw) ? gload(s.lw + tid) : 0.0;
+    pf.c = s.c;
 }
 
-// ... and its Qx / Qxw' / Qw tiles, loaded once this stage's tiles are no
-// longer needed (after phase C), so that the two sets of tiles are never live
-// together; their loads still have phases D and E to arrive.
+// ... and its Qx / Qxw' / Qw tiles (those of this thread's wave).
 template <class T, int NX, int NU>
 __device__ __forceinline__ void prefetch_q(Prefetch<T, NX, NU> &pf, const StageSrc &s) {
     using PF = Prefetch<T, NX, NU>;
@@ -282,16 +289,24 @@ __device__ __forceinline__ void prefetch_q(Prefetch<T, NX, NU> &pf, const StageS
 #pragma unroll
     for (int t = 0; t < PF::TILES; ++t) {
         if (PF::owner(t) != w) continue;
-        v4_t<T> q = zero4<T>();
+        d4 q = zero4<double>();
         int kind, ti, tj;
         phaseB_tile<NX, NU>(t, kind, ti, tj);
         tile_for<T>(ti, tj, [&](int r, int i, int j) {
-            if (kind == 0) q[r] = (T)gload(s.Qx + i * NX + j);
-            else if (kind == 1) q[r] = s.Qxw ? (T)gload(s.Qxw + j * NU + i) : T(0);
-            else q[r] = (T)gload(s.Qw + i * NU + j);
+            if (kind == 0) q[r] = gload(s.Qx + i * NX + j);
+            else if (kind == 1) q[r] = s.Qxw ? gload(s.Qxw + j * NU + i) : 0.0;
+            else q[r] = gload(s.Qw + i * NU + j);
         });
         pf.q[PF::slot(t)] = q;
     }
+}
+
+// The prefetched tiles in the working precision.
+template <class T, int NX, int NU>
+__device__ __forceinline__ void take_q(v4_t<T> *qt, const Prefetch<T, NX, NU> &pf) {
+#pragma unroll
+    for (int u = 0; u < Tiles<NX, NU>::PER_WAVE; ++u)
+        qt[u] = v4_t<T>{(T)pf.q[u][0], (T)pf.q[u][1], (T)pf.q[u][2], (T)pf.q[u][3]};
 }
 
 template <class T, int NX, int NU>
@@ -307,19 +322,19 @@ __device__ __forceinline__ void commit_stage(MSmem<T, NX, NU, RED, SOLVE> &S, co
 #pragma unroll
     for (int q = 0; q < PF::NA; ++q) {
         const int e = tid + q * NT;
-        if (e < NX * NX) S.A[e] = pf.a_[q];
+        if (e < NX * NX) S.A[e] = (T)pf.a_[q];
     }
 #pragma unroll
     for (int q = 0; q < PF::NB; ++q) {
         const int e = tid + q * NT;
-        if (e < NX * NU) S.B[e] = pf.b_[q];
+        if (e < NX * NU) S.B[e] = (T)pf.b_[q];
     }
     if (tid < NX) {
-        S.av[tid] = pf.av;
-        S.lx[tid] = pf.lx;
+        S.av[tid] = (T)pf.av;
+        S.lx[tid] = (T)pf.lx;
     }
-    if (tid < NU) S.lw[tid] = pf.lw;
-    if (tid == 0) S.c = pf.c;
+    if (tid < NU) S.lw[tid] = (T)pf.lw;
+    if (tid == 0) S.c = (T)pf.c;
 }
 
 // Cholesky factorization G = L L' ("a factorization of G", Alg. 1) and the
@@ -497,20 +512,21 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
     if (tid == 0) S.bad = 0;
     if (count > 0) {
         prefetch_stage<T, NX, NU>(pf, get(count - 1));
+        wait_global();
         commit_stage(S, pf);
-#pragma unroll
-        for (int u = 0; u < Tiles<NX, NU>::PER_WAVE; ++u) qt[u] = pf.q[u];
+        take_q(qt, pf);
     }
     lds_sync();
-    // The next stage's inputs are loaded into registers at the start of a
-    // stage and committed at the start of phase E (nothing in phase E reads
-    // A, B or the stage vectors), before phase E issues its global stores, so
-    // the only wait for the loads does not also wait for those stores.
+    // The next stage's inputs (A, B, stage vectors and the Q tiles) are
+    // loaded into registers at the start of a stage and committed at the
+    // start of phase E (nothing in phase E reads A, B or the stage vectors),
+    // after an explicit wait for them and before phase E issues its global
+    // stores.  The loads have the stage's first phases to arrive.
     for (int s = count - 1; s >= 0; --s) {
         // stage s inputs: A, B, a, lx, lw, c in LDS; Qx/Qxw'/Qw tiles in qt
         // the next stage's source (pointers and c), formed once per stage
         const StageSrc nxt = s > 0 ? get(s - 1) : StageSrc{};
-        if (s > 0) prefetch_mats<T, NX, NU>(pf, nxt);
+        if (s > 0) prefetch_stage<T, NX, NU>(pf, nxt);
         pre(s, S);
         using TT = Tiles<NX, NU>;
         v4_t<T> fkeep[TT::PER_WAVE_F];      // F tiles of this wave (merged phase)
@@ -700,7 +716,6 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
                 }
             }
         }
-        if (s > 0) prefetch_q<T, NX, NU>(pf, nxt);
         lds_sync();
         if (tid == 0 && S.bad) {
             record_failure(info, inst, fail_code, stage_base < 0 ? -1 : stage_base + s);
@@ -733,9 +748,9 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
         //      Psi = g_x - Y'z, (RED) v += V'a + X'z, cbar -= z'z/2
         {
             if (s > 0) {
+                wait_global();
                 commit_stage(S, pf);
-#pragma unroll
-                for (int u = 0; u < Tiles<NX, NU>::PER_WAVE; ++u) qt[u] = pf.q[u];
+                take_q(qt, pf);
             }
             constexpr int TL = TX * (TX + 1) / 2, TQ = RED ? TL : 0, TV = RED ? TX * TX : 0,
                           TK = KFORM ? TU * TX : 0, TLT = LTFORM ? TU * TX : 0;
