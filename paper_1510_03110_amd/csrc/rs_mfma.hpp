@@ -186,7 +186,7 @@ struct MSmem {
     T BV[RED ? NU * NX : 1];   // B'V
     T X[RED ? NU * NX : 1];    // L^{-1} B'V
     T AV[RED && Tiles<NX, NU>::FAST ? NX * NX : 1];   // A'V (merged first phase)
-    T Psi[NX], av[NX], lx[NX], pt[NX], gx[NX], x[NX], ax[NX];
+    T Psi[NX], av[NX], lx[NX], pt[NX], pt2[NX], gx[NX], x[NX], ax[NX];
     T lw[NU], gw[NU], z[NU], kk[NU], wv[NU];
     T v[RED ? NX : 1], Vta[RED ? NX : 1];
     T c, cbar, red[4];
@@ -337,6 +337,13 @@ __device__ __forceinline__ void commit_stage(MSmem<T, NX, NU, RED, SOLVE> &S, co
     if (tid == 0) S.c = (T)pf.c;
 }
 
+// Orders one wavefront's LDS accesses (no workgroup barrier).
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 // Cholesky factorization G = L L' ("a factorization of G", Alg. 1) and the
 // inverse L^{-1}, by one wavefront.  Lane i holds row i of G / L in
 // registers; entries of other rows are broadcast with readlane, which places
@@ -379,15 +386,22 @@ __device__ __forceinline__ int chol_inv_wave(T *G, T *LiT) {
     // c-th entry is set to 1 / L[c][c] at step c (where e_c would be scaled),
     // so no lane-dependent start vector is formed ahead of time (such a
     // vector, invariant across stages, is otherwise kept in scratch).
+    // Column k of L is broadcast again here from a copy that the compiler
+    // cannot see through, taken once x[k] is final: otherwise it would reuse
+    // the factorization's broadcasts of the same entries, or hoist this
+    // loop's broadcasts, and keep all of them live in scalar registers at
+    // once (spilled to vector lanes and back).
     T x[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) x[i] = T(0);
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-        const T ik = bcast_lane(invd, k);
+        T gk = g[k], dk = invd;
+        asm volatile("" : "+v"(gk), "+v"(dk) : "v"(x[k]));
+        const T ik = bcast_lane(dk, k);
         x[k] = (ln == k) ? ik : x[k] * ik;
 #pragma unroll
-        for (int i = k + 1; i < M; ++i) x[i] -= bcast_lane(g[k], i) * x[k];
+        for (int i = k + 1; i < M; ++i) x[i] -= bcast_lane(gk, i) * x[k];
     }
     if (ln < M) {
 #pragma unroll
@@ -475,12 +489,6 @@ __device__ __forceinline__ void chol_inv_block32(T *G, T *LiT, int *bad, Side si
 }
 
 // Wave-level sum over the 64 lanes (result in every lane).
-// Orders one wavefront's LDS accesses (no workgroup barrier).
-__device__ __forceinline__ void wave_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-}
 
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -592,30 +600,40 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
                     }
                 }
             }
-            if (VEC && w == 3) {
+            // Vector lines: pt = Psi - P a, cbar, g_x = A'pt - l_x, g_w = B'pt - l_w.
+            // In the reduction with n_x = 32, wave 3 has the B'V and A'V
+            // tiles, so waves 1 and 2 (the lighter matrix roles) take the
+            // vector lines, each forming pt itself: wave 1 also cbar and g_x,
+            // wave 2 g_w.  Otherwise wave 3 does all of them.
+            constexpr int VA = (RED && TX == 2) ? 1 : 3, VB = (RED && TX == 2) ? 2 : 3;
+            if (VEC && (w == VA || w == VB)) {
+                T *pt = w == VA ? S.pt : S.pt2;
                 T part = T(0);
                 if (l < NX) {
                     T pa = T(0);
 #pragma unroll 8
                     for (int k = 0; k < NX; ++k) pa += S.P[k * NX + l] * S.av[k];
-                    S.pt[l] = S.Psi[l] - pa;
+                    pt[l] = S.Psi[l] - pa;
                     part = S.av[l] * (T(0.5) * pa - S.Psi[l]);
                 }
-                // cbar += 1/2 a'Pa - Psi'a + c (Alg. 2, with P_{t+1}, Psi_{t+1})
-                part = wave_sum(part);
-                if (l == 0) S.cbar += part + S.c;
+                if (w == VA) {
+                    // cbar += 1/2 a'Pa - Psi'a + c (Alg. 2, with P_{t+1}, Psi_{t+1})
+                    part = wave_sum(part);
+                    if (l == 0) S.cbar += part + S.c;
+                }
                 wave_fence();
-                if (l < NX) {
+                if (w == VA && l < NX) {
                     T acc = -S.lx[l];
 #pragma unroll 8
-                    for (int k = 0; k < NX; ++k) acc += S.A[k * NX + l] * S.pt[k];
+                    for (int k = 0; k < NX; ++k) acc += S.A[k * NX + l] * pt[k];
                     S.gx[l] = acc;
-                } else if (l < NX + NU) {
-                    const int i = l - NX;
-                    T acc = -S.lw[i];
+                }
+                const int iw = VA == VB ? l - NX : l;
+                if (w == VB && iw >= 0 && iw < NU) {
+                    T acc = -S.lw[iw];
 #pragma unroll 8
-                    for (int k = 0; k < NX; ++k) acc += S.B[k * NU + i] * S.pt[k];
-                    S.gw[i] = acc;
+                    for (int k = 0; k < NX; ++k) acc += S.B[k * NU + iw] * pt[k];
+                    S.gw[iw] = acc;
                 }
             }
         } else {
