@@ -137,6 +137,36 @@ typedef struct rs_options {
  * from calls with the same flag. */
 #define RS_PLAN_RANK_REVEAL 2
 
+/* rs_options.flags: per-instance report of every solve (rs_info, read with
+ * rs_info_report).  The quantities are those of the KKT system of P(N)
+ * (Sec. 3: the optimality conditions whose solution the Newton step is;
+ * unknowns lam_0, x_0, w_0, lam_1, ..., x_N, right-hand side r), in infinity
+ * norms and FP64:
+ *   rel_resid   = ||r - K z|| / ||r||                 (returned solution z)
+ *   bwd_err     = ||r - K z|| / (||K|| ||z|| + ||r||) (normwise backward error)
+ *   est_fwd_err = estimated ||z - z*|| / ||z*||
+ * FP64 plans: after the solve, one FP64 residual pass gives rel_resid and
+ * bwd_err, and one correction solve K d = r - K z with the plan's own kernels
+ * (measured, not applied) gives est_fwd_err = ||d|| / ||z|| (about twice the
+ * solve's time in all).  Mixed plans: rel_resid and est_fwd_err are those of
+ * the refinement (see rs_refine_stats); bwd_err is formed from the final
+ * residual.  Either way ||K|| comes from one extra pass over the stage
+ * matrices per factorization.  Without this flag rs_info_report gives the
+ * status words, and for mixed plans rel_resid, est_fwd_err and the
+ * refinement count, with bwd_err = -1 (FP64 plans: all three measures -1). */
+#define RS_PLAN_REPORT 4
+
+/* Per-instance result report (device memory, 40 bytes each). */
+typedef struct rs_info {
+    double rel_resid;       /* ||r - K z||_inf / ||r||_inf                          */
+    double bwd_err;         /* ||r - K z||_inf / (||K||_inf ||z||_inf + ||r||_inf)  */
+    double est_fwd_err;     /* estimated relative forward error of z                */
+    int32_t refine_iters;   /* corrections applied (mixed precision; 0 in FP64)    */
+    int32_t bad_stage;      /* failing stage index, or -1                           */
+    int32_t status;         /* rs_status of the instance                            */
+    int32_t reserved;
+} rs_info;
+
 typedef struct rs_plan_s *rs_plan;
 
 /*
@@ -295,6 +325,18 @@ rs_status rs_ip_step(const rs_ip *ip, int32_t phase, double sigma_mu, void *stre
 rs_status rs_ip_mu(const rs_ip *ip, double alpha_p, double alpha_d, void *stream);
 rs_status rs_ip_update(const rs_ip *ip, double alpha_p, double alpha_d, void *stream);
 
+/*
+ * Write the per-instance report of the last rs_batch_solve / rs_solve with
+ * this plan and workspace into report_dev[count] (device memory, rs_info
+ * records), asynchronously on `stream`, after that call on the same stream.
+ * info_dev: the status array passed to that call (NULL if it was NULL).  The
+ * measures are meaningful for instances with status RS_OK; see
+ * RS_PLAN_REPORT for what is formed with and without it.  Errors: RS_ERR_ARG
+ * (NULL plan, work or report_dev, unaligned work), RS_ERR_HIP.
+ */
+rs_status rs_info_report(rs_plan plan, const void *work, const int32_t *info_dev, rs_info *report_dev,
+                         void *stream);
+
 /* Device workspace bytes the plan needs (caller allocates, 256-byte aligned). */
 rs_status rs_plan_workspace_size(rs_plan plan, size_t *bytes);
 
@@ -320,8 +362,9 @@ rs_status rs_batch_solve(rs_plan plan, const rs_problem *probs, void *work,
  * (RS_ERR_NOT_SPD with the stage, RS_ERR_SINGULAR_MASTER) go to info_dev as
  * for rs_batch_solve.  The factors stay valid until the next rs_factor or
  * rs_batch_solve with the same plan and workspace.  Needs a plan created
- * with RS_PLAN_FACTORED (else RS_ERR_ARG); RS_ERR_UNSUPPORTED for shapes
- * without factor kernels (nx, nu not multiples of 16).
+ * with RS_PLAN_FACTORED or a mixed precision (else RS_ERR_ARG); every shape
+ * that rs_plan_create accepts has factor kernels (matrix-core kernels for the
+ * tile shapes, large-block kernels for the others).
  */
 rs_status rs_factor(rs_plan plan, const rs_problem *probs, void *work, size_t work_bytes,
                     void *stream, int32_t *info_dev);

@@ -58,6 +58,8 @@ struct rs_plan_s {
     bool via_factor = false;        // FP64 solve = stored factorization + solve (large-block shapes)
     bool receding = false;          // receding-horizon layout (rs_plan_create_ring)
     bool rank_reveal = false;       // rank-revealing master stages (RS_PLAN_RANK_REVEAL)
+    bool report = false;            // per-instance report: K norm, FP64 residual, error estimate
+    bool refine_ws = false;         // workspace holds the refinement tables (mixed or report)
     rs_options opt{};               // options the plan was made with
     bool tables_dirty = false;      // host tables changed since the last upload
     hipEvent_t tables_ev = nullptr; // completion of the last table upload
@@ -371,12 +373,14 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         P->bf16 = opt->precision == RS_MIXED_BF16;
         P->factored = P->mixed || (opt->flags & RS_PLAN_FACTORED) != 0;
         P->rank_reveal = (opt->flags & RS_PLAN_RANK_REVEAL) != 0;
+        P->report = (opt->flags & RS_PLAN_REPORT) != 0;
         if (opt->Ns > 0) P->Ns = opt->Ns;
         if (opt->branch > 0) P->branch = opt->branch;
         P->max_refine = opt->max_refine > 0 ? opt->max_refine : (P->bf16 ? 20 : 5);
         if (opt->tol > 0) P->tol = opt->tol;
     }
     if (opt) P->opt = *opt;
+    P->refine_ws = P->mixed || P->report;
     P->top_max = P->branch;
     P->count = count;
     P->dims.resize(3 * (size_t)count);
@@ -469,7 +473,7 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
             P->factored = true;
             P->via_factor = true;
         }
-        if (!se || (P->factored && !(se->factor[fac][0] && se->vsolve[f32][0])) || (P->mixed && !se->refine[0])) {
+        if (!se || (P->factored && !(se->factor[fac][0] && se->vsolve[f32][0])) || (P->refine_ws && !se->refine[0])) {
             delete P;
             return RS_ERR_UNSUPPORTED;
         }
@@ -532,7 +536,7 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
     // workspace layout
     size_t off = 0;
     P->off_probs = off;                 // user problems, then (mixed) the correction problems,
-    P->off_padargs = off + sizeof(DevProb) * count * (P->mixed ? 2 : 1);   // then the padding jobs
+    P->off_padargs = off + sizeof(DevProb) * count * (P->refine_ws ? 2 : 1);   // then the padding jobs
     off = align_up(P->off_padargs + sizeof(PadArgs) * P->pad_inst.size());
     P->off_info = off;
     off = align_up(off + sizeof(int32_t) * 2 * count);
@@ -595,7 +599,7 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
             off = align_up(off + sizeof(double) * (size_t)g.leaf_stages * LeafRec{g.nx, g.nu}.vec());
         }
     }
-    if (P->mixed) {
+    if (P->refine_ws) {
         P->off_conv = off;                 // conv[count] | active[max_refine + 1]
         off = align_up(off + sizeof(int32_t) * (count + P->max_refine + 1));
         P->off_stats = off;
@@ -813,7 +817,7 @@ static rs_status bind_and_upload(rs_plan P, const rs_problem *probs, char *work,
         d.w = a.wp;
         d.nu = PAD_NU;
     }
-    if (P->mixed) {
+    if (P->refine_ws) {
         // correction problems: the same matrices; right-hand side and
         // solution in the workspace (c = cN = 0, no objective)
         dp.resize(2 * (size_t)P->count);
@@ -931,7 +935,7 @@ static GroupArgs group_args(rs_plan P, char *W, size_t gi, int32_t *info, bool c
     a.ident = P->rank_reveal ? reinterpret_cast<const double *>(W + g.off_ident) : nullptr;
     a.nx = g.nx;
     a.nu = g.nu;
-    if (P->mixed) {
+    if (P->refine_ws) {
         a.corr = user + P->count;
         a.conv = with_conv ? reinterpret_cast<const int32_t *>(W + P->off_conv) : nullptr;
         a.active = iter >= 0 ? reinterpret_cast<const int32_t *>(W + P->off_conv) + P->count + iter : nullptr;
@@ -1000,9 +1004,43 @@ static rs_status launch_check(rs_plan P, char *W, int32_t *info, hipStream_t st,
                                    reinterpret_cast<double *>(W + P->off_stats), conv, info,
                                    reinterpret_cast<const DevProb *>(W + P->off_probs), mode, P->tol,
                                    iter >= 0 ? conv + P->count + iter : (mode == 0 ? conv + P->count : nullptr),
-                                   mode == 0 ? P->max_refine + 1 : 0, st);
+                                   mode == 0 ? P->max_refine + 1 : 0, P->report ? 1 : 0, st);
     });
     return e == hipSuccess ? RS_OK : RS_ERR_HIP;
+}
+
+// Infinity norm of every leaf's rows of the KKT matrix (report plans), taken
+// once per factorization: the matrices do not change between its solves.
+static rs_status launch_knorm_all(rs_plan P, char *W, int32_t *info, hipStream_t st) {
+    for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+        GroupArgs a = group_args(P, W, gi, info, false, false);
+        if (a.nleaves == 0) continue;
+        if (timed(P, KK_REPORT, st, [&] { return launch_knorm(a, st); }) != hipSuccess) return RS_ERR_HIP;
+    }
+    return RS_OK;
+}
+
+// Report of an FP64 solve (report plans): the FP64 residual of the returned
+// solution (relative residual, backward error), then one correction solve
+// of K d = r - K z with the plan's own kernels, measured but not applied:
+// ||d|| / ||z|| estimates the relative forward error of z.
+static rs_status report_fp64(rs_plan P, char *W, int32_t *info, hipStream_t st, int pass) {
+    rs_status s = launch_check(P, W, info, st, 0);
+    if (s == RS_OK) s = launch_refine(P, W, info, st, 0, true);
+    if (s == RS_OK) s = launch_check(P, W, info, st, 4);
+    if (s == RS_OK) s = launch_pass(P, W, info, st, pass, true, true, true);
+    if (s == RS_OK) {
+        for (size_t gi = 0; gi < P->groups.size() && s == RS_OK; ++gi) {
+            Group &g = P->groups[gi];
+            GroupArgs a = group_args(P, W, gi, info, false, true);
+            a.measure_only = 1;
+            if (a.nleaves == 0) continue;
+            if (timed(P, KK_UPDATE, st, [&] { return g.shape->refine[1](a, a.nleaves, st); }) != hipSuccess)
+                s = RS_ERR_HIP;
+        }
+    }
+    if (s == RS_OK) s = launch_check(P, W, info, st, 5);
+    return s;
 }
 
 // Solve on the stored mixed-precision factorization with FP64 iterative
@@ -1042,13 +1080,25 @@ static rs_status run_padded(rs_plan P, char *W, int32_t *info, hipStream_t st, i
 // Kernel sequence of a call once the descriptors are bound.
 // mode 0 = rs_batch_solve, 1 = rs_factor, 2 = rs_solve.
 static rs_status run_sequence(rs_plan P, char *W, int32_t *info, hipStream_t st, int mode) {
-    if (!P->mixed && P->via_factor && mode == 0) {
-        rs_status s = launch_pass(P, W, info, st, 1, false, false, false);
-        return s == RS_OK ? launch_pass(P, W, info, st, 2, true, false, false) : s;
+    if (!P->mixed) {
+        rs_status s;
+        int solve_pass;
+        if (P->via_factor && mode == 0) {
+            s = launch_pass(P, W, info, st, 1, false, false, false);
+            if (s == RS_OK) s = launch_pass(P, W, info, st, 2, true, false, false);
+            solve_pass = 2;
+        } else {
+            s = launch_pass(P, W, info, st, mode, mode == 2, false, false);
+            solve_pass = mode;
+        }
+        if (s != RS_OK || !P->report) return s;
+        if (mode != 2) s = launch_knorm_all(P, W, info, st);
+        if (s != RS_OK || mode == 1) return s;
+        return report_fp64(P, W, info, st, solve_pass);
     }
-    if (!P->mixed) return launch_pass(P, W, info, st, mode, mode == 2, false, false);
     if (mode != 2) {
         rs_status s = launch_pass(P, W, info, st, 1, false, false, false);
+        if (s == RS_OK && P->report) s = launch_knorm_all(P, W, info, st);
         if (s != RS_OK || mode == 1) return s;
     }
     return mixed_solve(P, W, info, st);
@@ -1142,10 +1192,22 @@ rs_status rs_refine_stats(rs_plan P, const void *work, double *out, void *stream
     if (!P->mixed) return RS_ERR_ARG;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const char *W = static_cast<const char *>(work);
-    if (hipMemcpyAsync(out, W + P->off_stats, sizeof(double) * ST_N * P->count, hipMemcpyDeviceToHost, st) !=
-        hipSuccess)
+    if (hipMemcpy2DAsync(out, sizeof(double) * ST_PUBLIC, W + P->off_stats, sizeof(double) * ST_N,
+                         sizeof(double) * ST_PUBLIC, P->count, hipMemcpyDeviceToHost, st) != hipSuccess)
         return RS_ERR_HIP;
     return hipStreamSynchronize(st) == hipSuccess ? RS_OK : RS_ERR_HIP;
+}
+
+rs_status rs_info_report(rs_plan P, const void *work, const int32_t *info_dev, rs_info *report_dev, void *stream) {
+    static_assert(sizeof(rs_info) == 40, "rs_info layout (3 doubles, 4 int32)");
+    if (!P || !work || !report_dev) return RS_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(work) % ALIGN) return RS_ERR_ARG;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const char *W = static_cast<const char *>(work);
+    const int32_t *info = info_dev ? info_dev : reinterpret_cast<const int32_t *>(W + P->off_info);
+    const double *stats = P->refine_ws ? reinterpret_cast<const double *>(W + P->off_stats) : nullptr;
+    return launch_report(P->count, stats, info, P->mixed ? 1 : 0, report_dev, st) == hipSuccess ? RS_OK
+                                                                                                : RS_ERR_HIP;
 }
 
 rs_status rs_plan_set_timing(rs_plan P, int32_t enable) {

@@ -1160,8 +1160,8 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
     const LeafItem it = sv::load_leaf(g.leaves, blockIdx.x);
     if (sv::skip_inst(g, it.inst)) return;
     const sv::Prob p = sv::load_prob(g.probs, it.inst);
-    const sv::Prob c = sv::load_prob(g.corr, it.inst);
-    double rhs = 0.0, res = 0.0, obj = 0.0;
+    const sv::Prob c = sv::load_prob(g.corr ? g.corr : g.probs, it.inst);
+    double rhs = 0.0, res = 0.0, obj = 0.0, zn = 0.0;
     const int len = uni(it.len);
     double *xs = S.x, *ws = S.wv, *ls = S.lamN;
     for (int s = 0; s < len; ++s) {
@@ -1174,8 +1174,12 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
         for (int i = tid; i < n; i += NT) {
             xs[i] = x[i];
             ls[i] = lamn[i];
+            zn = fmax(zn, fmax(fabs(x[i]), fabs(lam[i])));
         }
-        for (int i = tid; i < m; i += NT) ws[i] = w[i];
+        for (int i = tid; i < m; i += NT) {
+            ws[i] = w[i];
+            zn = fmax(zn, fabs(w[i]));
+        }
         __syncthreads();
         // x row: Qx x + Qxw w - lam + A' lam+ ; lam+ row: A x + B w - x+ ;
         // w row: Qxw' x + Qw w + B' lam+.  A, B and Qxw are read once for
@@ -1199,8 +1203,10 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
             const double lxi = p.lx ? p.lx[t * p.slx + i] : 0.0, ai = p.a ? p.a[t * p.sa + i] : 0.0;
             const double dlx = lxi + S.pt[i] + S.d[i] - lam[i] + S.av[i];
             const double da = ai + S.y[i] + S.Psi[i] - xn[i];
-            const_cast<double *>(c.lx)[t * c.slx + i] = dlx;
-            const_cast<double *>(c.a)[t * c.sa + i] = da;
+            if (g.corr) {
+                const_cast<double *>(c.lx)[t * c.slx + i] = dlx;
+                const_cast<double *>(c.a)[t * c.sa + i] = da;
+            }
             rhs = fmax(rhs, fmax(fabs(lxi), fabs(ai)));
             res = fmax(res, fmax(fabs(dlx), fabs(da)));
             part += xs[i] * (0.5 * S.pt[i] + S.d[i] + lxi);
@@ -1208,7 +1214,7 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
         for (int j = tid; j < m; j += NT) {
             const double lwj = p.lw ? p.lw[t * p.slw + j] : 0.0;
             const double dlw = lwj + S.gw[j] + S.z[j] + S.kk[j];
-            const_cast<double *>(c.lw)[t * c.slw + j] = dlw;
+            if (g.corr) const_cast<double *>(c.lw)[t * c.slw + j] = dlw;
             rhs = fmax(rhs, fabs(lwj));
             res = fmax(res, fabs(dlw));
             part += ws[j] * (0.5 * S.z[j] + lwj);
@@ -1219,7 +1225,7 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
     if (it.t0 == 0) {            // lam_0 row
         for (int i = tid; i < n; i += NT) {
             const double d0 = p.x[i] - p.x0[i];
-            const_cast<double *>(c.x0)[i] = d0;
+            if (g.corr) const_cast<double *>(c.x0)[i] = d0;
             rhs = fmax(rhs, fabs(p.x0[i]));
             res = fmax(res, fabs(d0));
         }
@@ -1233,7 +1239,8 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
         gemv<true>(p.QxN, n, xs, n, n, [&](int i, double qx) {
             const double lNi = p.lN ? p.lN[i] : 0.0;
             const double dN = lNi + qx - lam[i];
-            const_cast<double *>(c.lN)[i] = dN;
+            if (g.corr) const_cast<double *>(c.lN)[i] = dN;
+            zn = fmax(zn, fmax(fabs(x[i]), fabs(lam[i])));
             rhs = fmax(rhs, fabs(lNi));
             res = fmax(res, fabs(dN));
             part += x[i] * (0.5 * qx + lNi);
@@ -1243,22 +1250,26 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
     }
     rhs = sv::wave_max(rhs);
     res = sv::wave_max(res);
+    zn = sv::wave_max(zn);
     __syncthreads();
     if (lane() == 0) {
         S.av[wave()] = rhs;
         S.pt[wave()] = res;
+        S.y[wave()] = zn;
     }
     __syncthreads();
     if (tid == 0) {
         double *out = g.part + (int64_t)(g.leaf_base + blockIdx.x) * PART_N;
-        double a = 0.0, b = 0.0;
+        double a = 0.0, b = 0.0, z = 0.0;
         for (int q = 0; q < NT / 64; ++q) {
             a = fmax(a, S.av[q]);
             b = fmax(b, S.pt[q]);
+            z = fmax(z, S.y[q]);
         }
         out[PART_RHS] = a;
         out[PART_RES] = b;
         out[PART_OBJ] = obj;
+        out[PART_ZN] = z;
     }
 }
 
@@ -1277,9 +1288,13 @@ __global__ void __launch_bounds__(NT) kw_update(GroupArgs g) {
         const int64_t b0 = (int64_t)it.t0 * n, cnt = (int64_t)nst * n;
         for (int64_t e = tid; e < cnt; e += NT) {
             const double dx = c.x[b0 + e], dl = c.lam[b0 + e];
-            const double xv = p.x[b0 + e] + dx, lv = p.lam[b0 + e] + dl;
-            p.x[b0 + e] = xv;
-            p.lam[b0 + e] = lv;
+            double xv = p.x[b0 + e], lv = p.lam[b0 + e];
+            if (!g.measure_only) {
+                xv += dx;
+                lv += dl;
+                p.x[b0 + e] = xv;
+                p.lam[b0 + e] = lv;
+            }
             mx[0] = fmax(mx[0], fabs(dx));
             mx[2] = fmax(mx[2], fabs(dl));
             mx[3] = fmax(mx[3], fabs(xv));
@@ -1290,8 +1305,11 @@ __global__ void __launch_bounds__(NT) kw_update(GroupArgs g) {
         const int64_t b0 = (int64_t)it.t0 * m, cnt = (int64_t)it.len * m;
         for (int64_t e = tid; e < cnt; e += NT) {
             const double dw = c.w[b0 + e];
-            const double wv = p.w[b0 + e] + dw;
-            p.w[b0 + e] = wv;
+            double wv = p.w[b0 + e];
+            if (!g.measure_only) {
+                wv += dw;
+                p.w[b0 + e] = wv;
+            }
             mx[1] = fmax(mx[1], fabs(dw));
             mx[4] = fmax(mx[4], fabs(wv));
         }

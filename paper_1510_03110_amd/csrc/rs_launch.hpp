@@ -22,6 +22,7 @@ enum KernelKind {
     KK_F_LEAF_UP = 4, KK_F_TREE = 5, KK_F_LEAF_DOWN = 6,    // rs_factor
     KK_S_LEAF_UP = 7, KK_S_TREE = 8, KK_S_LEAF_DOWN = 9,    // rs_solve
     KK_RESIDUAL = 10, KK_UPDATE = 11, KK_CHECK = 12,        // mixed-precision refinement
+    KK_REPORT = 13,                                         // K norm of the report
     KK_COUNT = 16
 };
 
@@ -44,7 +45,13 @@ Launcher leaf_forward(int nx, int nu);                   // leaf solve on the st
 // iterating into *active.
 hipError_t launch_refine_check(const InstInfo *tab, int count, const double *part, double *stats, int32_t *conv,
                                int32_t *info, const DevProb *probs, int mode, double tol, int32_t *active,
-                               int nactive, hipStream_t st);
+                               int nactive, int with_knorm, hipStream_t st);
+// KKT-matrix infinity norm of each leaf's rows (PART_KN of the leaf parts).
+hipError_t launch_knorm(const GroupArgs &g, hipStream_t st);
+// rs_info records (40 bytes each) from the statistics (or nullptr) and the
+// status words.
+hipError_t launch_report(int count, const double *stats, const int32_t *info, int refined, void *out,
+                         hipStream_t st);
 
 // Large-block family (any n_x, n_u up to 128): stored factorization with a
 // per-workgroup workspace of large_unit_bytes.

@@ -46,7 +46,7 @@ template <int NX, int NU>
 struct RSmem {
     double x[4][NX], w[4][NU], ln[4][NX];
     double cx[4][NX], cw[4][NU], ax[4][NX], qw[4][NX], bw[4][NX];
-    double red[4][3];
+    double red[4][4];
 };
 
 // R x C row-major matrix held by one wavefront, read with contiguous loads:
@@ -120,9 +120,9 @@ __global__ void __launch_bounds__(RT) kr_residual(GroupArgs g) {
     const LeafItem it = load_leaf(g.leaves, blockIdx.x);
     if (skip_inst(g, it.inst)) return;
     const Prob p = load_prob(g.probs, it.inst);
-    const Prob c = load_prob(g.corr, it.inst);
+    const Prob c = load_prob(g.corr ? g.corr : g.probs, it.inst);   // written only with g.corr
     const int wv = (int)(threadIdx.x >> 6), l = lane();
-    double rhs = 0.0, res = 0.0, obj = 0.0;
+    double rhs = 0.0, res = 0.0, obj = 0.0, zn = 0.0;
     double *xs = S.x[wv], *ws = S.w[wv], *ls = S.ln[wv];
     const int len = uni(it.len);
     using TX = Tile<NX, NX>;      // Q_x, A
@@ -142,6 +142,7 @@ __global__ void __launch_bounds__(RT) kr_residual(GroupArgs g) {
         mQw.load(p.Qw + (int64_t)t * p.sQw);
         const double xi = l < NX ? x[l] : 0.0, wi = l < NU ? w[l] : 0.0;
         const double lami = l < NX ? lam[l] : 0.0, xni = l < NX ? xn[l] : 0.0;
+        zn = fmax(zn, fmax(fabs(xi), fmax(fabs(wi), fabs(lami))));
         const double lxi = (l < NX && p.lx) ? p.lx[(int64_t)t * p.slx + l] : 0.0;
         const double lwi = (l < NU && p.lw) ? p.lw[(int64_t)t * p.slw + l] : 0.0;
         const double ai = (l < NX && p.a) ? p.a[(int64_t)t * p.sa + l] : 0.0;
@@ -170,15 +171,17 @@ __global__ void __launch_bounds__(RT) kr_residual(GroupArgs g) {
         if (l < NX) {
             const double dlx = lxi + S.cx[wv][l] + S.qw[wv][l] - lami;
             const double da = ai + S.ax[wv][l] + S.bw[wv][l] - xni;
-            const_cast<double *>(c.lx)[(int64_t)t * c.slx + l] = dlx;
-            const_cast<double *>(c.a)[(int64_t)t * c.sa + l] = da;
+            if (g.corr) {
+                const_cast<double *>(c.lx)[(int64_t)t * c.slx + l] = dlx;
+                const_cast<double *>(c.a)[(int64_t)t * c.sa + l] = da;
+            }
             rhs = fmax(rhs, fmax(fabs(lxi), fabs(ai)));
             res = fmax(res, fmax(fabs(dlx), fabs(da)));
             part += xi * lxi;
         }
         if (l < NU) {
             const double dlw = lwi + S.cw[wv][l];
-            const_cast<double *>(c.lw)[(int64_t)t * c.slw + l] = dlw;
+            if (g.corr) const_cast<double *>(c.lw)[(int64_t)t * c.slw + l] = dlw;
             rhs = fmax(rhs, fabs(lwi));
             res = fmax(res, fabs(dlw));
             part += wi * lwi;
@@ -189,7 +192,7 @@ __global__ void __launch_bounds__(RT) kr_residual(GroupArgs g) {
     if (wv == 0 && it.t0 == 0) {            // lam_0 row
         if (l < NX) {
             const double d0 = p.x[l] - p.x0[l];
-            const_cast<double *>(c.x0)[l] = d0;
+            if (g.corr) const_cast<double *>(c.x0)[l] = d0;
             rhs = fmax(rhs, fabs(p.x0[l]));
             res = fmax(res, fabs(d0));
         }
@@ -206,7 +209,8 @@ __global__ void __launch_bounds__(RT) kr_residual(GroupArgs g) {
         if (l < NX) {
             const double lNi = p.lN ? p.lN[l] : 0.0;
             const double dN = lNi + qx - lam[l];
-            const_cast<double *>(c.lN)[l] = dN;
+            if (g.corr) const_cast<double *>(c.lN)[l] = dN;
+            zn = fmax(zn, fmax(fabs(x[l]), fabs(lam[l])));
             rhs = fmax(rhs, fabs(lNi));
             res = fmax(res, fabs(dN));
             part = x[l] * (0.5 * qx + lNi);
@@ -215,23 +219,27 @@ __global__ void __launch_bounds__(RT) kr_residual(GroupArgs g) {
     }
     rhs = wave_max(rhs);
     res = wave_max(res);
+    zn = wave_max(zn);
     if (l == 0) {
         S.red[wv][0] = rhs;
         S.red[wv][1] = res;
         S.red[wv][2] = obj;
+        S.red[wv][3] = zn;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double* out = g.part + (int64_t)(g.leaf_base + blockIdx.x) * PART_N;
-        double a = 0.0, b = 0.0, o = 0.0;
+        double a = 0.0, b = 0.0, o = 0.0, z = 0.0;
         for (int q = 0; q < 4; ++q) {
             a = fmax(a, S.red[q][0]);
             b = fmax(b, S.red[q][1]);
             o += S.red[q][2];
+            z = fmax(z, S.red[q][3]);
         }
         out[PART_RHS] = a;
         out[PART_RES] = b;
         out[PART_OBJ] = o;
+        out[PART_ZN] = z;
     }
 }
 
@@ -250,9 +258,13 @@ __global__ void __launch_bounds__(RT) kr_update(GroupArgs g) {
         const int64_t b0 = (int64_t)it.t0 * NX, n = (int64_t)nst * NX;
         for (int64_t e = tid; e < n; e += RT) {
             const double dx = c.x[b0 + e], dl = c.lam[b0 + e];
-            const double xv = p.x[b0 + e] + dx, lv = p.lam[b0 + e] + dl;
-            p.x[b0 + e] = xv;
-            p.lam[b0 + e] = lv;
+            double xv = p.x[b0 + e], lv = p.lam[b0 + e];
+            if (!g.measure_only) {
+                xv += dx;
+                lv += dl;
+                p.x[b0 + e] = xv;
+                p.lam[b0 + e] = lv;
+            }
             m[0] = fmax(m[0], fabs(dx));
             m[2] = fmax(m[2], fabs(dl));
             m[3] = fmax(m[3], fabs(xv));
@@ -263,8 +275,11 @@ __global__ void __launch_bounds__(RT) kr_update(GroupArgs g) {
         const int64_t b0 = (int64_t)it.t0 * NU, n = (int64_t)it.len * NU;
         for (int64_t e = tid; e < n; e += RT) {
             const double dw = c.w[b0 + e];
-            const double wv2 = p.w[b0 + e] + dw;
-            p.w[b0 + e] = wv2;
+            double wv2 = p.w[b0 + e];
+            if (!g.measure_only) {
+                wv2 += dw;
+                p.w[b0 + e] = wv2;
+            }
             m[1] = fmax(m[1], fabs(dw));
             m[4] = fmax(m[4], fabs(wv2));
         }
@@ -286,9 +301,17 @@ __global__ void __launch_bounds__(RT) kr_update(GroupArgs g) {
 //         current iterate; converged once a correction has been applied,
 //         the residual is <= tol and the estimated forward error <= tol/10);
 // mode 2: after an update (correction size, forward-error estimate);
-// mode 3: final (RS_ERR_NOT_CONVERGED for instances that did not converge).
+// mode 3: final (RS_ERR_NOT_CONVERGED for instances that did not converge);
+// mode 4: report of a direct solve after a residual pass (relative residual
+//         and backward error of the returned solution; nothing else);
+// mode 5: report after a measuring update (estimated relative forward
+//         error = the size of the correction relative to the solution).
+// Modes 1 and 4 also form the normwise backward error
+// ||r - K z|| / (||K|| ||z|| + ||r||) when the leaves carry ||K|| (K-norm
+// pass, report plans), else store -1.
 __global__ void kr_check(const InstInfo *tab, int count, const double *part, double *stats, int32_t *conv,
-                         int32_t *info, const DevProb *probs, int mode, double tol, int32_t *active, int nactive) {
+                         int32_t *info, const DevProb *probs, int mode, double tol, int32_t *active, int nactive,
+                         int with_knorm) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (mode == 0 && i < nactive) active[i] = 0;
     if (i >= count) return;
@@ -298,6 +321,7 @@ __global__ void kr_check(const InstInfo *tab, int count, const double *part, dou
         for (int q = 0; q < ST_N; ++q) st[q] = 0.0;
         st[ST_EST] = 1.0;
         st[ST_DZ] = 1.0;      // the first solve is taken as 100% wrong
+        st[ST_BWD] = -1.0;
         return;
     }
     if (mode == 3) {
@@ -311,6 +335,19 @@ __global__ void kr_check(const InstInfo *tab, int count, const double *part, dou
     if (conv[i]) return;
     const InstInfo in = tab[i];
     const double *pp = part + (int64_t)in.first_leaf * PART_N;
+    if (mode == 5) {
+        double d[3] = {0, 0, 0}, z[3] = {0, 0, 0};
+        for (int lf = 0; lf < in.nleaves; ++lf)
+            for (int b = 0; b < 3; ++b) {
+                d[b] = fmax(d[b], pp[lf * PART_N + PART_DX + b]);
+                z[b] = fmax(z[b], pp[lf * PART_N + PART_X + b]);
+            }
+        double dz = 0.0;
+        for (int b = 0; b < 3; ++b) dz = fmax(dz, z[b] > 0.0 ? d[b] / z[b] : d[b]);
+        st[ST_EST] = dz;
+        st[ST_DZ] = dz;
+        return;
+    }
     if (mode == 2) {
         double d[3] = {0, 0, 0}, z[3] = {0, 0, 0};
         for (int lf = 0; lf < in.nleaves; ++lf)
@@ -329,14 +366,21 @@ __global__ void kr_check(const InstInfo *tab, int count, const double *part, dou
         st[ST_ITERS] += 1.0;
         return;
     }
-    double rhs = 0.0, res = 0.0, obj = 0.0;
+    double rhs = 0.0, res = 0.0, obj = 0.0, zn = 0.0, kn = 1.0;
     for (int lf = 0; lf < in.nleaves; ++lf) {
         rhs = fmax(rhs, pp[lf * PART_N + PART_RHS]);
         res = fmax(res, pp[lf * PART_N + PART_RES]);
         obj += pp[lf * PART_N + PART_OBJ];
+        zn = fmax(zn, pp[lf * PART_N + PART_ZN]);
+        kn = fmax(kn, pp[lf * PART_N + PART_KN]);    // the lam_0 row sums to 1
     }
     const double rres = rhs > 0.0 ? res / rhs : res;
     st[ST_RRES] = rres;
+    if (with_knorm) {
+        const double den = kn * zn + rhs;
+        st[ST_BWD] = den > 0.0 ? res / den : res;
+    }
+    if (mode == 4) return;
     if (probs[i].obj) probs[i].obj[0] = obj;
     if (st[ST_ITERS] >= 1.0 && rres <= tol && st[ST_EST] <= 0.1 * tol) conv[i] = 1;
     else if (active) atomicAdd(active, 1);      // the next correction pass has work
@@ -368,10 +412,110 @@ Launcher refine_kernel(int nx, int nu, int which) {
 
 hipError_t launch_refine_check(const InstInfo *tab, int count, const double *part, double *stats, int32_t *conv,
                                int32_t *info, const DevProb *probs, int mode, double tol, int32_t *active,
-                               int nactive, hipStream_t st) {
+                               int nactive, int with_knorm, hipStream_t st) {
     const int n = count > nactive ? count : nactive;
     hipLaunchKernelGGL(sv::kr_check, dim3((n + 63) / 64), dim3(64), 0, st, tab, count, part, stats, conv, info,
-                       probs, mode, tol, active, nactive);
+                       probs, mode, tol, active, nactive, with_knorm);
+    return hipGetLastError();
+}
+
+namespace sv {
+
+// Largest absolute row sum, over the rows that belong to one leaf, of the
+// KKT matrix of P(N) (the rows listed at the top of this file): for stage t
+// the x_t rows |Qx| + |Qxw| + 1 + |A'|, the w_t rows |Qxw'| + |Qw| + |B'|,
+// the lam_{t+1} rows |A| + |B| + 1; the last leaf adds the x_N rows
+// |QxN| + 1.  One workgroup per leaf, one stage at a time: threads i < nx
+// form the x and lam+ row sums of row i, threads 128 + j (j < nu) the w row
+// sum of row j, each reading its rows and columns in a fixed order
+// (deterministic).  Writes PART_KN of the leaf.
+__global__ void __launch_bounds__(RT) kn_norm(GroupArgs g) {
+    __shared__ double red[RT / 64];
+    const LeafItem it = load_leaf(g.leaves, blockIdx.x);
+    if (skip_inst(g, it.inst)) return;
+    const Prob p = load_prob(g.probs, it.inst);
+    const int n = g.nx, m = g.nu, tid = threadIdx.x;
+    const int len = uni(it.len);
+    double mx = 0.0;
+    for (int s = 0; s < len; ++s) {
+        const int64_t t = it.t0 + s;
+        const double *Qx = p.Qx + t * p.sQx, *Qw = p.Qw + t * p.sQw;
+        const double *Qxw = p.Qxw ? p.Qxw + t * p.sQxw : nullptr;
+        const double *A = p.A + t * p.sA, *B = p.B + t * p.sB;
+        if (tid < n) {
+            const int i = tid;
+            double rx = 1.0, rl = 1.0;
+            for (int j = 0; j < n; ++j) {
+                rx += fabs(Qx[(int64_t)i * n + j]) + fabs(A[(int64_t)j * n + i]);
+                rl += fabs(A[(int64_t)i * n + j]);
+            }
+            for (int j = 0; j < m; ++j) {
+                rl += fabs(B[(int64_t)i * m + j]);
+                if (Qxw) rx += fabs(Qxw[(int64_t)i * m + j]);
+            }
+            mx = fmax(mx, fmax(rx, rl));
+        } else if (tid >= 128 && tid < 128 + m) {
+            const int j = tid - 128;
+            double rw = 0.0;
+            for (int k = 0; k < n; ++k) {
+                rw += fabs(B[(int64_t)k * m + j]);
+                if (Qxw) rw += fabs(Qxw[(int64_t)k * m + j]);
+            }
+            for (int k = 0; k < m; ++k) rw += fabs(Qw[(int64_t)j * m + k]);
+            mx = fmax(mx, rw);
+        }
+    }
+    if ((it.flags & LEAF_LAST) && tid < n) {
+        double rN = 1.0;
+        for (int j = 0; j < n; ++j) rN += fabs(p.QxN[(int64_t)tid * n + j]);
+        mx = fmax(mx, rN);
+    }
+    mx = wave_max(mx);
+    if (lane() == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (tid == 0) {
+        double v = 0.0;
+        for (int q = 0; q < RT / 64; ++q) v = fmax(v, red[q]);
+        g.part[(int64_t)(g.leaf_base + blockIdx.x) * PART_N + PART_KN] = v;
+    }
+}
+
+// Per-instance report (rs_info layout: rel_resid, bwd_err, est_fwd_err as
+// doubles, then refine_iters, bad_stage, status, reserved as int32) from the
+// statistics and the status words.  Without statistics only the status
+// words are reported and the measures are -1.
+__global__ void kr_report(int count, const double *stats, const int32_t *info, int refined, char *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double *d = reinterpret_cast<double *>(out + (int64_t)i * 40);
+    int32_t *w = reinterpret_cast<int32_t *>(out + (int64_t)i * 40 + 24);
+    if (stats) {
+        const double *st = stats + (int64_t)i * ST_N;
+        d[0] = st[ST_RRES];
+        d[1] = st[ST_BWD];
+        d[2] = st[ST_EST];
+        w[0] = refined ? (int32_t)st[ST_ITERS] : 0;
+    } else {
+        d[0] = d[1] = d[2] = -1.0;
+        w[0] = 0;
+    }
+    w[1] = info[2 * i + 1];
+    w[2] = info[2 * i];
+    w[3] = 0;
+}
+
+}  // namespace sv
+
+hipError_t launch_knorm(const GroupArgs &g, hipStream_t st) {
+    if (g.nleaves < 1 || g.nx > 128 || g.nu > 128) return hipSuccess;
+    hipLaunchKernelGGL(sv::kn_norm, dim3(g.nleaves), dim3(sv::RT), 0, st, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_report(int count, const double *stats, const int32_t *info, int refined, void *out,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(sv::kr_report, dim3((count + 63) / 64), dim3(64), 0, st, count, stats, info, refined,
+                       static_cast<char *>(out));
     return hipGetLastError();
 }
 

@@ -126,13 +126,19 @@ struct InstInfo {
 };
 
 // Per-leaf partial results of the refinement kernels (doubles):
-//   residual: max |r| (right-hand side), max |r - K z|, objective part
+//   residual: max |r| (right-hand side), max |r - K z|, objective part,
+//             max |z| over the leaf's entries of x, w, lam
 //   update:   max |dx|, |dw|, |dlam|, max |x|, |w|, |lam| after the update
-enum { PART_RHS = 0, PART_RES = 1, PART_OBJ = 2, PART_DX = 3, PART_X = 6, PART_N = 9 };
+//   K norm:   largest absolute row sum of the leaf's rows of the KKT matrix
+enum { PART_RHS = 0, PART_RES = 1, PART_OBJ = 2, PART_DX = 3, PART_X = 6, PART_ZN = 9, PART_KN = 10, PART_N = 11 };
 // Per-instance refinement statistics (doubles): relative residual of the
 // returned solution, estimated relative forward error, corrections applied,
-// converged flag, size of the last correction relative to the solution.
-enum { ST_RRES = 0, ST_EST = 1, ST_ITERS = 2, ST_CONV = 3, ST_DZ = 4, ST_N = 5 };
+// converged flag, size of the last correction relative to the solution,
+// normwise backward error ||r - K z|| / (||K|| ||z|| + ||r||) (infinity
+// norms; -1 when ||K|| was not formed).
+enum { ST_RRES = 0, ST_EST = 1, ST_ITERS = 2, ST_CONV = 3, ST_DZ = 4, ST_BWD = 5, ST_N = 6 };
+// The first ST_PUBLIC statistics are what rs_refine_stats exports.
+constexpr int ST_PUBLIC = 5;
 
 // Everything a kernel launch of one shape group needs.
 struct GroupArgs {
@@ -168,6 +174,9 @@ struct GroupArgs {
     // rank-revealing master stages: an n_x x n_x identity (the master input
     // weight), nullptr for the plain form B = Q_w = Q_w_hat
     const double *ident;
+    // refinement update: 1 = only measure the correction and the solution
+    // (no z += d), for an error estimate of the returned solution
+    int32_t measure_only;
 };
 
 }  // namespace rs

@@ -20,6 +20,7 @@ RS_OK, RS_ERR_ARG, RS_ERR_NOT_SPD, RS_ERR_SINGULAR_MASTER, RS_ERR_NOT_CONVERGED,
 RS_FP64, RS_MIXED_FP32, RS_MIXED_BF16 = 0, 1, 2
 RS_PLAN_FACTORED = 1
 RS_PLAN_RANK_REVEAL = 2
+RS_PLAN_REPORT = 4
 RS_PROB_SKIP = 1
 RS_KERNEL_KINDS = 16
 
@@ -55,6 +56,12 @@ class rs_ip(ctypes.Structure):
 class rs_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("Ns", ctypes.c_int32), ("branch", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("tol", ctypes.c_double), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class rs_info(ctypes.Structure):
+    _fields_ = [("rel_resid", ctypes.c_double), ("bwd_err", ctypes.c_double), ("est_fwd_err", ctypes.c_double),
+                ("refine_iters", ctypes.c_int32), ("bad_stage", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
@@ -107,6 +114,8 @@ def library():
         lib.rs_plan_kernel_times.restype = i32
         lib.rs_refine_stats.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_double), _P]
         lib.rs_refine_stats.restype = i32
+        lib.rs_info_report.argtypes = [_P, _P, _P, _P, _P]
+        lib.rs_info_report.restype = i32
         lib.rs_status_string.argtypes = [i32]
         lib.rs_status_string.restype = ctypes.c_char_p
         for name in ("rs_plan_create", "rs_plan_create_ex", "rs_plan_create_split", "rs_plan_create_ring",
@@ -247,6 +256,16 @@ def rs_refine_stats(plan, work_ptr, count, stream_ptr=None):
     return out.reshape(count, 5)
 
 
+def rs_info_report(plan, work_ptr, info_ptr, report_ptr, stream_ptr=None):
+    """Queue the per-instance rs_info records of the last solve into the
+    device buffer at report_ptr (40 bytes per instance)."""
+    _check(library().rs_info_report(plan, work_ptr, info_ptr, report_ptr, stream_ptr), "rs_info_report")
+
+
+RS_INFO_DTYPE = np.dtype([("rel_resid", "<f8"), ("bwd_err", "<f8"), ("est_fwd_err", "<f8"),
+                          ("refine_iters", "<i4"), ("bad_stage", "<i4"), ("status", "<i4"), ("reserved", "<i4")])
+
+
 def _call(name, plan, probs, work_ptr, work_bytes, stream_ptr, info_ptr):
     st = getattr(library(), name)(plan, probs, work_ptr, work_bytes, stream_ptr, info_ptr)
     _check(st, name)
@@ -299,11 +318,12 @@ class Batch:
     that leaves with Ns * nu < nx, or whose inputs leave state directions
     unreached, are allowed.  ``split=(leaf_lens, branches)`` gives every
     instance its own leaf lengths and per-level master group sizes
-    (rs_plan_create_split).
+    (rs_plan_create_split).  ``report=True`` sets RS_PLAN_REPORT (per-instance
+    residual, backward error and forward-error estimate, read by ``report()``).
     """
 
     def __init__(self, data, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.0,
-                 device="cuda", factored=False, per_instance=None, rank_reveal=False, split=None):
+                 device="cuda", factored=False, per_instance=None, rank_reveal=False, split=None, report=False):
         import torch
         self.torch = torch
         keys = set(data)
@@ -329,7 +349,8 @@ class Batch:
         self.obj = torch.zeros(self.count, **f64)
         self.info = torch.zeros(2 * self.count, dtype=torch.int32, device=device)
         pdims = dims if per_instance is None else [d + tuple(pi) for d, pi in zip(dims, per_instance)]
-        flags = (RS_PLAN_FACTORED if factored else 0) | (RS_PLAN_RANK_REVEAL if rank_reveal else 0)
+        flags = (RS_PLAN_FACTORED if factored else 0) | (RS_PLAN_RANK_REVEAL if rank_reveal else 0) | \
+            (RS_PLAN_REPORT if report else 0)
         if split is not None:
             self.plan = rs_plan_create_split(dims, split[0], split[1], precision, max_refine, tol, flags)
         else:
@@ -398,6 +419,14 @@ class Batch:
 
     def refine_stats(self):
         return rs_refine_stats(self.plan, self.work_ptr, self.count, self.stream_ptr())
+
+    def report(self):
+        """Per-instance rs_info records of the last solve (numpy structured
+        array with the fields of rs_info; synchronizes)."""
+        torch = self.torch
+        buf = torch.zeros(40 * self.count, dtype=torch.uint8, device=self.info.device)
+        rs_info_report(self.plan, self.work_ptr, self.info.data_ptr(), buf.data_ptr(), self.stream_ptr())
+        return np.frombuffer(buf.cpu().numpy().tobytes(), dtype=RS_INFO_DTYPE)
 
     def update(self, key, i, values):
         """Overwrite problem field ``key`` of instance ``i`` in place (same
