@@ -196,7 +196,7 @@ class ServingEngine:
     """Continuous-batching solver for receding-horizon sessions."""
 
     def __init__(self, precision=rs.RS_FP64, lanes=2, max_batch=1 << 30, hbm_fraction=0.9, tuner=None,
-                 device="cuda", record=False, timing=False):
+                 device="cuda", record=False, timing=False, record_every=0):
         import torch
         self.torch = torch
         self.device = device
@@ -214,6 +214,8 @@ class ServingEngine:
         self.failed = 0               # requests whose solve reported a numerical failure
         self.rejected = 0
         self.record = record
+        self.record_every = record_every   # > 0: record every k-th served request (a parity sample)
+        self.served = 0
         self.results = {}
         self.launches = 0
         self.batch_sizes = []
@@ -347,7 +349,8 @@ class ServingEngine:
                 s.solved = False
                 s.current = (0, 0)
                 self.failed += 1
-            if self.record:
+            self.served += 1
+            if self.record or (self.record_every > 0 and self.served % self.record_every == 0):
                 self.results.setdefault(s.sid, []).append(
                     dict(x=s.x.cpu().numpy(), w=s.w.cpu().numpy(), lam=s.lam.cpu().numpy(),
                          obj=float(s.obj.cpu()[0]), status=status, stage=int(st[i, 1]),

@@ -205,6 +205,42 @@ def test_large_block_config_full_horizon(prec):
     assert kkt.rel_residual(prob, sol["x"], sol["w"], sol["lam"]) <= TOL
 
 
+@pytest.fixture(scope="module")
+def c5_single():
+    """The large-block configuration's single instance (n_x = 128, n_u = 64,
+    N = 16384; time-varying A_t, time-invariant B, Q, R given once, drawn on
+    the device) and its serial FP64 oracle solution, computed once per
+    session (about a minute on one host thread)."""
+    torch, rs = _rs()
+    data = W.c5_torch(128, 64, 16384, 1, seed=W.seed_for(5), device="cuda")
+    prob = W.materialize(W.instance_to_numpy(data, 0))
+    ref = riccati.solve(prob)
+    return data, prob, ref
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_large_block_config_full_horizon_matches_oracle(c5_single, prec):
+    """Full-size large-block configuration against the serial oracle, element
+    by element: relative error <= 1e-10 on each of x, w, lam in FP64, in mixed
+    precision and with BF16 products (after FP64 refinement)."""
+    torch, rs = _rs()
+    data, prob, ref = c5_single
+    bt = rs.Batch(data, precision=prec, Ns=64, branch=8)
+    bt.solve()
+    torch.cuda.synchronize()
+    assert bt.status()[0, 0] == 0
+    sol = bt.result(0)
+    if prec >= 1:
+        st = bt.refine_stats()[0]
+        assert st[3] == 1.0 and st[0] <= TOL
+    bt.close()
+    err = kkt.rel_error(sol, ref)
+    print("c5 full horizon, precision %d: rel err vs oracle %.3e" % (prec, err))
+    assert err <= TOL
+    assert abs(sol["obj"] - ref["obj"]) <= 1e-9 * max(1.0, abs(ref["obj"]))
+
+
 def test_large_block_config_batch64_sampled():
     """Batch of 64 instances of n_x = 128, n_u = 64 (the configuration's
     batch; horizon 256 so that the oracle finishes in seconds), mixed
