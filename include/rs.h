@@ -114,8 +114,21 @@ typedef struct rs_options {
     int32_t max_refine;  /* mixed precision: maximum refinement steps; 0 = default 5  */
     double tol;          /* mixed precision: relative KKT residual target; 0 = 1e-10  */
     int32_t flags;       /* RS_PLAN_* bits                                            */
-    int32_t reserved;
+    int32_t leaf_chunk;  /* > 0: FP64 plans of large-block shapes process their leaves
+                            in chunks of this many and keep the factorization of one
+                            chunk only (see below); 0 = the whole factorization     */
 } rs_options;
+
+/* rs_options.leaf_chunk (Alg. 6 at k = 0 solves every leaf subproblem again
+ * with its parent's message, so a leaf's factorization need not outlive its
+ * reduction): the workspace holds the stored factorization of at most
+ * leaf_chunk consecutive leaves (in plan order) instead of all of them; every
+ * chunk is factored on the way up (reduction, Alg. 4) and factored again on
+ * the way down (solve), twice the leaf matrix work for a factor store that no
+ * longer grows with the batch.  rs_batch_solve only (rs_factor / rs_solve:
+ * RS_ERR_ARG); FP64 plans whose every shape runs on the large-block kernels
+ * (else RS_ERR_UNSUPPORTED at plan creation); with RS_PLAN_REPORT the
+ * residual and backward error are reported, est_fwd_err is -1. */
 
 /* rs_options.flags: reserve workspace for the stored factorization so that
  * rs_factor / rs_solve can be used (about (4 nx^2 + 4 nu^2 + 2 nu nx) doubles

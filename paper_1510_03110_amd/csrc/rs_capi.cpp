@@ -60,6 +60,7 @@ struct rs_plan_s {
     bool rank_reveal = false;       // rank-revealing master stages (RS_PLAN_RANK_REVEAL)
     bool report = false;            // per-instance report: K norm, FP64 residual, error estimate
     bool refine_ws = false;         // workspace holds the refinement tables (mixed or report)
+    int32_t leaf_chunk = 0;         // > 0: leaves processed in chunks of this many (bounded factor store)
     rs_options opt{};               // options the plan was made with
     bool tables_dirty = false;      // host tables changed since the last upload
     hipEvent_t tables_ev = nullptr; // completion of the last table upload
@@ -360,7 +361,8 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
     rs_plan_s *P = new (std::nothrow) rs_plan_s();
     if (!P) return RS_ERR_NOMEM;
     if (opt) {
-        if (opt->Ns < 0 || opt->branch < 0 || opt->branch == 1 || opt->max_refine < 0 || opt->tol < 0) {
+        if (opt->Ns < 0 || opt->branch < 0 || opt->branch == 1 || opt->max_refine < 0 || opt->tol < 0 ||
+            opt->leaf_chunk < 0) {
             delete P;
             return RS_ERR_ARG;
         }
@@ -374,6 +376,7 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         P->factored = P->mixed || (opt->flags & RS_PLAN_FACTORED) != 0;
         P->rank_reveal = (opt->flags & RS_PLAN_RANK_REVEAL) != 0;
         P->report = (opt->flags & RS_PLAN_REPORT) != 0;
+        P->leaf_chunk = opt->leaf_chunk;
         if (opt->Ns > 0) P->Ns = opt->Ns;
         if (opt->branch > 0) P->branch = opt->branch;
         P->max_refine = opt->max_refine > 0 ? opt->max_refine : (P->bf16 ? 20 : 5);
@@ -533,6 +536,16 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         for (auto &lf : g.leaves) g.ntop += (lf.flags & LEAF_TOP) ? 1 : 0;
         finalize_items(g, tmp);
     }
+    // leaf-chunked solves: FP64 large-block plans only (their solve is the
+    // stored factorization followed by the solve on it, both per leaf)
+    if (P->leaf_chunk > 0) {
+        bool ok = !P->mixed && !P->receding && P->pad_inst.empty();
+        for (auto &g : P->groups) ok = ok && g.shape->large && g.shape->lb;
+        if (!ok) {
+            delete P;
+            return RS_ERR_UNSUPPORTED;
+        }
+    }
     // workspace layout
     size_t off = 0;
     P->off_probs = off;                 // user problems, then (mixed) the correction problems,
@@ -593,10 +606,21 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         if (P->receding) continue;
         g.off_fstore = off;
         if (P->factored) {
+            // a leaf-chunked plan stores the records of one chunk of leaves
+            int64_t stages = g.leaf_stages;
+            if (P->leaf_chunk > 0) {
+                stages = 0;
+                for (size_t lo = 0; lo < g.leaves.size(); lo += (size_t)P->leaf_chunk) {
+                    const size_t hi = std::min(g.leaves.size(), lo + (size_t)P->leaf_chunk);
+                    int64_t cs = 0;
+                    for (size_t k = lo; k < hi; ++k) cs += g.leaves[k].len;
+                    stages = std::max(stages, cs);
+                }
+            }
             const size_t rec = P->mixed ? sizeof(float) : sizeof(double);
-            off = align_up(off + rec * (size_t)g.leaf_stages * LeafRec{g.nx, g.nu}.per_stage());
+            off = align_up(off + rec * (size_t)stages * LeafRec{g.nx, g.nu}.per_stage());
             g.off_fvec = off;
-            off = align_up(off + sizeof(double) * (size_t)g.leaf_stages * LeafRec{g.nx, g.nu}.vec());
+            off = align_up(off + sizeof(double) * (size_t)stages * LeafRec{g.nx, g.nu}.vec());
         }
     }
     if (P->refine_ws) {
@@ -1028,6 +1052,7 @@ static rs_status report_fp64(rs_plan P, char *W, int32_t *info, hipStream_t st, 
     rs_status s = launch_check(P, W, info, st, 0);
     if (s == RS_OK) s = launch_refine(P, W, info, st, 0, true);
     if (s == RS_OK) s = launch_check(P, W, info, st, 4);
+    if (pass < 0) return s;      // leaf-chunked plans: no correction solve (est_fwd_err stays -1)
     if (s == RS_OK) s = launch_pass(P, W, info, st, pass, true, true, true);
     if (s == RS_OK) {
         for (size_t gi = 0; gi < P->groups.size() && s == RS_OK; ++gi) {
@@ -1066,6 +1091,81 @@ static rs_status mixed_solve(rs_plan P, char *W, int32_t *info, hipStream_t st) 
 
 static rs_status run_sequence(rs_plan P, char *W, int32_t *info, hipStream_t st, int mode);
 
+// FP64 large-block solve with the leaves in chunks of P->leaf_chunk, whose
+// stored factorization holds one chunk's records at a time.  Up: per chunk
+// the matrix lines (records, M1 matrix part) and at once the vector lines
+// on them (M1 vector part); then the master levels (matrix, then vector).
+// Down: per chunk the leaf factorization again (Alg. 6 solves every leaf
+// subproblem again with its parent's message; the records come out the
+// same, the M1 fields they rewrite too), its vector lines and the forward
+// sweep with the parent's message.  Twice the leaf matrix work of the
+// stored path for a factor store bounded by one chunk.
+static rs_status chunked_solve(rs_plan P, char *W, int32_t *info, hipStream_t st) {
+    int32_t *queues = reinterpret_cast<int32_t *>(W + P->off_queues);
+    auto chunk_args = [&](size_t gi, size_t lo, size_t hi) {
+        Group &g = P->groups[gi];
+        GroupArgs a = group_args(P, W, gi, info, false, false);
+        a.leaves += lo;
+        a.nleaves = (int32_t)(hi - lo);
+        a.leaf_base += (int32_t)lo;
+        a.rec_stage0 = g.leaves[lo].scratch / g.shape->scratch_per_stage;
+        return a;
+    };
+    auto for_chunks = [&](size_t gi, auto body) -> rs_status {
+        Group &g = P->groups[gi];
+        for (size_t lo = 0; lo < g.leaves.size(); lo += (size_t)P->leaf_chunk) {
+            const size_t hi = std::min(g.leaves.size(), lo + (size_t)P->leaf_chunk);
+            rs_status s = body(chunk_args(gi, lo, hi));
+            if (s != RS_OK) return s;
+        }
+        return RS_OK;
+    };
+    auto run = [&](int kind, Launcher L, const GroupArgs &a, int grid) -> rs_status {
+        return timed(P, kind, st, [&] { return L(a, grid, st); }) == hipSuccess ? RS_OK : RS_ERR_HIP;
+    };
+    ++P->epoch;
+    if (timed(P, KK_INIT, st, [&] { return launch_init(info, P->count, queues, (int)P->groups.size(), st); }) !=
+        hipSuccess)
+        return RS_ERR_HIP;
+    for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+        Group &g = P->groups[gi];
+        const Launcher *F = g.shape->factor[0], *V = g.shape->vsolve[0];
+        rs_status s = for_chunks(gi, [&](const GroupArgs &a) {
+            rs_status r = run(KK_F_LEAF_UP, F[0], a, a.nleaves);
+            return r == RS_OK ? run(KK_S_LEAF_UP, V[0], a, a.nleaves) : r;
+        });
+        if (s != RS_OK) return s;
+        if (!g.items.empty()) {
+            GroupArgs a = group_args(P, W, gi, info, false, false);
+            s = run(KK_F_TREE, F[1], a, std::max(1, std::min<int>((int)g.items.size(), 256)));
+            if (s != RS_OK) return s;
+        }
+    }
+    ++P->epoch;
+    if (timed(P, KK_INIT, st, [&] { return launch_init(info, 0, queues, (int)P->groups.size(), st); }) !=
+        hipSuccess)
+        return RS_ERR_HIP;
+    for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+        Group &g = P->groups[gi];
+        if (g.items.empty()) continue;
+        GroupArgs a = group_args(P, W, gi, info, false, false);
+        rs_status s = run(KK_S_TREE, g.shape->vsolve[0][1], a, std::max(1, std::min<int>((int)g.items.size(), 1024)));
+        if (s != RS_OK) return s;
+    }
+    for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+        Group &g = P->groups[gi];
+        const Launcher *F = g.shape->factor[0], *V = g.shape->vsolve[0];
+        rs_status s = for_chunks(gi, [&](const GroupArgs &a) {
+            rs_status r = run(KK_F_LEAF_UP, F[0], a, a.nleaves);
+            if (r == RS_OK) r = run(KK_F_LEAF_DOWN, F[2], a, a.nleaves);
+            if (r == RS_OK) r = run(KK_S_LEAF_UP, V[0], a, a.nleaves);
+            return r == RS_OK ? run(KK_S_LEAF_DOWN, V[2], a, a.nleaves) : r;
+        });
+        if (s != RS_OK) return s;
+    }
+    return RS_OK;
+}
+
 // The call's kernels, between the padded copies of the inputs of padded
 // instances and the copy of their w back to the caller.
 static rs_status run_padded(rs_plan P, char *W, int32_t *info, hipStream_t st, int mode) {
@@ -1080,6 +1180,12 @@ static rs_status run_padded(rs_plan P, char *W, int32_t *info, hipStream_t st, i
 // Kernel sequence of a call once the descriptors are bound.
 // mode 0 = rs_batch_solve, 1 = rs_factor, 2 = rs_solve.
 static rs_status run_sequence(rs_plan P, char *W, int32_t *info, hipStream_t st, int mode) {
+    if (P->leaf_chunk > 0) {
+        rs_status s = chunked_solve(P, W, info, st);
+        if (s != RS_OK || !P->report) return s;
+        s = launch_knorm_all(P, W, info, st);
+        return s == RS_OK ? report_fp64(P, W, info, st, -1) : s;
+    }
     if (!P->mixed) {
         rs_status s;
         int solve_pass;
@@ -1108,7 +1214,7 @@ static rs_status run_call(rs_plan P, const rs_problem *probs, void *work, size_t
                           int32_t *info_dev, int mode) {
     rs_status s = check_call(P, probs, work, work_bytes);
     if (s != RS_OK) return s;
-    if (mode != 0 && !P->factored) return RS_ERR_ARG;
+    if (mode != 0 && (!P->factored || P->leaf_chunk > 0)) return RS_ERR_ARG;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     char *W = static_cast<char *>(work);
     s = bind_and_upload(P, probs, W, st);
@@ -1129,7 +1235,7 @@ rs_status rs_graph_create(rs_plan P, int32_t mode, const rs_problem *probs, void
     *out = nullptr;
     rs_status s = check_call(P, probs, work, work_bytes);
     if (s != RS_OK) return s;
-    if (mode != 0 && !P->factored) return RS_ERR_ARG;
+    if (mode != 0 && (!P->factored || P->leaf_chunk > 0)) return RS_ERR_ARG;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     char *W = static_cast<char *>(work);
     s = bind_and_upload(P, probs, W, st);

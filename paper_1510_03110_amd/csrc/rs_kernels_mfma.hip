@@ -696,7 +696,7 @@ __global__ void __launch_bounds__(NT, 2) kf_leaf_up(GroupArgs g) {
     const DevProb p = load_prob(g.probs, it.inst);
     const SlotLayout SL{NX};
     double *out = g.slots + (int64_t)it.slot * SL.size();
-    T *base = reinterpret_cast<T *>(g.fstore) + (it.scratch / g.sps) * (int64_t)LeafRec{NX, NU}.per_stage();
+    T *base = reinterpret_cast<T *>(g.fstore) + g.rec_stage(it.scratch) * (int64_t)LeafRec{NX, NU}.per_stage();
     auto get = [&](int s) { return prob_stage(p, it.t0 + s); };
     const int tid = threadIdx.x;
     if (it.flags & LEAF_REUSE) {
@@ -752,7 +752,7 @@ __global__ void __launch_bounds__(NT, 3) kf_leaf_down(GroupArgs g) {
     const SlotLayout SL{NX};
     const bool known_end = (it.flags & (LEAF_LAST | LEAF_TOP)) != 0;
     const double *msg = (it.flags & LEAF_TOP) ? nullptr : g.slots + (int64_t)it.slot * SL.size();
-    T *base = reinterpret_cast<T *>(g.fstore) + (it.scratch / g.sps) * (int64_t)LeafRec{NX, NU}.per_stage();
+    T *base = reinterpret_cast<T *>(g.fstore) + g.rec_stage(it.scratch) * (int64_t)LeafRec{NX, NU}.per_stage();
     for (int e = threadIdx.x; e < NX * NX; e += NT) S.P[e] = (T)(known_end ? p.QxN[e] : msg[SL.P() + e]);
     __syncthreads();
     auto get = [&](int s) { return prob_stage(p, it.t0 + s); };

@@ -515,7 +515,7 @@ __global__ void __launch_bounds__(LB_MT) kl_leaf_up(GroupArgs g) {
             continue;
         }
         double *cache = (g.m1cache && it.m1 >= 0) ? g.m1cache + (int64_t)it.m1 * 3 * n * n : nullptr;
-        T *base = reinterpret_cast<T *>(g.fstore) + (it.scratch / g.sps) * (int64_t)LeafRec{n, m}.per_stage();
+        T *base = reinterpret_cast<T *>(g.fstore) + g.rec_stage(it.scratch) * (int64_t)LeafRec{n, m}.per_stage();
         auto get = [&](int s) { return leaf_stage(p, it.t0 + s); };
         const LeafOut<T> o{base, n, m, true};
         if (!(it.flags & LEAF_LAST)) {
@@ -557,7 +557,7 @@ __global__ void __launch_bounds__(LB_MT) kl_leaf_down(GroupArgs g) {
         // terminal; the others are solved from their up records
         if (!(it.flags & LEAF_TOP) || inst_skipped(g.probs, it.inst)) continue;
         const DevProb p = load_prob(g.probs, it.inst);
-        T *base = reinterpret_cast<T *>(g.fstore) + (it.scratch / g.sps) * (int64_t)LeafRec{n, m}.per_stage();
+        T *base = reinterpret_cast<T *>(g.fstore) + g.rec_stage(it.scratch) * (int64_t)LeafRec{n, m}.per_stage();
         for (int e = tid; e < n * n; e += nthr()) S.P[e] = (T)p.QxN[e];
         __syncthreads();
         auto get = [&](int s) { return leaf_stage(p, it.t0 + s); };
@@ -914,7 +914,7 @@ __global__ void __launch_bounds__(NT) kw_leaf_up(GroupArgs g) {
     const sv::Prob p = sv::load_prob(g.probs, it.inst);
     const LeafRec R{n, m};
     const SlotLayout SL{n};
-    const TR *rec = reinterpret_cast<const TR *>(g.fstore) + (it.scratch / g.sps) * (int64_t)R.per_stage();
+    const TR *rec = reinterpret_cast<const TR *>(g.fstore) + g.rec_stage(it.scratch) * (int64_t)R.per_stage();
     double *out = g.slots + (int64_t)it.slot * SL.size();
     const bool last = (it.flags & LEAF_LAST) != 0;
     for (int i = tid; i < n; i += NT) {
@@ -922,7 +922,7 @@ __global__ void __launch_bounds__(NT) kw_leaf_up(GroupArgs g) {
         S.v[i] = 0.0;
     }
     double cbar = (last && p.cN) ? p.cN[0] : 0.0;
-    double *vec0 = g.fvec + (it.scratch / g.sps) * (int64_t)R.vec();
+    double *vec0 = g.fvec + g.rec_stage(it.scratch) * (int64_t)R.vec();
     __syncthreads();
     for (int s = uni(it.len) - 1; s >= 0; --s) {
         VSrcL<TR> q = prob_src<TR>(p, it.t0 + s);
@@ -963,7 +963,7 @@ __device__ void leaf_forward(VS &S, const GroupArgs &g, const sv::Prob &p, const
     const int n = g.nx, m = g.nu, tid = threadIdx.x;
     const LeafRec R{n, m};
     const SlotLayout SL{n};
-    const int64_t stage0 = it.scratch / g.sps;
+    const int64_t stage0 = g.rec_stage(it.scratch);
     const TR *rec = reinterpret_cast<const TR *>(g.fstore) + stage0 * (int64_t)R.per_stage();
     const double *vec0 = g.fvec + stage0 * (int64_t)R.vec();
     const double *msg = g.slots + (int64_t)it.slot * SL.size();
@@ -1010,7 +1010,7 @@ __global__ void __launch_bounds__(NT) kw_leaf_down(GroupArgs g) {
     // whole-problem leaf: vector part of Alg. 1-2 with the true terminal on
     // the down records, then Alg. 3
     const LeafRec R{n, m};
-    const int64_t stage0 = it.scratch / g.sps;
+    const int64_t stage0 = g.rec_stage(it.scratch);
     const TR *rec = reinterpret_cast<const TR *>(g.fstore) + stage0 * (int64_t)R.per_stage();
     double *vec0 = g.fvec + stage0 * (int64_t)R.vec();
     for (int i = tid; i < n; i += NT) {

@@ -328,7 +328,7 @@ __global__ void __launch_bounds__(WT) kv_leaf_up(GroupArgs g) {
     const Prob p = load_prob(g.probs, it.inst);
     const LeafRec R{NX, NU};
     const SlotLayout SL{NX};
-    const TR *rec = reinterpret_cast<const TR *>(g.fstore) + (it.scratch / g.sps) * (int64_t)R.per_stage();
+    const TR *rec = reinterpret_cast<const TR *>(g.fstore) + g.rec_stage(it.scratch) * (int64_t)R.per_stage();
     double *out = g.slots + (int64_t)it.slot * SL.size();
     const int l = lane();
     const bool last = (it.flags & LEAF_LAST) != 0;
@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(WT) kv_leaf_up(GroupArgs g) {
         S.v[l] = 0.0;
     }
     double cbar = (last && p.cN) ? p.cN[0] : 0.0;
-    double *vec0 = g.fvec + (it.scratch / g.sps) * (int64_t)R.vec();
+    double *vec0 = g.fvec + g.rec_stage(it.scratch) * (int64_t)R.vec();
     wsync();
     for (int s = uni(it.len) - 1; s >= 0; --s) {
         VSrc<TR> q = prob_src<NX, NU, TR>(p, it.t0 + s);
@@ -379,7 +379,7 @@ __global__ void __launch_bounds__(WT) kv_leaf_down(GroupArgs g) {
     if (skip_inst(g, it.inst)) return;
     const Prob p = load_prob(g.probs, it.inst);
     if (!(it.flags & LEAF_TOP)) {
-        const int64_t stage0 = it.scratch / g.sps;
+        const int64_t stage0 = g.rec_stage(it.scratch);
         const TR *rec = reinterpret_cast<const TR *>(g.fstore) + stage0 * (int64_t)LeafRec{NX, NU}.per_stage();
         const double *msg = g.slots + (int64_t)it.slot * SlotLayout{NX}.size();
         leaf_forward_sweep<NX, NU>(S, lamN, p, it, msg,
@@ -388,7 +388,7 @@ __global__ void __launch_bounds__(WT) kv_leaf_down(GroupArgs g) {
     }
     const LeafRec R{NX, NU};
     const SlotLayout SL{NX};
-    const int64_t stage0 = it.scratch / g.sps;
+    const int64_t stage0 = g.rec_stage(it.scratch);
     const TR *rec = reinterpret_cast<const TR *>(g.fstore) + stage0 * (int64_t)R.per_stage();
     double *vec0 = g.fvec + stage0 * (int64_t)R.vec();
     const int l = lane();

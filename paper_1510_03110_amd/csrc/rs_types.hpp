@@ -177,6 +177,11 @@ struct GroupArgs {
     // refinement update: 1 = only measure the correction and the solution
     // (no z += d), for an error estimate of the returned solution
     int32_t measure_only;
+    // leaf-chunked solves: stage index (in the group's leaf stage numbering)
+    // of the first record held by the stored factorization of this launch
+    int64_t rec_stage0;
+    // first stage of a leaf's records in the stored factorization
+    __host__ __device__ int64_t rec_stage(int64_t leaf_scratch) const { return leaf_scratch / sps - rec_stage0; }
 };
 
 }  // namespace rs

@@ -56,7 +56,7 @@ class rs_ip(ctypes.Structure):
 class rs_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("Ns", ctypes.c_int32), ("branch", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("tol", ctypes.c_double), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("leaf_chunk", ctypes.c_int32)]
 
 
 class rs_info(ctypes.Structure):
@@ -157,14 +157,14 @@ def rs_plan_create_split(dims, leaf_lens, branches, precision=RS_FP64, max_refin
     return h
 
 
-def rs_plan_create(dims, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.0, flags=0):
+def rs_plan_create(dims, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.0, flags=0, leaf_chunk=0):
     """dims: sequence of (nx, nu, N), or of (nx, nu, N, Ns, branch) for a
     leaf length and branch per instance (rs_plan_create_ex).  Returns an
     opaque plan handle."""
     arr = np.asarray(dims, dtype=np.int32)
     width = 5 if arr.ndim == 2 and arr.shape[1] == 5 else 3
     arr = np.ascontiguousarray(arr.reshape(-1, width))
-    opt = rs_options(precision, Ns, branch, max_refine, tol, flags, 0)
+    opt = rs_options(precision, Ns, branch, max_refine, tol, flags, leaf_chunk)
     h = _P()
     fn = library().rs_plan_create_ex if width == 5 else library().rs_plan_create
     st = fn(arr.shape[0], arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(opt), ctypes.byref(h))
@@ -323,7 +323,8 @@ class Batch:
     """
 
     def __init__(self, data, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.0,
-                 device="cuda", factored=False, per_instance=None, rank_reveal=False, split=None, report=False):
+                 device="cuda", factored=False, per_instance=None, rank_reveal=False, split=None, report=False,
+                 leaf_chunk=0):
         import torch
         self.torch = torch
         keys = set(data)
@@ -354,7 +355,7 @@ class Batch:
         if split is not None:
             self.plan = rs_plan_create_split(dims, split[0], split[1], precision, max_refine, tol, flags)
         else:
-            self.plan = rs_plan_create(pdims, precision, Ns, branch, max_refine, tol, flags)
+            self.plan = rs_plan_create(pdims, precision, Ns, branch, max_refine, tol, flags, leaf_chunk)
         self.graphs = []
         self.work_bytes = rs_plan_workspace_size(self.plan)
         self.work = torch.empty(self.work_bytes + 256, dtype=torch.uint8, device=device)

@@ -258,6 +258,36 @@ def test_large_block_config_batch64_sampled():
     bt.close()
 
 
+@pytest.mark.timeout(1200)
+def test_large_block_config_batch64_full_horizon():
+    """The large-block configuration's batch at full size: 64 instances of
+    n_x = 128, n_u = 64, N = 16384 (A_t per stage, B, Q, R given once: about
+    141 GB of FP64 inputs), FP64, leaf length 64, branch 8, with the leaf
+    factorization kept for 1024 leaves at a time (leaf_chunk; the whole one
+    would need 790 GB).  Every status must be success and four instances
+    (first, last and two inside) must match the serial oracle at 1e-10."""
+    torch, rs = _rs()
+    from concurrent.futures import ThreadPoolExecutor
+    torch.cuda.empty_cache()
+    data = W.c5_torch(128, 64, 16384, 64, seed=W.seed_for(5, 64), device="cuda")
+    bt = rs.Batch(data, precision=rs.RS_FP64, Ns=64, branch=8, leaf_chunk=1024)
+    bt.solve()
+    torch.cuda.synchronize()
+    assert np.all(bt.status()[:, 0] == 0)
+    pick = (0, 21, 42, 63)
+    sols = [bt.result(i) for i in pick]
+    bt.close()
+    probs = [W.materialize(W.instance_to_numpy(data, i)) for i in pick]
+    del data
+    torch.cuda.empty_cache()
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        refs = list(ex.map(riccati.solve, probs))
+    for i, sol, ref in zip(pick, sols, refs):
+        err = kkt.rel_error(sol, ref)
+        print("c5 batch-64 instance %d: rel err vs oracle %.3e" % (i, err))
+        assert err <= TOL
+
+
 @pytest.mark.parametrize("nx,nu,N,Ns,b", [(128, 64, 40, 4, 3), (64, 32, 200, 8, 4), (48, 16, 64, 8, 2),
                                           (64, 32, 10, 16, 2)])
 def test_bf16_products_match_oracle_after_refinement(nx, nu, N, Ns, b):
