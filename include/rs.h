@@ -367,6 +367,29 @@ rs_status rs_batch_solve(rs_plan plan, const rs_problem *probs, void *work,
                          size_t work_bytes, void *stream, int32_t *info_dev);
 
 /*
+ * rs_batch_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the workspace is a device array of RS_NOALLOC_SCRATCH_BYTES (64 MiB) that
+ * the library holds on every GPU it runs on from its load until the process
+ * ends, so the caller passes only the problems (inputs and outputs, as for
+ * rs_batch_solve), the stream and the optional status array.  The call
+ * allocates nothing (no hipMalloc, hipFree, pinned or library allocation):
+ * the plan's pinned staging is taken at plan creation.  Every call on one GPU
+ * shares that GPU's array, which keeps the last call's contents; each call
+ * binds it afresh (tables, descriptors, cleared tree flags), so calls that
+ * follow one another on the GPU are independent, but calls that overlap on
+ * one GPU (other streams, other threads) race and must not be issued.
+ * The plan's kernel timing is not recorded by this call.  Results are the
+ * same as rs_batch_solve's.  Errors: RS_ERR_NOMEM if the plan's workspace
+ * (rs_plan_workspace_size) exceeds RS_NOALLOC_SCRATCH_BYTES, RS_ERR_ARG for
+ * receding-horizon plans (their stored factors cannot live in a shared
+ * array) and as rs_batch_solve, RS_ERR_HIP if the plan was created without
+ * a device.
+ */
+#define RS_NOALLOC_SCRATCH_BYTES (((size_t)64) << 20)
+rs_status rs_batch_solve_noalloc(rs_plan plan, const rs_problem *probs, void *stream, int32_t *info_dev);
+
+/*
  * Factorization part only (Alg. 1 and the matrix lines of Alg. 4 on every
  * level, including the down-pass factorizations with the true terminal
  * weights).  Reads the matrix fields of probs (Qx, Qw, Qxw, A, B, QxN);

@@ -13,7 +13,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB_PATH = os.path.join(BUILD_DIR, "librs.so")
-SOURCES = ["rs_kernels.hip", "rs_kernels_mfma.hip", "rs_solve.hip", "rs_refine.hip", "rs_large.hip", "rs_mhe.hip", "rs_ip.hip", "rs_pad.hip", "rs_capi.cpp"]
+SOURCES = ["rs_kernels.hip", "rs_kernels_mfma.hip", "rs_solve.hip", "rs_refine.hip", "rs_large.hip", "rs_mhe.hip",
+           "rs_ip.hip", "rs_pad.hip", "rs_static.hip", "rs_capi.cpp"]
 HEADERS = ["rs_types.hpp", "rs_device.hpp", "rs_mfma.hpp", "rs_launch.hpp", "rs_vec.hpp"]
 
 HIPCC_FLAGS = [

@@ -93,6 +93,8 @@ struct rs_plan_s {
     void *bound_work = nullptr;
     std::vector<DevProb> last_probs;
     std::vector<PadArgs> last_pads;
+    std::vector<DevProb> dp_host;       // descriptor images built per call (sized at creation)
+    std::vector<PadArgs> pads_host;
     bool probs_valid = false;
     int32_t epoch = 0;
     int64_t last_refine = 0;
@@ -333,6 +335,46 @@ hipError_t timed(rs_plan_s *P, int kind, hipStream_t st, F &&launch) {
     if (e == hipSuccess) e = hipEventRecord(b, st);
     P->recs.push_back({kind, a, b});
     return e;
+}
+
+// Pinned host staging for the uploads of plan tables and problem
+// descriptors, and the events that guard its reuse.  Taken at plan creation
+// where a device is present, so that no call on the plan allocates; without
+// a device (host-only plan inspection) the first call takes it instead.
+void alloc_staging(rs_plan_s *P) {
+    const size_t pbytes = sizeof(DevProb) * P->dp_host.size() + sizeof(PadArgs) * P->pad_inst.size();
+    if (P->tables_bytes && !P->pinned_tables) {
+        if (hipHostMalloc(&P->pinned_tables, P->tables_bytes) != hipSuccess) {
+            P->pinned_tables = nullptr;
+            (void)hipGetLastError();
+            return;
+        }
+        if (hipEventCreateWithFlags(&P->tables_ev, hipEventDisableTiming) != hipSuccess) {
+            P->tables_ev = nullptr;
+            (void)hipGetLastError();
+            return;
+        }
+    }
+    for (int r = 0; r < RING; ++r) {
+        if (P->pinned_probs[r]) continue;
+        if (hipHostMalloc(&P->pinned_probs[r], pbytes) != hipSuccess) {
+            P->pinned_probs[r] = nullptr;
+            (void)hipGetLastError();
+            return;
+        }
+        if (hipEventCreateWithFlags(&P->ev[r], hipEventDisableTiming) != hipSuccess) {
+            P->ev[r] = nullptr;
+            (void)hipGetLastError();
+            return;
+        }
+    }
+}
+
+bool staging_ready(const rs_plan_s *P) {
+    if (P->tables_bytes && (!P->pinned_tables || !P->tables_ev)) return false;
+    for (int r = 0; r < RING; ++r)
+        if (!P->pinned_probs[r] || !P->ev[r]) return false;
+    return true;
 }
 
 }  // namespace
@@ -661,6 +703,12 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
             for (int i = 0; i < g.nx; ++i) I[(size_t)i * g.nx + i] = 1.0;
         }
     }
+    const size_t nprob = (size_t)count * (P->refine_ws ? 2 : 1);
+    P->dp_host.resize(nprob);
+    P->last_probs.reserve(nprob);
+    P->pads_host.reserve(P->pad_inst.size());
+    P->last_pads.reserve(P->pad_inst.size());
+    alloc_staging(P);
     *out = P;
     return RS_OK;
 }
@@ -800,7 +848,9 @@ int64_t rs_plan_export(rs_plan P, int32_t what, int64_t *out, int64_t cap_rows) 
 static rs_status bind_and_upload(rs_plan P, const rs_problem *probs, char *work, hipStream_t st) {
     hipError_t e;
     // problem descriptors: upload only when they changed since the last call
-    std::vector<DevProb> dp(P->count);
+    if (!staging_ready(P)) alloc_staging(P);
+    if (!staging_ready(P)) return RS_ERR_HIP;
+    std::vector<DevProb> &dp = P->dp_host;
     for (int i = 0; i < P->count; ++i) {
         const rs_problem &q = probs[i];
         DevProb &d = dp[i];
@@ -813,7 +863,8 @@ static rs_status bind_and_upload(rs_plan P, const rs_problem *probs, char *work,
         d.nx = q.nx; d.nu = q.nu; d.N = q.N; d.flags = q.flags;
     }
     // padded instances: the kernels see the padded copies (rs_pad.hip)
-    std::vector<PadArgs> pads;
+    std::vector<PadArgs> &pads = P->pads_host;
+    pads.clear();
     for (int i : P->pad_inst) {
         const rs_problem &q = probs[i];
         DevProb &d = dp[i];
@@ -844,7 +895,6 @@ static rs_status bind_and_upload(rs_plan P, const rs_problem *probs, char *work,
     if (P->refine_ws) {
         // correction problems: the same matrices; right-hand side and
         // solution in the workspace (c = cN = 0, no objective)
-        dp.resize(2 * (size_t)P->count);
         for (int i = 0; i < P->count; ++i) {
             DevProb d = dp[i];
             const size_t nx = d.nx, nu = d.nu, N = d.N;
@@ -870,12 +920,7 @@ static rs_status bind_and_upload(rs_plan P, const rs_problem *probs, char *work,
     const size_t nprob = dp.size();
     const bool rebind = P->bound_work != work;
     if ((rebind || P->tables_dirty) && P->tables_bytes) {
-        if (!P->pinned_tables) {
-            if (hipHostMalloc(&P->pinned_tables, P->tables_bytes) != hipSuccess) return RS_ERR_HIP;
-            if (hipEventCreateWithFlags(&P->tables_ev, hipEventDisableTiming) != hipSuccess) return RS_ERR_HIP;
-        } else if (hipEventSynchronize(P->tables_ev) != hipSuccess) {   // the last upload has read it
-            return RS_ERR_HIP;
-        }
+        if (hipEventSynchronize(P->tables_ev) != hipSuccess) return RS_ERR_HIP;   // the last upload has read it
         std::memcpy(P->pinned_tables, P->tables.data(), P->tables_bytes);
         e = hipMemcpyAsync(work + P->off_tables, P->pinned_tables, P->tables_bytes, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return RS_ERR_HIP;
@@ -898,10 +943,6 @@ static rs_status bind_and_upload(rs_plan P, const rs_problem *probs, char *work,
         (abytes && std::memcmp(pads.data(), P->last_pads.data(), abytes) != 0)) {
         const int r = P->ring;
         P->ring = (P->ring + 1) % RING;
-        if (!P->pinned_probs[r]) {
-            if (hipHostMalloc(&P->pinned_probs[r], pbytes + abytes) != hipSuccess) return RS_ERR_HIP;
-            if (hipEventCreateWithFlags(&P->ev[r], hipEventDisableTiming) != hipSuccess) return RS_ERR_HIP;
-        }
         if (P->ev_used[r] && hipEventSynchronize(P->ev[r]) != hipSuccess) return RS_ERR_HIP;
         std::memcpy(P->pinned_probs[r], dp.data(), pbytes);
         if (abytes) std::memcpy(static_cast<char *>(P->pinned_probs[r]) + pbytes, pads.data(), abytes);
@@ -1291,6 +1332,27 @@ rs_status rs_graph_destroy(rs_graph G) {
 rs_status rs_batch_solve(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
                          int32_t *info_dev) {
     return run_call(P, probs, work, work_bytes, stream, info_dev, 0);
+}
+
+static_assert(RS_NOALLOC_SCRATCH_BYTES == STATIC_SCRATCH_BYTES, "scratch size in rs.h and the library agree");
+
+rs_status rs_batch_solve_noalloc(rs_plan P, const rs_problem *probs, void *stream, int32_t *info_dev) {
+    if (!P || !probs) return RS_ERR_ARG;
+    if (P->receding) return RS_ERR_ARG;      // its stored factors would not survive other calls' use
+    size_t bytes = 0;
+    void *work = static_scratch(&bytes);
+    if (!work) return RS_ERR_HIP;
+    if (P->total > bytes) return RS_ERR_NOMEM;
+    if (!staging_ready(P)) return RS_ERR_HIP;  // plan created without a device
+    // the scratch is shared by every call on this device and keeps the last
+    // call's contents: bind it afresh, which uploads the tables and the
+    // descriptors and clears the tree's completion flags with a fill kernel
+    P->bound_work = nullptr;
+    const bool timing = P->timing;            // per-kernel events would be created
+    P->timing = false;
+    const rs_status s = run_call(P, probs, work, bytes, stream, info_dev, 0);
+    P->timing = timing;
+    return s;
 }
 
 rs_status rs_refine_stats(rs_plan P, const void *work, double *out, void *stream) {

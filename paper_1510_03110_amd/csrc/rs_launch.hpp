@@ -64,6 +64,11 @@ Launcher large_refine(int which);
 Launcher mfma_factor_leaf32(int nx, int nu, int which);   // FP32 leaves of n_x = 64 (which 0 up, 2 down)
 
 const ShapeEntry *find_shape(int nx, int nu);
+
+// Device scratch of rs_batch_solve_noalloc (rs_static.hip): its device
+// address on the current device (taken once per device), and its size.
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(64) << 20;
+void *static_scratch(size_t *bytes);
 hipError_t launch_init(int32_t *info, int count, int32_t *queues, int nq, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 // padded copies of the inputs of npad instances (back = false), or their w

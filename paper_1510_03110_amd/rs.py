@@ -116,6 +116,8 @@ def library():
         lib.rs_refine_stats.restype = i32
         lib.rs_info_report.argtypes = [_P, _P, _P, _P, _P]
         lib.rs_info_report.restype = i32
+        lib.rs_batch_solve_noalloc.argtypes = [_P, ctypes.POINTER(rs_problem), _P, _P]
+        lib.rs_batch_solve_noalloc.restype = i32
         lib.rs_status_string.argtypes = [i32]
         lib.rs_status_string.restype = ctypes.c_char_p
         for name in ("rs_plan_create", "rs_plan_create_ex", "rs_plan_create_split", "rs_plan_create_ring",
@@ -273,6 +275,14 @@ def _call(name, plan, probs, work_ptr, work_bytes, stream_ptr, info_ptr):
 
 def rs_batch_solve(plan, probs, work_ptr, work_bytes, stream_ptr=None, info_ptr=None):
     _call("rs_batch_solve", plan, probs, work_ptr, work_bytes, stream_ptr, info_ptr)
+
+
+def rs_batch_solve_noalloc(plan, probs, stream_ptr=None, info_ptr=None):
+    """rs_batch_solve on the library's static device scratch (no workspace)."""
+    _check(library().rs_batch_solve_noalloc(plan, probs, stream_ptr, info_ptr), "rs_batch_solve_noalloc")
+
+
+RS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def rs_factor(plan, probs, work_ptr, work_bytes, stream_ptr=None, info_ptr=None):
