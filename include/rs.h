@@ -169,6 +169,14 @@ typedef struct rs_options {
  * refinement count, with bwd_err = -1 (FP64 plans: all three measures -1). */
 #define RS_PLAN_REPORT 4
 
+/* rs_options.flags: check the inputs for NaN and infinity on the device after
+ * every call (one more pass over them).  An instance with a non-finite entry
+ * in any of its input arrays gets status RS_ERR_ARG in info_dev, whatever
+ * the solve reported, and as stage the first offending place: -1 for x0,
+ * t for the data of stage t (Qx, Qw, Qxw, A, B, a, lx, lw, c), N for the
+ * terminal data (QxN, lN, cN).  Its outputs are not meaningful. */
+#define RS_PLAN_CHECK_INPUTS 8
+
 /* Per-instance result report (device memory, 40 bytes each). */
 typedef struct rs_info {
     double rel_resid;       /* ||r - K z||_inf / ||r||_inf                          */

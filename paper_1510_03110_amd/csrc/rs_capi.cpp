@@ -61,6 +61,8 @@ struct rs_plan_s {
     bool report = false;            // per-instance report: K norm, FP64 residual, error estimate
     bool refine_ws = false;         // workspace holds the refinement tables (mixed or report)
     int32_t leaf_chunk = 0;         // > 0: leaves processed in chunks of this many (bounded factor store)
+    bool check_inputs = false;      // RS_PLAN_CHECK_INPUTS: finite-input scan after every call
+    size_t off_scan = 0;            // its per-instance first offending place
     rs_options opt{};               // options the plan was made with
     bool tables_dirty = false;      // host tables changed since the last upload
     hipEvent_t tables_ev = nullptr; // completion of the last table upload
@@ -419,6 +421,7 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         P->rank_reveal = (opt->flags & RS_PLAN_RANK_REVEAL) != 0;
         P->report = (opt->flags & RS_PLAN_REPORT) != 0;
         P->leaf_chunk = opt->leaf_chunk;
+        P->check_inputs = (opt->flags & RS_PLAN_CHECK_INPUTS) != 0;
         if (opt->Ns > 0) P->Ns = opt->Ns;
         if (opt->branch > 0) P->branch = opt->branch;
         P->max_refine = opt->max_refine > 0 ? opt->max_refine : (P->bf16 ? 20 : 5);
@@ -595,6 +598,10 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
     off = align_up(P->off_padargs + sizeof(PadArgs) * P->pad_inst.size());
     P->off_info = off;
     off = align_up(off + sizeof(int32_t) * 2 * count);
+    if (P->check_inputs) {
+        P->off_scan = off;
+        off = align_up(off + sizeof(int32_t) * count);
+    }
     P->off_queues = off;
     off = align_up(off + sizeof(int32_t) * P->groups.size());
     if (P->receding) {
@@ -1215,6 +1222,16 @@ static rs_status run_padded(rs_plan P, char *W, int32_t *info, hipStream_t st, i
     if (npad && launch_pad(pa, npad, false, st) != hipSuccess) return RS_ERR_HIP;
     rs_status s = run_sequence(P, W, info, st, mode);
     if (s == RS_OK && npad && mode != 1 && launch_pad(pa, npad, true, st) != hipSuccess) s = RS_ERR_HIP;
+    if (s == RS_OK && P->check_inputs) {
+        // after the solve, so that its status words are what this overrides
+        int32_t *first = reinterpret_cast<int32_t *>(W + P->off_scan);
+        if (launch_fill_i32(first, P->count, 0x7fffffff, st) != hipSuccess) return RS_ERR_HIP;
+        for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+            GroupArgs a = group_args(P, W, gi, info, false, false);
+            if (timed(P, KK_REPORT, st, [&] { return launch_scan(a, first, st); }) != hipSuccess) return RS_ERR_HIP;
+        }
+        if (launch_scan_mark(P->count, first, info, st) != hipSuccess) return RS_ERR_HIP;
+    }
     return s;
 }
 

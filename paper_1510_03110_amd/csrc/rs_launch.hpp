@@ -46,6 +46,11 @@ Launcher leaf_forward(int nx, int nu);                   // leaf solve on the st
 hipError_t launch_refine_check(const InstInfo *tab, int count, const double *part, double *stats, int32_t *conv,
                                int32_t *info, const DevProb *probs, int mode, double tol, int32_t *active,
                                int nactive, int with_knorm, hipStream_t st);
+// Finite-input check (RS_PLAN_CHECK_INPUTS): per leaf, the smallest
+// offending place per instance into first[] (preset to INT32_MAX), then
+// RS_ERR_ARG and the place in the status words.
+hipError_t launch_scan(const GroupArgs &g, int32_t *first, hipStream_t st);
+hipError_t launch_scan_mark(int count, const int32_t *first, int32_t *info, hipStream_t st);
 // KKT-matrix infinity norm of each leaf's rows (PART_KN of the leaf parts).
 hipError_t launch_knorm(const GroupArgs &g, hipStream_t st);
 // rs_info records (40 bytes each) from the statistics (or nullptr) and the

@@ -506,6 +506,71 @@ __global__ void kr_report(int count, const double *stats, const int32_t *info, i
 
 }  // namespace sv
 
+namespace sv {
+
+// Finite-input check of one leaf's stages (RS_PLAN_CHECK_INPUTS): every
+// element of Qx, Qw, Qxw, A, B, a, lx, lw and c of the leaf's stages, and of
+// x0 (first leaf) and QxN, lN, cN (last leaf).  The smallest offending place
+// of the instance, encoded 0 for x0, t + 1 for stage t and N + 1 for the
+// terminal data, goes to first[inst] (atomic minimum).
+__device__ __forceinline__ bool finite_block(const double *p, int64_t n, int tid) {
+    bool ok = true;
+    if (p)
+        for (int64_t e = tid; e < n; e += RT) ok = ok && __builtin_isfinite(p[e]);
+    return ok;
+}
+
+__global__ void __launch_bounds__(RT) kc_scan(GroupArgs g, int32_t *first) {
+    __shared__ int bad_s;
+    const LeafItem it = load_leaf(g.leaves, blockIdx.x);
+    if ((uni(g.probs[it.inst].flags) & PROB_SKIP) != 0) return;
+    const Prob p = load_prob(g.probs, it.inst);
+    const int64_t n = g.nx, m = g.nu;
+    const int tid = threadIdx.x, len = uni(it.len);
+    if (tid == 0) bad_s = 0x7fffffff;
+    __syncthreads();
+    for (int s = 0; s < len; ++s) {
+        const int64_t t = it.t0 + s;
+        bool ok = finite_block(p.Qx + t * p.sQx, n * n, tid) && finite_block(p.Qw + t * p.sQw, m * m, tid) &&
+                  finite_block(p.Qxw ? p.Qxw + t * p.sQxw : nullptr, n * m, tid) &&
+                  finite_block(p.A + t * p.sA, n * n, tid) && finite_block(p.B + t * p.sB, n * m, tid) &&
+                  finite_block(p.a ? p.a + t * p.sa : nullptr, n, tid) &&
+                  finite_block(p.lx ? p.lx + t * p.slx : nullptr, n, tid) &&
+                  finite_block(p.lw ? p.lw + t * p.slw : nullptr, m, tid) &&
+                  finite_block(p.c ? p.c + t * p.sc : nullptr, 1, tid);
+        if (!ok) atomicMin(&bad_s, (int)t + 1);
+    }
+    if (it.t0 == 0 && !finite_block(p.x0, n, tid)) atomicMin(&bad_s, 0);
+    if (it.flags & LEAF_LAST) {
+        const bool ok = finite_block(p.QxN, n * n, tid) && finite_block(p.lN, n, tid) && finite_block(p.cN, 1, tid);
+        if (!ok) atomicMin(&bad_s, it.t0 + len + 1);
+    }
+    __syncthreads();
+    if (tid == 0 && bad_s != 0x7fffffff) atomicMin(&first[it.inst], bad_s);
+}
+
+// Instances with a non-finite input: status RS_ERR_ARG and the place
+// (-1 for x0, the stage, N for the terminal data).
+__global__ void kc_mark(int count, const int32_t *first, int32_t *info) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count || first[i] == 0x7fffffff) return;
+    info[2 * i] = 1;     // RS_ERR_ARG
+    info[2 * i + 1] = first[i] - 1;
+}
+
+}  // namespace sv
+
+hipError_t launch_scan(const GroupArgs &g, int32_t *first, hipStream_t st) {
+    if (g.nleaves < 1) return hipSuccess;
+    hipLaunchKernelGGL(sv::kc_scan, dim3(g.nleaves), dim3(sv::RT), 0, st, g, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_mark(int count, const int32_t *first, int32_t *info, hipStream_t st) {
+    hipLaunchKernelGGL(sv::kc_mark, dim3((count + 63) / 64), dim3(64), 0, st, count, first, info);
+    return hipGetLastError();
+}
+
 hipError_t launch_knorm(const GroupArgs &g, hipStream_t st) {
     if (g.nleaves < 1 || g.nx > 128 || g.nu > 128) return hipSuccess;
     hipLaunchKernelGGL(sv::kn_norm, dim3(g.nleaves), dim3(sv::RT), 0, st, g);
