@@ -120,12 +120,34 @@ def load_traffic(kernel, workload):
 
 
 # ------------------------------------------------------------- CPU baseline
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(host_probs, seconds):
     """The serial FP64 oracle on the host cores: instances are solved one per
-    thread (ctypes releases the GIL) until `seconds` of wall time are used."""
+    thread (ctypes releases the GIL) until `seconds` of wall time are used.
+    The oracle is built here with -O3 -march=native for this host (same
+    source and summation order as the portable build the tests use)."""
     from concurrent.futures import ThreadPoolExecutor, wait, FIRST_COMPLETED
-    from oracle import riccati
+    import tempfile
+    from oracle import build as obuild, riccati
     threads = max(1, min(16, os.cpu_count() or 1))
+    try:
+        path = obuild.build(path=os.path.join(tempfile.gettempdir(), "rs_oracle_native_%d" % os.getpid(),
+                                              "liboracle.so"), native=True)
+        riccati.use_library(path)
+        flags = "-O3 -march=native"
+    except Exception as e:          # no compiler: the portable build
+        log("native oracle build failed (%s); using the portable build" % e)
+        flags = "-O3"
     riccati.solve(host_probs[0])              # load/build outside the timing
     done = 0
     t0 = time.perf_counter()
@@ -141,7 +163,7 @@ def cpu_baseline(host_probs, seconds):
             fin, pending = wait(pending, return_when=FIRST_COMPLETED)
             done += len(fin)
     el = time.perf_counter() - t0
-    return done, el, threads
+    return done, el, threads, flags
 
 
 def leaf_work(leaves, n, m, up_fn, elim_fn, down_fn, top_fn=None):
@@ -465,6 +487,109 @@ def run_batching(args):
     print(json.dumps(out), flush=True)
 
 
+def _timed_solves(batch, reps, warmup=1):
+    """ms per rs_batch_solve (host clock around `reps` calls, synchronized)."""
+    import torch
+    for _ in range(warmup):
+        batch.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        batch.solve()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / reps
+
+
+def run_extras(args, dev):
+    """The other configurations, each small enough to add seconds to the run:
+    single-instance latency across leaf lengths at n_x = 20, n_u = 10,
+    N = 1024 (FP64); 4096 instances of n_x = 16, n_u = 8 with horizons in
+    [32, 2048], leaf length and branch chosen by the autotuner measured here
+    (FP64 and mixed); the large-block configuration's single instance
+    (n_x = 128, n_u = 64, N = 16384; FP64, mixed, BF16 products) and its batch
+    of 64 (FP64, leaf factorization kept for 1024 leaves at a time).  Sampled
+    instances are checked against the oracle where it finishes in seconds."""
+    import tempfile
+    import numpy as np
+    import torch
+    from oracle import kkt, riccati
+    from paper_1510_03110_amd import autotune, rs
+    from paper_1510_03110_amd import workloads as W
+    out = {}
+    # ----------------------------------------- C2: latency across N_s
+    prob = W.g2(20, 10, 1024, seed=W.seed_for(1))
+    ref = riccati.solve(prob)
+    lat = {}
+    for Ns in (4, 8, 16, 32, 64):
+        one = rs.Batch({k: [prob[k]] for k in prob}, precision=rs.RS_FP64, Ns=Ns, branch=4, device=dev)
+        for _ in range(5):
+            one.solve()
+        torch.cuda.synchronize()
+        smp = []
+        for _ in range(50):
+            s0 = time.perf_counter()
+            one.solve()
+            torch.cuda.synchronize()
+            smp.append(1e3 * (time.perf_counter() - s0))
+        err = kkt.rel_error(one.result(0), ref)
+        lat[str(Ns)] = {"p50_ms": round(float(np.percentile(smp, 50)), 4),
+                        "p99_ms": round(float(np.percentile(smp, 99)), 4), "rel_err": float(err),
+                        "status": int(one.status()[0, 0])}
+        one.close()
+    out["c2_latency_nx20_nu10_N1024_branch4_by_Ns"] = lat
+    log("extras c2:", lat)
+    # ------------------------------------- C3: 4096 uneven, autotuned
+    rng = np.random.default_rng(W.seed_for(2))
+    horizons = rng.integers(32, 2049, size=4096)
+    data = W.g1_invariant_torch(16, 8, horizons, seed=W.seed_for(2, 1), device=dev)
+    dims = [(16, 8, int(n)) for n in horizons]
+    tuner = autotune.Tuner(os.path.join(tempfile.gettempdir(), "rs_tune_%d.json" % os.getpid()))
+    c3 = {}
+    for prec, pc in (("fp64", rs.RS_FP64), ("mixed", rs.RS_MIXED_FP32)):
+        for b in sorted({autotune.n_bucket(N) for _, _, N in dims}):
+            tuner.tune(16, 8, b, pc, reps=2)
+        per = tuner.per_instance(dims, pc)
+        bt = rs.Batch(data, precision=pc, per_instance=per, device=dev)
+        ms = _timed_solves(bt, 3)
+        st = bt.status()
+        errs = [kkt.rel_error(bt.result(i), riccati.solve(W.materialize(W.instance_to_numpy(data, i))))
+                for i in (0, 2047, 4095)]
+        c3[prec] = {"solves_per_s": round(4096 / (ms * 1e-3), 1), "ms_per_batch": round(ms, 3),
+                    "nonzero_status": int((st[:, 0] != 0).sum()), "max_rel_err_sampled": float(max(errs)),
+                    "tree_shapes": sorted({"%d/%d" % tuple(p) for p in per})}
+        bt.close()
+    del data
+    torch.cuda.empty_cache()
+    out["c3_batching_4096_nx16_nu8_N32to2048_autotuned"] = c3
+    log("extras c3:", c3)
+    # --------------------------------------- C5: single and batch of 64
+    data = W.c5_torch(128, 64, 16384, 1, seed=W.seed_for(5), device=dev)
+    c5 = {}
+    for prec, pc in (("fp64", rs.RS_FP64), ("mixed", rs.RS_MIXED_FP32), ("bf16", rs.RS_MIXED_BF16)):
+        bt = rs.Batch(data, precision=pc, Ns=64, branch=8, device=dev)
+        ms = _timed_solves(bt, 3)
+        c5[prec] = {"ms_per_solve": round(ms, 3), "status": int(bt.status()[0, 0])}
+        if pc != rs.RS_FP64:
+            c5[prec]["corrections"] = float(bt.refine_stats()[0, 2])
+        bt.close()
+    del data
+    torch.cuda.empty_cache()
+    out["c5_single_nx128_nu64_N16384"] = c5
+    log("extras c5 single:", c5)
+    data = W.c5_torch(128, 64, 16384, 64, seed=W.seed_for(5, 64), device=dev)
+    bt = rs.Batch(data, precision=rs.RS_FP64, Ns=64, branch=8, leaf_chunk=1024, device=dev)
+    ms = _timed_solves(bt, 1)
+    out["c5_batch64_nx128_nu64_N16384_fp64"] = {
+        "solves_per_s": round(64 / (ms * 1e-3), 3), "ms_per_batch": round(ms, 1),
+        "nonzero_status": int((bt.status()[:, 0] != 0).sum()), "leaf_chunk": 1024,
+        "workspace_gb": round(bt.work_bytes / 1e9, 1)}
+    bt.close()
+    del data
+    torch.cuda.empty_cache()
+    log("extras c5 batch:", out["c5_batch64_nx128_nu64_N16384_fp64"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -498,6 +623,9 @@ def main():
     ap.add_argument("--rank-reveal", action="store_true",
                     help="rank-revealing master stages (allows Ns * nu < nx)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-extras", dest="extras", action="store_false",
+                    help="skip the other configurations (single-instance latency across leaf lengths, the "
+                         "4096-instance batching configuration, the large-block single and batch-64 runs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -541,15 +669,17 @@ def main():
 
     head = max(precs, key=lambda k: results[k]["value"])
     r = results[head]
+    extras = run_extras(args, dev) if args.extras else None
 
     # --------------------------------------------------- CPU oracle baseline
     cpu = None
     if args.cpu_seconds > 0:
-        done, cel, threads = cpu_baseline(host, args.cpu_seconds)
+        done, cel, threads, flags = cpu_baseline(host, args.cpu_seconds)
         cpu = {"value": round(done / cel, 3), "unit": "solves/s", "cores": threads, "kind": "oracle",
-               "sample": "%d solves of instances %s of the same workload (serial FP64 Riccati, C) "
-                         "in %.1fs on %d host threads" % (done, [int(i) for i in r["sampled_instances"]], cel,
-                                                          threads)}
+               "cpu_model": cpu_model(), "build": "gcc %s" % flags,
+               "sample": "%d solves of instances %s of the same workload (serial FP64 Riccati, C, gcc %s) "
+                         "in %.1fs on %d host threads" % (done, [int(i) for i in r["sampled_instances"]], flags,
+                                                          cel, threads)}
         log("cpu baseline:", cpu)
 
     out = {
@@ -566,6 +696,7 @@ def main():
         "cpu_baseline": cpu,
         "precisions": {k: {kk: vv for kk, vv in v.items() if kk != "sampled_instances"}
                        for k, v in results.items()},
+        "extras": extras,
     }
     if args.copy_calibration_mib > 0:
         # a plain copy kernel of known size, for scaling FETCH_SIZE/WRITE_SIZE

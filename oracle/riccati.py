@@ -11,10 +11,20 @@ from . import build as _build
 _lib = None
 
 
+def use_library(path):
+    """Load the oracle from another build of the same source (the host-tuned
+    build the timed CPU baseline uses); the next call loads it."""
+    global _lib, _path
+    _lib, _path = None, path
+
+
+_path = None
+
+
 def _load():
     global _lib
     if _lib is None:
-        path = _build.ensure_built()
+        path = _path or _build.ensure_built()
         lib = ctypes.CDLL(path)
         dp = ctypes.c_void_p
         lib.oracle_riccati_solve.restype = ctypes.c_int

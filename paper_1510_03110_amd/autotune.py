@@ -15,8 +15,8 @@ persist in a JSON cache: $RS_TUNE_CACHE, else
 ~/.cache/paper_1510_03110_amd/tune.json.
 
 Timing runs the library's own HIP-graph replay of rs_batch_solve on a
-synthetic G2 batch of the key's shape (about 2^20 stages, so the GPU is
-full), three replays per candidate after one warm-up.
+synthetic batch of the key's shape (G1 stages, about 2^20 of them, so the
+GPU is full), three replays per candidate after one warm-up.
 """
 import json
 import os
@@ -103,7 +103,9 @@ class Tuner:
         from . import workloads as W
         Nt = n_bucket(N)
         B = batch or max(1, min(1024, (1 << 20) // Nt))
-        data = W.g2_torch(nx, nu, Nt, B, seed=W.seed_for(2, 0), device=device)
+        # the timing depends on the shape only: G1 stages drawn in a few
+        # device calls (A, B given once per instance)
+        data = W.g1_invariant_torch(nx, nu, [Nt] * B, seed=W.seed_for(2, 0), device=device)
         results = {}
         for Ns in ns_candidates:
             for br in branch_candidates:

@@ -228,6 +228,40 @@ def c5_torch(nx, nu, N, count, seed, device="cuda"):
     )
 
 
+def g1_invariant_torch(nx, nu, horizons, seed, device="cuda"):
+    """Batch of G1 instances with the given horizons drawn in device memory:
+    A scaled to spectral radius 0.95 and B ~ N(0,1), both time-invariant and
+    given once (stage axis of length 1); Q_x, Q_w diagonal U[0.5, 2] per
+    stage; no cross term; a_t, l_{x,t}, l_{w,t}, l_N, xbar_0 ~ N(0,1); c_t = 0;
+    Q_{x,N} = diag U[0.5, 2].  Same distributions as ``g1_invariant``, a
+    different random stream.  Returns a dict of per-instance tensor lists
+    (views into a few large tensors)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    f64 = dict(dtype=torch.float64, device=device)
+    Ns = [int(n) for n in horizons]
+    cnt, S = len(Ns), int(sum(Ns))
+    A0 = torch.randn((cnt, nx, nx), generator=gen, **f64)
+    rad = torch.linalg.eigvals(A0.cpu()).abs().amax(dim=-1).to(device)
+    A = (A0 * (0.95 / rad)[:, None, None])[:, None]
+    B = torch.randn((cnt, 1, nx, nu), generator=gen, **f64)
+    Qx = torch.diag_embed(torch.rand((S, nx), generator=gen, **f64) * 1.5 + 0.5)
+    Qw = torch.diag_embed(torch.rand((S, nu), generator=gen, **f64) * 1.5 + 0.5)
+    a = torch.randn((S, nx), generator=gen, **f64)
+    lx = torch.randn((S, nx), generator=gen, **f64)
+    lw = torch.randn((S, nu), generator=gen, **f64)
+    c = torch.zeros((S,), **f64)
+    QxN = torch.diag_embed(torch.rand((cnt, nx), generator=gen, **f64) * 1.5 + 0.5)
+    lN = torch.randn((cnt, nx), generator=gen, **f64)
+    x0 = torch.randn((cnt, nx), generator=gen, **f64)
+    out = {k: list(torch.split(v, Ns)) for k, v in (("Qx", Qx), ("Qw", Qw), ("a", a), ("lx", lx), ("lw", lw),
+                                                      ("c", c))}
+    out.update(A=list(A), B=list(B), QxN=list(QxN), lN=list(lN), x0=list(x0),
+               cN=list(torch.zeros((cnt,), **f64)))
+    return out
+
+
 def instance_to_numpy(batch, i):
     """Instance ``i`` of a stacked torch batch as a numpy problem dict."""
     out = {}
