@@ -455,7 +455,7 @@ def run_batching(args):
             for b in sorted({autotune.n_bucket(N) for _, _, N in dims}):
                 tuner.tune(nx, nu, b, pc, log=log)
         per = tuner.per_instance(dims, pc)
-        bt = rs.Batch(data, precision=pc, per_instance=per)
+        bt = rs.Batch(data, precision=pc, per_instance=per, flags=tuner.plan_flags(dims, pc))
         for _ in range(args.warmup):
             bt.solve()
         torch.cuda.synchronize()
@@ -549,14 +549,16 @@ def run_extras(args, dev):
         for b in sorted({autotune.n_bucket(N) for _, _, N in dims}):
             tuner.tune(16, 8, b, pc, reps=2)
         per = tuner.per_instance(dims, pc)
-        bt = rs.Batch(data, precision=pc, per_instance=per, device=dev)
+        flags = tuner.plan_flags(dims, pc)
+        bt = rs.Batch(data, precision=pc, per_instance=per, device=dev, flags=flags)
         ms = _timed_solves(bt, 3)
         st = bt.status()
         errs = [kkt.rel_error(bt.result(i), riccati.solve(W.materialize(W.instance_to_numpy(data, i))))
                 for i in (0, 2047, 4095)]
         c3[prec] = {"solves_per_s": round(4096 / (ms * 1e-3), 1), "ms_per_batch": round(ms, 3),
                     "nonzero_status": int((st[:, 0] != 0).sum()), "max_rel_err_sampled": float(max(errs)),
-                    "tree_shapes": sorted({"%d/%d" % tuple(p) for p in per})}
+                    "tree_shapes": sorted({"%d/%d" % tuple(p) for p in per}),
+                    "tiles": "native" if flags else "mfma16"}
         bt.close()
     del data
     torch.cuda.empty_cache()

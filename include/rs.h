@@ -177,6 +177,13 @@ typedef struct rs_options {
  * terminal data (QxN, lN, cN).  Its outputs are not meaningful. */
 #define RS_PLAN_CHECK_INPUTS 8
 
+/* rs_options.flags: tile shape.  Instances with n_x = 16 or 32 and n_u < 16
+ * are by default solved on the 16 x 16 matrix-core tile kernels with their
+ * inputs padded to n_u = 16 (inputs that act on nothing, see the padding
+ * kernels); with this flag they run on the kernels for their own shape
+ * instead (wavefront and large-block kernels).  An autotuner chooses. */
+#define RS_PLAN_NATIVE_TILES 16
+
 /* Per-instance result report (device memory, 40 bytes each). */
 typedef struct rs_info {
     double rel_resid;       /* ||r - K z||_inf / ||r||_inf                          */

@@ -508,7 +508,8 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         // (not in receding-horizon plans, whose records are windows of
         // caller-owned rings, nor with BF16 products)
         int nuk = nu;
-        if (nu < PAD_NU && (nx == 16 || nx == 32) && !P->receding && !P->bf16) {
+        if (nu < PAD_NU && (nx == 16 || nx == 32) && !P->receding && !P->bf16 &&
+            !(P->opt.flags & RS_PLAN_NATIVE_TILES)) {
             P->nu_user[i] = nu;
             P->dims[3 * i + 1] = PAD_NU;
             P->pad_inst.push_back(i);

@@ -22,6 +22,7 @@ RS_PLAN_FACTORED = 1
 RS_PLAN_RANK_REVEAL = 2
 RS_PLAN_REPORT = 4
 RS_PLAN_CHECK_INPUTS = 8
+RS_PLAN_NATIVE_TILES = 16
 RS_PROB_SKIP = 1
 RS_KERNEL_KINDS = 16
 
@@ -335,7 +336,7 @@ class Batch:
 
     def __init__(self, data, precision=RS_FP64, Ns=0, branch=0, max_refine=0, tol=0.0,
                  device="cuda", factored=False, per_instance=None, rank_reveal=False, split=None, report=False,
-                 leaf_chunk=0, check_inputs=False):
+                 leaf_chunk=0, check_inputs=False, flags=0):
         import torch
         self.torch = torch
         keys = set(data)
@@ -362,7 +363,7 @@ class Batch:
         self.info = torch.zeros(2 * self.count, dtype=torch.int32, device=device)
         pdims = dims if per_instance is None else [d + tuple(pi) for d, pi in zip(dims, per_instance)]
         flags = (RS_PLAN_FACTORED if factored else 0) | (RS_PLAN_RANK_REVEAL if rank_reveal else 0) | \
-            (RS_PLAN_REPORT if report else 0) | (RS_PLAN_CHECK_INPUTS if check_inputs else 0)
+            (RS_PLAN_REPORT if report else 0) | (RS_PLAN_CHECK_INPUTS if check_inputs else 0) | int(flags)
         if split is not None:
             self.plan = rs_plan_create_split(dims, split[0], split[1], precision, max_refine, tol, flags)
         else:
