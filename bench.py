@@ -592,6 +592,43 @@ def run_extras(args, dev):
     return out
 
 
+def run_large(args):
+    """Large-block mode: the large-block configuration's single instance
+    (n_x = 128, n_u = 64, N = 16384, A_t per stage, B, Q, R given once) in
+    one precision (--precision fp64|mixed|bf16), K timed solves after W
+    warm-up solves, leaf length 64, branch 8; one JSON line with ms per solve
+    and the per-kernel device times (for profiling runs)."""
+    import torch
+    from paper_1510_03110_amd import rs
+    from paper_1510_03110_amd import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prec = args.precision if args.precision in ("fp64", "mixed", "bf16") else "fp64"
+    pc = {"fp64": rs.RS_FP64, "mixed": rs.RS_MIXED_FP32, "bf16": rs.RS_MIXED_BF16}[prec]
+    data = W.c5_torch(128, 64, 16384, 1, seed=W.seed_for(5), device="cuda")
+    bt = rs.Batch(data, precision=pc, Ns=64, branch=8)
+    for _ in range(args.warmup):
+        bt.solve()
+    torch.cuda.synchronize()
+    rs.rs_plan_kernel_times(bt.plan, reset=True)
+    rs.rs_plan_set_timing(bt.plan, True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bt.solve()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rs.rs_plan_set_timing(bt.plan, False)
+    kt = rs.rs_plan_kernel_times(bt.plan, reset=True)
+    out = {"metric": "KKT Newton solve time, n_x=128, n_u=64, N=16384, one instance", "value": round(1e3 * el / args.steps, 3),
+           "unit": "ms/solve", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": False,
+           "dtype": {"fp64": "f64", "mixed": "f32+f64", "bf16": "bf16+f32+f64"}[prec],
+           "data": "synthetic: seeded, A_t per stage, B, Q, R given once (drawn on the device)",
+           "config": {"workload": "uftoc_c5_nx128_nu64_N16384_batch1", "precision": prec, "Ns": 64, "branch": 8},
+           "status": int(bt.status()[0, 0]),
+           "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kt.items() if v[1]}}
+    bt.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -622,6 +659,8 @@ def main():
     ap.add_argument("--tune-cache", default="", help="autotuner cache file (default: the tuner's)")
     ap.add_argument("--ip", action="store_true",
                     help="interior-point mode: one problem with input bounds (see run_ip)")
+    ap.add_argument("--large", action="store_true",
+                    help="large-block mode: the n_x=128, n_u=64, N=16384 single instance (see run_large)")
     ap.add_argument("--rank-reveal", action="store_true",
                     help="rank-revealing master stages (allows Ns * nu < nx)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -649,6 +688,9 @@ def main():
         return
     if args.batching:
         run_batching(args)
+        return
+    if args.large:
+        run_large(args)
         return
 
     import torch

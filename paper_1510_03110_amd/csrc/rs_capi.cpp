@@ -1378,10 +1378,16 @@ rs_status rs_refine_stats(rs_plan P, const void *work, double *out, void *stream
     if (!P->mixed) return RS_ERR_ARG;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const char *W = static_cast<const char *>(work);
-    if (hipMemcpy2DAsync(out, sizeof(double) * ST_PUBLIC, W + P->off_stats, sizeof(double) * ST_N,
-                         sizeof(double) * ST_PUBLIC, P->count, hipMemcpyDeviceToHost, st) != hipSuccess)
+    // the whole statistics block, then the public columns (a plain copy:
+    // the caller's buffer is ordinary host memory)
+    std::vector<double> all((size_t)ST_N * P->count);
+    if (hipMemcpyAsync(all.data(), W + P->off_stats, sizeof(double) * all.size(), hipMemcpyDeviceToHost, st) !=
+        hipSuccess)
         return RS_ERR_HIP;
-    return hipStreamSynchronize(st) == hipSuccess ? RS_OK : RS_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return RS_ERR_HIP;
+    for (int i = 0; i < P->count; ++i)
+        for (int q = 0; q < ST_PUBLIC; ++q) out[(size_t)i * ST_PUBLIC + q] = all[(size_t)i * ST_N + q];
+    return RS_OK;
 }
 
 rs_status rs_info_report(rs_plan P, const void *work, const int32_t *info_dev, rs_info *report_dev, void *stream) {
