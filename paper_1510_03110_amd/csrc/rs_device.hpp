@@ -190,6 +190,7 @@ __device__ __forceinline__ void trsv_lt(const T *__restrict__ L, const T *__rest
 struct StageSrc {
     const double *Qx, *Qw, *Qxw, *A, *B, *a, *lx, *lw;
     double c;
+    const double *cp;      // where c is read from (nullptr: c = 0), for prefetching passes
 };
 
 // Problem descriptor copied once into wave-uniform registers.  Reading it
@@ -252,7 +253,8 @@ __device__ __forceinline__ StageSrc prob_stage(const DevProb &p, int t) {
     s.a = p.a ? p.a + (int64_t)t * p.sa : nullptr;
     s.lx = p.lx ? p.lx + (int64_t)t * p.slx : nullptr;
     s.lw = p.lw ? p.lw + (int64_t)t * p.slw : nullptr;
-    s.c = p.c ? gload(p.c + (int64_t)t * p.sc) : 0.0;
+    s.cp = p.c ? p.c + (int64_t)t * p.sc : nullptr;
+    s.c = s.cp ? gload(s.cp) : 0.0;
     return s;
 }
 
@@ -271,7 +273,8 @@ __device__ __forceinline__ StageSrc slot_stage(const double *slot, int n, const 
     s.a = slot + L.a();
     s.lx = slot + L.lx();
     s.lw = nullptr;
-    s.c = slot[L.c()];
+    s.cp = slot + L.c();
+    s.c = *s.cp;
     return s;
 }
 

@@ -231,6 +231,7 @@ struct Prefetch : Tiles<NX, NU> {
     double a_[NA], b_[NB];
     double av, lx, lw, c;
     d4 q[Tiles<NX, NU>::PER_WAVE];
+    bool no_qxw;
 };
 
 // Waits until every global load and store this wave issued has completed
@@ -278,35 +279,65 @@ __device__ __forceinline__ void prefetch_mats(Prefetch<T, NX, NU> &pf, const Sta
     pf.av = (tid < NX && s.a) ? gload(s.a + tid) : 0.0;
     pf.lx = (tid < NX && s.lx) ? gload(s.lx + tid) : 0.0;
     pf.lw = (tid < NU && s.lw) ? gload(s.lw + tid) : 0.0;
-    pf.c = s.c;
+    // read through the pointer into the register that holds it until the
+    // commit: a copy of an earlier load's result would wait for that load
+    pf.c = (tid == 0 && s.cp) ? gload(s.cp) : 0.0;
 }
 
-// ... and its Qx / Qxw' / Qw tiles (those of this thread's wave).
+// The phase-B tile held in prefetch slot u by wave w (wave-uniform; false if
+// the wave has fewer slots).
+template <int NX, int NU>
+__device__ __forceinline__ bool slot_tile(int w, int u, int &kind, int &ti, int &tj) {
+    using PF = Tiles<NX, NU>;
+    bool has = false;
+    kind = ti = tj = 0;
+#pragma unroll
+    for (int t = 0; t < PF::TILES; ++t) {
+        int k, a, b;
+        phaseB_tile<NX, NU>(t, k, a, b);
+        const bool hit = PF::owner(t) == w && PF::slot(t) == u;
+        kind = hit ? k : kind;
+        ti = hit ? a : ti;
+        tj = hit ? b : tj;
+        has = has || hit;
+    }
+    return has;
+}
+
+// ... and its Qx / Qxw' / Qw tiles (those of this thread's wave).  Each slot
+// register is the destination of one load sequence whose addresses depend on
+// the wave: with one sequence per tile instead, the compiler cannot see that
+// the waves' sequences exclude each other and makes a later one wait for the
+// earlier ones' loads into the same registers.  Without Q_xw the slot reads
+// Qx (in bounds) and take_q replaces it with zeros.
 template <class T, int NX, int NU>
 __device__ __forceinline__ void prefetch_q(Prefetch<T, NX, NU> &pf, const StageSrc &s) {
     using PF = Prefetch<T, NX, NU>;
-    const int w = wave();
+    const int w = wave(), c = lane() & 15;
 #pragma unroll
-    for (int t = 0; t < PF::TILES; ++t) {
-        if (PF::owner(t) != w) continue;
-        d4 q = zero4<double>();
+    for (int u = 0; u < PF::PER_WAVE; ++u) {
         int kind, ti, tj;
-        phaseB_tile<NX, NU>(t, kind, ti, tj);
-        tile_for<T>(ti, tj, [&](int r, int i, int j) {
-            if (kind == 0) q[r] = gload(s.Qx + i * NX + j);
-            else if (kind == 1) q[r] = s.Qxw ? gload(s.Qxw + j * NU + i) : 0.0;
-            else q[r] = gload(s.Qw + i * NU + j);
-        });
-        pf.q[PF::slot(t)] = q;
+        if (!slot_tile<NX, NU>(w, u, kind, ti, tj)) continue;
+        const double *base = kind == 0 ? s.Qx : kind == 1 ? (s.Qxw ? s.Qxw : s.Qx) : s.Qw;
+        const int si = kind == 0 ? NX : kind == 1 ? 1 : NU, sj = kind == 1 ? NU : 1;
+        d4 q;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) q[r] = gload(base + (16 * ti + MT<T>::row(r)) * si + (16 * tj + c) * sj);
+        pf.q[u] = q;
     }
+    pf.no_qxw = s.Qxw == nullptr;
 }
 
 // The prefetched tiles in the working precision.
 template <class T, int NX, int NU>
 __device__ __forceinline__ void take_q(v4_t<T> *qt, const Prefetch<T, NX, NU> &pf) {
+    const int w = wave();
 #pragma unroll
-    for (int u = 0; u < Tiles<NX, NU>::PER_WAVE; ++u)
-        qt[u] = v4_t<T>{(T)pf.q[u][0], (T)pf.q[u][1], (T)pf.q[u][2], (T)pf.q[u][3]};
+    for (int u = 0; u < Tiles<NX, NU>::PER_WAVE; ++u) {
+        int kind, ti, tj;
+        const bool zero = slot_tile<NX, NU>(w, u, kind, ti, tj) && kind == 1 && pf.no_qxw;
+        qt[u] = zero ? zero4<T>() : v4_t<T>{(T)pf.q[u][0], (T)pf.q[u][1], (T)pf.q[u][2], (T)pf.q[u][3]};
+    }
 }
 
 template <class T, int NX, int NU>
@@ -344,6 +375,79 @@ __device__ __forceinline__ void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
+// Value of lane N of this lane's row of 16 lanes (DPP row_newbcast; one
+// 64-bit move for a double).
+template <int N>
+__device__ __forceinline__ double row_bcast(double v) {
+    return __longlong_as_double(
+        __builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x150 + N, 0xF, 0xF, false));
+}
+template <int N>
+__device__ __forceinline__ float row_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + N, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double rsq_est(double d) { return __builtin_amdgcn_rsq(d); }
+__device__ __forceinline__ float rsq_est(float d) { return __builtin_amdgcn_rsqf(d); }
+
+// Step K of chol_inv16: eliminate column K below the pivot in [G | I].
+template <int K, class T>
+__device__ __forceinline__ void chol16_step(T (&a)[8], int i, T &sdi, int &fail) {
+    constexpr int kh = K >> 3, kc = K & 7;
+    T d = bcast_lane(a[kc], 16 * kh + K);              // pivot d_K (wave-uniform)
+    if (!(d > T(0)) || !__builtin_isfinite(d)) {
+        fail = 1;
+        d = T(1);
+    }
+    T is = rsq_est(d);
+    is = is * (T(1.5) - T(0.5) * d * is * is);
+    is = is * (T(1.5) - T(0.5) * d * is * is);
+    if (i == K) sdi = is;
+    const T f = __shfl(a[kc], 16 * kh + i, 64);       // entry (i, K) of this lane's row
+    const T m = i > K ? f * (is * is) : T(0);           // rows above the pivot keep their values
+#pragma unroll
+    for (int c = 0; c < 8; ++c) a[c] -= m * row_bcast<K>(a[c]);
+    if constexpr (K + 1 < 16) chol16_step<K + 1>(a, i, sdi, fail);
+}
+
+// chol_inv_wave for M = 16 with every lane of the wavefront at work: Gaussian
+// elimination without pivoting on the 16 x 32 matrix [G | I] turns it into
+// [D L_u' | L_u^{-1}] with G = L_u D L_u' (L_u unit lower triangular), i.e.
+// the Cholesky factor L = L_u D^{1/2} and L^{-1} = D^{-1/2} L_u^{-1}, the
+// same factorization and forward substitution as the row-per-lane sweep.
+// Lane l holds row l % 16 of [G | I], columns 8 (l / 16) .. 8 (l / 16) + 7;
+// the pivot row reaches the other lanes of each row of 16 by DPP, the pivot
+// column by one bpermute, the pivot by readlane.
+// The lane's row and column block are taken through an opaque copy: the
+// compare masks formed from them (one per step) are the same in every stage,
+// and the compiler would otherwise hoist all of them out of the caller's
+// stage loop and keep them live in scalar registers (spilled to vector lanes).
+template <class T>
+__device__ __forceinline__ int chol_inv16(T *G, T *LiT) {
+    int l = lane();
+    asm volatile("" : "+v"(l));
+    const int i = l & 15, h = l >> 4;
+    T a[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const T g = G[i * 16 + ((8 * h + c) & 15)];
+        a[c] = h < 2 ? g : (8 * (h - 2) + c == i ? T(1) : T(0));
+    }
+    int fail = 0;
+    T sdi = T(0);
+    chol16_step<0>(a, i, sdi, fail);
+    if (h >= 2) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int j = 8 * (h - 2) + c;
+            const T v = a[c] * sdi;
+            G[i * 16 + j] = v;       // L^{-1}[i][j]
+            LiT[j * 16 + i] = v;     // L^{-T}[j][i]
+        }
+    }
+    return fail;
+}
+
 // Cholesky factorization G = L L' ("a factorization of G", Alg. 1) and the
 // inverse L^{-1}, by one wavefront.  Lane i holds row i of G / L in
 // registers; entries of other rows are broadcast with readlane, which places
@@ -360,6 +464,7 @@ __device__ __forceinline__ void wave_fence() {
 template <int M, class T>
 __device__ __forceinline__ int chol_inv_wave(T *G, T *LiT) {
     static_assert(M <= 64, "one wavefront factors at most 64 rows");
+    if constexpr (M == 16) return chol_inv16(G, LiT);
     const int ln = threadIdx.x & 63;
     T g[M];
 #pragma unroll
@@ -765,8 +870,12 @@ __device__ void mfma_pass(MSmem<T, NX, NU, RED, SOLVE> &S, Get get, int count, i
         //      (SOLVE) K = -L^{-T} Y, k = L^{-T} z;
         //      Psi = g_x - Y'z, (RED) v += V'a + X'z, cbar -= z'z/2
         {
+            // the wait is on every path: where it is skipped, the compiler
+            // takes the prefetch loads as still outstanding at the next
+            // stage and waits for them (and for every store behind them)
+            // when their registers are reused
+            wait_global();
             if (s > 0) {
-                wait_global();
                 commit_stage(S, pf);
                 take_q(qt, pf);
             }
