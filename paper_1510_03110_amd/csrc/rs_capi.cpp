@@ -716,27 +716,35 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
     P->last_probs.reserve(nprob);
     P->pads_host.reserve(P->pad_inst.size());
     P->last_pads.reserve(P->pad_inst.size());
-    alloc_staging(P);
     *out = P;
     return RS_OK;
 }
 
+// A plan handed to the caller takes its pinned staging now, so that no call
+// on it allocates.  (The plans that rs_plan_ring_update builds only for their
+// tables take none: pinned allocation and release synchronize the device,
+// which would serialize every serving launch.)
+static rs_status with_staging(rs_status s, rs_plan *out) {
+    if (s == RS_OK) alloc_staging(*out);
+    return s;
+}
+
 rs_status rs_plan_create(int32_t count, const int32_t *dims, const rs_options *opt, rs_plan *out) {
-    return plan_create(count, dims, 3, opt, out);
+    return with_staging(plan_create(count, dims, 3, opt, out), out);
 }
 
 rs_status rs_plan_create_ex(int32_t count, const int32_t *dims5, const rs_options *opt, rs_plan *out) {
-    return plan_create(count, dims5, 5, opt, out);
+    return with_staging(plan_create(count, dims5, 5, opt, out), out);
 }
 
 rs_status rs_plan_create_ring(int32_t count, const int32_t *dims8, const rs_options *opt, rs_plan *out) {
-    return plan_create(count, dims8, 8, opt, out);
+    return with_staging(plan_create(count, dims8, 8, opt, out), out);
 }
 
 rs_status rs_plan_create_split(int32_t count, const int32_t *dims, const int32_t *leaf_off, const int32_t *leaf_len,
                                const int32_t *branch_off, const int32_t *branch, const rs_options *opt, rs_plan *out) {
     if (!leaf_off || !leaf_len || !branch_off || !branch) return RS_ERR_ARG;
-    return plan_create(count, dims, 3, opt, out, leaf_off, leaf_len, branch_off, branch);
+    return with_staging(plan_create(count, dims, 3, opt, out, leaf_off, leaf_len, branch_off, branch), out);
 }
 
 rs_status rs_plan_ring_update(rs_plan P, const int32_t *dims8) {
