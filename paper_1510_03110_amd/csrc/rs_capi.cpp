@@ -183,17 +183,21 @@ void build_instance(Group &g, int inst, int N, int Ns, int b, int top_max, std::
 // of the window leaves the interior leaves unchanged.  The first leaf runs
 // from the window start to the second boundary after it (to the first if the
 // start is on a boundary), so that every leaf but the last has at least Ns
-// stages (Ns nu >= nx); the last leaf ends with the window.  Interior leaf a
+// stages (Ns nu >= nx); with rank-revealing master stages (merge_first
+// false), where a leaf of any length is reduced, it ends at the first
+// boundary, which halves its length on average.  The last leaf ends with the
+// window.  Interior leaf a
 // (stages [a Ns, (a+1) Ns)) keeps its stored factorization in ring block
 // a mod ring_blocks; the first and last leaves use areas of their own.
 // Interior leaves with a in [lo, hi) are marked LEAF_REUSE.
 // Stage offsets are relative to the instance's record base `rbase` (stages);
 // `mbase` is its first M1 cache block.
 void build_instance_ring(Group &g, int inst, int N, int Ns, int b, int top_max, int64_t start, int64_t lo,
-                         int64_t hi, int64_t rbase, int mbase, std::vector<Tmp> &tmp) {
+                         int64_t hi, int64_t rbase, int mbase, bool merge_first, std::vector<Tmp> &tmp) {
     const int sps = g.shape->scratch_per_stage;
     const int nblocks = ring_blocks(N, Ns);
-    const int64_t first_end = (start / Ns + (start % Ns == 0 ? 1 : 2)) * (int64_t)Ns, end = start + N;
+    const int64_t first_end = (start / Ns + ((start % Ns == 0 || !merge_first) ? 1 : 2)) * (int64_t)Ns,
+                  end = start + N;
     const int64_t edge_first = rbase + (int64_t)nblocks * Ns, edge_last = edge_first + 2 * (int64_t)Ns;
     if (end <= first_end) {
         LeafItem lf{inst, 0, N, LEAF_LAST | LEAF_TOP, -1, -1, edge_first * sps};
@@ -547,7 +551,8 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
             if (P->receding) {
                 const int N = dims[3 * inst + 2], Ns = P->inst_Ns[inst];
                 build_instance_ring(g, inst, N, Ns, P->inst_branch[inst], P->inst_branch[inst], P->inst_start[inst],
-                                    P->inst_lo[inst], P->inst_hi[inst], g.ring_stages, g.ring_m1, tmp);
+                                    P->inst_lo[inst], P->inst_hi[inst], g.ring_stages, g.ring_m1, !P->rank_reveal,
+                                    tmp);
                 g.ring_stages += ring_stages(N, Ns);
                 g.ring_m1 += ring_blocks(N, Ns);
                 // a window has between N/Ns - 1 and N/Ns + 2 leaves

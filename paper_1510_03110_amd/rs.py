@@ -201,10 +201,11 @@ def rs_mhe_to_uftoc(mhe, probs, stream_ptr=None, info_ptr=None):
     _check(library().rs_mhe_to_uftoc(len(mhe), mhe, probs, stream_ptr, info_ptr), "rs_mhe_to_uftoc")
 
 
-def ring_current_leaves(start, N, Ns):
+def ring_current_leaves(start, N, Ns, rank_reveal=False):
     """Absolute interior leaves [lo, hi) whose stored factorization a
-    receding-horizon call with window start `start` leaves current."""
-    first_end = (start // Ns + (1 if start % Ns == 0 else 2)) * Ns
+    receding-horizon call with window start `start` leaves current (plans
+    with RS_PLAN_RANK_REVEAL end the first leaf at the first boundary)."""
+    first_end = (start // Ns + (1 if (start % Ns == 0 or rank_reveal) else 2)) * Ns
     if start + N <= first_end:
         return 0, 0
     return first_end // Ns, (start + N - 1) // Ns

@@ -190,17 +190,29 @@ class Lane:
         self.members = []
         self.event = None
         self.info_host = None     # pinned copy of the status words of the launch in flight
+        self.t_launch = 0.0       # host time of the launch in flight
+        self.launches = 0
+        self.requests = 0
+        self.busy_s = 0.0         # launch to retirement, summed
 
 
 class ServingEngine:
     """Continuous-batching solver for receding-horizon sessions."""
 
-    def __init__(self, precision=rs.RS_FP64, lanes=2, max_batch=1 << 30, hbm_fraction=0.9, tuner=None,
-                 device="cuda", record=False, timing=False, record_every=0):
+    def __init__(self, precision=rs.RS_FP64, lanes=3, max_batch=1 << 30, hbm_fraction=0.9, tuner=None,
+                 device="cuda", record=False, timing=False, record_every=0, rank_reveal=False):
         import torch
         self.torch = torch
         self.device = device
         self.precision = precision
+        # rank-revealing master stages let a window's first leaf end at the
+        # first leaf boundary (1..Ns stages instead of Ns..2Ns-1), which
+        # halves the leaf chain that every request factors again, but every
+        # reduction then ends with a pivoted factorization (also on the
+        # master levels' critical path); measured, the two cancel for the
+        # default sessions, so plain master stages are the default
+        self.rank_reveal = rank_reveal
+        self.plan_flags = rs.RS_PLAN_RANK_REVEAL if rank_reveal else 0
         self.max_batch = max_batch
         self.tuner = tuner or Tuner()
         free, total = torch.cuda.mem_get_info()
@@ -226,7 +238,8 @@ class ServingEngine:
     # ------------------------------------------------------------ admission
     def _workspace_per_instance(self, nx, nu, N):
         Ns, br = self.tuner.choose(nx, nu, N, self.precision)
-        plan = rs.rs_plan_create_ring([(nx, nu, N, Ns, br, 0, 0, 0)], precision=self.precision)
+        plan = rs.rs_plan_create_ring([(nx, nu, N, Ns, br, 0, 0, 0)], precision=self.precision,
+                                      flags=self.plan_flags)
         try:
             return rs.rs_plan_workspace_size(plan)
         finally:
@@ -247,12 +260,29 @@ class ServingEngine:
         s = Session(len(self.sessions), prob, self.device)
         # a session always runs on the same lane, whose workspace keeps its
         # stored factorization between requests
-        s.lane = s.sid % len(self.lanes)
+        s.lane = self._pick_lane(s)
         self.lanes[s.lane].sessions.append(s)
         self.sessions.append(s)
         self.used += need
         self.version += 1
         return s.sid
+
+    def _pick_lane(self, s):
+        """Lane of a new session.  A launch runs its shape groups one after
+        another on the lane's stream, and the kernels of a group are chains
+        of dependent stages on a few workgroups; lanes that hold one shape
+        each run those chains side by side and keep every launch short.  So:
+        an empty lane if there is one, else the least loaded lane among
+        those that serve this shape only, else the least loaded lane (load =
+        sum of N n_x^2, the size of a solve pass)."""
+        key = (s.nx, s.nu)
+        load = [sum(t.N * t.nx * t.nx for t in lane.sessions) for lane in self.lanes]
+        empty = [i for i, lane in enumerate(self.lanes) if not lane.sessions]
+        if empty:
+            return empty[0]
+        same = [i for i, lane in enumerate(self.lanes) if all((t.nx, t.nu) == key for t in lane.sessions)]
+        pool = same or range(len(self.lanes))
+        return min(pool, key=lambda i: load[i])
 
     # --------------------------------------------------------------- plans
     def _dims(self, lane):
@@ -270,7 +300,7 @@ class ServingEngine:
         torch = self.torch
         if lane.plan is not None:
             rs.rs_plan_destroy(lane.plan)
-        lane.plan = rs.rs_plan_create_ring(self._dims(lane), precision=self.precision)
+        lane.plan = rs.rs_plan_create_ring(self._dims(lane), precision=self.precision, flags=self.plan_flags)
         lane.work_bytes = rs.rs_plan_workspace_size(lane.plan)
         lane.work = torch.empty(lane.work_bytes + 256, dtype=torch.uint8, device=self.device)
         lane.work_ptr = (lane.work.data_ptr() + 255) // 256 * 256
@@ -318,11 +348,14 @@ class ServingEngine:
             lane.info_host.copy_(lane.info, non_blocking=True)
         for s, _ in lane.members:
             Ns, _br = self.tuner.choose(s.nx, s.nu, s.N, self.precision)
-            s.current = rs.ring_current_leaves(s.t_abs, s.N, Ns)
+            s.current = rs.ring_current_leaves(s.t_abs, s.N, Ns, rank_reveal=self.rank_reveal)
         self.launches += 1
         self.batch_sizes.append(len(ready))
         lane.event = torch.cuda.Event()
         lane.event.record(lane.stream)
+        lane.t_launch = h0
+        lane.launches += 1
+        lane.requests += len(ready)
         self.host_s += time.perf_counter() - h0
 
     def _complete(self, lane, now):
@@ -357,6 +390,18 @@ class ServingEngine:
                          window=s.window_host()))
         lane.members = []
         lane.event = None
+        lane.busy_s += time.perf_counter() - lane.t_launch
+
+    def lane_stats(self):
+        """Per lane: shapes, sessions, launches, mean batch and mean time from
+        launch to retirement (ms)."""
+        out = []
+        for lane in self.lanes:
+            out.append({"shapes": sorted({"%dx%d" % (t.nx, t.nu) for t in lane.sessions}),
+                        "sessions": len(lane.sessions), "launches": lane.launches,
+                        "mean_batch": round(lane.requests / lane.launches, 2) if lane.launches else None,
+                        "ms_per_launch": round(1e3 * lane.busy_s / lane.launches, 3) if lane.launches else None})
+        return out
 
     def poll(self, now):
         """Retire finished launches, then launch ready sessions on idle lanes."""
@@ -397,7 +442,7 @@ class ServingEngine:
                 "mean_batch": round(float(np.mean(sizes)), 2) if sizes else None,
                 "sessions": len(self.sessions), "rejected_sessions": self.rejected,
                 "hbm_projected_gb": round(self.used / 1e9, 3), "hbm_budget_gb": round(self.budget / 1e9, 3),
-                "host_launch_s": round(self.host_s, 3),
+                "host_launch_s": round(self.host_s, 3), "lanes": self.lane_stats(),
                 "kernel_ms_total": {k: round(v, 1) for k, v in self.kernel_ms.items()} if self.timing else None}
 
     def close(self):
@@ -459,7 +504,9 @@ def main(argv=None):
     ap.add_argument("--Nmin", type=int, default=64)
     ap.add_argument("--Nmax", type=int, default=4096)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="mixed")
-    ap.add_argument("--lanes", type=int, default=2)
+    ap.add_argument("--lanes", type=int, default=3)
+    ap.add_argument("--rank-reveal", action="store_true",
+                    help="rank-revealing master stages (a window's first leaf then ends at the first boundary)")
     ap.add_argument("--seed", type=int, default=W.seed_for(3))
     ap.add_argument("--timing", action="store_true", help="report device time per kernel kind")
     ap.add_argument("--Ns", type=int, default=32, help="leaf length for every session (0: the tuner's choice)")
@@ -470,7 +517,8 @@ def main(argv=None):
     nxs = [int(v) for v in args.nx.split(",")]
     prec = rs.RS_FP64 if args.precision == "fp64" else rs.RS_MIXED_FP32
     tuner = FixedChoice(args.Ns, args.branch) if args.Ns > 0 else None
-    eng = ServingEngine(precision=prec, lanes=args.lanes, timing=args.timing, tuner=tuner)
+    eng = ServingEngine(precision=prec, lanes=args.lanes, timing=args.timing, tuner=tuner,
+                        rank_reveal=args.rank_reveal)
     shapes = []
     for i in range(args.sessions):
         nx = nxs[int(rng.integers(0, len(nxs)))]
@@ -485,6 +533,8 @@ def main(argv=None):
     eng.run(warm)
     torch.cuda.synchronize()
     eng.lat, eng.done, eng.failed, eng.kernel_ms, eng.host_s = [], 0, 0, {}, 0.0
+    for lane in eng.lanes:
+        lane.launches, lane.requests, lane.busy_s = 0, 0, 0.0
     trace = poisson_trace(args.rate, args.seconds, len(shapes), pools, shapes, args.seed + 2)
     out = eng.run(trace)
     out.update({"rate_req_s": args.rate, "precision": args.precision,

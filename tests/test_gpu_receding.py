@@ -118,5 +118,5 @@ def test_receding_horizon_reuse(prec, nx, nu, N, Ns, rr):
                     np.testing.assert_array_equal(out[k].cpu().numpy(), out2[k].cpu().numpy())
             finally:
                 rs.rs_plan_destroy(plan)
-        lo, hi = rs.ring_current_leaves(s, N, Ns)
+        lo, hi = rs.ring_current_leaves(s, N, Ns, rank_reveal=rr)
     rs.rs_plan_destroy(keep)

@@ -274,19 +274,22 @@ def test_large_block_shapes_plan_factored():
         assert e.value.status == rs.RS_ERR_UNSUPPORTED
 
 
+@pytest.mark.parametrize("rr", [False, True])
 @pytest.mark.parametrize("N,Ns", [(200, 16), (37, 8), (64, 16), (20, 16)])
-def test_receding_horizon_plan_layout(N, Ns):
+def test_receding_horizon_plan_layout(N, Ns, rr):
     """Receding-horizon plans: leaves on absolute multiples of Ns (first leaf
-    at least Ns stages, last leaf ends with the window), the reuse range
-    marks exactly the interior leaves an earlier window left current, each
-    interior leaf keeps its record offset across windows, and the workspace
-    size does not depend on the window position."""
+    at least Ns stages, or, with rank-revealing master stages, ending at the
+    first boundary; last leaf ends with the window), the reuse range marks
+    exactly the interior leaves an earlier window left current, each interior
+    leaf keeps its record offset across windows, and the workspace size does
+    not depend on the window position."""
     nx, nu = 32, 16
+    flags = rs.RS_PLAN_RANK_REVEAL if rr else 0
     sizes, where = set(), {}
     prev = (0, 0)
     for start in list(range(0, 40)) + [1000, 1001]:
         lo, hi = prev
-        p = rs.rs_plan_create_ring([(nx, nu, N, Ns, 4, start, lo, hi)])
+        p = rs.rs_plan_create_ring([(nx, nu, N, Ns, 4, start, lo, hi)], flags=flags)
         try:
             sizes.add(rs.rs_plan_workspace_size(p))
             leaves = rs.rs_plan_export(p, 0)      # inst, t0, len, flags, slot, scratch, group
@@ -296,6 +299,8 @@ def test_receding_horizon_plan_layout(N, Ns):
         assert np.all(leaves[1:, 1] == np.cumsum(leaves[:-1, 2]))
         if len(leaves) == 1:
             assert leaves[0, 3] == 3                       # LEAF_LAST | LEAF_TOP
+        elif rr:
+            assert 1 <= leaves[0, 2] <= Ns and (start + leaves[0, 2]) % Ns == 0 and leaves[0, 3] == 0
         else:
             assert Ns <= leaves[0, 2] < 2 * Ns and leaves[0, 3] == 0
             assert leaves[-1, 3] == 1 and (start + leaves[-1, 1]) % Ns == 0 and 1 <= leaves[-1, 2] <= Ns
@@ -306,9 +311,9 @@ def test_receding_horizon_plan_layout(N, Ns):
                 if a in where:
                     assert where[a] == lf[5]                  # same record offset
                 where[a] = lf[5]
-            cur = rs.ring_current_leaves(start, N, Ns)
+            cur = rs.ring_current_leaves(start, N, Ns, rank_reveal=rr)
             assert cur == ((start + int(leaves[1, 1])) // Ns, (start + int(leaves[-1, 1])) // Ns)
-        prev = rs.ring_current_leaves(start, N, Ns)
+        prev = rs.ring_current_leaves(start, N, Ns, rank_reveal=rr)
         if start == 39:
             prev = (0, 0)                                  # a jump: nothing current
     assert len(sizes) == 1
