@@ -20,8 +20,12 @@ The printed formulas place S without these transposes, which is dimensionally
 consistent only if S is read as n_y x n_w; the expressions above are the ones
 derived from the cost and coincide with the printed ones when S = 0.
 
-The UFTOC noise dimension is n_x at stage 0 and n_w afterwards; this module
-requires n_w = n_x so that all stages share one dimension.
+The UFTOC noise dimension is n_x at stage 0 and n_w afterwards, while P(N)
+has one input dimension n_u for all stages.  Reading: every stage's input
+is padded to n_u = max(n_x, n_w) with inputs that act on nothing (zero
+columns of B and Q_xw, an identity block of Q_w, zero l_w).  They are
+decoupled from the rest and strictly convex, so they are zero at the
+optimum and the other unknowns are those of the unpadded problem.
 """
 import numpy as np
 
@@ -30,19 +34,34 @@ def mhe_to_uftoc(A, B, a, C, d, y, xtil0, Ptil0, wtil, vtil, Qw_cov, Qv_cov, Qwv
     """Arrays indexed by the MHE sample k = 0..Nmhe.  Returns a UFTOC dict."""
     Nm = len(A) - 1
     nx, nw = A[0].shape[0], B[0].shape[1]
-    if nw != nx:
-        raise ValueError("this conversion needs n_w == n_x")
+    nu = max(nx, nw)
     N = Nm + 2
+
+    def cols(M, n):          # M (rows x n) followed by zero columns up to nu
+        out = np.zeros((M.shape[0], nu))
+        out[:, :n] = M
+        return out
+
+    def weight(M, n):        # blockdiag(M, I) of size nu
+        out = np.eye(nu)
+        out[:n, :n] = M
+        return out
+
+    def vec(v, n):
+        out = np.zeros(nu)
+        out[:n] = v
+        return out
+
     prob = {k: [] for k in ("Qx", "Qw", "Qxw", "A", "B", "a", "lx", "lw", "c")}
     # stage 0: arrival cost as noise cost on w_{-1}
     prob["Qx"].append(np.zeros((nx, nx)))
-    prob["Qw"].append(np.linalg.inv(Ptil0))
-    prob["Qxw"].append(np.zeros((nx, nx)))
+    prob["Qw"].append(weight(np.linalg.inv(Ptil0), nx))
+    prob["Qxw"].append(np.zeros((nx, nu)))
     prob["A"].append(np.eye(nx))
-    prob["B"].append(np.eye(nx))
+    prob["B"].append(cols(np.eye(nx), nx))
     prob["a"].append(np.zeros(nx))
     prob["lx"].append(np.zeros(nx))
-    prob["lw"].append(np.zeros(nx))
+    prob["lw"].append(np.zeros(nu))
     prob["c"].append(0.0)
     for k in range(Nm + 1):
         ny = C[k].shape[0]
@@ -57,13 +76,13 @@ def mhe_to_uftoc(A, B, a, C, d, y, xtil0, Ptil0, wtil, vtil, Qw_cov, Qv_cov, Qwv
         yt = y[k] - d[k] - vtil[k]
         Ck = C[k]
         prob["Qx"].append(Ck.T @ V @ Ck)
-        prob["Qxw"].append(-Ck.T @ S.T)
-        prob["Qw"].append(W)
+        prob["Qxw"].append(cols(-Ck.T @ S.T, nw))
+        prob["Qw"].append(weight(W, nw))
         prob["lx"].append(Ck.T @ (S.T @ wtil[k] - V @ yt))
-        prob["lw"].append(S @ yt - W @ wtil[k])
+        prob["lw"].append(vec(S @ yt - W @ wtil[k], nw))
         prob["c"].append(0.5 * wtil[k] @ W @ wtil[k] - wtil[k] @ S @ yt + 0.5 * yt @ V @ yt)
         prob["A"].append(A[k])
-        prob["B"].append(B[k])
+        prob["B"].append(cols(B[k], nw))
         prob["a"].append(a[k])
     out = {k: np.array(v) for k, v in prob.items()}
     out["QxN"] = np.zeros((nx, nx))

@@ -151,55 +151,65 @@ def test_not_spd_is_reported():
         riccati.solve(prob)
 
 
-def _mhe_case(nx, ny, Nm, seed):
+def _mhe_case(nx, ny, Nm, seed, nw=None):
+    nw = nx if nw is None else nw
     rng = np.random.default_rng(seed)
     A0 = W._spectral_scale(rng.standard_normal((nx, nx)))
     A = [A0 + 0.05 * rng.standard_normal((nx, nx)) for _ in range(Nm + 1)]
-    B = [rng.standard_normal((nx, nx)) / np.sqrt(nx) for _ in range(Nm + 1)]
+    B = [rng.standard_normal((nx, nw)) / np.sqrt(nx) for _ in range(Nm + 1)]
     a = [0.1 * rng.standard_normal(nx) for _ in range(Nm + 1)]
     C = [rng.standard_normal((ny, nx)) for _ in range(Nm + 1)]
     d = [0.1 * rng.standard_normal(ny) for _ in range(Nm + 1)]
     y = [rng.standard_normal(ny) for _ in range(Nm + 1)]
-    wtil = [0.1 * rng.standard_normal(nx) for _ in range(Nm + 1)]
+    wtil = [0.1 * rng.standard_normal(nw) for _ in range(Nm + 1)]
     vtil = [0.1 * rng.standard_normal(ny) for _ in range(Nm + 1)]
 
     def spd(k):
         M = rng.standard_normal((k, k))
         return M @ M.T / k + 0.5 * np.eye(k)
 
-    Qw = [spd(nx) for _ in range(Nm + 1)]
+    Qw = [spd(nw) for _ in range(Nm + 1)]
     Qv = [spd(ny) for _ in range(Nm + 1)]
     xtil0 = rng.standard_normal(nx)
     P0 = spd(nx)
     return A, B, a, C, d, y, xtil0, P0, wtil, vtil, Qw, Qv
 
 
-@pytest.mark.parametrize("nx,ny,Nm", [(3, 2, 6), (4, 4, 20), (2, 1, 0)])
-def test_oracle_vs_rts_smoother(nx, ny, Nm):
+@pytest.mark.parametrize("nx,ny,Nm,nw", [(3, 2, 6, 3), (4, 4, 20, 4), (2, 1, 0, 2), (4, 2, 9, 2), (3, 2, 7, 5),
+                                         (5, 3, 12, 1)])
+def test_oracle_vs_rts_smoother(nx, ny, Nm, nw):
     """MHE with uncorrelated noise (S = 0): the UFTOC solution of the paper's
-    conversion equals the RTS-smoothed state means x_0..x_{Nmhe+1}."""
-    args = _mhe_case(nx, ny, Nm, seed=nx * 100 + Nm)
+    conversion equals the RTS-smoothed state means x_0..x_{Nmhe+1}, also with
+    a noise dimension n_w other than n_x (inputs padded to max(n_x, n_w); the
+    padded inputs come out zero)."""
+    args = _mhe_case(nx, ny, Nm, seed=nx * 100 + Nm + nw, nw=nw)
     prob = mhe.mhe_to_uftoc(*args)
+    assert prob["B"].shape[2] == max(nx, nw)
     sol = riccati.solve(prob)
     ms = mhe.rts_smoother(*args)
     # UFTOC state t is the MHE state k = t - 1 (t = 1..N)
     np.testing.assert_allclose(sol["x"][1:], ms, rtol=1e-10, atol=1e-10)
     np.testing.assert_allclose(sol["x"][0], args[6], rtol=0, atol=0)
+    # the padded inputs: stage 0 has n_x real inputs, the others n_w
+    assert np.abs(sol["w"][0, nx:]).max(initial=0.0) <= 1e-12
+    assert np.abs(sol["w"][1:, nw:]).max(initial=0.0) <= 1e-12
 
 
-def test_mhe_conversion_correlated_noise_matches_direct_map():
+@pytest.mark.parametrize("nw", [2, 1, 3])
+def test_mhe_conversion_correlated_noise_matches_direct_map(nw):
     """Correlated noise (S != 0): the converted UFTOC optimum equals the
     minimiser of the MHE objective of eq. org_mhe written directly over
-    (x_0, w_0..w_Nmhe) and solved by dense least squares."""
+    (x_0, w_0..w_Nmhe) and solved by dense least squares, for noise
+    dimensions below, equal to and above n_x."""
     nx, ny, Nm = 2, 2, 3
     rng = np.random.default_rng(42)
-    A, B, a, C, d, y, xtil0, P0, wtil, vtil, Qw, Qv = _mhe_case(nx, ny, Nm, seed=3)
-    Qwv = [0.2 * rng.standard_normal((nx, ny)) for _ in range(Nm + 1)]
+    A, B, a, C, d, y, xtil0, P0, wtil, vtil, Qw, Qv = _mhe_case(nx, ny, Nm, seed=3, nw=nw)
+    Qwv = [0.2 * rng.standard_normal((nw, ny)) for _ in range(Nm + 1)]
     prob = mhe.mhe_to_uftoc(A, B, a, C, d, y, xtil0, P0, wtil, vtil, Qw, Qv, Qwv)
     sol = riccati.solve(prob)
     # direct: unknowns u = (x0, w_0..w_Nm); x_k affine in u; cost = sum of
     # squared whitened residuals -> linear least squares
-    nvar = nx + (Nm + 1) * nx
+    nvar = nx + (Nm + 1) * nw
     xs = []          # x_k = X_k u + x_k^c
     Xk, xk = np.zeros((nx, nvar)), np.zeros(nx)
     Xk[:, :nx] = np.eye(nx)
@@ -213,8 +223,8 @@ def test_mhe_conversion_correlated_noise_matches_direct_map():
         xs.append((Xk.copy(), xk.copy()))
         cov = np.block([[Qw[k], Qwv[k]], [Qwv[k].T, Qv[k]]])
         Lc = np.linalg.cholesky(np.linalg.inv(cov))
-        Wsel = np.zeros((nx, nvar))
-        Wsel[:, nx + k * nx: nx + (k + 1) * nx] = np.eye(nx)
+        Wsel = np.zeros((nw, nvar))
+        Wsel[:, nx + k * nw: nx + (k + 1) * nw] = np.eye(nw)
         # [w - wtil; v - vtil] with v = y - C x - d
         Rk = np.vstack([Wsel, -C[k] @ Xk])
         ck = np.concatenate([wtil[k], vtil[k] - (y[k] - d[k] - C[k] @ xk)])
