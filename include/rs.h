@@ -286,18 +286,19 @@ rs_status rs_plan_ring_update(rs_plan plan, const int32_t *dims8);
  * The process noise has the state dimension (n_w = n_x).
  */
 typedef struct rs_mhe {
-    int32_t nx, ny, Nmhe, reserved;
+    int32_t nx, ny, Nmhe;
+    int32_t nw;                          /* process noise dimension; 0 = nx          */
     const double *A;    int64_t sA;      /* nx*nx                                  */
-    const double *B;    int64_t sB;      /* nx*nx (n_w = n_x)                      */
+    const double *B;    int64_t sB;      /* nx*nw noise input matrix                */
     const double *a;    int64_t sa;      /* nx; NULL = zero                        */
     const double *C;    int64_t sC;      /* ny*nx                                  */
     const double *d;    int64_t sd;      /* ny; NULL = zero                        */
     const double *y;    int64_t sy;      /* ny measurements                        */
-    const double *wtil; int64_t swtil;   /* nx; NULL = zero                        */
+    const double *wtil; int64_t swtil;   /* nw; NULL = zero                        */
     const double *vtil; int64_t svtil;   /* ny; NULL = zero                        */
-    const double *Qw;   int64_t sQw;     /* nx*nx process noise covariance, SPD     */
+    const double *Qw;   int64_t sQw;     /* nw*nw process noise covariance, SPD     */
     const double *Qv;   int64_t sQv;     /* ny*ny measurement noise covariance      */
-    const double *Qwv;  int64_t sQwv;    /* nx*ny cross covariance; NULL = zero     */
+    const double *Qwv;  int64_t sQwv;    /* nw*ny cross covariance; NULL = zero     */
     const double *xtil0;                 /* nx                                     */
     const double *Ptil0;                 /* nx*nx, SPD                             */
 } rs_mhe;
@@ -310,9 +311,14 @@ typedef struct rs_mhe {
  * the inverse joint noise covariance; zero terminal cost).  Written: Qx, Qw,
  * Qxw (if non-NULL), A, B (blocks of out[i]'s strides), a, lx, lw, c, QxN,
  * lN, cN and x0 (= xtil0), through out[i]'s pointers; out[i].nx = nx,
- * out[i].nu = nx, out[i].N = Nmhe + 2.  The result is then solved with
- * rs_batch_solve; x_t of the solution is the estimate of x_{t-1}.
- * Asynchronous on `stream`.  nx + ny <= 48.  A covariance that is not
+ * out[i].nu = max(nx, nw), out[i].N = Nmhe + 2.  The stage-0 noise has nx
+ * components and the samples' nw, so every stage's input is padded to
+ * max(nx, nw) with inputs that act on nothing (zero columns of B and Qxw,
+ * an identity block of Qw, zero lw); they come out zero in the solution.
+ * The result is then solved with rs_batch_solve; x_t of the solution is the
+ * estimate of x_{t-1} and w_{t} (t >= 1, first nw components) the noise
+ * estimate of sample t - 1.  Asynchronous on `stream`.  nx <= 48 and
+ * nw + ny <= 48.  A covariance that is not
  * positive definite sets info_dev[2i] = RS_ERR_NOT_SPD, info_dev[2i+1] = k
  * (-1 for Ptil0) when info_dev is given.  Errors: RS_ERR_ARG (sizes, NULL
  * required pointers, Qwv without an out.Qxw array).

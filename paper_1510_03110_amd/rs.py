@@ -42,7 +42,7 @@ class rs_problem(ctypes.Structure):
 
 class rs_mhe(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("Nmhe", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)] + \
+                ("nw", ctypes.c_int32)] + \
                [f for k in ("A", "B", "a", "C", "d", "y", "wtil", "vtil", "Qw", "Qv", "Qwv")
                 for f in ((k, _P), ("s" + k, ctypes.c_int64))] + \
                [("xtil0", _P), ("Ptil0", _P)]

@@ -271,13 +271,15 @@ def instance_to_numpy(batch, i):
     return out
 
 
-def mhe_problem(nx, ny, Nm, seed, correlated=False):
-    """Seeded linear-Gaussian MHE problem with samples k = 0..Nm (n_w = n_x):
-    A_k = A + 0.05 N(0,1) (A scaled to spectral radius 0.95), B_k, C_k N(0,1)
-    (B_k / sqrt(nx)), small affine and nominal terms, measurements N(0,1),
-    covariances M M'/k + 0.5 I and, if `correlated`, a cross covariance
-    0.2 N(0,1) / sqrt(max(nx, ny)) (small enough for the joint covariance to
+def mhe_problem(nx, ny, Nm, seed, correlated=False, nw=None):
+    """Seeded linear-Gaussian MHE problem with samples k = 0..Nm and process
+    noise of dimension nw (default n_x): A_k = A + 0.05 N(0,1) (A scaled to
+    spectral radius 0.95), B_k (n_x x n_w), C_k N(0,1) (B_k / sqrt(nx)),
+    small affine and nominal terms, measurements N(0,1), covariances
+    M M'/k + 0.5 I and, if `correlated`, a cross covariance
+    0.2 N(0,1) / sqrt(max(nw, ny)) (small enough for the joint covariance to
     stay positive definite).  Returns a dict of numpy arrays with a leading sample axis."""
+    nw = nx if nw is None else nw
     rng = np.random.default_rng(seed)
     A0 = _spectral_scale(rng.standard_normal((nx, nx)))
 
@@ -288,17 +290,17 @@ def mhe_problem(nx, ny, Nm, seed, correlated=False):
     K = Nm + 1
     p = dict(
         A=A0[None] + 0.05 * rng.standard_normal((K, nx, nx)),
-        B=rng.standard_normal((K, nx, nx)) / math.sqrt(nx),
+        B=rng.standard_normal((K, nx, nw)) / math.sqrt(nx),
         a=0.1 * rng.standard_normal((K, nx)),
         C=rng.standard_normal((K, ny, nx)),
         d=0.1 * rng.standard_normal((K, ny)),
         y=rng.standard_normal((K, ny)),
-        wtil=0.1 * rng.standard_normal((K, nx)),
+        wtil=0.1 * rng.standard_normal((K, nw)),
         vtil=0.1 * rng.standard_normal((K, ny)),
-        Qw=spd(nx, K),
+        Qw=spd(nw, K),
         Qv=spd(ny, K),
         xtil0=rng.standard_normal(nx),
         Ptil0=spd(nx, 1)[0],
     )
-    p["Qwv"] = 0.2 * rng.standard_normal((K, nx, ny)) / math.sqrt(max(nx, ny)) if correlated else None
+    p["Qwv"] = 0.2 * rng.standard_normal((K, nw, ny)) / math.sqrt(max(nw, ny)) if correlated else None
     return p

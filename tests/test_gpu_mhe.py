@@ -27,7 +27,8 @@ def _rs():
 
 def _convert(torch, rs, m, invariant_cov=False):
     """Device conversion of the MHE dict m; returns (device UFTOC dict, info)."""
-    nx, ny = m["A"].shape[1], m["C"].shape[1]
+    nx, ny, nw = m["A"].shape[1], m["C"].shape[1], m["B"].shape[2]
+    nu = max(nx, nw)
     Nm = m["A"].shape[0] - 1
     N = Nm + 2
     f64 = dict(device="cuda", dtype=torch.float64)
@@ -35,18 +36,18 @@ def _convert(torch, rs, m, invariant_cov=False):
     if invariant_cov:
         for k in ("Qw", "Qv"):
             dev[k] = dev[k][:1].contiguous()
-    out = dict(Qx=torch.full((N, nx, nx), np.nan, **f64), Qw=torch.full((N, nx, nx), np.nan, **f64),
-               Qxw=torch.full((N, nx, nx), np.nan, **f64), A=torch.full((N, nx, nx), np.nan, **f64),
-               B=torch.full((N, nx, nx), np.nan, **f64), a=torch.full((N, nx), np.nan, **f64),
-               lx=torch.full((N, nx), np.nan, **f64), lw=torch.full((N, nx), np.nan, **f64),
+    out = dict(Qx=torch.full((N, nx, nx), np.nan, **f64), Qw=torch.full((N, nu, nu), np.nan, **f64),
+               Qxw=torch.full((N, nx, nu), np.nan, **f64), A=torch.full((N, nx, nx), np.nan, **f64),
+               B=torch.full((N, nx, nu), np.nan, **f64), a=torch.full((N, nx), np.nan, **f64),
+               lx=torch.full((N, nx), np.nan, **f64), lw=torch.full((N, nu), np.nan, **f64),
                c=torch.full((N,), np.nan, **f64), QxN=torch.full((nx, nx), np.nan, **f64),
                lN=torch.full((nx,), np.nan, **f64), cN=torch.full((1,), np.nan, **f64),
                x0=torch.full((nx,), np.nan, **f64))
     mm = (rs.rs_mhe * 1)()
     q = mm[0]
-    q.nx, q.ny, q.Nmhe = nx, ny, Nm
-    blocks = dict(A=nx * nx, B=nx * nx, a=nx, C=ny * nx, d=ny, y=ny, wtil=nx, vtil=ny, Qw=nx * nx, Qv=ny * ny,
-                  Qwv=nx * ny)
+    q.nx, q.ny, q.Nmhe, q.nw = nx, ny, Nm, nw
+    blocks = dict(A=nx * nx, B=nx * nw, a=nx, C=ny * nx, d=ny, y=ny, wtil=nw, vtil=ny, Qw=nw * nw, Qv=ny * ny,
+                  Qwv=nw * ny)
     for k, bs in blocks.items():
         t = dev.get(k)
         setattr(q, k, t.data_ptr() if t is not None else None)
@@ -54,11 +55,11 @@ def _convert(torch, rs, m, invariant_cov=False):
     q.xtil0, q.Ptil0 = dev["xtil0"].data_ptr(), dev["Ptil0"].data_ptr()
     pp = (rs.rs_problem * 1)()
     p = pp[0]
-    p.nx, p.nu, p.N = nx, nx, N
-    for k, bs in (("Qx", nx * nx), ("Qw", nx * nx), ("Qxw", nx * nx), ("A", nx * nx), ("B", nx * nx)):
+    p.nx, p.nu, p.N = nx, nu, N
+    for k, bs in (("Qx", nx * nx), ("Qw", nu * nu), ("Qxw", nx * nu), ("A", nx * nx), ("B", nx * nu)):
         setattr(p, k, out[k].data_ptr())
         setattr(p, "s" + k, bs)
-    for k, bs in (("a", nx), ("lx", nx), ("lw", nx), ("c", 1)):
+    for k, bs in (("a", nx), ("lx", nx), ("lw", nu), ("c", 1)):
         setattr(p, k, out[k].data_ptr())
         setattr(p, "s" + k, bs)
     for k in ("QxN", "lN", "cN", "x0"):
@@ -76,11 +77,15 @@ def _oracle_args(m):
             lst("vtil"), lst("Qw"), lst("Qv"), lst("Qwv") if m["Qwv"] is not None else None)
 
 
-@pytest.mark.parametrize("nx,ny,Nm,corr", [(20, 20, 100, False), (20, 20, 60, True), (4, 2, 10, False),
-                                           (3, 5, 0, True), (8, 8, 33, True)])
-def test_mhe_conversion_matches_oracle(nx, ny, Nm, corr):
+@pytest.mark.parametrize("nx,ny,Nm,corr,nw", [(20, 20, 100, False, 20), (20, 20, 60, True, 20), (4, 2, 10, False, 4),
+                                              (3, 5, 0, True, 3), (8, 8, 33, True, 8), (12, 6, 40, True, 4),
+                                              (6, 4, 25, True, 10), (20, 8, 30, False, 1), (40, 8, 5, True, 40)])
+def test_mhe_conversion_matches_oracle(nx, ny, Nm, corr, nw):
+    """Every UFTOC array of the device conversion against the oracle's,
+    including noise dimensions n_w other than n_x (inputs padded to
+    max(n_x, n_w)) and the largest sizes (n_x = 40, n_w + n_y = 48)."""
     torch, rs = _rs()
-    m = W.mhe_problem(nx, ny, Nm, seed=W.seed_for(6, nx * 100 + Nm), correlated=corr)
+    m = W.mhe_problem(nx, ny, Nm, seed=W.seed_for(6, nx * 100 + Nm), correlated=corr, nw=nw)
     out, info = _convert(torch, rs, m)
     assert info[0] == 0
     ref = mhe.mhe_to_uftoc(*_oracle_args(m))
@@ -110,6 +115,28 @@ def test_mhe_end_to_end_equals_rts_smoother(prec):
     err = np.abs(sol["x"][1:] - ms).max() / np.abs(ms).max()
     assert err <= TOL, err
     np.testing.assert_array_equal(sol["x"][0], m["xtil0"])
+
+
+@pytest.mark.parametrize("nx,nw,prec", [(12, 4, 0), (12, 4, 1), (6, 10, 0), (6, 10, 1)])
+def test_mhe_end_to_end_other_noise_dimension_equals_rts_smoother(nx, nw, prec):
+    """n_w != n_x, uncorrelated noise: the GPU solve of the GPU conversion
+    (inputs padded to max(n_x, n_w)) gives the RTS-smoothed means, and the
+    padded inputs come out zero."""
+    torch, rs = _rs()
+    m = W.mhe_problem(nx, 5, 150, seed=W.seed_for(6, 3 + nw), nw=nw)
+    out, info = _convert(torch, rs, m)
+    assert info[0] == 0
+    bt = rs.Batch({k: [v] for k, v in out.items()}, precision=prec, Ns=8, branch=4)
+    bt.solve()
+    torch.cuda.synchronize()
+    assert bt.status()[0, 0] == 0
+    sol = bt.result(0)
+    bt.close()
+    ms = mhe.rts_smoother(*_oracle_args(m)[:12])
+    err = np.abs(sol["x"][1:] - ms).max() / np.abs(ms).max()
+    assert err <= TOL, err
+    assert np.abs(sol["w"][0, nx:]).max(initial=0.0) <= 1e-10
+    assert np.abs(sol["w"][1:, nw:]).max(initial=0.0) <= 1e-10
 
 
 def test_mhe_end_to_end_correlated_noise_and_invariant_covariances():
