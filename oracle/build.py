@@ -14,14 +14,21 @@ LIB_PATH = os.path.join(BUILD_DIR, "liboracle.so")
 SOURCES = [os.path.join(HERE, "riccati_ref.c")]
 
 
-def build(verbose=False, path=None, native=False):
+SAN_PATH = os.path.join(BUILD_DIR, "liboracle_san.so")
+
+
+def build(verbose=False, path=None, native=False, sanitize=False):
     """Compile the oracle.  ``native=True`` adds -march=native (for timing the
-    oracle on the host that runs it; such a library is not portable), and
-    ``path`` places it elsewhere than the default library."""
-    out = path or LIB_PATH
+    oracle on the host that runs it; such a library is not portable),
+    ``sanitize=True`` builds it with AddressSanitizer and
+    UndefinedBehaviorSanitizer (default path SAN_PATH; load it in a process
+    that preloads gcc's ASan runtime), and ``path`` places it elsewhere."""
+    out = path or (SAN_PATH if sanitize else LIB_PATH)
     os.makedirs(os.path.dirname(out), exist_ok=True)
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O3"] + (["-march=native"] if native else []) + ["-std=c99", "-fPIC", "-shared", "-o", tmp] + \
+    opt = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           "-fno-omit-frame-pointer"] if sanitize else ["-O3"]
+    cmd = ["gcc"] + opt + (["-march=native"] if native else []) + ["-std=c99", "-fPIC", "-shared", "-o", tmp] + \
         SOURCES + ["-lm"]
     if verbose:
         print(" ".join(cmd))

@@ -3,6 +3,7 @@
 Test infrastructure only (see the package docstring).
 """
 import ctypes
+import os
 
 import numpy as np
 
@@ -18,7 +19,9 @@ def use_library(path):
     _lib, _path = None, path
 
 
-_path = None
+# ORACLE_LIBRARY names another build of the same source (the sanitized copy
+# that the sanitizer test loads)
+_path = os.environ.get("ORACLE_LIBRARY")
 
 
 def _load():

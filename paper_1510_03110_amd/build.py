@@ -65,5 +65,41 @@ def build(verbose=False):
     return LIB_PATH
 
 
+# Host sanitizers for the C ABI's own code (plan construction, work tables,
+# argument checks), each flag routed to the host compilation only.
+SAN_DIR = os.path.join(PKG, "_build_san")
+SAN_LIB = os.path.join(SAN_DIR, "librs_san.so")
+HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_host_sanitized(verbose=False):
+    """A copy of the library whose host C ABI (rs_capi.cpp) is built with
+    AddressSanitizer and UndefinedBehaviorSanitizer, linked with the regular
+    objects of every other source (built first if missing).  For host-only
+    tests on the CPU, in a process that preloads clang's ASan runtime."""
+    objs = [os.path.join(BUILD_DIR, os.path.splitext(s)[0] + ".o") for s in SOURCES if s != "rs_capi.cpp"]
+    if not all(os.path.exists(o) for o in objs):
+        build(verbose)
+    os.makedirs(SAN_DIR, exist_ok=True)
+    obj = os.path.join(SAN_DIR, "rs_capi.o")
+    cmd = [hipcc()] + HIPCC_FLAGS + HOST_SAN + ["-g", "-c", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                                                os.path.join(CSRC, "rs_capi.cpp"), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + "\n")
+        raise RuntimeError("hipcc failed on rs_capi.cpp (sanitized, %d)" % res.returncode)
+    tmp = SAN_LIB + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + HOST_SAN + \
+        ["-Xarch_host", "-shared-libsan"] + objs + [obj, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

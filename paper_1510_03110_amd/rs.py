@@ -77,10 +77,12 @@ _lib = None
 
 
 def library():
-    """Load ``librs.so`` (building it first only if no build exists)."""
+    """Load ``librs.so`` (building it first only if no build exists).
+    RS_LIBRARY names another build of the same sources (the host-sanitized
+    copy that the sanitizer test loads)."""
     global _lib
     if _lib is None:
-        path = _build.LIB_PATH
+        path = os.environ.get("RS_LIBRARY") or _build.LIB_PATH
         if not os.path.exists(path):
             _build.build()
         lib = ctypes.CDLL(path)
