@@ -17,6 +17,9 @@ SOURCES = ["rs_kernels.hip", "rs_kernels_mfma.hip", "rs_solve.hip", "rs_refine.h
            "rs_ip.hip", "rs_pad.hip", "rs_static.hip", "rs_capi.cpp"]
 HEADERS = ["rs_types.hpp", "rs_device.hpp", "rs_mfma.hpp", "rs_launch.hpp", "rs_vec.hpp"]
 
+# roctx (the ranges the C ABI marks around its calls and kernel launches)
+LINK_LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
+
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -57,7 +60,7 @@ def build(verbose=False):
         if verbose and out.strip():
             print(out)
     tmp = LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + LINK_LIBS + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
@@ -93,7 +96,7 @@ def build_host_sanitized(verbose=False):
         raise RuntimeError("hipcc failed on rs_capi.cpp (sanitized, %d)" % res.returncode)
     tmp = SAN_LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + HOST_SAN + \
-        ["-Xarch_host", "-shared-libsan"] + objs + [obj, "-o", tmp]
+        ["-Xarch_host", "-shared-libsan"] + objs + [obj] + LINK_LIBS + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -1,6 +1,7 @@
 // C ABI of the parallel Riccati solver: argument checking, the tree plan
 // (Alg. 5/6 levels and work lists), the workspace layout and the launches.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cstring>
@@ -329,10 +330,30 @@ hipEvent_t take_event(rs_plan_s *P) {
     return e;
 }
 
-// Launch one kernel of the given kind, bracketed by timing events when the
-// plan's timing mode is on.
+// roctx range over a host-side span (a public call, or the launch of one
+// kernel kind): a profiler with marker tracing (rocprofv3 --marker-trace)
+// shows the calls and the kernel kinds they launch by name.
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
+
+// Kernel kind names (the order of rs_plan_kernel_times).
+const char *kind_name(int kind) {
+    static const char *const names[KK_COUNT] = {
+        "rs.init", "rs.leaf_up", "rs.tree", "rs.leaf_down", "rs.factor_leaf_up", "rs.factor_tree",
+        "rs.factor_leaf_down", "rs.solve_leaf_up", "rs.solve_tree", "rs.solve_leaf_down", "rs.residual",
+        "rs.update", "rs.check", "rs.report", "rs.kind14", "rs.kind15"};
+    return kind >= 0 && kind < KK_COUNT ? names[kind] : "rs.kernel";
+}
+
+// Launch one kernel of the given kind, inside a roctx range of its kind and
+// bracketed by timing events when the plan's timing mode is on.
 template <class F>
 hipError_t timed(rs_plan_s *P, int kind, hipStream_t st, F &&launch) {
+    Range range(kind_name(kind));
     if (!P->timing) return launch();
     hipEvent_t a = take_event(P), b = take_event(P);
     if (!a || !b) return hipErrorOutOfMemory;
@@ -1284,6 +1305,7 @@ static rs_status run_sequence(rs_plan P, char *W, int32_t *info, hipStream_t st,
 
 static rs_status run_call(rs_plan P, const rs_problem *probs, void *work, size_t work_bytes, void *stream,
                           int32_t *info_dev, int mode) {
+    Range range(mode == 0 ? "rs_batch_solve" : mode == 1 ? "rs_factor" : "rs_solve");
     rs_status s = check_call(P, probs, work, work_bytes);
     if (s != RS_OK) return s;
     if (mode != 0 && (!P->factored || P->leaf_chunk > 0)) return RS_ERR_ARG;
