@@ -605,7 +605,8 @@ def run_large(args):
     prec = args.precision if args.precision in ("fp64", "mixed", "bf16") else "fp64"
     pc = {"fp64": rs.RS_FP64, "mixed": rs.RS_MIXED_FP32, "bf16": rs.RS_MIXED_BF16}[prec]
     data = W.c5_torch(128, 64, 16384, 1, seed=W.seed_for(5), device="cuda")
-    bt = rs.Batch(data, precision=pc, Ns=64, branch=8)
+    flags = rs.RS_PLAN_REFACTOR_DOWN if args.refactor_down else 0
+    bt = rs.Batch(data, precision=pc, Ns=64, branch=8, flags=flags)
     for _ in range(args.warmup):
         bt.solve()
     torch.cuda.synchronize()
@@ -622,7 +623,8 @@ def run_large(args):
            "unit": "ms/solve", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": False,
            "dtype": {"fp64": "f64", "mixed": "f32+f64", "bf16": "bf16+f32+f64"}[prec],
            "data": "synthetic: seeded, A_t per stage, B, Q, R given once (drawn on the device)",
-           "config": {"workload": "uftoc_c5_nx128_nu64_N16384_batch1", "precision": prec, "Ns": 64, "branch": 8},
+           "config": {"workload": "uftoc_c5_nx128_nu64_N16384_batch1", "precision": prec, "Ns": 64, "branch": 8,
+                      "master_down": "refactor" if args.refactor_down else "superposition"},
            "status": int(bt.status()[0, 0]),
            "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kt.items() if v[1]}}
     bt.close()
@@ -659,6 +661,9 @@ def main():
     ap.add_argument("--tune-cache", default="", help="autotuner cache file (default: the tuner's)")
     ap.add_argument("--ip", action="store_true",
                     help="interior-point mode: one problem with input bounds (see run_ip)")
+    ap.add_argument("--refactor-down", action="store_true",
+                    help="large-block mode: factor the master levels again on the way down (RS_PLAN_REFACTOR_DOWN) "
+                         "instead of the superposition sweep")
     ap.add_argument("--large", action="store_true",
                     help="large-block mode: the n_x=128, n_u=64, N=16384 single instance (see run_large)")
     ap.add_argument("--rank-reveal", action="store_true",

@@ -184,6 +184,19 @@ typedef struct rs_options {
  * instead (wavefront and large-block kernels).  An autotuner chooses. */
 #define RS_PLAN_NATIVE_TILES 16
 
+/* rs_options.flags: down pass of the large-block master levels (shapes with
+ * n_x > 64 or n_u > 64, and those the other kernels do not cover).  By
+ * default every master subproblem below the top is solved on the way down
+ * by a forward sweep on the records of its own reduction (Alg. 4 keeps
+ * P, K, V, L_t and the preliminary Psi, k of each master stage; with the
+ * terminal costate lam_N sent by the parent, w = K x + k + L_t lam_N and
+ * lam = P x - Psi + V lam_N), the superposition that the leaf solve also
+ * uses: the master levels are factored once.  With this flag the down pass
+ * factors every such subproblem again from its parent's message (P, Psi;
+ * Alg. 6 as the paper states it), twice the master-level matrix work; kept
+ * for comparison.  Both give the same solution up to rounding. */
+#define RS_PLAN_REFACTOR_DOWN 32
+
 /* Per-instance result report (device memory, 40 bytes each). */
 typedef struct rs_info {
     double rel_resid;       /* ||r - K z||_inf / ||r||_inf                          */

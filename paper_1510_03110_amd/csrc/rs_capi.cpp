@@ -63,6 +63,7 @@ struct rs_plan_s {
     bool refine_ws = false;         // workspace holds the refinement tables (mixed or report)
     int32_t leaf_chunk = 0;         // > 0: leaves processed in chunks of this many (bounded factor store)
     bool check_inputs = false;      // RS_PLAN_CHECK_INPUTS: finite-input scan after every call
+    bool superpose = true;          // large-block master levels: superposition down pass (else RS_PLAN_REFACTOR_DOWN)
     size_t off_scan = 0;            // its per-instance first offending place
     rs_options opt{};               // options the plan was made with
     bool tables_dirty = false;      // host tables changed since the last upload
@@ -447,6 +448,7 @@ static rs_status plan_create(int32_t count, const int32_t *dims_in, int stride, 
         P->report = (opt->flags & RS_PLAN_REPORT) != 0;
         P->leaf_chunk = opt->leaf_chunk;
         P->check_inputs = (opt->flags & RS_PLAN_CHECK_INPUTS) != 0;
+        P->superpose = (opt->flags & RS_PLAN_REFACTOR_DOWN) == 0;
         if (opt->Ns > 0) P->Ns = opt->Ns;
         if (opt->branch > 0) P->branch = opt->branch;
         P->max_refine = opt->max_refine > 0 ? opt->max_refine : (P->bf16 ? 20 : 5);
@@ -1042,6 +1044,7 @@ static GroupArgs group_args(rs_plan P, char *W, size_t gi, int32_t *info, bool c
     a.ident = P->rank_reveal ? reinterpret_cast<const double *>(W + g.off_ident) : nullptr;
     a.nx = g.nx;
     a.nu = g.nu;
+    a.superpose = P->superpose ? 1 : 0;
     if (P->refine_ws) {
         a.corr = user + P->count;
         a.conv = with_conv ? reinterpret_cast<const int32_t *>(W + P->off_conv) : nullptr;

@@ -356,12 +356,13 @@ struct LeafOut {
     }
 };
 
-// Master-slot factors (SlotLayout): up pass uK, uP, uV, uL, uLT; down pass
-// K, dL, dLT.
+// Master-slot factors (SlotLayout): up pass uK, uP, uV, uL, uLT (and, for
+// the superposition sweep, L_t in the dL place); down pass K, dL, dLT.
 struct SlotOut {
     double *slots;
     int first, n;
     bool up;
+    bool lt;
     __device__ double *at(int s) const { return slots + (int64_t)(first + s) * SlotLayout{n}.size(); }
     __device__ void P(int s, int i, int j, double v) const {
         if (up) at(s)[SlotLayout{n}.uP() + i * n + j] = v;
@@ -373,7 +374,9 @@ struct SlotOut {
     __device__ void V(int s, int i, int j, double v) const {
         if (up) at(s)[SlotLayout{n}.uV() + i * n + j] = v;
     }
-    __device__ void Lt(int, int, int, double) const {}
+    __device__ void Lt(int s, int i, int j, double v) const {
+        if (lt) at(s)[SlotLayout{n}.dL() + i * n + j] = v;
+    }
     __device__ void L(int s, const double *Li, const double *LiT) const {
         double *d = at(s);
         const SlotLayout SL{n};
@@ -616,8 +619,8 @@ __global__ void __launch_bounds__(LB_MT) kl_tree(GroupArgs g) {
             // excluded instance: only its completion flag is published
         } else if (it.kind == ITEM_UP) {
             init_red(S);
-            mpass<double, true, false>(S, get, it.count, g.info, it.inst, -1, 3, [](int) {}, SlotOut{slots, it.first, n, true},
-                                &bad);
+            mpass<double, true, false>(S, get, it.count, g.info, it.inst, -1, 3, [](int) {},
+                                       SlotOut{slots, it.first, n, true, g.superpose != 0}, &bad);
             double *out = slot(it.out_slot);
             for (int e = tid; e < n * n; e += nthr()) {
                 const int i = e / n, j = e % n;
@@ -626,31 +629,30 @@ __global__ void __launch_bounds__(LB_MT) kl_tree(GroupArgs g) {
                 out[SL.Qx() + e] = S.P[e];
             }
             if (g.ident) rank_reveal(S.Qh, n, unit_roundoff<double>(), out + SL.Qw(), nullptr);
-        } else if (it.kind == ITEM_UP_LAST) {
-            const double *term = slot(it.term_slot);
-            for (int e = tid; e < n * n; e += nthr()) S.P[e] = term[SL.Qx() + e];
-            __syncthreads();
-            mpass<double, false, false>(S, get, it.count, g.info, it.inst, -1, 3, [](int) {},
-                                 SlotOut{slots, it.first, n, true}, &bad);
-            double *out = slot(it.out_slot);
-            for (int e = tid; e < n * n; e += nthr()) out[SL.Qx() + e] = S.P[e];
+        } else if (it.kind == ITEM_DOWN && g.superpose) {
+            // solved by the vector pass from the up records: nothing to factor
         } else {
-            const bool top = it.kind == ITEM_TOP;
-            const double *msg = top ? nullptr : slot(it.out_slot);
-            const double *term = it.last ? slot(it.term_slot) : nullptr;
+            // Alg. 1 on the master stages from the true terminal (a level's
+            // last item, up records) or from the parent's message (down
+            // records; top, and below it without superposition)
+            const bool upl = it.kind == ITEM_UP_LAST;
+            const double *msg = it.kind == ITEM_DOWN ? slot(it.out_slot) : nullptr;
+            double *term = it.last ? slot(it.term_slot) : nullptr;
             for (int e = tid; e < n * n; e += nthr()) S.P[e] = term ? term[SL.Qx() + e] : msg[SL.P() + e];
             __syncthreads();
             mpass<double, false, false>(
                 S, get, it.count, g.info, it.inst, -1, 3,
                 [&](int s) {      // M2 for child s: P at the end of master stage s
-                    double *d = slot(it.first + s) + SL.P();
-                    for (int e = tid; e < n * n; e += nthr()) d[e] = S.P[e];
+                    if (!upl) {
+                        double *d = slot(it.first + s) + SL.P();
+                        for (int e = tid; e < n * n; e += nthr()) d[e] = S.P[e];
+                    }
                 },
-                SlotOut{slots, it.first, n, false}, &bad);
-            if (top) {
-                double *d = slot(it.term_slot) + SL.P();      // P_0, for the optimal value
+                SlotOut{slots, it.first, n, upl, false}, &bad);
+            // a level's last item: its reduced terminal; the top: P_0, for the optimal value
+            double *d = upl ? slot(it.out_slot) + SL.Qx() : it.kind == ITEM_TOP ? term + SL.P() : nullptr;
+            if (d)
                 for (int e = tid; e < n * n; e += nthr()) d[e] = S.P[e];
-            }
         }
         publish(g, idx);
     }
@@ -840,9 +842,10 @@ __device__ void vstage(VS &S, const VSrcL<TR> &q, int n, int m, double &cbar) {
 // and lam_t = P_t x - Psi_t (+ V_t lam_N); x, w, lam of stage t written to
 // the outputs when given.
 template <class TR>
-__device__ void fstage(VS &S, int n, int m, const TR *K, const double *kvec, const TR *Lt, const double *A,
-                       const double *B, const double *a, const TR *P, const double *Psi, const TR *Vt, double *x_out,
-                       double *w_out, double *lam_out) {
+__device__ __forceinline__ void fstage(VS &S, int n, int m, const TR *K, const double *kvec, const TR *Lt,
+                                       const double *A, const double *B, const double *a, const TR *P,
+                                       const double *Psi, const TR *Vt, double *x_out, double *w_out,
+                                       double *lam_out) {
     const int tid = threadIdx.x;
     for (int i = tid; i < n; i += NT)
         if (x_out) x_out[i] = S.x[i];
@@ -968,7 +971,9 @@ __device__ void leaf_forward(VS &S, const GroupArgs &g, const sv::Prob &p, const
     const double *vec0 = g.fvec + stage0 * (int64_t)R.vec();
     const double *msg = g.slots + (int64_t)it.slot * SL.size();
     const bool last = (it.flags & LEAF_LAST) != 0;
-    if (!last) {
+    if (!last && g.superpose) {
+        for (int i = tid; i < n; i += NT) S.lamN[i] = msg[SL.lamN() + i];    // sent by the master level
+    } else if (!last) {
         const double *nxt = msg + SL.size();           // the next leaf's slot: x_hat_{i+1}
         for (int i = tid; i < n; i += NT) S.x[i] = nxt[SL.xh() + i];
         __syncthreads();
@@ -1055,7 +1060,10 @@ __global__ void __launch_bounds__(NT) kw_leaf_down(GroupArgs g) {
     }, S.gred);
 }
 
-__global__ void __launch_bounds__(NT) kw_tree(GroupArgs g) {
+// A tree item is a chain of matrix-vector products with one workgroup per
+// CU; the occupancy cap of two waves per SIMD keeps the compiler from
+// trading the loads in flight of each product's unrolled loop for registers.
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) kw_tree(GroupArgs g) {
     __shared__ VS S;
     __shared__ int s_item;
     const int n = g.nx, tid = threadIdx.x;
@@ -1074,76 +1082,142 @@ __global__ void __launch_bounds__(NT) kw_tree(GroupArgs g) {
         const int count = it.count;
         if (sv::skip_inst(g, it.inst)) {
             // converged or excluded: nothing to do (its dependents belong to the same instance)
-        } else if (it.kind == ITEM_UP || it.kind == ITEM_UP_LAST) {
-            const bool red = it.kind == ITEM_UP;
-            const double *term = red ? nullptr : slot(it.term_slot);
+        } else if (it.kind == ITEM_UP) {
+            // Alg. 4 on the master stages (vector lines)
             for (int i = tid; i < n; i += NT) {
-                S.Psi[i] = red ? 0.0 : -term[SL.lx() + i];
+                S.Psi[i] = 0.0;
                 S.v[i] = 0.0;
             }
-            double cbar = red ? 0.0 : term[SL.c()];
+            double cbar = 0.0;
             __syncthreads();
             for (int s = count - 1; s >= 0; --s) {
-                const double *sl = slot(it.first + s);
+                double *sl = slot(it.first + s);
                 VSrcL<double> q = slot_src(sl, n);
                 const double *sn = slot(it.first + s + 1);
                 const bool end = s + 1 == count;
                 q.Li = sl + SL.uL();
                 q.LT = sl + SL.uLT();
                 q.K = sl + SL.uK();
-                if (red) {
-                    q.Pn = end ? nullptr : sn + SL.uP();
-                    q.Vn = end ? nullptr : sn + SL.uV();
-                    vstage<true, false>(S, q, n, n, cbar);
-                } else {
-                    q.Pn = end ? term + SL.Qx() : sn + SL.uP();
-                    vstage<false, false>(S, q, n, n, cbar);
+                q.Pn = end ? nullptr : sn + SL.uP();
+                q.Vn = end ? nullptr : sn + SL.uV();
+                vstage<true, false>(S, q, n, n, cbar);
+                if (g.superpose) {
+                    // Psi_s and k_s of this sweep, for the superposition sweep down
+                    for (int i = tid; i < n; i += NT) {
+                        sl[SL.Psi() + i] = S.Psi[i];
+                        sl[SL.k() + i] = S.kk[i];
+                    }
                 }
                 __syncthreads();
             }
             double *out = slot(it.out_slot);
             for (int i = tid; i < n; i += NT) {
-                if (red) out[SL.a() + i] = S.v[i];
+                out[SL.a() + i] = S.v[i];
                 out[SL.lx() + i] = -S.Psi[i];
             }
             if (tid == 0) out[SL.c()] = cbar;
         } else {
+            // Up pass of a level's last item (Alg. 1 from the true terminal
+            // on the up records), and the down pass.  Down at the top, and
+            // below it without superposition: the vector part of Alg. 1 from
+            // the parent's message (or the true terminal), then Alg. 3.
+            // Below the top with superposition (Alg. 6, k >= 1, as in the leaf
+            // solve): a forward sweep on the records of the item's up pass
+            // with its terminal costate lam_N from the parent,
+            //   w = K x + k_0 + L_t lam_N,  lam = P x - Psi_0 + V lam_N,
+            // x+ = A_hat x + B_hat w + a_hat (no lam_N terms for the last
+            // item of a level, whose records are final); child s receives
+            // x_s and its terminal costate lam_{s+1}.
+            const bool upl = it.kind == ITEM_UP_LAST;
             const bool top = it.kind == ITEM_TOP;
-            const sv::Prob p = sv::load_prob(g.probs, it.inst);
-            const double *msg = top ? nullptr : slot(it.out_slot);
-            const double *term = it.last ? slot(it.term_slot) : nullptr;
-            for (int i = tid; i < n; i += NT) {
-                S.Psi[i] = term ? -term[SL.lx() + i] : msg[SL.Psi() + i];
-                S.x[i] = top ? p.x0[i] : msg[SL.xh() + i];
-            }
-            double cbar = term ? term[SL.c()] : msg[SL.cb()];
-            __syncthreads();
-            for (int s = count - 1; s >= 0; --s) {
-                double *sl = slot(it.first + s);
-                // message to child s: cost to go at the end of master stage s
-                for (int i = tid; i < n; i += NT) sl[SL.Psi() + i] = S.Psi[i];
-                if (tid == 0) sl[SL.cb()] = cbar;
-                VSrcL<double> q = slot_src(sl, n);
-                q.Pn = sl + SL.P();
-                q.Li = sl + SL.dL();
-                q.LT = sl + SL.dLT();
-                q.K = sl + SL.K();
-                vstage<false, true>(S, q, n, n, cbar);
-                for (int i = tid; i < n; i += NT) sl[SL.k() + i] = S.kk[i];
+            const bool sweep = !upl && !top && g.superpose;
+            const bool lterms = sweep && !it.last;
+            const double *msg = upl || top ? nullptr : slot(it.out_slot);
+            double *term = it.last ? slot(it.term_slot) : nullptr;
+            if (sweep) {
+                for (int i = tid; i < n; i += NT) {
+                    S.x[i] = msg[SL.xh() + i];
+                    S.lamN[i] = lterms ? msg[SL.lamN() + i] : 0.0;
+                }
+                __syncthreads();
+            } else {
+                const sv::Prob p = sv::load_prob(g.probs, it.inst);
+                for (int i = tid; i < n; i += NT) {
+                    S.Psi[i] = term ? -term[SL.lx() + i] : msg[SL.Psi() + i];
+                    if (!upl) S.x[i] = top ? p.x0[i] : msg[SL.xh() + i];
+                }
+                double cbar = term ? term[SL.c()] : msg[SL.cb()];
+                __syncthreads();
+                for (int s = count - 1; s >= 0; --s) {
+                    double *sl = slot(it.first + s);
+                    VSrcL<double> q = slot_src(sl, n);
+                    if (upl) {
+                        q.Pn = s + 1 == count ? term + SL.Qx() : slot(it.first + s + 1) + SL.uP();
+                        q.Li = sl + SL.uL();
+                        q.LT = sl + SL.uLT();
+                        q.K = sl + SL.uK();
+                    } else {
+                        // message to child s: cost to go at the end of master stage s
+                        for (int i = tid; i < n; i += NT) sl[SL.Psi() + i] = S.Psi[i];
+                        if (tid == 0) sl[SL.cb()] = cbar;
+                        q.Pn = sl + SL.P();
+                        q.Li = sl + SL.dL();
+                        q.LT = sl + SL.dLT();
+                        q.K = sl + SL.K();
+                    }
+                    vstage<false, true>(S, q, n, n, cbar);
+                    // k_s (and for the sweep down, Psi_s of the up records)
+                    if (!upl || g.superpose)
+                        for (int i = tid; i < n; i += NT) sl[SL.k() + i] = S.kk[i];
+                    if (upl && g.superpose)
+                        for (int i = tid; i < n; i += NT) sl[SL.Psi() + i] = S.Psi[i];
+                    __syncthreads();
+                }
+                if (upl) {
+                    double *out = slot(it.out_slot);
+                    for (int i = tid; i < n; i += NT) out[SL.lx() + i] = -S.Psi[i];
+                    if (tid == 0) out[SL.c()] = cbar;
+                } else if (top && p.obj) {
+                    const double v = cost_to_go(S, slot(it.term_slot) + SL.P(), n, cbar);
+                    if (tid == 0) p.obj[0] = v;
+                }
                 __syncthreads();
             }
-            if (top && p.obj) {
-                const double v = cost_to_go(S, slot(it.term_slot) + SL.P(), n, cbar);
-                if (tid == 0) p.obj[0] = v;
+            if (!upl) {
+                for (int s = 0; s < count; ++s) {
+                    double *sl = slot(it.first + s);
+                    fstage<double>(S, n, n, sl + (sweep ? SL.uK() : SL.K()), sl + SL.k(),
+                                   lterms ? sl + SL.dL() : nullptr, sl + SL.A(), sl + SL.Qw(), sl + SL.a(),
+                                   sweep ? sl + SL.uP() : nullptr, sl + SL.Psi(), lterms ? sl + SL.uV() : nullptr,
+                                   sl + SL.xh(), nullptr, sweep && s > 0 ? slot(it.first + s - 1) + SL.lamN() : nullptr);
+                }
+                if (it.last)
+                    for (int i = tid; i < n; i += NT) term[SL.xh() + i] = S.x[i];
             }
-            __syncthreads();
-            for (int s = 0; s < count; ++s) {
-                double *sl = slot(it.first + s);
-                fstage<double>(S, n, n, sl + SL.K(), sl + SL.k(), nullptr, sl + SL.A(), sl + SL.Qw(), sl + SL.a(),
-                               nullptr, nullptr, nullptr, sl + SL.xh(), nullptr, nullptr);
+            if (sweep) {
+                // the last child ends where the item does: at lam_N, or for
+                // the last item at the terminal node, lam = P_term x - Psi_term
+                double *lend = slot(it.first + count - 1) + SL.lamN();
+                if (it.last)
+                    gemv<false>(term + SL.Qx(), n, S.x, n, n, [&](int i, double v) { lend[i] = v + term[SL.lx() + i]; },
+                                S.gred);
+                else
+                    for (int i = tid; i < n; i += NT) lend[i] = S.lamN[i];
+            } else if (top && g.superpose) {
+                // terminal costate of child s, lam_{s+1} = P_{s+1} x_{s+1} -
+                // Psi_{s+1}, from the cost to go sent to it and the initial
+                // state of the next child (of the terminal node for the last)
+                __threadfence_block();
+                __syncthreads();
+                for (int s = 0; s < count; ++s) {
+                    double *sl = slot(it.first + s);
+                    const double *xn = (s + 1 < count ? slot(it.first + s + 1) : term) + SL.xh();
+                    for (int i = tid; i < n; i += NT) S.y[i] = xn[i];
+                    __syncthreads();
+                    gemv<false>(sl + SL.P(), n, S.y, n, n, [&](int i, double v) { sl[SL.lamN() + i] = v - sl[SL.Psi() + i]; },
+                                S.gred);
+                }
             }
-            if (it.last)
-                for (int i = tid; i < n; i += NT) slot(it.term_slot)[SL.xh() + i] = S.x[i];
         }
         publish(g, idx);
     }

@@ -89,7 +89,8 @@ struct SlotLayout {
     __host__ __device__ int dL() const { return 10 * n * n + 5 * n + 2; }
     __host__ __device__ int dLT() const { return 11 * n * n + 5 * n + 2; }
     // costate at the end of the node's subproblem (its terminal lam_N), sent
-    // down by the fused matrix-core tree
+    // down by the fused matrix-core tree and by the superposition sweep of the
+    // large-block tree (whose up pass then keeps L_t = -G^{-1} B' V in dL)
     __host__ __device__ int lamN() const { return 12 * n * n + 5 * n + 2; }
     __host__ __device__ int size() const { return ((12 * n * n + 6 * n + 2) + 7) & ~7; }
 };
@@ -180,6 +181,11 @@ struct GroupArgs {
     // leaf-chunked solves: stage index (in the group's leaf stage numbering)
     // of the first record held by the stored factorization of this launch
     int64_t rec_stage0;
+    // large-block master levels: 1 = the down pass of every master
+    // subproblem below the top is the superposition sweep on its up records
+    // (Alg. 6 without a second factorization), 0 = factored again with the
+    // parent's message
+    int32_t superpose;
     // first stage of a leaf's records in the stored factorization
     __host__ __device__ int64_t rec_stage(int64_t leaf_scratch) const { return leaf_scratch / sps - rec_stage0; }
 };

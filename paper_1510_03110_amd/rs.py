@@ -23,6 +23,7 @@ RS_PLAN_RANK_REVEAL = 2
 RS_PLAN_REPORT = 4
 RS_PLAN_CHECK_INPUTS = 8
 RS_PLAN_NATIVE_TILES = 16
+RS_PLAN_REFACTOR_DOWN = 32
 RS_PROB_SKIP = 1
 RS_KERNEL_KINDS = 16
 

@@ -50,6 +50,34 @@ def test_large_fp64_matches_oracle(nx, nu, N, Ns, b):
     bt.close()
 
 
+@pytest.mark.parametrize("refactor", [False, True])
+@pytest.mark.parametrize("nx,nu,N,Ns,b,rr,mixed", [(64, 32, 256, 4, 2, False, False),
+                                                   (48, 16, 301, 4, 3, True, False),
+                                                   (128, 64, 96, 4, 2, False, False),
+                                                   (64, 32, 150, 4, 3, False, True)])
+def test_large_master_down_pass_forms(nx, nu, N, Ns, b, rr, mixed, refactor):
+    """Down pass of the master levels below the top (Alg. 6, k >= 1): the
+    superposition sweep on the records of the up pass (default) and the
+    second factorization from the parent's message (RS_PLAN_REFACTOR_DOWN),
+    on trees of four to six levels with interior and last items, plain and
+    rank-revealing master stages, FP64 and mixed.  Both against the oracle,
+    and against each other."""
+    prob = W.with_costs(W.g2(nx, nu, N, seed=nx + 13 * N), seed=N + 1)
+    torch, rs = _rs()
+    sols = []
+    for flags in ((rs.RS_PLAN_REFACTOR_DOWN if refactor else 0), rs.RS_PLAN_REFACTOR_DOWN):
+        _, _, bt = _batch([prob], Ns=Ns, branch=b, rank_reveal=rr, flags=flags,
+                          precision=rs.RS_MIXED_FP32 if mixed else rs.RS_FP64)
+        bt.solve()
+        torch.cuda.synchronize()
+        assert bt.status()[0, 0] == 0
+        sols.append(bt.result(0))
+        bt.close()
+    _check(prob, sols[0])
+    if not refactor:
+        assert kkt.rel_error(sols[0], sols[1]) <= TOL
+
+
 @pytest.mark.parametrize("N,Ns", [(8, 16), (16, 16), (1, 4)])
 def test_large_whole_problem_leaf(N, Ns):
     """A horizon that fits one leaf: Alg. 1-3 on the leaf with the true
