@@ -184,9 +184,10 @@ typedef struct rs_options {
  * instead (wavefront and large-block kernels).  An autotuner chooses. */
 #define RS_PLAN_NATIVE_TILES 16
 
-/* rs_options.flags: down pass of the large-block master levels (shapes with
- * n_x > 64 or n_u > 64, and those the other kernels do not cover).  By
- * default every master subproblem below the top is solved on the way down
+/* rs_options.flags: down pass of the master levels of the stored
+ * factorization (rs_factor / rs_solve, mixed precision, and every solve of
+ * the shapes that run on the large-block kernels).  By default every master
+ * subproblem below the top is solved on the way down
  * by a forward sweep on the records of its own reduction (Alg. 4 keeps
  * P, K, V, L_t and the preliminary Psi, k of each master stage; with the
  * terminal costate lam_N sent by the parent, w = K x + k + L_t lam_N and

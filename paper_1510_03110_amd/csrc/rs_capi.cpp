@@ -63,7 +63,7 @@ struct rs_plan_s {
     bool refine_ws = false;         // workspace holds the refinement tables (mixed or report)
     int32_t leaf_chunk = 0;         // > 0: leaves processed in chunks of this many (bounded factor store)
     bool check_inputs = false;      // RS_PLAN_CHECK_INPUTS: finite-input scan after every call
-    bool superpose = true;          // large-block master levels: superposition down pass (else RS_PLAN_REFACTOR_DOWN)
+    bool superpose = true;          // stored factorization: superposition down pass (else RS_PLAN_REFACTOR_DOWN)
     size_t off_scan = 0;            // its per-instance first offending place
     rs_options opt{};               // options the plan was made with
     bool tables_dirty = false;      // host tables changed since the last upload

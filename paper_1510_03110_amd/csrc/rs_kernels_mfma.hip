@@ -653,11 +653,17 @@ struct LeafFacOut : NoEmit {
 };
 
 // Master-slot writer: up factors (Alg. 4 / elimination) or down factors.
+// With `lt` (superposition down pass), the up pass of Alg. 4 also keeps
+// L_t = -G^{-1} B' V in the dL place.
 template <int NX, bool UP>
 struct SlotFacOut : NoEmit {
-    static constexpr bool VEC = false, KF = true, PF = UP, LF = true, VF = UP;
+    static constexpr bool VEC = false, KF = true, PF = UP, LF = true, VF = UP, LTF = UP;
     double *slots;
     int first;
+    bool lt;
+    __device__ void Lt(int s, int i, int j, double v) const {
+        if (lt) at(s)[SlotLayout{NX}.dL() + i * NX + j] = v;
+    }
     __device__ double *at(int s) const { return slots + (int64_t)(first + s) * SlotLayout{NX}.size(); }
     __device__ void K(int s, int i, int j, double v) const {
         const SlotLayout L{NX};
@@ -801,7 +807,7 @@ __global__ void __launch_bounds__(NT) kf_tree(GroupArgs g) {
             }
             __syncthreads();
             mfma_pass(S, get, it.count, g.info, it.inst, -1, 3, [](int, auto &) {},
-                                           SlotFacOut<NX, true>{{}, slots, it.first});
+                      SlotFacOut<NX, true>{{}, slots, it.first, g.superpose != 0});
             double *out = slot(it.out_slot);
             for (int e = tid; e < NX * NX; e += NT) {
                 const int i = e / NX, j = e % NX;
@@ -816,9 +822,11 @@ __global__ void __launch_bounds__(NT) kf_tree(GroupArgs g) {
             for (int e = tid; e < NX * NX; e += NT) S.P[e] = term[SL.Qx() + e];
             __syncthreads();
             mfma_pass(S, get, it.count, g.info, it.inst, -1, 3, [](int, auto &) {},
-                                            SlotFacOut<NX, true>{{}, slots, it.first});
+                      SlotFacOut<NX, true>{{}, slots, it.first, false});
             double *out = slot(it.out_slot);
             for (int e = tid; e < NX * NX; e += NT) out[SL.Qx() + e] = S.P[e];
+        } else if (it.kind == ITEM_DOWN && g.superpose) {
+            // solved by the vector pass from the up records: nothing to factor
         } else {
             auto &S = *reinterpret_cast<MSmem<double, NX, NX, false, true> *>(raw);
             const bool top = it.kind == ITEM_TOP;
@@ -831,7 +839,7 @@ __global__ void __launch_bounds__(NT) kf_tree(GroupArgs g) {
                 [&](int s, auto &Sm) {      // M2 for child s: P at the end of stage s
                     block_copy<NX * NX>(slot(it.first + s) + SL.P(), Sm.P);
                 },
-                SlotFacOut<NX, false>{{}, slots, it.first});
+                SlotFacOut<NX, false>{{}, slots, it.first, false});
             if (top) block_copy<NX * NX>(slot(it.term_slot) + SL.P(), S.P);   // P_0, for the optimal value
         }
         __threadfence();

@@ -225,15 +225,17 @@ __device__ __forceinline__ VSrc<double> slot_src(const double *sl) {
 //   x_{t+1} = A x_t + B w_t + a_t.
 // The last leaf was reduced with the true terminal, so its records are
 // final (no V, L terms).  `rec` gives the stage pointers K, k, P, Psi, V, L.
-// LAMN: the parent sent lam_N itself (the fused matrix-core tree) rather than
-// its cost to go P_hat, Psi_hat.
+// LAMN (or lamn_sent at run time): the parent sent lam_N itself (the fused
+// matrix-core tree, and the superposition down pass of the stored
+// factorization) rather than its cost to go P_hat, Psi_hat.
 template <int NX, int NU, bool LAMN = false, class Rec>
 __device__ __forceinline__ void leaf_forward_sweep(VSmem<NX, NU> &S, double *lamN, const Prob &p,
-                                                   const LeafItem &it, const double *msg, Rec rec) {
+                                                   const LeafItem &it, const double *msg, Rec rec,
+                                                   bool lamn_sent = false) {
     const SlotLayout SL{NX};
     const bool last = (it.flags & LEAF_LAST) != 0;
     const int l = lane();
-    if (LAMN && !last) {
+    if ((LAMN || lamn_sent) && !last) {
         if (l < NX) lamN[l] = msg[SL.lamN() + l];
         wsync();
     } else if (!last) {
@@ -383,7 +385,8 @@ __global__ void __launch_bounds__(WT) kv_leaf_down(GroupArgs g) {
         const TR *rec = reinterpret_cast<const TR *>(g.fstore) + stage0 * (int64_t)LeafRec{NX, NU}.per_stage();
         const double *msg = g.slots + (int64_t)it.slot * SlotLayout{NX}.size();
         leaf_forward_sweep<NX, NU>(S, lamN, p, it, msg,
-                                   UpRecs<NX, NU, TR>{rec, g.fvec + stage0 * (int64_t)LeafRec{NX, NU}.vec()});
+                                   UpRecs<NX, NU, TR>{rec, g.fvec + stage0 * (int64_t)LeafRec{NX, NU}.vec()},
+                                   g.superpose != 0);
         return;
     }
     const LeafRec R{NX, NU};
@@ -486,6 +489,7 @@ hipError_t launch_fwd(const GroupArgs &g, int, hipStream_t st) {
 template <int NX>
 __global__ void __launch_bounds__(WT) kv_tree(GroupArgs g) {
     __shared__ VSmem<NX, NX> S;
+    __shared__ double lamN[NX];
     __shared__ int s_item;
     const int l = lane();
     const SlotLayout SL{NX};
@@ -528,23 +532,29 @@ __global__ void __launch_bounds__(WT) kv_tree(GroupArgs g) {
             }
             double cbar = red ? 0.0 : term[SL.c()];
             wsync();
-            auto none = [](double, double) {};
             for (int s = count - 1; s >= 0; --s) {
-                const double *sl = slot(it.first + s);
+                double *sl = slot(it.first + s);
                 VSrc<double> q = slot_src<NX>(sl);
                 const double *sn = slot(it.first + s + 1);
                 const bool end = s + 1 == count;
                 q.Li = sl + SL.uL();
                 q.LT = sl + SL.uLT();
                 q.K = sl + SL.uK();
+                // Psi_s and k_s of this sweep, for the superposition sweep down
+                auto keep = [&](double psi, double k) {
+                    if (g.superpose && l < NX) {
+                        sl[SL.Psi() + l] = psi;
+                        sl[SL.k() + l] = k;
+                    }
+                };
                 if (red) {
                     q.Pn = end ? nullptr : sn + SL.uP();
                     q.Vn = end ? nullptr : sn + SL.uV();
-                    vstage<NX, NX, true, false>(S, q, cbar, none);
+                    vstage<NX, NX, true, false>(S, q, cbar, keep);
                 } else {
                     q.Pn = end ? term + SL.Qx() : sn + SL.uP();
                     q.Vn = nullptr;
-                    vstage<NX, NX, false, false>(S, q, cbar, none);
+                    vstage<NX, NX, false, true>(S, q, cbar, keep);
                 }
             }
             double *out = slot(it.out_slot);
@@ -553,6 +563,71 @@ __global__ void __launch_bounds__(WT) kv_tree(GroupArgs g) {
                 out[SL.lx() + l] = -S.Psi[l];
             }
             if (l == 0) out[SL.c()] = cbar;
+        } else if (it.kind == ITEM_DOWN && g.superpose) {
+            // Down pass below the top (Alg. 6, k >= 1) as a forward sweep on
+            // the records of the item's up pass, with the terminal costate
+            // lam_N sent by the parent (the superposition of the leaf solve):
+            //   w = K x + k_0 + L_t lam_N,  lam = P x - Psi_0 + V lam_N,
+            // x+ = A_hat x + B_hat w + a_hat; the last item of a level holds
+            // final records (no lam_N terms).  Child s receives x_s and its
+            // terminal costate lam_{s+1}.
+            const bool last = it.last != 0;
+            const double *msg = slot(it.out_slot);
+            if (l < NX) {
+                S.x[l] = msg[SL.xh() + l];
+                lamN[l] = last ? 0.0 : msg[SL.lamN() + l];
+            }
+            wsync();
+            for (int s = 0; s < count; ++s) {
+                double *sl = slot(it.first + s);
+                RowOp<NX, NX> rK, rA, rB, rL, rV;
+                Op<NX, NX> oP;
+                rK.load(sl + SL.uK(), NX);
+                rA.load(sl + SL.A(), NX);
+                rB.load(sl + SL.Qw(), NX);
+                oP.template load<false>(sl + SL.uP(), NX);
+                if (!last) {
+                    rL.load(sl + SL.dL(), NX);
+                    rV.load(sl + SL.uV(), NX);
+                }
+                const double kk = l < NX ? sl[SL.k() + l] : 0.0;
+                const double psi = l < NX ? sl[SL.Psi() + l] : 0.0;
+                const double av = l < NX ? sl[SL.a() + l] : 0.0;
+                rK.apply(S.x, [&](int i, double v) { S.fk[i] = v; });
+                rA.apply(S.x, [&](int i, double v) { S.fa[i] = v; });
+                if (!last) {
+                    rL.apply(lamN, [&](int i, double v) { S.fl[i] = v; });
+                    rV.apply(lamN, [&](int i, double v) { S.fv[i] = v; });
+                }
+                double lam = oP.apply(S.x) - psi;
+                wsync();
+                if (l < NX) {
+                    if (!last) lam += S.fv[l];
+                    sl[SL.xh() + l] = S.x[l];                                    // child s starts at x_s
+                    if (s > 0) slot(it.first + s - 1)[SL.lamN() + l] = lam;      // child s-1 ends at lam_s
+                    S.wv[l] = S.fk[l] + kk + (last ? 0.0 : S.fl[l]);
+                }
+                wsync();
+                rB.apply(S.wv, [&](int i, double v) { S.fb[i] = v; });
+                wsync();
+                if (l < NX) S.x[l] = S.fa[l] + av + S.fb[l];
+                wsync();
+            }
+            // the last child ends where the item does: at lam_N, or for the
+            // last item at the terminal node, lam = P_term x - Psi_term
+            double *lend = slot(it.first + count - 1) + SL.lamN();
+            if (last) {
+                double *term = slot(it.term_slot);
+                Op<NX, NX> oQ;
+                oQ.template load<false>(term + SL.Qx(), NX);
+                const double v = oQ.apply(S.x);
+                if (l < NX) {
+                    lend[l] = v + term[SL.lx() + l];
+                    term[SL.xh() + l] = S.x[l];
+                }
+            } else if (l < NX) {
+                lend[l] = lamN[l];
+            }
         } else {
             const bool top = it.kind == ITEM_TOP;
             const Prob p = load_prob(g.probs, it.inst);
@@ -592,6 +667,24 @@ __global__ void __launch_bounds__(WT) kv_tree(GroupArgs g) {
                                               nullptr, nullptr, lam, w);
             }
             if (it.last && l < NX) slot(it.term_slot)[SL.xh() + l] = S.x[l];
+            if (top && g.superpose) {
+                // terminal costate of child s, lam_{s+1} = P_{s+1} x_{s+1} -
+                // Psi_{s+1}, from the cost to go sent to it and the initial
+                // state of the next child (of the terminal node for the last)
+                __threadfence_block();
+                wsync();
+                for (int s = 0; s < count; ++s) {
+                    double *sl = slot(it.first + s);
+                    const double *xn = (s + 1 < count ? slot(it.first + s + 1) : slot(it.term_slot)) + SL.xh();
+                    if (l < NX) S.fv[l] = xn[l];
+                    wsync();
+                    Op<NX, NX> oP;
+                    oP.template load<false>(sl + SL.P(), NX);
+                    const double v = oP.apply(S.fv);
+                    if (l < NX) sl[SL.lamN() + l] = v - sl[SL.Psi() + l];
+                    wsync();
+                }
+            }
         }
         __threadfence();
         wsync();

@@ -181,10 +181,10 @@ struct GroupArgs {
     // leaf-chunked solves: stage index (in the group's leaf stage numbering)
     // of the first record held by the stored factorization of this launch
     int64_t rec_stage0;
-    // large-block master levels: 1 = the down pass of every master
-    // subproblem below the top is the superposition sweep on its up records
-    // (Alg. 6 without a second factorization), 0 = factored again with the
-    // parent's message
+    // master levels of the stored factorization: 1 = the down pass of every
+    // master subproblem below the top is the superposition sweep on its up
+    // records (Alg. 6 without a second factorization), 0 = factored again
+    // with the parent's message
     int32_t superpose;
     // first stage of a leaf's records in the stored factorization
     __host__ __device__ int64_t rec_stage(int64_t leaf_scratch) const { return leaf_scratch / sps - rec_stage0; }

@@ -43,6 +43,38 @@ def _new_rhs(prob, seed):
     return q
 
 
+@pytest.mark.parametrize("refactor", [False, True])
+@pytest.mark.parametrize("nx,nu,N,Ns,b,rr,mixed", [(32, 16, 512, 4, 2, False, False),
+                                                   (16, 16, 301, 4, 3, True, False),
+                                                   (32, 32, 257, 4, 2, False, True),
+                                                   (32, 16, 600, 8, 3, False, True)])
+def test_master_down_pass_forms(nx, nu, N, Ns, b, rr, mixed, refactor):
+    """Down pass of the master levels below the top on the matrix-core
+    stored factorization: the superposition sweep on the records of the up
+    pass (default) and the second factorization from the parent's message
+    (RS_PLAN_REFACTOR_DOWN), on trees of four to seven levels with interior
+    and last items, plain and rank-revealing master stages, FP64 (factor,
+    then solve) and mixed.  Both against the oracle, and against each other."""
+    prob = W.with_costs(W.g2(nx, nu, N, seed=3 * N + nx), seed=N + 2)
+    torch, rs = _rs()
+    sols = []
+    for flags in ((rs.RS_PLAN_REFACTOR_DOWN if refactor else 0), rs.RS_PLAN_REFACTOR_DOWN):
+        _, bt = _batch([prob], Ns=Ns, branch=b, rank_reveal=rr, flags=flags,
+                       precision=rs.RS_MIXED_FP32 if mixed else rs.RS_FP64)
+        if mixed:
+            bt.solve()
+        else:
+            bt.factor()
+            bt.solve_factored()
+        torch.cuda.synchronize()
+        assert bt.status()[0, 0] == 0
+        sols.append(bt.result(0))
+        bt.close()
+    _check(prob, sols[0])
+    if not refactor:
+        assert kkt.rel_error(sols[0], sols[1]) <= TOL
+
+
 @pytest.mark.parametrize("nx,nu,N,Ns,b", [(16, 16, 96, 4, 3), (32, 16, 200, 8, 2), (32, 32, 77, 4, 4),
                                           (32, 16, 1024, 16, 4), (16, 16, 13, 16, 2), (16, 16, 17, 4, 2)])
 def test_factor_then_solve_matches_oracle(nx, nu, N, Ns, b):
