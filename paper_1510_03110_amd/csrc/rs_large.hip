@@ -130,47 +130,187 @@ __device__ __forceinline__ void wave_gfence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// C = opA(A) opB(B): M x N, inner size K (any sizes; edge tiles are padded
-// with zeros on load).  opA(i,k) = TA ? A[k*lda+i] : A[i*lda+k], opB(k,j) =
-// TB ? B[j*ldb+k] : B[k*ldb+j].  16x16 tile t goes to wave t mod 4; every
-// element (i, j) of the result with i < M, j < N is handed to epi(i, j, c).
-// With `lower` (square results) only the tiles on and below the diagonal are
-// formed, and epi must use the elements with i >= j.
-template <bool TA, bool TB, class T, class Epi>
-__device__ __forceinline__ void gemm(int M, int N, int K, const T *__restrict__ A, int lda, const T *__restrict__ B,
-                                     int ldb, bool lower, Epi epi) {
-    const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
-    const int nt = lower ? tm * (tm + 1) / 2 : tm * tn;
-    const int l = lane(), r16 = l & 15, k4 = l >> 4;
-    for (int t = wave(); t < nt; t += nwav()) {
-        int ti, tj;
-        if (lower) {
-            mf::lower_tile(t, ti, tj);
-        } else {
-            ti = t / tn;
-            tj = t - ti * tn;
-        }
-        const int i = 16 * ti + r16, j = 16 * tj + r16;
-        const bool iv = i < M, jv = j < N;
-        v4_t<T> acc = mf::zero4<T>();
-#pragma unroll 2
-        for (int k0 = 0; k0 < K; k0 += 16) {
-            T a[4], b[4];
+// Where the result of a large-block product goes: element (i, j) of
+// v = sgn * opA(A) opB(B) + D is stored to C and, when given, to the record R;
+// with `sym` (the lower products of symmetric results, i >= j) also to (j, i).
+// D is problem data (FP64) or a workspace matrix (element type T), or none.
+template <class T>
+struct Ep {
+    T *C = nullptr;
+    int ldc = 0;
+    const double *D64 = nullptr;
+    const T *DT = nullptr;
+    int ldd = 0;
+    T sgn = T(1);
+    bool sym = false;
+    T *R = nullptr;
+    int ldr = 0;
+};
+
+// Global-memory views of the operands of an out-of-line product (its pointer
+// arguments would otherwise be generic, and generic loads are also counted
+// with the LDS accesses).
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gview(const T *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gview(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
+template <class T>
+__device__ __forceinline__ void put(const Ep<T> &e, int i, int j, T c) {
+    T v = e.sgn * c;
+    if (e.D64)
+        v += (T)gview(e.D64)[(int64_t)i * e.ldd + j];
+    else if (e.DT)
+        v += gview(e.DT)[(int64_t)i * e.ldd + j];
+    if (e.C) {
+        gview(e.C)[(int64_t)i * e.ldc + j] = v;
+        if (e.sym) gview(e.C)[(int64_t)j * e.ldc + i] = v;
+    }
+    if (e.R) {
+        gview(e.R)[(int64_t)i * e.ldr + j] = v;
+        if (e.sym && i != j) gview(e.R)[(int64_t)j * e.ldr + i] = v;
+    }
+}
+
+// Operand panels of the large-block products, staged in LDS: a 16-wide
+// inner panel of A (up to 128 rows, row pitch 17) and of B (16 rows of up to
+// 128 columns, pitch 144), shared by every wavefront of the workgroup.  The
+// pitches keep the MFMA operand reads nearly free of bank conflicts: rows of
+// the A panel 17 doubles apart fall on distinct banks for the 16 lanes of a
+// row group, and the two row groups of a half-wave read B rows 32 banks apart.
+constexpr int GP_K = 16, GP_M = 128, GP_N = 128, GP_AP = GP_K + 1, GP_BP = GP_N + 16;
+constexpr int GP_ELEMS = GP_M * GP_AP + GP_K * GP_BP;
+__shared__ double gp_sm[GP_ELEMS];
+
+// C = opA(A) opB(B): M x N (M <= 128, any N; with `lower` square and
+// N <= 128), inner size K; the result goes through the epilogue `ep`.
+// opA(i,k) = TA ? A[k*lda+i] : A[i*lda+k], opB(k,j) = TB ? B[j*ldb+k] :
+// B[k*ldb+j].  The result is formed in column chunks of up to 128; for each
+// chunk the workgroup walks the inner dimension in panels of 16: its threads
+// load the A and B panels (zero-padded to whole 16 x 16 tiles, loads laid out
+// along the operand's contiguous direction) into LDS, and each wavefront
+// accumulates its 16 x 16 tiles (tile t goes to wave t mod 8, at most 8 per
+// wave) from there while the next panel's loads are in flight: one memory
+// round trip per panel of 16 for every tile of the chunk at once, where a
+// tile that read its own operand strips needed one per 32 of inner size.
+// With `lower` only the tiles on and below the diagonal are formed and only
+// the elements with i >= j are put.  One out-of-line body per operand
+// layout keeps the stage's code within the instruction cache.  Every thread
+// of the workgroup must call it (it synchronizes the workgroup).
+template <bool TA, bool TB, class T>
+__device__ __attribute__((noinline)) void gemm(int M, int N, int K, const T *A, int lda, const T *B, int ldb,
+                                               bool lower, Ep<T> ep) {
+    static_assert(LB_MT == 512, "eight wavefronts: at most eight 16 x 16 tiles of a chunk per wave");
+    constexpr int QMAX = (GP_M / 16) * (GP_N / 16) / (LB_MT / 64);
+    constexpr int EA = GP_M * GP_K / LB_MT, EB = GP_K * GP_N / LB_MT;
+    const auto gA = gview(A);
+    const auto gB = gview(B);
+    T *As = reinterpret_cast<T *>(gp_sm), *Bs = As + GP_M * GP_AP;
+    const int tid = threadIdx.x, w = wave(), l = lane(), r16 = l & 15, k4 = l >> 4;
+    const int tm = (M + 15) >> 4, Mp = 16 * tm;
+    for (int n0 = 0; n0 < N; n0 += GP_N) {
+        const int NC = N - n0 < GP_N ? N - n0 : GP_N, tn = (NC + 15) >> 4, Np = 16 * tn;
+        const int nt = lower ? tm * (tm + 1) / 2 : tm * tn;
+        int ti[QMAX], tj[QMAX];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int k = k0 + 4 * s + k4;
-                a[s] = (iv && k < K) ? (TA ? A[(int64_t)k * lda + i] : A[(int64_t)i * lda + k]) : T(0);
-                b[s] = (jv && k < K) ? (TB ? B[(int64_t)j * ldb + k] : B[(int64_t)k * ldb + j]) : T(0);
+        for (int q = 0; q < QMAX; ++q) {
+            const int t = w + 8 * q;
+            if (lower) {
+                mf::lower_tile(t < nt ? t : 0, ti[q], tj[q]);
+            } else {
+                ti[q] = t / tn;
+                tj[q] = t - ti[q] * tn;
+            }
+        }
+        v4_t<T> acc[QMAX];
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) acc[q] = mf::zero4<T>();
+        // panel element e of A: (row, inner index) along A's contiguous
+        // direction; of B: (inner index, column) along B's
+        auto a_at = [&](int e, int &m, int &kk) {
+            if (TA) {
+                kk = e / Mp;
+                m = e - kk * Mp;
+            } else {
+                m = e >> 4;
+                kk = e & 15;
+            }
+        };
+        auto b_at = [&](int e, int &kk, int &n) {
+            if (TB) {
+                n = e >> 4;
+                kk = e & 15;
+            } else {
+                kk = e / Np;
+                n = e - kk * Np;
+            }
+        };
+        T ra[EA], rb[EB];
+        auto fetch = [&](int k0) {
+#pragma unroll
+            for (int u = 0; u < EA; ++u) {
+                const int e = tid + u * LB_MT;
+                int m, kk;
+                a_at(e, m, kk);
+                const int k = k0 + kk;
+                ra[u] = (e < Mp * GP_K && m < M && k < K) ? (TA ? gA[(int64_t)k * lda + m] : gA[(int64_t)m * lda + k])
+                                                          : T(0);
             }
 #pragma unroll
-            for (int s = 0; s < 4; ++s) acc = MT<T>::mfma(a[s], b[s], acc);
+            for (int u = 0; u < EB; ++u) {
+                const int e = tid + u * LB_MT;
+                int kk, n;
+                b_at(e, kk, n);
+                const int k = k0 + kk, j = n0 + n;
+                rb[u] = (e < Np * GP_K && n < NC && k < K) ? (TB ? gB[(int64_t)j * ldb + k] : gB[(int64_t)k * ldb + j])
+                                                           : T(0);
+            }
+        };
+        fetch(0);
+        for (int k0 = 0; k0 < K; k0 += GP_K) {
+            __syncthreads();      // every wave is done with the previous panel
+#pragma unroll
+            for (int u = 0; u < EA; ++u) {
+                const int e = tid + u * LB_MT;
+                int m, kk;
+                a_at(e, m, kk);
+                if (e < Mp * GP_K) As[m * GP_AP + kk] = ra[u];
+            }
+#pragma unroll
+            for (int u = 0; u < EB; ++u) {
+                const int e = tid + u * LB_MT;
+                int kk, n;
+                b_at(e, kk, n);
+                if (e < Np * GP_K) Bs[kk * GP_BP + n] = rb[u];
+            }
+            __syncthreads();
+            if (k0 + GP_K < K) fetch(k0 + GP_K);
+#pragma unroll
+            for (int q = 0; q < QMAX; ++q) {
+                if (w + 8 * q < nt) {
+                    const T *ap = As + (16 * ti[q] + r16) * GP_AP + k4;
+                    const T *bp = Bs + k4 * GP_BP + 16 * tj[q] + r16;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) acc[q] = MT<T>::mfma(ap[4 * s], bp[4 * s * GP_BP], acc[q]);
+                }
+            }
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int ii = mf::trow<T>(ti, r), jj = mf::tcol(tj);
-            if (ii < M && jj < N) epi(ii, jj, acc[r]);
+        for (int q = 0; q < QMAX; ++q) {
+            if (w + 8 * q < nt) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = mf::trow<T>(ti[q], r), j = n0 + mf::tcol(tj[q]);
+                    if (i < M && j < N && (!lower || i >= j)) put(ep, i, j, acc[q][r]);
+                }
+            }
         }
     }
+    __syncthreads();      // the results are visible to the workgroup
 }
 
 // BF16 operands (round to nearest even of the FP32 value; finite inputs).
@@ -183,9 +323,9 @@ __device__ __forceinline__ short to_bf16(float x) {
 // gemm with operands rounded to BF16 and FP32 accumulation
 // (v_mfma_f32_16x16x16_bf16: lane l holds A(l % 16, 4 (l / 16) + q) and
 // B(4 (l / 16) + q, l % 16), q = 0..3; the result layout is the FP32 one).
-template <bool TA, bool TB, class Epi>
+template <bool TA, bool TB>
 __device__ __forceinline__ void gemm_bf16(int M, int N, int K, const float *__restrict__ A, int lda,
-                                          const float *__restrict__ B, int ldb, bool lower, Epi epi) {
+                                          const float *__restrict__ B, int ldb, bool lower, const Ep<float> &ep) {
     typedef short s4 __attribute__((ext_vector_type(4)));
     const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
     const int nt = lower ? tm * (tm + 1) / 2 : tm * tn;
@@ -216,19 +356,29 @@ __device__ __forceinline__ void gemm_bf16(int M, int N, int K, const float *__re
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int ii = mf::trow<float>(ti, r), jj = mf::tcol(tj);
-            if (ii < M && jj < N) epi(ii, jj, acc[r]);
+            if (ii < M && jj < N && (!lower || ii >= jj)) put(ep, ii, jj, acc[r]);
         }
     }
 }
 
 // The products of the stage that may run on BF16 operands.
-template <bool BF, bool TA, bool TB, class T, class Epi>
+template <bool BF, bool TA, bool TB, class T>
 __device__ __forceinline__ void gemm_big(int M, int N, int K, const T *A, int lda, const T *B, int ldb, bool lower,
-                                         Epi epi) {
+                                         const Ep<T> &ep) {
     if constexpr (BF)
-        gemm_bf16<TA, TB>(M, N, K, A, lda, B, ldb, lower, epi);
+        gemm_bf16<TA, TB>(M, N, K, A, lda, B, ldb, lower, ep);
     else
-        gemm<TA, TB>(M, N, K, A, lda, B, ldb, lower, epi);
+        gemm<TA, TB>(M, N, K, A, lda, B, ldb, lower, ep);
+}
+
+// Epilogue descriptors: store to C (leading dimension ldc); plus a
+// symmetric addend, a sign or a record copy.
+template <class T>
+__device__ __forceinline__ Ep<T> to(T *C, int ldc) {
+    Ep<T> e;
+    e.C = C;
+    e.ldc = ldc;
+    return e;
 }
 
 // acc += opA(A) opB(B) for one 16 x 16 x 16 block with only the first ri
@@ -346,6 +496,11 @@ struct LeafOut {
     __device__ void K(int s, int i, int j, T v) const { at(s)[LeafRec{n, m}.K() + i * n + j] = v; }
     __device__ void V(int s, int i, int j, T v) const { at(s)[LeafRec{n, m}.V() + i * n + j] = v; }
     __device__ void Lt(int s, int i, int j, T v) const { at(s)[LeafRec{n, m}.Lt() + i * n + j] = v; }
+    // the records of stage s that the products write (row length n)
+    __device__ T *Prec(int s) const { return at(s) + LeafRec{n, m}.P(); }
+    __device__ T *Krec(int s) const { return at(s) + LeafRec{n, m}.K(); }
+    __device__ T *Vrec(int s) const { return up ? at(s) + LeafRec{n, m}.V() : nullptr; }
+    __device__ T *Ltrec(int s) const { return up ? at(s) + LeafRec{n, m}.Lt() : nullptr; }
     __device__ void L(int s, const T *Li, const T *LiT) const {
         T *d = at(s);
         const LeafRec R{n, m};
@@ -377,6 +532,11 @@ struct SlotOut {
     __device__ void Lt(int s, int i, int j, double v) const {
         if (lt) at(s)[SlotLayout{n}.dL() + i * n + j] = v;
     }
+    // the records of stage s that the products write (row length n)
+    __device__ double *Prec(int s) const { return up ? at(s) + SlotLayout{n}.uP() : nullptr; }
+    __device__ double *Krec(int s) const { return at(s) + (up ? SlotLayout{n}.uK() : SlotLayout{n}.K()); }
+    __device__ double *Vrec(int s) const { return up ? at(s) + SlotLayout{n}.uV() : nullptr; }
+    __device__ double *Ltrec(int s) const { return lt ? at(s) + SlotLayout{n}.dL() : nullptr; }
     __device__ void L(int s, const double *Li, const double *LiT) const {
         double *d = at(s);
         const SlotLayout SL{n};
@@ -407,32 +567,33 @@ __device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int
         }
         __syncthreads();
         // W = P [A B]; Alg. 4: B'V, A'V
-        gemm_big<BF, false, false>(n, nw, n, S.P, n, S.AB, nw, false,
-                                   [&](int i, int j, T c) { S.W[(int64_t)i * nw + j] = c; });
+        gemm_big<BF, false, false>(n, nw, n, S.P, n, S.AB, nw, false, to(S.W, nw));
         if constexpr (RED) {
-            gemm<true, false>(m, n, n, S.AB + n, nw, S.V, n, false,
-                              [&](int i, int j, T c) { S.BV[(int64_t)i * n + j] = c; });
-            gemm<true, false>(n, n, n, S.AB, nw, S.V, n, false, [&](int i, int j, T c) { S.AV[(int64_t)i * n + j] = c; });
+            gemm<true, false>(m, n, n, S.AB + n, nw, S.V, n, false, to(S.BV, n));
+            gemm<true, false>(n, n, n, S.AB, nw, S.V, n, false, to(S.AV, n));
         }
         __syncthreads();
         // F = Qx + A'W_A (symmetric), H = Qxw + A'W_B, G = Qw + B'W_B (symmetric)
-        gemm_big<BF, true, false>(n, n, n, S.AB, nw, S.W, nw, true, [&](int i, int j, T c) {
-            if (i >= j) {
-                const T v = (T)src.Qx[(int64_t)i * n + j] + c;
-                S.F[(int64_t)i * n + j] = v;
-                S.F[(int64_t)j * n + i] = v;
-            }
-        });
-        gemm_big<BF, true, false>(n, m, n, S.AB, nw, S.W + n, nw, false, [&](int i, int j, T c) {
-            S.H[(int64_t)i * m + j] = (src.Qxw ? (T)src.Qxw[(int64_t)i * m + j] : T(0)) + c;
-        });
-        gemm_big<BF, true, false>(m, m, n, S.AB + n, nw, S.W + n, nw, true, [&](int i, int j, T c) {
-            if (i >= j) {
-                const T v = (T)src.Qw[(int64_t)i * m + j] + c;
-                S.G[(int64_t)i * m + j] = v;
-                S.G[(int64_t)j * m + i] = v;
-            }
-        });
+        {
+            Ep<T> e = to(S.F, n);
+            e.D64 = src.Qx;
+            e.ldd = n;
+            e.sym = true;
+            gemm_big<BF, true, false>(n, n, n, S.AB, nw, S.W, nw, true, e);
+        }
+        {
+            Ep<T> e = to(S.H, m);
+            e.D64 = src.Qxw;
+            e.ldd = m;
+            gemm_big<BF, true, false>(n, m, n, S.AB, nw, S.W + n, nw, false, e);
+        }
+        {
+            Ep<T> e = to(S.G, m);
+            e.D64 = src.Qw;
+            e.ldd = m;
+            e.sym = true;
+            gemm_big<BF, true, false>(m, m, n, S.AB + n, nw, S.W + n, nw, true, e);
+        }
         __syncthreads();
         chol_inv(S, m, bad);
         if (tid == 0 && *bad) {
@@ -441,37 +602,48 @@ __device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int
         }
         out.L(s, S.Li, S.LiT);
         // Y' = H L^{-T}; Alg. 4: X = L^{-1} B'V
-        gemm<false, false>(n, m, m, S.H, m, S.LiT, m, false, [&](int i, int j, T c) { S.HY[(int64_t)i * m + j] = c; });
-        if constexpr (RED) {
-            gemm<false, false>(m, n, m, S.Li, m, S.BV, n, false, [&](int i, int j, T c) { S.X[(int64_t)i * n + j] = c; });
-        }
+        gemm<false, false>(n, m, m, S.H, m, S.LiT, m, false, to(S.HY, m));
+        if constexpr (RED) gemm<false, false>(m, n, m, S.Li, m, S.BV, n, false, to(S.X, n));
         __syncthreads();
         // P = F - Y'Y (symmetric), K = -L^{-T} Y
-        gemm<false, true>(n, n, m, S.HY, m, S.HY, m, true, [&](int i, int j, T c) {
-            if (i >= j) {
-                const T v = S.F[(int64_t)i * n + j] - c;
-                S.P[(int64_t)i * n + j] = v;
-                S.P[(int64_t)j * n + i] = v;
-                out.P(s, i, j, v);
-                out.P(s, j, i, v);
-            }
-        });
-        gemm<false, true>(m, n, m, S.LiT, m, S.HY, m, false, [&](int i, int j, T c) { out.K(s, i, j, -c); });
+        {
+            Ep<T> e = to(S.P, n);
+            e.DT = S.F;
+            e.ldd = n;
+            e.sgn = T(-1);
+            e.sym = true;
+            e.R = out.Prec(s);
+            e.ldr = n;
+            gemm<false, true>(n, n, m, S.HY, m, S.HY, m, true, e);
+        }
+        {
+            Ep<T> e = to(out.Krec(s), n);
+            e.sgn = T(-1);
+            gemm<false, true>(m, n, m, S.LiT, m, S.HY, m, false, e);
+        }
         if constexpr (RED) {
             // Q_w_hat += X'X, V = A'V - Y'X, L_t = -L^{-T} X
-            gemm<true, false>(n, n, m, S.X, n, S.X, n, true, [&](int i, int j, T c) {
-                if (i >= j) {
-                    const T v = S.Qh[(int64_t)i * n + j] + c;
-                    S.Qh[(int64_t)i * n + j] = v;
-                    S.Qh[(int64_t)j * n + i] = v;
-                }
-            });
-            gemm<false, false>(n, n, m, S.HY, m, S.X, n, false, [&](int i, int j, T c) {
-                const T v = S.AV[(int64_t)i * n + j] - c;
-                S.V[(int64_t)i * n + j] = v;
-                out.V(s, i, j, v);
-            });
-            gemm<false, false>(m, n, m, S.LiT, m, S.X, n, false, [&](int i, int j, T c) { out.Lt(s, i, j, -c); });
+            {
+                Ep<T> e = to(S.Qh, n);
+                e.DT = S.Qh;
+                e.ldd = n;
+                e.sym = true;
+                gemm<true, false>(n, n, m, S.X, n, S.X, n, true, e);
+            }
+            {
+                Ep<T> e = to(S.V, n);
+                e.DT = S.AV;
+                e.ldd = n;
+                e.sgn = T(-1);
+                e.R = out.Vrec(s);
+                e.ldr = n;
+                gemm<false, false>(n, n, m, S.HY, m, S.X, n, false, e);
+            }
+            {
+                Ep<T> e = to(out.Ltrec(s), n);
+                e.sgn = T(-1);
+                gemm<false, false>(m, n, m, S.LiT, m, S.X, n, false, e);
+            }
         }
         __syncthreads();
     }
