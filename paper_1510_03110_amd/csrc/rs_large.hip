@@ -184,6 +184,8 @@ __device__ __forceinline__ void put(const Ep<T> &e, int i, int j, T c) {
 // row group, and the two row groups of a half-wave read B rows 32 banks apart.
 constexpr int GP_K = 16, GP_M = 128, GP_N = 128, GP_AP = GP_K + 1, GP_BP = GP_N + 16;
 constexpr int GP_ELEMS = GP_M * GP_AP + GP_K * GP_BP;
+// products with fewer 16 x 16 tiles than this take the per-tile form
+constexpr int GP_MIN_TILES = 32;
 __shared__ double gp_sm[GP_ELEMS];
 
 // C = opA(A) opB(B): M x N (M <= 128, any N; with `lower` square and
@@ -198,12 +200,14 @@ __shared__ double gp_sm[GP_ELEMS];
 // round trip per panel of 16 for every tile of the chunk at once, where a
 // tile that read its own operand strips needed one per 32 of inner size.
 // With `lower` only the tiles on and below the diagonal are formed and only
-// the elements with i >= j are put.  One out-of-line body per operand
+// the elements with i >= j are put.  Small products (fewer than
+// GP_MIN_TILES tiles: every product at n_x <= 64) skip the panels, and each
+// wave reads its tiles' operand strips itself.  One out-of-line body per operand
 // layout keeps the stage's code within the instruction cache.  Every thread
 // of the workgroup must call it (it synchronizes the workgroup).
 template <bool TA, bool TB, class T>
-__device__ __attribute__((noinline)) void gemm(int M, int N, int K, const T *A, int lda, const T *B, int ldb,
-                                               bool lower, Ep<T> ep) {
+__device__ __attribute__((noinline)) void gemm_panel(int M, int N, int K, const T *A, int lda, const T *B, int ldb,
+                                                     bool lower, Ep<T> ep) {
     static_assert(LB_MT == 512, "eight wavefronts: at most eight 16 x 16 tiles of a chunk per wave");
     constexpr int QMAX = (GP_M / 16) * (GP_N / 16) / (LB_MT / 64);
     constexpr int EA = GP_M * GP_K / LB_MT, EB = GP_K * GP_N / LB_MT;
@@ -212,6 +216,42 @@ __device__ __attribute__((noinline)) void gemm(int M, int N, int K, const T *A, 
     T *As = reinterpret_cast<T *>(gp_sm), *Bs = As + GP_M * GP_AP;
     const int tid = threadIdx.x, w = wave(), l = lane(), r16 = l & 15, k4 = l >> 4;
     const int tm = (M + 15) >> 4, Mp = 16 * tm;
+    if ((lower ? tm * (tm + 1) / 2 : tm * ((N + 15) >> 4)) < GP_MIN_TILES) {
+        // small product: each wave forms its tiles from operand strips read
+        // straight from memory (no barriers; the panels would cost more in
+        // synchronization than they save)
+        const int tn = (N + 15) >> 4, nt = lower ? tm * (tm + 1) / 2 : tm * tn;
+        for (int t = w; t < nt; t += LB_MT / 64) {
+            int ti, tj;
+            if (lower) {
+                mf::lower_tile(t, ti, tj);
+            } else {
+                ti = t / tn;
+                tj = t - ti * tn;
+            }
+            const int i = 16 * ti + r16, j = 16 * tj + r16;
+            const bool iv = i < M, jv = j < N;
+            v4_t<T> acc = mf::zero4<T>();
+#pragma unroll 2
+            for (int k0 = 0; k0 < K; k0 += 16) {
+                T a[4], b[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int k = k0 + 4 * s + k4;
+                    a[s] = (iv && k < K) ? (TA ? gA[(int64_t)k * lda + i] : gA[(int64_t)i * lda + k]) : T(0);
+                    b[s] = (jv && k < K) ? (TB ? gB[(int64_t)j * ldb + k] : gB[(int64_t)k * ldb + j]) : T(0);
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc = MT<T>::mfma(a[s], b[s], acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ii = mf::trow<T>(ti, r), jj = mf::tcol(tj);
+                if (ii < M && jj < N && (!lower || ii >= jj)) put(ep, ii, jj, acc[r]);
+            }
+        }
+        return;
+    }
     for (int n0 = 0; n0 < N; n0 += GP_N) {
         const int NC = N - n0 < GP_N ? N - n0 : GP_N, tn = (NC + 15) >> 4, Np = 16 * tn;
         const int nt = lower ? tm * (tm + 1) / 2 : tm * tn;
@@ -313,6 +353,51 @@ __device__ __attribute__((noinline)) void gemm(int M, int N, int K, const T *A, 
     __syncthreads();      // the results are visible to the workgroup
 }
 
+// Stages with n_x <= 64 (products of at most 24 tiles), inline with the
+// epilogue as a functor:
+// C = opA(A) opB(B): M x N, inner size K (any sizes; edge tiles are padded
+// with zeros on load).  opA(i,k) = TA ? A[k*lda+i] : A[i*lda+k], opB(k,j) =
+// TB ? B[j*ldb+k] : B[k*ldb+j].  16x16 tile t goes to wave t mod 4; every
+// element (i, j) of the result with i < M, j < N is handed to epi(i, j, c).
+// With `lower` (square results) only the tiles on and below the diagonal are
+// formed, and epi must use the elements with i >= j.
+template <bool TA, bool TB, class T, class Epi>
+__device__ __forceinline__ void gemm_tile(int M, int N, int K, const T *__restrict__ A, int lda, const T *__restrict__ B,
+                                     int ldb, bool lower, Epi epi) {
+    const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
+    const int nt = lower ? tm * (tm + 1) / 2 : tm * tn;
+    const int l = lane(), r16 = l & 15, k4 = l >> 4;
+    for (int t = wave(); t < nt; t += nwav()) {
+        int ti, tj;
+        if (lower) {
+            mf::lower_tile(t, ti, tj);
+        } else {
+            ti = t / tn;
+            tj = t - ti * tn;
+        }
+        const int i = 16 * ti + r16, j = 16 * tj + r16;
+        const bool iv = i < M, jv = j < N;
+        v4_t<T> acc = mf::zero4<T>();
+#pragma unroll 2
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            T a[4], b[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = k0 + 4 * s + k4;
+                a[s] = (iv && k < K) ? (TA ? A[(int64_t)k * lda + i] : A[(int64_t)i * lda + k]) : T(0);
+                b[s] = (jv && k < K) ? (TB ? B[(int64_t)j * ldb + k] : B[(int64_t)k * ldb + j]) : T(0);
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc = MT<T>::mfma(a[s], b[s], acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ii = mf::trow<T>(ti, r), jj = mf::tcol(tj);
+            if (ii < M && jj < N) epi(ii, jj, acc[r]);
+        }
+    }
+}
+
 // BF16 operands (round to nearest even of the FP32 value; finite inputs).
 __device__ __forceinline__ short to_bf16(float x) {
     unsigned u = __float_as_uint(x);
@@ -323,9 +408,9 @@ __device__ __forceinline__ short to_bf16(float x) {
 // gemm with operands rounded to BF16 and FP32 accumulation
 // (v_mfma_f32_16x16x16_bf16: lane l holds A(l % 16, 4 (l / 16) + q) and
 // B(4 (l / 16) + q, l % 16), q = 0..3; the result layout is the FP32 one).
-template <bool TA, bool TB>
+template <bool TA, bool TB, class Epi>
 __device__ __forceinline__ void gemm_bf16(int M, int N, int K, const float *__restrict__ A, int lda,
-                                          const float *__restrict__ B, int ldb, bool lower, const Ep<float> &ep) {
+                                          const float *__restrict__ B, int ldb, bool lower, Epi epi) {
     typedef short s4 __attribute__((ext_vector_type(4)));
     const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
     const int nt = lower ? tm * (tm + 1) / 2 : tm * tn;
@@ -356,19 +441,29 @@ __device__ __forceinline__ void gemm_bf16(int M, int N, int K, const float *__re
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int ii = mf::trow<float>(ti, r), jj = mf::tcol(tj);
-            if (ii < M && jj < N && (!lower || ii >= jj)) put(ep, ii, jj, acc[r]);
+            if (ii < M && jj < N) epi(ii, jj, acc[r]);
         }
     }
 }
 
 // The products of the stage that may run on BF16 operands.
-template <bool BF, bool TA, bool TB, class T>
+template <bool BF, bool TA, bool TB, class T, class Epi>
 __device__ __forceinline__ void gemm_big(int M, int N, int K, const T *A, int lda, const T *B, int ldb, bool lower,
-                                         const Ep<T> &ep) {
+                                         Epi epi) {
     if constexpr (BF)
-        gemm_bf16<TA, TB>(M, N, K, A, lda, B, ldb, lower, ep);
+        gemm_bf16<TA, TB>(M, N, K, A, lda, B, ldb, lower, epi);
     else
-        gemm<TA, TB>(M, N, K, A, lda, B, ldb, lower, ep);
+        gemm_tile<TA, TB>(M, N, K, A, lda, B, ldb, lower, epi);
+}
+template <bool BF, bool TA, bool TB, class T>
+__device__ __forceinline__ void gemm_big_panel(int M, int N, int K, const T *A, int lda, const T *B, int ldb,
+                                               bool lower, const Ep<T> &ep) {
+    if constexpr (BF)
+        gemm_bf16<TA, TB>(M, N, K, A, lda, B, ldb, lower, [&](int i, int j, float c) {
+            if (!lower || i >= j) put(ep, i, j, c);
+        });
+    else
+        gemm_panel<TA, TB>(M, N, K, A, lda, B, ldb, lower, ep);
 }
 
 // Epilogue descriptors: store to C (leading dimension ldc); plus a
@@ -553,7 +648,7 @@ struct SlotOut {
 // from the P in the workspace.  pre(s) runs before stage s and sees P_{s+1}.
 // BF: P [A B], A'W_A, A'W_B and B'W_B (A'PA, A'PB, B'PB) on BF16 operands.
 template <class T, bool RED, bool BF, class Get, class Pre, class Out>
-__device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int stage_base, int fail_code, Pre pre,
+__device__ void mpass_tile(WS<T> &S, Get get, int count, int32_t *info, int inst, int stage_base, int fail_code, Pre pre,
                       const Out &out, int *bad) {
     static_assert(!BF || sizeof(T) == 4, "BF16 products accumulate in FP32");
     const int n = S.n, m = S.m, nw = S.nw, tid = threadIdx.x;
@@ -567,10 +662,97 @@ __device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int
         }
         __syncthreads();
         // W = P [A B]; Alg. 4: B'V, A'V
-        gemm_big<BF, false, false>(n, nw, n, S.P, n, S.AB, nw, false, to(S.W, nw));
+        gemm_big<BF, false, false>(n, nw, n, S.P, n, S.AB, nw, false,
+                                   [&](int i, int j, T c) { S.W[(int64_t)i * nw + j] = c; });
         if constexpr (RED) {
-            gemm<true, false>(m, n, n, S.AB + n, nw, S.V, n, false, to(S.BV, n));
-            gemm<true, false>(n, n, n, S.AB, nw, S.V, n, false, to(S.AV, n));
+            gemm_tile<true, false>(m, n, n, S.AB + n, nw, S.V, n, false,
+                              [&](int i, int j, T c) { S.BV[(int64_t)i * n + j] = c; });
+            gemm_tile<true, false>(n, n, n, S.AB, nw, S.V, n, false, [&](int i, int j, T c) { S.AV[(int64_t)i * n + j] = c; });
+        }
+        __syncthreads();
+        // F = Qx + A'W_A (symmetric), H = Qxw + A'W_B, G = Qw + B'W_B (symmetric)
+        gemm_big<BF, true, false>(n, n, n, S.AB, nw, S.W, nw, true, [&](int i, int j, T c) {
+            if (i >= j) {
+                const T v = (T)src.Qx[(int64_t)i * n + j] + c;
+                S.F[(int64_t)i * n + j] = v;
+                S.F[(int64_t)j * n + i] = v;
+            }
+        });
+        gemm_big<BF, true, false>(n, m, n, S.AB, nw, S.W + n, nw, false, [&](int i, int j, T c) {
+            S.H[(int64_t)i * m + j] = (src.Qxw ? (T)src.Qxw[(int64_t)i * m + j] : T(0)) + c;
+        });
+        gemm_big<BF, true, false>(m, m, n, S.AB + n, nw, S.W + n, nw, true, [&](int i, int j, T c) {
+            if (i >= j) {
+                const T v = (T)src.Qw[(int64_t)i * m + j] + c;
+                S.G[(int64_t)i * m + j] = v;
+                S.G[(int64_t)j * m + i] = v;
+            }
+        });
+        __syncthreads();
+        chol_inv(S, m, bad);
+        if (tid == 0 && *bad) {
+            record_failure(info, inst, fail_code, stage_base < 0 ? -1 : stage_base + s);
+            *bad = 0;
+        }
+        out.L(s, S.Li, S.LiT);
+        // Y' = H L^{-T}; Alg. 4: X = L^{-1} B'V
+        gemm_tile<false, false>(n, m, m, S.H, m, S.LiT, m, false, [&](int i, int j, T c) { S.HY[(int64_t)i * m + j] = c; });
+        if constexpr (RED) {
+            gemm_tile<false, false>(m, n, m, S.Li, m, S.BV, n, false, [&](int i, int j, T c) { S.X[(int64_t)i * n + j] = c; });
+        }
+        __syncthreads();
+        // P = F - Y'Y (symmetric), K = -L^{-T} Y
+        gemm_tile<false, true>(n, n, m, S.HY, m, S.HY, m, true, [&](int i, int j, T c) {
+            if (i >= j) {
+                const T v = S.F[(int64_t)i * n + j] - c;
+                S.P[(int64_t)i * n + j] = v;
+                S.P[(int64_t)j * n + i] = v;
+                out.P(s, i, j, v);
+                out.P(s, j, i, v);
+            }
+        });
+        gemm_tile<false, true>(m, n, m, S.LiT, m, S.HY, m, false, [&](int i, int j, T c) { out.K(s, i, j, -c); });
+        if constexpr (RED) {
+            // Q_w_hat += X'X, V = A'V - Y'X, L_t = -L^{-T} X
+            gemm_tile<true, false>(n, n, m, S.X, n, S.X, n, true, [&](int i, int j, T c) {
+                if (i >= j) {
+                    const T v = S.Qh[(int64_t)i * n + j] + c;
+                    S.Qh[(int64_t)i * n + j] = v;
+                    S.Qh[(int64_t)j * n + i] = v;
+                }
+            });
+            gemm_tile<false, false>(n, n, m, S.HY, m, S.X, n, false, [&](int i, int j, T c) {
+                const T v = S.AV[(int64_t)i * n + j] - c;
+                S.V[(int64_t)i * n + j] = v;
+                out.V(s, i, j, v);
+            });
+            gemm_tile<false, false>(m, n, m, S.LiT, m, S.X, n, false, [&](int i, int j, T c) { out.Lt(s, i, j, -c); });
+        }
+        __syncthreads();
+    }
+}
+
+// The same pass with the products on LDS panels (gemm_panel) and their
+// results through epilogue descriptors: the stages with n_x > 64.
+template <class T, bool RED, bool BF, class Get, class Pre, class Out>
+__device__ void mpass_panel(WS<T> &S, Get get, int count, int32_t *info, int inst, int stage_base, int fail_code, Pre pre,
+                      const Out &out, int *bad) {
+    static_assert(!BF || sizeof(T) == 4, "BF16 products accumulate in FP32");
+    const int n = S.n, m = S.m, nw = S.nw, tid = threadIdx.x;
+    count = uni(count);
+    for (int s = count - 1; s >= 0; --s) {
+        pre(s);
+        const StageSrc src = get(s);
+        for (int e = tid; e < n * nw; e += nthr()) {
+            const int i = e / nw, j = e - (e / nw) * nw;
+            S.AB[e] = (T)(j < n ? src.A[(int64_t)i * n + j] : src.B[(int64_t)i * m + j - n]);
+        }
+        __syncthreads();
+        // W = P [A B]; Alg. 4: B'V, A'V
+        gemm_big_panel<BF, false, false>(n, nw, n, S.P, n, S.AB, nw, false, to(S.W, nw));
+        if constexpr (RED) {
+            gemm_panel<true, false>(m, n, n, S.AB + n, nw, S.V, n, false, to(S.BV, n));
+            gemm_panel<true, false>(n, n, n, S.AB, nw, S.V, n, false, to(S.AV, n));
         }
         __syncthreads();
         // F = Qx + A'W_A (symmetric), H = Qxw + A'W_B, G = Qw + B'W_B (symmetric)
@@ -579,20 +761,20 @@ __device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int
             e.D64 = src.Qx;
             e.ldd = n;
             e.sym = true;
-            gemm_big<BF, true, false>(n, n, n, S.AB, nw, S.W, nw, true, e);
+            gemm_big_panel<BF, true, false>(n, n, n, S.AB, nw, S.W, nw, true, e);
         }
         {
             Ep<T> e = to(S.H, m);
             e.D64 = src.Qxw;
             e.ldd = m;
-            gemm_big<BF, true, false>(n, m, n, S.AB, nw, S.W + n, nw, false, e);
+            gemm_big_panel<BF, true, false>(n, m, n, S.AB, nw, S.W + n, nw, false, e);
         }
         {
             Ep<T> e = to(S.G, m);
             e.D64 = src.Qw;
             e.ldd = m;
             e.sym = true;
-            gemm_big<BF, true, false>(m, m, n, S.AB + n, nw, S.W + n, nw, true, e);
+            gemm_big_panel<BF, true, false>(m, m, n, S.AB + n, nw, S.W + n, nw, true, e);
         }
         __syncthreads();
         chol_inv(S, m, bad);
@@ -602,8 +784,8 @@ __device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int
         }
         out.L(s, S.Li, S.LiT);
         // Y' = H L^{-T}; Alg. 4: X = L^{-1} B'V
-        gemm<false, false>(n, m, m, S.H, m, S.LiT, m, false, to(S.HY, m));
-        if constexpr (RED) gemm<false, false>(m, n, m, S.Li, m, S.BV, n, false, to(S.X, n));
+        gemm_panel<false, false>(n, m, m, S.H, m, S.LiT, m, false, to(S.HY, m));
+        if constexpr (RED) gemm_panel<false, false>(m, n, m, S.Li, m, S.BV, n, false, to(S.X, n));
         __syncthreads();
         // P = F - Y'Y (symmetric), K = -L^{-T} Y
         {
@@ -614,12 +796,12 @@ __device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int
             e.sym = true;
             e.R = out.Prec(s);
             e.ldr = n;
-            gemm<false, true>(n, n, m, S.HY, m, S.HY, m, true, e);
+            gemm_panel<false, true>(n, n, m, S.HY, m, S.HY, m, true, e);
         }
         {
             Ep<T> e = to(out.Krec(s), n);
             e.sgn = T(-1);
-            gemm<false, true>(m, n, m, S.LiT, m, S.HY, m, false, e);
+            gemm_panel<false, true>(m, n, m, S.LiT, m, S.HY, m, false, e);
         }
         if constexpr (RED) {
             // Q_w_hat += X'X, V = A'V - Y'X, L_t = -L^{-T} X
@@ -628,7 +810,7 @@ __device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int
                 e.DT = S.Qh;
                 e.ldd = n;
                 e.sym = true;
-                gemm<true, false>(n, n, m, S.X, n, S.X, n, true, e);
+                gemm_panel<true, false>(n, n, m, S.X, n, S.X, n, true, e);
             }
             {
                 Ep<T> e = to(S.V, n);
@@ -637,16 +819,27 @@ __device__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int
                 e.sgn = T(-1);
                 e.R = out.Vrec(s);
                 e.ldr = n;
-                gemm<false, false>(n, n, m, S.HY, m, S.X, n, false, e);
+                gemm_panel<false, false>(n, n, m, S.HY, m, S.X, n, false, e);
             }
             {
                 Ep<T> e = to(out.Ltrec(s), n);
                 e.sgn = T(-1);
-                gemm<false, false>(m, n, m, S.LiT, m, S.X, n, false, e);
+                gemm_panel<false, false>(m, n, m, S.LiT, m, S.X, n, false, e);
             }
         }
         __syncthreads();
     }
+}
+
+// A pass over `count` stages: LDS-panel products out of line for the large
+// stages (BIG: n_x > 64), the inline per-tile products otherwise.
+template <class T, bool RED, bool BF, bool BIG, class Get, class Pre, class Out>
+__device__ __forceinline__ void mpass(WS<T> &S, Get get, int count, int32_t *info, int inst, int stage_base,
+                                      int fail_code, Pre pre, const Out &out, int *bad) {
+    if constexpr (BIG)
+        mpass_panel<T, RED, BF>(S, get, count, info, inst, stage_base, fail_code, pre, out, bad);
+    else
+        mpass_tile<T, RED, BF>(S, get, count, info, inst, stage_base, fail_code, pre, out, bad);
 }
 
 __device__ __forceinline__ StageSrc leaf_stage(const DevProb &p, int t) { return prob_stage(p, t); }
@@ -669,7 +862,7 @@ __device__ T *unit_ws(const GroupArgs &g) {
 }
 
 // ------------------------------------------------------------ matrix side
-template <class T, bool BF>
+template <class T, bool BF, bool BIG>
 __global__ void __launch_bounds__(LB_MT) kl_leaf_up(GroupArgs g) {
     __shared__ int bad;
     const int n = g.nx, m = g.nu, tid = threadIdx.x;
@@ -695,7 +888,7 @@ __global__ void __launch_bounds__(LB_MT) kl_leaf_up(GroupArgs g) {
         const LeafOut<T> o{base, n, m, true};
         if (!(it.flags & LEAF_LAST)) {
             init_red(S);
-            mpass<T, true, BF>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, o, &bad);
+            mpass<T, true, BF, BIG>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, o, &bad);
             for (int e = tid; e < n * n; e += nthr()) {
                 const int i = e / n, j = e % n;
                 const double a = (double)S.V[(int64_t)j * n + i], q = (double)S.Qh[e], x = (double)S.P[e];
@@ -712,14 +905,14 @@ __global__ void __launch_bounds__(LB_MT) kl_leaf_up(GroupArgs g) {
         } else {
             for (int e = tid; e < n * n; e += nthr()) S.P[e] = (T)p.QxN[e];
             __syncthreads();
-            mpass<T, false, BF>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, o, &bad);
+            mpass<T, false, BF, BIG>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, o, &bad);
             for (int e = tid; e < n * n; e += nthr()) out[SL.Qx() + e] = (double)S.P[e];
         }
         __syncthreads();
     }
 }
 
-template <class T, bool BF>
+template <class T, bool BF, bool BIG>
 __global__ void __launch_bounds__(LB_MT) kl_leaf_down(GroupArgs g) {
     __shared__ int bad;
     const int n = g.nx, m = g.nu, tid = threadIdx.x;
@@ -736,7 +929,7 @@ __global__ void __launch_bounds__(LB_MT) kl_leaf_down(GroupArgs g) {
         for (int e = tid; e < n * n; e += nthr()) S.P[e] = (T)p.QxN[e];
         __syncthreads();
         auto get = [&](int s) { return leaf_stage(p, it.t0 + s); };
-        mpass<T, false, BF>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, LeafOut<T>{base, n, m, false},
+        mpass<T, false, BF, BIG>(S, get, it.len, g.info, it.inst, it.t0, 2, [](int) {}, LeafOut<T>{base, n, m, false},
                             &bad);
         __syncthreads();
     }
@@ -769,6 +962,7 @@ __device__ void publish(const GroupArgs &g, int idx) {
     __syncthreads();
 }
 
+template <bool BIG>
 __global__ void __launch_bounds__(LB_MT) kl_tree(GroupArgs g) {
     __shared__ int s_item, bad;
     const int n = g.nx, tid = threadIdx.x;
@@ -791,7 +985,7 @@ __global__ void __launch_bounds__(LB_MT) kl_tree(GroupArgs g) {
             // excluded instance: only its completion flag is published
         } else if (it.kind == ITEM_UP) {
             init_red(S);
-            mpass<double, true, false>(S, get, it.count, g.info, it.inst, -1, 3, [](int) {},
+            mpass<double, true, false, BIG>(S, get, it.count, g.info, it.inst, -1, 3, [](int) {},
                                        SlotOut{slots, it.first, n, true, g.superpose != 0}, &bad);
             double *out = slot(it.out_slot);
             for (int e = tid; e < n * n; e += nthr()) {
@@ -812,7 +1006,7 @@ __global__ void __launch_bounds__(LB_MT) kl_tree(GroupArgs g) {
             double *term = it.last ? slot(it.term_slot) : nullptr;
             for (int e = tid; e < n * n; e += nthr()) S.P[e] = term ? term[SL.Qx() + e] : msg[SL.P() + e];
             __syncthreads();
-            mpass<double, false, false>(
+            mpass<double, false, false, BIG>(
                 S, get, it.count, g.info, it.inst, -1, 3,
                 [&](int s) {      // M2 for child s: P at the end of master stage s
                     if (!upl) {
@@ -1578,19 +1772,31 @@ __global__ void __launch_bounds__(NT) kw_update(GroupArgs g) {
 // ------------------------------------------------------------- launchers
 int leaf_units(const GroupArgs &g) { return std::max(1, std::min<int>(g.nleaves, LB_LEAF_UNITS)); }
 
+// the LDS-panel products serve the stages with n_x > 64
+inline bool big_stage(const GroupArgs &g) { return g.nx > 64; }
+
 template <class T, bool BF = false>
 hipError_t launch_leaf_up(const GroupArgs &g, int, hipStream_t st) {
-    hipLaunchKernelGGL((kl_leaf_up<T, BF>), dim3(leaf_units(g)), dim3(LB_MT), 0, st, g);
+    if (big_stage(g))
+        hipLaunchKernelGGL((kl_leaf_up<T, BF, true>), dim3(leaf_units(g)), dim3(LB_MT), 0, st, g);
+    else
+        hipLaunchKernelGGL((kl_leaf_up<T, BF, false>), dim3(leaf_units(g)), dim3(LB_MT), 0, st, g);
     return hipGetLastError();
 }
 hipError_t launch_tree(const GroupArgs &g, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(kl_tree, dim3(std::min(grid, LB_TREE_UNITS)), dim3(LB_MT), 0, st, g);
+    if (big_stage(g))
+        hipLaunchKernelGGL(kl_tree<true>, dim3(std::min(grid, LB_TREE_UNITS)), dim3(LB_MT), 0, st, g);
+    else
+        hipLaunchKernelGGL(kl_tree<false>, dim3(std::min(grid, LB_TREE_UNITS)), dim3(LB_MT), 0, st, g);
     return hipGetLastError();
 }
 template <class T, bool BF = false>
 hipError_t launch_leaf_down(const GroupArgs &g, int, hipStream_t st) {
     if (g.ntop == 0) return hipSuccess;
-    hipLaunchKernelGGL((kl_leaf_down<T, BF>), dim3(leaf_units(g)), dim3(LB_MT), 0, st, g);
+    if (big_stage(g))
+        hipLaunchKernelGGL((kl_leaf_down<T, BF, true>), dim3(leaf_units(g)), dim3(LB_MT), 0, st, g);
+    else
+        hipLaunchKernelGGL((kl_leaf_down<T, BF, false>), dim3(leaf_units(g)), dim3(LB_MT), 0, st, g);
     return hipGetLastError();
 }
 template <class TR>
