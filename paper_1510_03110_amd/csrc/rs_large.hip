@@ -643,6 +643,26 @@ struct SlotOut {
     }
 };
 
+// [A B] of a stage into the workspace (n x (n + m), row-major, element
+// type T), eight loads per thread in flight before their stores (a load
+// issued after a store to memory the compiler cannot tell apart waits for
+// it).
+template <class T>
+__device__ __forceinline__ void load_ab(WS<T> &S, const StageSrc &src) {
+    const int n = S.n, m = S.m, nw = S.nw, total = n * nw, nt = nthr();
+    for (int e0 = threadIdx.x; e0 < total; e0 += 8 * nt) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * nt, i = e / nw, j = e - (e / nw) * nw;
+            v[u] = e < total ? (T)(j < n ? src.A[(int64_t)i * n + j] : src.B[(int64_t)i * m + j - n]) : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (e0 + u * nt < total) S.AB[e0 + u * nt] = v[u];
+    }
+}
+
 // Backward pass over `count` stages (local s = count-1 .. 0), matrix lines
 // only.  RED: Alg. 4 (state P, V, Q_w_hat in the workspace); otherwise Alg. 1
 // from the P in the workspace.  pre(s) runs before stage s and sees P_{s+1}.
@@ -743,10 +763,7 @@ __device__ void mpass_panel(WS<T> &S, Get get, int count, int32_t *info, int ins
     for (int s = count - 1; s >= 0; --s) {
         pre(s);
         const StageSrc src = get(s);
-        for (int e = tid; e < n * nw; e += nthr()) {
-            const int i = e / nw, j = e - (e / nw) * nw;
-            S.AB[e] = (T)(j < n ? src.A[(int64_t)i * n + j] : src.B[(int64_t)i * m + j - n]);
-        }
+        load_ab(S, src);
         __syncthreads();
         // W = P [A B]; Alg. 4: B'V, A'V
         gemm_big_panel<BF, false, false>(n, nw, n, S.P, n, S.AB, nw, false, to(S.W, nw));
