@@ -13,7 +13,10 @@
 //                  matrix part of the M1 message
 //   kl_tree        work-queue kernel over the master levels: Alg. 4 on master
 //                  groups (Alg. 5), elimination of the last group, and the
-//                  factorization of the top / down subproblems (Alg. 6)
+//                  factorization of the top subproblem (Alg. 6; below the
+//                  top the down pass is kw_tree's superposition sweep on the
+//                  up records, or, with RS_PLAN_REFACTOR_DOWN, a second
+//                  factorization from the parent's message)
 //   kl_leaf_down   whole-problem leaves: Alg. 1 with the true terminal
 //   kw_leaf_up / kw_tree / kw_leaf_down
 //                  the vector lines of the same passes and the forward
@@ -24,7 +27,9 @@
 //
 // Every dense product of a stage is a list of 16x16 output tiles on the
 // matrix cores (v_mfma_f64_16x16x4f64, or the f32 form for FP32 factors),
-// tile t of a product going to wave t mod 4; products of one phase are
+// tile t of a product going to wave t mod 8; at n_x > 64 the operands come
+// through LDS panels shared by the workgroup (gemm_panel), at n_x <= 64 each
+// tile reads its own strips (gemm_tile).  Products of one phase are
 // independent, and a workgroup barrier separates phases.  Per stage:
 //   W = P [A B];  (Alg. 4) B'V, A'V
 //   F = Qx + A'W_A,  H = Qxw + A'W_B,  G = Qw + B'W_B                 (Alg. 1)
