@@ -32,3 +32,24 @@ def test_library_exports_every_declared_symbol():
 def test_options_struct_matches_header_size():
     # int32 precision, Ns, branch, max_refine; double tol; int32 flags, reserved
     assert ctypes.sizeof(rs.rs_options) == 32
+
+
+def test_binding_constants_match_header():
+    """Every #define and enum value of include/rs.h that the binding mirrors
+    has the header's value (flags, status codes, precisions, sizes)."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    values = {}
+    for name, expr in re.findall(r"#define\s+(RS_[A-Z0-9_]+)\s+(.+)", text):
+        expr = expr.replace("(size_t)", "").strip()
+        m = re.fullmatch(r"\(*\s*(\d+)\s*\)*(?:\s*<<\s*(\d+)\s*\)*)?", expr)
+        if m:
+            values[name] = int(m.group(1)) << int(m.group(2) or 0)
+    for name, val in re.findall(r"\b(RS_[A-Z0-9_]+)\s*=\s*(\d+)", text):
+        values[name] = int(val)
+    checked = 0
+    for name, val in values.items():
+        if hasattr(rs, name):
+            assert getattr(rs, name) == val, (name, getattr(rs, name), val)
+            checked += 1
+    assert checked >= 15
