@@ -1048,12 +1048,18 @@ __global__ void __launch_bounds__(LB_MT) kl_tree(GroupArgs g) {
 
 // ------------------------------------------------------------ vector side
 constexpr int VMAX = 128;
+// threads of the vector-line kernels, at most (8 wavefronts; the launch
+// takes 4 or 8, and every loop and partition below follows the launch): with
+// 8, a matrix-vector product of up to 128 rows takes two passes of 64 rows
+// (row form) or eight column groups (column form), so its loads are in
+// flight in few round trips
+constexpr int VNT = 512;
 
 struct VS {
     double Psi[VMAX], pt[VMAX], av[VMAX], d[VMAX], x[VMAX], gw[VMAX], z[VMAX], kk[VMAX], wv[VMAX], v[VMAX],
         lamN[VMAX], y[VMAX];
-    double red[NT / 64];
-    double gred[NT];
+    double red[VNT / 64];
+    double gred[VNT];
 };
 
 __device__ __forceinline__ double block_sum(double v, VS &S) {
@@ -1063,7 +1069,7 @@ __device__ __forceinline__ double block_sum(double v, VS &S) {
     __syncthreads();
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < NT / 64; ++w) s += S.red[w];
+    for (int w = 0; w < nwav(); ++w) s += S.red[w];
     return s;
 }
 
@@ -1080,7 +1086,7 @@ __device__ __forceinline__ void gemv(const U *M, int ld, const double *x, int R,
     if constexpr (!ROW) {
         int Rp = 16;
         while (Rp < R) Rp <<= 1;
-        const int parts = NT / Rp, i = tid & (Rp - 1), p = tid / Rp;
+        const int parts = nthr() / Rp, i = tid & (Rp - 1), p = tid / Rp;
         const int chunk = (C + parts - 1) / parts, k0 = p * chunk, k1 = k0 + chunk < C ? k0 + chunk : C;
         double acc = 0.0;
         if (M && i < R) {
@@ -1097,7 +1103,7 @@ __device__ __forceinline__ void gemv(const U *M, int ld, const double *x, int R,
         __syncthreads();
     } else {
         const int l = lane(), c16 = l & 15, row = wave() * 4 + (l >> 4);
-        for (int base = 0; base < R; base += NT / 16) {
+        for (int base = 0; base < R; base += nthr() / 16) {
             const int i = base + row;
             double acc = 0.0;
             if (M && i < R) {
@@ -1119,12 +1125,12 @@ __device__ __forceinline__ void gemv(const U *M, int ld, const double *x, int R,
 // group's chunk, adds M(k, i) v_k to its column sum and passes M(k, i) u_i
 // through a DPP sum over the group for the row sum of k.  Every group runs
 // the same number of iterations, so the sums run with all lanes active.
-// The column sums of the groups are added through LDS (red, NT doubles) in a
+// The column sums of the groups are added through LDS (red, VNT doubles) in a
 // fixed order; all threads of the workgroup must call it.
 template <int G, class OC, class OR>
 __device__ __forceinline__ void gemv_dual(const double *M, int ld, const double *v, const double *u, int rows,
                                           int cols, OC ocol, OR orow, double *red) {
-    const int tid = threadIdx.x, parts = NT / G, i = tid & (G - 1), p = tid / G;
+    const int tid = threadIdx.x, parts = nthr() / G, i = tid & (G - 1), p = tid / G;
     const int chunk = (rows + parts - 1) / parts, k0 = p * chunk;
     const bool col = i < cols;
     const double ui = col ? u[i] : 0.0;
@@ -1184,7 +1190,7 @@ struct VSrcL {
 template <bool RED, bool WANTK, class TR>
 __device__ void vstage(VS &S, const VSrcL<TR> &q, int n, int m, double &cbar) {
     const int tid = threadIdx.x;
-    for (int i = tid; i < n; i += NT) S.av[i] = q.a ? q.a[i] : 0.0;
+    for (int i = tid; i < n; i += nthr()) S.av[i] = q.a ? q.a[i] : 0.0;
     __syncthreads();
     double part = 0.0;
     if (q.Pn)
@@ -1221,7 +1227,7 @@ __device__ void vstage(VS &S, const VSrcL<TR> &q, int n, int m, double &cbar) {
         if (q.Vn)
             gemv<false>(q.Vn, n, S.d, n, n, [&](int i, double v) { S.v[i] += v; }, S.gred);
         else
-            for (int i = tid; i < n; i += NT) S.v[i] += S.d[i];
+            for (int i = tid; i < n; i += nthr()) S.v[i] += S.d[i];
         __syncthreads();
     }
 }
@@ -1235,7 +1241,7 @@ __device__ __forceinline__ void fstage(VS &S, int n, int m, const TR *K, const d
                                        const double *Psi, const TR *Vt, double *x_out, double *w_out,
                                        double *lam_out) {
     const int tid = threadIdx.x;
-    for (int i = tid; i < n; i += NT)
+    for (int i = tid; i < n; i += nthr())
         if (x_out) x_out[i] = S.x[i];
     gemv<true>(K, n, S.x, m, n, [&](int i, double v) { S.wv[i] = v + kvec[i]; }, S.gred);
     gemv<true>(A, n, S.x, n, n, [&](int i, double v) { S.y[i] = v + (a ? a[i] : 0.0); }, S.gred);
@@ -1246,13 +1252,13 @@ __device__ __forceinline__ void fstage(VS &S, int n, int m, const TR *K, const d
         gemv<true>(Vt, n, S.lamN, n, n, [&](int i, double v) { S.d[i] += v; }, S.gred);
         __syncthreads();
     }
-    for (int i = tid; i < m; i += NT)
+    for (int i = tid; i < m; i += nthr())
         if (w_out) w_out[i] = S.wv[i];
-    for (int i = tid; i < n; i += NT)
+    for (int i = tid; i < n; i += nthr())
         if (lam_out) lam_out[i] = S.d[i];
     gemv<true>(B, m, S.wv, n, m, [&](int i, double v) { S.y[i] += v; }, S.gred);
     __syncthreads();
-    for (int i = tid; i < n; i += NT) S.x[i] = S.y[i];
+    for (int i = tid; i < n; i += nthr()) S.x[i] = S.y[i];
     __syncthreads();
 }
 
@@ -1296,7 +1302,7 @@ __device__ VSrcL<double> slot_src(const double *sl, int n) {
 }
 
 template <class TR>
-__global__ void __launch_bounds__(NT) kw_leaf_up(GroupArgs g) {
+__global__ void __launch_bounds__(VNT) kw_leaf_up(GroupArgs g) {
     __shared__ VS S;
     if (sv::pass_idle(g)) return;
     const int n = g.nx, m = g.nu, tid = threadIdx.x;
@@ -1308,7 +1314,7 @@ __global__ void __launch_bounds__(NT) kw_leaf_up(GroupArgs g) {
     const TR *rec = reinterpret_cast<const TR *>(g.fstore) + g.rec_stage(it.scratch) * (int64_t)R.per_stage();
     double *out = g.slots + (int64_t)it.slot * SL.size();
     const bool last = (it.flags & LEAF_LAST) != 0;
-    for (int i = tid; i < n; i += NT) {
+    for (int i = tid; i < n; i += nthr()) {
         S.Psi[i] = (last && p.lN) ? -p.lN[i] : 0.0;
         S.v[i] = 0.0;
     }
@@ -1333,11 +1339,11 @@ __global__ void __launch_bounds__(NT) kw_leaf_up(GroupArgs g) {
         }
         // Psi_t and k_{t+1} of this sweep, for the leaf solve
         double *vec = vec0 + (int64_t)s * R.vec();
-        for (int i = tid; i < n; i += NT) vec[i] = S.Psi[i];
-        for (int i = tid; i < m; i += NT) vec[n + i] = S.kk[i];
+        for (int i = tid; i < n; i += nthr()) vec[i] = S.Psi[i];
+        for (int i = tid; i < m; i += nthr()) vec[n + i] = S.kk[i];
         __syncthreads();
     }
-    for (int i = tid; i < n; i += NT) {
+    for (int i = tid; i < n; i += nthr()) {
         if (!last) out[SL.a() + i] = S.v[i];
         out[SL.lx() + i] = -S.Psi[i];
     }
@@ -1360,15 +1366,15 @@ __device__ void leaf_forward(VS &S, const GroupArgs &g, const sv::Prob &p, const
     const double *msg = g.slots + (int64_t)it.slot * SL.size();
     const bool last = (it.flags & LEAF_LAST) != 0;
     if (!last && g.superpose) {
-        for (int i = tid; i < n; i += NT) S.lamN[i] = msg[SL.lamN() + i];    // sent by the master level
+        for (int i = tid; i < n; i += nthr()) S.lamN[i] = msg[SL.lamN() + i];    // sent by the master level
     } else if (!last) {
         const double *nxt = msg + SL.size();           // the next leaf's slot: x_hat_{i+1}
-        for (int i = tid; i < n; i += NT) S.x[i] = nxt[SL.xh() + i];
+        for (int i = tid; i < n; i += nthr()) S.x[i] = nxt[SL.xh() + i];
         __syncthreads();
         gemv<false>(msg + SL.P(), n, S.x, n, n, [&](int i, double v) { S.lamN[i] = v - msg[SL.Psi() + i]; }, S.gred);
         __syncthreads();
     }
-    for (int i = tid; i < n; i += NT) S.x[i] = msg[SL.xh() + i];
+    for (int i = tid; i < n; i += nthr()) S.x[i] = msg[SL.xh() + i];
     __syncthreads();
     const int len = uni(it.len);
     for (int s = 0; s < len; ++s) {
@@ -1389,7 +1395,7 @@ __device__ void leaf_forward(VS &S, const GroupArgs &g, const sv::Prob &p, const
 }
 
 template <class TR>
-__global__ void __launch_bounds__(NT) kw_leaf_down(GroupArgs g) {
+__global__ void __launch_bounds__(VNT) kw_leaf_down(GroupArgs g) {
     __shared__ VS S;
     if (sv::pass_idle(g)) return;
     const int n = g.nx, m = g.nu, tid = threadIdx.x;
@@ -1406,7 +1412,7 @@ __global__ void __launch_bounds__(NT) kw_leaf_down(GroupArgs g) {
     const int64_t stage0 = g.rec_stage(it.scratch);
     const TR *rec = reinterpret_cast<const TR *>(g.fstore) + stage0 * (int64_t)R.per_stage();
     double *vec0 = g.fvec + stage0 * (int64_t)R.vec();
-    for (int i = tid; i < n; i += NT) {
+    for (int i = tid; i < n; i += nthr()) {
         S.Psi[i] = p.lN ? -p.lN[i] : 0.0;
         S.x[i] = p.x0[i];
     }
@@ -1424,8 +1430,8 @@ __global__ void __launch_bounds__(NT) kw_leaf_down(GroupArgs g) {
         q.K = dn + R.K();
         vstage<false, true>(S, q, n, m, cbar);
         double *vec = vec0 + (int64_t)s * R.vec();
-        for (int i = tid; i < n; i += NT) vec[i] = S.Psi[i];
-        for (int i = tid; i < m; i += NT) vec[n + i] = S.kk[i];
+        for (int i = tid; i < n; i += nthr()) vec[i] = S.Psi[i];
+        for (int i = tid; i < m; i += nthr()) vec[n + i] = S.kk[i];
         __syncthreads();
     }
     if (p.obj) {
@@ -1449,9 +1455,10 @@ __global__ void __launch_bounds__(NT) kw_leaf_down(GroupArgs g) {
 }
 
 // A tree item is a chain of matrix-vector products with one workgroup per
-// CU; the occupancy cap of two waves per SIMD keeps the compiler from
-// trading the loads in flight of each product's unrolled loop for registers.
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) kw_tree(GroupArgs g) {
+// CU; the occupancy range of two to three waves per SIMD keeps the compiler
+// from trading the loads in flight of each product's unrolled loop for
+// registers.
+__global__ void __launch_bounds__(VNT) __attribute__((amdgpu_waves_per_eu(2, 3))) kw_tree(GroupArgs g) {
     __shared__ VS S;
     __shared__ int s_item;
     const int n = g.nx, tid = threadIdx.x;
@@ -1472,7 +1479,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
             // converged or excluded: nothing to do (its dependents belong to the same instance)
         } else if (it.kind == ITEM_UP) {
             // Alg. 4 on the master stages (vector lines)
-            for (int i = tid; i < n; i += NT) {
+            for (int i = tid; i < n; i += nthr()) {
                 S.Psi[i] = 0.0;
                 S.v[i] = 0.0;
             }
@@ -1491,7 +1498,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
                 vstage<true, false>(S, q, n, n, cbar);
                 if (g.superpose) {
                     // Psi_s and k_s of this sweep, for the superposition sweep down
-                    for (int i = tid; i < n; i += NT) {
+                    for (int i = tid; i < n; i += nthr()) {
                         sl[SL.Psi() + i] = S.Psi[i];
                         sl[SL.k() + i] = S.kk[i];
                     }
@@ -1499,7 +1506,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
                 __syncthreads();
             }
             double *out = slot(it.out_slot);
-            for (int i = tid; i < n; i += NT) {
+            for (int i = tid; i < n; i += nthr()) {
                 out[SL.a() + i] = S.v[i];
                 out[SL.lx() + i] = -S.Psi[i];
             }
@@ -1523,14 +1530,14 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
             const double *msg = upl || top ? nullptr : slot(it.out_slot);
             double *term = it.last ? slot(it.term_slot) : nullptr;
             if (sweep) {
-                for (int i = tid; i < n; i += NT) {
+                for (int i = tid; i < n; i += nthr()) {
                     S.x[i] = msg[SL.xh() + i];
                     S.lamN[i] = lterms ? msg[SL.lamN() + i] : 0.0;
                 }
                 __syncthreads();
             } else {
                 const sv::Prob p = sv::load_prob(g.probs, it.inst);
-                for (int i = tid; i < n; i += NT) {
+                for (int i = tid; i < n; i += nthr()) {
                     S.Psi[i] = term ? -term[SL.lx() + i] : msg[SL.Psi() + i];
                     if (!upl) S.x[i] = top ? p.x0[i] : msg[SL.xh() + i];
                 }
@@ -1546,7 +1553,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
                         q.K = sl + SL.uK();
                     } else {
                         // message to child s: cost to go at the end of master stage s
-                        for (int i = tid; i < n; i += NT) sl[SL.Psi() + i] = S.Psi[i];
+                        for (int i = tid; i < n; i += nthr()) sl[SL.Psi() + i] = S.Psi[i];
                         if (tid == 0) sl[SL.cb()] = cbar;
                         q.Pn = sl + SL.P();
                         q.Li = sl + SL.dL();
@@ -1556,14 +1563,14 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
                     vstage<false, true>(S, q, n, n, cbar);
                     // k_s (and for the sweep down, Psi_s of the up records)
                     if (!upl || g.superpose)
-                        for (int i = tid; i < n; i += NT) sl[SL.k() + i] = S.kk[i];
+                        for (int i = tid; i < n; i += nthr()) sl[SL.k() + i] = S.kk[i];
                     if (upl && g.superpose)
-                        for (int i = tid; i < n; i += NT) sl[SL.Psi() + i] = S.Psi[i];
+                        for (int i = tid; i < n; i += nthr()) sl[SL.Psi() + i] = S.Psi[i];
                     __syncthreads();
                 }
                 if (upl) {
                     double *out = slot(it.out_slot);
-                    for (int i = tid; i < n; i += NT) out[SL.lx() + i] = -S.Psi[i];
+                    for (int i = tid; i < n; i += nthr()) out[SL.lx() + i] = -S.Psi[i];
                     if (tid == 0) out[SL.c()] = cbar;
                 } else if (top && p.obj) {
                     const double v = cost_to_go(S, slot(it.term_slot) + SL.P(), n, cbar);
@@ -1580,7 +1587,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
                                    sl + SL.xh(), nullptr, sweep && s > 0 ? slot(it.first + s - 1) + SL.lamN() : nullptr);
                 }
                 if (it.last)
-                    for (int i = tid; i < n; i += NT) term[SL.xh() + i] = S.x[i];
+                    for (int i = tid; i < n; i += nthr()) term[SL.xh() + i] = S.x[i];
             }
             if (sweep) {
                 // the last child ends where the item does: at lam_N, or for
@@ -1590,7 +1597,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
                     gemv<false>(term + SL.Qx(), n, S.x, n, n, [&](int i, double v) { lend[i] = v + term[SL.lx() + i]; },
                                 S.gred);
                 else
-                    for (int i = tid; i < n; i += NT) lend[i] = S.lamN[i];
+                    for (int i = tid; i < n; i += nthr()) lend[i] = S.lamN[i];
             } else if (top && g.superpose) {
                 // terminal costate of child s, lam_{s+1} = P_{s+1} x_{s+1} -
                 // Psi_{s+1}, from the cost to go sent to it and the initial
@@ -1600,7 +1607,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
                 for (int s = 0; s < count; ++s) {
                     double *sl = slot(it.first + s);
                     const double *xn = (s + 1 < count ? slot(it.first + s + 1) : term) + SL.xh();
-                    for (int i = tid; i < n; i += NT) S.y[i] = xn[i];
+                    for (int i = tid; i < n; i += nthr()) S.y[i] = xn[i];
                     __syncthreads();
                     gemv<false>(sl + SL.P(), n, S.y, n, n, [&](int i, double v) { sl[SL.lamN() + i] = v - sl[SL.Psi() + i]; },
                                 S.gred);
@@ -1616,7 +1623,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
 // stages of one leaf, one stage at a time over the whole workgroup; writes
 // the correction problem's data (-rho as problem data, see the register
 // kernels) and the leaf's max |r|, max |rho| and objective part.
-__global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
+__global__ void __launch_bounds__(VNT) kw_residual(GroupArgs g) {
     __shared__ VS S;
     const int n = g.nx, m = g.nu, tid = threadIdx.x;
     const LeafItem it = sv::load_leaf(g.leaves, blockIdx.x);
@@ -1633,12 +1640,12 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
         const double *Qx = p.Qx + t * p.sQx, *Qw = p.Qw + t * p.sQw;
         const double *Qxw = p.Qxw ? p.Qxw + t * p.sQxw : nullptr;
         const double *A = p.A + t * p.sA, *B = p.B + t * p.sB;
-        for (int i = tid; i < n; i += NT) {
+        for (int i = tid; i < n; i += nthr()) {
             xs[i] = x[i];
             ls[i] = lamn[i];
             zn = fmax(zn, fmax(fabs(x[i]), fabs(lam[i])));
         }
-        for (int i = tid; i < m; i += NT) {
+        for (int i = tid; i < m; i += nthr()) {
             ws[i] = w[i];
             zn = fmax(zn, fabs(w[i]));
         }
@@ -1655,13 +1662,13 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
             gemv_both(Qxw, m, xs, ws, n, m, [&](int j, double v) { S.gw[j] = v; },
                       [&](int k, double v) { S.d[k] = v; }, S.gred);
         } else {
-            for (int i = tid; i < n; i += NT) S.d[i] = 0.0;
-            for (int j = tid; j < m; j += NT) S.gw[j] = 0.0;
+            for (int i = tid; i < n; i += nthr()) S.d[i] = 0.0;
+            for (int j = tid; j < m; j += nthr()) S.gw[j] = 0.0;
         }
         gemv<false>(Qw, m, ws, m, m, [&](int j, double v) { S.z[j] = v; }, S.gred);
         __syncthreads();
         double part = 0.0;
-        for (int i = tid; i < n; i += NT) {
+        for (int i = tid; i < n; i += nthr()) {
             const double lxi = p.lx ? p.lx[t * p.slx + i] : 0.0, ai = p.a ? p.a[t * p.sa + i] : 0.0;
             const double dlx = lxi + S.pt[i] + S.d[i] - lam[i] + S.av[i];
             const double da = ai + S.y[i] + S.Psi[i] - xn[i];
@@ -1673,7 +1680,7 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
             res = fmax(res, fmax(fabs(dlx), fabs(da)));
             part += xs[i] * (0.5 * S.pt[i] + S.d[i] + lxi);
         }
-        for (int j = tid; j < m; j += NT) {
+        for (int j = tid; j < m; j += nthr()) {
             const double lwj = p.lw ? p.lw[t * p.slw + j] : 0.0;
             const double dlw = lwj + S.gw[j] + S.z[j] + S.kk[j];
             if (g.corr) const_cast<double *>(c.lw)[t * c.slw + j] = dlw;
@@ -1685,7 +1692,7 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
         if (tid == 0) obj += tot + (p.c ? p.c[t * p.sc] : 0.0);
     }
     if (it.t0 == 0) {            // lam_0 row
-        for (int i = tid; i < n; i += NT) {
+        for (int i = tid; i < n; i += nthr()) {
             const double d0 = p.x[i] - p.x0[i];
             if (g.corr) const_cast<double *>(c.x0)[i] = d0;
             rhs = fmax(rhs, fabs(p.x0[i]));
@@ -1695,7 +1702,7 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
     if (it.flags & LEAF_LAST) {  // x_N row and the terminal cost
         const int64_t N = it.t0 + len;
         const double *x = p.x + N * n, *lam = p.lam + N * n;
-        for (int i = tid; i < n; i += NT) xs[i] = x[i];
+        for (int i = tid; i < n; i += nthr()) xs[i] = x[i];
         __syncthreads();
         double part = 0.0;
         gemv<true>(p.QxN, n, xs, n, n, [&](int i, double qx) {
@@ -1723,7 +1730,7 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
     if (tid == 0) {
         double *out = g.part + (int64_t)(g.leaf_base + blockIdx.x) * PART_N;
         double a = 0.0, b = 0.0, z = 0.0;
-        for (int q = 0; q < NT / 64; ++q) {
+        for (int q = 0; q < nwav(); ++q) {
             a = fmax(a, S.av[q]);
             b = fmax(b, S.pt[q]);
             z = fmax(z, S.y[q]);
@@ -1737,8 +1744,8 @@ __global__ void __launch_bounds__(NT) kw_residual(GroupArgs g) {
 
 // z += d over the leaf's stages (and x_N, lam_N for the last leaf); max |d|
 // and max |z| per block (x, w, lam).
-__global__ void __launch_bounds__(NT) kw_update(GroupArgs g) {
-    __shared__ double red[NT / 64][6];
+__global__ void __launch_bounds__(VNT) kw_update(GroupArgs g) {
+    __shared__ double red[VNT / 64][6];
     const int n = g.nx, m = g.nu, tid = threadIdx.x;
     const LeafItem it = sv::load_leaf(g.leaves, blockIdx.x);
     if (sv::skip_inst(g, it.inst)) return;
@@ -1748,7 +1755,7 @@ __global__ void __launch_bounds__(NT) kw_update(GroupArgs g) {
     double mx[6] = {0, 0, 0, 0, 0, 0};
     {
         const int64_t b0 = (int64_t)it.t0 * n, cnt = (int64_t)nst * n;
-        for (int64_t e = tid; e < cnt; e += NT) {
+        for (int64_t e = tid; e < cnt; e += nthr()) {
             const double dx = c.x[b0 + e], dl = c.lam[b0 + e];
             double xv = p.x[b0 + e], lv = p.lam[b0 + e];
             if (!g.measure_only) {
@@ -1765,7 +1772,7 @@ __global__ void __launch_bounds__(NT) kw_update(GroupArgs g) {
     }
     {
         const int64_t b0 = (int64_t)it.t0 * m, cnt = (int64_t)it.len * m;
-        for (int64_t e = tid; e < cnt; e += NT) {
+        for (int64_t e = tid; e < cnt; e += nthr()) {
             const double dw = c.w[b0 + e];
             double wv = p.w[b0 + e];
             if (!g.measure_only) {
@@ -1785,13 +1792,17 @@ __global__ void __launch_bounds__(NT) kw_update(GroupArgs g) {
         double *out = g.part + (int64_t)(g.leaf_base + blockIdx.x) * PART_N;
         for (int q = 0; q < 6; ++q) {
             double v = 0.0;
-            for (int w = 0; w < NT / 64; ++w) v = fmax(v, red[w][q]);
+            for (int w = 0; w < nwav(); ++w) v = fmax(v, red[w][q]);
             out[PART_DX + q] = v;
         }
     }
 }
 
 // ------------------------------------------------------------- launchers
+// threads of a vector-line launch: all eight wavefronts for the larger
+// shapes, four for n_x < 32, where each product is a few short rows and the
+// extra waves cost more in synchronization than they bring in loads
+int vthreads(const GroupArgs &g) { return g.nx >= 32 ? VNT : VNT / 2; }
 int leaf_units(const GroupArgs &g) { return std::max(1, std::min<int>(g.nleaves, LB_LEAF_UNITS)); }
 
 // the LDS-panel products serve the stages with n_x > 64
@@ -1823,24 +1834,24 @@ hipError_t launch_leaf_down(const GroupArgs &g, int, hipStream_t st) {
 }
 template <class TR>
 hipError_t launch_vup(const GroupArgs &g, int, hipStream_t st) {
-    hipLaunchKernelGGL((kw_leaf_up<TR>), dim3(g.nleaves), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL((kw_leaf_up<TR>), dim3(g.nleaves), dim3(vthreads(g)), 0, st, g);
     return hipGetLastError();
 }
 hipError_t launch_vtree(const GroupArgs &g, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(kw_tree, dim3(grid), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL(kw_tree, dim3(grid), dim3(vthreads(g)), 0, st, g);
     return hipGetLastError();
 }
 template <class TR>
 hipError_t launch_vdown(const GroupArgs &g, int, hipStream_t st) {
-    hipLaunchKernelGGL((kw_leaf_down<TR>), dim3(g.nleaves), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL((kw_leaf_down<TR>), dim3(g.nleaves), dim3(vthreads(g)), 0, st, g);
     return hipGetLastError();
 }
 hipError_t launch_residual(const GroupArgs &g, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(kw_residual, dim3(grid), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL(kw_residual, dim3(grid), dim3(vthreads(g)), 0, st, g);
     return hipGetLastError();
 }
 hipError_t launch_update(const GroupArgs &g, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(kw_update, dim3(grid), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL(kw_update, dim3(grid), dim3(vthreads(g)), 0, st, g);
     return hipGetLastError();
 }
 
