@@ -206,8 +206,8 @@ __shared__ double gp_sm[GP_ELEMS];
 // tile that read its own operand strips needed one per 32 of inner size.
 // With `lower` only the tiles on and below the diagonal are formed and only
 // the elements with i >= j are put.  Small products (fewer than
-// GP_MIN_TILES tiles: every product at n_x <= 64) skip the panels, and each
-// wave reads its tiles' operand strips itself.  One out-of-line body per operand
+// GP_MIN_TILES tiles, such as G at n_u <= 64) skip the panels, and each wave
+// reads its tiles' operand strips itself.  One out-of-line body per operand
 // layout keeps the stage's code within the instruction cache.  Every thread
 // of the workgroup must call it (it synchronizes the workgroup).
 template <bool TA, bool TB, class T>
@@ -362,7 +362,7 @@ __device__ __attribute__((noinline)) void gemm_panel(int M, int N, int K, const 
 // epilogue as a functor:
 // C = opA(A) opB(B): M x N, inner size K (any sizes; edge tiles are padded
 // with zeros on load).  opA(i,k) = TA ? A[k*lda+i] : A[i*lda+k], opB(k,j) =
-// TB ? B[j*ldb+k] : B[k*ldb+j].  16x16 tile t goes to wave t mod 4; every
+// TB ? B[j*ldb+k] : B[k*ldb+j].  16x16 tile t goes to wave t mod 8; every
 // element (i, j) of the result with i < M, j < N is handed to epi(i, j, c).
 // With `lower` (square results) only the tiles on and below the diagonal are
 // formed, and epi must use the elements with i >= j.
